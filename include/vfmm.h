@@ -1,0 +1,202 @@
+/*
+ * vfmm -- velocity of N regularised vortex particles by a uniform-quadtree Fast
+ * Multipole Method on one AMD MI355X (gfx950) GPU.
+ *
+ * The method is the one characterised by F. A. Cruz and L. A. Barba,
+ * "Characterization of the errors of the Fast Multipole Method approximation in
+ * particle simulations" (2008):
+ *   - the velocity of Gaussian vortex blobs, eq. 6-7 (direct sum, eq. 9);
+ *   - a uniform quadtree of L levels (Section 3.3, Fig. 6) with local lists and
+ *     interaction lists (Section 3.3.1);
+ *   - p-term multipole and local expansions of the singular far-field kernel
+ *     (eq. 14-22), translated by M2M (Section 3.3.2), M2L (eq. 22) and L2L
+ *     (Section 3.3.3), evaluated by L2P; the near field is summed directly with
+ *     the regularised kernel (eq. 10).
+ *
+ * Conventions shared by every entry point
+ *   - Particles are given as structure-of-arrays float64: x[n], y[n], gamma[n]
+ *     (position and circulation).  Velocities u[n], v[n] are float64 and are
+ *     written in the caller's particle order.  Targets are the particles
+ *     themselves; the self term is excluded (eq. 9), and coincident particles
+ *     contribute zero.
+ *   - Array arguments are DEVICE pointers unless marked (host).  The caller owns
+ *     every input, output and workspace buffer; the library never allocates
+ *     device memory.  The library owns only the opaque tree handle.
+ *   - Calls that take a `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) are asynchronous: they validate arguments on the host,
+ *     enqueue kernels and return.  The caller synchronises before reading
+ *     results.  A tree must not be used from two streams at once.
+ *   - Every entry point returns a status; 0 (VFMM_OK) is success and negative
+ *     values are errors.  On error nothing has been enqueued (argument errors)
+ *     or the outputs are unspecified (HIP errors); vfmm_last_error() returns a
+ *     thread-local message.  No entry point aborts or throws.
+ *
+ * Tree conventions (the paper leaves them open; fixed here):
+ *   - root box: the bounding square of the particles, side
+ *     S = max extent * (1 + 2^-20), centred on the bounding-box midpoint
+ *     (S = 1 for a zero extent), or a caller-given square;
+ *   - leaf of a particle: ix = clamp(floor(((x - x0) / S) * 2^L), 0, 2^L - 1),
+ *     likewise iy (a particle on a box edge belongs to the upper/right box);
+ *   - expansion centres are geometric box centres; M2L starts at level 2;
+ *     with L <= 1 every pair is near and the result equals the direct sum.
+ */
+#ifndef VFMM_H
+#define VFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vfmm_status_t;
+
+#define VFMM_OK 0
+#define VFMM_ERR_INVALID_ARG (-1)
+#define VFMM_ERR_HIP (-3)
+#define VFMM_ERR_UNSUPPORTED (-4)
+#define VFMM_ERR_WORKSPACE (-6)
+
+/* Arithmetic of the evaluation (vfmm_fmm_velocity `precision`).
+ *   VFMM_FP64      : every step in float64.
+ *   VFMM_FP32      : P2M, M2M, M2L, L2L, L2P and P2P in float32 on scaled
+ *                    coefficients; the P2P source loop keeps compensated float32
+ *                    sums; output float64.
+ *   VFMM_M2L_BF16  : as VFMM_FP32 but M2L on bfloat16 matrix cores with float32
+ *                    accumulation.
+ *   VFMM_M2L_FP16  : as VFMM_FP32 but M2L on float16 matrix cores with float32
+ *                    accumulation. */
+#define VFMM_FP64 0
+#define VFMM_FP32 1
+#define VFMM_M2L_BF16 2
+#define VFMM_M2L_FP16 3
+
+/* Which part of eq. 10 vfmm_fmm_velocity_parts writes. */
+#define VFMM_PART_NEAR 1
+#define VFMM_PART_FAR 2
+#define VFMM_PART_ALL 3
+
+#define VFMM_MAX_P 40
+#define VFMM_MAX_LEVELS 12
+
+typedef struct vfmm_tree_s* vfmm_tree_t;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t vfmm_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* vfmm_status_string(vfmm_status_t status);
+
+/* Detail of the last error raised on the calling thread (static per thread). */
+const char* vfmm_last_error(void);
+
+/* Bytes of device workspace that vfmm_build_tree needs for n particles, a tree
+ * of `levels` levels (leaf level L, 0 <= L <= 12) and expansions of up to p_max
+ * terms (1 <= p_max <= 40).  `bytes` is a host pointer.  The workspace holds the
+ * sorted particles, the leaf ranges, the multipole and local coefficients of
+ * levels 2..L (Section 3.3: 4^l boxes per level) and the translation tables. */
+vfmm_status_t vfmm_workspace_bytes(int64_t n, int32_t levels, int32_t p_max, size_t* bytes);
+
+/* Builds the quadtree of Section 3.3 over the particles (x, y) (device, n each,
+ * 1 <= n <= 2^31 - 1): root box, leaf of every particle, stable sort of the
+ * particles by leaf (row-major leaf order, input order kept inside a leaf), leaf
+ * ranges and box-local coordinates.
+ *   domain    (host, may be NULL): {x0, y0, S}, lower-left corner and side of the
+ *             root square; NULL = bounding square of the particles.  Particles
+ *             outside a given square are clamped into its edge boxes.
+ *   workspace (device): at least vfmm_workspace_bytes(n, levels, p_max) bytes,
+ *             256-byte aligned; owned by the caller, used by the tree until
+ *             vfmm_tree_destroy.  x and y are read only during this call's
+ *             kernels; they may change afterwards.
+ *   out       (host): receives the tree handle.
+ * Errors: VFMM_ERR_INVALID_ARG (null pointer, n, levels or p_max out of range,
+ * non-finite or non-positive domain side), VFMM_ERR_WORKSPACE (too small or
+ * misaligned), VFMM_ERR_HIP (launch failure). */
+vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32_t levels,
+                              const double* domain, int32_t p_max, void* workspace,
+                              size_t ws_bytes, void* stream, vfmm_tree_t* out);
+
+/* FMM velocity of eq. 9 (the approximation of eq. 10): u[n], v[n] (device) at
+ * every particle of the tree, in input order.
+ *   gamma     (device, n): circulations, input order (eq. 2, 13).
+ *   sigma     : Gaussian core size (eq. 3, 6), finite and > 0.
+ *   p         : expansion terms, 1 <= p <= p_max of the tree (eq. 21).
+ *   precision : VFMM_FP64, VFMM_FP32, VFMM_M2L_BF16 or VFMM_M2L_FP16.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
+                                int32_t precision, double* u, double* v, void* stream);
+
+/* As vfmm_fmm_velocity, writing only the near part (P2P over the local list,
+ * eq. 10 first sum), only the far part (the expansions, eq. 10 second sum) or
+ * both (`parts` = VFMM_PART_NEAR, VFMM_PART_FAR or VFMM_PART_ALL). */
+vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t tree, const double* gamma, double sigma,
+                                      int32_t p, int32_t precision, int32_t parts, double* u,
+                                      double* v, void* stream);
+
+/* Float64 direct sum of eq. 7 / eq. 9 over all n particles, evaluated at the
+ * particles listed in `targets` (device int64, n_targets entries, each in
+ * [0, n)) or at all particles when targets is NULL (then n_targets must be n).
+ * u, v (device) receive n_targets values, in the order of `targets`.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_direct_velocity(const double* x, const double* y, const double* gamma,
+                                   int64_t n, double sigma, const int64_t* targets,
+                                   int64_t n_targets, double* u, double* v, void* stream);
+
+/* Bytes of device scratch needed by vfmm_error_metrics. */
+size_t vfmm_metrics_scratch_bytes(void);
+
+/* Error of (u, v) against a reference (u_ref, v_ref), all device float64 [n]
+ * (Section 5.1: errors normalised by the maximum velocity).  Writes out[3]
+ * (device): max_i |dW_i|, sum_i |dW_i|^2, max_i |W_ref,i|, so that
+ * e_max = out[0] / out[2] and e_rms = sqrt(out[1] / n) / out[2].
+ *   scratch (device): vfmm_metrics_scratch_bytes() bytes.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_error_metrics(const double* u, const double* v, const double* u_ref,
+                                 const double* v_ref, int64_t n, void* scratch, double* out,
+                                 void* stream);
+
+/* Copies tree arrays out of the workspace (device destinations, any may be
+ * NULL): root[4] = {x0, y0, S, w_L}; perm[n] = input index of each sorted
+ * particle; leaf_start[4^L + 1] = first sorted position of each leaf
+ * (row-major leaf index iy * 2^L + ix). */
+vfmm_status_t vfmm_tree_arrays(vfmm_tree_t tree, double* root, int32_t* perm,
+                               int32_t* leaf_start, void* stream);
+
+/* Copies the coefficients of the last vfmm_fmm_velocity call at `level`
+ * (2 <= level <= L) out as float64 complex pairs: dst[(box * p + k) * 2 + {0,1}]
+ * for the 4^level boxes in row-major order (device).  kind 0 = multipole
+ * M_k = sum_i Gamma_i ((z_i - c)/w)^k; kind 1 = local L_n with the far-field
+ * conjugate velocity W(z) = (-j / (2 pi w)) sum_n L_n ((z - c)/w)^n, where c is
+ * the box centre and w the box side at that level.  Coefficients of an FP32
+ * evaluation are widened to float64. */
+vfmm_status_t vfmm_tree_expansions(vfmm_tree_t tree, int32_t kind, int32_t level, double* dst,
+                                   void* stream);
+
+/* Rebuilds an existing tree in place for new positions (same n, levels, p_max
+ * and workspace), as a time-stepping loop does after moving the particles.
+ * Same conventions and errors as vfmm_build_tree. */
+vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double* y,
+                                const double* domain, void* stream);
+
+/* Phase timing.  Phases of one vfmm_fmm_velocity call, in order:
+ * 0 gather circulations, 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
+ * 4 M2L + L2L (levels 2..L), 5 P2P + L2P + combine.  After
+ * vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
+ * next max_calls evaluations record HIP events at the phase boundaries on their
+ * stream (no synchronisation).  vfmm_tree_read_timing waits for the recorded
+ * events, writes ms[call * VFMM_N_PHASES + phase] (host, max_calls *
+ * VFMM_N_PHASES doubles) and *n_calls (host), and starts a new recording.
+ * Phases skipped by a call read 0. */
+#define VFMM_N_PHASES 6
+vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t tree, int32_t max_calls);
+vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t tree, double* ms, int32_t* n_calls);
+
+/* Releases the tree handle (not the caller's workspace).  NULL is ignored. */
+void vfmm_tree_destroy(vfmm_tree_t tree);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VFMM_H */

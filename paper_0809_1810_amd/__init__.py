@@ -1,0 +1,16 @@
+"""MI355X-native vortex-particle Fast Multipole Method (Cruz & Barba 2008).
+
+The computation lives in the HIP library ``libvfmm.so`` (C ABI in
+``include/vfmm.h``); this package is its thin Python binding.
+"""
+from .vfmm import (FP32, FP64, M2L_BF16, M2L_FP16, MAX_LEVELS, MAX_P, PART_ALL, PART_FAR,
+                   PART_NEAR, PRECISIONS, Tree, VfmmError, VfmmUnavailable, build_tree,
+                   direct_velocity, error_metrics, fmm_velocity, header_symbols, lib,
+                   workspace_bytes)
+
+__all__ = [
+    "FP32", "FP64", "M2L_BF16", "M2L_FP16", "MAX_LEVELS", "MAX_P", "PART_ALL", "PART_FAR",
+    "PART_NEAR", "PRECISIONS", "Tree", "VfmmError", "VfmmUnavailable", "build_tree",
+    "direct_velocity", "error_metrics", "fmm_velocity", "header_symbols", "lib",
+    "workspace_bytes",
+]

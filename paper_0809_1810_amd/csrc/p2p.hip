@@ -1,0 +1,183 @@
+// Near field (P2P) with the far-field evaluation (L2P), the near + far sum and
+// the scatter back to the caller's particle order fused into one kernel
+// (Cruz & Barba 2008, eq. 10: f = f_near + f_far).
+//
+// P2P: for each target i, the regularised Biot-Savart sum (eq. 6) over the
+// particles of the 3 x 3 local list of its leaf (Section 3.3.1), self term
+// excluded; it contributes exactly zero because the pair offset is (0, 0).
+// L2P: W_far = (-j / (2 pi w)) sum_n L_n ((z - c)/w)^n, Horner's rule.
+//
+// Work decomposition: one wave per tile of <= 64 targets of one leaf (tiles
+// built with the tree), one target per lane.  The source loop runs over the 9
+// leaf ranges of the local list; the source index is the same for all lanes of
+// the wave, so sources are fetched with scalar loads and broadcast.  Source
+// coordinates are box-local; the target is shifted once per neighbour leaf by
+// the exact centre offset.
+//
+// FP32 variant: per-pair arithmetic in FP32 with the hardware exp2 and
+// reciprocal; partial sums over chunks of 64 sources are added into a
+// compensated (TwoSum) FP32 accumulator, which keeps the rounding of long
+// source loops (up to ~1e5 sources per target) near the per-term level.
+// FP64 variant: plain FP64 with expm1.
+#include "vfmm_device.hpp"
+
+namespace vfmm {
+
+namespace {
+
+constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+
+struct Acc32 {
+  float s, c;
+  __device__ __forceinline__ void add(float x) {  // Knuth TwoSum
+    const float t = s + x;
+    const float z = t - s;
+    c += (s - (t - z)) + (x - z);
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return double(s) + double(c); }
+};
+
+template <typename R> struct P2PMath;
+
+template <> struct P2PMath<double> {
+  // factor = (1 - exp(-r2 / 2 sigma^2)) / r2 ; kexp = -1 / (2 sigma^2)
+  __device__ __forceinline__ static double factor(double r2, double kexp) {
+    return -expm1(r2 * kexp) / r2;
+  }
+};
+
+template <> struct P2PMath<float> {
+  // kexp = -log2(e) / (2 sigma^2)
+  __device__ __forceinline__ static float factor(float r2, float kexp) {
+    const float e = __builtin_amdgcn_exp2f(r2 * kexp);
+    return (1.0f - e) * __builtin_amdgcn_rcpf(r2);
+  }
+};
+
+template <typename R, int PMAX>
+__global__ void __launch_bounds__(256) k_p2p_l2p(
+    const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
+    const Tile* __restrict__ tiles, const int32_t* __restrict__ ntiles,
+    const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::C* __restrict__ le_leaf, R kexp, int parts,
+    const int32_t* __restrict__ perm, double* __restrict__ u, double* __restrict__ v) {
+  using C = typename Types<R>::C;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const Tile tile = tiles[wid];
+  const bool active = lane < tile.count;
+  const int32_t i = tile.start + (active ? lane : 0);
+  const auto tp = part[i];
+  const int m = 1 << levels;
+  const int bx = tile.leaf & (m - 1), by = tile.leaf >> levels;
+  const double w = root[3];
+
+  double nu = 0.0, nv = 0.0;
+  if (parts & 1) {
+    const R tiny = R(w * w * 0x1p-80);
+    Acc32 au{0.f, 0.f}, av{0.f, 0.f};
+    for (int oy = -1; oy <= 1; ++oy) {
+      const int sy = by + oy;
+      if (sy < 0 || sy >= m) continue;
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int sx = bx + ox;
+        if (sx < 0 || sx >= m) continue;
+        const int sl = sy * m + sx;
+        const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
+        // target relative to the source leaf centre
+        const R tx = tp.x - R(double(ox) * w);
+        const R ty = tp.y - R(double(oy) * w);
+        for (int32_t j0 = js; j0 < je; j0 += 64) {
+          const int32_t j1 = min(j0 + 64, je);
+          R cu = R(0), cv = R(0);
+          for (int32_t j = j0; j < j1; ++j) {
+            const auto s = part[j];
+            const R dx = tx - s.x;
+            const R dy = ty - s.y;
+            const R r2 = dx * dx + dy * dy + tiny;
+            const R f = s.g * P2PMath<R>::factor(r2, kexp);
+            cu -= f * dy;
+            cv += f * dx;
+          }
+          if constexpr (sizeof(R) == 4) {
+            au.add(cu);
+            av.add(cv);
+          } else {
+            nu += cu;
+            nv += cv;
+          }
+        }
+      }
+    }
+    if constexpr (sizeof(R) == 4) {
+      nu = au.value();
+      nv = av.value();
+    }
+    nu *= kInv2Pi;
+    nv *= kInv2Pi;
+  }
+
+  double fu = 0.0, fv = 0.0;
+  if ((parts & 2) && levels >= 2) {
+    const R inv_w = R(1.0 / w);
+    const C z = cmake<C>(tp.x * inv_w, tp.y * inv_w);
+    const C* L = le_leaf + int64_t(tile.leaf) * p;
+    C acc = cmake<C>(R(0), R(0));
+#pragma unroll
+    for (int k = PMAX - 1; k >= 0; --k) {
+      if (k < p) {
+        const C lk = L[k];
+        acc = cmul(acc, z);
+        acc.x += lk.x;
+        acc.y += lk.y;
+      }
+    }
+    // (-j/(2 pi w)) (a + j b) = (b - j a)/(2 pi w); u = Re, v = -Im
+    const double sc = kInv2Pi / w;
+    fu = double(acc.y) * sc;
+    fv = double(acc.x) * sc;
+  }
+
+  if (active) {
+    const int32_t o = perm[i];
+    u[o] = nu + fu;
+    v[o] = nv + fv;
+  }
+}
+
+template <typename R, int PMAX>
+void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+              double* u, double* v, hipStream_t st) {
+  using C = typename Types<R>::C;
+  const auto* part = reinterpret_cast<const typename Types<R>::Part*>(
+      sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32));
+  const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
+  const double k64 = -1.0 / (2.0 * sigma * sigma);
+  const R kexp = sizeof(R) == 8 ? R(k64) : R(k64 * 1.4426950408889634074);
+  const unsigned blocks = unsigned((lay.max_tiles + 3) / 4);
+  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX>), dim3(blocks), dim3(256), 0, st, part, t.leaf_start,
+                     t.tiles, t.ntiles, t.root, levels, p, le, kexp, parts, t.perm, u, v);
+}
+
+template <typename R>
+void launch_r(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+              double* u, double* v, hipStream_t st) {
+  if (p <= 8) launch_t<R, 8>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 16) launch_t<R, 16>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 24) launch_t<R, 24>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 32) launch_t<R, 32>(t, lay, levels, p, sigma, parts, u, v, st);
+  else launch_t<R, 40>(t, lay, levels, p, sigma, parts, u, v, st);
+}
+
+}  // namespace
+
+hipError_t launch_p2p_l2p(const TreeDev& t, const Layout& lay, int levels, int p, int prec,
+                          double sigma, int parts, double* u, double* v, hipStream_t st) {
+  if (prec == kFP64) launch_r<double>(t, lay, levels, p, sigma, parts, u, v, st);
+  else launch_r<float>(t, lay, levels, p, sigma, parts, u, v, st);
+  return hipGetLastError();
+}
+
+}  // namespace vfmm

@@ -1,0 +1,391 @@
+// Uniform quadtree construction on the GPU (Section 3.3, Fig. 6).
+//
+// Steps: bounding square of the particles (root box, level 0), leaf key of every
+// particle at level L, stable LSD radix sort of the keys (so particles of a leaf
+// keep their input order), leaf ranges by binary search, box-local coordinates,
+// and the list of P2P target tiles (<= 64 targets of one leaf each).
+//
+// Leaf convention: ix = clamp(floor(((x - x0) / S) * 2^L), 0, 2^L - 1), the same
+// for y; key = iy * 2^L + ix.  The root is the bounding square of side
+// S = max extent * (1 + 2^-20) centred on the bounding-box midpoint (S = 1 for a
+// zero extent), unless the caller gives (x0, y0, S).  These floating-point
+// operations are written without contraction so that the integer leaf decision
+// is reproducible bit for bit.
+#include "vfmm_internal.hpp"
+
+namespace vfmm {
+
+namespace {
+
+__device__ inline double dmin(double a, double b) { return a < b ? a : b; }
+__device__ inline double dmax(double a, double b) { return a > b ? a : b; }
+
+__global__ void __launch_bounds__(256) k_bbox_partial(const double* __restrict__ x,
+                                                      const double* __restrict__ y, int64_t n,
+                                                      double* __restrict__ part) {
+  __shared__ double s[4][256];
+  double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    double xi = x[i], yi = y[i];
+    a = dmin(a, xi); b = dmax(b, xi); c = dmin(c, yi); d = dmax(d, yi);
+  }
+  s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c; s[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      int o = threadIdx.x + st;
+      s[0][threadIdx.x] = dmin(s[0][threadIdx.x], s[0][o]);
+      s[1][threadIdx.x] = dmax(s[1][threadIdx.x], s[1][o]);
+      s[2][threadIdx.x] = dmin(s[2][threadIdx.x], s[2][o]);
+      s[3][threadIdx.x] = dmax(s[3][threadIdx.x], s[3][o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_root(const double* __restrict__ part, int nb,
+                                              int has_domain, double dx0, double dy0, double ds,
+                                              int levels, double* __restrict__ root) {
+#pragma clang fp contract(off)
+  __shared__ double s[4][256];
+  double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a = dmin(a, part[4 * i + 0]); b = dmax(b, part[4 * i + 1]);
+    c = dmin(c, part[4 * i + 2]); d = dmax(d, part[4 * i + 3]);
+  }
+  s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c; s[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      int o = threadIdx.x + st;
+      s[0][threadIdx.x] = dmin(s[0][threadIdx.x], s[0][o]);
+      s[1][threadIdx.x] = dmax(s[1][threadIdx.x], s[1][o]);
+      s[2][threadIdx.x] = dmin(s[2][threadIdx.x], s[2][o]);
+      s[3][threadIdx.x] = dmax(s[3][threadIdx.x], s[3][o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double x0, y0, S;
+    if (has_domain) {
+      x0 = dx0; y0 = dy0; S = ds;
+    } else {
+      double xmin = s[0][0], xmax = s[1][0], ymin = s[2][0], ymax = s[3][0];
+      double ext = dmax(xmax - xmin, ymax - ymin);
+      S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : 1.0;
+      x0 = 0.5 * (xmin + xmax) - 0.5 * S;
+      y0 = 0.5 * (ymin + ymax) - 0.5 * S;
+    }
+    root[0] = x0; root[1] = y0; root[2] = S;
+    root[3] = S / double(1LL << levels);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
+                                              const double* __restrict__ y, int64_t n,
+                                              const double* __restrict__ root, int levels,
+                                              uint32_t* __restrict__ keys,
+                                              int32_t* __restrict__ idx) {
+#pragma clang fp contract(off)
+  int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double x0 = root[0], y0 = root[1], S = root[2];
+  const int m = 1 << levels;
+  const double scale = double(m);
+  double fx = floor(((x[i] - x0) / S) * scale);
+  double fy = floor(((y[i] - y0) / S) * scale);
+  int ix = fx < 0.0 ? 0 : (fx > double(m - 1) ? m - 1 : int(fx));
+  int iy = fy < 0.0 ? 0 : (fy > double(m - 1) ? m - 1 : int(fy));
+  keys[i] = (uint32_t(iy) << levels) | uint32_t(ix);
+  idx[i] = int32_t(i);
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum of uint32, in place, three phases.
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns the
+// exclusive prefix and writes the block total.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t ws[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) ws[wave] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += ws[w];
+  uint32_t t = ws[0] + ws[1] + ws[2] + ws[3];
+  __syncthreads();
+  *total = t;
+  return pre + incl - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t* __restrict__ a,
+                                                            int64_t n, uint32_t* __restrict__ tmp) {
+  const int64_t base = blockIdx.x * int64_t(kScanPerBlock) + threadIdx.x * int64_t(kScanItems);
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += a[base + k];
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_tmp(uint32_t* __restrict__ tmp, int64_t nb) {
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += kScanBlock) {
+    int64_t i = base + threadIdx.x;
+    uint32_t v = i < nb ? tmp[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, &tot);
+    uint32_t c = carry;
+    if (i < nb) tmp[i] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c + tot;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t* __restrict__ a, int64_t n,
+                                                           const uint32_t* __restrict__ tmp) {
+  const int64_t base = blockIdx.x * int64_t(kScanPerBlock) + threadIdx.x * int64_t(kScanItems);
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? a[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + tmp[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) a[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+  hipLaunchKernelGGL(k_scan_tmp, dim3(1), dim3(kScanBlock), 0, st, tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix sort
+// Stable LSD counting sort on `bits` (<= 8) key bits per pass.  counts is
+// digit-major: counts[d * nblk + b].
+
+__global__ void __launch_bounds__(kSortBlock) k_radix_count(const uint32_t* __restrict__ keys,
+                                                            int64_t n, int shift, uint32_t mask,
+                                                            uint32_t* __restrict__ counts, int nblk) {
+  __shared__ uint32_t hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * int64_t(kSortPerBlock);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = base + r * kSortBlock + threadIdx.x;
+    if (i < n) atomicAdd(&hist[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  counts[int64_t(threadIdx.x) * nblk + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ iin, int64_t n, int shift,
+    uint32_t mask, int bits, const uint32_t* __restrict__ offs, int nblk,
+    uint32_t* __restrict__ kout, int32_t* __restrict__ iout) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  run[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * int64_t(kSortPerBlock);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kSortBlock + tid;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & mask;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const uint64_t lower = m & below;
+    const uint32_t rank_w = __popcll(lower);
+    if (valid && lower == 0) wc[wave][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank_w;
+      for (int w = 0; w < wave; ++w) pos += wc[w][d];
+      kout[pos] = k;
+      iout[pos] = iin[i];
+    }
+    __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int64_t nleaves, int32_t* __restrict__ start) {
+  int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k > nleaves) return;
+  int64_t lo = 0, hi = n;  // first position with key >= k
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < uint32_t(k)) lo = mid + 1; else hi = mid;
+  }
+  start[k] = int32_t(lo);
+}
+
+__global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const uint32_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ perm, int64_t n,
+                                                      const double* __restrict__ root, int levels,
+                                                      Part64* __restrict__ p64,
+                                                      Part32* __restrict__ p32) {
+#pragma clang fp contract(off)
+  int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t key = keys[i];
+  const int ix = int(key & ((1u << levels) - 1u)), iy = int(key >> levels);
+  const double w = root[3];
+  const double cx = root[0] + (double(ix) + 0.5) * w;
+  const double cy = root[1] + (double(iy) + 0.5) * w;
+  const int32_t j = perm[i];
+  const double lx = x[j] - cx, ly = y[j] - cy;
+  p64[i] = Part64{lx, ly, 0.0, 0.0};
+  p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
+}
+
+__global__ void __launch_bounds__(256) k_tile_counts(const int32_t* __restrict__ start,
+                                                     int64_t nleaves, uint32_t* __restrict__ cnt) {
+  int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k > nleaves) return;
+  cnt[k] = k < nleaves ? uint32_t((start[k + 1] - start[k] + kTile - 1) / kTile) : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_tile_fill(const int32_t* __restrict__ start,
+                                                   const uint32_t* __restrict__ off, int64_t nleaves,
+                                                   Tile* __restrict__ tiles,
+                                                   int32_t* __restrict__ ntiles) {
+  int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k == 0) *ntiles = int32_t(off[nleaves]);
+  if (k >= nleaves) return;
+  const int32_t s = start[k], c = start[k + 1] - s;
+  uint32_t o = off[k];
+  for (int32_t t = 0; t * kTile < c; ++t) {
+    int32_t cc = c - t * kTile;
+    tiles[o + t] = Tile{int32_t(k), s + t * kTile, cc < kTile ? cc : kTile, 0};
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gather_gamma(const double* __restrict__ gamma,
+                                                      const int32_t* __restrict__ perm, int64_t n,
+                                                      Part64* __restrict__ p64,
+                                                      Part32* __restrict__ p32) {
+  int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double g = gamma[perm[i]];
+  p64[i].g = g;
+  p32[i].g = float(g);
+}
+
+inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
+                             const double* domain, const Layout& lay, char* ws, TreeDev& t,
+                             hipStream_t st) {
+  double* root = reinterpret_cast<double*>(ws + lay.root);
+  double* bbox = reinterpret_cast<double*>(ws + lay.bbox);
+  uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + lay.keys0);
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(ws + lay.keys1);
+  int32_t* i0 = reinterpret_cast<int32_t*>(ws + lay.idx0);
+  int32_t* i1 = reinterpret_cast<int32_t*>(ws + lay.idx1);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + lay.scan_tmp);
+  int32_t* lstart = reinterpret_cast<int32_t*>(ws + lay.leaf_start);
+  uint32_t* toff = reinterpret_cast<uint32_t*>(ws + lay.tile_off);
+
+  const int nbb = int(nblocks(n, 256) < unsigned(kBBoxBlocks) ? nblocks(n, 256) : kBBoxBlocks);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, st, x, y, n, bbox);
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, st, bbox, nbb, domain ? 1 : 0,
+                     domain ? domain[0] : 0.0, domain ? domain[1] : 0.0,
+                     domain ? domain[2] : 1.0, levels, root);
+  hipLaunchKernelGGL(k_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, n, root, levels, k0,
+                     i0);
+  const int nblk = int(lay.sort_blocks);
+  int bits_left = 2 * levels, shift = 0;
+  while (bits_left > 0) {
+    const int bits = bits_left < 8 ? bits_left : 8;
+    const uint32_t mask = (1u << bits) - 1u;
+    hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kSortBlock), 0, st, k0, n, shift, mask,
+                       counts, nblk);
+    hipError_t e = scan_exclusive(counts, int64_t(256) * nblk, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortBlock), 0, st, k0, i0, n, shift,
+                       mask, bits, counts, nblk, k1, i1);
+    uint32_t* tk = k0; k0 = k1; k1 = tk;
+    int32_t* ti = i0; i0 = i1; i1 = ti;
+    shift += bits;
+    bits_left -= bits;
+  }
+  const int64_t nl = lay.nleaves;
+  hipLaunchKernelGGL(k_leaf_start, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, k0, n, nl,
+                     lstart);
+  t.root = root;
+  t.keys = k0;
+  t.perm = i0;
+  t.leaf_start = lstart;
+  t.tiles = reinterpret_cast<Tile*>(ws + lay.tiles);
+  t.ntiles = reinterpret_cast<int32_t*>(ws + lay.ntiles);
+  t.part64 = reinterpret_cast<Part64*>(ws + lay.part64);
+  t.part32 = reinterpret_cast<Part32*>(ws + lay.part32);
+  t.me = ws + lay.me;
+  t.le = ws + lay.le;
+  t.ops = ws + lay.ops;
+  t.reduce = reinterpret_cast<double*>(ws + lay.reduce);
+  hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, k0, i0, n,
+                     root, levels, t.part64, t.part32);
+  hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
+                     toff);
+  hipError_t e = scan_exclusive(toff, nl + 1, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(nl, 256)), dim3(256), 0, st, lstart, toff, nl,
+                     t.tiles, t.ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_gamma, dim3(nblocks(n, 256)), dim3(256), 0, st, gamma, t.perm, n,
+                     t.part64, t.part32);
+  return hipGetLastError();
+}
+
+}  // namespace vfmm

@@ -1,0 +1,353 @@
+// C ABI of the vortex-particle FMM library: argument validation, workspace
+// layout, and the order of the kernel launches (upward sweep, downward sweep,
+// near field + evaluation; Cruz & Barba 2008, Section 3.1 and Fig. 3).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vfmm.h"
+#include "vfmm_device.hpp"
+
+using namespace vfmm;
+
+struct vfmm_tree_s {
+  Layout lay;
+  TreeDev dev;
+  char* ws;
+  int64_t n;
+  int levels;
+  int p_max;
+  int ops_p;        // order the operator tables were built for (-1 = none)
+  int last_p;       // order / precision of the last evaluation
+  int last_prec;
+  std::vector<hipEvent_t> ev;  // phase-timing ring: (VFMM_N_PHASES + 1) per call
+  int t_slots;
+  int t_used;
+  ~vfmm_tree_s() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+vfmm_status_t fail(vfmm_status_t s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+vfmm_status_t fail(vfmm_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+vfmm_status_t hip_fail(hipError_t e, const char* where) {
+  return fail(VFMM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool finite_pos(double s) { return std::isfinite(s) && s > 0.0; }
+
+vfmm_status_t check_common(int64_t n, int32_t levels, int32_t p_max) {
+  if (n < 1 || n > 2147483647LL) return fail(VFMM_ERR_INVALID_ARG, "n=%lld out of [1, 2^31-1]", (long long)n);
+  if (levels < 0 || levels > kMaxLevels)
+    return fail(VFMM_ERR_INVALID_ARG, "levels=%d out of [0, %d]", levels, kMaxLevels);
+  if (p_max < 1 || p_max > kMaxP) return fail(VFMM_ERR_INVALID_ARG, "p=%d out of [1, %d]", p_max, kMaxP);
+  return VFMM_OK;
+}
+
+template <typename R>
+__global__ void k_copy_expansion(const typename Types<R>::C* __restrict__ src, int64_t count,
+                                 double* __restrict__ dst) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= count) return;
+  const auto c = src[i];
+  dst[2 * i] = double(c.x);
+  dst[2 * i + 1] = double(c.y);
+}
+
+}  // namespace
+
+namespace vfmm {
+
+Layout make_layout(int64_t n, int levels, int p_max) {
+  Layout L{};
+  L.n = n;
+  L.levels = levels;
+  L.p_max = p_max;
+  L.nleaves = int64_t(1) << (2 * levels);
+  L.sort_blocks = (n + kSortPerBlock - 1) / kSortPerBlock;
+  L.count_len = 256 * L.sort_blocks;
+  const int64_t nonempty = n < L.nleaves ? n : L.nleaves;
+  L.max_tiles = (n + kTile - 1) / kTile + nonempty;
+  const int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
+  const int64_t nbox = n_boxes_2_to(levels);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+  L.root = take(8 * sizeof(double));
+  L.bbox = take(size_t(kBBoxBlocks) * 4 * sizeof(double));
+  L.keys0 = take(size_t(n) * 4);
+  L.keys1 = take(size_t(n) * 4);
+  L.idx0 = take(size_t(n) * 4);
+  L.idx1 = take(size_t(n) * 4);
+  L.counts = take(size_t(L.count_len) * 4);
+  L.scan_tmp = take(size_t(scan_tmp) * 4);
+  L.leaf_start = take(size_t(L.nleaves + 1) * 4);
+  L.tile_off = take(size_t(L.nleaves + 1) * 4);
+  L.tiles = take(size_t(L.max_tiles) * sizeof(Tile));
+  L.ntiles = take(4);
+  L.part64 = take(size_t(n) * sizeof(Part64));
+  L.part32 = take(size_t(n) * sizeof(Part32));
+  L.me = take(size_t(nbox) * p_max * sizeof(double2));
+  L.le = take(size_t(nbox) * p_max * sizeof(double2));
+  L.ops = take(ops_bytes(p_max));
+  L.reduce = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace vfmm
+
+extern "C" {
+
+int32_t vfmm_version(void) { return 100; }
+
+const char* vfmm_status_string(vfmm_status_t s) {
+  switch (s) {
+    case VFMM_OK: return "ok";
+    case VFMM_ERR_INVALID_ARG: return "invalid argument";
+    case VFMM_ERR_HIP: return "HIP runtime error";
+    case VFMM_ERR_UNSUPPORTED: return "unsupported";
+    case VFMM_ERR_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+const char* vfmm_last_error(void) { return g_err.c_str(); }
+
+vfmm_status_t vfmm_workspace_bytes(int64_t n, int32_t levels, int32_t p_max, size_t* bytes) {
+  if (!bytes) return fail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  vfmm_status_t s = check_common(n, levels, p_max);
+  if (s) return s;
+  *bytes = make_layout(n, levels, p_max).total;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32_t levels,
+                              const double* domain, int32_t p_max, void* workspace,
+                              size_t ws_bytes, void* stream, vfmm_tree_t* out) {
+  if (!out) return fail(VFMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!x || !y) return fail(VFMM_ERR_INVALID_ARG, "x or y is NULL");
+  if (!workspace) return fail(VFMM_ERR_INVALID_ARG, "workspace is NULL");
+  vfmm_status_t s = check_common(n, levels, p_max);
+  if (s) return s;
+  if (domain && (!std::isfinite(domain[0]) || !std::isfinite(domain[1]) || !finite_pos(domain[2])))
+    return fail(VFMM_ERR_INVALID_ARG, "domain must be finite with side > 0");
+  const Layout lay = make_layout(n, levels, p_max);
+  if (ws_bytes < lay.total)
+    return fail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  vfmm_tree_s* t = new (std::nothrow) vfmm_tree_s{};
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "host allocation of the tree handle failed");
+  t->lay = lay;
+  t->ws = static_cast<char*>(workspace);
+  t->n = n;
+  t->levels = levels;
+  t->p_max = p_max;
+  t->ops_p = -1;
+  t->last_p = -1;
+  t->last_prec = -1;
+  hipError_t e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, t->dev,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    delete t;
+    return hip_fail(e, "vfmm_build_tree");
+  }
+  *out = t;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                                      int32_t precision, int32_t parts, double* u, double* v,
+                                      void* stream) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  if (!gamma || !u || !v) return fail(VFMM_ERR_INVALID_ARG, "gamma, u or v is NULL");
+  if (!finite_pos(sigma)) return fail(VFMM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  if (p < 1 || p > t->p_max)
+    return fail(VFMM_ERR_INVALID_ARG, "p=%d out of [1, p_max=%d]", p, t->p_max);
+  if (precision < VFMM_FP64 || precision > VFMM_M2L_FP16)
+    return fail(VFMM_ERR_INVALID_ARG, "unknown precision %d", precision);
+  if (parts < 1 || parts > 3) return fail(VFMM_ERR_INVALID_ARG, "parts must be 1, 2 or 3");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int L = t->levels;
+  // the reduced-precision M2L variants share the FP32 pipeline
+  const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
+  hipEvent_t* ev = nullptr;
+  if (t->t_used < t->t_slots) ev = &t->ev[size_t(t->t_used++) * (VFMM_N_PHASES + 1)];
+  auto mark = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  };
+  mark(0);
+  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, st);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  mark(1);
+  const bool far = L >= 2 && (parts & VFMM_PART_FAR);
+  if (far && t->ops_p != p) {
+    e = launch_build_ops(t->dev, p, prec, st);
+    if (e != hipSuccess) return hip_fail(e, "operator tables");
+    t->ops_p = p;
+  }
+  mark(2);
+  if (far) {
+    e = launch_p2m(t->dev, L, p, prec, st);
+    if (e != hipSuccess) return hip_fail(e, "P2M");
+  }
+  mark(3);
+  if (far) {
+    e = launch_m2m(t->dev, L, p, prec, st);
+    if (e != hipSuccess) return hip_fail(e, "M2M");
+  }
+  mark(4);
+  if (far) {
+    e = launch_downward(t->dev, L, p, prec, st);
+    if (e != hipSuccess) return hip_fail(e, "M2L/L2L");
+    t->last_p = p;
+    t->last_prec = prec;
+  }
+  mark(5);
+  e = launch_p2p_l2p(t->dev, t->lay, L, p, prec, sigma, parts, u, v, st);
+  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
+  mark(6);
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                                int32_t precision, double* u, double* v, void* stream) {
+  return vfmm_fmm_velocity_parts(t, gamma, sigma, p, precision, VFMM_PART_ALL, u, v, stream);
+}
+
+vfmm_status_t vfmm_direct_velocity(const double* x, const double* y, const double* gamma,
+                                   int64_t n, double sigma, const int64_t* targets,
+                                   int64_t n_targets, double* u, double* v, void* stream) {
+  if (!x || !y || !gamma || !u || !v) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1) return fail(VFMM_ERR_INVALID_ARG, "n must be >= 1");
+  if (!finite_pos(sigma)) return fail(VFMM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  if (!targets && n_targets != n)
+    return fail(VFMM_ERR_INVALID_ARG, "n_targets must equal n when targets is NULL");
+  if (n_targets < 0) return fail(VFMM_ERR_INVALID_ARG, "n_targets < 0");
+  if (n_targets == 0) return VFMM_OK;
+  hipError_t e = launch_direct(x, y, gamma, n, sigma, targets, n_targets, u, v,
+                               static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "direct");
+}
+
+size_t vfmm_metrics_scratch_bytes(void) { return size_t(kReduceBlocks) * 3 * sizeof(double); }
+
+vfmm_status_t vfmm_error_metrics(const double* u, const double* v, const double* ur,
+                                 const double* vr, int64_t n, void* scratch, double* out,
+                                 void* stream) {
+  if (!u || !v || !ur || !vr || !scratch || !out) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1) return fail(VFMM_ERR_INVALID_ARG, "n must be >= 1");
+  hipError_t e = launch_error_metrics(u, v, ur, vr, n, static_cast<double*>(scratch), out,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "metrics");
+}
+
+vfmm_status_t vfmm_tree_arrays(vfmm_tree_t t, double* root, int32_t* perm, int32_t* leaf_start,
+                               void* stream) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (root && e == hipSuccess)
+    e = hipMemcpyAsync(root, t->dev.root, 4 * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (perm && e == hipSuccess)
+    e = hipMemcpyAsync(perm, t->dev.perm, size_t(t->n) * 4, hipMemcpyDeviceToDevice, st);
+  if (leaf_start && e == hipSuccess)
+    e = hipMemcpyAsync(leaf_start, t->dev.leaf_start, size_t(t->lay.nleaves + 1) * 4,
+                       hipMemcpyDeviceToDevice, st);
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "tree arrays");
+}
+
+vfmm_status_t vfmm_tree_expansions(vfmm_tree_t t, int32_t kind, int32_t level, double* dst,
+                                   void* stream) {
+  if (!t || !dst) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (kind != 0 && kind != 1) return fail(VFMM_ERR_INVALID_ARG, "kind must be 0 or 1");
+  if (t->last_p < 1) return fail(VFMM_ERR_INVALID_ARG, "no far-field evaluation yet");
+  if (level < 2 || level > t->levels)
+    return fail(VFMM_ERR_INVALID_ARG, "level %d out of [2, %d]", level, t->levels);
+  const int p = t->last_p;
+  const int64_t count = (int64_t(1) << (2 * level)) * p;
+  const int64_t off = level_offset(level) * p;
+  const void* base = kind == 0 ? t->dev.me : t->dev.le;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned nb = unsigned((count + 255) / 256);
+  if (t->last_prec == kFP64)
+    hipLaunchKernelGGL(k_copy_expansion<double>, dim3(nb), dim3(256), 0, st,
+                       static_cast<const double2*>(base) + off, count, dst);
+  else
+    hipLaunchKernelGGL(k_copy_expansion<float>, dim3(nb), dim3(256), 0, st,
+                       static_cast<const float2*>(base) + off, count, dst);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "expansions");
+}
+
+vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t t, const double* x, const double* y,
+                                const double* domain, void* stream) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  if (!x || !y) return fail(VFMM_ERR_INVALID_ARG, "x or y is NULL");
+  if (domain && (!std::isfinite(domain[0]) || !std::isfinite(domain[1]) || !finite_pos(domain[2])))
+    return fail(VFMM_ERR_INVALID_ARG, "domain must be finite with side > 0");
+  hipError_t e = launch_build_tree(x, y, t->n, t->levels, domain, t->lay, t->ws, t->dev,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "vfmm_tree_rebuild");
+  t->last_p = -1;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t t, int32_t max_calls) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  if (max_calls < 0 || max_calls > 100000) return fail(VFMM_ERR_INVALID_ARG, "max_calls out of range");
+  const size_t need = size_t(max_calls) * (VFMM_N_PHASES + 1);
+  while (t->ev.size() < need) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+    t->ev.push_back(e);
+  }
+  t->t_slots = max_calls;
+  t->t_used = 0;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t t, double* ms, int32_t* n_calls) {
+  if (!t || !ms || !n_calls) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  const int used = t->t_used;
+  for (int c = 0; c < used; ++c) {
+    hipEvent_t* ev = &t->ev[size_t(c) * (VFMM_N_PHASES + 1)];
+    hipError_t r = hipEventSynchronize(ev[VFMM_N_PHASES]);
+    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+    for (int k = 0; k < VFMM_N_PHASES; ++k) {
+      float f = 0.f;
+      r = hipEventElapsedTime(&f, ev[k], ev[k + 1]);
+      if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+      ms[size_t(c) * VFMM_N_PHASES + k] = double(f);
+    }
+  }
+  *n_calls = used;
+  t->t_used = 0;
+  return VFMM_OK;
+}
+
+void vfmm_tree_destroy(vfmm_tree_t t) { delete t; }
+
+}  // extern "C"

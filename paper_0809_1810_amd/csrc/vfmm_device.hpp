@@ -1,0 +1,50 @@
+// Small device-side helpers shared by the kernels: complex arithmetic on HIP
+// vector types and the per-precision particle / coefficient types.
+#pragma once
+
+#include "vfmm_internal.hpp"
+
+namespace vfmm {
+
+template <typename R> struct Types;
+template <> struct Types<double> { using C = double2; using Part = Part64; };
+template <> struct Types<float> { using C = float2; using Part = Part32; };
+
+template <typename C> __device__ __forceinline__ C cmake(decltype(C::x) r, decltype(C::x) i) {
+  C c; c.x = r; c.y = i; return c;
+}
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc += a * b
+template <typename C> __device__ __forceinline__ void cfma(C& acc, C a, C b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+}
+
+// Offsets of the interaction list: t = (ox, oy) in [-3,3]^2, table index.
+__host__ __device__ __forceinline__ int m2l_index(int ox, int oy) { return (oy + 3) * 7 + (ox + 3); }
+
+// Byte offsets inside the operator-table buffer for expansion order p.
+struct OpsLayout {
+  size_t m2m64, l2l64, m2l64, m2m32, l2l32, m2l32, mfma, total;
+};
+__host__ __device__ inline OpsLayout ops_layout(int p) {
+  OpsLayout o;
+  const size_t pp = size_t(p) * size_t(p);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off += (b + 255) & ~size_t(255); return r; };
+  o.m2m64 = take(4 * pp * sizeof(double2));
+  o.l2l64 = take(4 * pp * sizeof(double2));
+  o.m2l64 = take(kM2LOffsets * pp * sizeof(double2));
+  o.m2m32 = take(4 * pp * sizeof(float2));
+  o.l2l32 = take(4 * pp * sizeof(float2));
+  o.m2l32 = take(kM2LOffsets * pp * sizeof(float2));
+  // packed MFMA operands for the reduced-precision M2L (see m2l_mfma.hip)
+  const size_t pk = size_t((2 * p + 15) / 16) * 16;  // padded real K per offset
+  o.mfma = take(size_t(kM2LOffsets) * pk * pk * sizeof(float));
+  o.total = off;
+  return o;
+}
+
+}  // namespace vfmm

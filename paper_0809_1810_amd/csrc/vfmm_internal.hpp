@@ -1,0 +1,111 @@
+// Internal declarations of the vortex-particle FMM library (device helpers,
+// workspace layout, kernel launchers).  Not part of the public C ABI.
+//
+// Conventions used by every kernel (Cruz & Barba 2008, Section 3):
+//   * complex z = x + j y; the kernels carry the conjugate velocity
+//     W = u_x - j u_y, and the velocity of eq. 6 is u = (Re W, -Im W);
+//   * level l has 4^l boxes of side w_l = S / 2^l addressed row-major,
+//     box = iy * 2^l + ix (Fig. 6);
+//   * scaled multipole coefficients M_k = sum_i Gamma_i ((z_i - c)/w)^k
+//     (eq. 20 without the -j/2pi factor, divided by w^k);
+//   * scaled local coefficients L_n with
+//     W(z) = (-j / (2 pi w)) sum_n L_n ((z - c)/w)^n
+//     (the LE of Section 3.2.3 multiplied by w^(n+1) and by 2 pi j);
+//   * with these scalings every translation operator is level independent:
+//       M2M: M'_n = sum_{k<=n} C(n,k) d^(n-k) 2^-n M_k,       d = (c_child - c_parent)/w_child
+//       M2L: L_n  = sum_k (-1)^n C(n+k,k) t^-(n+k+1) M_k,      t = (c_target - c_source)/w
+//       L2L: L'_n = sum_{k>=n} C(k,n) d^(k-n) 2^-(k+1) L_k,   d = (c_child - c_parent)/w_child
+//     where d in {(+-1 +- j)/2} and t is an integer offset in [-3,3]^2 \ [-1,1]^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace vfmm {
+
+constexpr int kMaxP = 40;
+constexpr int kMaxLevels = 12;
+constexpr int kTile = 64;            // P2P targets per wave tile
+constexpr int kSortItems = 8;        // radix-sort elements per thread
+constexpr int kSortBlock = 256;      // radix-sort threads per block
+constexpr int kSortPerBlock = kSortItems * kSortBlock;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256;
+constexpr int kScanPerBlock = kScanItems * kScanBlock;
+constexpr int kBBoxBlocks = 512;
+constexpr int kReduceBlocks = 512;
+constexpr int kM2LOffsets = 49;      // 7x7 table indexed by t = (ox, oy) in [-3,3]^2
+
+enum Precision : int32_t {
+  kFP64 = 0,
+  kFP32 = 1,
+  kM2L_BF16 = 2,
+  kM2L_FP16 = 3,
+};
+
+// Particle record in leaf-sorted order: offsets from the leaf centre, circulation.
+struct __align__(32) Part64 { double x, y, g, pad; };
+struct __align__(16) Part32 { float x, y, g, pad; };
+
+struct Tile { int32_t leaf, start, count, pad; };
+
+inline __host__ __device__ int64_t level_offset(int l) {
+  // boxes of levels 2 .. l-1 stored before level l
+  int64_t off = 0;
+  for (int k = 2; k < l; ++k) off += int64_t(1) << (2 * k);
+  return off;
+}
+
+inline __host__ __device__ int64_t n_boxes_2_to(int L) {
+  return L < 2 ? 0 : level_offset(L + 1);
+}
+
+struct Layout {
+  size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
+  size_t leaf_start, tile_off, tiles, ntiles;
+  size_t part64, part32, me, le, ops, reduce, total;
+  int64_t n, nleaves, max_tiles, sort_blocks, count_len;
+  int levels, p_max;
+};
+
+Layout make_layout(int64_t n, int levels, int p_max);
+
+// Device tree state: pointers into the caller's workspace.
+struct TreeDev {
+  double* root;          // [0]=x0 [1]=y0 [2]=S [3]=w_L
+  uint32_t* keys;        // sorted leaf keys
+  int32_t* perm;         // sorted position -> input index
+  int32_t* leaf_start;   // [nleaves + 1]
+  Tile* tiles;           // P2P target tiles
+  int32_t* ntiles;       // device count of tiles
+  Part64* part64;
+  Part32* part32;
+  void* me;
+  void* le;
+  void* ops;
+  double* reduce;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
+                             const double* domain, const Layout& lay, char* ws,
+                             TreeDev& t, hipStream_t stream);
+hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n,
+                               hipStream_t stream);
+hipError_t launch_build_ops(const TreeDev& t, int p, int prec, hipStream_t stream);
+hipError_t launch_p2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+hipError_t launch_m2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+hipError_t launch_p2p_l2p(const TreeDev& t, const Layout& lay, int levels, int p, int prec,
+                          double sigma, int parts, double* u, double* v, hipStream_t stream);
+hipError_t launch_direct(const double* x, const double* y, const double* g, int64_t n,
+                         double sigma, const int64_t* targets, int64_t nt, double* u,
+                         double* v, hipStream_t stream);
+hipError_t launch_error_metrics(const double* u, const double* v, const double* ur,
+                                const double* vr, int64_t n, double* partial, double* out,
+                                hipStream_t stream);
+size_t ops_bytes(int p);
+
+}  // namespace vfmm

@@ -1,0 +1,265 @@
+"""Python binding of ``libvfmm.so`` (the C ABI declared in ``include/vfmm.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (float64 CUDA tensors, the workspace)
+and the current stream.  If the library has not been built, every entry point
+raises ``VfmmUnavailable``: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvfmm.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "vfmm.h")
+
+FP64, FP32, M2L_BF16, M2L_FP16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": M2L_BF16, "fp16": M2L_FP16}
+PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
+MAX_P, MAX_LEVELS = 40, 12
+
+OK = 0
+ERR_INVALID_ARG, ERR_HIP, ERR_UNSUPPORTED, ERR_WORKSPACE = -1, -3, -4, -6
+
+
+class VfmmUnavailable(ImportError):
+    """The HIP library is missing (not built)."""
+
+
+class VfmmError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed with status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "vfmm_version": (C.c_int32, []),
+    "vfmm_status_string": (C.c_char_p, [C.c_int32]),
+    "vfmm_last_error": (C.c_char_p, []),
+    "vfmm_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "vfmm_build_tree": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                    C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "vfmm_fmm_velocity": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_fmm_velocity_parts": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+    "vfmm_direct_velocity": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+    "vfmm_metrics_scratch_bytes": (C.c_size_t, []),
+    "vfmm_error_metrics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_tree_arrays": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_tree_expansions": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "vfmm_tree_destroy": (None, [C.c_void_p]),
+    "vfmm_tree_rebuild": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_tree_enable_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "vfmm_tree_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+}
+
+N_PHASES = 6
+PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_l2p")
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Function names declared in the public header."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vfmm_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """The loaded library (raises VfmmUnavailable when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise VfmmUnavailable(f"{LIB_PATH} is missing; build it with "
+                                  "`python -m paper_0809_1810_amd.build`")
+        l = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        detail = lib().vfmm_last_error().decode(errors="replace")
+        raise VfmmError(status, where, detail)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _dev_f64(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t
+
+
+def workspace_bytes(n: int, levels: int, p_max: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().vfmm_workspace_bytes(int(n), int(levels), int(p_max), C.byref(b)),
+           "vfmm_workspace_bytes")
+    return int(b.value)
+
+
+class Tree:
+    """A quadtree over device-resident particles, with its workspace."""
+
+    def __init__(self, x, y, levels: int, p_max: int = MAX_P, domain=None, workspace=None):
+        torch = _torch()
+        x = _dev_f64(x, "x"); y = _dev_f64(y, "y")
+        if x.shape != y.shape or x.dim() != 1:
+            raise ValueError("x and y must be 1-D tensors of equal length")
+        self.n = int(x.shape[0])
+        self.levels = int(levels)
+        self.p_max = int(p_max)
+        nbytes = workspace_bytes(self.n, self.levels, self.p_max)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        self.workspace = workspace
+        self.device = x.device
+        dom = None
+        if domain is not None:
+            dom = (C.c_double * 3)(*[float(d) for d in domain])
+        h = C.c_void_p(0)
+        _check(lib().vfmm_build_tree(x.data_ptr(), y.data_ptr(), self.n, self.levels, dom,
+                                     self.p_max, workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(), _stream(),
+                                     C.byref(h)), "vfmm_build_tree")
+        self._h = h
+        self._keep = (x, y)
+
+    def velocity(self, gamma, sigma: float, p: int, precision=FP64, parts=PART_ALL, out=None):
+        torch = _torch()
+        gamma = _dev_f64(gamma, "gamma")
+        if gamma.shape[0] != self.n:
+            raise ValueError("gamma has the wrong length")
+        precision = PRECISIONS.get(precision, precision)
+        if out is None:
+            u = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            v = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        else:
+            u, v = out
+        _check(lib().vfmm_fmm_velocity_parts(self._h, gamma.data_ptr(), float(sigma), int(p),
+                                             int(precision), int(parts), u.data_ptr(),
+                                             v.data_ptr(), _stream()), "vfmm_fmm_velocity")
+        return u, v
+
+    def rebuild(self, x, y, domain=None):
+        """Rebuild in place for new positions (same n, levels, workspace)."""
+        x = _dev_f64(x, "x"); y = _dev_f64(y, "y")
+        if int(x.shape[0]) != self.n or int(y.shape[0]) != self.n:
+            raise ValueError("rebuild needs the same number of particles")
+        dom = None if domain is None else (C.c_double * 3)(*[float(d) for d in domain])
+        _check(lib().vfmm_tree_rebuild(self._h, x.data_ptr(), y.data_ptr(), dom, _stream()),
+               "vfmm_tree_rebuild")
+        self._keep = (x, y)
+
+    def enable_timing(self, max_calls: int):
+        _check(lib().vfmm_tree_enable_timing(self._h, int(max_calls)), "vfmm_tree_enable_timing")
+        self._tslots = int(max_calls)
+
+    def read_timing(self):
+        """List of per-call dicts {phase: ms} for the recorded calls (synchronises)."""
+        slots = max(1, getattr(self, "_tslots", 1))
+        buf = (C.c_double * (slots * N_PHASES))()
+        n = C.c_int32(0)
+        _check(lib().vfmm_tree_read_timing(self._h, buf, C.byref(n)), "vfmm_tree_read_timing")
+        return [{PHASES[k]: buf[c * N_PHASES + k] for k in range(N_PHASES)} for c in range(n.value)]
+
+    def arrays(self):
+        """(root[4], perm[n], leaf_start[4^L + 1]) as device tensors."""
+        torch = _torch()
+        root = torch.empty(4, dtype=torch.float64, device=self.device)
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        ls = torch.empty((1 << (2 * self.levels)) + 1, dtype=torch.int32, device=self.device)
+        _check(lib().vfmm_tree_arrays(self._h, root.data_ptr(), perm.data_ptr(), ls.data_ptr(),
+                                      _stream()), "vfmm_tree_arrays")
+        return root, perm, ls
+
+    def expansions(self, kind: int, level: int, p: int):
+        """Scaled ME (kind 0) or LE (kind 1) coefficients of `level`: complex [4^level, p]."""
+        torch = _torch()
+        nb = 1 << (2 * level)
+        dst = torch.empty(nb * p * 2, dtype=torch.float64, device=self.device)
+        _check(lib().vfmm_tree_expansions(self._h, int(kind), int(level), dst.data_ptr(),
+                                          _stream()), "vfmm_tree_expansions")
+        return torch.view_as_complex(dst.view(nb, p, 2))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vfmm_tree_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_tree(x, y, levels: int, p_max: int = MAX_P, domain=None) -> Tree:
+    return Tree(x, y, levels, p_max, domain)
+
+
+def fmm_velocity(x, y, gamma, sigma: float, p: int, levels: int, precision=FP64, domain=None):
+    """One-shot: build the tree and evaluate the FMM velocity."""
+    t = Tree(x, y, levels, p_max=p, domain=domain)
+    return t.velocity(gamma, sigma, p, precision)
+
+
+def direct_velocity(x, y, gamma, sigma: float, targets=None, out=None):
+    torch = _torch()
+    x = _dev_f64(x, "x"); y = _dev_f64(y, "y"); gamma = _dev_f64(gamma, "gamma")
+    n = int(x.shape[0])
+    if targets is not None:
+        if not targets.is_cuda or targets.dtype != torch.int64 or not targets.is_contiguous():
+            raise TypeError("targets must be a contiguous CUDA int64 tensor")
+        nt = int(targets.shape[0]); tp = targets.data_ptr()
+    else:
+        nt = n; tp = None
+    if out is None:
+        u = torch.empty(nt, dtype=torch.float64, device=x.device)
+        v = torch.empty(nt, dtype=torch.float64, device=x.device)
+    else:
+        u, v = out
+    _check(lib().vfmm_direct_velocity(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n,
+                                      float(sigma), tp, nt, u.data_ptr(), v.data_ptr(), _stream()),
+           "vfmm_direct_velocity")
+    return u, v
+
+
+def error_metrics(u, v, u_ref, v_ref):
+    """(e_max, e_rms, max|W_ref|) computed on the GPU (synchronises)."""
+    torch = _torch()
+    for t, nme in ((u, "u"), (v, "v"), (u_ref, "u_ref"), (v_ref, "v_ref")):
+        _dev_f64(t, nme)
+    n = int(u.shape[0])
+    scratch = torch.empty(int(lib().vfmm_metrics_scratch_bytes()), dtype=torch.uint8,
+                          device=u.device)
+    out = torch.empty(3, dtype=torch.float64, device=u.device)
+    _check(lib().vfmm_error_metrics(u.data_ptr(), v.data_ptr(), u_ref.data_ptr(),
+                                    v_ref.data_ptr(), n, scratch.data_ptr(), out.data_ptr(),
+                                    _stream()), "vfmm_error_metrics")
+    mx, ss, den = out.cpu().tolist()
+    den = den if den > 0 else 1.0
+    return mx / den, (ss / n) ** 0.5 / den, den

@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed, no kernel launched).
+
+The library must load, export every function the public header declares, and
+reject invalid arguments on the host with the documented status codes before
+any device call.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+import paper_0809_1810_amd as vf
+from paper_0809_1810_amd import vfmm as B
+
+
+def _lib():
+    try:
+        return vf.lib()
+    except vf.VfmmUnavailable:
+        pytest.skip("libvfmm.so not built (run __graft_entry__.build())")
+
+
+def test_exports_every_header_symbol():
+    _lib()
+    declared = set(vf.header_symbols())
+    assert len(declared) >= 16
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert declared <= exported, declared - exported
+    assert set(B._SIGS) == declared  # the binding covers exactly the header
+
+
+def test_workspace_bytes_host_only():
+    l = _lib()
+    b = C.c_size_t(0)
+    assert l.vfmm_workspace_bytes(1 << 20, 6, 20, C.byref(b)) == 0
+    small = C.c_size_t(0)
+    assert l.vfmm_workspace_bytes(1000, 3, 10, C.byref(small)) == 0
+    assert 0 < small.value < b.value
+    # grows with p and levels
+    b2 = C.c_size_t(0)
+    assert l.vfmm_workspace_bytes(1 << 20, 6, 40, C.byref(b2)) == 0 and b2.value > b.value
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 3, 10), B.ERR_INVALID_ARG),
+    ((10, -1, 10), B.ERR_INVALID_ARG),
+    ((10, 13, 10), B.ERR_INVALID_ARG),
+    ((10, 3, 0), B.ERR_INVALID_ARG),
+    ((10, 3, 41), B.ERR_INVALID_ARG),
+])
+def test_workspace_bytes_validation(args, status):
+    l = _lib()
+    assert l.vfmm_workspace_bytes(*args, C.byref(C.c_size_t())) == status
+    assert len(l.vfmm_last_error()) > 0
+
+
+def test_build_tree_rejects_before_device_work():
+    l = _lib()
+    h = C.c_void_p(0)
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # null positions
+    assert l.vfmm_build_tree(None, None, 10, 3, None, 10, fake, 1 << 30, None, C.byref(h)) == B.ERR_INVALID_ARG
+    # workspace too small
+    assert l.vfmm_build_tree(fake, fake, 10, 3, None, 10, fake, 16, None, C.byref(h)) == B.ERR_WORKSPACE
+    # misaligned workspace
+    assert l.vfmm_build_tree(fake, fake, 10, 3, None, 10, C.c_void_p(0x1001), 1 << 30, None,
+                             C.byref(h)) == B.ERR_WORKSPACE
+    # bad domain side
+    dom = (C.c_double * 3)(0.0, 0.0, -1.0)
+    assert l.vfmm_build_tree(fake, fake, 10, 3, dom, 10, fake, 1 << 30, None, C.byref(h)) == B.ERR_INVALID_ARG
+    assert h.value is None
+    # null tree handles
+    assert l.vfmm_fmm_velocity(None, fake, 0.1, 5, 0, fake, fake, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_tree_enable_timing(None, 4) == B.ERR_INVALID_ARG
+    assert l.vfmm_direct_velocity(fake, fake, fake, 10, -1.0, None, 10, fake, fake, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_direct_velocity(fake, fake, fake, 10, 0.1, None, 5, fake, fake, None) == B.ERR_INVALID_ARG
+    l.vfmm_tree_destroy(None)  # ignored
+
+
+def test_status_strings():
+    l = _lib()
+    for s in (0, -1, -3, -4, -6, -99):
+        assert len(l.vfmm_status_string(s)) > 0
+    assert l.vfmm_version() >= 100
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(vf.VfmmUnavailable):
+        B.lib()

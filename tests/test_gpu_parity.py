@@ -1,0 +1,192 @@
+"""GPU (HIP) path vs the float64 CPU oracle, through the C ABI.
+
+Every result is compared element by element on the same seeded inputs:
+tree arrays bit-exact (root, leaf ranges, stable permutation), expansions and
+velocities within stated tolerances normalised by the maximum velocity
+(Section 5.1).  Float64 tolerance: 1e-12 at p = 20.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fmm as F
+from oracle import kernel as K
+from oracle import quadtree as qt
+from tests.gpu_util import (dev, host, oracle_le_scaled, oracle_me_scaled, print_case, rel_err,
+                            require_gpu)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vf():
+    return require_gpu()
+
+
+def _tree_check(vf, P, levels, domain=None):
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=20, domain=domain)
+    root, perm, ls = (host(a) for a in t.arrays())
+    ot = F.build_tree(P.x, P.y, levels, domain)
+    assert tuple(root[:3]) == ot.root, (root, ot.root)
+    key = ot.leaf_key()
+    counts = np.bincount(key, minlength=1 << (2 * levels))
+    assert np.array_equal(ls, np.concatenate([[0], np.cumsum(counts)]).astype(np.int32))
+    assert np.array_equal(perm, np.argsort(key, kind="stable").astype(np.int32))
+    return t
+
+
+@pytest.mark.parametrize("case", ["uniform_1k_L3", "uniform_1k_L0", "clusters_64k_L5",
+                                  "lattice_320_L6", "edges_L2"])
+def test_tree_bit_exact(vf, case):
+    print_case("tree", case=case)
+    if case.startswith("uniform_1k"):
+        P = W.config("uniform_1k"); L = int(case[-1])
+        _tree_check(vf, P, L)
+    elif case == "clusters_64k_L5":
+        _tree_check(vf, W.clusters(65536, seed=3), 5)
+    elif case == "lattice_320_L6":
+        _tree_check(vf, W.config("lattice_320"), 6)
+    else:
+        # particles exactly on box edges of a given root: upper/right box wins
+        x = np.array([0.0, 1.0, 2.0, 3.0, 4.0, 0.5, 3.999999]); y = np.array([4.0, 3.0, 2.0, 1.0, 0.0, 2.0, 2.0])
+        P = W.Particles(x, y, np.ones_like(x), 0.1)
+        _tree_check(vf, P, 2, domain=(0.0, 0.0, 4.0))
+
+
+def test_direct_fp64(vf):
+    P = W.config("uniform_1k")
+    print_case("direct", n=P.n)
+    u, v = vf.direct_velocity(dev(P.x), dev(P.y), dev(P.gamma), P.sigma)
+    ur, vr = K.direct_velocity(P.x, P.y, P.gamma, P.sigma)
+    assert rel_err(host(u), host(v), ur, vr)[0] < 1e-13
+    t = W.sample_targets(P.n, 77, seed=3)
+    us, vs = vf.direct_velocity(dev(P.x), dev(P.y), dev(P.gamma), P.sigma, targets=dev(t))
+    assert rel_err(host(us), host(vs), ur[t], vr[t])[0] < 1e-13
+
+
+def test_direct_ragged_and_duplicates(vf):
+    P = W.uniform(300, seed=12, sigma=0.05)
+    x = np.concatenate([P.x, P.x[:5]]); y = np.concatenate([P.y, P.y[:5]])
+    g = np.concatenate([P.gamma, np.linspace(-1, 1, 5)])
+    print_case("direct_dup", n=len(x))
+    u, v = vf.direct_velocity(dev(x), dev(y), dev(g), P.sigma)
+    ur, vr = K.direct_velocity(x, y, g, P.sigma)
+    assert rel_err(host(u), host(v), ur, vr)[0] < 1e-13
+
+
+@pytest.mark.parametrize("p,levels", [(10, 3), (20, 3), (20, 4), (5, 2)])
+def test_fmm_fp64_uniform(vf, p, levels):
+    P = W.config("uniform_1k")
+    print_case("fmm_fp64", p=p, levels=levels)
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=p)
+    u, v = t.velocity(dev(P.gamma), P.sigma, p, vf.FP64)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, levels)
+    assert rel_err(host(u), host(v), r.u, r.v)[0] < 1e-12
+
+
+@pytest.mark.parametrize("levels", [0, 1])
+def test_fmm_shallow_equals_direct(vf, levels):
+    P = W.config("uniform_1k")
+    print_case("fmm_shallow", levels=levels)
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=8)
+    ur, vr = K.direct_velocity(P.x, P.y, P.gamma, P.sigma)
+    for prec, tol in ((vf.FP64, 1e-13), (vf.FP32, 2e-6)):
+        u, v = t.velocity(dev(P.gamma), P.sigma, 8, prec)
+        assert rel_err(host(u), host(v), ur, vr)[0] < tol
+
+
+def test_fmm_fp64_lattice_parts_and_expansions(vf):
+    P = W.config("lattice_320")
+    L, p = 5, 20
+    print_case("fmm_fp64_lattice", n=P.n, levels=L, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    un, vn = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_NEAR))
+    uf, vf_ = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_FAR))
+    u, v = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, keep_expansions=True)
+    den = np.max(np.hypot(r.u, r.v))
+    assert np.max(np.hypot(un - r.near_u, vn - r.near_v)) / den < 1e-13
+    assert np.max(np.hypot(uf - r.far_u, vf_ - r.far_v)) / den < 1e-12
+    assert rel_err(u, v, r.u, r.v)[0] < 1e-12
+    root = r.tree.root
+    for lev in (2, 3, L):
+        w = qt.box_side(root, lev)
+        me = host(t.expansions(0, lev, p))
+        le = host(t.expansions(1, lev, p))
+        m = 1 << lev
+        for box, a in r.me[lev].items():
+            ref = oracle_me_scaled(a, w)
+            got = me[box[1] * m + box[0]]
+            assert np.max(np.abs(got - ref)) <= 1e-13 * max(np.max(np.abs(ref)), 1e-300)
+        for box, b in r.le[lev].items():
+            ref = oracle_le_scaled(b, w)
+            got = le[box[1] * m + box[0]]
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_fmm_fp32_vs_fp64(vf):
+    P = W.config("lattice_320")
+    print_case("fmm_fp32", n=P.n)
+    for L, p in ((5, 12), (6, 20)):
+        t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+        g = dev(P.gamma)
+        u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+        u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+        emax, erms = rel_err(u32, v32, u64, v64)
+        print(f"fp32 vs fp64 L={L} p={p}: max {emax:.3e} rms {erms:.3e}")
+        assert emax < 1e-6 and erms < 2e-7
+
+
+def test_degenerate_inputs(vf):
+    # one particle; all particles coincident; two particles
+    for x, y, g in (([0.3], [0.2], [1.0]), ([0.5] * 70, [0.5] * 70, list(np.linspace(-1, 1, 70))),
+                    ([0.0, 0.01], [0.0, 0.0], [1.0, -2.0])):
+        x = np.array(x, float); y = np.array(y, float); g = np.array(g, float)
+        print_case("degenerate", n=len(x))
+        t = vf.Tree(dev(x), dev(y), 3, p_max=6)
+        # compared with the oracle FMM: in the two-particle case the pair sits in
+        # the far field closer than sigma, so the FMM differs from eq. 7 by design
+        r = F.fmm_velocity(x, y, g, 0.02, 6, 3)
+        for prec, tol in ((vf.FP64, 1e-12), (vf.FP32, 1e-6)):
+            u, v = (host(a) for a in t.velocity(dev(g), 0.02, 6, prec))
+            assert np.all(np.isfinite(u)) and np.all(np.isfinite(v))
+            if np.max(np.hypot(r.u, r.v)) == 0:
+                assert np.all(u == 0) and np.all(v == 0)
+            else:
+                assert rel_err(u, v, r.u, r.v)[0] < tol
+
+
+def test_invalid_arguments_raise(vf):
+    P = W.uniform(100, seed=1)
+    t = vf.Tree(dev(P.x), dev(P.y), 3, p_max=10)
+    with pytest.raises(vf.VfmmError):
+        t.velocity(dev(P.gamma), -1.0, 10)
+    with pytest.raises(vf.VfmmError):
+        t.velocity(dev(P.gamma), 0.02, 11)
+    with pytest.raises(vf.VfmmError):
+        t.velocity(dev(P.gamma), 0.02, 5, precision=9)
+    with pytest.raises(vf.VfmmError):
+        vf.Tree(dev(P.x), dev(P.y), 13)
+
+
+def test_clusters_full_size_sampled(vf):
+    """N = 2^20 clustered workload at the benchmark's launch configuration,
+    checked on 192 sampled targets against the oracle FMM and the oracle direct sum."""
+    P = W.config("clusters_1m")
+    L, p = 6, 20
+    print_case("clusters_1m", n=P.n, levels=L, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    tg = W.sample_targets(P.n, 192, seed=77)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=tg)
+    assert rel_err(u64[tg], v64[tg], r.u, r.v)[0] < 1e-12
+    ud, vd = K.direct_velocity(P.x, P.y, P.gamma, P.sigma, targets=tg)
+    e64 = rel_err(u64[tg], v64[tg], ud, vd)[0]
+    u32, v32 = (host(a) for a in t.velocity(g, P.sigma, 14, vf.FP32))
+    e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
+    print(f"clusters_1m L6: fp64 p20 vs direct {e64:.3e}; fp32 p14 vs direct {e32:.3e}")
+    assert e64 < 1e-6 and e32 < 1e-6
