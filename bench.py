@@ -64,6 +64,23 @@ def p2p_pairs(leaf_start, levels):
     return int(np.sum(cnt * nb))
 
 
+def recorded_traffic(workload, p, levels):
+    """HBM bytes per P2P launch from the committed rocprofv3 counter runs, or None
+    when the kernel source or the configuration differs from the measured one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "p2p_traffic_clusters_1m.json")
+    src = os.path.join(ROOT, "paper_0809_1810_amd", "csrc", "p2p.hip")
+    try:
+        rec = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if (rec.get("p2p_source_sha256") != cur or rec.get("workload") != workload
+            or rec.get("p") != p or rec.get("levels") != levels):
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,9 +90,12 @@ def main():
     ap.add_argument("--p", type=int, default=None, help="override the tuned expansion order")
     ap.add_argument("--levels", type=int, default=None, help="override the tuned level")
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--cpu-targets", type=int, default=8192)
+    ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB (float64), "
+                         "used to scale HBM byte counters")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -90,6 +110,15 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     vf.lib()
+
+    if a.calibrate_copy_mib > 0:
+        src = torch.ones(a.calibrate_copy_mib * (1 << 17), dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {a.calibrate_copy_mib} MiB read + written, 3 times")
+        del src, dst
 
     P = W.config(a.workload)
     n = P.n
@@ -154,7 +183,8 @@ def main():
     p2p_ms = float(np.mean([ph["p2p_l2p"] for ph in tuned["phases"]]))
     achieved = P2P_FLOPS_PER_PAIR * tuned["pairs"] / (p2p_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(a.workload, p_t, L_t),
                 "kernel": "k_p2p_l2p<float>", "kernel_ms": round(p2p_ms, 4),
                 "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR}
 

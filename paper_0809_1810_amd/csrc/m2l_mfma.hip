@@ -1,0 +1,297 @@
+// M2L on the matrix cores (eq. 22), for the FP32 / BF16 / FP16 evaluations.
+//
+// With scaled coefficients the M2L operator of an interaction offset t depends
+// only on t (40 offsets in [-3,3]^2 \ [-1,1]^2).  Written on interleaved real
+// vectors m = (Re M_0, Im M_0, Re M_1, ...), each complex p x p operator becomes
+// a real 2p x 2p matrix R_t with 2x2 blocks [[Re T, -Im T], [Im T, Re T]].  For a
+// target box b of child class c = (bx & 1, by & 1) the 27 interaction offsets
+// are fixed, so
+//      l_b = sum_{t in IL(c)} R_t m_{b - t}
+// is one real GEMM per (level, class): rows = 2p output components, columns =
+// target boxes, K = 27 x 2p (source vectors gathered per column).  Every level
+// depends only on the multipoles of the upward sweep, so all levels run in one
+// launch.  The L2L chain (Section 3.3.3) then adds each parent's LE top-down.
+//
+// One wave computes a 32-box column tile with 32 x 32 matrix instructions:
+//   FP32  v_mfma_f32_32x32x2_f32  (A, B in float32)
+//   BF16  v_mfma_f32_32x32x16_bf16 (A, B rounded to bfloat16, RNE)
+//   FP16  v_mfma_f32_32x32x16_f16  (A, B rounded to float16, RNE)
+// all accumulating in float32.  A 32x32 instruction takes A[i][k] with
+// i = lane % 32 and B[k][j] with j = lane % 32 (K-slot given by lane / 32) and
+// returns D[i][j] in 16 registers per lane, row
+//   i = 8 (r / 4) + 4 (lane / 32) + r % 4,   column j = lane % 32.
+// For BF16/FP16 the source vectors of a level are multiplied by a power of two
+// 2^-e (e from the largest magnitude of that level's coefficients) so that
+// every input lies in [-1, 1]; the result is divided by the same power of two.
+#include "vfmm_device.hpp"
+
+namespace vfmm {
+
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+enum Mode { kModeF32 = 0, kModeBF16 = 1, kModeF16 = 2 };
+
+struct LevelTiles {
+  int first[kMaxLevels + 2];  // first flat tile of each level (levels 2..L), first[L+1] = total
+};
+
+__device__ __forceinline__ float real_block(const double2* T, int p, int i, int k) {
+  // R[2n + a][2k' + b] from the complex operator T[n][k']
+  const int n = i >> 1, a = i & 1, kk = k >> 1, b = k & 1;
+  const double2 t = T[n * p + kk];
+  double v;
+  if (a == 0) v = b == 0 ? t.x : -t.y;
+  else v = b == 0 ? t.y : t.x;
+  return float(v);
+}
+
+__global__ void __launch_bounds__(256) k_pack_f32(const double2* __restrict__ m2l64, int p, int mt,
+                                                  float* __restrict__ out) {
+  const int ks_n = p;  // K = 2 per instruction
+  const int64_t total = int64_t(kM2LOffsets) * mt * ks_n * 64;
+  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= total) return;
+  const int lane = int(e % 64);
+  const int ks = int((e / 64) % ks_n);
+  const int t = int((e / (64LL * ks_n)) % mt);
+  const int o = int(e / (64LL * ks_n * mt));
+  const int i = t * 32 + (lane & 31), k = 2 * ks + (lane >> 5);
+  out[e] = (i < 2 * p && k < 2 * p) ? real_block(m2l64 + int64_t(o) * p * p, p, i, k) : 0.f;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_pack_16(const double2* __restrict__ m2l64, int p, int mt,
+                                                 uint16_t* __restrict__ out) {
+  const int ks_n = (2 * p + 15) / 16;
+  const int64_t total = int64_t(kM2LOffsets) * mt * ks_n * 64 * 8;
+  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= total) return;
+  const int s = int(e % 8);
+  const int lane = int((e / 8) % 64);
+  const int ks = int((e / 512) % ks_n);
+  const int t = int((e / (512LL * ks_n)) % mt);
+  const int o = int(e / (512LL * ks_n * mt));
+  const int i = t * 32 + (lane & 31), k = 16 * ks + 8 * (lane >> 5) + s;
+  const float v = (i < 2 * p && k < 2 * p) ? real_block(m2l64 + int64_t(o) * p * p, p, i, k) : 0.f;
+  if (MODE == kModeBF16) {
+    const __bf16 h = __bf16(v);
+    out[e] = __builtin_bit_cast(uint16_t, h);
+  } else {
+    const _Float16 h = _Float16(v);
+    out[e] = __builtin_bit_cast(uint16_t, h);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ a, int n) {
+  if (int(threadIdx.x) < n) a[threadIdx.x] = 0u;
+}
+
+// Largest |component| of the level's multipoles, as float bits (order-preserving
+// for non-negative floats), combined with an integer atomic max.
+__global__ void __launch_bounds__(256) k_absmax(const float* __restrict__ a, int64_t n,
+                                                uint32_t* __restrict__ slot) {
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    m = fmaxf(m, fabsf(a[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
+}
+
+__device__ __forceinline__ float level_scale(const uint32_t* scales, int lev) {
+  const float mx = __uint_as_float(scales[lev]);
+  if (!(mx > 0.f)) return 1.f;
+  int e;
+  (void)frexpf(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, -e);
+}
+
+template <int MODE, int MT>
+__global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
+                                                  float2* __restrict__ le, int levels, int p,
+                                                  LevelTiles lt, const void* __restrict__ packA,
+                                                  const uint32_t* __restrict__ scales) {
+  const int lane = threadIdx.x & 63;
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (tile >= lt.first[levels + 1]) return;
+  int lev = 2;
+  while (tile >= lt.first[lev + 1]) ++lev;
+  const int half = 1 << (lev - 1), m = 1 << lev;
+  const int per_class = half * half;
+  const int tiles_pc = (per_class + 31) / 32;
+  const int local = tile - lt.first[lev];
+  const int c = local / tiles_pc, tt = local % tiles_pc;
+  const int cx = c & 1, cy = c >> 1;
+  const int col = lane & 31, hi = lane >> 5;
+  const int q = tt * 32 + col;
+  const bool valid = q < per_class;
+  const int qq = valid ? q : 0;
+  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
+  const int twop = 2 * p;
+  const float2* me_l = me + level_offset(lev) * p;
+  constexpr int KPI = MODE == kModeF32 ? 2 : 16;
+  const int ks_n = (twop + KPI - 1) / KPI;
+  const float sc = MODE == kModeF32 ? 1.f : level_scale(scales, lev);
+
+  v16f acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  for (int oy = cy - 3; oy <= cy + 2; ++oy) {
+    for (int ox = cx - 3; ox <= cx + 2; ++ox) {
+      if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
+      const int sx = bx - ox, sy = by - oy;
+      const bool sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+      const float* src = reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
+      const int oi = m2l_index(ox, oy);
+      for (int ks = 0; ks < ks_n; ++ks) {
+        if constexpr (MODE == kModeF32) {
+          const int k = 2 * ks + hi;
+          const float b = (sv && k < twop) ? src[k] : 0.f;
+          const float* A = static_cast<const float*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
+#pragma unroll
+          for (int t = 0; t < MT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[int64_t(t) * ks_n * 64], b, acc[t], 0, 0, 0);
+        } else {
+          const int k0 = 16 * ks + 8 * hi;
+          float f[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) f[s] = (sv && k0 + s < twop) ? src[k0 + s] * sc : 0.f;
+          const uint4* A = static_cast<const uint4*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
+          if constexpr (MODE == kModeBF16) {
+            v8bf b;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) b[s] = __bf16(f[s]);
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+              const uint4 a4 = A[int64_t(t) * ks_n * 64];
+              const v8bf a = __builtin_bit_cast(v8bf, a4);
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            }
+          } else {
+            v8h b;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) b[s] = _Float16(f[s]);
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+              const uint4 a4 = A[int64_t(t) * ks_n * 64];
+              const v8h a = __builtin_bit_cast(v8h, a4);
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!valid) return;
+  const float inv = 1.f / sc;
+  float* out = reinterpret_cast<float*>(le + level_offset(lev) * p + (int64_t(by) * m + bx) * p);
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = t * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+      if (i < twop) out[i] = acc[t][r] * inv;
+    }
+}
+
+// le[l] += L2L(le[l-1]) for one level (the M2L part is already in le[l]).
+__global__ void __launch_bounds__(256) k_l2l_add(const float2* __restrict__ le_par,
+                                                 float2* __restrict__ le, int lev, int p,
+                                                 const float2* __restrict__ B) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t nb = int64_t(1) << (2 * lev);
+  if (t >= nb * p) return;
+  const int64_t box = t / p;
+  const int n = int(t % p);
+  const int m = 1 << lev;
+  const int bx = int(box & (m - 1)), by = int(box >> lev);
+  const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
+  const int c = ((by & 1) << 1) | (bx & 1);
+  const float2* lp = le_par + pb * p;
+  const float2* b = B + (c * p + n) * p;
+  float2 acc = le[box * p + n];
+  for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
+  le[box * p + n] = acc;
+}
+
+template <int MODE>
+void launch_mode(const TreeDev& t, int levels, int p, const LevelTiles& lt, const void* pack,
+                 const uint32_t* scales, hipStream_t st) {
+  const int mt = (2 * p + 31) / 32;
+  const unsigned blocks = unsigned((lt.first[levels + 1] + 3) / 4);
+  const float2* me = static_cast<const float2*>(t.me);
+  float2* le = static_cast<float2*>(t.le);
+  if (mt == 1)
+    hipLaunchKernelGGL((k_m2l_mfma<MODE, 1>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+  else if (mt == 2)
+    hipLaunchKernelGGL((k_m2l_mfma<MODE, 2>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+  else
+    hipLaunchKernelGGL((k_m2l_mfma<MODE, 3>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+}
+
+}  // namespace
+
+hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t st) {
+  const OpsLayout ol = ops_layout(p);
+  char* ops = static_cast<char*>(t.ops);
+  const double2* m2l64 = reinterpret_cast<const double2*>(ops + ol.m2l64);
+  if (prec == kFP32) {
+    const int64_t total = int64_t(kM2LOffsets) * ol.mt * ol.ks32 * 64;
+    hipLaunchKernelGGL(k_pack_f32, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, m2l64, p,
+                       ol.mt, reinterpret_cast<float*>(ops + ol.mfma32));
+  } else {
+    const int64_t total = int64_t(kM2LOffsets) * ol.mt * ol.ks16 * 64 * 8;
+    if (prec == kM2L_BF16)
+      hipLaunchKernelGGL(k_pack_16<kModeBF16>, dim3(unsigned((total + 255) / 256)), dim3(256), 0,
+                         st, m2l64, p, ol.mt, reinterpret_cast<uint16_t*>(ops + ol.mfma16));
+    else
+      hipLaunchKernelGGL(k_pack_16<kModeF16>, dim3(unsigned((total + 255) / 256)), dim3(256), 0,
+                         st, m2l64, p, ol.mt, reinterpret_cast<uint16_t*>(ops + ol.mfma16));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t st) {
+  if (levels < 2) return hipSuccess;
+  const OpsLayout ol = ops_layout(p);
+  char* ops = static_cast<char*>(t.ops);
+  uint32_t* scales = reinterpret_cast<uint32_t*>(ops + ol.scales);
+  LevelTiles lt{};
+  int acc = 0;
+  for (int l = 2; l <= levels; ++l) {
+    lt.first[l] = acc;
+    const int64_t per_class = int64_t(1) << (2 * (l - 1));
+    acc += int(4 * ((per_class + 31) / 32));
+  }
+  lt.first[levels + 1] = acc;
+  if (prec != kFP32) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, scales, kMaxLevels + 1);
+    for (int l = 2; l <= levels; ++l) {
+      const int64_t n = (int64_t(1) << (2 * l)) * 2 * p;
+      int nb = int((n + 255) / 256);
+      if (nb > 1024) nb = 1024;
+      hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(256), 0, st,
+                         reinterpret_cast<const float*>(static_cast<const float2*>(t.me) + level_offset(l) * p),
+                         n, scales + l);
+    }
+  }
+  if (prec == kFP32) launch_mode<kModeF32>(t, levels, p, lt, ops + ol.mfma32, scales, st);
+  else if (prec == kM2L_BF16) launch_mode<kModeBF16>(t, levels, p, lt, ops + ol.mfma16, scales, st);
+  else launch_mode<kModeF16>(t, levels, p, lt, ops + ol.mfma16, scales, st);
+  const float2* B = reinterpret_cast<const float2*>(ops + ol.l2l32);
+  float2* le = static_cast<float2*>(t.le);
+  for (int l = 3; l <= levels; ++l) {
+    const int64_t work = (int64_t(1) << (2 * l)) * p;
+    hipLaunchKernelGGL(k_l2l_add, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st,
+                       le + level_offset(l - 1) * p, le + level_offset(l) * p, l, p, B);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vfmm

@@ -22,6 +22,8 @@ struct vfmm_tree_s {
   int levels;
   int p_max;
   int ops_p;        // order the operator tables were built for (-1 = none)
+  int pack_p;       // order / mode of the packed matrix-core M2L operands
+  int pack_mode;
   int last_p;       // order / precision of the last evaluation
   int last_prec;
   std::vector<hipEvent_t> ev;  // phase-timing ring: (VFMM_N_PHASES + 1) per call
@@ -165,6 +167,8 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   t->levels = levels;
   t->p_max = p_max;
   t->ops_p = -1;
+  t->pack_p = -1;
+  t->pack_mode = -1;
   t->last_p = -1;
   t->last_prec = -1;
   hipError_t e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, t->dev,
@@ -206,6 +210,13 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
     e = launch_build_ops(t->dev, p, prec, st);
     if (e != hipSuccess) return hip_fail(e, "operator tables");
     t->ops_p = p;
+    t->pack_p = -1;
+  }
+  if (far && prec != kFP64 && (t->pack_p != p || t->pack_mode != precision)) {
+    e = launch_pack_m2l_mfma(t->dev, p, precision, st);
+    if (e != hipSuccess) return hip_fail(e, "matrix-core operands");
+    t->pack_p = p;
+    t->pack_mode = precision;
   }
   mark(2);
   if (far) {
@@ -219,7 +230,8 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   }
   mark(4);
   if (far) {
-    e = launch_downward(t->dev, L, p, prec, st);
+    e = prec == kFP64 ? launch_downward(t->dev, L, p, prec, st)
+                      : launch_downward_mfma(t->dev, L, p, precision, st);
     if (e != hipSuccess) return hip_fail(e, "M2L/L2L");
     t->last_p = p;
     t->last_prec = prec;

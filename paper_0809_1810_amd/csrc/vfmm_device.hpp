@@ -27,7 +27,10 @@ __host__ __device__ __forceinline__ int m2l_index(int ox, int oy) { return (oy +
 
 // Byte offsets inside the operator-table buffer for expansion order p.
 struct OpsLayout {
-  size_t m2m64, l2l64, m2l64, m2m32, l2l32, m2l32, mfma, total;
+  size_t m2m64, l2l64, m2l64, m2m32, l2l32, m2l32, mfma32, mfma16, scales, total;
+  int mt;        // 32-row output tiles of the real 2p x 2p M2L block
+  int ks32;      // K steps of the FP32 matrix instruction (K = 2)
+  int ks16;      // K steps of the BF16/FP16 matrix instructions (K = 16)
 };
 __host__ __device__ inline OpsLayout ops_layout(int p) {
   OpsLayout o;
@@ -40,9 +43,13 @@ __host__ __device__ inline OpsLayout ops_layout(int p) {
   o.m2m32 = take(4 * pp * sizeof(float2));
   o.l2l32 = take(4 * pp * sizeof(float2));
   o.m2l32 = take(kM2LOffsets * pp * sizeof(float2));
-  // packed MFMA operands for the reduced-precision M2L (see m2l_mfma.hip)
-  const size_t pk = size_t((2 * p + 15) / 16) * 16;  // padded real K per offset
-  o.mfma = take(size_t(kM2LOffsets) * pk * pk * sizeof(float));
+  // M2L operands packed in matrix-instruction lane order (see m2l_mfma.hip)
+  o.mt = (2 * p + 31) / 32;
+  o.ks32 = p;
+  o.ks16 = (2 * p + 15) / 16;
+  o.mfma32 = take(size_t(kM2LOffsets) * o.mt * o.ks32 * 64 * sizeof(float));
+  o.mfma16 = take(size_t(kM2LOffsets) * o.mt * o.ks16 * 64 * 8 * sizeof(uint16_t));
+  o.scales = take(size_t(kMaxLevels + 1) * sizeof(uint32_t));
   o.total = off;
   return o;
 }

@@ -98,6 +98,10 @@ hipError_t launch_build_ops(const TreeDev& t, int p, int prec, hipStream_t strea
 hipError_t launch_p2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
 hipError_t launch_m2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
 hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+// Reduced-precision downward sweep: M2L of all levels on the matrix cores
+// (prec = kFP32, kM2L_BF16 or kM2L_FP16), then the L2L chain.
+hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t stream);
+hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
 hipError_t launch_p2p_l2p(const TreeDev& t, const Layout& lay, int levels, int p, int prec,
                           double sigma, int parts, double* u, double* v, hipStream_t stream);
 hipError_t launch_direct(const double* x, const double* y, const double* g, int64_t n,

@@ -1,0 +1,84 @@
+"""Reduced-precision evaluations (FP32 / BF16 / FP16 M2L on the matrix cores).
+
+Compared with the float64 GPU evaluation at the same (p, levels), which isolates
+rounding, and with the float64 oracle.  Tolerances:
+
+* FP32 (scaled coefficients, FP32 matrix instructions): local expansions within
+  1e-5 of the largest coefficient of their level, velocities within 1e-6 of
+  the maximum velocity;
+* BF16 / FP16 inputs with FP32 accumulation: measured error bars, bounded by
+  the input rounding (2^-8 and 2^-11 relative) times the far-field share of the
+  velocity; checked loosely and for ordering FP32 < FP16 < BF16.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fmm as F
+from tests.gpu_util import dev, host, print_case, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vf():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("p,levels", [(3, 3), (12, 5), (17, 4), (40, 3)])
+def test_fp32_mfma_locals_match_fp64(vf, p, levels):
+    P = W.uniform(20000, seed=31, sigma=0.005)
+    print_case("mfma_locals", p=p, levels=levels)
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=p)
+    g = dev(P.gamma)
+    t.velocity(g, P.sigma, p, vf.FP64)
+    le64 = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+    me64 = [host(t.expansions(0, l, p)) for l in range(2, levels + 1)]
+    u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+    le32 = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+    me32 = [host(t.expansions(0, l, p)) for l in range(2, levels + 1)]
+    for a, b in zip(me32, me64):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+    for a, b in zip(le32, le64):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+    u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    assert rel_err(u32, v32, u64, v64)[0] < 1e-6
+
+
+def test_reduced_precision_error_bars(vf):
+    P = W.config("lattice_320")
+    L, p = 5, 12
+    print_case("bf16_fp16", n=P.n, levels=L, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    fu, fv = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_FAR))
+    far_share = np.max(np.hypot(fu, fv)) / np.max(np.hypot(u64, v64))
+    errs = {}
+    for name, prec in (("fp32", vf.FP32), ("fp16", vf.M2L_FP16), ("bf16", vf.M2L_BF16)):
+        u, v = (host(a) for a in t.velocity(g, P.sigma, p, prec))
+        errs[name] = rel_err(u, v, u64, v64)
+    print("far share", far_share, {k: f"max {e[0]:.2e} rms {e[1]:.2e}" for k, e in errs.items()})
+    assert errs["fp32"][0] < 1e-6
+    assert errs["fp32"][0] < errs["fp16"][0] < errs["bf16"][0]
+    assert errs["fp16"][0] < 30 * 2.0 ** -11 * far_share
+    assert errs["bf16"][0] < 30 * 2.0 ** -8 * far_share
+    # against the oracle too (same p, L)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=W.sample_targets(P.n, 300, 1))
+    u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+    assert rel_err(u32[r.targets], v32[r.targets], r.u, r.v)[0] < 1e-6
+
+
+def test_mode_switching_keeps_tables_consistent(vf):
+    P = W.uniform(5000, seed=5, sigma=0.01)
+    t = vf.Tree(dev(P.x), dev(P.y), 4, p_max=16)
+    g = dev(P.gamma)
+    ref = {}
+    for prec in (vf.FP32, vf.M2L_BF16, vf.M2L_FP16):
+        ref[prec] = [host(a) for a in t.velocity(g, P.sigma, 10, prec)]
+    # interleave orders and modes: every repeat must reproduce bit for bit
+    for p in (16, 10):
+        for prec in (vf.M2L_FP16, vf.FP32, vf.M2L_BF16):
+            out = [host(a) for a in t.velocity(g, P.sigma, p, prec)]
+            if p == 10:
+                assert np.array_equal(out[0], ref[prec][0]) and np.array_equal(out[1], ref[prec][1])
