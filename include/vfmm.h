@@ -99,9 +99,10 @@ const char* vfmm_last_error(void);
 vfmm_status_t vfmm_workspace_bytes(int64_t n, int32_t levels, int32_t p_max, size_t* bytes);
 
 /* Builds the quadtree of Section 3.3 over the particles (x, y) (device, n each,
- * 1 <= n <= 2^31 - 1): root box, leaf of every particle, stable sort of the
- * particles by leaf (row-major leaf order, input order kept inside a leaf), leaf
- * ranges and box-local coordinates.
+ * 1 <= n <= 2^31 - 1): root box, leaf of every particle, sort of the particles
+ * by leaf (row-major leaf order; inside a leaf by the Morton index of the
+ * particle's cell at level L + 4, ties in input order), leaf ranges, box-local
+ * coordinates and the near-field target tiles.
  *   domain    (host, may be NULL): {x0, y0, S}, lower-left corner and side of the
  *             root square; NULL = bounding square of the particles.  Particles
  *             outside a given square are clamped into its edge boxes.

@@ -1,12 +1,17 @@
 // Uniform quadtree construction on the GPU (Section 3.3, Fig. 6).
 //
-// Steps: bounding square of the particles (root box, level 0), leaf key of every
-// particle at level L, stable LSD radix sort of the keys (so particles of a leaf
-// keep their input order), leaf ranges by binary search, box-local coordinates,
-// and the list of P2P target tiles (<= 64 targets of one leaf each).
+// Steps: bounding square of the particles (root box, level 0), sort key of every
+// particle, stable LSD radix sort of the keys, leaf ranges by binary search,
+// box-local coordinates, and the P2P target tiles (<= 64 consecutive particles
+// of one leaf) with their bounding boxes.
+//
+// Sort key: the row-major leaf index at level L in the high bits, and below it
+// the Morton index of the particle's cell at level L + 4 inside the leaf, so a
+// leaf's particles are contiguous and a tile of 64 consecutive particles covers
+// a compact part of the leaf (ties keep input order).
 //
 // Leaf convention: ix = clamp(floor(((x - x0) / S) * 2^L), 0, 2^L - 1), the same
-// for y; key = iy * 2^L + ix.  The root is the bounding square of side
+// for y; leaf index iy * 2^L + ix.  The root is the bounding square of side
 // S = max extent * (1 + 2^-20) centred on the bounding-box midpoint (S = 1 for a
 // zero extent), unless the caller gives (x0, y0, S).  These floating-point
 // operations are written without contraction so that the integer leaf decision
@@ -82,6 +87,13 @@ __global__ void __launch_bounds__(256) k_root(const double* __restrict__ part, i
   }
 }
 
+__device__ inline uint32_t spread4(uint32_t v) {  // bits b3 b2 b1 b0 -> b3 0 b2 0 b1 0 b0
+  v &= 15u;
+  v = (v | (v << 2)) & 0x33u;
+  v = (v | (v << 1)) & 0x55u;
+  return v;
+}
+
 __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
                                               const double* __restrict__ y, int64_t n,
                                               const double* __restrict__ root, int levels,
@@ -91,13 +103,16 @@ __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
   const double x0 = root[0], y0 = root[1], S = root[2];
-  const int m = 1 << levels;
-  const double scale = double(m);
+  const int mf = 1 << (levels + kSubLevels);
+  const double scale = double(mf);
+  // floor(t 2^(L+4)) >> 4 == floor(t 2^L): the leaf decision is unchanged
   double fx = floor(((x[i] - x0) / S) * scale);
   double fy = floor(((y[i] - y0) / S) * scale);
-  int ix = fx < 0.0 ? 0 : (fx > double(m - 1) ? m - 1 : int(fx));
-  int iy = fy < 0.0 ? 0 : (fy > double(m - 1) ? m - 1 : int(fy));
-  keys[i] = (uint32_t(iy) << levels) | uint32_t(ix);
+  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
+  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
+  const uint32_t leaf = (uint32_t(iy >> kSubLevels) << levels) | uint32_t(ix >> kSubLevels);
+  const uint32_t sub = spread4(uint32_t(ix)) | (spread4(uint32_t(iy)) << 1);
+  keys[i] = (leaf << (2 * kSubLevels)) | sub;
   idx[i] = int32_t(i);
 }
 
@@ -253,10 +268,11 @@ __global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__
                                                     int64_t nleaves, int32_t* __restrict__ start) {
   int64_t k = blockIdx.x * 256LL + threadIdx.x;
   if (k > nleaves) return;
-  int64_t lo = 0, hi = n;  // first position with key >= k
+  const uint64_t kk = uint64_t(k) << (2 * kSubLevels);
+  int64_t lo = 0, hi = n;  // first position whose leaf is >= k
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < uint32_t(k)) lo = mid + 1; else hi = mid;
+    if (uint64_t(keys[mid]) < kk) lo = mid + 1; else hi = mid;
   }
   start[k] = int32_t(lo);
 }
@@ -271,8 +287,8 @@ __global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__
 #pragma clang fp contract(off)
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
-  const uint32_t key = keys[i];
-  const int ix = int(key & ((1u << levels) - 1u)), iy = int(key >> levels);
+  const uint32_t leaf = keys[i] >> (2 * kSubLevels);
+  const int ix = int(leaf & ((1u << levels) - 1u)), iy = int(leaf >> levels);
   const double w = root[3];
   const double cx = root[0] + (double(ix) + 0.5) * w;
   const double cy = root[1] + (double(iy) + 0.5) * w;
@@ -289,19 +305,42 @@ __global__ void __launch_bounds__(256) k_tile_counts(const int32_t* __restrict__
   cnt[k] = k < nleaves ? uint32_t((start[k + 1] - start[k] + kTile - 1) / kTile) : 0u;
 }
 
-__global__ void __launch_bounds__(256) k_tile_fill(const int32_t* __restrict__ start,
-                                                   const uint32_t* __restrict__ off, int64_t nleaves,
-                                                   Tile* __restrict__ tiles,
+// One thread per particle: a particle that starts a 64-block of its leaf writes
+// that tile.
+__global__ void __launch_bounds__(256) k_tile_fill(const uint32_t* __restrict__ keys,
+                                                   const int32_t* __restrict__ start,
+                                                   const uint32_t* __restrict__ off, int64_t n,
+                                                   int64_t nleaves, Tile* __restrict__ tiles,
                                                    int32_t* __restrict__ ntiles) {
-  int64_t k = blockIdx.x * 256LL + threadIdx.x;
-  if (k == 0) *ntiles = int32_t(off[nleaves]);
-  if (k >= nleaves) return;
-  const int32_t s = start[k], c = start[k + 1] - s;
-  uint32_t o = off[k];
-  for (int32_t t = 0; t * kTile < c; ++t) {
-    int32_t cc = c - t * kTile;
-    tiles[o + t] = Tile{int32_t(k), s + t * kTile, cc < kTile ? cc : kTile, 0};
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i == 0) *ntiles = int32_t(off[nleaves]);
+  if (i >= n) return;
+  const uint32_t leaf = keys[i] >> (2 * kSubLevels);
+  const int32_t s = start[leaf], c = start[leaf + 1] - s;
+  const int32_t r = int32_t(i) - s;
+  if (r % kTile != 0) return;
+  const int32_t cc = c - r;
+  tiles[off[leaf] + r / kTile] = Tile{int32_t(leaf), int32_t(i), cc < kTile ? cc : kTile, 0};
+}
+
+// One wave per tile: bounding box of its particles in the leaf's local frame.
+__global__ void __launch_bounds__(256) k_tile_box(const Tile* __restrict__ tiles,
+                                                  const int32_t* __restrict__ ntiles,
+                                                  const Part32* __restrict__ p32,
+                                                  float4* __restrict__ box) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const Tile t = tiles[wid];
+  const Part32 q = p32[t.start + (lane < t.count ? lane : 0)];
+  float x0 = q.x, x1 = q.x, y0 = q.y, y1 = q.y;
+  for (int o = 32; o > 0; o >>= 1) {
+    x0 = fminf(x0, __shfl_xor(x0, o, 64));
+    x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
+    y0 = fminf(y0, __shfl_xor(y0, o, 64));
+    y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
   }
+  if (lane == 0) box[wid] = make_float4(x0, x1, y0, y1);
 }
 
 __global__ void __launch_bounds__(256) k_gather_gamma(const double* __restrict__ gamma,
@@ -341,7 +380,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   hipLaunchKernelGGL(k_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, n, root, levels, k0,
                      i0);
   const int nblk = int(lay.sort_blocks);
-  int bits_left = 2 * levels, shift = 0;
+  int bits_left = 2 * (levels + kSubLevels), shift = 0;
   while (bits_left > 0) {
     const int bits = bits_left < 8 ? bits_left : 8;
     const uint32_t mask = (1u << bits) - 1u;
@@ -377,8 +416,12 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      toff);
   hipError_t e = scan_exclusive(toff, nl + 1, tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(nl, 256)), dim3(256), 0, st, lstart, toff, nl,
+  t.tile_off = toff;
+  t.tile_box = reinterpret_cast<float4*>(ws + lay.tile_box);
+  hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
                      t.tiles, t.ntiles);
+  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
+                     t.tiles, t.ntiles, t.part32, t.tile_box);
   return hipGetLastError();
 }
 

@@ -106,6 +106,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.tile_off = take(size_t(L.nleaves + 1) * 4);
   L.tiles = take(size_t(L.max_tiles) * sizeof(Tile));
   L.ntiles = take(4);
+  L.tile_box = take(size_t(L.max_tiles) * sizeof(float4));
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));

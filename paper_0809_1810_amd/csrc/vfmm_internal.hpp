@@ -27,6 +27,7 @@ namespace vfmm {
 constexpr int kMaxP = 40;
 constexpr int kMaxLevels = 12;
 constexpr int kTile = 64;            // P2P targets per wave tile
+constexpr int kSubLevels = 4;        // within a leaf, particles are ordered by their cell at level L + 4
 constexpr int kSortItems = 8;        // radix-sort elements per thread
 constexpr int kSortBlock = 256;      // radix-sort threads per block
 constexpr int kSortPerBlock = kSortItems * kSortBlock;
@@ -63,7 +64,7 @@ inline __host__ __device__ int64_t n_boxes_2_to(int L) {
 
 struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
-  size_t leaf_start, tile_off, tiles, ntiles;
+  size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t part64, part32, me, le, ops, reduce, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
@@ -77,8 +78,10 @@ struct TreeDev {
   uint32_t* keys;        // sorted leaf keys
   int32_t* perm;         // sorted position -> input index
   int32_t* leaf_start;   // [nleaves + 1]
-  Tile* tiles;           // P2P target tiles
+  Tile* tiles;           // P2P target tiles (<= 64 consecutive particles of one leaf)
   int32_t* ntiles;       // device count of tiles
+  uint32_t* tile_off;    // [nleaves + 1] first tile of each leaf
+  float4* tile_box;      // per tile: (xmin, xmax, ymin, ymax) in its leaf's local frame
   Part64* part64;
   Part32* part32;
   void* me;

@@ -25,6 +25,13 @@ def vf():
     return require_gpu()
 
 
+def _morton4(ix, iy):
+    out = np.zeros_like(ix)
+    for b in range(4):
+        out |= ((ix >> b) & 1) << (2 * b) | ((iy >> b) & 1) << (2 * b + 1)
+    return out
+
+
 def _tree_check(vf, P, levels, domain=None):
     t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=20, domain=domain)
     root, perm, ls = (host(a) for a in t.arrays())
@@ -32,8 +39,17 @@ def _tree_check(vf, P, levels, domain=None):
     assert tuple(root[:3]) == ot.root, (root, ot.root)
     key = ot.leaf_key()
     counts = np.bincount(key, minlength=1 << (2 * levels))
+    # unique: the leaf ranges and the set of particles of every leaf
     assert np.array_equal(ls, np.concatenate([[0], np.cumsum(counts)]).astype(np.int32))
-    assert np.array_equal(perm, np.argsort(key, kind="stable").astype(np.int32))
+    assert np.array_equal(np.sort(perm), np.arange(P.n))
+    assert np.array_equal(key[perm], np.sort(key))
+    # order inside a leaf (documented convention): Morton index of the cell at
+    # level L + 4, then input order
+    fx, fy = (np.clip(np.floor((a - o) / ot.root[2] * 2.0 ** (levels + 4)), 0, 2 ** (levels + 4) - 1).astype(np.int64)
+              for a, o in ((P.x, ot.root[0]), (P.y, ot.root[1])))
+    fine = key * 256 + _morton4(fx & 15, fy & 15)
+    assert np.array_equal(fine >> 8, key)
+    assert np.array_equal(perm, np.argsort(fine, kind="stable").astype(np.int32))
     return t
 
 
