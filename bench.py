@@ -7,8 +7,10 @@ quadtree rebuild (root box, keys, sort, leaf ranges) + FMM velocity (gather,
 P2M, M2M, M2L + L2L, P2P + L2P + combine), i.e. N / t particles per second.
 Two paths are timed on the same particles:
 
-* tuned: float32 arithmetic on scaled coefficients, (p, levels) chosen to meet a
-  max error of 1e-6 (normalised by max |u|) against the float64 direct sum;
+* tuned: float32 arithmetic on scaled coefficients, (p, levels) chosen by the
+  learned selector to meet a max error of 1e-6 (normalised by max |u|) against
+  the float64 direct sum, audited on sampled targets (selection and audit are
+  reported separately and not part of a step);
 * plain: everything in float64, p = 20 and the largest level with
   box side / sigma >= 8.
 
@@ -132,10 +134,25 @@ def main():
     # ---------------- parameter choice
     L_plain = largest_level(side, P.sigma, 8.0)
     p_plain = 20
-    L_t = a.levels if a.levels is not None else L_plain
-    p_t = a.p if a.p is not None else 14
     prec_t = vf.PRECISIONS[a.precision]
-    selector = "fixed"
+    sel_info = None
+    if a.p is not None and a.levels is not None:
+        p_t, L_t, selector = a.p, a.levels, "fixed"
+    else:
+        from paper_0809_1810_amd import selector as S
+        weights = S.load_weights()
+        s0 = time.perf_counter()
+        r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=weights, n_audit=AUDIT_TARGETS,
+                               seed=7)
+        torch.cuda.synchronize()
+        sel_ms = (time.perf_counter() - s0) * 1e3
+        p_t, L_t = r["p"], r["levels"]
+        if r["precision"] == "fp64":
+            prec_t = vf.FP64
+        selector = "learned" if not r["fallback"] else "fallback"
+        sel_info = {"predicted_log10_emax": r["predicted_log10"], "audit_emax": r["audit_emax"],
+                    "fallback": r["fallback"], "select_and_audit_ms": round(sel_ms, 2)}
+        log(f"[bench] selector: {json.dumps(r)} in {sel_ms:.1f} ms")
 
     # ---------------- audit targets and FP64 direct reference
     tg = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
@@ -229,8 +246,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{P.name}: N={n}, sigma={P.sigma}, seeded synthetic",
-            "p": p_t, "levels": L_t, "precision": a.precision, "selector": selector,
-            "audit_targets": AUDIT_TARGETS,
+            "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
+            "selector": selector, "selector_info": sel_info, "audit_targets": AUDIT_TARGETS,
         },
         "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
         "roofline": roofline,

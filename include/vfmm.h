@@ -193,6 +193,77 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
 vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t tree, int32_t max_calls);
 vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t tree, double* ms, int32_t* n_calls);
 
+/* ---------------------------------------------------------------------------
+ * (p, levels) selector.  The paper measures how the FMM error depends on N, the
+ * number of levels and the truncation p (Sections 4-5); a 10 -> 64 -> 64 -> 1
+ * GELU network learns log10 of the maximum error (normalised by the maximum
+ * velocity, Section 5.1) from runs of this library, and the cheapest (p, L)
+ * whose prediction meets a tolerance is chosen.
+ *
+ * Network parameters: VFMM_MLP_PARAMS float32 values (device), laid out as
+ * W1[10][64] (row = input feature), b1[64], W2[64][64] (row = input unit),
+ * b2[64], W3[64], b3.  Activations: GELU, tanh form.  Inputs are the
+ * VFMM_N_FEATURES features of vfmm_selector_features, standardised by the
+ * caller (x - mean) / std.  With bf16 != 0 the weights, inputs and
+ * activations are rounded to bfloat16 and products accumulate in float32;
+ * gradients, master weights and Adam moments are float32. */
+#define VFMM_MLP_PARAMS 4929
+#define VFMM_N_FEATURES 10
+
+/* Device scratch needed by vfmm_mlp_gradient for `batch` samples. */
+size_t vfmm_mlp_scratch_bytes(int64_t batch);
+
+/* y[b] = network(x[b]) for b < batch (device arrays; x is [batch][10]). */
+vfmm_status_t vfmm_mlp_forward(const float* params, int32_t bf16, const float* x, int64_t batch,
+                               float* y, void* stream);
+
+/* grad[VFMM_MLP_PARAMS] = d/dparams of mean_b (y_b - target_b)^2 and, if loss is
+ * not NULL, loss[0] = that mean (device arrays).  Deterministic: per-block
+ * partial gradients are summed in a fixed order.  scratch: device,
+ * vfmm_mlp_scratch_bytes(batch) bytes. */
+vfmm_status_t vfmm_mlp_gradient(const float* params, int32_t bf16, const float* x,
+                                const float* target, int64_t batch, float* grad, float* loss,
+                                void* scratch, size_t scratch_bytes, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
+ * on params, with first/second moments m, v (device, VFMM_MLP_PARAMS each). */
+vfmm_status_t vfmm_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                            float lr, void* stream);
+
+/* Device scratch needed by vfmm_particle_stats and vfmm_select_params for n. */
+size_t vfmm_select_scratch_bytes(int64_t n);
+
+/* Particle statistics (float64, host out[12]): sum x, sum x^2, sum y, sum y^2,
+ * sum Gamma, sum Gamma^2, sum |Gamma|, max |Gamma|, min x, max x, min y,
+ * max y.  Synchronises `stream`. */
+vfmm_status_t vfmm_particle_stats(const double* x, const double* y, const double* gamma,
+                                  int64_t n, void* scratch, size_t scratch_bytes, double* stats,
+                                  void* stream);
+
+/* Host function: the 10 selector features of (p, levels) for particles with
+ * these statistics (out[10], host): p, L, log2 N, log2 N - 2L,
+ * log2(leaf side / sigma), log2(sigma / h) with h = S / sqrt(N), mean Gamma /
+ * rms Gamma, log10(sum |Gamma| / max |Gamma|), std x / S, std y / S, where S is
+ * the root side of vfmm_build_tree's bounding square. */
+vfmm_status_t vfmm_selector_features(const double* stats, int64_t n, double sigma, int32_t p,
+                                     int32_t levels, float* out);
+
+/* Chooses (p, levels) for an FP32 evaluation of these particles with max error
+ * <= tol: candidates p = 4..20 and L = 2..min(10, level with ~4 particles per
+ * leaf); the network (params, device; bf16) predicts log10 of each
+ * candidate's error from its standardised features (feat_mean, feat_std: host,
+ * 10 each); among those with prediction + margin <= log10(tol) the one with the
+ * least modelled cost (near-field pairs counted from the leaf occupancy,
+ * expansion and translation work) is returned.  If none qualifies:
+ * p = 20, L = deepest level with leaf side >= 8 sigma, *used_fallback = 1.
+ * Outputs are host pointers; the call synchronises `stream`.
+ * scratch: device, vfmm_select_scratch_bytes(n) bytes. */
+vfmm_status_t vfmm_select_params(const double* x, const double* y, const double* gamma, int64_t n,
+                                 double sigma, double tol, const float* params,
+                                 const float* feat_mean, const float* feat_std, double margin,
+                                 void* scratch, size_t scratch_bytes, int32_t* p, int32_t* levels,
+                                 double* predicted_log10, int32_t* used_fallback, void* stream);
+
 /* Releases the tree handle (not the caller's workspace).  NULL is ignored. */
 void vfmm_tree_destroy(vfmm_tree_t tree);
 

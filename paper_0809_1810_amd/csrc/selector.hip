@@ -1,0 +1,281 @@
+// C ABI of the selector network and of the (p, levels) choice.
+//
+// The choice follows the experiment design of the paper (Section 5: the error
+// of an FMM evaluation as a function of N, the number of levels l and the
+// truncation p): among candidate (p, L), take the cheapest whose predicted
+// log10 max error (normalised by the maximum velocity, Section 5.1), plus a
+// safety margin, is within the tolerance; when none qualifies, take the
+// conservative choice p = 20 and the deepest level whose leaf side is at
+// least 8 sigma (keeping the kernel-substitution error of Section 4.1
+// negligible).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/vfmm.h"
+#include "vfmm_device.hpp"
+
+namespace vfmm {
+int mlp_param_count();
+int mlp_blocks(int64_t B);
+hipError_t launch_mlp_forward(const float* W, bool bf16, const float* X, int64_t B, float* Y,
+                              hipStream_t st);
+hipError_t launch_mlp_gradient(const float* W, bool bf16, const float* X, const float* T,
+                               int64_t B, float* Y, float* part, float* lpart, float* grad,
+                               float* loss, hipStream_t st);
+hipError_t launch_adam(float* W, float* m, float* v, const float* g, int step, float lr,
+                       hipStream_t st);
+hipError_t launch_stats(const double* x, const double* y, const double* g, int64_t n,
+                        double* part, double* out, hipStream_t st);
+hipError_t launch_leaf_hist(const double* x, const double* y, int64_t n, const double* root3,
+                            int lev, uint32_t* counts, hipStream_t st);
+void set_last_error(const char* msg);
+}  // namespace vfmm
+
+using namespace vfmm;
+
+namespace {
+
+vfmm_status_t sfail(vfmm_status_t s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+vfmm_status_t sfail(vfmm_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return s;
+}
+
+inline size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+constexpr int kHistMax = 10;   // finest level of the occupancy histogram
+constexpr int kPMin = 4, kPMax = 20;
+
+int hist_level(int64_t n) {
+  int l = 2;
+  while (l < kHistMax && (int64_t(1) << (2 * (l + 1))) <= 4 * n) ++l;
+  return l;
+}
+
+size_t select_scratch(int64_t n) {
+  const int lh = hist_level(n);
+  const int ncand = (kPMax - kPMin + 1) * (lh - 1);
+  return a256(size_t(kReduceBlocks) * 12 * 8) + a256(12 * 8) +
+         a256((size_t(1) << (2 * lh)) * 4) + a256(size_t(ncand) * 10 * 4) + a256(size_t(ncand) * 4);
+}
+
+double root_side(const double* st) {
+  const double ext = std::fmax(st[9] - st[8], st[11] - st[10]);
+  return ext > 0.0 ? ext * (1.0 + 0x1p-20) : 1.0;
+}
+
+// pairs(L) = sum over leaves of n_b * (sum over its 3 x 3 local list of n_s)
+double near_pairs(const std::vector<double>& c, int lev) {
+  const int m = 1 << lev;
+  double s = 0.0;
+  for (int iy = 0; iy < m; ++iy)
+    for (int ix = 0; ix < m; ++ix) {
+      const double nb = c[size_t(iy) * m + ix];
+      if (nb == 0.0) continue;
+      double src = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int jx = ix + dx, jy = iy + dy;
+          if (jx >= 0 && jx < m && jy >= 0 && jy < m) src += c[size_t(jy) * m + jx];
+        }
+      s += nb * src;
+    }
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vfmm_mlp_scratch_bytes(int64_t batch) {
+  if (batch < 1) batch = 1;
+  const int nb = mlp_blocks(batch);
+  return a256(size_t(nb) * mlp_param_count() * 4) + a256(size_t(nb) * 4) + a256(size_t(batch) * 4);
+}
+
+vfmm_status_t vfmm_mlp_forward(const float* params, int32_t bf16, const float* x, int64_t batch,
+                               float* y, void* stream) {
+  if (!params || !x || !y) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (batch < 1 || batch > (int64_t(1) << 30)) return sfail(VFMM_ERR_INVALID_ARG, "bad batch");
+  hipError_t e = launch_mlp_forward(params, bf16 != 0, x, batch, y, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "mlp forward: %s", hipGetErrorString(e));
+}
+
+vfmm_status_t vfmm_mlp_gradient(const float* params, int32_t bf16, const float* x,
+                                const float* target, int64_t batch, float* grad, float* loss,
+                                void* scratch, size_t scratch_bytes, void* stream) {
+  if (!params || !x || !target || !grad || !scratch) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (batch < 1 || batch > (int64_t(1) << 30)) return sfail(VFMM_ERR_INVALID_ARG, "bad batch");
+  if (scratch_bytes < vfmm_mlp_scratch_bytes(batch))
+    return sfail(VFMM_ERR_WORKSPACE, "scratch too small");
+  const int nb = mlp_blocks(batch);
+  char* s = static_cast<char*>(scratch);
+  float* part = reinterpret_cast<float*>(s);
+  float* lpart = reinterpret_cast<float*>(s + a256(size_t(nb) * mlp_param_count() * 4));
+  float* yv = reinterpret_cast<float*>(s + a256(size_t(nb) * mlp_param_count() * 4) + a256(size_t(nb) * 4));
+  hipError_t e = launch_mlp_gradient(params, bf16 != 0, x, target, batch, yv, part, lpart, grad,
+                                     loss, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "mlp gradient: %s", hipGetErrorString(e));
+}
+
+vfmm_status_t vfmm_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                            float lr, void* stream) {
+  if (!params || !m || !v || !grad) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (step < 1 || !(lr > 0.f)) return sfail(VFMM_ERR_INVALID_ARG, "step >= 1 and lr > 0 required");
+  hipError_t e = launch_adam(params, m, v, grad, step, lr, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "adam: %s", hipGetErrorString(e));
+}
+
+size_t vfmm_select_scratch_bytes(int64_t n) { return select_scratch(n < 1 ? 1 : n); }
+
+vfmm_status_t vfmm_particle_stats(const double* x, const double* y, const double* gamma, int64_t n,
+                                  void* scratch, size_t scratch_bytes, double* stats,
+                                  void* stream) {
+  if (!x || !y || !gamma || !scratch || !stats) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1) return sfail(VFMM_ERR_INVALID_ARG, "n must be >= 1");
+  if (scratch_bytes < a256(size_t(kReduceBlocks) * 12 * 8) + a256(12 * 8))
+    return sfail(VFMM_ERR_WORKSPACE, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* s = static_cast<char*>(scratch);
+  double* part = reinterpret_cast<double*>(s);
+  double* out = reinterpret_cast<double*>(s + a256(size_t(kReduceBlocks) * 12 * 8));
+  hipError_t e = launch_stats(x, y, gamma, n, part, out, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(stats, out, 12 * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "stats: %s", hipGetErrorString(e));
+}
+
+vfmm_status_t vfmm_selector_features(const double* st, int64_t n, double sigma, int32_t p,
+                                     int32_t levels, float* out) {
+  if (!st || !out) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1 || !(sigma > 0.0)) return sfail(VFMM_ERR_INVALID_ARG, "n >= 1 and sigma > 0 required");
+  const double dn = double(n);
+  const double S = root_side(st);
+  const double h = S / std::sqrt(dn);
+  const double mean_g = st[4] / dn, rms = std::sqrt(st[5] / dn);
+  const double mx = st[0] / dn, my = st[2] / dn;
+  const double sx = std::sqrt(std::fmax(0.0, st[1] / dn - mx * mx));
+  const double sy = std::sqrt(std::fmax(0.0, st[3] / dn - my * my));
+  const double lg = std::log2(dn);
+  out[0] = float(p);
+  out[1] = float(levels);
+  out[2] = float(lg);
+  out[3] = float(lg - 2.0 * levels);
+  out[4] = float(std::log2(S / std::ldexp(1.0, levels) / sigma));
+  out[5] = float(std::log2(sigma / h));
+  out[6] = float(rms > 0.0 ? mean_g / rms : 0.0);
+  out[7] = float(st[7] > 0.0 ? std::log10(st[6] / st[7]) : 0.0);
+  out[8] = float(sx / S);
+  out[9] = float(sy / S);
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_select_params(const double* x, const double* y, const double* gamma, int64_t n,
+                                 double sigma, double tol, const float* params,
+                                 const float* feat_mean, const float* feat_std, double margin,
+                                 void* scratch, size_t scratch_bytes, int32_t* p_out,
+                                 int32_t* levels_out, double* pred_out, int32_t* fallback_out,
+                                 void* stream) {
+  if (!x || !y || !gamma || !params || !feat_mean || !feat_std || !scratch || !p_out ||
+      !levels_out || !pred_out || !fallback_out)
+    return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1 || !(sigma > 0.0) || !std::isfinite(sigma)) return sfail(VFMM_ERR_INVALID_ARG, "bad n or sigma");
+  if (!(tol > 0.0) || !(margin >= 0.0)) return sfail(VFMM_ERR_INVALID_ARG, "tol > 0 and margin >= 0 required");
+  if (scratch_bytes < select_scratch(n)) return sfail(VFMM_ERR_WORKSPACE, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int lh = hist_level(n);
+  char* s = static_cast<char*>(scratch);
+  size_t off = 0;
+  double* part = reinterpret_cast<double*>(s + off); off += a256(size_t(kReduceBlocks) * 12 * 8);
+  double* sout = reinterpret_cast<double*>(s + off); off += a256(12 * 8);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(s + off); off += a256((size_t(1) << (2 * lh)) * 4);
+  const int ncand = (kPMax - kPMin + 1) * (lh - 1);
+  float* xd = reinterpret_cast<float*>(s + off); off += a256(size_t(ncand) * 10 * 4);
+  float* yd = reinterpret_cast<float*>(s + off);
+
+  double stats[12];
+  hipError_t e = launch_stats(x, y, gamma, n, part, sout, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(stats, sout, sizeof(stats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select stats: %s", hipGetErrorString(e));
+  const double S = root_side(stats);
+  const double root3[3] = {0.5 * (stats[8] + stats[9]) - 0.5 * S, 0.5 * (stats[10] + stats[11]) - 0.5 * S, S};
+  const size_t nl = size_t(1) << (2 * lh);
+  e = hipMemsetAsync(counts, 0, nl * 4, st);
+  if (e == hipSuccess) e = launch_leaf_hist(x, y, n, root3, lh, counts, st);
+  std::vector<uint32_t> hc(nl);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), counts, nl * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select histogram: %s", hipGetErrorString(e));
+
+  // occupancy at every level <= lh by 2 x 2 pooling; near-field pair counts
+  std::vector<std::vector<double>> occ(lh + 1);
+  occ[lh].assign(hc.begin(), hc.end());
+  for (int l = lh - 1; l >= 0; --l) {
+    const int m = 1 << l;
+    occ[l].assign(size_t(m) * m, 0.0);
+    for (int iy = 0; iy < 2 * m; ++iy)
+      for (int ix = 0; ix < 2 * m; ++ix) occ[l][size_t(iy >> 1) * m + (ix >> 1)] += occ[l + 1][size_t(iy) * 2 * m + ix];
+  }
+  // candidates and their features (z-scored)
+  std::vector<float> X(size_t(ncand) * 10);
+  std::vector<int> cp(ncand), cl(ncand);
+  int c = 0;
+  for (int L = 2; L <= lh; ++L)
+    for (int p = kPMin; p <= kPMax; ++p, ++c) {
+      float f[10];
+      vfmm_selector_features(stats, n, sigma, p, L, f);
+      for (int k = 0; k < 10; ++k) X[size_t(c) * 10 + k] = (f[k] - feat_mean[k]) / feat_std[k];
+      cp[c] = p;
+      cl[c] = L;
+    }
+  std::vector<float> pred(ncand);
+  e = hipMemcpyAsync(xd, X.data(), X.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_mlp_forward(params, true, xd, ncand, yd, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pred.data(), yd, size_t(ncand) * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select network: %s", hipGetErrorString(e));
+
+  // cost model (seconds on one MI355X, FP32 evaluation): near-field pairs,
+  // per-particle expansion work, per-box translations, per-level launches
+  const double lt = std::log10(tol);
+  double best = INFINITY;
+  int bi = -1;
+  for (int k = 0; k < ncand; ++k) {
+    if (double(pred[k]) + margin > lt) continue;
+    const int L = cl[k], p = cp[k];
+    double boxes = 0.0;
+    for (int l = 2; l <= L; ++l) boxes += std::ldexp(1.0, 2 * l);
+    const double cost = 3.1e-13 * near_pairs(occ[L], L) + 2.0e-11 * double(n) * p +
+                        1.2e-10 * boxes * p * p + 2.0e-5 * L;
+    if (cost < best) {
+      best = cost;
+      bi = k;
+    }
+  }
+  if (bi >= 0) {
+    *p_out = cp[bi];
+    *levels_out = cl[bi];
+    *pred_out = double(pred[bi]);
+    *fallback_out = 0;
+  } else {
+    int L = 0;
+    while (L + 1 <= kMaxLevels && S / std::ldexp(1.0, L + 1) / sigma >= 8.0 &&
+           (int64_t(1) << (2 * (L + 1))) <= 4 * n)
+      ++L;
+    *p_out = 20;
+    *levels_out = L;
+    *pred_out = NAN;
+    *fallback_out = 1;
+  }
+  return VFMM_OK;
+}
+
+}  // extern "C"

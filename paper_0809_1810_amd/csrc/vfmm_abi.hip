@@ -49,6 +49,14 @@ vfmm_status_t fail(vfmm_status_t s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+namespace vfmm {
+void set_last_error(const char* msg) { g_err = msg; }
+}  // namespace vfmm
+
+namespace {
+
 vfmm_status_t hip_fail(hipError_t e, const char* where) {
   return fail(VFMM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }

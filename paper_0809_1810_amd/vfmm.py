@@ -61,7 +61,27 @@ _SIGS = {
     "vfmm_tree_rebuild": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_tree_enable_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "vfmm_tree_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "vfmm_mlp_scratch_bytes": (C.c_size_t, [C.c_int64]),
+    "vfmm_mlp_forward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p]),
+    "vfmm_mlp_gradient": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "vfmm_mlp_adam": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_float, C.c_void_p]),
+    "vfmm_select_scratch_bytes": (C.c_size_t, [C.c_int64]),
+    "vfmm_particle_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
+    "vfmm_selector_features": (C.c_int32, [C.POINTER(C.c_double), C.c_int64, C.c_double, C.c_int32,
+                                           C.c_int32, C.POINTER(C.c_float)]),
+    "vfmm_select_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
+                                       C.c_double, C.c_void_p, C.POINTER(C.c_float),
+                                       C.POINTER(C.c_float), C.c_double, C.c_void_p, C.c_size_t,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
 }
+
+MLP_PARAMS = 4929
+N_FEATURES = 10
 
 N_PHASES = 6
 PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_l2p")
@@ -263,3 +283,100 @@ def error_metrics(u, v, u_ref, v_ref):
     mx, ss, den = out.cpu().tolist()
     den = den if den > 0 else 1.0
     return mx / den, (ss / n) ** 0.5 / den, den
+
+
+# ----------------------------------------------------------------- selector network
+
+
+def _dev_f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CUDA float32 tensor")
+    return t
+
+
+def mlp_forward(params, x, bf16=True, out=None):
+    """Network outputs for standardised features x [B, 10] (float32, device)."""
+    torch = _torch()
+    _dev_f32(params, "params"); _dev_f32(x, "x")
+    B = int(x.shape[0])
+    y = torch.empty(B, dtype=torch.float32, device=x.device) if out is None else out
+    _check(lib().vfmm_mlp_forward(params.data_ptr(), int(bool(bf16)), x.data_ptr(), B, y.data_ptr(),
+                                  _stream()), "vfmm_mlp_forward")
+    return y
+
+
+class MlpTrainer:
+    """Device state for training: master params, Adam moments, gradient, scratch."""
+
+    def __init__(self, params, max_batch):
+        torch = _torch()
+        self.params = _dev_f32(params, "params")
+        self.m = torch.zeros_like(params); self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        nb = int(lib().vfmm_mlp_scratch_bytes(int(max_batch)))
+        self.scratch = torch.empty(nb, dtype=torch.uint8, device=params.device)
+        self.max_batch = int(max_batch)
+        self.step_count = 0
+
+    def gradient(self, x, t, bf16=True):
+        _dev_f32(x, "x"); _dev_f32(t, "target")
+        B = int(x.shape[0])
+        if B > self.max_batch:
+            raise ValueError("batch larger than the trainer's scratch")
+        _check(lib().vfmm_mlp_gradient(self.params.data_ptr(), int(bool(bf16)), x.data_ptr(),
+                                       t.data_ptr(), B, self.grad.data_ptr(), self.loss.data_ptr(),
+                                       self.scratch.data_ptr(), self.scratch.numel(), _stream()),
+               "vfmm_mlp_gradient")
+        return self.grad, self.loss
+
+    def adam(self, lr):
+        self.step_count += 1
+        _check(lib().vfmm_mlp_adam(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                   self.grad.data_ptr(), self.step_count, float(lr), _stream()),
+               "vfmm_mlp_adam")
+
+    def step(self, x, t, lr, bf16=True):
+        self.gradient(x, t, bf16)
+        self.adam(lr)
+        return self.loss
+
+
+def particle_stats(x, y, gamma):
+    torch = _torch()
+    for t, n in ((x, "x"), (y, "y"), (gamma, "gamma")):
+        _dev_f64(t, n)
+    n = int(x.shape[0])
+    scratch = torch.empty(int(lib().vfmm_select_scratch_bytes(n)), dtype=torch.uint8, device=x.device)
+    st = (C.c_double * 12)()
+    _check(lib().vfmm_particle_stats(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n,
+                                     scratch.data_ptr(), scratch.numel(), st, _stream()),
+           "vfmm_particle_stats")
+    return list(st)
+
+
+def selector_features(stats, n, sigma, p, levels):
+    st = (C.c_double * 12)(*stats)
+    out = (C.c_float * N_FEATURES)()
+    _check(lib().vfmm_selector_features(st, int(n), float(sigma), int(p), int(levels), out),
+           "vfmm_selector_features")
+    return list(out)
+
+
+def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0.3):
+    """(p, levels, predicted log10 error, used_fallback) for an FP32 evaluation."""
+    torch = _torch()
+    for t, nme in ((x, "x"), (y, "y"), (gamma, "gamma")):
+        _dev_f64(t, nme)
+    _dev_f32(params, "params")
+    n = int(x.shape[0])
+    scratch = torch.empty(int(lib().vfmm_select_scratch_bytes(n)), dtype=torch.uint8, device=x.device)
+    fm = (C.c_float * N_FEATURES)(*[float(v) for v in feat_mean])
+    fs = (C.c_float * N_FEATURES)(*[float(v) for v in feat_std])
+    p = C.c_int32(0); L = C.c_int32(0); pred = C.c_double(0.0); fb = C.c_int32(0)
+    _check(lib().vfmm_select_params(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n, float(sigma),
+                                    float(tol), params.data_ptr(), fm, fs, float(margin),
+                                    scratch.data_ptr(), scratch.numel(), C.byref(p), C.byref(L),
+                                    C.byref(pred), C.byref(fb), _stream()), "vfmm_select_params")
+    return int(p.value), int(L.value), float(pred.value), bool(fb.value)

@@ -92,3 +92,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(vf.VfmmUnavailable):
         B.lib()
+
+
+def test_selector_features_host_function_matches_oracle():
+    """vfmm_selector_features is pure host code: compare with the oracle definition."""
+    _lib()
+    import numpy as np
+
+    import workloads as W
+    from oracle import mlp as OM
+    from oracle import quadtree as qt
+    P = W.clusters(3000, seed=2)
+    g = P.gamma
+    st = [P.x.sum(), (P.x ** 2).sum(), P.y.sum(), (P.y ** 2).sum(), g.sum(), (g ** 2).sum(),
+          np.abs(g).sum(), np.abs(g).max(), P.x.min(), P.x.max(), P.y.min(), P.y.max()]
+    side = qt.root_square(P.x, P.y)[2]
+    for p, L in ((4, 2), (9, 4), (20, 8)):
+        f = vf.selector_features(st, P.n, P.sigma, p, L)
+        fr = OM.features(P.x, P.y, g, P.sigma, p, L, side)
+        assert np.allclose(f, fr, rtol=1e-6, atol=1e-6), (f, fr)
