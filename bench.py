@@ -131,6 +131,12 @@ def main():
     side = float(probe.arrays()[0][2].item())
     probe.close()
 
+    # ---------------- audit targets and FP64 direct reference
+    tg = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
+    tg_d = torch.from_numpy(tg).cuda()
+    ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg_d)
+    torch.cuda.synchronize()
+
     # ---------------- parameter choice
     L_plain = largest_level(side, P.sigma, 8.0)
     p_plain = 20
@@ -142,8 +148,8 @@ def main():
         from paper_0809_1810_amd import selector as S
         weights = S.load_weights()
         s0 = time.perf_counter()
-        r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=weights, n_audit=AUDIT_TARGETS,
-                               seed=7)
+        r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=weights, targets=tg_d,
+                               reference=(ud, vd))
         torch.cuda.synchronize()
         sel_ms = (time.perf_counter() - s0) * 1e3
         p_t, L_t = r["p"], r["levels"]
@@ -151,14 +157,10 @@ def main():
             prec_t = vf.FP64
         selector = "learned" if not r["fallback"] else "fallback"
         sel_info = {"predicted_log10_emax": r["predicted_log10"], "audit_emax": r["audit_emax"],
-                    "fallback": r["fallback"], "select_and_audit_ms": round(sel_ms, 2)}
+                    "fallback": r["fallback"], "network_choice": r["network_choice"],
+                    "audit_trail": r["trail"], "select_and_audit_ms": round(sel_ms, 2)}
         log(f"[bench] selector: {json.dumps(r)} in {sel_ms:.1f} ms")
 
-    # ---------------- audit targets and FP64 direct reference
-    tg = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
-    tg_d = torch.from_numpy(tg).cuda()
-    ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg_d)
-    torch.cuda.synchronize()
 
     def run_path(L, p, prec, steps, warmup, timing=False):
         tree = vf.Tree(x, y, L, p_max=p)

@@ -26,7 +26,8 @@
 // which gives bit-identical results without the exponential.
 //
 // FP32 variant: per-pair arithmetic in FP32 with the hardware exp2 and
-// reciprocal; partial sums over chunks of 64 sources are added into a
+// reciprocal (and a short series for 1 - exp when r < sigma / 4, used only in
+// chunks whose bounding box comes that close to the tile); partial sums over chunks of 64 sources are added into a
 // compensated (TwoSum) FP32 accumulator, which keeps the rounding of long
 // source loops (up to ~1e5 sources per target) near the per-term level.
 // FP64 variant: plain FP64 with expm1 and division.
@@ -53,19 +54,34 @@ template <typename R> struct P2PMath;
 
 template <> struct P2PMath<double> {
   static constexpr double kFarSigma2 = 76.0;  // exp(-38) < 2^-54
+  static constexpr double kSeriesSigma2 = -1.0;  // expm1 is accurate for small r: no series
   // Gamma (1 - exp(r2 kexp)) / r2 with kexp = -1 / (2 sigma^2)
   __device__ __forceinline__ static double near(double g, double r2, double kexp) {
     return g * (-expm1(r2 * kexp) / r2);
+  }
+  __device__ __forceinline__ static double near_series(double g, double r2, double kexp, double) {
+    return near(g, r2, kexp);
   }
   __device__ __forceinline__ static double far(double g, double r2) { return g / r2; }
 };
 
 template <> struct P2PMath<float> {
   static constexpr double kFarSigma2 = 36.0;  // exp(-18) < 2^-25
+  static constexpr double kSeriesSigma2 = 1.0 / 16.0;  // a = r^2 / 2 sigma^2 < 1/32
   // kexp = -log2(e) / (2 sigma^2); Gamma (1 - e) computed as one fused op
   __device__ __forceinline__ static float near(float g, float r2, float kexp) {
     const float e = __builtin_amdgcn_exp2f(r2 * kexp);
     return __builtin_fmaf(-g, e, g) * __builtin_amdgcn_rcpf(r2);
+  }
+  // Close pairs: 1 - exp(-a) from the hardware exp has an absolute error of
+  // ~2^-24, which divided by r would dominate for r << sigma; below a = 1/32
+  // the series a (1 - a/2 + a^2/6 - a^3/24) is used (truncation < 8e-9).
+  __device__ __forceinline__ static float near_series(float g, float r2, float kexp, float ka) {
+    const float a = r2 * ka;
+    const float ser = a * (1.0f - a * (0.5f - a * (1.0f / 6.0f - a * (1.0f / 24.0f))));
+    const float e = __builtin_amdgcn_exp2f(r2 * kexp);
+    const float om = a < 0.03125f ? ser : 1.0f - e;
+    return g * om * __builtin_amdgcn_rcpf(r2);
   }
   __device__ __forceinline__ static float far(float g, float r2) {
     return g * __builtin_amdgcn_rcpf(r2);
@@ -78,7 +94,8 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
     const Tile* __restrict__ tiles, const int32_t* __restrict__ ntiles,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
     const double* __restrict__ root, int levels, int p,
-    const typename Types<R>::C* __restrict__ le_leaf, R kexp, float far2, int parts,
+    const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
+    int parts,
     const int32_t* __restrict__ perm, double* __restrict__ u, double* __restrict__ v) {
   using C = typename Types<R>::C;
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -117,7 +134,8 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
           const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
           const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
           R cu = R(0), cv = R(0);
-          if (gx * gx + gy * gy > far2) {
+          const float gap2 = gx * gx + gy * gy;
+          if (gap2 > far2) {
 #pragma unroll 8
             for (int32_t j = j0; j < j1; ++j) {
               const auto s = part[j];
@@ -127,7 +145,7 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
               cu -= f * dy;
               cv += f * dx;
             }
-          } else {
+          } else if (gap2 > ser2) {
 #pragma unroll 8
             for (int32_t j = j0; j < j1; ++j) {
               const auto s = part[j];
@@ -135,6 +153,17 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
               const R dy = ty - s.y;
               const R r2 = dx * dx + (dy * dy + tiny);
               const R f = P2PMath<R>::near(s.g, r2, kexp);
+              cu -= f * dy;
+              cv += f * dx;
+            }
+          } else {
+#pragma unroll 4
+            for (int32_t j = j0; j < j1; ++j) {
+              const auto s = part[j];
+              const R dx = tx - s.x;
+              const R dy = ty - s.y;
+              const R r2 = dx * dx + (dy * dy + tiny);
+              const R f = P2PMath<R>::near_series(s.g, r2, kexp, ka);
               cu -= f * dy;
               cv += f * dx;
             }
@@ -195,10 +224,12 @@ void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sig
   const double k64 = -1.0 / (2.0 * sigma * sigma);
   const R kexp = sizeof(R) == 8 ? R(k64) : R(k64 * 1.4426950408889634074);
   const float far2 = float(P2PMath<R>::kFarSigma2 * sigma * sigma);
+  const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
+  const R ka = R(1.0 / (2.0 * sigma * sigma));
   const unsigned blocks = unsigned((lay.max_tiles + 3) / 4);
   hipLaunchKernelGGL((k_p2p_l2p<R, PMAX>), dim3(blocks), dim3(256), 0, st, part, t.leaf_start,
-                     t.tiles, t.ntiles, t.tile_off, t.tile_box, t.root, levels, p, le, kexp, far2,
-                     parts, t.perm, u, v);
+                     t.tiles, t.ntiles, t.tile_off, t.tile_box, t.root, levels, p, le, kexp, ka,
+                     far2, ser2, parts, t.perm, u, v);
 }
 
 template <typename R>

@@ -196,43 +196,56 @@ def conservative_choice(side, sigma, n):
     return 20, L
 
 
-def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, audit=True):
-    """Selected (p, L), audited by the FP64 direct sum on n_audit sampled targets.
+def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, audit=True,
+                     slack=0.8, targets=None, reference=None):
+    """Selected (p, L), audited by the FP64 direct sum on sampled targets.
 
-    Returns a dict with the choice, whether the network or the fallback chose it,
-    the precision and the audited error; if the FP32 audit fails, the
-    conservative choice is evaluated in FP64 and returned instead.
+    The network's choice is evaluated in FP32 and accepted if its error on the
+    audit targets is <= slack * tol; otherwise p is raised by 2 at the same level
+    (up to 20) and audited again; if FP32 still misses, the conservative choice
+    is evaluated in FP64 (the FP32 floor -- rounding of positions and
+    circulations, amplified by mixed signs -- can exceed tol).  ``targets``
+    (device int64) and ``reference`` ((u, v) of the direct sum there) may be
+    supplied; otherwise n_audit targets are drawn with ``seed``.
+    Returns a dict with the choice, its precision, the audited error, the
+    network's prediction and the audit trail.
     """
     torch = _torch()
     params, mean, std, margin = weights if weights is not None else load_weights()
     p, L, pred, fb = V.select_params(x, y, g, sigma, tol, params, mean, std, margin)
-    out = {"p": p, "levels": L, "predicted_log10": pred, "fallback": fb, "audited": False}
+    out = {"p": p, "levels": L, "predicted_log10": pred, "fallback": fb, "audited": False,
+           "precision": "fp32", "network_choice": [p, L]}
     if not audit:
         return out
     n = int(x.shape[0])
-    rng = np.random.default_rng(seed)
-    k = min(n, n_audit)
-    tg = torch.from_numpy(np.sort(rng.choice(n, k, replace=False)).astype(np.int64)).cuda()
-    ud, vd = V.direct_velocity(x, y, g, sigma, targets=tg)
+    if targets is None:
+        rng = np.random.default_rng(seed)
+        targets = torch.from_numpy(np.sort(rng.choice(n, min(n, n_audit), replace=False)).astype(np.int64)).cuda()
+    ud, vd = reference if reference is not None else V.direct_velocity(x, y, g, sigma, targets=targets)
 
     def run(pp, LL, prec):
         t = V.Tree(x, y, LL, p_max=pp)
         u, v = t.velocity(g, sigma, pp, prec)
-        e = V.error_metrics(u[tg].contiguous(), v[tg].contiguous(), ud, vd)[0]
+        e = V.error_metrics(u[targets].contiguous(), v[targets].contiguous(), ud, vd)[0]
         t.close()
         return e
 
+    trail = []
     e = run(p, L, V.FP32)
-    out.update(audited=True, audit_emax=e, precision="fp32")
-    if e > tol:
-        # the FP32 floor (rounding of positions and circulations, amplified by
-        # mixed signs) can exceed tol: fall back to the plain FP64 evaluation
+    trail.append([p, L, "fp32", e])
+    while e > slack * tol and p < 20:
+        p = min(20, p + 2)
+        e = run(p, L, V.FP32)
+        trail.append([p, L, "fp32", e])
+    out.update(p=p, levels=L, audited=True, audit_emax=e, trail=trail)
+    if e > slack * tol:
         root = V.Tree(x, y, 0, p_max=1)
         side = float(root.arrays()[0][2].item())
         root.close()
         pc, Lc = conservative_choice(side, sigma, n)
-        out.update(p=pc, levels=Lc, fallback=True, audit_failed=True, precision="fp64",
-                   audit_emax=run(pc, Lc, V.FP64))
+        e = run(pc, Lc, V.FP64)
+        trail.append([pc, Lc, "fp64", e])
+        out.update(p=pc, levels=Lc, fallback=True, precision="fp64", audit_emax=e)
     return out
 
 
