@@ -264,6 +264,47 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
                                  void* scratch, size_t scratch_bytes, int32_t* p, int32_t* levels,
                                  double* predicted_log10, int32_t* used_fallback, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched evaluation of many independent instances (uneven n, p, levels), the
+ * parameter sweeps of Section 5 run together.  Each phase runs once for all
+ * instances (a global sort on (instance, leaf, sub-cell) keys, one launch per
+ * phase or per level), so the launch count does not grow with the number of
+ * instances, and the sequence can be captured in a hipGraph and replayed.
+ * Arithmetic: near field in FP32 (compensated sums, series for close pairs);
+ * expansions in FP32 for p <= 16 and FP64 for p > 16. */
+typedef struct vfmm_instance {
+  const double* x;      /* device, n: positions */
+  const double* y;
+  const double* gamma;  /* device, n: circulations */
+  double* u;            /* device, n: velocity out (input order) */
+  double* v;
+  int64_t n;            /* >= 1; sum over instances <= 2^31 - 1 */
+  double sigma;         /* > 0 */
+  int32_t p;            /* 1 .. 24 */
+  int32_t levels;       /* 0 .. 6 */
+} vfmm_instance;
+
+typedef struct vfmm_batch_s* vfmm_batch_t;
+
+/* Device workspace for a batch of `count` instances (1 .. 4096), host array. */
+vfmm_status_t vfmm_batch_workspace_bytes(const vfmm_instance* inst, int32_t count, size_t* bytes);
+
+/* Plans a batch: validates the instances, lays out the workspace (256-byte
+ * aligned, caller-owned) and uploads the per-instance offset tables
+ * (synchronous).  The instance pointers are recorded: later runs read and
+ * write the same buffers, whose contents may change between runs. */
+vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* workspace,
+                                size_t ws_bytes, vfmm_batch_t* out);
+
+/* Evaluates every instance.  use_graph = 0: enqueue the kernels on `stream`.
+ * use_graph = 1: the first call captures the sequence in a hipGraph on
+ * `stream` (which must not be the NULL stream) and every call replays it.
+ * The first call also builds the translation tables (outside any capture). */
+vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream);
+
+/* Releases the plan and its graph (not the workspace).  NULL is ignored. */
+void vfmm_batch_destroy(vfmm_batch_t batch);
+
 /* Releases the tree handle (not the caller's workspace).  NULL is ignored. */
 void vfmm_tree_destroy(vfmm_tree_t tree);
 

@@ -3,14 +3,14 @@
 The computation lives in the HIP library ``libvfmm.so`` (C ABI in
 ``include/vfmm.h``); this package is its thin Python binding.
 """
-from .vfmm import (FP32, FP64, M2L_BF16, M2L_FP16, MAX_LEVELS, MAX_P, MLP_PARAMS, N_FEATURES,
+from .vfmm import (Batch, FP32, FP64, M2L_BF16, M2L_FP16, MAX_LEVELS, MAX_P, MLP_PARAMS, N_FEATURES,
                    PART_ALL, PART_FAR, PART_NEAR, PRECISIONS, MlpTrainer, Tree, VfmmError,
                    VfmmUnavailable, build_tree, direct_velocity, error_metrics, fmm_velocity,
                    header_symbols, lib, mlp_forward, particle_stats, select_params,
                    selector_features, workspace_bytes)
 
 __all__ = [
-    "FP32", "FP64", "M2L_BF16", "M2L_FP16", "MAX_LEVELS", "MAX_P", "MLP_PARAMS", "N_FEATURES",
+    "Batch", "FP32", "FP64", "M2L_BF16", "M2L_FP16", "MAX_LEVELS", "MAX_P", "MLP_PARAMS", "N_FEATURES",
     "PART_ALL", "PART_FAR", "PART_NEAR", "PRECISIONS", "MlpTrainer", "Tree", "VfmmError",
     "VfmmUnavailable", "build_tree", "direct_velocity", "error_metrics", "fmm_velocity",
     "header_symbols", "lib", "mlp_forward", "particle_stats", "select_params",

@@ -1,0 +1,771 @@
+// Batched evaluation of many independent FMM instances (uneven N, p, levels).
+//
+// Each phase of the method (Section 3.1, Fig. 3) runs ONCE for all instances:
+// bounding squares, one global stable radix sort on (instance, leaf, sub-cell)
+// keys, leaf ranges, tiles, P2M, M2M (one launch per level), M2L + L2L (one
+// launch per level), and P2P + L2P + combine.  A work item (particle, leaf,
+// box coefficient, tile) finds its instance by binary search in a small table of
+// per-instance offsets, so the launch count does not depend on the number of
+// instances, and the whole sequence can be captured once in a hipGraph and
+// replayed.
+//
+// Arithmetic per instance: P2P in FP32 (as in p2p.hip); expansions (P2M, M2M,
+// M2L, L2L, L2P) in FP32 for p <= 16 and in FP64 for p > 16, on the scaled,
+// level-independent operators of expansions.hip (one table set per p).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "../../include/vfmm.h"
+#include "p2p_math.hpp"
+
+namespace vfmm {
+
+// Device descriptor of one instance.
+struct BatchInst {
+  const double* x;
+  const double* y;
+  const double* g;
+  double* u;
+  double* v;
+  int64_t n;
+  int64_t part_off;  // first particle in the concatenated (sorted) arrays
+  int64_t leaf_off;  // first global leaf; leaf_start entries start at leaf_off + index
+  int64_t me_off;    // byte offset of the level-2 coefficients in the ME / LE buffers
+  double sigma;
+  int32_t p, L, fp64, pad;
+};
+
+constexpr int kBatchMaxLevels = 6;   // leaf index fits 12 key bits
+constexpr int kBatchKeyInst = 20;    // key = inst << 20 | leaf << 8 | sub-cell
+constexpr int kBatchPMax = 24;
+
+namespace {
+
+__device__ __forceinline__ int find_seg(const int64_t* off, int count, int64_t i) {
+  // index c with off[c] <= i < off[c + 1] (off has count + 1 entries)
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline uint32_t spread4b(uint32_t v) {
+  v &= 15u;
+  v = (v | (v << 2)) & 0x33u;
+  v = (v | (v << 1)) & 0x55u;
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_b_bbox(const BatchInst* __restrict__ I,
+                                                double* __restrict__ roots) {
+#pragma clang fp contract(off)
+  __shared__ double s[4][256];
+  const BatchInst in = I[blockIdx.x];
+  double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
+  for (int64_t i = threadIdx.x; i < in.n; i += 256) {
+    const double xi = in.x[i], yi = in.y[i];
+    a = fmin(a, xi); b = fmax(b, xi); c = fmin(c, yi); d = fmax(d, yi);
+  }
+  s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c; s[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) {
+      const int o = threadIdx.x + st;
+      s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][o]);
+      s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][o]);
+      s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][o]);
+      s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ext = fmax(s[1][0] - s[0][0], s[3][0] - s[2][0]);
+    const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : 1.0;
+    double* r = roots + 4 * blockIdx.x;
+    r[0] = 0.5 * (s[0][0] + s[1][0]) - 0.5 * S;
+    r[1] = 0.5 * (s[2][0] + s[3][0]) - 0.5 * S;
+    r[2] = S;
+    r[3] = S / double(1 << in.L);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
+                                                const int64_t* __restrict__ part_off, int count,
+                                                int64_t ntot, const double* __restrict__ roots,
+                                                uint32_t* __restrict__ keys,
+                                                int32_t* __restrict__ idx) {
+#pragma clang fp contract(off)
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= ntot) return;
+  const int c = find_seg(part_off, count, i);
+  const BatchInst in = I[c];
+  const int64_t j = i - in.part_off;
+  const double* r = roots + 4 * c;
+  const int mf = 1 << (in.L + kSubLevels);
+  const double fx = floor(((in.x[j] - r[0]) / r[2]) * double(mf));
+  const double fy = floor(((in.y[j] - r[1]) / r[2]) * double(mf));
+  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
+  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
+  const uint32_t leaf = (uint32_t(iy >> kSubLevels) << in.L) | uint32_t(ix >> kSubLevels);
+  const uint32_t sub = spread4b(uint32_t(ix)) | (spread4b(uint32_t(iy)) << 1);
+  keys[i] = (uint32_t(c) << kBatchKeyInst) | (leaf << (2 * kSubLevels)) | sub;
+  idx[i] = int32_t(i);
+}
+
+// leaf_start[leaf_off + c + k] = first sorted position of leaf k of instance c,
+// k = 0 .. 4^L (the last entry ends the instance).
+__global__ void __launch_bounds__(256) k_b_leaf_start(const int64_t* __restrict__ ls_off,
+                                                      int count, const uint32_t* __restrict__ keys,
+                                                      int64_t ntot, int32_t* __restrict__ start) {
+  const int64_t q = blockIdx.x * 256LL + threadIdx.x;
+  if (q >= ls_off[count]) return;
+  const int c = find_seg(ls_off, count, q);
+  const int64_t k = q - ls_off[c];
+  const uint64_t key = (uint64_t(c) << kBatchKeyInst) + (uint64_t(k) << (2 * kSubLevels));
+  int64_t lo = 0, hi = ntot;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (uint64_t(keys[mid]) < key) lo = mid + 1; else hi = mid;
+  }
+  start[q] = int32_t(lo);
+}
+
+__global__ void __launch_bounds__(256) k_b_local(const BatchInst* __restrict__ I,
+                                                 const uint32_t* __restrict__ keys,
+                                                 const int32_t* __restrict__ perm, int64_t ntot,
+                                                 const double* __restrict__ roots,
+                                                 Part32* __restrict__ p32) {
+#pragma clang fp contract(off)
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= ntot) return;
+  const uint32_t key = keys[i];
+  const int c = int(key >> kBatchKeyInst);
+  const BatchInst in = I[c];
+  const uint32_t leaf = (key >> (2 * kSubLevels)) & 0xFFFu;
+  const int ix = int(leaf & ((1u << in.L) - 1u)), iy = int(leaf >> in.L);
+  const double* r = roots + 4 * c;
+  const double cx = r[0] + (double(ix) + 0.5) * r[3];
+  const double cy = r[1] + (double(iy) + 0.5) * r[3];
+  const int64_t j = int64_t(perm[i]) - in.part_off;
+  p32[i] = Part32{float(in.x[j] - cx), float(in.y[j] - cy), float(in.g[j]), 0.0f};
+}
+
+__global__ void __launch_bounds__(256) k_b_tile_counts(const int64_t* __restrict__ leaf_off,
+                                                       int count,
+                                                       const int32_t* __restrict__ start,
+                                                       uint32_t* __restrict__ cnt) {
+  const int64_t gl = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t nl = leaf_off[count];
+  if (gl > nl) return;
+  if (gl == nl) {
+    cnt[gl] = 0u;
+    return;
+  }
+  const int c = find_seg(leaf_off, count, gl);
+  const int64_t q = gl + c;
+  cnt[gl] = uint32_t((start[q + 1] - start[q] + kTile - 1) / kTile);
+}
+
+__global__ void __launch_bounds__(256) k_b_tile_fill(const BatchInst* __restrict__ I,
+                                                     const uint32_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ toff,
+                                                     int64_t ntot, int64_t nleaves,
+                                                     Tile* __restrict__ tiles,
+                                                     int32_t* __restrict__ ntiles) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i == 0) *ntiles = int32_t(toff[nleaves]);
+  if (i >= ntot) return;
+  const uint32_t key = keys[i];
+  const int c = int(key >> kBatchKeyInst);
+  const int64_t gl = I[c].leaf_off + ((key >> (2 * kSubLevels)) & 0xFFFu);
+  const int32_t s = start[gl + c], cnt = start[gl + c + 1] - s;
+  const int32_t r = int32_t(i) - s;
+  if (r % kTile != 0) return;
+  const int32_t cc = cnt - r;
+  tiles[toff[gl] + r / kTile] = Tile{int32_t(gl), int32_t(i), cc < kTile ? cc : kTile, c};
+}
+
+// ------------------------------------------------------------------ expansions
+
+template <typename R>
+__device__ __forceinline__ typename Types<R>::C* coef(char* base, const BatchInst& in, int lev) {
+  return reinterpret_cast<typename Types<R>::C*>(base + in.me_off) + level_offset(lev) * in.p;
+}
+
+template <typename R>
+__device__ void p2m_leaf(const BatchInst& in, const Part32* __restrict__ p32, int32_t s, int32_t e,
+                         double w, int leaf, char* me, double* red) {
+  using C = typename Types<R>::C;
+  const int lane = threadIdx.x;
+  const R inv_w = R(1.0 / w);
+  C acc[kBatchPMax];
+#pragma unroll
+  for (int k = 0; k < kBatchPMax; ++k) acc[k] = cmake<C>(R(0), R(0));
+  for (int32_t i = s + lane; i < e; i += 64) {
+    const Part32 q = p32[i];
+    const C z = cmake<C>(R(q.x) * inv_w, R(q.y) * inv_w);
+    C pw = cmake<C>(R(q.g), R(0));
+#pragma unroll
+    for (int k = 0; k < kBatchPMax; ++k) {
+      if (k < in.p) {
+        acc[k].x += pw.x;
+        acc[k].y += pw.y;
+        pw = cmul(pw, z);
+      }
+    }
+  }
+  // reduce over lanes: 2 p values per lane, through LDS (stride 65)
+#pragma unroll
+  for (int k = 0; k < kBatchPMax; ++k) {
+    red[(2 * k) * 65 + lane] = double(acc[k].x);
+    red[(2 * k + 1) * 65 + lane] = double(acc[k].y);
+  }
+  __syncthreads();
+  R* out = reinterpret_cast<R*>(coef<R>(me, in, in.L) + int64_t(leaf) * in.p);
+  for (int cc = lane; cc < 2 * in.p; cc += 64) {
+    double t = 0.0;
+    for (int l = 0; l < 64; ++l) t += red[cc * 65 + l];
+    out[cc] = R(t);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_b_p2m(const BatchInst* __restrict__ I,
+                                              const int64_t* __restrict__ leaf_off, int count,
+                                              const int32_t* __restrict__ start,
+                                              const Part32* __restrict__ p32,
+                                              const double* __restrict__ roots, char* me) {
+  __shared__ double red[2 * kBatchPMax * 65];
+  const int64_t gl = blockIdx.x;
+  const int c = find_seg(leaf_off, count, gl);
+  const BatchInst in = I[c];
+  const int leaf = int(gl - in.leaf_off);
+  if (in.L < 2) return;
+  const int32_t s = start[gl + c], e = start[gl + c + 1];
+  const double w = roots[4 * c + 3];
+  if (in.fp64) p2m_leaf<double>(in, p32, s, e, w, leaf, me, red);
+  else p2m_leaf<float>(in, p32, s, e, w, leaf, me, red);
+}
+
+template <typename R>
+__device__ void m2m_item(const BatchInst& in, int lev, int64_t item, char* me, const char* tab,
+                         const int64_t* tab_off) {
+  using C = typename Types<R>::C;
+  const int p = in.p;
+  const int64_t box = item / p;
+  const int n = int(item % p);
+  const int mp = 1 << lev, mc = 2 * mp;
+  const int px = int(box & (mp - 1)), py = int(box >> lev);
+  const OpsLayout ol = ops_layout(p);
+  const C* A = reinterpret_cast<const C*>(tab + tab_off[p] + (sizeof(R) == 8 ? ol.m2m64 : ol.m2m32));
+  const C* child = coef<R>(me, in, lev + 1);
+  C acc = cmake<C>(R(0), R(0));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t cb = int64_t(2 * py + (q >> 1)) * mc + (2 * px + (q & 1));
+    const C* m = child + cb * p;
+    const C* a = A + (q * p + n) * p;
+    for (int k = 0; k <= n; ++k) cfma(acc, a[k], m[k]);
+  }
+  coef<R>(me, in, lev)[box * p + n] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_b_m2m(const BatchInst* __restrict__ I,
+                                               const int64_t* __restrict__ items, int count,
+                                               int lev, char* me, const char* tab,
+                                               const int64_t* __restrict__ tab_off) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= items[count]) return;
+  const int c = find_seg(items, count, t);
+  const BatchInst in = I[c];
+  const int64_t item = t - items[c];
+  if (in.fp64) m2m_item<double>(in, lev, item, me, tab, tab_off);
+  else m2m_item<float>(in, lev, item, me, tab, tab_off);
+}
+
+template <typename R>
+__device__ void m2l_item(const BatchInst& in, int lev, int64_t item, char* me, char* le,
+                         const char* tab, const int64_t* tab_off) {
+  using C = typename Types<R>::C;
+  const int p = in.p;
+  const int64_t box = item / p;
+  const int n = int(item % p);
+  const int m = 1 << lev;
+  const int bx = int(box & (m - 1)), by = int(box >> lev);
+  const OpsLayout ol = ops_layout(p);
+  const C* T = reinterpret_cast<const C*>(tab + tab_off[p] + (sizeof(R) == 8 ? ol.m2l64 : ol.m2l32));
+  const C* B = reinterpret_cast<const C*>(tab + tab_off[p] + (sizeof(R) == 8 ? ol.l2l64 : ol.l2l32));
+  C acc = cmake<C>(R(0), R(0));
+  if (lev > 2) {
+    const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
+    const int q = ((by & 1) << 1) | (bx & 1);
+    const C* lp = coef<R>(le, in, lev - 1) + pb * p;
+    const C* b = B + (q * p + n) * p;
+    for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
+  }
+  const C* mel = coef<R>(me, in, lev);
+  const int px = bx >> 1, py = by >> 1;
+  const int x0 = max(2 * px - 2, 0), x1 = min(2 * px + 3, m - 1);
+  const int y0 = max(2 * py - 2, 0), y1 = min(2 * py + 3, m - 1);
+  for (int sy = y0; sy <= y1; ++sy)
+    for (int sx = x0; sx <= x1; ++sx) {
+      const int ox = bx - sx, oy = by - sy;
+      if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
+      const C* ms = mel + (int64_t(sy) * m + sx) * p;
+      const C* tr = T + (m2l_index(ox, oy) * p + n) * p;
+      for (int k = 0; k < p; ++k) cfma(acc, tr[k], ms[k]);
+    }
+  coef<R>(le, in, lev)[box * p + n] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_b_m2l(const BatchInst* __restrict__ I,
+                                               const int64_t* __restrict__ items, int count,
+                                               int lev, char* me, char* le, const char* tab,
+                                               const int64_t* __restrict__ tab_off) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= items[count]) return;
+  const int c = find_seg(items, count, t);
+  const BatchInst in = I[c];
+  const int64_t item = t - items[c];
+  if (in.fp64) m2l_item<double>(in, lev, item, me, le, tab, tab_off);
+  else m2l_item<float>(in, lev, item, me, le, tab, tab_off);
+}
+
+// ------------------------------------------------------------------ near field + evaluation
+
+template <typename R>
+__device__ __forceinline__ void l2p_eval(const BatchInst& in, const char* le, int leaf, float zx,
+                                         float zy, double w, double& fu, double& fv) {
+  using C = typename Types<R>::C;
+  const R inv_w = R(1.0 / w);
+  const C z = cmake<C>(R(zx) * inv_w, R(zy) * inv_w);
+  const C* Lc = reinterpret_cast<const C*>(le + in.me_off) + level_offset(in.L) * in.p +
+                int64_t(leaf) * in.p;
+  C acc = cmake<C>(R(0), R(0));
+  for (int k = in.p - 1; k >= 0; --k) {
+    const C lk = Lc[k];
+    acc = cmul(acc, z);
+    acc.x += lk.x;
+    acc.y += lk.y;
+  }
+  const double sc = kInv2Pi / w;
+  fu = double(acc.y) * sc;
+  fv = double(acc.x) * sc;
+}
+
+__global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
+                                               const Part32* __restrict__ part,
+                                               const int32_t* __restrict__ start,
+                                               const Tile* __restrict__ tiles,
+                                               const int32_t* __restrict__ ntiles,
+                                               const uint32_t* __restrict__ tile_off,
+                                               const float4* __restrict__ tile_box,
+                                               const double* __restrict__ roots,
+                                               const char* __restrict__ le,
+                                               const int32_t* __restrict__ perm) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const Tile tile = tiles[wid];
+  const int c = __builtin_amdgcn_readfirstlane(tile.pad);
+  const BatchInst in = I[c];
+  const bool active = lane < tile.count;
+  const int32_t i = tile.start + (active ? lane : 0);
+  const Part32 tp = part[i];
+  const int L = in.L, m = 1 << L;
+  const int leaf = int(tile.leaf - in.leaf_off);
+  const int bx = leaf & (m - 1), by = leaf >> L;
+  const double w = roots[4 * c + 3];
+  const double sg = in.sigma;
+  const float kexp = float(-1.4426950408889634074 / (2.0 * sg * sg));
+  const float ka = float(1.0 / (2.0 * sg * sg));
+  const float far2 = float(P2PMath<float>::kFarSigma2 * sg * sg);
+  const float ser2 = float(P2PMath<float>::kSeriesSigma2 * sg * sg);
+  const float tiny = float(w * w * 0x1p-80);
+  const float4 tb = tile_box[wid];
+  Acc32 au{0.f, 0.f}, av{0.f, 0.f};
+  for (int oy = -1; oy <= 1; ++oy) {
+    const int sy = by + oy;
+    if (sy < 0 || sy >= m) continue;
+    for (int ox = -1; ox <= 1; ++ox) {
+      const int sx = bx + ox;
+      if (sx < 0 || sx >= m) continue;
+      const int64_t gsl = in.leaf_off + sy * m + sx;
+      const int32_t js = start[gsl + c], je = start[gsl + c + 1];
+      const float tx = tp.x - float(double(ox) * w);
+      const float ty = tp.y - float(double(oy) * w);
+      const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
+      const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
+      uint32_t ci = tile_off[gsl];
+      for (int32_t j0 = js; j0 < je; j0 += 64, ++ci) {
+        const int32_t j1 = min(j0 + 64, je);
+        const float4 sb = tile_box[ci];
+        const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
+        const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
+        const float gap2 = gx * gx + gy * gy;
+        float cu = 0.f, cv = 0.f;
+        if (gap2 > far2) {
+#pragma unroll 8
+          for (int32_t j = j0; j < j1; ++j) {
+            const Part32 s = part[j];
+            const float dx = tx - s.x, dy = ty - s.y;
+            const float f = P2PMath<float>::far(s.g, dx * dx + dy * dy);
+            cu -= f * dy;
+            cv += f * dx;
+          }
+        } else if (gap2 > ser2) {
+#pragma unroll 8
+          for (int32_t j = j0; j < j1; ++j) {
+            const Part32 s = part[j];
+            const float dx = tx - s.x, dy = ty - s.y;
+            const float f = P2PMath<float>::near(s.g, dx * dx + (dy * dy + tiny), kexp);
+            cu -= f * dy;
+            cv += f * dx;
+          }
+        } else {
+#pragma unroll 4
+          for (int32_t j = j0; j < j1; ++j) {
+            const Part32 s = part[j];
+            const float dx = tx - s.x, dy = ty - s.y;
+            const float f = P2PMath<float>::near_series(s.g, dx * dx + (dy * dy + tiny), kexp, ka);
+            cu -= f * dy;
+            cv += f * dx;
+          }
+        }
+        au.add(cu);
+        av.add(cv);
+      }
+    }
+  }
+  double fu = 0.0, fv = 0.0;
+  if (L >= 2) {
+    if (in.fp64) l2p_eval<double>(in, le, leaf, tp.x, tp.y, w, fu, fv);
+    else l2p_eval<float>(in, le, leaf, tp.x, tp.y, w, fu, fv);
+  }
+  if (active) {
+    const int64_t o = int64_t(perm[i]) - in.part_off;
+    in.u[o] = au.value() * kInv2Pi + fu;
+    in.v[o] = av.value() * kInv2Pi + fv;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host plan
+
+struct BatchPlanDev {
+  BatchInst* inst;
+  int64_t *part_off, *leaf_off, *ls_off, *tab_off;
+  int64_t* m2m_items;  // [kBatchMaxLevels + 1][count + 1]
+  int64_t* m2l_items;
+  double* roots;
+  uint32_t *k0, *k1, *counts, *tmp, *toff;
+  int32_t *i0, *i1, *start, *ntiles;
+  Tile* tiles;
+  float4* tile_box;
+  Part32* p32;
+  char *me, *le, *tab;
+};
+
+hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int64_t nleaves,
+                            int64_t max_tiles, const int64_t* m2m_tot, const int64_t* m2l_tot,
+                            int maxL, hipStream_t st) {
+  auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
+  hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots);
+  hipLaunchKernelGGL(k_b_keys, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, d.part_off, count,
+                     ntot, d.roots, d.k0, d.i0);
+  uint32_t* k0 = d.k0; uint32_t* k1 = d.k1;
+  int32_t* i0 = d.i0; int32_t* i1 = d.i1;
+  int ibits = 1;
+  while ((1 << ibits) < count) ++ibits;
+  hipError_t e = radix_sort_pairs(k0, k1, i0, i1, ntot, kBatchKeyInst + ibits, d.counts, d.tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_leaf_start, dim3(nb(nleaves + count, 256)), dim3(256), 0, st, d.ls_off,
+                     count, k0, ntot, d.start);
+  hipLaunchKernelGGL(k_b_local, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, i0, ntot,
+                     d.roots, d.p32);
+  hipLaunchKernelGGL(k_b_tile_counts, dim3(nb(nleaves + 1, 256)), dim3(256), 0, st, d.leaf_off,
+                     count, d.start, d.toff);
+  e = scan_exclusive(d.toff, nleaves + 1, d.tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_tile_fill, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, d.start,
+                     d.toff, ntot, nleaves, d.tiles, d.ntiles);
+  e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_p2m, dim3(unsigned(nleaves)), dim3(64), 0, st, d.inst, d.leaf_off, count,
+                     d.start, d.p32, d.roots, d.me);
+  for (int l = maxL - 1; l >= 2; --l)
+    if (m2m_tot[l] > 0)
+      hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, st, d.inst,
+                         d.m2m_items + int64_t(l) * (count + 1), count, l, d.me, d.tab, d.tab_off);
+  for (int l = 2; l <= maxL; ++l)
+    if (m2l_tot[l] > 0)
+      hipLaunchKernelGGL(k_b_m2l, dim3(nb(m2l_tot[l], 256)), dim3(256), 0, st, d.inst,
+                         d.m2l_items + int64_t(l) * (count + 1), count, l, d.me, d.le, d.tab,
+                         d.tab_off);
+  hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.start,
+                     d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.le, i0);
+  return hipGetLastError();
+}
+
+void set_last_error(const char* msg);
+
+}  // namespace vfmm
+
+using namespace vfmm;
+
+struct vfmm_batch_s {
+  int count;
+  int64_t ntot, nleaves, max_tiles;
+  int maxL;
+  int64_t m2m_tot[kBatchMaxLevels + 1], m2l_tot[kBatchMaxLevels + 1];
+  std::vector<int> ps;  // distinct expansion orders
+  int64_t tab_at[VFMM_MAX_P + 1];  // byte offset of each order's table set
+  BatchPlanDev d;
+  bool tables_built;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+vfmm_status_t bfail(vfmm_status_t s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+vfmm_status_t bfail(vfmm_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return s;
+}
+
+inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct BatchLayout {
+  size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, m2l_items, roots, k0, k1, i0, i1,
+      counts, tmp, toff, start, ntiles, tiles, tile_box, p32, me, le, tab, total;
+  int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
+  int maxL;
+  std::vector<int64_t> me_off;
+  int64_t tab_at[VFMM_MAX_P + 1];
+};
+
+vfmm_status_t check_instances(const vfmm_instance* in, int count) {
+  if (!in || count < 1 || count > (1 << (32 - kBatchKeyInst)))
+    return bfail(VFMM_ERR_INVALID_ARG, "count must be in [1, %d]", 1 << (32 - kBatchKeyInst));
+  int64_t ntot = 0;
+  for (int c = 0; c < count; ++c) {
+    const vfmm_instance& a = in[c];
+    if (!a.x || !a.y || !a.gamma || !a.u || !a.v) return bfail(VFMM_ERR_INVALID_ARG, "instance %d: null pointer", c);
+    if (a.n < 1) return bfail(VFMM_ERR_INVALID_ARG, "instance %d: n must be >= 1", c);
+    if (!(a.sigma > 0.0) || !std::isfinite(a.sigma)) return bfail(VFMM_ERR_INVALID_ARG, "instance %d: bad sigma", c);
+    if (a.p < 1 || a.p > kBatchPMax) return bfail(VFMM_ERR_INVALID_ARG, "instance %d: p out of [1, %d]", c, kBatchPMax);
+    if (a.levels < 0 || a.levels > kBatchMaxLevels)
+      return bfail(VFMM_ERR_INVALID_ARG, "instance %d: levels out of [0, %d]", c, kBatchMaxLevels);
+    ntot += a.n;
+  }
+  if (ntot > 2147483647LL) return bfail(VFMM_ERR_INVALID_ARG, "too many particles in total");
+  return VFMM_OK;
+}
+
+BatchLayout batch_layout(const vfmm_instance* in, int count) {
+  BatchLayout L{};
+  L.me_off.resize(count);
+  int64_t me = 0;
+  bool has_p[VFMM_MAX_P + 1] = {};
+  for (int c = 0; c < count; ++c) {
+    const vfmm_instance& a = in[c];
+    L.ntot += a.n;
+    L.nleaves += int64_t(1) << (2 * a.levels);
+    L.max_tiles += (a.n + kTile - 1) / kTile + std::min<int64_t>(a.n, int64_t(1) << (2 * a.levels));
+    L.maxL = std::max(L.maxL, int(a.levels));
+    L.me_off[c] = me;
+    me += int64_t(al(size_t(n_boxes_2_to(a.levels)) * a.p * (a.p > 16 ? 16 : 8)));
+    has_p[a.p] = true;
+  }
+  L.me_bytes = me;
+  int64_t tb = 0;
+  for (int p = 0; p <= VFMM_MAX_P; ++p) {
+    L.tab_at[p] = tb;
+    if (has_p[p]) tb += int64_t(al(ops_bytes(p)));
+  }
+  L.tab_bytes = tb;
+  const int64_t sort_blocks = (L.ntot + kSortPerBlock - 1) / kSortPerBlock;
+  const int64_t scan_src = std::max<int64_t>(256 * sort_blocks, L.nleaves + 1);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off += al(b); return r; };
+  L.inst = take(sizeof(BatchInst) * count);
+  L.part_off = take(8 * (count + 1));
+  L.leaf_off = take(8 * (count + 1));
+  L.ls_off = take(8 * (count + 1));
+  L.tab_off = take(8 * (VFMM_MAX_P + 1));
+  L.m2m_items = take(8 * size_t(kBatchMaxLevels + 1) * (count + 1));
+  L.m2l_items = take(8 * size_t(kBatchMaxLevels + 1) * (count + 1));
+  L.roots = take(32 * size_t(count));
+  L.k0 = take(4 * L.ntot); L.k1 = take(4 * L.ntot);
+  L.i0 = take(4 * L.ntot); L.i1 = take(4 * L.ntot);
+  L.counts = take(4 * 256 * size_t(sort_blocks));
+  L.tmp = take(4 * size_t((scan_src + kScanPerBlock - 1) / kScanPerBlock + 1));
+  L.toff = take(4 * size_t(L.nleaves + 1));
+  L.start = take(4 * size_t(L.nleaves + count));
+  L.ntiles = take(4);
+  L.tiles = take(sizeof(Tile) * size_t(L.max_tiles));
+  L.tile_box = take(sizeof(float4) * size_t(L.max_tiles));
+  L.p32 = take(sizeof(Part32) * size_t(L.ntot));
+  L.me = take(size_t(L.me_bytes));
+  L.le = take(size_t(L.me_bytes));
+  L.tab = take(size_t(L.tab_bytes));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+vfmm_status_t vfmm_batch_workspace_bytes(const vfmm_instance* inst, int32_t count, size_t* bytes) {
+  if (!bytes) return bfail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  vfmm_status_t s = check_instances(inst, count);
+  if (s) return s;
+  *bytes = batch_layout(inst, count).total;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* workspace,
+                                size_t ws_bytes, vfmm_batch_t* out) {
+  if (!out) return bfail(VFMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  vfmm_status_t s = check_instances(inst, count);
+  if (s) return s;
+  if (!workspace) return bfail(VFMM_ERR_INVALID_ARG, "workspace is NULL");
+  const BatchLayout L = batch_layout(inst, count);
+  if (ws_bytes < L.total) return bfail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return bfail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  // host tables
+  std::vector<BatchInst> hi(count);
+  std::vector<int64_t> part_off(count + 1), leaf_off(count + 1), ls_off(count + 1), tab_off(VFMM_MAX_P + 1);
+  std::vector<int64_t> m2m(size_t(kBatchMaxLevels + 1) * (count + 1), 0), m2l(size_t(kBatchMaxLevels + 1) * (count + 1), 0);
+  for (int c = 0; c < count; ++c) {
+    const vfmm_instance& a = inst[c];
+    part_off[c + 1] = part_off[c] + a.n;
+    leaf_off[c + 1] = leaf_off[c] + (int64_t(1) << (2 * a.levels));
+    ls_off[c] = leaf_off[c] + c;
+    hi[c] = BatchInst{a.x, a.y, a.gamma, a.u, a.v, a.n, part_off[c], leaf_off[c], L.me_off[c],
+                      a.sigma, a.p, a.levels, a.p > 16 ? 1 : 0, 0};
+  }
+  ls_off[count] = leaf_off[count] + count;
+  for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
+  vfmm_batch_s* b = new (std::nothrow) vfmm_batch_s{};
+  if (!b) return bfail(VFMM_ERR_INVALID_ARG, "host allocation failed");
+  for (int p = 0; p <= VFMM_MAX_P; ++p) b->tab_at[p] = L.tab_at[p];
+  b->count = count;
+  b->ntot = L.ntot;
+  b->nleaves = L.nleaves;
+  b->max_tiles = L.max_tiles;
+  b->maxL = L.maxL;
+  for (int l = 0; l <= kBatchMaxLevels; ++l) {
+    int64_t a = 0, bb = 0;
+    for (int c = 0; c < count; ++c) {
+      m2m[size_t(l) * (count + 1) + c] = a;
+      m2l[size_t(l) * (count + 1) + c] = bb;
+      const int64_t items = (int64_t(1) << (2 * l)) * inst[c].p;
+      if (l >= 2 && inst[c].levels > l) a += items;
+      if (l >= 2 && inst[c].levels >= l) bb += items;
+    }
+    m2m[size_t(l) * (count + 1) + count] = a;
+    m2l[size_t(l) * (count + 1) + count] = bb;
+    b->m2m_tot[l] = a;
+    b->m2l_tot[l] = bb;
+  }
+  for (int c = 0; c < count; ++c) {
+    bool seen = false;
+    for (int q : b->ps) seen |= q == inst[c].p;
+    if (!seen) b->ps.push_back(inst[c].p);
+  }
+  char* ws = static_cast<char*>(workspace);
+  BatchPlanDev& d = b->d;
+  d.inst = reinterpret_cast<BatchInst*>(ws + L.inst);
+  d.part_off = reinterpret_cast<int64_t*>(ws + L.part_off);
+  d.leaf_off = reinterpret_cast<int64_t*>(ws + L.leaf_off);
+  d.ls_off = reinterpret_cast<int64_t*>(ws + L.ls_off);
+  d.tab_off = reinterpret_cast<int64_t*>(ws + L.tab_off);
+  d.m2m_items = reinterpret_cast<int64_t*>(ws + L.m2m_items);
+  d.m2l_items = reinterpret_cast<int64_t*>(ws + L.m2l_items);
+  d.roots = reinterpret_cast<double*>(ws + L.roots);
+  d.k0 = reinterpret_cast<uint32_t*>(ws + L.k0); d.k1 = reinterpret_cast<uint32_t*>(ws + L.k1);
+  d.i0 = reinterpret_cast<int32_t*>(ws + L.i0); d.i1 = reinterpret_cast<int32_t*>(ws + L.i1);
+  d.counts = reinterpret_cast<uint32_t*>(ws + L.counts);
+  d.tmp = reinterpret_cast<uint32_t*>(ws + L.tmp);
+  d.toff = reinterpret_cast<uint32_t*>(ws + L.toff);
+  d.start = reinterpret_cast<int32_t*>(ws + L.start);
+  d.ntiles = reinterpret_cast<int32_t*>(ws + L.ntiles);
+  d.tiles = reinterpret_cast<Tile*>(ws + L.tiles);
+  d.tile_box = reinterpret_cast<float4*>(ws + L.tile_box);
+  d.p32 = reinterpret_cast<Part32*>(ws + L.p32);
+  d.me = ws + L.me;
+  d.le = ws + L.le;
+  d.tab = ws + L.tab;
+  hipError_t e = hipMemcpy(d.inst, hi.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.part_off, part_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.leaf_off, leaf_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.ls_off, ls_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.tab_off, tab_off.data(), 8 * (VFMM_MAX_P + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.m2m_items, m2m.data(), 8 * m2m.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.m2l_items, m2l.data(), 8 * m2l.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete b;
+    return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
+  if (!b) return bfail(VFMM_ERR_INVALID_ARG, "batch is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (use_graph && !st) return bfail(VFMM_ERR_UNSUPPORTED, "graph replay needs a non-default stream");
+  hipError_t e = hipSuccess;
+  if (!b->tables_built) {
+    for (int p : b->ps) {
+      TreeDev t{};
+      t.ops = b->d.tab + b->tab_at[p];  // translation tables of order p
+      e = launch_build_ops(t, p, kFP64, st);
+      if (e != hipSuccess) break;
+    }
+    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
+    b->tables_built = true;
+  }
+  if (!use_graph) {
+    e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->m2l_tot,
+                         b->maxL, st);
+    return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "batch run: %s", hipGetErrorString(e));
+  }
+  if (!b->exec) {
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+    hipError_t le = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot,
+                                     b->m2l_tot, b->maxL, st);
+    e = hipStreamEndCapture(st, &b->graph);
+    if (le != hipSuccess || e != hipSuccess)
+      return bfail(VFMM_ERR_HIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+  }
+  e = hipGraphLaunch(b->exec, st);
+  return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+}
+
+void vfmm_batch_destroy(vfmm_batch_t b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+}
+
+}  // extern "C"

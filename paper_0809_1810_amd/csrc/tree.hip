@@ -116,6 +116,8 @@ __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
   idx[i] = int32_t(i);
 }
 
+}  // namespace
+
 // ------------------------------------------------------------------ scan
 // Exclusive prefix sum of uint32, in place, three phases.
 
@@ -263,6 +265,8 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
     __syncthreads();
   }
 }
+
+namespace {
 
 __global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__ keys, int64_t n,
                                                     int64_t nleaves, int32_t* __restrict__ start) {
@@ -422,6 +426,34 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      t.tiles, t.ntiles);
   hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
                      t.tiles, t.ntiles, t.part32, t.tile_box);
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint32_t*& k0, uint32_t*& k1, int32_t*& i0, int32_t*& i1, int64_t n,
+                            int bits, uint32_t* counts, uint32_t* tmp, hipStream_t st) {
+  const int nblk = int((n + kSortPerBlock - 1) / kSortPerBlock);
+  int shift = 0;
+  while (bits > 0) {
+    const int b = bits < 8 ? bits : 8;
+    const uint32_t mask = (1u << b) - 1u;
+    hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kSortBlock), 0, st, k0, n, shift, mask,
+                       counts, nblk);
+    hipError_t e = scan_exclusive(counts, int64_t(256) * nblk, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortBlock), 0, st, k0, i0, n, shift,
+                       mask, b, counts, nblk, k1, i1);
+    uint32_t* tk = k0; k0 = k1; k1 = tk;
+    int32_t* ti = i0; i0 = i1; i1 = ti;
+    shift += b;
+    bits -= b;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_box(const Tile* tiles, const int32_t* ntiles, int64_t max_tiles,
+                           const Part32* p32, float4* box, hipStream_t st) {
+  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((max_tiles + 3) / 4)), dim3(256), 0, st, tiles,
+                     ntiles, p32, box);
   return hipGetLastError();
 }
 

@@ -114,5 +114,13 @@ hipError_t launch_error_metrics(const double* u, const double* v, const double* 
                                 const double* vr, int64_t n, double* partial, double* out,
                                 hipStream_t stream);
 size_t ops_bytes(int p);
+// Shared building blocks (tree.hip).
+hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st);
+// Stable LSD radix sort of (key, index) pairs on the low `bits` key bits; on
+// return k0/i0 point to the sorted arrays (the other pair is scratch).
+hipError_t radix_sort_pairs(uint32_t*& k0, uint32_t*& k1, int32_t*& i0, int32_t*& i1, int64_t n,
+                            int bits, uint32_t* counts, uint32_t* tmp, hipStream_t st);
+hipError_t launch_tile_box(const Tile* tiles, const int32_t* ntiles, int64_t max_tiles,
+                           const Part32* p32, float4* box, hipStream_t st);
 
 }  // namespace vfmm

@@ -68,6 +68,11 @@ _SIGS = {
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "vfmm_mlp_adam": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                   C.c_float, C.c_void_p]),
+    "vfmm_batch_workspace_bytes": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
+    "vfmm_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                                      C.POINTER(C.c_void_p)]),
+    "vfmm_batch_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "vfmm_batch_destroy": (None, [C.c_void_p]),
     "vfmm_select_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "vfmm_particle_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
@@ -82,6 +87,13 @@ _SIGS = {
 
 MLP_PARAMS = 4929
 N_FEATURES = 10
+
+
+class Instance(C.Structure):
+    """Mirror of ``vfmm_instance``."""
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("gamma", C.c_void_p), ("u", C.c_void_p),
+                ("v", C.c_void_p), ("n", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32),
+                ("levels", C.c_int32)]
 
 N_PHASES = 6
 PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_l2p")
@@ -380,3 +392,51 @@ def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0
                                     scratch.data_ptr(), scratch.numel(), C.byref(p), C.byref(L),
                                     C.byref(pred), C.byref(fb), _stream()), "vfmm_select_params")
     return int(p.value), int(L.value), float(pred.value), bool(fb.value)
+
+
+# ----------------------------------------------------------------- batched instances
+
+
+class Batch:
+    """Many independent instances evaluated together (see vfmm_batch_create).
+
+    ``instances``: list of dicts with device float64 tensors x, y, gamma and
+    sigma, p, levels.  Outputs live in ``self.u[i]``, ``self.v[i]``.
+    """
+
+    def __init__(self, instances):
+        torch = _torch()
+        self.inputs, self.u, self.v = [], [], []
+        arr = (Instance * len(instances))()
+        for i, d in enumerate(instances):
+            x = _dev_f64(d["x"], "x"); y = _dev_f64(d["y"], "y"); g = _dev_f64(d["gamma"], "gamma")
+            n = int(x.shape[0])
+            u = torch.empty(n, dtype=torch.float64, device=x.device)
+            v = torch.empty(n, dtype=torch.float64, device=x.device)
+            self.inputs.append((x, y, g)); self.u.append(u); self.v.append(v)
+            arr[i] = Instance(x.data_ptr(), y.data_ptr(), g.data_ptr(), u.data_ptr(), v.data_ptr(), n,
+                              float(d["sigma"]), int(d["p"]), int(d["levels"]))
+        self._arr = arr
+        nb = C.c_size_t(0)
+        _check(lib().vfmm_batch_workspace_bytes(arr, len(instances), C.byref(nb)),
+               "vfmm_batch_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8,
+                                     device=self.inputs[0][0].device)
+        h = C.c_void_p(0)
+        _check(lib().vfmm_batch_create(arr, len(instances), self.workspace.data_ptr(),
+                                       self.workspace.numel(), C.byref(h)), "vfmm_batch_create")
+        self._h = h
+
+    def run(self, use_graph=False):
+        _check(lib().vfmm_batch_run(self._h, int(bool(use_graph)), _stream()), "vfmm_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vfmm_batch_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
