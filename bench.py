@@ -168,7 +168,10 @@ def main():
         log(f"[bench] selector: {json.dumps(r)} in {sel_ms:.1f} ms")
 
 
+    from paper_0809_1810_amd import autotune as AT
+
     def run_path(L, p, prec, steps, warmup, timing=False):
+        AT.apply_for(n, L)  # near-field launch shape from the autotuner's table
         tree = vf.Tree(x, y, L, p_max=p)
         u = torch.empty(n, dtype=torch.float64, device="cuda")
         v = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -256,6 +259,7 @@ def main():
             "workload": f"{P.name}: N={n}, sigma={P.sigma}, seeded synthetic",
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
             "selector": selector, "selector_info": sel_info, "audit_targets": AUDIT_TARGETS,
+            "p2p_tile_waves": list(AT.lookup(n, L_t)),
         },
         "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
         "roofline": roofline,

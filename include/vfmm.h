@@ -305,6 +305,18 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream
 /* Releases the plan and its graph (not the workspace).  NULL is ignored. */
 void vfmm_batch_destroy(vfmm_batch_t batch);
 
+/* ---------------------------------------------------------------------------
+ * Tuning (process-wide settings chosen by the autotuner).
+ *   VFMM_TUNE_P2P_TILE : particles per near-field tile for trees built from now
+ *                        on: 64, 32 or 16 (one, two or four lanes per target;
+ *                        also the source-chunk size of the far-pair test).
+ *   VFMM_TUNE_P2P_WAVES: waves per workgroup of the near-field launch: 1, 2, 4, 8.
+ * Results do not depend on the settings beyond float32 summation order. */
+#define VFMM_TUNE_P2P_TILE 1
+#define VFMM_TUNE_P2P_WAVES 2
+vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value);
+int32_t vfmm_get_tuning(int32_t param); /* -1 for an unknown parameter */
+
 /* Releases the tree handle (not the caller's workspace).  NULL is ignored. */
 void vfmm_tree_destroy(vfmm_tree_t tree);
 

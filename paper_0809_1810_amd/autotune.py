@@ -1,0 +1,111 @@
+"""Autotuner for the near-field (P2P) launch shape.
+
+Tunable shape: particles per tile T (64, 32, 16: one, two or four lanes per
+target; T is also the source-chunk size of the far-pair test, so smaller tiles
+have tighter bounding boxes) and waves per workgroup (1, 2, 4, 8).  For each
+workload the tuner times the P2P phase of FP32 evaluations with HIP events
+(median of repeated calls) for every shape, keeps the fastest, and writes a
+table keyed by log2 of the mean particles per leaf.  ``apply_for(n, levels)``
+sets the library's tuning from the nearest table entry.
+
+    python -m paper_0809_1810_amd.autotune --out tuning.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import vfmm as V
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE_PATH = os.path.join(HERE, "tuning.json")
+TILES = (64, 32, 16)
+WAVES = (1, 2, 4, 8)
+
+
+def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5):
+    """Median P2P phase time (ms) for one launch shape."""
+    V.set_tuning(tile=tile, waves=waves)
+    t = V.Tree(x, y, levels, p_max=p)
+    t.velocity(g, sigma, p, V.FP32)
+    t.enable_timing(reps)
+    for _ in range(reps):
+        t.velocity(g, sigma, p, V.FP32)
+    ms = float(np.median([ph["p2p_l2p"] for ph in t.read_timing()]))
+    t.close()
+    return ms
+
+
+def tune_workload(name, P, p, levels, log=print):
+    import torch
+    x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda(); g = torch.from_numpy(P.gamma).cuda()
+    res = {}
+    for tile in TILES:
+        for waves in WAVES:
+            res[(tile, waves)] = time_p2p(x, y, g, P.sigma, p, levels, tile, waves)
+    best = min(res, key=res.get)
+    entry = {"workload": name, "n": P.n, "levels": levels, "p": p,
+             "ppl_log2": math.log2(P.n) - 2 * levels, "tile": best[0], "waves": best[1],
+             "p2p_ms": res[best], "default_ms": res[(64, 4)],
+             "all_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in sorted(res.items())}}
+    log(f"[tune] {name} L={levels}: best tile {best[0]} waves {best[1]} {res[best]:.3f} ms "
+        f"(default 64x4 {res[(64, 4)]:.3f} ms)")
+    return entry
+
+
+def default_workloads():
+    import workloads as W
+    return [
+        ("clusters_1m", W.config("clusters_1m"), 14, 6),
+        ("clusters_1m", W.config("clusters_1m"), 14, 7),
+        ("lattice_1024", W.config("lattice_1024"), 14, 6),
+        ("lattice_1024", W.config("lattice_1024"), 14, 7),
+        ("lattice_1024", W.config("lattice_1024"), 14, 8),
+        ("lattice_320", W.config("lattice_320"), 14, 5),
+        ("lattice_320", W.config("lattice_320"), 14, 6),
+        ("uniform_64k", W.uniform(65536, seed=9, sigma=2.0 / 256 / 0.8), 12, 6),
+    ]
+
+
+def tune(out=TABLE_PATH, log=print):
+    t0 = time.time()
+    entries = [tune_workload(*w, log=log) for w in default_workloads()]
+    V.set_tuning(tile=64, waves=4)
+    table = {"entries": entries, "seconds": round(time.time() - t0, 1)}
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
+def lookup(n, levels, path=TABLE_PATH):
+    """(tile, waves) of the table entry nearest in log2 particles per leaf."""
+    try:
+        table = json.load(open(path))
+    except (OSError, ValueError):
+        return 64, 4
+    ppl = math.log2(max(n, 1)) - 2 * levels
+    e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
+    return int(e["tile"]), int(e["waves"])
+
+
+def apply_for(n, levels, path=TABLE_PATH):
+    tile, waves = lookup(n, levels, path)
+    V.set_tuning(tile=tile, waves=waves)
+    return tile, waves
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE_PATH)
+    a = ap.parse_args(argv)
+    tune(a.out, log=lambda m: print(m, flush=True))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

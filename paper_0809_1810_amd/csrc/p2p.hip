@@ -7,15 +7,17 @@
 // excluded; it contributes exactly zero because the pair offset is (0, 0).
 // L2P: W_far = (-j / (2 pi w)) sum_n L_n ((z - c)/w)^n, Horner's rule.
 //
-// Work decomposition: one wave per tile of <= 64 targets of one leaf (tiles
-// built with the tree, in leaf order), one target per lane.  Blocks keep the
+// Work decomposition: one wave per tile of <= T targets of one leaf (tiles built
+// with the tree, in leaf order; T = 64, 32 or 16 from the tuning), 64 / T lanes
+// per target, each lane taking every (64 / T)-th source of a chunk, the lanes of a
+// target summed by shuffles at the end.  Blocks keep the
 // hardware's round-robin dealing to the 8 XCDs, which spreads the heavy tiles of
 // dense regions over all XCDs (contiguous per-XCD ranges, or ordering tiles by
 // cost, were measured 1.7-2x slower on clustered inputs).
-// The source loop runs over the 9 leaf ranges of the local list in chunks of 64,
-// which are exactly the tiles of the source leaf; the source index is the same
-// for all lanes of the wave, so sources are fetched with scalar loads and
-// broadcast (8 per loop trip, so several loads are in flight).  Source
+// The source loop runs over the 9 leaf ranges of the local list in chunks of T,
+// which are exactly the tiles of the source leaf; with T = 64 the source index
+// is the same for all lanes of the wave, so sources are fetched with scalar
+// loads and broadcast (8 per loop trip, so several loads are in flight).  Source
 // coordinates are box-local; the target is shifted once per neighbour leaf by
 // the exact centre offset.
 //
@@ -37,22 +39,25 @@ namespace vfmm {
 
 namespace {
 
-template <typename R, int PMAX>
-__global__ void __launch_bounds__(256) k_p2p_l2p(
+template <typename R, int PMAX, int LPT>
+__global__ void __launch_bounds__(512) k_p2p_l2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
     const Tile* __restrict__ tiles, const int32_t* __restrict__ ntiles,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
     const double* __restrict__ root, int levels, int p,
     const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
-    int parts,
-    const int32_t* __restrict__ perm, double* __restrict__ u, double* __restrict__ v) {
+    int parts, const int32_t* __restrict__ perm, double* __restrict__ u,
+    double* __restrict__ v) {
   using C = typename Types<R>::C;
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
+  const int wpb = blockDim.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
   if (wid >= *ntiles) return;
   const int lane = threadIdx.x & 63;
+  const int tl = lane % T, grp = lane / T;  // target in tile, source sub-stream
   const Tile tile = tiles[wid];
-  const bool active = lane < tile.count;
-  const int32_t i = tile.start + (active ? lane : 0);
+  const bool active = tl < tile.count;
+  const int32_t i = tile.start + (active ? tl : 0);
   const auto tp = part[i];
   const int m = 1 << levels;
   const int bx = tile.leaf & (m - 1), by = tile.leaf >> levels;
@@ -77,8 +82,8 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
         const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
         const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
         uint32_t ci = tile_off[sl];
-        for (int32_t j0 = js; j0 < je; j0 += 64, ++ci) {
-          const int32_t j1 = min(j0 + 64, je);
+        for (int32_t j0 = js; j0 < je; j0 += T, ++ci) {
+          const int32_t j1 = min(j0 + T, je);
           const float4 sb = tile_box[ci];
           const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
           const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
@@ -86,7 +91,7 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
           const float gap2 = gx * gx + gy * gy;
           if (gap2 > far2) {
 #pragma unroll 8
-            for (int32_t j = j0; j < j1; ++j) {
+            for (int32_t j = j0 + grp; j < j1; j += LPT) {
               const auto s = part[j];
               const R dx = tx - s.x;
               const R dy = ty - s.y;
@@ -96,7 +101,7 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
             }
           } else if (gap2 > ser2) {
 #pragma unroll 8
-            for (int32_t j = j0; j < j1; ++j) {
+            for (int32_t j = j0 + grp; j < j1; j += LPT) {
               const auto s = part[j];
               const R dx = tx - s.x;
               const R dy = ty - s.y;
@@ -107,7 +112,7 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
             }
           } else {
 #pragma unroll 4
-            for (int32_t j = j0; j < j1; ++j) {
+            for (int32_t j = j0 + grp; j < j1; j += LPT) {
               const auto s = part[j];
               const R dx = tx - s.x;
               const R dy = ty - s.y;
@@ -130,6 +135,12 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
     if constexpr (sizeof(R) == 4) {
       nu = au.value();
       nv = av.value();
+    }
+    // sum the LPT source sub-streams of each target
+#pragma unroll
+    for (int o = T; o < 64; o <<= 1) {
+      nu += __shfl_xor(nu, o, 64);
+      nv += __shfl_xor(nv, o, 64);
     }
     nu *= kInv2Pi;
     nv *= kInv2Pi;
@@ -156,14 +167,14 @@ __global__ void __launch_bounds__(256) k_p2p_l2p(
     fv = double(acc.x) * sc;
   }
 
-  if (active) {
+  if (active && grp == 0) {
     const int32_t o = perm[i];
     u[o] = nu + fu;
     v[o] = nv + fv;
   }
 }
 
-template <typename R, int PMAX>
+template <typename R, int PMAX, int LPT>
 void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
               double* u, double* v, hipStream_t st) {
   using C = typename Types<R>::C;
@@ -175,20 +186,29 @@ void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sig
   const float far2 = float(P2PMath<R>::kFarSigma2 * sigma * sigma);
   const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
   const R ka = R(1.0 / (2.0 * sigma * sigma));
-  const unsigned blocks = unsigned((lay.max_tiles + 3) / 4);
-  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX>), dim3(blocks), dim3(256), 0, st, part, t.leaf_start,
-                     t.tiles, t.ntiles, t.tile_off, t.tile_box, t.root, levels, p, le, kexp, ka,
-                     far2, ser2, parts, t.perm, u, v);
+  const int wpb = tuning_waves();
+  const unsigned blocks = unsigned((lay.max_tiles + wpb - 1) / wpb);
+  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(blocks), dim3(64 * wpb), 0, st, part,
+                     t.leaf_start, t.tiles, t.ntiles, t.tile_off, t.tile_box, t.root, levels, p,
+                     le, kexp, ka, far2, ser2, parts, t.perm, u, v);
+}
+
+template <typename R, int PMAX>
+void launch_l(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+              double* u, double* v, hipStream_t st) {
+  if (t.tile == 16) launch_t<R, PMAX, 4>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, lay, levels, p, sigma, parts, u, v, st);
+  else launch_t<R, PMAX, 1>(t, lay, levels, p, sigma, parts, u, v, st);
 }
 
 template <typename R>
 void launch_r(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
               double* u, double* v, hipStream_t st) {
-  if (p <= 8) launch_t<R, 8>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 16) launch_t<R, 16>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 24) launch_t<R, 24>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 32) launch_t<R, 32>(t, lay, levels, p, sigma, parts, u, v, st);
-  else launch_t<R, 40>(t, lay, levels, p, sigma, parts, u, v, st);
+  if (p <= 8) launch_l<R, 8>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 16) launch_l<R, 16>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 24) launch_l<R, 24>(t, lay, levels, p, sigma, parts, u, v, st);
+  else if (p <= 32) launch_l<R, 32>(t, lay, levels, p, sigma, parts, u, v, st);
+  else launch_l<R, 40>(t, lay, levels, p, sigma, parts, u, v, st);
 }
 
 }  // namespace

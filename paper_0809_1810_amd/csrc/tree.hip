@@ -303,18 +303,20 @@ __global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__
 }
 
 __global__ void __launch_bounds__(256) k_tile_counts(const int32_t* __restrict__ start,
-                                                     int64_t nleaves, uint32_t* __restrict__ cnt) {
+                                                     int64_t nleaves, int tile,
+                                                     uint32_t* __restrict__ cnt) {
   int64_t k = blockIdx.x * 256LL + threadIdx.x;
   if (k > nleaves) return;
-  cnt[k] = k < nleaves ? uint32_t((start[k + 1] - start[k] + kTile - 1) / kTile) : 0u;
+  cnt[k] = k < nleaves ? uint32_t((start[k + 1] - start[k] + tile - 1) / tile) : 0u;
 }
 
-// One thread per particle: a particle that starts a 64-block of its leaf writes
-// that tile.
+// One thread per particle: a particle that starts a tile-sized block of its
+// leaf writes that tile.
 __global__ void __launch_bounds__(256) k_tile_fill(const uint32_t* __restrict__ keys,
                                                    const int32_t* __restrict__ start,
                                                    const uint32_t* __restrict__ off, int64_t n,
-                                                   int64_t nleaves, Tile* __restrict__ tiles,
+                                                   int64_t nleaves, int tile,
+                                                   Tile* __restrict__ tiles,
                                                    int32_t* __restrict__ ntiles) {
   const int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i == 0) *ntiles = int32_t(off[nleaves]);
@@ -322,9 +324,9 @@ __global__ void __launch_bounds__(256) k_tile_fill(const uint32_t* __restrict__ 
   const uint32_t leaf = keys[i] >> (2 * kSubLevels);
   const int32_t s = start[leaf], c = start[leaf + 1] - s;
   const int32_t r = int32_t(i) - s;
-  if (r % kTile != 0) return;
+  if (r % tile != 0) return;
   const int32_t cc = c - r;
-  tiles[off[leaf] + r / kTile] = Tile{int32_t(leaf), int32_t(i), cc < kTile ? cc : kTile, 0};
+  tiles[off[leaf] + r / tile] = Tile{int32_t(leaf), int32_t(i), cc < tile ? cc : tile, 0};
 }
 
 // One wave per tile: bounding box of its particles in the leaf's local frame.
@@ -363,8 +365,8 @@ inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 }  // namespace
 
 hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
-                             const double* domain, const Layout& lay, char* ws, TreeDev& t,
-                             hipStream_t st) {
+                             const double* domain, const Layout& lay, char* ws, int tile,
+                             TreeDev& t, hipStream_t st) {
   double* root = reinterpret_cast<double*>(ws + lay.root);
   double* bbox = reinterpret_cast<double*>(ws + lay.bbox);
   uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + lay.keys0);
@@ -416,14 +418,15 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.reduce = reinterpret_cast<double*>(ws + lay.reduce);
   hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, k0, i0, n,
                      root, levels, t.part64, t.part32);
+  t.tile = tile;
   hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
-                     toff);
+                     tile, toff);
   hipError_t e = scan_exclusive(toff, nl + 1, tmp, st);
   if (e != hipSuccess) return e;
   t.tile_off = toff;
   t.tile_box = reinterpret_cast<float4*>(ws + lay.tile_box);
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
-                     t.tiles, t.ntiles);
+                     tile, t.tiles, t.ntiles);
   hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
                      t.tiles, t.ntiles, t.part32, t.tile_box);
   return hipGetLastError();

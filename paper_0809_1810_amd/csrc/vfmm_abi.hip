@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -53,6 +54,11 @@ vfmm_status_t fail(vfmm_status_t s, const char* fmt, ...) {
 
 namespace vfmm {
 void set_last_error(const char* msg) { g_err = msg; }
+
+std::atomic<int> g_tile{kTile};
+std::atomic<int> g_waves{4};
+int tuning_tile() { return g_tile.load(); }
+int tuning_waves() { return g_waves.load(); }
 }  // namespace vfmm
 
 namespace {
@@ -96,7 +102,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.sort_blocks = (n + kSortPerBlock - 1) / kSortPerBlock;
   L.count_len = 256 * L.sort_blocks;
   const int64_t nonempty = n < L.nleaves ? n : L.nleaves;
-  L.max_tiles = (n + kTile - 1) / kTile + nonempty;
+  L.max_tiles = (n + kTileMin - 1) / kTileMin + nonempty;  // any tunable tile size fits
   const int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
   const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
   const int64_t nbox = n_boxes_2_to(levels);
@@ -180,7 +186,7 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   t->pack_mode = -1;
   t->last_p = -1;
   t->last_prec = -1;
-  hipError_t e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, t->dev,
+  hipError_t e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, tuning_tile(), t->dev,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     delete t;
@@ -328,8 +334,8 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t t, const double* x, const double* y,
   if (!x || !y) return fail(VFMM_ERR_INVALID_ARG, "x or y is NULL");
   if (domain && (!std::isfinite(domain[0]) || !std::isfinite(domain[1]) || !finite_pos(domain[2])))
     return fail(VFMM_ERR_INVALID_ARG, "domain must be finite with side > 0");
-  hipError_t e = launch_build_tree(x, y, t->n, t->levels, domain, t->lay, t->ws, t->dev,
-                                   static_cast<hipStream_t>(stream));
+  hipError_t e = launch_build_tree(x, y, t->n, t->levels, domain, t->lay, t->ws, t->dev.tile,
+                                   t->dev, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "vfmm_tree_rebuild");
   t->last_p = -1;
   return VFMM_OK;
@@ -367,6 +373,28 @@ vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t t, double* ms, int32_t* n_calls)
   *n_calls = used;
   t->t_used = 0;
   return VFMM_OK;
+}
+
+vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value) {
+  if (param == VFMM_TUNE_P2P_TILE) {
+    if (value != 64 && value != 32 && value != 16)
+      return fail(VFMM_ERR_INVALID_ARG, "P2P tile must be 64, 32 or 16");
+    g_tile.store(value);
+    return VFMM_OK;
+  }
+  if (param == VFMM_TUNE_P2P_WAVES) {
+    if (value != 1 && value != 2 && value != 4 && value != 8)
+      return fail(VFMM_ERR_INVALID_ARG, "P2P waves per workgroup must be 1, 2, 4 or 8");
+    g_waves.store(value);
+    return VFMM_OK;
+  }
+  return fail(VFMM_ERR_INVALID_ARG, "unknown tuning parameter %d", param);
+}
+
+int32_t vfmm_get_tuning(int32_t param) {
+  if (param == VFMM_TUNE_P2P_TILE) return g_tile.load();
+  if (param == VFMM_TUNE_P2P_WAVES) return g_waves.load();
+  return -1;
 }
 
 void vfmm_tree_destroy(vfmm_tree_t t) { delete t; }

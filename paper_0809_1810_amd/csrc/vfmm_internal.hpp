@@ -26,7 +26,8 @@ namespace vfmm {
 
 constexpr int kMaxP = 40;
 constexpr int kMaxLevels = 12;
-constexpr int kTile = 64;            // P2P targets per wave tile
+constexpr int kTile = 64;            // P2P targets per wave tile (default; the batched path)
+constexpr int kTileMin = 16;         // smallest tunable tile (4 lanes per target)
 constexpr int kSubLevels = 4;        // within a leaf, particles are ordered by their cell at level L + 4
 constexpr int kSortItems = 8;        // radix-sort elements per thread
 constexpr int kSortBlock = 256;      // radix-sort threads per block
@@ -78,7 +79,8 @@ struct TreeDev {
   uint32_t* keys;        // sorted leaf keys
   int32_t* perm;         // sorted position -> input index
   int32_t* leaf_start;   // [nleaves + 1]
-  Tile* tiles;           // P2P target tiles (<= 64 consecutive particles of one leaf)
+  int tile;              // particles per P2P tile: 64, 32 or 16 (64 / lanes per target)
+  Tile* tiles;           // P2P target tiles (<= tile consecutive particles of one leaf)
   int32_t* ntiles;       // device count of tiles
   uint32_t* tile_off;    // [nleaves + 1] first tile of each leaf
   float4* tile_box;      // per tile: (xmin, xmax, ymin, ymax) in its leaf's local frame
@@ -93,8 +95,12 @@ struct TreeDev {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
-                             const double* domain, const Layout& lay, char* ws,
+                             const double* domain, const Layout& lay, char* ws, int tile,
                              TreeDev& t, hipStream_t stream);
+// Tuning parameters (process-wide): P2P tile size for new trees, P2P waves per
+// workgroup for launches.
+int tuning_tile();
+int tuning_waves();
 hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n,
                                hipStream_t stream);
 hipError_t launch_build_ops(const TreeDev& t, int p, int prec, hipStream_t stream);

@@ -73,6 +73,8 @@ _SIGS = {
                                       C.POINTER(C.c_void_p)]),
     "vfmm_batch_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "vfmm_batch_destroy": (None, [C.c_void_p]),
+    "vfmm_set_tuning": (C.c_int32, [C.c_int32, C.c_int32]),
+    "vfmm_get_tuning": (C.c_int32, [C.c_int32]),
     "vfmm_select_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "vfmm_particle_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
@@ -94,6 +96,8 @@ class Instance(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("gamma", C.c_void_p), ("u", C.c_void_p),
                 ("v", C.c_void_p), ("n", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32),
                 ("levels", C.c_int32)]
+
+TUNE_P2P_TILE, TUNE_P2P_WAVES = 1, 2
 
 N_PHASES = 6
 PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_l2p")
@@ -440,3 +444,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def set_tuning(tile=None, waves=None):
+    """Near-field tile size (64/32/16, for trees built afterwards) and waves per workgroup."""
+    if tile is not None:
+        _check(lib().vfmm_set_tuning(TUNE_P2P_TILE, int(tile)), "vfmm_set_tuning")
+    if waves is not None:
+        _check(lib().vfmm_set_tuning(TUNE_P2P_WAVES, int(waves)), "vfmm_set_tuning")
+
+
+def get_tuning():
+    return {"tile": int(lib().vfmm_get_tuning(TUNE_P2P_TILE)),
+            "waves": int(lib().vfmm_get_tuning(TUNE_P2P_WAVES))}

@@ -206,3 +206,31 @@ def test_clusters_full_size_sampled(vf):
     e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
     print(f"clusters_1m L6: fp64 p20 vs direct {e64:.3e}; fp32 p14 vs direct {e32:.3e}")
     assert e64 < 1e-6 and e32 < 1e-6
+
+
+@pytest.mark.parametrize("tile,waves", [(64, 1), (32, 2), (16, 8), (32, 4)])
+def test_tile_shapes_match_oracle(vf, tile, waves):
+    """Every tunable near-field shape gives the same result (FP64: to 1e-13 of the
+    oracle; FP32: within FP32 rounding of the default shape)."""
+    P = W.config("lattice_320")
+    L, p = 5, 12
+    print_case("tile_shape", tile=tile, waves=waves)
+    vf.set_tuning(tile=64, waves=4)
+    t0 = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    u0, v0 = (host(a) for a in t0.velocity(g, P.sigma, p, vf.FP32))
+    try:
+        vf.set_tuning(tile=tile, waves=waves)
+        t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+        un, vn = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_NEAR))
+        u, v = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+        t.rebuild(dev(P.x), dev(P.y))
+        u2, v2 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+    finally:
+        vf.set_tuning(tile=64, waves=4)
+    idx = W.sample_targets(P.n, 400, 3)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=idx)
+    den = np.max(np.hypot(r.u, r.v))
+    assert np.max(np.hypot(un[idx] - r.near_u, vn[idx] - r.near_v)) / den < 1e-13
+    assert rel_err(u, v, u0, v0)[0] < 1e-6
+    assert np.array_equal(u, u2) and np.array_equal(v, v2)
