@@ -71,13 +71,15 @@ def recorded_traffic(workload, p, levels):
     when the kernel source or the configuration differs from the measured one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "p2p_traffic_clusters_1m.json")
-    src = os.path.join(ROOT, "paper_0809_1810_amd", "csrc", "p2p.hip")
+    csrc = os.path.join(ROOT, "paper_0809_1810_amd", "csrc")
     try:
         rec = json.load(open(path))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        cur = hashlib.sha256(open(os.path.join(csrc, "p2p.hip"), "rb").read()).hexdigest()
+        cur_math = hashlib.sha256(open(os.path.join(csrc, "p2p_math.hpp"), "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if (rec.get("p2p_source_sha256") != cur or rec.get("workload") != workload
+    if (rec.get("p2p_source_sha256") != cur or rec.get("p2p_math_sha256") != cur_math
+            or rec.get("workload") != workload
             or rec.get("p") != p or rec.get("levels") != levels):
         return None
     return float(rec["traffic_bytes"])
