@@ -298,3 +298,59 @@ def hybrid_velocity(x, y, gamma, sigma, levels, domain=None, targets=None):
         ku[rows, ti] = 0.0; kv[rows, ti] = 0.0
         u[s:s + cs] = ku @ g; v[s:s + cs] = kv @ g
     return u, v
+
+
+# ----------------------------------------------------------------- evaluation points
+
+def inside_root(xe, ye, root):
+    """True where an evaluation point lies in the closed root square."""
+    x0, y0, s = root
+    xe = np.asarray(xe, np.float64); ye = np.asarray(ye, np.float64)
+    return (xe >= x0) & (xe <= x0 + s) & (ye >= y0) & (ye <= y0 + s)
+
+
+def fmm_velocity_at(x, y, gamma, sigma, p, levels, xe, ye, domain=None) -> FMMResult:
+    """The FMM of eq. 10 evaluated at separate points (eq. 8) instead of at the
+    particles (eq. 9).
+
+    The tree is built on the particles.  An evaluation point belongs to the
+    leaf given by the same floor-and-clamp rule; its near field is the
+    regularised kernel over the particles of that leaf's local list (a particle
+    at the point itself contributes zero, the limit of eq. 6), its far field the
+    L2P of that leaf's LE.  Points outside the closed root square have no leaf
+    whose expansions converge there: their velocity is NaN.
+    """
+    x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
+    gamma = np.asarray(gamma, np.float64)
+    xe = np.asarray(xe, np.float64); ye = np.asarray(ye, np.float64)
+    tree = build_tree(x, y, levels, domain)
+    L = levels
+    ok = inside_root(xe, ye, tree.root)
+    ex, ey = qt.leaf_coords(np.where(ok, xe, tree.root[0]), np.where(ok, ye, tree.root[1]),
+                            tree.root, L)
+    ze = xe + 1j * ye
+    ne = len(xe)
+    nu = np.zeros(ne); nv = np.zeros(ne); fu = np.zeros(ne); fv = np.zeros(ne)
+    boxes = {}
+    for k in np.nonzero(ok)[0]:
+        boxes.setdefault((int(ex[k]), int(ey[k])), []).append(k)
+    me = le = {}
+    if L >= 2 and boxes:
+        me = upward_sweep(x + 1j * y, gamma, tree, p)
+        le = downward_sweep(me, tree, p, set(boxes))
+    for box, ks in boxes.items():
+        ks = np.asarray(ks, np.int64)
+        src = [tree.members[b] for b in qt.local_list(L, *box) if b in tree.members]
+        if src:
+            sj = np.concatenate(src)
+            ku, kv = regularized_kernel(xe[ks, None] - x[None, sj], ye[ks, None] - y[None, sj], sigma)
+            nu[ks] = ku @ gamma[sj]
+            nv[ks] = kv @ gamma[sj]
+        if L >= 2:
+            w = l2p(le[L][box], qt.box_centre(tree.root, L, *box), ze[ks])
+            fu[ks] = w.real
+            fv[ks] = -w.imag
+    bad = ~ok
+    for a in (nu, nv, fu, fv):
+        a[bad] = np.nan
+    return FMMResult(nu + fu, nv + fv, nu, nv, fu, fv, np.arange(ne), tree, me, le)
