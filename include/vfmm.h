@@ -135,6 +135,36 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t tree, const double* gamma, dou
                                       int32_t p, int32_t precision, int32_t parts, double* u,
                                       double* v, void* stream);
 
+/* Bytes of device workspace that vfmm_fmm_velocity_at needs for n_targets
+ * evaluation points (0 <= n_targets <= 2^31 - 1) of a tree with `levels`
+ * levels.  `bytes` is a host pointer.  The workspace holds the points sorted
+ * into the tree's leaves, their leaf-local coordinates and their tiles. */
+vfmm_status_t vfmm_targets_workspace_bytes(int64_t n_targets, int32_t levels, size_t* bytes);
+
+/* FMM velocity at separate evaluation points (eq. 8, as in the error maps of
+ * Section 5.2) instead of at the particles: u[n_targets], v[n_targets]
+ * (device) at the points (xt, yt) (device, n_targets each), in their order.
+ * The particles' expansions are formed as in vfmm_fmm_velocity (and left in
+ * the tree, as that call leaves them).  A point belongs to the leaf given by
+ * the tree's floor-and-clamp rule; its near field sums the regularised kernel
+ * (eq. 6) over the particles of that leaf's 3 x 3 local list (a particle at
+ * the point itself contributes zero), its far field is the L2P of that leaf's
+ * local expansion.  Points outside the closed root square of the tree (or
+ * with NaN coordinates) receive NaN: no leaf expansion converges there; give
+ * vfmm_build_tree a domain that covers them.
+ *   gamma, sigma, p, precision, parts: as in vfmm_fmm_velocity_parts.
+ *   workspace (device): at least vfmm_targets_workspace_bytes(n_targets,
+ *             levels) bytes, 256-byte aligned, caller-owned, used only by
+ *             this call's kernels (separate from the tree's workspace).
+ * n_targets = 0 does nothing (xt, yt, u, v, workspace may then be NULL).
+ * With phase timing on, the sort of the points
+ * is counted in the gather phase.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_WORKSPACE, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
+                                   int32_t precision, int32_t parts, const double* xt,
+                                   const double* yt, int64_t n_targets, void* workspace,
+                                   size_t ws_bytes, double* u, double* v, void* stream);
+
 /* Float64 direct sum of eq. 7 / eq. 9 over all n particles, evaluated at the
  * particles listed in `targets` (device int64, n_targets entries, each in
  * [0, n)) or at all particles when targets is NULL (then n_targets must be n).
@@ -143,6 +173,15 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t tree, const double* gamma, dou
 vfmm_status_t vfmm_direct_velocity(const double* x, const double* y, const double* gamma,
                                    int64_t n, double sigma, const int64_t* targets,
                                    int64_t n_targets, double* u, double* v, void* stream);
+
+/* Float64 direct sum of eq. 8: the velocity induced by all n particles at
+ * separate evaluation points (xt, yt) (device, n_targets each), written to
+ * u, v (device, n_targets) in the points' order.  A particle at a point
+ * contributes zero (the limit of eq. 6).  n_targets = 0 does nothing.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_direct_velocity_at(const double* x, const double* y, const double* gamma,
+                                      int64_t n, double sigma, const double* xt, const double* yt,
+                                      int64_t n_targets, double* u, double* v, void* stream);
 
 /* Bytes of device scratch needed by vfmm_error_metrics. */
 size_t vfmm_metrics_scratch_bytes(void);
@@ -156,6 +195,17 @@ size_t vfmm_metrics_scratch_bytes(void);
 vfmm_status_t vfmm_error_metrics(const double* u, const double* v, const double* u_ref,
                                  const double* v_ref, int64_t n, void* scratch, double* out,
                                  void* stream);
+
+/* Per-point error field behind the paper's spatial error maps (Section 5):
+ * out[i] = log10(|dW_i| / max |W_ref|) (device, n), with |dW_i| the distance
+ * between (u_i, v_i) and (u_ref_i, v_ref_i), floored at log10(1e-300) = -300;
+ * NaN inputs give NaN.  `metrics` (device) is the out[3] of a previous
+ * vfmm_error_metrics call on the same arrays (metrics[2] = max |W_ref|; a zero
+ * maximum is read as 1).  n = 0 does nothing.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_error_field(const double* u, const double* v, const double* u_ref,
+                               const double* v_ref, int64_t n, const double* metrics,
+                               double* out, void* stream);
 
 /* Copies tree arrays out of the workspace (device destinations, any may be
  * NULL): root[4] = {x0, y0, S, w_L}; perm[n] = input index of each sorted

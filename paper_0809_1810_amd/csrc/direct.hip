@@ -1,13 +1,16 @@
 // FP64 direct sum (eq. 7 / eq. 9) and the error metrics used to judge the FMM.
 //
 // Direct: u(x_i) = sum_{j != i} Gamma_j K_sigma(x_i - x_j) with the regularised
-// kernel of eq. 6, evaluated at all particles or at a list of particle indices.
+// kernel of eq. 6, evaluated at all particles, at a list of particle indices, or
+// at separate evaluation points (eq. 8).
 // One thread per target; each block stages 256 sources at a time through LDS,
 // so every source is read once per block.  The self pair (and any coincident
 // pair) has a zero offset and contributes exactly zero.
 //
 // Metrics (Section 5.1, errors normalised by the maximum velocity):
-// out[0] = max_i |dW_i|, out[1] = sum_i |dW_i|^2, out[2] = max_i |W_ref,i|.
+// out[0] = max_i |dW_i|, out[1] = sum_i |dW_i|^2, out[2] = max_i |W_ref,i|; and
+// the per-point error field log10(|dW_i| / max |W_ref|) behind the paper's
+// spatial error maps (Section 5).
 #include "vfmm_device.hpp"
 
 namespace vfmm {
@@ -20,15 +23,24 @@ __global__ void __launch_bounds__(256) k_direct(const double* __restrict__ x,
                                                 const double* __restrict__ y,
                                                 const double* __restrict__ g, int64_t n,
                                                 double kexp, const int64_t* __restrict__ targets,
-                                                int64_t nt, double* __restrict__ u,
-                                                double* __restrict__ v) {
+                                                const double* __restrict__ xt,
+                                                const double* __restrict__ yt, int64_t nt,
+                                                double* __restrict__ u, double* __restrict__ v) {
   __shared__ double sx[256], sy[256], sg[256];
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
-  int64_t i = t < nt ? (targets ? targets[t] : t) : 0;
-  const bool in_range = i >= 0 && i < n;  // out-of-range target indices yield NaN
   const bool valid = t < nt;
-  if (!in_range) i = 0;
-  const double xi = x[i], yi = y[i];
+  double xi, yi;
+  bool in_range = true;
+  if (xt) {  // separate evaluation points (eq. 8)
+    xi = valid ? xt[t] : 0.0;
+    yi = valid ? yt[t] : 0.0;
+  } else {
+    int64_t i = valid ? (targets ? targets[t] : t) : 0;
+    in_range = i >= 0 && i < n;  // out-of-range target indices yield NaN
+    if (!in_range) i = 0;
+    xi = x[i];
+    yi = y[i];
+  }
   double au = 0.0, av = 0.0;
   for (int64_t base = 0; base < n; base += 256) {
     const int64_t j = base + threadIdx.x;
@@ -101,14 +113,37 @@ __global__ void __launch_bounds__(256) k_metrics_final(const double* __restrict_
   if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
+// log10(|dW_i| / max |W_ref|), floored at 1e-300; NaN propagates.
+__global__ void __launch_bounds__(256) k_error_field(const double* __restrict__ u,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ ur,
+                                                     const double* __restrict__ vr, int64_t n,
+                                                     const double* __restrict__ metrics,
+                                                     double* __restrict__ out) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double m = metrics[2];
+  const double den = m > 0.0 ? m : 1.0;
+  const double d = hypot(u[i] - ur[i], v[i] - vr[i]) / den;
+  out[i] = log10(d > 1e-300 ? d : (d == d ? 1e-300 : d));
+}
+
 }  // namespace
 
+hipError_t launch_error_field(const double* u, const double* v, const double* ur,
+                              const double* vr, int64_t n, const double* metrics, double* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_error_field, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, u, v, ur,
+                     vr, n, metrics, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_direct(const double* x, const double* y, const double* g, int64_t n,
-                         double sigma, const int64_t* targets, int64_t nt, double* u, double* v,
-                         hipStream_t st) {
+                         double sigma, const int64_t* targets, const double* xt,
+                         const double* yt, int64_t nt, double* u, double* v, hipStream_t st) {
   const double kexp = -1.0 / (2.0 * sigma * sigma);
   hipLaunchKernelGGL(k_direct, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st, x, y, g, n,
-                     kexp, targets, nt, u, v);
+                     kexp, targets, xt, yt, nt, u, v);
   return hipGetLastError();
 }
 

@@ -42,23 +42,23 @@ namespace {
 template <typename R, int PMAX, int LPT>
 __global__ void __launch_bounds__(512) k_p2p_l2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
-    const Tile* __restrict__ tiles, const int32_t* __restrict__ ntiles,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
-    const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
+    const int32_t* __restrict__ tntiles, const float4* __restrict__ ttile_box,
+    const int32_t* __restrict__ tperm, const double* __restrict__ root, int levels, int p,
     const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
-    int parts, const int32_t* __restrict__ perm, double* __restrict__ u,
-    double* __restrict__ v) {
+    int parts, double* __restrict__ u, double* __restrict__ v) {
   using C = typename Types<R>::C;
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   const int wpb = blockDim.x >> 6;
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-  if (wid >= *ntiles) return;
+  if (wid >= *tntiles) return;
   const int lane = threadIdx.x & 63;
   const int tl = lane % T, grp = lane / T;  // target in tile, source sub-stream
-  const Tile tile = tiles[wid];
+  const Tile tile = ttiles[wid];
   const bool active = tl < tile.count;
   const int32_t i = tile.start + (active ? tl : 0);
-  const auto tp = part[i];
+  const auto tp = tpart[i];
   const int m = 1 << levels;
   const int bx = tile.leaf & (m - 1), by = tile.leaf >> levels;
   const double w = root[3];
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
   double nu = 0.0, nv = 0.0;
   if (parts & 1) {
     const R tiny = R(w * w * 0x1p-80);
-    const float4 tb = tile_box[wid];
+    const float4 tb = ttile_box[wid];
     Acc32 au{0.f, 0.f}, av{0.f, 0.f};
     for (int oy = -1; oy <= 1; ++oy) {
       const int sy = by + oy;
@@ -168,18 +168,21 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
   }
 
   if (active && grp == 0) {
-    const int32_t o = perm[i];
+    const int32_t o = tperm[i];
     u[o] = nu + fu;
     v[o] = nv + fv;
   }
 }
 
 template <typename R, int PMAX, int LPT>
-void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
               double* u, double* v, hipStream_t st) {
   using C = typename Types<R>::C;
-  const auto* part = reinterpret_cast<const typename Types<R>::Part*>(
+  using Part = typename Types<R>::Part;
+  const auto* part = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32));
+  const auto* tpart = reinterpret_cast<const Part*>(
+      sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
   const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
   const double k64 = -1.0 / (2.0 * sigma * sigma);
   const R kexp = sizeof(R) == 8 ? R(k64) : R(k64 * 1.4426950408889634074);
@@ -187,36 +190,37 @@ void launch_t(const TreeDev& t, const Layout& lay, int levels, int p, double sig
   const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
   const R ka = R(1.0 / (2.0 * sigma * sigma));
   const int wpb = tuning_waves();
-  const unsigned blocks = unsigned((lay.max_tiles + wpb - 1) / wpb);
+  const unsigned blocks = unsigned((tg.max_tiles + wpb - 1) / wpb);
   hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(blocks), dim3(64 * wpb), 0, st, part,
-                     t.leaf_start, t.tiles, t.ntiles, t.tile_off, t.tile_box, t.root, levels, p,
-                     le, kexp, ka, far2, ser2, parts, t.perm, u, v);
+                     t.leaf_start, t.tile_off, t.tile_box, tpart, tg.tiles, tg.ntiles,
+                     tg.tile_box, tg.perm, t.root, levels, p, le, kexp, ka, far2, ser2, parts, u,
+                     v);
 }
 
 template <typename R, int PMAX>
-void launch_l(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+void launch_l(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
               double* u, double* v, hipStream_t st) {
-  if (t.tile == 16) launch_t<R, PMAX, 4>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, lay, levels, p, sigma, parts, u, v, st);
-  else launch_t<R, PMAX, 1>(t, lay, levels, p, sigma, parts, u, v, st);
+  if (t.tile == 16) launch_t<R, PMAX, 4>(t, tg, levels, p, sigma, parts, u, v, st);
+  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, tg, levels, p, sigma, parts, u, v, st);
+  else launch_t<R, PMAX, 1>(t, tg, levels, p, sigma, parts, u, v, st);
 }
 
 template <typename R>
-void launch_r(const TreeDev& t, const Layout& lay, int levels, int p, double sigma, int parts,
+void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
               double* u, double* v, hipStream_t st) {
-  if (p <= 8) launch_l<R, 8>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 16) launch_l<R, 16>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 24) launch_l<R, 24>(t, lay, levels, p, sigma, parts, u, v, st);
-  else if (p <= 32) launch_l<R, 32>(t, lay, levels, p, sigma, parts, u, v, st);
-  else launch_l<R, 40>(t, lay, levels, p, sigma, parts, u, v, st);
+  if (p <= 8) launch_l<R, 8>(t, tg, levels, p, sigma, parts, u, v, st);
+  else if (p <= 16) launch_l<R, 16>(t, tg, levels, p, sigma, parts, u, v, st);
+  else if (p <= 24) launch_l<R, 24>(t, tg, levels, p, sigma, parts, u, v, st);
+  else if (p <= 32) launch_l<R, 32>(t, tg, levels, p, sigma, parts, u, v, st);
+  else launch_l<R, 40>(t, tg, levels, p, sigma, parts, u, v, st);
 }
 
 }  // namespace
 
-hipError_t launch_p2p_l2p(const TreeDev& t, const Layout& lay, int levels, int p, int prec,
+hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
                           double sigma, int parts, double* u, double* v, hipStream_t st) {
-  if (prec == kFP64) launch_r<double>(t, lay, levels, p, sigma, parts, u, v, st);
-  else launch_r<float>(t, lay, levels, p, sigma, parts, u, v, st);
+  if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, u, v, st);
+  else launch_r<float>(t, tg, levels, p, sigma, parts, u, v, st);
   return hipGetLastError();
 }
 

@@ -94,25 +94,53 @@ __device__ inline uint32_t spread4(uint32_t v) {  // bits b3 b2 b1 b0 -> b3 0 b2
   return v;
 }
 
+// Sort key of a point: leaf (row-major) above the Morton index of its cell at
+// level L + 4 inside the leaf.
+__device__ inline uint32_t point_key(double x, double y, const double* __restrict__ root,
+                                     int levels) {
+#pragma clang fp contract(off)
+  const double x0 = root[0], y0 = root[1], S = root[2];
+  const int mf = 1 << (levels + kSubLevels);
+  const double scale = double(mf);
+  // floor(t 2^(L+4)) >> 4 == floor(t 2^L): the leaf decision is unchanged
+  double fx = floor(((x - x0) / S) * scale);
+  double fy = floor(((y - y0) / S) * scale);
+  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
+  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
+  const uint32_t leaf = (uint32_t(iy >> kSubLevels) << levels) | uint32_t(ix >> kSubLevels);
+  const uint32_t sub = spread4(uint32_t(ix)) | (spread4(uint32_t(iy)) << 1);
+  return (leaf << (2 * kSubLevels)) | sub;
+}
+
+// Inside the closed root square (NaN coordinates are outside).
+__device__ inline bool in_root(double x, double y, const double* __restrict__ root) {
+#pragma clang fp contract(off)
+  const double x0 = root[0], y0 = root[1], S = root[2];
+  return x >= x0 && x <= x0 + S && y >= y0 && y <= y0 + S;
+}
+
 __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
                                               const double* __restrict__ y, int64_t n,
                                               const double* __restrict__ root, int levels,
                                               uint32_t* __restrict__ keys,
                                               int32_t* __restrict__ idx) {
-#pragma clang fp contract(off)
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
-  const double x0 = root[0], y0 = root[1], S = root[2];
-  const int mf = 1 << (levels + kSubLevels);
-  const double scale = double(mf);
-  // floor(t 2^(L+4)) >> 4 == floor(t 2^L): the leaf decision is unchanged
-  double fx = floor(((x[i] - x0) / S) * scale);
-  double fy = floor(((y[i] - y0) / S) * scale);
-  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
-  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
-  const uint32_t leaf = (uint32_t(iy >> kSubLevels) << levels) | uint32_t(ix >> kSubLevels);
-  const uint32_t sub = spread4(uint32_t(ix)) | (spread4(uint32_t(iy)) << 1);
-  keys[i] = (leaf << (2 * kSubLevels)) | sub;
+  keys[i] = point_key(x[i], y[i], root, levels);
+  idx[i] = int32_t(i);
+}
+
+// Evaluation points: points outside the root square get key 0 (their
+// coordinates become NaN below, so they only produce NaN velocities).
+__global__ void __launch_bounds__(256) k_target_keys(const double* __restrict__ x,
+                                                     const double* __restrict__ y, int64_t n,
+                                                     const double* __restrict__ root, int levels,
+                                                     uint32_t* __restrict__ keys,
+                                                     int32_t* __restrict__ idx) {
+  int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  keys[i] = in_root(xi, yi, root) ? point_key(xi, yi, root, levels) : 0u;
   idx[i] = int32_t(i);
 }
 
@@ -302,6 +330,29 @@ __global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__
   p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
 }
 
+__global__ void __launch_bounds__(256) k_target_coords(const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const uint32_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ perm, int64_t n,
+                                                       const double* __restrict__ root, int levels,
+                                                       Part64* __restrict__ p64,
+                                                       Part32* __restrict__ p32) {
+#pragma clang fp contract(off)
+  int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t leaf = keys[i] >> (2 * kSubLevels);
+  const int ix = int(leaf & ((1u << levels) - 1u)), iy = int(leaf >> levels);
+  const double w = root[3];
+  const double cx = root[0] + (double(ix) + 0.5) * w;
+  const double cy = root[1] + (double(iy) + 0.5) * w;
+  const int32_t j = perm[i];
+  const double xj = x[j], yj = y[j];
+  const bool ok = in_root(xj, yj, root);
+  const double lx = ok ? xj - cx : NAN, ly = ok ? yj - cy : NAN;
+  p64[i] = Part64{lx, ly, 0.0, 0.0};
+  p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
+}
+
 __global__ void __launch_bounds__(256) k_tile_counts(const int32_t* __restrict__ start,
                                                      int64_t nleaves, int tile,
                                                      uint32_t* __restrict__ cnt) {
@@ -429,6 +480,43 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      tile, t.tiles, t.ntiles);
   hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
                      t.tiles, t.ntiles, t.part32, t.tile_box);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, const TreeDev& t,
+                                int levels, const TargetLayout& lay, char* ws, TargetsDev& out,
+                                hipStream_t st) {
+  uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + lay.keys0);
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(ws + lay.keys1);
+  int32_t* i0 = reinterpret_cast<int32_t*>(ws + lay.idx0);
+  int32_t* i1 = reinterpret_cast<int32_t*>(ws + lay.idx1);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + lay.scan_tmp);
+  int32_t* lstart = reinterpret_cast<int32_t*>(ws + lay.leaf_start);
+  uint32_t* toff = reinterpret_cast<uint32_t*>(ws + lay.tile_off);
+  Tile* tiles = reinterpret_cast<Tile*>(ws + lay.tiles);
+  int32_t* ntiles = reinterpret_cast<int32_t*>(ws + lay.ntiles);
+  float4* tbox = reinterpret_cast<float4*>(ws + lay.tile_box);
+  Part64* p64 = reinterpret_cast<Part64*>(ws + lay.part64);
+  Part32* p32 = reinterpret_cast<Part32*>(ws + lay.part32);
+  const int64_t nl = lay.nleaves;
+  hipLaunchKernelGGL(k_target_keys, dim3(nblocks(nt, 256)), dim3(256), 0, st, xt, yt, nt, t.root,
+                     levels, k0, i0);
+  hipError_t e = radix_sort_pairs(k0, k1, i0, i1, nt, 2 * (levels + kSubLevels), counts, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_leaf_start, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, k0, nt, nl,
+                     lstart);
+  hipLaunchKernelGGL(k_target_coords, dim3(nblocks(nt, 256)), dim3(256), 0, st, xt, yt, k0, i0,
+                     nt, t.root, levels, p64, p32);
+  hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
+                     t.tile, toff);
+  e = scan_exclusive(toff, nl + 1, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(nt, 256)), dim3(256), 0, st, k0, lstart, toff, nt,
+                     nl, t.tile, tiles, ntiles);
+  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st, tiles,
+                     ntiles, p32, tbox);
+  out = TargetsDev{p64, p32, tiles, ntiles, tbox, i0, lay.max_tiles};
   return hipGetLastError();
 }
 

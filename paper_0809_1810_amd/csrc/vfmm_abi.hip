@@ -196,27 +196,45 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   return VFMM_OK;
 }
 
-vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
-                                      int32_t precision, int32_t parts, double* u, double* v,
-                                      void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Outputs u, v are checked only when there is something to write (`need_out`).
+vfmm_status_t check_eval(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                         int32_t precision, int32_t parts, const double* u, const double* v,
+                         bool need_out = true) {
   if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
-  if (!gamma || !u || !v) return fail(VFMM_ERR_INVALID_ARG, "gamma, u or v is NULL");
+  if (!gamma) return fail(VFMM_ERR_INVALID_ARG, "gamma is NULL");
+  if (need_out && (!u || !v)) return fail(VFMM_ERR_INVALID_ARG, "u or v is NULL");
   if (!finite_pos(sigma)) return fail(VFMM_ERR_INVALID_ARG, "sigma must be finite and > 0");
   if (p < 1 || p > t->p_max)
     return fail(VFMM_ERR_INVALID_ARG, "p=%d out of [1, p_max=%d]", p, t->p_max);
   if (precision < VFMM_FP64 || precision > VFMM_M2L_FP16)
     return fail(VFMM_ERR_INVALID_ARG, "unknown precision %d", precision);
   if (parts < 1 || parts > 3) return fail(VFMM_ERR_INVALID_ARG, "parts must be 1, 2 or 3");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  return VFMM_OK;
+}
+
+// Phase-timing marks of one evaluation (no-op when timing is off or the ring is full).
+struct Marks {
+  hipEvent_t* ev = nullptr;
+  hipStream_t st;
+  Marks(vfmm_tree_t t, hipStream_t s) : st(s) {
+    if (t->t_used < t->t_slots) ev = &t->ev[size_t(t->t_used++) * (VFMM_N_PHASES + 1)];
+  }
+  void operator()(int k) const {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  }
+};
+
+// Circulations into the sorted particles, then the upward and downward sweeps
+// (Fig. 3): operator tables, P2M, M2M, M2L + L2L.  Marks phases 1 .. 5.
+vfmm_status_t sweeps(vfmm_tree_t t, const double* gamma, int32_t p, int32_t precision,
+                     int32_t parts, const Marks& mark, hipStream_t st) {
   const int L = t->levels;
   // the reduced-precision M2L variants share the FP32 pipeline
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  hipEvent_t* ev = nullptr;
-  if (t->t_used < t->t_slots) ev = &t->ev[size_t(t->t_used++) * (VFMM_N_PHASES + 1)];
-  auto mark = [&](int k) {
-    if (ev) (void)hipEventRecord(ev[k], st);
-  };
-  mark(0);
   hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, st);
   if (e != hipSuccess) return hip_fail(e, "gather");
   mark(1);
@@ -252,10 +270,114 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
     t->last_prec = prec;
   }
   mark(5);
-  e = launch_p2p_l2p(t->dev, t->lay, L, p, prec, sigma, parts, u, v, st);
+  return VFMM_OK;
+}
+
+}  // namespace
+
+namespace vfmm {
+
+TargetLayout make_target_layout(int64_t nt, int levels) {
+  TargetLayout L{};
+  L.nt = nt;
+  L.nleaves = int64_t(1) << (2 * levels);
+  L.sort_blocks = (nt + kSortPerBlock - 1) / kSortPerBlock;
+  L.count_len = 256 * L.sort_blocks;
+  const int64_t nonempty = nt < L.nleaves ? nt : L.nleaves;
+  L.max_tiles = (nt + kTileMin - 1) / kTileMin + nonempty;
+  const int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+  L.keys0 = take(size_t(nt) * 4);
+  L.keys1 = take(size_t(nt) * 4);
+  L.idx0 = take(size_t(nt) * 4);
+  L.idx1 = take(size_t(nt) * 4);
+  L.counts = take(size_t(L.count_len) * 4);
+  L.scan_tmp = take(size_t(scan_tmp) * 4);
+  L.leaf_start = take(size_t(L.nleaves + 1) * 4);
+  L.tile_off = take(size_t(L.nleaves + 1) * 4);
+  L.tiles = take(size_t(L.max_tiles) * sizeof(Tile));
+  L.ntiles = take(4);
+  L.tile_box = take(size_t(L.max_tiles) * sizeof(float4));
+  L.part64 = take(size_t(nt) * sizeof(Part64));
+  L.part32 = take(size_t(nt) * sizeof(Part32));
+  L.total = off;
+  return L;
+}
+
+}  // namespace vfmm
+
+extern "C" {
+
+vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                                      int32_t precision, int32_t parts, double* u, double* v,
+                                      void* stream) {
+  vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, parts, u, v);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Marks mark(t, st);
+  mark(0);
+  s = sweeps(t, gamma, p, precision, parts, mark, st);
+  if (s) return s;
+  const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
+  hipError_t e = launch_p2p_l2p(t->dev, self_targets(t->dev, t->lay), t->levels, p, prec, sigma,
+                                parts, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
   mark(6);
   return VFMM_OK;
+}
+
+vfmm_status_t vfmm_targets_workspace_bytes(int64_t n_targets, int32_t levels, size_t* bytes) {
+  if (!bytes) return fail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_targets < 0 || n_targets > 2147483647LL)
+    return fail(VFMM_ERR_INVALID_ARG, "n_targets=%lld out of [0, 2^31-1]", (long long)n_targets);
+  if (levels < 0 || levels > kMaxLevels)
+    return fail(VFMM_ERR_INVALID_ARG, "levels=%d out of [0, %d]", levels, kMaxLevels);
+  *bytes = make_target_layout(n_targets, levels).total;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                                   int32_t precision, int32_t parts, const double* xt,
+                                   const double* yt, int64_t n_targets, void* workspace,
+                                   size_t ws_bytes, double* u, double* v, void* stream) {
+  vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, parts, u, v, n_targets > 0);
+  if (s) return s;
+  if (n_targets < 0 || n_targets > 2147483647LL)
+    return fail(VFMM_ERR_INVALID_ARG, "n_targets=%lld out of [0, 2^31-1]", (long long)n_targets);
+  if (n_targets == 0) return VFMM_OK;
+  if (!xt || !yt) return fail(VFMM_ERR_INVALID_ARG, "xt or yt is NULL");
+  if (!workspace) return fail(VFMM_ERR_INVALID_ARG, "workspace is NULL");
+  const TargetLayout lay = make_target_layout(n_targets, t->levels);
+  if (ws_bytes < lay.total)
+    return fail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Marks mark(t, st);
+  mark(0);
+  TargetsDev tg{};
+  hipError_t e = launch_build_targets(xt, yt, n_targets, t->dev, t->levels, lay,
+                                      static_cast<char*>(workspace), tg, st);
+  if (e != hipSuccess) return hip_fail(e, "evaluation points");
+  s = sweeps(t, gamma, p, precision, parts, mark, st);
+  if (s) return s;
+  const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
+  e = launch_p2p_l2p(t->dev, tg, t->levels, p, prec, sigma, parts, u, v, st);
+  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
+  mark(6);
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_error_field(const double* u, const double* v, const double* ur,
+                               const double* vr, int64_t n, const double* metrics, double* out,
+                               void* stream) {
+  if (!u || !v || !ur || !vr || !metrics || !out) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 0) return fail(VFMM_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return VFMM_OK;
+  hipError_t e = launch_error_field(u, v, ur, vr, n, metrics, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "error field");
 }
 
 vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
@@ -273,7 +395,21 @@ vfmm_status_t vfmm_direct_velocity(const double* x, const double* y, const doubl
     return fail(VFMM_ERR_INVALID_ARG, "n_targets must equal n when targets is NULL");
   if (n_targets < 0) return fail(VFMM_ERR_INVALID_ARG, "n_targets < 0");
   if (n_targets == 0) return VFMM_OK;
-  hipError_t e = launch_direct(x, y, gamma, n, sigma, targets, n_targets, u, v,
+  hipError_t e = launch_direct(x, y, gamma, n, sigma, targets, nullptr, nullptr, n_targets, u, v,
+                               static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? VFMM_OK : hip_fail(e, "direct");
+}
+
+vfmm_status_t vfmm_direct_velocity_at(const double* x, const double* y, const double* gamma,
+                                      int64_t n, double sigma, const double* xt, const double* yt,
+                                      int64_t n_targets, double* u, double* v, void* stream) {
+  if (!x || !y || !gamma) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1) return fail(VFMM_ERR_INVALID_ARG, "n must be >= 1");
+  if (!finite_pos(sigma)) return fail(VFMM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  if (n_targets < 0) return fail(VFMM_ERR_INVALID_ARG, "n_targets < 0");
+  if (n_targets == 0) return VFMM_OK;
+  if (!xt || !yt || !u || !v) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
+  hipError_t e = launch_direct(x, y, gamma, n, sigma, nullptr, xt, yt, n_targets, u, v,
                                static_cast<hipStream_t>(stream));
   return e == hipSuccess ? VFMM_OK : hip_fail(e, "direct");
 }

@@ -92,6 +92,32 @@ struct TreeDev {
   double* reduce;
 };
 
+// Evaluation points of the near-field + L2P kernel: the tree's own particles,
+// or a separate point set sorted into the tree's leaves (same tile size).
+// Points with NaN coordinates produce NaN velocities.
+struct TargetsDev {
+  const Part64* part64;  // leaf-local coordinates (g unused for separate points)
+  const Part32* part32;
+  const Tile* tiles;
+  const int32_t* ntiles;
+  const float4* tile_box;
+  const int32_t* perm;   // sorted position -> caller's index
+  int64_t max_tiles;
+};
+
+inline TargetsDev self_targets(const TreeDev& t, const Layout& lay) {
+  return TargetsDev{t.part64, t.part32, t.tiles, t.ntiles, t.tile_box, t.perm, lay.max_tiles};
+}
+
+// Workspace of a separate evaluation-point set of nt points at leaf level L.
+struct TargetLayout {
+  size_t keys0, keys1, idx0, idx1, counts, scan_tmp, leaf_start, tile_off, tiles, ntiles,
+      tile_box, part64, part32, total;
+  int64_t nt, nleaves, max_tiles, sort_blocks, count_len;
+};
+
+TargetLayout make_target_layout(int64_t nt, int levels);
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
@@ -111,11 +137,23 @@ hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStr
 // (prec = kFP32, kM2L_BF16 or kM2L_FP16), then the L2L chain.
 hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t stream);
 hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
-hipError_t launch_p2p_l2p(const TreeDev& t, const Layout& lay, int levels, int p, int prec,
+hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
                           double sigma, int parts, double* u, double* v, hipStream_t stream);
+// Sorts nt evaluation points into the leaves of tree t (built with `levels`),
+// with leaf-local coordinates (NaN outside the closed root square) and tiles of
+// t.tile points.
+hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, const TreeDev& t,
+                                int levels, const TargetLayout& lay, char* ws, TargetsDev& out,
+                                hipStream_t stream);
+// Per-point log10 of |dW| / max |W_ref| (metrics[2] holds max |W_ref|).
+hipError_t launch_error_field(const double* u, const double* v, const double* ur,
+                              const double* vr, int64_t n, const double* metrics, double* out,
+                              hipStream_t stream);
+// Targets: particle indices (targets, or all when NULL and xt is NULL) or
+// separate points (xt, yt).
 hipError_t launch_direct(const double* x, const double* y, const double* g, int64_t n,
-                         double sigma, const int64_t* targets, int64_t nt, double* u,
-                         double* v, hipStream_t stream);
+                         double sigma, const int64_t* targets, const double* xt,
+                         const double* yt, int64_t nt, double* u, double* v, hipStream_t stream);
 hipError_t launch_error_metrics(const double* u, const double* v, const double* ur,
                                 const double* vr, int64_t n, double* partial, double* out,
                                 hipStream_t stream);

@@ -52,6 +52,15 @@ _SIGS = {
     "vfmm_direct_velocity": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                          C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
                                          C.c_void_p, C.c_void_p]),
+    "vfmm_targets_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "vfmm_fmm_velocity_at": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_direct_velocity_at": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                            C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_error_field": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_metrics_scratch_bytes": (C.c_size_t, []),
     "vfmm_error_metrics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -157,6 +166,13 @@ def workspace_bytes(n: int, levels: int, p_max: int) -> int:
     return int(b.value)
 
 
+def targets_workspace_bytes(n_targets: int, levels: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().vfmm_targets_workspace_bytes(int(n_targets), int(levels), C.byref(b)),
+           "vfmm_targets_workspace_bytes")
+    return int(b.value)
+
+
 class Tree:
     """A quadtree over device-resident particles, with its workspace."""
 
@@ -198,6 +214,34 @@ class Tree:
         _check(lib().vfmm_fmm_velocity_parts(self._h, gamma.data_ptr(), float(sigma), int(p),
                                              int(precision), int(parts), u.data_ptr(),
                                              v.data_ptr(), _stream()), "vfmm_fmm_velocity")
+        return u, v
+
+    def velocity_at(self, gamma, sigma: float, p: int, xt, yt, precision=FP64, parts=PART_ALL,
+                    out=None, workspace=None):
+        """FMM velocity at separate evaluation points (xt, yt); NaN outside the root square."""
+        torch = _torch()
+        gamma = _dev_f64(gamma, "gamma")
+        xt = _dev_f64(xt, "xt"); yt = _dev_f64(yt, "yt")
+        if gamma.shape[0] != self.n:
+            raise ValueError("gamma has the wrong length")
+        if xt.shape != yt.shape or xt.dim() != 1:
+            raise ValueError("xt and yt must be 1-D tensors of equal length")
+        nt = int(xt.shape[0])
+        precision = PRECISIONS.get(precision, precision)
+        if out is None:
+            u = torch.empty(nt, dtype=torch.float64, device=self.device)
+            v = torch.empty(nt, dtype=torch.float64, device=self.device)
+        else:
+            u, v = out
+        if workspace is None:
+            workspace = torch.empty(max(1, targets_workspace_bytes(nt, self.levels)),
+                                    dtype=torch.uint8, device=self.device)
+        _check(lib().vfmm_fmm_velocity_at(self._h, gamma.data_ptr(), float(sigma), int(p),
+                                          int(precision), int(parts), xt.data_ptr(), yt.data_ptr(),
+                                          nt, workspace.data_ptr(),
+                                          workspace.numel() * workspace.element_size(),
+                                          u.data_ptr(), v.data_ptr(), _stream()),
+               "vfmm_fmm_velocity_at")
         return u, v
 
     def rebuild(self, x, y, domain=None):
@@ -282,6 +326,45 @@ def direct_velocity(x, y, gamma, sigma: float, targets=None, out=None):
                                       float(sigma), tp, nt, u.data_ptr(), v.data_ptr(), _stream()),
            "vfmm_direct_velocity")
     return u, v
+
+
+def direct_velocity_at(x, y, gamma, sigma: float, xt, yt, out=None):
+    """Float64 direct sum (eq. 8) at separate evaluation points."""
+    torch = _torch()
+    x = _dev_f64(x, "x"); y = _dev_f64(y, "y"); gamma = _dev_f64(gamma, "gamma")
+    xt = _dev_f64(xt, "xt"); yt = _dev_f64(yt, "yt")
+    nt = int(xt.shape[0])
+    if out is None:
+        u = torch.empty(nt, dtype=torch.float64, device=x.device)
+        v = torch.empty(nt, dtype=torch.float64, device=x.device)
+    else:
+        u, v = out
+    _check(lib().vfmm_direct_velocity_at(x.data_ptr(), y.data_ptr(), gamma.data_ptr(),
+                                         int(x.shape[0]), float(sigma), xt.data_ptr(),
+                                         yt.data_ptr(), nt, u.data_ptr(), v.data_ptr(), _stream()),
+           "vfmm_direct_velocity_at")
+    return u, v
+
+
+def error_field(u, v, u_ref, v_ref):
+    """Per-point log10(|dW| / max|W_ref|) (device tensor), floored at -300."""
+    torch = _torch()
+    for t, nme in ((u, "u"), (v, "v"), (u_ref, "u_ref"), (v_ref, "v_ref")):
+        _dev_f64(t, nme)
+    n = int(u.shape[0])
+    scratch = torch.empty(int(lib().vfmm_metrics_scratch_bytes()), dtype=torch.uint8,
+                          device=u.device)
+    met = torch.empty(3, dtype=torch.float64, device=u.device)
+    out = torch.empty(n, dtype=torch.float64, device=u.device)
+    if n == 0:
+        return out
+    _check(lib().vfmm_error_metrics(u.data_ptr(), v.data_ptr(), u_ref.data_ptr(),
+                                    v_ref.data_ptr(), n, scratch.data_ptr(), met.data_ptr(),
+                                    _stream()), "vfmm_error_metrics")
+    _check(lib().vfmm_error_field(u.data_ptr(), v.data_ptr(), u_ref.data_ptr(), v_ref.data_ptr(),
+                                  n, met.data_ptr(), out.data_ptr(), _stream()),
+           "vfmm_error_field")
+    return out
 
 
 def error_metrics(u, v, u_ref, v_ref):

@@ -111,3 +111,27 @@ def test_selector_features_host_function_matches_oracle():
         f = vf.selector_features(st, P.n, P.sigma, p, L)
         fr = OM.features(P.x, P.y, g, P.sigma, p, L, side)
         assert np.allclose(f, fr, rtol=1e-6, atol=1e-6), (f, fr)
+
+
+def test_evaluation_point_calls_reject_before_device_work():
+    l = _lib()
+    b = C.c_size_t(0)
+    assert l.vfmm_targets_workspace_bytes(1000, 5, C.byref(b)) == 0 and b.value > 0
+    b0 = C.c_size_t(1)
+    assert l.vfmm_targets_workspace_bytes(0, 5, C.byref(b0)) == 0
+    assert l.vfmm_targets_workspace_bytes(-1, 5, C.byref(b)) == B.ERR_INVALID_ARG
+    assert l.vfmm_targets_workspace_bytes(10, 13, C.byref(b)) == B.ERR_INVALID_ARG
+    fake = C.c_void_p(0x1000)
+    assert l.vfmm_fmm_velocity_at(None, fake, 0.1, 5, 0, 3, fake, fake, 10, fake, 1 << 30, fake,
+                                  fake, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_direct_velocity_at(fake, fake, fake, 10, 0.1, fake, fake, -1, fake, fake,
+                                     None) == B.ERR_INVALID_ARG
+    assert l.vfmm_direct_velocity_at(fake, fake, fake, 10, 0.0, fake, fake, 5, fake, fake,
+                                     None) == B.ERR_INVALID_ARG
+    assert l.vfmm_direct_velocity_at(fake, fake, fake, 10, 0.1, None, fake, 5, fake, fake,
+                                     None) == B.ERR_INVALID_ARG
+    # nothing to do: no device access
+    assert l.vfmm_direct_velocity_at(fake, fake, fake, 10, 0.1, None, None, 0, None, None, None) == 0
+    assert l.vfmm_error_field(fake, fake, fake, fake, 4, None, fake, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_error_field(fake, fake, fake, fake, -1, fake, fake, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_error_field(fake, fake, fake, fake, 0, fake, fake, None) == 0

@@ -219,6 +219,22 @@ def sample_targets(n: int, k: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
 
 
+def eval_lattice(n_side: int, square) -> tuple:
+    """Evaluation points: the n_side^2 cell centres of the square (x0, y0, S),
+    row-major, as (x, y) float64 arrays (the error-map grids of Section 5.2)."""
+    x0, y0, s = (float(v) for v in square)
+    c = (np.arange(n_side, dtype=np.float64) + 0.5) * (s / n_side)
+    gx, gy = np.meshgrid(x0 + c, y0 + c)
+    return _f64(gx.ravel()), _f64(gy.ravel())
+
+
+def eval_points(k: int, seed: int, square) -> tuple:
+    """k evaluation points uniform in the square (x0, y0, S), seeded."""
+    rng = np.random.default_rng(seed)
+    x0, y0, s = (float(v) for v in square)
+    return _f64(x0 + s * rng.uniform(size=k)), _f64(y0 + s * rng.uniform(size=k))
+
+
 def config(name: str) -> Particles:
     """Named workloads used by tests and the benchmark.
 
