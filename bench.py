@@ -100,6 +100,13 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (float64), "
                          "used to scale HBM byte counters")
+    ap.add_argument("--eval-lattice", type=int, default=0, metavar="M",
+                    help="instead of the N=1M line, evaluate the FMM of the workload at an "
+                         "M x M lattice of separate points covering the root square")
+    ap.add_argument("--p2p-tile", type=int, default=0,
+                    help="override the autotuned near-field tile (64, 32 or 16 targets)")
+    ap.add_argument("--p2p-waves", type=int, default=0,
+                    help="override the autotuned near-field waves per workgroup (1, 2, 4, 8)")
     ap.add_argument("--batched", action="store_true",
                     help="instead of the N=1M line, time 256 uneven instances evaluated as one "
                          "batch (graph replay) against one call per instance")
@@ -120,6 +127,8 @@ def main():
 
     if a.batched:
         return bench_batched(a, torch, vf)
+    if a.eval_lattice > 0:
+        return bench_eval_points(a, torch, vf)
 
     if a.calibrate_copy_mib > 0:
         src = torch.ones(a.calibrate_copy_mib * (1 << 17), dtype=torch.float64, device="cuda")
@@ -174,6 +183,7 @@ def main():
 
     def run_path(L, p, prec, steps, warmup, timing=False):
         AT.apply_for(n, L)  # near-field launch shape from the autotuner's table
+        override_tuning(a, vf)
         tree = vf.Tree(x, y, L, p_max=p)
         u = torch.empty(n, dtype=torch.float64, device="cuda")
         v = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -198,7 +208,8 @@ def main():
         _, _, ls = tree.arrays()
         pairs = p2p_pairs(ls.cpu().numpy(), L)
         tree.close()
-        return dict(ms=ms, wall_s=wall, phases=phases, emax=emax, erms=erms, pairs=pairs)
+        return dict(ms=ms, wall_s=wall, phases=phases, emax=emax, erms=erms, pairs=pairs,
+                    tile_waves=list(vf.get_tuning().values()))
 
     log(f"[bench] tuned: p={p_t} L={L_t} precision={a.precision}")
     tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True)
@@ -261,7 +272,7 @@ def main():
             "workload": f"{P.name}: N={n}, sigma={P.sigma}, seeded synthetic",
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
             "selector": selector, "selector_info": sel_info, "audit_targets": AUDIT_TARGETS,
-            "p2p_tile_waves": list(AT.lookup(n, L_t)),
+            "p2p_tile_waves": tuned["tile_waves"],
         },
         "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
         "roofline": roofline,
@@ -274,6 +285,103 @@ def main():
         out["speedup_vs_plain"] = round(plain["ms"] / tuned["ms"], 3)
     out["phases_ms"] = {k: round(float(np.mean([ph[k] for ph in tuned["phases"]])), 4)
                         for k in tuned["phases"][0]}
+    print(json.dumps(out), flush=True)
+
+
+def override_tuning(a, vf):
+    if a.p2p_tile or a.p2p_waves:
+        vf.set_tuning(tile=a.p2p_tile or None, waves=a.p2p_waves or None)
+
+
+def target_pairs(leaf_start, xe, ye, root, levels):
+    """Near-field (point, particle) pairs of an evaluation-point launch: points
+    per leaf (floor-and-clamp rule) times the particles of the 3 x 3 list."""
+    m = 1 << levels
+    x0, y0, s = root
+    ix = np.clip(np.floor((xe - x0) / s * m), 0, m - 1).astype(np.int64)
+    iy = np.clip(np.floor((ye - y0) / s * m), 0, m - 1).astype(np.int64)
+    tcnt = np.bincount(iy * m + ix, minlength=m * m).reshape(m, m)
+    cnt = np.diff(leaf_start.astype(np.int64)).reshape(m, m)
+    pad = np.pad(cnt, 1)
+    nb = sum(pad[1 + dy:1 + dy + m, 1 + dx:1 + dx + m] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    return int(np.sum(tcnt * nb))
+
+
+def bench_eval_points(a, torch, vf):
+    """FMM velocity of the workload's particles at an M x M lattice of separate
+    evaluation points covering the root square (the error-map set-up of
+    Section 5.2 at full size): tree rebuild + evaluation at the points (their
+    sort into the leaves included) per step; error against the FP64 direct
+    sum at 4096 sampled points, with the quantiles of the per-point log10
+    error field."""
+    from paper_0809_1810_amd import autotune as AT
+    from paper_0809_1810_amd import selector as S
+    P = W.config(a.workload)
+    n = P.n
+    x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
+    g = torch.from_numpy(P.gamma).cuda()
+    probe = vf.Tree(x, y, 0, p_max=1)
+    root = tuple(float(r) for r in probe.arrays()[0][:3].cpu().tolist())
+    probe.close()
+    xe_h, ye_h = W.eval_lattice(a.eval_lattice, root)
+    nt = len(xe_h)
+    xe = torch.from_numpy(xe_h).cuda(); ye = torch.from_numpy(ye_h).cuda()
+    sel = torch.from_numpy(W.sample_targets(nt, AUDIT_TARGETS, seed=2025)).cuda()
+    xs, ys = xe[sel].contiguous(), ye[sel].contiguous()
+    ud, vd = vf.direct_velocity_at(x, y, g, P.sigma, xs, ys)
+    if a.p is not None and a.levels is not None:
+        p, L, prec, how = a.p, a.levels, vf.PRECISIONS[a.precision], "fixed"
+    else:
+        r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights())
+        p, L = r["p"], r["levels"]
+        prec = vf.FP64 if r["precision"] == "fp64" else vf.PRECISIONS[a.precision]
+        how = "learned" if not r["fallback"] else "fallback"
+    log(f"[bench] evaluation points: {nt} on the root square, p={p} L={L} ({how})")
+    AT.apply_for(n, L)
+    override_tuning(a, vf)
+    tree = vf.Tree(x, y, L, p_max=p)
+    ws = torch.empty(vf.targets_workspace_bytes(nt, L), dtype=torch.uint8, device="cuda")
+    u = torch.empty(nt, dtype=torch.float64, device="cuda")
+    v = torch.empty(nt, dtype=torch.float64, device="cuda")
+    for _ in range(a.warmup):
+        tree.rebuild(x, y)
+        tree.velocity_at(g, P.sigma, p, xe, ye, prec, out=(u, v), workspace=ws)
+    torch.cuda.synchronize()
+    tree.enable_timing(a.steps)
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        tree.rebuild(x, y)
+        tree.velocity_at(g, P.sigma, p, xe, ye, prec, out=(u, v), workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    phases = tree.read_timing()
+    us, vs = u[sel].contiguous(), v[sel].contiguous()
+    emax, erms, _ = vf.error_metrics(us, vs, ud, vd)
+    field = vf.error_field(us, vs, ud, vd).cpu().numpy()
+    pairs = target_pairs(tree.arrays()[2].cpu().numpy(), xe_h, ye_h, root, L)
+    tree.close()
+    p2p_ms = float(np.mean([ph["p2p_l2p"] for ph in phases]))
+    achieved = P2P_FLOPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
+    out = {"metric": "evaluation points/s, FMM of N=2^20 particles at an M x M lattice of points",
+           "value": round(nt / (ms * 1e-3), 1), "unit": "points/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec != vf.FP64 else "f64", "data": "synthetic",
+           "config": {"workload": f"{P.name}: N={n}, sigma={P.sigma}; {a.eval_lattice}^2 "
+                                  "cell-centred lattice of evaluation points on the root square",
+                      "p": p, "levels": L, "selector": how,
+                      "p2p_tile_waves": list(vf.get_tuning().values())},
+           "accuracy": {"emax": emax, "erms": erms, "sample": AUDIT_TARGETS,
+                        "log10_error_quantiles": {q: float(np.quantile(field, float(q)))
+                                                  for q in ("0.5", "0.9", "0.99", "1.0")}},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 3),
+                        "traffic": None, "kernel": "k_p2p_l2p<float>",
+                        "kernel_ms": round(p2p_ms, 4), "pairs_per_launch": pairs,
+                        "flops_per_pair": P2P_FLOPS_PER_PAIR},
+           "phases_ms": {k: round(float(np.mean([ph[k] for ph in phases])), 4) for k in phases[0]}}
     print(json.dumps(out), flush=True)
 
 

@@ -1,25 +1,36 @@
 // Near field (P2P) with the far-field evaluation (L2P), the near + far sum and
-// the scatter back to the caller's particle order fused into one kernel
-// (Cruz & Barba 2008, eq. 10: f = f_near + f_far).
+// the scatter back to the caller's order fused into one kernel
+// (Cruz & Barba 2008, eq. 10: f = f_near + f_far), at the particles (eq. 9) or
+// at a separate set of evaluation points sorted into the same leaves (eq. 8).
 //
-// P2P: for each target i, the regularised Biot-Savart sum (eq. 6) over the
-// particles of the 3 x 3 local list of its leaf (Section 3.3.1), self term
-// excluded; it contributes exactly zero because the pair offset is (0, 0).
+// P2P: for each target, the regularised Biot-Savart sum (eq. 6) over the
+// particles of the 3 x 3 local list of its leaf (Section 3.3.1); a source at
+// the target itself (the self term) contributes exactly zero because the pair
+// offset is (0, 0).
 // L2P: W_far = (-j / (2 pi w)) sum_n L_n ((z - c)/w)^n, Horner's rule.
 //
-// Work decomposition: one wave per tile of <= T targets of one leaf (tiles built
-// with the tree, in leaf order; T = 64, 32 or 16 from the tuning), 64 / T lanes
-// per target, each lane taking every (64 / T)-th source of a chunk, the lanes of a
-// target summed by shuffles at the end.  Blocks keep the
-// hardware's round-robin dealing to the 8 XCDs, which spreads the heavy tiles of
-// dense regions over all XCDs (contiguous per-XCD ranges, or ordering tiles by
-// cost, were measured 1.7-2x slower on clustered inputs).
-// The source loop runs over the 9 leaf ranges of the local list in chunks of T,
-// which are exactly the tiles of the source leaf; with T = 64 the source index
-// is the same for all lanes of the wave, so sources are fetched with scalar
-// loads and broadcast (8 per loop trip, so several loads are in flight).  Source
-// coordinates are box-local; the target is shifted once per neighbour leaf by
-// the exact centre offset.
+// Work decomposition: targets come in tiles of <= T points of one leaf (T = 64,
+// 32 or 16 from the tuning; 64 / T lanes per target, each lane taking every
+// (64 / T)-th source of a chunk, the lanes of a target summed by shuffles).
+// The sources of a tile's local list are the source tiles ("chunks", <= T
+// particles of one leaf) of its three rows of leaves; in each row the chunks of
+// the three leaves are consecutive.  A schedule cuts every tile's chunk
+// sequence into parts of similar size, so that a launch has a set number of
+// parts (4 per target tile, 4096 to 65536) whatever the spread of the work: on
+// clustered particles, or on a lattice of evaluation points, a few leaves hold
+// most of the pairs.  One wave per part; a tile with one part writes its
+// result directly, the parts of a split tile write partial sums that a second
+// kernel adds in part order (so results do not depend on timing) before the
+// L2P.  The parts of the tiles of one leaf are interleaved so that
+// neighbouring waves read the same sources.  Workgroups keep the hardware's
+// round-robin dealing to the 8 XCDs (contiguous per-XCD ranges, or ordering
+// tiles by cost, were measured 1.7-2x slower on clustered inputs).
+// With T = 64 the source index is the same for all lanes of the wave, so
+// sources are fetched with scalar loads and broadcast (8 per loop trip, so
+// several loads are in flight); the part and tile fields are read into scalar
+// registers so that the compiler keeps the loop bounds, and the loads, scalar.
+// Coordinates are box-local; the target is shifted once per source leaf by the
+// exact centre offset.
 //
 // Far chunks: when the bounding boxes of the target tile and of a source chunk
 // are more than r_c apart, every pair has exp(-r^2 / 2 sigma^2) below half an
@@ -29,9 +40,10 @@
 //
 // FP32 variant: per-pair arithmetic in FP32 with the hardware exp2 and
 // reciprocal (and a short series for 1 - exp when r < sigma / 4, used only in
-// chunks whose bounding box comes that close to the tile); partial sums over chunks of 64 sources are added into a
-// compensated (TwoSum) FP32 accumulator, which keeps the rounding of long
-// source loops (up to ~1e5 sources per target) near the per-term level.
+// chunks whose bounding box comes that close to the tile); partial sums over
+// chunks are added into a compensated (TwoSum) FP32 accumulator, which keeps
+// the rounding of long source loops (up to ~1e5 sources per target) near the
+// per-term level; the parts of a split tile are added in FP64.
 // FP64 variant: plain FP64 with expm1 and division.
 #include "p2p_math.hpp"
 
@@ -39,139 +51,326 @@ namespace vfmm {
 
 namespace {
 
+// The local list of a leaf, row by row: in row sy the leaves lo .. hi (its
+// x neighbours clipped to the level) hold the consecutive chunks
+// tile_off[sy m + lo] .. tile_off[sy m + hi + 1] - 1.
+__device__ __forceinline__ uint32_t local_chunks(int leaf, int levels,
+                                                 const uint32_t* __restrict__ tile_off) {
+  const int m = 1 << levels;
+  const int bx = leaf & (m - 1), by = leaf >> levels;
+  const int lo = bx > 0 ? bx - 1 : 0, hi = bx < m - 1 ? bx + 1 : m - 1;
+  uint32_t c = 0;
+  for (int sy = by > 0 ? by - 1 : 0; sy <= by + 1 && sy < m; ++sy)
+    c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
+  return c;
+}
+
+// Source chunks per target tile (0 past the last tile), and per block their
+// 64-bit sum (the total over all tiles can exceed 32 bits).
+__global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ ttiles,
+                                                     const int32_t* __restrict__ tntiles,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     int levels, int64_t max_tiles,
+                                                     uint32_t* __restrict__ cnt,
+                                                     uint64_t* __restrict__ bsum) {
+  __shared__ uint64_t red[256];
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  uint32_t c = 0;
+  if (t < *tntiles) c = local_chunks(ttiles[t].leaf, levels, tile_off);
+  if (t <= max_tiles) cnt[t] = c;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// Total chunk count: bsum[nb] = sum of the nb block sums (fixed order).
+__global__ void __launch_bounds__(256) k_sched_total(uint64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ uint64_t red[256];
+  uint64_t s = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += 256) s += bsum[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[nb] = red[0];
+}
+
+// Parts per tile: part size K = max(kP2PMinChunks, ceil(total / P)) with
+// P = p2p_parts(max_tiles), parts = max(1, ceil(ch / K)); so the parts number
+// at most max_tiles + P and the parts of split tiles at most 2 P.
+// ch is the difference of the scanned counts (exact modulo 2^32).
+__global__ void __launch_bounds__(256) k_sched_parts(const int32_t* __restrict__ tntiles,
+                                                     const uint32_t* __restrict__ cnt,
+                                                     const uint64_t* __restrict__ total_p,
+                                                     int64_t max_tiles,
+                                                     uint32_t* __restrict__ pcnt,
+                                                     uint32_t* __restrict__ scnt) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  if (t > max_tiles) return;
+  uint32_t np = 0;
+  if (t < *tntiles) {
+    const uint64_t total = *total_p;
+    const uint64_t P = uint64_t(p2p_parts(max_tiles));
+    uint64_t k = (total + P - 1) / P;
+    if (k < kP2PMinChunks) k = kP2PMinChunks;
+    const uint64_t ch = uint32_t(cnt[t + 1] - cnt[t]);
+    np = ch == 0 ? 1u : uint32_t((ch + k - 1) / k);
+  }
+  pcnt[t] = np;
+  scnt[t] = np > 1 ? np : 0u;
+}
+
+// The tiles of one leaf share their local list, hence their chunk count and
+// number of parts; their parts are stored part-major (part k of every tile of
+// the leaf, then part k + 1), so that neighbouring waves read the same sources.
+__global__ void __launch_bounds__(256) k_sched_fill(const Tile* __restrict__ ttiles,
+                                                    const int32_t* __restrict__ tntiles,
+                                                    const uint32_t* __restrict__ ttile_off,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ p_off,
+                                                    const uint32_t* __restrict__ s_off,
+                                                    P2PPart* __restrict__ parts) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= *tntiles) return;
+  const int leaf = ttiles[t].leaf;
+  const uint32_t t0 = ttile_off[leaf], ntl = ttile_off[leaf + 1] - t0;
+  const uint64_t ch = uint32_t(cnt[t + 1] - cnt[t]);
+  const uint32_t np = p_off[t + 1] - p_off[t];
+  const uint32_t base = p_off[t0], r = uint32_t(t) - t0;
+  for (uint32_t k = 0; k < np; ++k)
+    parts[base + k * ntl + r] = P2PPart{int32_t(t), int32_t(k * ch / np),
+                                        int32_t((k + 1) * ch / np),
+                                        np > 1 ? int32_t(s_off[t] + k) : -1};
+}
+
+// Far-field evaluation at a target: (-j / (2 pi w)) sum_n L_n (z / w)^n with z
+// relative to the leaf centre; returns (u, v) = (Re, -Im).
+template <typename R, int PMAX>
+__device__ __forceinline__ void l2p(const typename Types<R>::C* __restrict__ L, R x, R y,
+                                    double w, int p, double& fu, double& fv) {
+  using C = typename Types<R>::C;
+  const R inv_w = R(1.0 / w);
+  const C z = cmake<C>(x * inv_w, y * inv_w);
+  C acc = cmake<C>(R(0), R(0));
+#pragma unroll
+  for (int k = PMAX - 1; k >= 0; --k) {
+    if (k < p) {
+      const C lk = L[k];
+      acc = cmul(acc, z);
+      acc.x += lk.x;
+      acc.y += lk.y;
+    }
+  }
+  // (-j/(2 pi w)) (a + j b) = (b - j a)/(2 pi w); u = Re, v = -Im
+  const double sc = kInv2Pi / w;
+  fu = double(acc.y) * sc;
+  fv = double(acc.x) * sc;
+}
+
 template <typename R, int PMAX, int LPT>
 __global__ void __launch_bounds__(512) k_p2p_l2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
     const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
-    const int32_t* __restrict__ tntiles, const float4* __restrict__ ttile_box,
-    const int32_t* __restrict__ tperm, const double* __restrict__ root, int levels, int p,
+    const float4* __restrict__ ttile_box, const int32_t* __restrict__ tperm,
+    const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts,
+    double2* __restrict__ partial, const double* __restrict__ root, int levels, int p,
     const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
-    int parts, double* __restrict__ u, double* __restrict__ v) {
-  using C = typename Types<R>::C;
+    int parts_mask, double* __restrict__ u, double* __restrict__ v) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   const int wpb = blockDim.x >> 6;
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-  if (wid >= *tntiles) return;
+  const int nwaves = gridDim.x * wpb;
   const int lane = threadIdx.x & 63;
   const int tl = lane % T, grp = lane / T;  // target in tile, source sub-stream
-  const Tile tile = ttiles[wid];
-  const bool active = tl < tile.count;
-  const int32_t i = tile.start + (active ? tl : 0);
-  const auto tp = tpart[i];
   const int m = 1 << levels;
-  const int bx = tile.leaf & (m - 1), by = tile.leaf >> levels;
   const double w = root[3];
+  const int np_total = int(*nparts);
+  for (int pi = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+       pi < np_total; pi += nwaves) {
+    // part and tile fields are wave-uniform: keep them in scalar registers so
+    // that the source loop bounds, and hence the source loads, stay scalar
+    const P2PPart ptv = parts[pi];
+    const int pt_tile = __builtin_amdgcn_readfirstlane(ptv.tile);
+    const uint32_t v0 = __builtin_amdgcn_readfirstlane(ptv.v0);
+    const uint32_t v1 = __builtin_amdgcn_readfirstlane(ptv.v1);
+    const int slot = __builtin_amdgcn_readfirstlane(ptv.slot);
+    const Tile tv = ttiles[pt_tile];
+    const int t_leaf = __builtin_amdgcn_readfirstlane(tv.leaf);
+    const int t_start = __builtin_amdgcn_readfirstlane(tv.start);
+    const int t_count = __builtin_amdgcn_readfirstlane(tv.count);
+    const bool active = tl < t_count;
+    const int32_t i = t_start + (active ? tl : 0);
+    const auto tp = tpart[i];
+    const int bx = t_leaf & (m - 1), by = t_leaf >> levels;
 
-  double nu = 0.0, nv = 0.0;
-  if (parts & 1) {
-    const R tiny = R(w * w * 0x1p-80);
-    const float4 tb = ttile_box[wid];
-    Acc32 au{0.f, 0.f}, av{0.f, 0.f};
-    for (int oy = -1; oy <= 1; ++oy) {
-      const int sy = by + oy;
-      if (sy < 0 || sy >= m) continue;
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int sx = bx + ox;
-        if (sx < 0 || sx >= m) continue;
-        const int sl = sy * m + sx;
-        const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
-        // target relative to the source leaf centre
-        const R tx = tp.x - R(double(ox) * w);
+    double nu = 0.0, nv = 0.0;
+    if (parts_mask & 1) {
+      const R tiny = R(w * w * 0x1p-80);
+      const float4 tb = ttile_box[pt_tile];
+      const int lo = bx > 0 ? bx - 1 : 0, hi = bx < m - 1 ? bx + 1 : m - 1;
+      Acc32 au{0.f, 0.f}, av{0.f, 0.f};
+      // chunks [v0, v1) of the sequence row by - 1, row by, row by + 1
+      uint32_t vb = 0;  // sequence index of the current row's first chunk
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int sy = by + oy;
+        if (sy < 0 || sy >= m) continue;
+        const uint32_t ra = tile_off[sy * m + lo], rb = tile_off[sy * m + hi + 1];
+        const uint32_t len = rb - ra;
+        const uint32_t cl = v0 > vb ? v0 - vb : 0u;
+        const uint32_t ch = v1 > vb ? (v1 - vb < len ? v1 - vb : len) : 0u;
+        vb += len;
+        if (cl >= ch) continue;
+        const uint32_t cb = ra + cl, ce = ra + ch;
         const R ty = tp.y - R(double(oy) * w);
-        const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
         const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
-        uint32_t ci = tile_off[sl];
-        for (int32_t j0 = js; j0 < je; j0 += T, ++ci) {
-          const int32_t j1 = min(j0 + T, je);
-          const float4 sb = tile_box[ci];
-          const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
-          const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
-          R cu = R(0), cv = R(0);
-          const float gap2 = gx * gx + gy * gy;
-          if (gap2 > far2) {
+        for (int sx = lo; sx <= hi; ++sx) {
+          const int sl = sy * m + sx;
+          const uint32_t la = tile_off[sl], lb = tile_off[sl + 1];
+          const uint32_t qa = la > cb ? la : cb, qb = lb < ce ? lb : ce;
+          if (qa >= qb) continue;
+          const int ox = sx - bx;
+          // target relative to the source leaf centre
+          const R tx = tp.x - R(double(ox) * w);
+          const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
+          const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
+          for (uint32_t ci = qa; ci < qb; ++ci) {
+            const int32_t j0 = js + int32_t(ci - la) * T;
+            const int32_t j1 = min(j0 + T, je);
+            const float4 sb = tile_box[ci];
+            const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
+            const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
+            R cu = R(0), cv = R(0);
+            const float gap2 = gx * gx + gy * gy;
+            if (gap2 > far2) {
 #pragma unroll 8
-            for (int32_t j = j0 + grp; j < j1; j += LPT) {
-              const auto s = part[j];
-              const R dx = tx - s.x;
-              const R dy = ty - s.y;
-              const R f = P2PMath<R>::far(s.g, dx * dx + dy * dy);
-              cu -= f * dy;
-              cv += f * dx;
-            }
-          } else if (gap2 > ser2) {
+              for (int32_t j = j0 + grp; j < j1; j += LPT) {
+                const auto s = part[j];
+                const R dx = tx - s.x;
+                const R dy = ty - s.y;
+                const R f = P2PMath<R>::far(s.g, dx * dx + dy * dy);
+                cu -= f * dy;
+                cv += f * dx;
+              }
+            } else if (gap2 > ser2) {
 #pragma unroll 8
-            for (int32_t j = j0 + grp; j < j1; j += LPT) {
-              const auto s = part[j];
-              const R dx = tx - s.x;
-              const R dy = ty - s.y;
-              const R r2 = dx * dx + (dy * dy + tiny);
-              const R f = P2PMath<R>::near(s.g, r2, kexp);
-              cu -= f * dy;
-              cv += f * dx;
-            }
-          } else {
+              for (int32_t j = j0 + grp; j < j1; j += LPT) {
+                const auto s = part[j];
+                const R dx = tx - s.x;
+                const R dy = ty - s.y;
+                const R r2 = dx * dx + (dy * dy + tiny);
+                const R f = P2PMath<R>::near(s.g, r2, kexp);
+                cu -= f * dy;
+                cv += f * dx;
+              }
+            } else {
 #pragma unroll 4
-            for (int32_t j = j0 + grp; j < j1; j += LPT) {
-              const auto s = part[j];
-              const R dx = tx - s.x;
-              const R dy = ty - s.y;
-              const R r2 = dx * dx + (dy * dy + tiny);
-              const R f = P2PMath<R>::near_series(s.g, r2, kexp, ka);
-              cu -= f * dy;
-              cv += f * dx;
+              for (int32_t j = j0 + grp; j < j1; j += LPT) {
+                const auto s = part[j];
+                const R dx = tx - s.x;
+                const R dy = ty - s.y;
+                const R r2 = dx * dx + (dy * dy + tiny);
+                const R f = P2PMath<R>::near_series(s.g, r2, kexp, ka);
+                cu -= f * dy;
+                cv += f * dx;
+              }
             }
-          }
-          if constexpr (sizeof(R) == 4) {
-            au.add(cu);
-            av.add(cv);
-          } else {
-            nu += cu;
-            nv += cv;
+            if constexpr (sizeof(R) == 4) {
+              au.add(cu);
+              av.add(cv);
+            } else {
+              nu += cu;
+              nv += cv;
+            }
           }
         }
       }
-    }
-    if constexpr (sizeof(R) == 4) {
-      nu = au.value();
-      nv = av.value();
-    }
-    // sum the LPT source sub-streams of each target
+      if constexpr (sizeof(R) == 4) {
+        nu = au.value();
+        nv = av.value();
+      }
+      // sum the LPT source sub-streams of each target
 #pragma unroll
-    for (int o = T; o < 64; o <<= 1) {
-      nu += __shfl_xor(nu, o, 64);
-      nv += __shfl_xor(nv, o, 64);
-    }
-    nu *= kInv2Pi;
-    nv *= kInv2Pi;
-  }
-
-  double fu = 0.0, fv = 0.0;
-  if ((parts & 2) && levels >= 2) {
-    const R inv_w = R(1.0 / w);
-    const C z = cmake<C>(tp.x * inv_w, tp.y * inv_w);
-    const C* L = le_leaf + int64_t(tile.leaf) * p;
-    C acc = cmake<C>(R(0), R(0));
-#pragma unroll
-    for (int k = PMAX - 1; k >= 0; --k) {
-      if (k < p) {
-        const C lk = L[k];
-        acc = cmul(acc, z);
-        acc.x += lk.x;
-        acc.y += lk.y;
+      for (int o = T; o < 64; o <<= 1) {
+        nu += __shfl_xor(nu, o, 64);
+        nv += __shfl_xor(nv, o, 64);
       }
     }
-    // (-j/(2 pi w)) (a + j b) = (b - j a)/(2 pi w); u = Re, v = -Im
-    const double sc = kInv2Pi / w;
-    fu = double(acc.y) * sc;
-    fv = double(acc.x) * sc;
-  }
 
-  if (active && grp == 0) {
-    const int32_t o = tperm[i];
-    u[o] = nu + fu;
-    v[o] = nv + fv;
+    if (slot >= 0) {
+      if (active && grp == 0) partial[int64_t(slot) * kTile + tl] = make_double2(nu, nv);
+      continue;
+    }
+    double fu = 0.0, fv = 0.0;
+    if ((parts_mask & 2) && levels >= 2)
+      l2p<R, PMAX>(le_leaf + int64_t(t_leaf) * p, tp.x, tp.y, w, p, fu, fv);
+    if (active && grp == 0) {
+      const int32_t o = tperm[i];
+      u[o] = nu * kInv2Pi + fu;
+      v[o] = nv * kInv2Pi + fv;
+    }
   }
+}
+
+// Split tiles: add the partial sums of their parts in part order, then L2P.
+template <typename R, int PMAX>
+__global__ void __launch_bounds__(256) k_p2p_reduce(
+    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
+    const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
+    const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
+    const double2* __restrict__ partial, const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::C* __restrict__ le_leaf, int parts_mask, double* __restrict__ u,
+    double* __restrict__ v) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *tntiles) return;
+  const uint32_t np = p_off[wid + 1] - p_off[wid];
+  if (np <= 1) return;
+  const int lane = threadIdx.x & 63;
+  const Tile tile = ttiles[wid];
+  if (lane >= tile.count) return;
+  const uint32_t s0 = s_off[wid];
+  double nu = 0.0, nv = 0.0;
+  for (uint32_t k = 0; k < np; ++k) {
+    const double2 q = partial[int64_t(s0 + k) * kTile + lane];
+    nu += q.x;
+    nv += q.y;
+  }
+  const int32_t i = tile.start + lane;
+  const auto tp = tpart[i];
+  const double w = root[3];
+  double fu = 0.0, fv = 0.0;
+  if ((parts_mask & 2) && levels >= 2)
+    l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, w, p, fu, fv);
+  const int32_t o = tperm[i];
+  u[o] = nu * kInv2Pi + fu;
+  v[o] = nv * kInv2Pi + fv;
+}
+
+inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, hipStream_t st) {
+  const P2PSched& s = tg.sched;
+  const int64_t mt = tg.max_tiles;
+  const int64_t nb = nblk(mt + 1, 256);
+  hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
+                     t.tile_off, levels, mt, s.cnt, s.bsum);
+  hipLaunchKernelGGL(k_sched_total, dim3(1), dim3(256), 0, st, s.bsum, nb);
+  hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,
+                     s.bsum + nb, mt, s.p_off, s.s_off);
+  e = scan_exclusive(s.p_off, mt + 1, s.scan_tmp, st);
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(s.s_off, mt + 1, s.scan_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sched_fill, dim3(nblk(mt, 256)), dim3(256), 0, st, tg.tiles, tg.ntiles,
+                     tg.tile_off, s.cnt, s.p_off, s.s_off, s.parts);
+  return hipGetLastError();
 }
 
 template <typename R, int PMAX, int LPT>
@@ -190,11 +389,21 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
   const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
   const R ka = R(1.0 / (2.0 * sigma * sigma));
   const int wpb = tuning_waves();
-  const unsigned blocks = unsigned((tg.max_tiles + wpb - 1) / wpb);
-  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(blocks), dim3(64 * wpb), 0, st, part,
-                     t.leaf_start, t.tile_off, t.tile_box, tpart, tg.tiles, tg.ntiles,
-                     tg.tile_box, tg.perm, t.root, levels, p, le, kexp, ka, far2, ser2, parts, u,
-                     v);
+  // bound on the number of parts: target tiles + min(P, chunks / K) with
+  // chunks <= target tiles x source tiles and K >= kP2PMinChunks
+  const int64_t pairs_bound = tg.max_tiles * t.max_tiles / kP2PMinChunks + 1;
+  const int64_t P = p2p_parts(tg.max_tiles);
+  int64_t waves = tg.max_tiles + (pairs_bound < P ? pairs_bound : P);
+  if (waves > kP2PMaxWaves) waves = kP2PMaxWaves;
+  const P2PSched& s = tg.sched;
+  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st,
+                     part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.tiles, tg.tile_box,
+                     tg.perm,
+                     s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, p, le, kexp, ka,
+                     far2, ser2, parts, u, v);
+  hipLaunchKernelGGL((k_p2p_reduce<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st,
+                     tpart, tg.tiles, tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, t.root,
+                     levels, p, le, parts, u, v);
 }
 
 template <typename R, int PMAX>
@@ -219,6 +428,8 @@ void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
 
 hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
                           double sigma, int parts, double* u, double* v, hipStream_t st) {
+  hipError_t e = build_schedule(t, tg, levels, st);
+  if (e != hipSuccess) return e;
   if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, u, v, st);
   else launch_r<float>(t, tg, levels, p, sigma, parts, u, v, st);
   return hipGetLastError();

@@ -476,6 +476,13 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   if (e != hipSuccess) return e;
   t.tile_off = toff;
   t.tile_box = reinterpret_cast<float4*>(ws + lay.tile_box);
+  t.sched = P2PSched{reinterpret_cast<uint32_t*>(ws + lay.sched_cnt),
+                     reinterpret_cast<uint32_t*>(ws + lay.sched_poff),
+                     reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
+                     reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
+                     reinterpret_cast<double2*>(ws + lay.sched_partial),
+                     reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp};
+  t.max_tiles = lay.max_tiles;
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
                      tile, t.tiles, t.ntiles);
   hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
@@ -516,7 +523,13 @@ hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, 
                      nl, t.tile, tiles, ntiles);
   hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st, tiles,
                      ntiles, p32, tbox);
-  out = TargetsDev{p64, p32, tiles, ntiles, tbox, i0, lay.max_tiles};
+  const P2PSched sched{reinterpret_cast<uint32_t*>(ws + lay.sched_cnt),
+                       reinterpret_cast<uint32_t*>(ws + lay.sched_poff),
+                       reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
+                       reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
+                       reinterpret_cast<double2*>(ws + lay.sched_partial),
+                       reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp};
+  out = TargetsDev{p64, p32, tiles, ntiles, tbox, toff, i0, lay.max_tiles, sched};
   return hipGetLastError();
 }
 

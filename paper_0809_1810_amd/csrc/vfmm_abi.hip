@@ -103,7 +103,8 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.count_len = 256 * L.sort_blocks;
   const int64_t nonempty = n < L.nleaves ? n : L.nleaves;
   L.max_tiles = (n + kTileMin - 1) / kTileMin + nonempty;  // any tunable tile size fits
-  const int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  if (scan_src < L.max_tiles + 1) scan_src = L.max_tiles + 1;
   const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
   const int64_t nbox = n_boxes_2_to(levels);
   size_t off = 0;
@@ -121,6 +122,12 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.tiles = take(size_t(L.max_tiles) * sizeof(Tile));
   L.ntiles = take(4);
   L.tile_box = take(size_t(L.max_tiles) * sizeof(float4));
+  L.sched_cnt = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_poff = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_soff = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
+  L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
+  L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
@@ -285,7 +292,8 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   L.count_len = 256 * L.sort_blocks;
   const int64_t nonempty = nt < L.nleaves ? nt : L.nleaves;
   L.max_tiles = (nt + kTileMin - 1) / kTileMin + nonempty;
-  const int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
+  if (scan_src < L.max_tiles + 1) scan_src = L.max_tiles + 1;
   const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
@@ -300,6 +308,12 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   L.tiles = take(size_t(L.max_tiles) * sizeof(Tile));
   L.ntiles = take(4);
   L.tile_box = take(size_t(L.max_tiles) * sizeof(float4));
+  L.sched_cnt = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_poff = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_soff = take(size_t(L.max_tiles + 1) * 4);
+  L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
+  L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
+  L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
   L.part64 = take(size_t(nt) * sizeof(Part64));
   L.part32 = take(size_t(nt) * sizeof(Part32));
   L.total = off;
