@@ -89,7 +89,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="clusters_1m")
     ap.add_argument("--p", type=int, default=None, help="override the tuned expansion order")
     ap.add_argument("--levels", type=int, default=None, help="override the tuned level")
