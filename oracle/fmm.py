@@ -24,6 +24,11 @@ The method (Cruz & Barba 2008, Sections 3.1-3.3):
   its parent (from level 3 on) plus the M2L of every box of its interaction
   list; finally L2P at the leaves plus P2P.
 
+Distance cut-off (optional, ``radius`` > 0): Section 4.1 bounds the error of
+using the singular kernel for far pairs by the distance a between them; with a
+radius a, far pairs closer than a also use the regularised kernel, added as the
+correction Gamma (K_sigma - K') to the expansion result.
+
 Readings: p terms (indices 0 .. p-1) for both ME and LE (eq. 21; the p+1 upper
 limits printed for M2L and M2M are taken as the same truncation); M2L starts at
 level 2 (Section 3.3.3); with L <= 1 there is no far field and the result is the
@@ -250,9 +255,34 @@ def near_field(x, y, gamma, sigma, tree: Tree, targets):
     return nu, nv
 
 
+def cutoff_correction(x, y, gamma, sigma, tree: Tree, xe, ye, ex, ey, radius):
+    """Distance cut-off of the near field (the distance a of Section 4.1): for
+    every evaluation point (xe, ye) in leaf (ex, ey) and every particle outside
+    that leaf's local list closer than ``radius``, the regularised kernel (eq. 6)
+    replaces the singular one (eq. 27) that the expansions carry, i.e. the sum
+    adds Gamma_j (K_sigma - K')(z - z_j).  Brute force over all particles."""
+    cu = np.zeros(len(xe)); cv = np.zeros(len(xe))
+    if radius <= 0.0 or len(xe) == 0:
+        return cu, cv
+    cs = max(1, (1 << 21) // max(1, len(x)))
+    for s in range(0, len(xe), cs):
+        sl = slice(s, s + cs)
+        dx = xe[sl, None] - x[None, :]; dy = ye[sl, None] - y[None, :]
+        far = (np.abs(ex[sl, None] - tree.ix[None, :]) > 1) | (np.abs(ey[sl, None] - tree.iy[None, :]) > 1)
+        close = far & (dx * dx + dy * dy < radius * radius)
+        ru, rv = regularized_kernel(dx, dy, sigma)
+        su, sv = singular_kernel(dx, dy)
+        cu[sl] = np.where(close, ru - su, 0.0) @ gamma
+        cv[sl] = np.where(close, rv - sv, 0.0) @ gamma
+    return cu, cv
+
+
 def fmm_velocity(x, y, gamma, sigma, p, levels, domain=None, targets=None,
-                 keep_expansions=False) -> FMMResult:
-    """The paper's FMM evaluation of eq. 9 at all particles (or at ``targets``)."""
+                 keep_expansions=False, radius=0.0) -> FMMResult:
+    """The paper's FMM evaluation of eq. 9 at all particles (or at ``targets``).
+
+    ``radius`` > 0 adds the distance cut-off of the near field
+    (``cutoff_correction``), counted in the near part."""
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
     gamma = np.asarray(gamma, np.float64)
     z = x + 1j * y
@@ -271,15 +301,19 @@ def fmm_velocity(x, y, gamma, sigma, p, levels, domain=None, targets=None,
             fu[sel] = w.real
             fv[sel] = -w.imag
     nu, nv = near_field(x, y, gamma, sigma, tree, tidx)
+    cu, cv = cutoff_correction(x, y, gamma, sigma, tree, x[tidx], y[tidx], tree.ix[tidx],
+                               tree.iy[tidx], radius)
+    nu = nu + cu; nv = nv + cv
     res = FMMResult(nu + fu, nv + fv, nu, nv, fu, fv, tidx, tree)
     if keep_expansions:
         res.me = me; res.le = le
     return res
 
 
-def hybrid_velocity(x, y, gamma, sigma, levels, domain=None, targets=None):
-    """The p -> infinity limit of the FMM: eq. 6 inside the leaf's local list and
-    the singular kernel (eq. 27) everywhere else (Section 4 opening)."""
+def hybrid_velocity(x, y, gamma, sigma, levels, domain=None, targets=None, radius=0.0):
+    """The p -> infinity limit of the FMM: eq. 6 inside the leaf's local list (and,
+    with ``radius`` > 0, for every pair closer than radius) and the singular
+    kernel (eq. 27) everywhere else (Section 4 opening)."""
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
     g = np.asarray(gamma, np.float64)
     root = qt.root_square(x, y, domain)
@@ -291,6 +325,8 @@ def hybrid_velocity(x, y, gamma, sigma, levels, domain=None, targets=None):
         ti = tidx[s:s + cs]
         dx = x[ti, None] - x[None, :]; dy = y[ti, None] - y[None, :]
         near = (np.abs(ix[ti, None] - ix[None, :]) <= 1) & (np.abs(iy[ti, None] - iy[None, :]) <= 1)
+        if radius > 0.0:
+            near = near | (dx * dx + dy * dy < radius * radius)
         ru, rv = regularized_kernel(dx, dy, sigma)
         su, sv = singular_kernel(dx, dy)
         ku = np.where(near, ru, su); kv = np.where(near, rv, sv)
@@ -309,7 +345,7 @@ def inside_root(xe, ye, root):
     return (xe >= x0) & (xe <= x0 + s) & (ye >= y0) & (ye <= y0 + s)
 
 
-def fmm_velocity_at(x, y, gamma, sigma, p, levels, xe, ye, domain=None) -> FMMResult:
+def fmm_velocity_at(x, y, gamma, sigma, p, levels, xe, ye, domain=None, radius=0.0) -> FMMResult:
     """The FMM of eq. 10 evaluated at separate points (eq. 8) instead of at the
     particles (eq. 9).
 
@@ -318,7 +354,8 @@ def fmm_velocity_at(x, y, gamma, sigma, p, levels, xe, ye, domain=None) -> FMMRe
     regularised kernel over the particles of that leaf's local list (a particle
     at the point itself contributes zero, the limit of eq. 6), its far field the
     L2P of that leaf's LE.  Points outside the closed root square have no leaf
-    whose expansions converge there: their velocity is NaN.
+    whose expansions converge there: their velocity is NaN.  ``radius`` adds
+    the distance cut-off (``cutoff_correction``) to the near part.
     """
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
     gamma = np.asarray(gamma, np.float64)
@@ -350,6 +387,9 @@ def fmm_velocity_at(x, y, gamma, sigma, p, levels, xe, ye, domain=None) -> FMMRe
             w = l2p(le[L][box], qt.box_centre(tree.root, L, *box), ze[ks])
             fu[ks] = w.real
             fv[ks] = -w.imag
+    okk = np.nonzero(ok)[0]
+    cu, cv = cutoff_correction(x, y, gamma, sigma, tree, xe[okk], ye[okk], ex[okk], ey[okk], radius)
+    nu[okk] += cu; nv[okk] += cv
     bad = ~ok
     for a in (nu, nv, fu, fv):
         a[bad] = np.nan
