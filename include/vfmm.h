@@ -355,6 +355,26 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream
 /* Releases the plan and its graph (not the workspace).  NULL is ignored. */
 void vfmm_batch_destroy(vfmm_batch_t batch);
 
+/* Distance cut-off of the near field (Section 4.1: the error of taking the
+ * singular kernel for a far pair is bounded through the distance a of the
+ * pair).  For later evaluations of this tree (vfmm_fmm_velocity*,
+ * vfmm_fmm_velocity_at), a particle outside the target's local list but
+ * closer than the radius a also interacts through the regularised kernel
+ * (eq. 6): Gamma (K_sigma - K') is added to the expansion result.
+ *   radius = 0 (the default): the paper's split (local list only);
+ *   radius > 0: a = min(radius, 2 w_L), w_L the leaf side (every particle
+ *               closer than 2 w_L lies in the local list or in the ring of
+ *               leaves at distance 2, which is searched);
+ *   radius < 0 (VFMM_NEAR_RADIUS_AUTO): a = min(r_p, 2 w_L) with r_p the
+ *               distance beyond which exp(-r^2 / 2 sigma^2) is below half an
+ *               ulp of the evaluation's precision (6 sigma in FP32, sqrt(76)
+ *               sigma in FP64), so that up to 2 w_L no kernel substitution
+ *               error remains at that precision.
+ * The batched evaluation always uses the paper's split.
+ * Errors: VFMM_ERR_INVALID_ARG (NULL tree, radius not finite). */
+#define VFMM_NEAR_RADIUS_AUTO (-1.0)
+vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t tree, double radius);
+
 /* ---------------------------------------------------------------------------
  * Tuning (process-wide settings chosen by the autotuner).
  *   VFMM_TUNE_P2P_TILE : particles per near-field tile for trees built from now

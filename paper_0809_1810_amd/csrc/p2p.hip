@@ -32,6 +32,14 @@
 // Coordinates are box-local; the target is shifted once per source leaf by the
 // exact centre offset.
 //
+// Distance cut-off (optional; the distance a of Section 4.1): the chunk
+// sequence also holds the ring of leaves at distance 2, whose particles the
+// expansions already carry with the singular kernel; a ring chunk whose box
+// gap to the target tile is below the radius adds Gamma (K_sigma - K') for its
+// pairs closer than the radius (Gamma exp(-r^2 / 2 sigma^2) / r^2 in complex
+// form); the radius is clamped to 2 w_L, the distance beyond which no particle
+// is outside the ring and the local list.
+//
 // Far chunks: when the bounding boxes of the target tile and of a source chunk
 // are more than r_c apart, every pair has exp(-r^2 / 2 sigma^2) below half an
 // ulp of 1 (r_c^2 = 36 sigma^2 in FP32, 76 sigma^2 in FP64), so 1 - exp rounds
@@ -51,17 +59,45 @@ namespace vfmm {
 
 namespace {
 
-// The local list of a leaf, row by row: in row sy the leaves lo .. hi (its
-// x neighbours clipped to the level) hold the consecutive chunks
-// tile_off[sy m + lo] .. tile_off[sy m + hi + 1] - 1.
-__device__ __forceinline__ uint32_t local_chunks(int leaf, int levels,
-                                                 const uint32_t* __restrict__ tile_off) {
+// The chunk sequence of a target leaf (bx, by) is a list of segments, each a
+// run of consecutive leaves lo .. hi of one row sy, whose chunks are
+// tile_off[sy m + lo] .. tile_off[sy m + hi + 1] - 1:
+//   s = 0, 1, 2: the local list, rows by - 1 .. by + 1, leaves bx - 1 .. bx + 1;
+//   with the distance cut-off, the ring of leaves at distance 2:
+//   s = 3: row by - 2, leaves bx - 2 .. bx + 2;  s = 4 .. 9: rows by - 1, by,
+//   by + 1, leaf bx - 2 then leaf bx + 2;  s = 10: row by + 2, bx - 2 .. bx + 2;
+// all clipped to the level.  Returns false for an empty segment.
+__device__ __forceinline__ bool segment(int s, int bx, int by, int m, int& sy, int& lo, int& hi) {
+  int d0, d1;
+  if (s < 3) {
+    sy = by - 1 + s;
+    d0 = -1;
+    d1 = 1;
+  } else if (s == 3 || s == 10) {
+    sy = s == 3 ? by - 2 : by + 2;
+    d0 = -2;
+    d1 = 2;
+  } else {
+    const int k = s - 4;
+    sy = by - 1 + (k >> 1);
+    d0 = d1 = (k & 1) ? 2 : -2;
+  }
+  lo = bx + d0 < 0 ? 0 : bx + d0;
+  hi = bx + d1 > m - 1 ? m - 1 : bx + d1;
+  return sy >= 0 && sy < m && lo <= hi;
+}
+
+constexpr int kSegNear = 3, kSegRing = 11;
+
+__device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int nseg,
+                                                    const uint32_t* __restrict__ tile_off) {
   const int m = 1 << levels;
   const int bx = leaf & (m - 1), by = leaf >> levels;
-  const int lo = bx > 0 ? bx - 1 : 0, hi = bx < m - 1 ? bx + 1 : m - 1;
   uint32_t c = 0;
-  for (int sy = by > 0 ? by - 1 : 0; sy <= by + 1 && sy < m; ++sy)
-    c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
+  for (int s = 0; s < nseg; ++s) {
+    int sy, lo, hi;
+    if (segment(s, bx, by, m, sy, lo, hi)) c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
+  }
   return c;
 }
 
@@ -70,13 +106,13 @@ __device__ __forceinline__ uint32_t local_chunks(int leaf, int levels,
 __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ ttiles,
                                                      const int32_t* __restrict__ tntiles,
                                                      const uint32_t* __restrict__ tile_off,
-                                                     int levels, int64_t max_tiles,
+                                                     int levels, int nseg, int64_t max_tiles,
                                                      uint32_t* __restrict__ cnt,
                                                      uint64_t* __restrict__ bsum) {
   __shared__ uint64_t red[256];
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
   uint32_t c = 0;
-  if (t < *tntiles) c = local_chunks(ttiles[t].leaf, levels, tile_off);
+  if (t < *tntiles) c = sequence_chunks(ttiles[t].leaf, levels, nseg, tile_off);
   if (t <= max_tiles) cnt[t] = c;
   red[threadIdx.x] = c;
   __syncthreads();
@@ -182,7 +218,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
     const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts,
     double2* __restrict__ partial, const double* __restrict__ root, int levels, int p,
     const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
-    int parts_mask, double* __restrict__ u, double* __restrict__ v) {
+    int nseg, double cut2, int parts_mask, double* __restrict__ u, double* __restrict__ v) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   const int wpb = blockDim.x >> 6;
   const int nwaves = gridDim.x * wpb;
@@ -191,6 +227,11 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
   const int m = 1 << levels;
   const double w = root[3];
   const int np_total = int(*nparts);
+  // distance cut-off radius^2, at most (2 w)^2: only the ring of leaves at
+  // distance 2 is searched, and every farther particle is >= 2 w away
+  const double rc2d = cut2 < 4.0 * w * w ? cut2 : 4.0 * w * w;
+  const float rc2f = float(rc2d);
+  const R rc2 = R(rc2d);
   for (int pi = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
        pi < np_total; pi += nwaves) {
     // part and tile fields are wave-uniform: keep them in scalar registers so
@@ -213,13 +254,14 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
     if (parts_mask & 1) {
       const R tiny = R(w * w * 0x1p-80);
       const float4 tb = ttile_box[pt_tile];
-      const int lo = bx > 0 ? bx - 1 : 0, hi = bx < m - 1 ? bx + 1 : m - 1;
       Acc32 au{0.f, 0.f}, av{0.f, 0.f};
-      // chunks [v0, v1) of the sequence row by - 1, row by, row by + 1
-      uint32_t vb = 0;  // sequence index of the current row's first chunk
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int sy = by + oy;
-        if (sy < 0 || sy >= m) continue;
+      // chunks [v0, v1) of the segment sequence
+      uint32_t vb = 0;  // sequence index of the current segment's first chunk
+      for (int sg = 0; sg < nseg && vb < v1; ++sg) {
+        int sy, lo, hi;
+        if (!segment(sg, bx, by, m, sy, lo, hi)) continue;
+        const bool ring = sg >= kSegNear;
+        const int oy = sy - by;
         const uint32_t ra = tile_off[sy * m + lo], rb = tile_off[sy * m + hi + 1];
         const uint32_t len = rb - ra;
         const uint32_t cl = v0 > vb ? v0 - vb : 0u;
@@ -247,7 +289,20 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
             const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
             R cu = R(0), cv = R(0);
             const float gap2 = gx * gx + gy * gy;
-            if (gap2 > far2) {
+            if (ring) {
+              // beyond the local list: add Gamma (K_sigma - K') for r^2 < rc2
+              if (gap2 >= rc2f) continue;
+#pragma unroll 4
+              for (int32_t j = j0 + grp; j < j1; j += LPT) {
+                const auto s = part[j];
+                const R dx = tx - s.x;
+                const R dy = ty - s.y;
+                const R r2 = dx * dx + (dy * dy + tiny);
+                const R f = r2 < rc2 ? P2PMath<R>::gauss(s.g, r2, kexp) : R(0);
+                cu += f * dy;
+                cv -= f * dx;
+              }
+            } else if (gap2 > far2) {
 #pragma unroll 8
               for (int32_t j = j0 + grp; j < j1; j += LPT) {
                 const auto s = part[j];
@@ -353,12 +408,13 @@ __global__ void __launch_bounds__(256) k_p2p_reduce(
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, hipStream_t st) {
+hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, int nseg,
+                          hipStream_t st) {
   const P2PSched& s = tg.sched;
   const int64_t mt = tg.max_tiles;
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, levels, mt, s.cnt, s.bsum);
+                     t.tile_off, levels, nseg, mt, s.cnt, s.bsum);
   hipLaunchKernelGGL(k_sched_total, dim3(1), dim3(256), 0, st, s.bsum, nb);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
@@ -375,7 +431,7 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, hi
 
 template <typename R, int PMAX, int LPT>
 void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              double* u, double* v, hipStream_t st) {
+              int nseg, double cut2, double* u, double* v, hipStream_t st) {
   using C = typename Types<R>::C;
   using Part = typename Types<R>::Part;
   const auto* part = reinterpret_cast<const Part*>(
@@ -400,7 +456,7 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
                      part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.tiles, tg.tile_box,
                      tg.perm,
                      s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, p, le, kexp, ka,
-                     far2, ser2, parts, u, v);
+                     far2, ser2, nseg, cut2, parts, u, v);
   hipLaunchKernelGGL((k_p2p_reduce<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st,
                      tpart, tg.tiles, tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, t.root,
                      levels, p, le, parts, u, v);
@@ -408,30 +464,35 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
 
 template <typename R, int PMAX>
 void launch_l(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              double* u, double* v, hipStream_t st) {
-  if (t.tile == 16) launch_t<R, PMAX, 4>(t, tg, levels, p, sigma, parts, u, v, st);
-  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, tg, levels, p, sigma, parts, u, v, st);
-  else launch_t<R, PMAX, 1>(t, tg, levels, p, sigma, parts, u, v, st);
+              int nseg, double cut2, double* u, double* v, hipStream_t st) {
+  if (t.tile == 16) launch_t<R, PMAX, 4>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else launch_t<R, PMAX, 1>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
 }
 
 template <typename R>
 void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              double* u, double* v, hipStream_t st) {
-  if (p <= 8) launch_l<R, 8>(t, tg, levels, p, sigma, parts, u, v, st);
-  else if (p <= 16) launch_l<R, 16>(t, tg, levels, p, sigma, parts, u, v, st);
-  else if (p <= 24) launch_l<R, 24>(t, tg, levels, p, sigma, parts, u, v, st);
-  else if (p <= 32) launch_l<R, 32>(t, tg, levels, p, sigma, parts, u, v, st);
-  else launch_l<R, 40>(t, tg, levels, p, sigma, parts, u, v, st);
+              double radius, double* u, double* v, hipStream_t st) {
+  // radius 0: the paper's split; < 0: the distance beyond which the two kernels
+  // agree in this precision; the kernel clamps it to 2 w_L
+  const int nseg = radius == 0.0 ? kSegNear : kSegRing;
+  const double cut2 = radius > 0.0 ? radius * radius : P2PMath<R>::kFarSigma2 * sigma * sigma;
+  if (p <= 8) launch_l<R, 8>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else if (p <= 16) launch_l<R, 16>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else if (p <= 24) launch_l<R, 24>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else if (p <= 32) launch_l<R, 32>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  else launch_l<R, 40>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
 }
 
 }  // namespace
 
 hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
-                          double sigma, int parts, double* u, double* v, hipStream_t st) {
-  hipError_t e = build_schedule(t, tg, levels, st);
+                          double sigma, int parts, double radius, double* u, double* v,
+                          hipStream_t st) {
+  hipError_t e = build_schedule(t, tg, levels, radius == 0.0 ? kSegNear : kSegRing, st);
   if (e != hipSuccess) return e;
-  if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, u, v, st);
-  else launch_r<float>(t, tg, levels, p, sigma, parts, u, v, st);
+  if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, radius, u, v, st);
+  else launch_r<float>(t, tg, levels, p, sigma, parts, radius, u, v, st);
   return hipGetLastError();
 }
 

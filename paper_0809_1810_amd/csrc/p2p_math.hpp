@@ -32,6 +32,11 @@ template <> struct P2PMath<double> {
     return near(g, r2, kexp);
   }
   __device__ __forceinline__ static double far(double g, double r2) { return g / r2; }
+  // Gamma exp(r2 kexp) / r2: the regularised kernel minus the singular one
+  // (up to sign), for the distance cut-off beyond the local list
+  __device__ __forceinline__ static double gauss(double g, double r2, double kexp) {
+    return g * (exp(r2 * kexp) / r2);
+  }
 };
 
 template <> struct P2PMath<float> {
@@ -54,6 +59,9 @@ template <> struct P2PMath<float> {
   }
   __device__ __forceinline__ static float far(float g, float r2) {
     return g * __builtin_amdgcn_rcpf(r2);
+  }
+  __device__ __forceinline__ static float gauss(float g, float r2, float kexp) {
+    return g * __builtin_amdgcn_exp2f(r2 * kexp) * __builtin_amdgcn_rcpf(r2);
   }
 };
 

@@ -27,6 +27,7 @@ struct vfmm_tree_s {
   int pack_mode;
   int last_p;       // order / precision of the last evaluation
   int last_prec;
+  double near_radius;  // distance cut-off of the near field (0 = the paper's split)
   std::vector<hipEvent_t> ev;  // phase-timing ring: (VFMM_N_PHASES + 1) per call
   int t_slots;
   int t_used;
@@ -336,7 +337,7 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
   hipError_t e = launch_p2p_l2p(t->dev, self_targets(t->dev, t->lay), t->levels, p, prec, sigma,
-                                parts, u, v, st);
+                                parts, t->near_radius, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
   mark(6);
   return VFMM_OK;
@@ -378,7 +379,7 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   s = sweeps(t, gamma, p, precision, parts, mark, st);
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  e = launch_p2p_l2p(t->dev, tg, t->levels, p, prec, sigma, parts, u, v, st);
+  e = launch_p2p_l2p(t->dev, tg, t->levels, p, prec, sigma, parts, t->near_radius, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
   mark(6);
   return VFMM_OK;
@@ -488,6 +489,14 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t t, const double* x, const double* y,
                                    t->dev, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "vfmm_tree_rebuild");
   t->last_p = -1;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t t, double radius) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  if (std::isnan(radius) || std::isinf(radius))
+    return fail(VFMM_ERR_INVALID_ARG, "radius must be finite");
+  t->near_radius = radius < 0.0 ? -1.0 : radius;
   return VFMM_OK;
 }
 

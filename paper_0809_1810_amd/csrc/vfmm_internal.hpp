@@ -172,8 +172,11 @@ hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStr
 // (prec = kFP32, kM2L_BF16 or kM2L_FP16), then the L2L chain.
 hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t stream);
 hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+// radius: distance cut-off of the near field (0 = off, < 0 = the distance at
+// which the regularised and singular kernels agree in this precision).
 hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
-                          double sigma, int parts, double* u, double* v, hipStream_t stream);
+                          double sigma, int parts, double radius, double* u, double* v,
+                          hipStream_t stream);
 // Sorts nt evaluation points into the leaves of tree t (built with `levels`),
 // with leaf-local coordinates (NaN outside the closed root square) and tiles of
 // t.tile points.

@@ -69,6 +69,7 @@ _SIGS = {
     "vfmm_tree_destroy": (None, [C.c_void_p]),
     "vfmm_tree_rebuild": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_tree_enable_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "vfmm_tree_set_near_radius": (C.c_int32, [C.c_void_p, C.c_double]),
     "vfmm_tree_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "vfmm_mlp_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "vfmm_mlp_forward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
@@ -96,6 +97,7 @@ _SIGS = {
                                        C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
 }
 
+NEAR_RADIUS_AUTO = -1.0
 MLP_PARAMS = 4929
 N_FEATURES = 10
 
@@ -253,6 +255,12 @@ class Tree:
         _check(lib().vfmm_tree_rebuild(self._h, x.data_ptr(), y.data_ptr(), dom, _stream()),
                "vfmm_tree_rebuild")
         self._keep = (x, y)
+
+    def set_near_radius(self, radius: float):
+        """Distance cut-off of the near field for later evaluations: 0 = the
+        paper's split, > 0 = min(radius, 2 w_L), NEAR_RADIUS_AUTO = automatic."""
+        _check(lib().vfmm_tree_set_near_radius(self._h, float(radius)), "vfmm_tree_set_near_radius")
+        self.near_radius = float(radius)
 
     def enable_timing(self, max_calls: int):
         _check(lib().vfmm_tree_enable_timing(self._h, int(max_calls)), "vfmm_tree_enable_timing")
