@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--p", type=int, default=None, help="override the tuned expansion order")
     ap.add_argument("--levels", type=int, default=None, help="override the tuned level")
     ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--cutoff", action="store_true",
+                    help="with --p/--levels: use the automatic distance cut-off of the near field")
     ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -159,8 +161,10 @@ def main():
     p_plain = 20
     prec_t = vf.PRECISIONS[a.precision]
     sel_info = None
+    radius_t = 0.0
     if a.p is not None and a.levels is not None:
         p_t, L_t, selector = a.p, a.levels, "fixed"
+        radius_t = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
     else:
         from paper_0809_1810_amd import selector as S
         weights = S.load_weights()
@@ -169,7 +173,7 @@ def main():
                                reference=(ud, vd))
         torch.cuda.synchronize()
         sel_ms = (time.perf_counter() - s0) * 1e3
-        p_t, L_t = r["p"], r["levels"]
+        p_t, L_t, radius_t = r["p"], r["levels"], r["radius"]
         if r["precision"] == "fp64":
             prec_t = vf.FP64
         selector = "learned" if not r["fallback"] else "fallback"
@@ -181,10 +185,11 @@ def main():
 
     from paper_0809_1810_amd import autotune as AT
 
-    def run_path(L, p, prec, steps, warmup, timing=False):
+    def run_path(L, p, prec, steps, warmup, timing=False, radius=0.0):
         AT.apply_for(n, L)  # near-field launch shape from the autotuner's table
         override_tuning(a, vf)
         tree = vf.Tree(x, y, L, p_max=p)
+        tree.set_near_radius(radius)
         u = torch.empty(n, dtype=torch.float64, device="cuda")
         v = torch.empty(n, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
@@ -211,8 +216,8 @@ def main():
         return dict(ms=ms, wall_s=wall, phases=phases, emax=emax, erms=erms, pairs=pairs,
                     tile_waves=list(vf.get_tuning().values()))
 
-    log(f"[bench] tuned: p={p_t} L={L_t} precision={a.precision}")
-    tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True)
+    log(f"[bench] tuned: p={p_t} L={L_t} precision={a.precision} near radius={radius_t}")
+    tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True, radius=radius_t)
     log(f"[bench] tuned {tuned['ms']:.3f} ms/step emax={tuned['emax']:.3e}")
     plain = None
     if not a.no_plain:
@@ -227,7 +232,9 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": recorded_traffic(a.workload, p_t, L_t),
                 "kernel": "k_p2p_l2p<float>", "kernel_ms": round(p2p_ms, 4),
-                "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR}
+                "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR,
+                "work_counted": "local-list pairs only (cut-off ring pairs not counted)"
+                if radius_t else "local-list pairs"}
 
     # ---------------- CPU baseline: the oracle on a bounded sample of targets
     cpu = None
@@ -273,6 +280,8 @@ def main():
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
             "selector": selector, "selector_info": sel_info, "audit_targets": AUDIT_TARGETS,
             "p2p_tile_waves": tuned["tile_waves"],
+            "near_radius": ("auto: min(6 sigma, 2 w_L), distance cut-off of the near field"
+                            if radius_t < 0 else radius_t),
         },
         "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
         "roofline": roofline,
@@ -331,15 +340,18 @@ def bench_eval_points(a, torch, vf):
     ud, vd = vf.direct_velocity_at(x, y, g, P.sigma, xs, ys)
     if a.p is not None and a.levels is not None:
         p, L, prec, how = a.p, a.levels, vf.PRECISIONS[a.precision], "fixed"
+        radius = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
     else:
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights())
-        p, L = r["p"], r["levels"]
+        p, L, radius = r["p"], r["levels"], r["radius"]
         prec = vf.FP64 if r["precision"] == "fp64" else vf.PRECISIONS[a.precision]
         how = "learned" if not r["fallback"] else "fallback"
-    log(f"[bench] evaluation points: {nt} on the root square, p={p} L={L} ({how})")
+    log(f"[bench] evaluation points: {nt} on the root square, p={p} L={L} ({how}), "
+        f"near radius {radius}")
     AT.apply_for(n, L)
     override_tuning(a, vf)
     tree = vf.Tree(x, y, L, p_max=p)
+    tree.set_near_radius(radius)
     ws = torch.empty(vf.targets_workspace_bytes(nt, L), dtype=torch.uint8, device="cuda")
     u = torch.empty(nt, dtype=torch.float64, device="cuda")
     v = torch.empty(nt, dtype=torch.float64, device="cuda")
@@ -372,6 +384,7 @@ def bench_eval_points(a, torch, vf):
            "config": {"workload": f"{P.name}: N={n}, sigma={P.sigma}; {a.eval_lattice}^2 "
                                   "cell-centred lattice of evaluation points on the root square",
                       "p": p, "levels": L, "selector": how,
+                      "near_radius": "auto: min(6 sigma, 2 w_L)" if radius < 0 else radius,
                       "p2p_tile_waves": list(vf.get_tuning().values())},
            "accuracy": {"emax": emax, "erms": erms, "sample": AUDIT_TARGETS,
                         "log10_error_quantiles": {q: float(np.quantile(field, float(q)))

@@ -197,24 +197,34 @@ def conservative_choice(side, sigma, n):
 
 
 def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, audit=True,
-                     slack=0.8, targets=None, reference=None):
+                     slack=0.8, targets=None, reference=None, cutoff=True, time_reps=3):
     """Selected (p, L), audited by the FP64 direct sum on sampled targets.
 
     The network's choice is evaluated in FP32 and accepted if its error on the
     audit targets is <= slack * tol; otherwise p is raised by 2 at the same level
     (up to 20) and audited again; if FP32 still misses, the conservative choice
     is evaluated in FP64 (the FP32 floor -- rounding of positions and
-    circulations, amplified by mixed signs -- can exceed tol).  ``targets``
-    (device int64) and ``reference`` ((u, v) of the direct sum there) may be
-    supplied; otherwise n_audit targets are drawn with ``seed``.
-    Returns a dict with the choice, its precision, the audited error, the
-    network's prediction and the audit trail.
+    circulations, amplified by mixed signs -- can exceed tol).
+
+    With ``cutoff``, an accepted FP32 choice (p, L) is compared with the same p
+    one or two levels deeper with the distance cut-off of the near field
+    (Section 4.1's distance a; automatic radius, 6 sigma in FP32), for the
+    levels whose leaf side is still >= 3 sigma (so that the clamp 2 w_L does
+    not cut the radius): each such candidate is audited, the passing ones are
+    timed (median of ``time_reps`` rebuild + evaluation runs, HIP events) and
+    the fastest is kept.
+
+    ``targets`` (device int64) and ``reference`` ((u, v) of the direct sum
+    there) may be supplied; otherwise n_audit targets are drawn with ``seed``.
+    Returns a dict with the choice (p, levels, radius: 0 or NEAR_RADIUS_AUTO,
+    precision), the audited error, the network's prediction and the audit
+    trail [p, L, mode, e_max, ms].
     """
     torch = _torch()
     params, mean, std, margin = weights if weights is not None else load_weights()
     p, L, pred, fb = V.select_params(x, y, g, sigma, tol, params, mean, std, margin)
     out = {"p": p, "levels": L, "predicted_log10": pred, "fallback": fb, "audited": False,
-           "precision": "fp32", "network_choice": [p, L]}
+           "precision": "fp32", "radius": 0.0, "network_choice": [p, L]}
     if not audit:
         return out
     n = int(x.shape[0])
@@ -223,29 +233,62 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
         targets = torch.from_numpy(np.sort(rng.choice(n, min(n, n_audit), replace=False)).astype(np.int64)).cuda()
     ud, vd = reference if reference is not None else V.direct_velocity(x, y, g, sigma, targets=targets)
 
-    def run(pp, LL, prec):
+    def run(pp, LL, prec, radius=0.0, timed=False):
         t = V.Tree(x, y, LL, p_max=pp)
+        if radius:
+            t.set_near_radius(radius)
         u, v = t.velocity(g, sigma, pp, prec)
         e = V.error_metrics(u[targets].contiguous(), v[targets].contiguous(), ud, vd)[0]
+        ms = None
+        if timed:
+            times = []
+            for _ in range(time_reps):
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                t.rebuild(x, y)
+                t.velocity(g, sigma, pp, prec, out=(u, v))
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
         t.close()
-        return e
+        return e, ms
 
     trail = []
-    e = run(p, L, V.FP32)
-    trail.append([p, L, "fp32", e])
+    e, _ = run(p, L, V.FP32)
+    trail.append([p, L, "fp32", e, None])
     while e > slack * tol and p < 20:
         p = min(20, p + 2)
-        e = run(p, L, V.FP32)
-        trail.append([p, L, "fp32", e])
+        e, _ = run(p, L, V.FP32)
+        trail.append([p, L, "fp32", e, None])
     out.update(p=p, levels=L, audited=True, audit_emax=e, trail=trail)
     if e > slack * tol:
         root = V.Tree(x, y, 0, p_max=1)
         side = float(root.arrays()[0][2].item())
         root.close()
         pc, Lc = conservative_choice(side, sigma, n)
-        e = run(pc, Lc, V.FP64)
-        trail.append([pc, Lc, "fp64", e])
+        e, _ = run(pc, Lc, V.FP64)
+        trail.append([pc, Lc, "fp64", e, None])
         out.update(p=pc, levels=Lc, fallback=True, precision="fp64", audit_emax=e)
+        return out
+    if not cutoff:
+        return out
+    root = V.Tree(x, y, 0, p_max=1)
+    side = float(root.arrays()[0][2].item())
+    root.close()
+    deeper = [LL for LL in (L + 1, L + 2)
+              if LL <= min(V.MAX_LEVELS, 10) and side / 2 ** LL >= 3.0 * sigma and 4 ** LL <= 4 * n]
+    if not deeper:
+        return out
+    _, ms0 = run(p, L, V.FP32, timed=True)
+    trail[-1][4] = ms0
+    best = (ms0, L, 0.0, e)
+    for LL in deeper:
+        ec, msc = run(p, LL, V.FP32, radius=V.NEAR_RADIUS_AUTO, timed=True)
+        trail.append([p, LL, "fp32+cutoff", ec, msc])
+        if ec <= slack * tol and msc < best[0]:
+            best = (msc, LL, V.NEAR_RADIUS_AUTO, ec)
+    out.update(levels=best[1], radius=best[2], audit_emax=best[3])
     return out
 
 

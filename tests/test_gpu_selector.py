@@ -112,12 +112,13 @@ def test_particle_stats_and_features(vf):
         assert np.allclose(f, fr, rtol=1e-6, atol=1e-6)
 
 
-def _time_eval(vf, x, y, g, sigma, p, L, prec, reps=3):
+def _time_eval(vf, x, y, g, sigma, p, L, prec, reps=3, radius=0.0):
     times = []
     for _ in range(reps + 1):
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         t = vf.Tree(x, y, L, p_max=p)
+        t.set_near_radius(radius)
         t.velocity(g, sigma, p, prec)
         e1.record()
         torch.cuda.synchronize()
@@ -141,11 +142,12 @@ def test_selector_gain_over_conservative_choice(vf):
         P = S.random_instance(rng, (2 ** 13, 2 ** 17))
         x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
         r = S.select_and_audit(x, y, g, P.sigma, tol, weights=weights, n_audit=2048, seed=i)
-        print_case("selector", i=i, n=P.n, kind=P.meta["kind"], **{k: r[k] for k in ("p", "levels", "fallback", "precision")},
+        print_case("selector", i=i, n=P.n, kind=P.meta["kind"],
+                   **{k: r[k] for k in ("p", "levels", "radius", "fallback", "precision")},
                    emax=f"{r['audit_emax']:.2e}")
         assert r["audit_emax"] <= tol
         prec = vf.FP32 if r["precision"] == "fp32" else vf.FP64
-        t_sel += _time_eval(vf, x, y, g, P.sigma, r["p"], r["levels"], prec)
+        t_sel += _time_eval(vf, x, y, g, P.sigma, r["p"], r["levels"], prec, radius=r["radius"])
         probe = vf.Tree(x, y, 0, p_max=1)
         side = float(probe.arrays()[0][2].item())
         pc, Lc = S.conservative_choice(side, P.sigma, P.n)
