@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--cutoff", action="store_true",
                     help="with --p/--levels: use the automatic distance cut-off of the near field")
-    ap.add_argument("--cpu-targets", type=int, default=65536)
+    ap.add_argument("--cpu-targets", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -245,20 +245,27 @@ def main():
             threadpool_limits = None
         from oracle import fmm as OF
         ts = W.sample_targets(n, a.cpu_targets, seed=99)
-        log(f"[bench] cpu baseline: oracle FMM (p={p_t}, L={L_t}) on {len(ts)} targets")
+        # the same method as the tuned path: its effective cut-off radius
+        r_cpu = 0.0
+        if radius_t != 0.0:
+            r_auto = (6.0 if prec_t != vf.FP64 else math.sqrt(76.0)) * P.sigma
+            r_cpu = min(r_auto if radius_t < 0 else radius_t, 2.0 * side / 2 ** L_t)
+        log(f"[bench] cpu baseline: oracle FMM (p={p_t}, L={L_t}, radius={r_cpu:.4g}) "
+            f"on {len(ts)} targets")
         ctx = threadpool_limits(1) if threadpool_limits else None
         if ctx:
             ctx.__enter__()
         c0 = time.perf_counter()
-        OF.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p_t, L_t, targets=ts)
+        OF.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p_t, L_t, targets=ts, radius=r_cpu)
         cdt = time.perf_counter() - c0
         if ctx:
             ctx.__exit__(None, None, None)
         cpu = {"value": round(len(ts) / cdt, 2), "unit": "particles/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"float64 NumPy oracle FMM (p={p_t}, levels={L_t}) evaluated at "
-                         f"{len(ts)} sampled targets of the same {n}-particle workload, "
-                         f"including its full upward sweep; {cdt:.1f} s on 1 thread"}
+               "sample": f"float64 NumPy oracle FMM (p={p_t}, levels={L_t}, near cut-off "
+                         f"radius {r_cpu:.4g}) evaluated at {len(ts)} sampled targets of the "
+                         f"same {n}-particle workload, including its full upward sweep; "
+                         f"{cdt:.1f} s on 1 thread"}
         log(f"[bench] cpu {cpu['value']} particles/s")
 
     value = n / (tuned["ms"] * 1e-3)

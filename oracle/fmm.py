@@ -260,20 +260,37 @@ def cutoff_correction(x, y, gamma, sigma, tree: Tree, xe, ye, ex, ey, radius):
     every evaluation point (xe, ye) in leaf (ex, ey) and every particle outside
     that leaf's local list closer than ``radius``, the regularised kernel (eq. 6)
     replaces the singular one (eq. 27) that the expansions carry, i.e. the sum
-    adds Gamma_j (K_sigma - K')(z - z_j).  Brute force over all particles."""
+    adds Gamma_j (K_sigma - K')(z - z_j).
+
+    A particle closer than a to a point of leaf (ex, ey) lies in a leaf at
+    Chebyshev distance at most ceil(a / w_L) from it, so the candidates are the
+    members of those leaves outside the local list; each pair is then tested
+    exactly (r < a)."""
+    xe = np.asarray(xe, np.float64); ye = np.asarray(ye, np.float64)
     cu = np.zeros(len(xe)); cv = np.zeros(len(xe))
     if radius <= 0.0 or len(xe) == 0:
         return cu, cv
-    cs = max(1, (1 << 21) // max(1, len(x)))
-    for s in range(0, len(xe), cs):
-        sl = slice(s, s + cs)
-        dx = xe[sl, None] - x[None, :]; dy = ye[sl, None] - y[None, :]
-        far = (np.abs(ex[sl, None] - tree.ix[None, :]) > 1) | (np.abs(ey[sl, None] - tree.iy[None, :]) > 1)
-        close = far & (dx * dx + dy * dy < radius * radius)
+    L = tree.levels
+    m = 1 << L
+    reach = int(math.ceil(radius / qt.box_side(tree.root, L)))
+    groups = {}
+    for k in range(len(xe)):
+        groups.setdefault((int(ex[k]), int(ey[k])), []).append(k)
+    for (bx, by), ks in groups.items():
+        ks = np.asarray(ks, np.int64)
+        cand = [tree.members[(sx, sy)]
+                for sy in range(max(0, by - reach), min(m, by + reach + 1))
+                for sx in range(max(0, bx - reach), min(m, bx + reach + 1))
+                if max(abs(sx - bx), abs(sy - by)) > 1 and (sx, sy) in tree.members]
+        if not cand:
+            continue
+        sj = np.concatenate(cand)
+        dx = xe[ks, None] - x[None, sj]; dy = ye[ks, None] - y[None, sj]
+        close = dx * dx + dy * dy < radius * radius
         ru, rv = regularized_kernel(dx, dy, sigma)
         su, sv = singular_kernel(dx, dy)
-        cu[sl] = np.where(close, ru - su, 0.0) @ gamma
-        cv[sl] = np.where(close, rv - sv, 0.0) @ gamma
+        cu[ks] = np.where(close, ru - su, 0.0) @ gamma[sj]
+        cv[ks] = np.where(close, rv - sv, 0.0) @ gamma[sj]
     return cu, cv
 
 
