@@ -66,7 +66,7 @@ def p2p_pairs(leaf_start, levels):
     return int(np.sum(cnt * nb))
 
 
-def recorded_traffic(workload, p, levels):
+def recorded_traffic(workload, p, levels, radius=0.0):
     """HBM bytes per P2P launch from the committed rocprofv3 counter runs, or None
     when the kernel source or the configuration differs from the measured one."""
     import hashlib
@@ -80,7 +80,8 @@ def recorded_traffic(workload, p, levels):
         return None
     if (rec.get("p2p_source_sha256") != cur or rec.get("p2p_math_sha256") != cur_math
             or rec.get("workload") != workload
-            or rec.get("p") != p or rec.get("levels") != levels):
+            or rec.get("p") != p or rec.get("levels") != levels
+            or rec.get("near_radius", 0.0) != ("auto" if radius < 0 else radius)):
         return None
     return float(rec["traffic_bytes"])
 
@@ -96,7 +97,7 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--cutoff", action="store_true",
                     help="with --p/--levels: use the automatic distance cut-off of the near field")
-    ap.add_argument("--cpu-targets", type=int, default=32768)
+    ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -230,7 +231,7 @@ def main():
     achieved = P2P_FLOPS_PER_PAIR * tuned["pairs"] / (p2p_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": recorded_traffic(a.workload, p_t, L_t),
+                "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t),
                 "kernel": "k_p2p_l2p<float>", "kernel_ms": round(p2p_ms, 4),
                 "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR,
                 "work_counted": "local-list pairs only (cut-off ring pairs not counted)"

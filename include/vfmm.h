@@ -157,8 +157,6 @@ vfmm_status_t vfmm_targets_workspace_bytes(int64_t n_targets, int32_t levels, si
  *             levels) bytes, 256-byte aligned, caller-owned, used only by
  *             this call's kernels (separate from the tree's workspace).
  * n_targets = 0 does nothing (xt, yt, u, v, workspace may then be NULL).
- * With phase timing on, the sort of the points
- * is counted in the gather phase.
  * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_WORKSPACE, VFMM_ERR_HIP. */
 vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
                                    int32_t precision, int32_t parts, const double* xt,
@@ -231,15 +229,18 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
                                 const double* domain, void* stream);
 
 /* Phase timing.  Phases of one vfmm_fmm_velocity call, in order:
- * 0 gather circulations, 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
- * 4 M2L + L2L (levels 2..L), 5 P2P + L2P + combine.  After
+ * 0 gather circulations (and, for vfmm_fmm_velocity_at, the sort of the
+ * evaluation points), 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
+ * 4 M2L + L2L (levels 2..L), 5 near-field work schedule, 6 P2P + L2P +
+ * combine (the near-field kernel and the sum of the parts of split tiles).
+ * After
  * vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
  * next max_calls evaluations record HIP events at the phase boundaries on their
  * stream (no synchronisation).  vfmm_tree_read_timing waits for the recorded
  * events, writes ms[call * VFMM_N_PHASES + phase] (host, max_calls *
  * VFMM_N_PHASES doubles) and *n_calls (host), and starts a new recording.
  * Phases skipped by a call read 0. */
-#define VFMM_N_PHASES 6
+#define VFMM_N_PHASES 7
 vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t tree, int32_t max_calls);
 vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t tree, double* ms, int32_t* n_calls);
 

@@ -515,11 +515,14 @@ void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
 
 }  // namespace
 
+hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
+                               hipStream_t st) {
+  return build_schedule(t, tg, levels, radius == 0.0 ? kSegNear : kSegRing, st);
+}
+
 hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
                           double sigma, int parts, double radius, double* u, double* v,
                           hipStream_t st) {
-  hipError_t e = build_schedule(t, tg, levels, radius == 0.0 ? kSegNear : kSegRing, st);
-  if (e != hipSuccess) return e;
   if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, radius, u, v, st);
   else launch_r<float>(t, tg, levels, p, sigma, parts, radius, u, v, st);
   return hipGetLastError();

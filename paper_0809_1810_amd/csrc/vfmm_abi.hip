@@ -336,10 +336,13 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   s = sweeps(t, gamma, p, precision, parts, mark, st);
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  hipError_t e = launch_p2p_l2p(t->dev, self_targets(t->dev, t->lay), t->levels, p, prec, sigma,
-                                parts, t->near_radius, u, v, st);
-  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
+  const TargetsDev self = self_targets(t->dev, t->lay);
+  hipError_t e = launch_p2p_schedule(t->dev, self, t->levels, t->near_radius, st);
+  if (e != hipSuccess) return hip_fail(e, "P2P schedule");
   mark(6);
+  e = launch_p2p_l2p(t->dev, self, t->levels, p, prec, sigma, parts, t->near_radius, u, v, st);
+  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
+  mark(7);
   return VFMM_OK;
 }
 
@@ -379,9 +382,12 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   s = sweeps(t, gamma, p, precision, parts, mark, st);
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
+  e = launch_p2p_schedule(t->dev, tg, t->levels, t->near_radius, st);
+  if (e != hipSuccess) return hip_fail(e, "P2P schedule");
+  mark(6);
   e = launch_p2p_l2p(t->dev, tg, t->levels, p, prec, sigma, parts, t->near_radius, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
-  mark(6);
+  mark(7);
   return VFMM_OK;
 }
 

@@ -174,6 +174,10 @@ hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t s
 hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
 // radius: distance cut-off of the near field (0 = off, < 0 = the distance at
 // which the regularised and singular kernels agree in this precision).
+// The near-field work schedule of target set tg (launch_p2p_schedule), then
+// the near-field + L2P kernels over it (launch_p2p_l2p, same radius).
+hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
+                               hipStream_t stream);
 hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
                           double sigma, int parts, double radius, double* u, double* v,
                           hipStream_t stream);
