@@ -19,6 +19,8 @@ notation:
 * ``bounds``   -- kernel-substitution error estimate (Section 4.1, Table 1)
   and the multipole truncation bound (Section 4.2, eq. 30-31);
 * ``metrics``  -- error normalised by the maximum velocity (Section 5.1);
+* ``advect``   -- particles moved with their own velocity (eq. 5), Heun's
+  two-stage Runge-Kutta method;
 * ``mlp``      -- float64 reference of the parameter-selector network.
 
 Every function is pinned by tests under ``tests/`` against closed forms,
