@@ -376,6 +376,26 @@ void vfmm_batch_destroy(vfmm_batch_t batch);
 #define VFMM_NEAR_RADIUS_AUTO (-1.0)
 vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t tree, double radius);
 
+/* Advection of the particles with their own velocity (eq. 5, dx_i/dt = u(x_i);
+ * the viscous diffusion of eq. 1 is not included).  Heun's explicit two-stage
+ * Runge-Kutta method, `steps` times:
+ *   x* = x + dt u(x),   x <- x + (dt / 2) (u(x) + u(x*)),
+ * each stage's velocity being a vfmm_fmm_velocity evaluation (order p,
+ * `precision`, the tree's near radius) after vfmm_tree_rebuild of the tree on
+ * the stage's positions (root = their bounding square).
+ *   x, y      (device, n each, in/out): positions in input order, advanced in
+ *             place.  gamma (device, n): circulations (unchanged).
+ *   workspace (device): at least vfmm_advect_workspace_bytes(n) bytes (six
+ *             float64 arrays of n: both stages' velocities and the predictor
+ *             positions), 256-byte aligned, caller-owned.
+ * On return the tree is built on the last predictor positions.  steps = 0
+ * does nothing.
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_WORKSPACE, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_advect_workspace_bytes(int64_t n, size_t* bytes);
+vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* gamma,
+                          double sigma, int32_t p, int32_t precision, double dt, int32_t steps,
+                          void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Tuning (process-wide settings chosen by the autotuner).
  *   VFMM_TUNE_P2P_TILE : particles per near-field tile for trees built from now

@@ -498,6 +498,47 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t t, const double* x, const double* y,
   return VFMM_OK;
 }
 
+vfmm_status_t vfmm_advect_workspace_bytes(int64_t n, size_t* bytes) {
+  if (!bytes) return fail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  if (n < 1 || n > 2147483647LL) return fail(VFMM_ERR_INVALID_ARG, "n out of [1, 2^31-1]");
+  *bytes = 6 * align256(size_t(n) * sizeof(double));
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_advect(vfmm_tree_t t, double* x, double* y, const double* gamma, double sigma,
+                          int32_t p, int32_t precision, double dt, int32_t steps, void* workspace,
+                          size_t ws_bytes, void* stream) {
+  vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, VFMM_PART_ALL, x, y);
+  if (s) return s;
+  if (!std::isfinite(dt)) return fail(VFMM_ERR_INVALID_ARG, "dt must be finite");
+  if (steps < 0) return fail(VFMM_ERR_INVALID_ARG, "steps < 0");
+  if (!workspace) return fail(VFMM_ERR_INVALID_ARG, "workspace is NULL");
+  const size_t a = align256(size_t(t->n) * sizeof(double));
+  if (ws_bytes < 6 * a)
+    return fail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, 6 * a);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  char* w = static_cast<char*>(workspace);
+  double* u1 = reinterpret_cast<double*>(w);
+  double* v1 = reinterpret_cast<double*>(w + a);
+  double* u2 = reinterpret_cast<double*>(w + 2 * a);
+  double* v2 = reinterpret_cast<double*>(w + 3 * a);
+  double* xs = reinterpret_cast<double*>(w + 4 * a);
+  double* ys = reinterpret_cast<double*>(w + 5 * a);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < steps; ++k) {
+    if ((s = vfmm_tree_rebuild(t, x, y, nullptr, stream))) return s;
+    if ((s = vfmm_fmm_velocity(t, gamma, sigma, p, precision, u1, v1, stream))) return s;
+    hipError_t e = launch_heun_predict(x, y, u1, v1, t->n, dt, xs, ys, st);
+    if (e != hipSuccess) return hip_fail(e, "Heun predictor");
+    if ((s = vfmm_tree_rebuild(t, xs, ys, nullptr, stream))) return s;
+    if ((s = vfmm_fmm_velocity(t, gamma, sigma, p, precision, u2, v2, stream))) return s;
+    e = launch_heun_correct(x, y, u1, v1, u2, v2, t->n, dt, st);
+    if (e != hipSuccess) return hip_fail(e, "Heun corrector");
+  }
+  return VFMM_OK;
+}
+
 vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t t, double radius) {
   if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
   if (std::isnan(radius) || std::isinf(radius))

@@ -199,6 +199,12 @@ hipError_t launch_direct(const double* x, const double* y, const double* g, int6
 hipError_t launch_error_metrics(const double* u, const double* v, const double* ur,
                                 const double* vr, int64_t n, double* partial, double* out,
                                 hipStream_t stream);
+// Heun's method (advect.hip): x* = x + dt u; x += dt/2 (u1 + u2).
+hipError_t launch_heun_predict(const double* x, const double* y, const double* u, const double* v,
+                               int64_t n, double dt, double* xs, double* ys, hipStream_t stream);
+hipError_t launch_heun_correct(double* x, double* y, const double* u1, const double* v1,
+                               const double* u2, const double* v2, int64_t n, double dt,
+                               hipStream_t stream);
 size_t ops_bytes(int p);
 // Shared building blocks (tree.hip).
 hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st);

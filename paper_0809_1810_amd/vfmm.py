@@ -70,6 +70,10 @@ _SIGS = {
     "vfmm_tree_rebuild": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_tree_enable_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "vfmm_tree_set_near_radius": (C.c_int32, [C.c_void_p, C.c_double]),
+    "vfmm_advect_workspace_bytes": (C.c_int32, [C.c_int64, C.POINTER(C.c_size_t)]),
+    "vfmm_advect": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
+                                C.c_size_t, C.c_void_p]),
     "vfmm_tree_read_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "vfmm_mlp_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "vfmm_mlp_forward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
@@ -255,6 +259,26 @@ class Tree:
         _check(lib().vfmm_tree_rebuild(self._h, x.data_ptr(), y.data_ptr(), dom, _stream()),
                "vfmm_tree_rebuild")
         self._keep = (x, y)
+
+    def advect(self, x, y, gamma, sigma: float, p: int, dt: float, steps: int, precision=FP64,
+               workspace=None):
+        """Advance the positions x, y (device float64, in place) by `steps` Heun
+        steps with the FMM velocity (eq. 5); rebuilds this tree at every stage."""
+        torch = _torch()
+        x = _dev_f64(x, "x"); y = _dev_f64(y, "y"); gamma = _dev_f64(gamma, "gamma")
+        if int(x.shape[0]) != self.n or int(y.shape[0]) != self.n or int(gamma.shape[0]) != self.n:
+            raise ValueError("x, y and gamma must have the tree's length")
+        precision = PRECISIONS.get(precision, precision)
+        if workspace is None:
+            b = C.c_size_t(0)
+            _check(lib().vfmm_advect_workspace_bytes(self.n, C.byref(b)), "vfmm_advect_workspace_bytes")
+            workspace = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        _check(lib().vfmm_advect(self._h, x.data_ptr(), y.data_ptr(), gamma.data_ptr(), float(sigma),
+                                 int(p), int(precision), float(dt), int(steps), workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(), _stream()),
+               "vfmm_advect")
+        self._keep = (x, y)
+        return x, y
 
     def set_near_radius(self, radius: float):
         """Distance cut-off of the near field for later evaluations: 0 = the

@@ -135,3 +135,14 @@ def test_evaluation_point_calls_reject_before_device_work():
     assert l.vfmm_error_field(fake, fake, fake, fake, 4, None, fake, None) == B.ERR_INVALID_ARG
     assert l.vfmm_error_field(fake, fake, fake, fake, -1, fake, fake, None) == B.ERR_INVALID_ARG
     assert l.vfmm_error_field(fake, fake, fake, fake, 0, fake, fake, None) == 0
+
+
+def test_advect_calls_reject_before_device_work():
+    l = _lib()
+    b = C.c_size_t(0)
+    assert l.vfmm_advect_workspace_bytes(1000, C.byref(b)) == 0 and b.value >= 6 * 8000
+    assert l.vfmm_advect_workspace_bytes(0, C.byref(b)) == B.ERR_INVALID_ARG
+    fake = C.c_void_p(0x1000)
+    assert l.vfmm_advect(None, fake, fake, fake, 0.1, 5, 0, 0.01, 1, fake, 1 << 30,
+                         None) == B.ERR_INVALID_ARG
+    assert l.vfmm_tree_set_near_radius(None, 0.1) == B.ERR_INVALID_ARG
