@@ -110,6 +110,9 @@ def main():
                     help="override the autotuned near-field tile (64, 32 or 16 targets)")
     ap.add_argument("--p2p-waves", type=int, default=0,
                     help="override the autotuned near-field waves per workgroup (1, 2, 4, 8)")
+    ap.add_argument("--advect", type=int, default=0, metavar="K",
+                    help="instead of the N=1M line, time K steps of advecting the particles with "
+                         "their FMM velocity (Heun's method, two evaluations and rebuilds per step)")
     ap.add_argument("--batched", action="store_true",
                     help="instead of the N=1M line, time 256 uneven instances evaluated as one "
                          "batch (graph replay) against one call per instance")
@@ -132,6 +135,8 @@ def main():
         return bench_batched(a, torch, vf)
     if a.eval_lattice > 0:
         return bench_eval_points(a, torch, vf)
+    if a.advect > 0:
+        return bench_advect(a, torch, vf)
 
     if a.calibrate_copy_mib > 0:
         src = torch.ones(a.calibrate_copy_mib * (1 << 17), dtype=torch.float64, device="cuda")
@@ -403,6 +408,72 @@ def bench_eval_points(a, torch, vf):
                         "kernel_ms": round(p2p_ms, 4), "pairs_per_launch": pairs,
                         "flops_per_pair": P2P_FLOPS_PER_PAIR},
            "phases_ms": {k: round(float(np.mean([ph[k] for ph in phases])), 4) for k in phases[0]}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_advect(a, torch, vf):
+    """K steps of advecting the workload's particles with their own velocity
+    (eq. 5, Heun's method: per step two tree rebuilds and two evaluations),
+    tuned path (selected p, L, near radius, FP32) vs the plain FP64 path;
+    dt = 0.2 sigma / max|u|.  Accuracy: the tuned trajectory's final positions
+    against the plain path's, relative to the largest displacement."""
+    from paper_0809_1810_amd import autotune as AT
+    from paper_0809_1810_amd import selector as S
+    P = W.config(a.workload)
+    n = P.n
+    x0 = torch.from_numpy(P.x).cuda(); y0 = torch.from_numpy(P.y).cuda()
+    g = torch.from_numpy(P.gamma).cuda()
+    probe = vf.Tree(x0, y0, 0, p_max=1)
+    side = float(probe.arrays()[0][2].item())
+    probe.close()
+    if a.p is not None and a.levels is not None:
+        p, L = a.p, a.levels
+        radius = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
+    else:
+        r = S.select_and_audit(x0, y0, g, P.sigma, 1e-6, weights=S.load_weights())
+        p, L, radius = r["p"], r["levels"], r["radius"]
+    Lp = largest_level(side, P.sigma, 8.0)
+    t0 = vf.Tree(x0, y0, Lp, p_max=20)
+    u, v = t0.velocity(g, P.sigma, 20, vf.FP64)
+    umax = float(torch.hypot(u, v).max().item())
+    t0.close()
+    dt = 0.2 * P.sigma / umax
+    ws = None
+
+    def run(pp, LL, prec, rad, steps):
+        AT.apply_for(n, LL)
+        override_tuning(a, vf)
+        x = x0.clone(); y = y0.clone()
+        tree = vf.Tree(x, y, LL, p_max=pp)
+        tree.set_near_radius(rad)
+        xw = x0.clone(); yw = y0.clone()
+        tree.advect(xw, yw, g, P.sigma, pp, dt, max(1, a.warmup // 2), prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tree.advect(x, y, g, P.sigma, pp, dt, steps, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        tree.close()
+        return x, y, e0.elapsed_time(e1) / steps
+
+    K = a.advect
+    log(f"[bench] advect: {K} Heun steps, dt={dt:.3e}, tuned p={p} L={L} radius={radius}")
+    xt, yt, ms_t = run(p, L, vf.FP32, radius, K)
+    xp, yp, ms_p = run(20, Lp, vf.FP64, 0.0, K)
+    disp = float(torch.hypot(xp - x0, yp - y0).max().item())
+    dev_ = float(torch.hypot(xt - xp, yt - yp).max().item())
+    out = {"metric": "particle steps/s, advecting N=2^20 particles with their FMM velocity (Heun)",
+           "value": round(n / (ms_t * 1e-3), 1), "unit": "particle steps/s", "n_gpus": 1,
+           "steps": K, "warmup": max(1, a.warmup // 2), "ms_per_step": round(ms_t, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{P.name}: N={n}, sigma={P.sigma}, dt = 0.2 sigma / max|u| = {dt:.4g}",
+                      "p": p, "levels": L, "near_radius": "auto" if radius < 0 else radius},
+           "plain_fp64": {"ms_per_step": round(ms_p, 4), "p": 20, "levels": Lp},
+           "speedup_vs_plain": round(ms_p / ms_t, 3),
+           "accuracy": {"max_position_difference_vs_plain": dev_, "max_displacement": disp,
+                        "relative": dev_ / disp if disp > 0 else None}}
     print(json.dumps(out), flush=True)
 
 
