@@ -212,17 +212,44 @@ __device__ __forceinline__ void l2p(const typename Types<R>::C* __restrict__ L, 
   fv = double(acc.x) * sc;
 }
 
+// Pair arithmetic in the kernel's units: FP32 in units of the Gaussian width
+// (sources pre-scaled by the gather kernel), FP64 in plain units.
+template <typename R> struct PairK;
+template <> struct PairK<float> {
+  __device__ __forceinline__ float near(float g, float r2) const { return P2PMath<float>::near_s(g, r2); }
+  __device__ __forceinline__ float series(float g, float r2) const {
+    return P2PMath<float>::near_series_s(g, r2);
+  }
+  __device__ __forceinline__ float far(float g, float r2) const { return P2PMath<float>::far(g, r2); }
+  __device__ __forceinline__ float gauss(float g, float r2) const { return P2PMath<float>::gauss_s(g, r2); }
+};
+template <> struct PairK<double> {
+  double kexp;
+  __device__ __forceinline__ double near(double g, double r2) const {
+    return P2PMath<double>::near(g, r2, kexp);
+  }
+  __device__ __forceinline__ double series(double g, double r2) const { return near(g, r2); }
+  __device__ __forceinline__ double far(double g, double r2) const { return P2PMath<double>::far(g, r2); }
+  __device__ __forceinline__ double gauss(double g, double r2) const {
+    return P2PMath<double>::gauss(g, r2, kexp);
+  }
+};
+
 template <typename R, int PMAX, int LPT>
 __global__ void __launch_bounds__(512) k_p2p_l2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
-    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
-    const float4* __restrict__ ttile_box, const int32_t* __restrict__ tperm,
-    const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts,
-    double2* __restrict__ partial, const double* __restrict__ root, int levels, int p,
-    const typename Types<R>::C* __restrict__ le_leaf, R kexp, R ka, float far2, float ser2,
-    int nseg, double cut2, int parts_mask, double* __restrict__ u, double* __restrict__ v) {
+    const typename Types<R>::Part* __restrict__ tpart, const Part64* __restrict__ tpart64,
+    const Tile* __restrict__ ttiles, const float4* __restrict__ ttile_box,
+    const int32_t* __restrict__ tperm, const P2PPart* __restrict__ parts,
+    const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
+    const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::C* __restrict__ le_leaf, PairK<R> pk, double sd, float far2,
+    float ser2, int nseg, double cut2, int parts_mask, double* __restrict__ u,
+    double* __restrict__ v) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
+  // FP32: sources and targets in units of the Gaussian width (factor sd);
+  // FP64: plain units (sd = 1)
   const int wpb = blockDim.x >> 6;
   const int nwaves = gridDim.x * wpb;
   const int lane = threadIdx.x & 63;
@@ -234,7 +261,10 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
   // distance 2 is searched, and every farther particle is >= 2 w away
   const double rc2d = cut2 < 4.0 * w * w ? cut2 : 4.0 * w * w;
   const float rc2f = float(rc2d);
-  const R rc2 = R(rc2d);
+  const R rc2 = R(rc2d * sd * sd);
+  const float rc2s = float(rc2d * sd * sd);
+  const float sdf = float(sd);
+  const double wsd = w * sd;
   for (int pi = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
        pi < np_total; pi += nwaves) {
     // part and tile fields are wave-uniform: keep them in scalar registers so
@@ -250,12 +280,23 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
     const int t_count = __builtin_amdgcn_readfirstlane(tv.count);
     const bool active = tl < t_count;
     const int32_t i = t_start + (active ? tl : 0);
-    const auto tp = tpart[i];
+    R tx0, ty0;
+    if constexpr (sizeof(R) == 4) {
+      // the same rounding as the gather kernel's, so that a target at a
+      // source's position (the self pair) has an offset of exactly zero
+      const Part64 q = tpart64[i];
+      tx0 = float(q.x * sd);
+      ty0 = float(q.y * sd);
+    } else {
+      const auto q = tpart[i];
+      tx0 = q.x;
+      ty0 = q.y;
+    }
     const int bx = t_leaf & (m - 1), by = t_leaf >> levels;
 
     double nu = 0.0, nv = 0.0;
     if (parts_mask & 1) {
-      const R tiny = R(w * w * 0x1p-80);
+      const R tiny = R(wsd * wsd * 0x1p-80);
       const float4 tb = ttile_box[pt_tile];
       Acc32 au{0.f, 0.f}, av{0.f, 0.f};
       // chunks [v0, v1) of the segment sequence
@@ -272,7 +313,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
         vb += len;
         if (cl >= ch) continue;
         const uint32_t cb = ra + cl, ce = ra + ch;
-        const R ty = tp.y - R(double(oy) * w);
+        const R ty = ty0 - R(double(oy) * wsd);
         const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
         for (int sx = lo; sx <= hi; ++sx) {
           const int sl = sy * m + sx;
@@ -281,7 +322,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
           if (qa >= qb) continue;
           const int ox = sx - bx;
           // target relative to the source leaf centre
-          const R tx = tp.x - R(double(ox) * w);
+          const R tx = tx0 - R(double(ox) * wsd);
           const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
           const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
           for (uint32_t ci = qa; ci < qb; ++ci) {
@@ -303,11 +344,11 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                 if (j0 + lane < j1) {
                   const auto q = part[j0 + lane];
                   const float qx = float(q.x), qy = float(q.y);
-                  const float hx = fmaxf(0.f, fmaxf(bx0 - qx, qx - bx1));
-                  const float hy = fmaxf(0.f, fmaxf(by0 - qy, qy - by1));
+                  const float hx = fmaxf(0.f, fmaxf(bx0 * sdf - qx, qx - bx1 * sdf));
+                  const float hy = fmaxf(0.f, fmaxf(by0 * sdf - qy, qy - by1 * sdf));
                   d2 = hx * hx + hy * hy;
                 }
-                uint64_t keep = __ballot(d2 < rc2f);
+                uint64_t keep = __ballot(d2 < rc2s);
                 while (keep) {
                   const int k = __builtin_ctzll(keep);
                   keep &= keep - 1;
@@ -315,7 +356,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                   const R dx = tx - s.x;
                   const R dy = ty - s.y;
                   const R r2 = dx * dx + (dy * dy + tiny);
-                  const R f = r2 < rc2 ? P2PMath<R>::gauss(s.g, r2, kexp) : R(0);
+                  const R f = r2 < rc2 ? pk.gauss(s.g, r2) : R(0);
                   cu += f * dy;
                   cv -= f * dx;
                 }
@@ -326,7 +367,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                   const R dx = tx - s.x;
                   const R dy = ty - s.y;
                   const R r2 = dx * dx + (dy * dy + tiny);
-                  const R f = r2 < rc2 ? P2PMath<R>::gauss(s.g, r2, kexp) : R(0);
+                  const R f = r2 < rc2 ? pk.gauss(s.g, r2) : R(0);
                   cu += f * dy;
                   cv -= f * dx;
                 }
@@ -337,7 +378,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                 const auto s = part[j];
                 const R dx = tx - s.x;
                 const R dy = ty - s.y;
-                const R f = P2PMath<R>::far(s.g, dx * dx + dy * dy);
+                const R f = pk.far(s.g, dx * dx + dy * dy);
                 cu -= f * dy;
                 cv += f * dx;
               }
@@ -348,7 +389,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                 const R dx = tx - s.x;
                 const R dy = ty - s.y;
                 const R r2 = dx * dx + (dy * dy + tiny);
-                const R f = P2PMath<R>::near(s.g, r2, kexp);
+                const R f = pk.near(s.g, r2);
                 cu -= f * dy;
                 cv += f * dx;
               }
@@ -359,7 +400,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
                 const R dx = tx - s.x;
                 const R dy = ty - s.y;
                 const R r2 = dx * dx + (dy * dy + tiny);
-                const R f = P2PMath<R>::near_series(s.g, r2, kexp, ka);
+                const R f = pk.series(s.g, r2);
                 cu -= f * dy;
                 cv += f * dx;
               }
@@ -384,6 +425,8 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
         nu += __shfl_xor(nu, o, 64);
         nv += __shfl_xor(nv, o, 64);
       }
+      nu *= sd;  // back to plain units (Gamma dx / r^2 scales as 1 / sd)
+      nv *= sd;
     }
 
     if (slot >= 0) {
@@ -391,8 +434,10 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
       continue;
     }
     double fu = 0.0, fv = 0.0;
-    if ((parts_mask & 2) && levels >= 2)
+    if ((parts_mask & 2) && levels >= 2) {
+      const auto tp = tpart[i];  // plain units, reloaded rather than kept live
       l2p<R, PMAX>(le_leaf + int64_t(t_leaf) * p, tp.x, tp.y, w, p, fu, fv);
+    }
     if (active && grp == 0) {
       const int32_t o = tperm[i];
       u[o] = nu * kInv2Pi + fu;
@@ -464,15 +509,16 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
   using C = typename Types<R>::C;
   using Part = typename Types<R>::Part;
   const auto* part = reinterpret_cast<const Part*>(
-      sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32));
+      sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32s));
   const auto* tpart = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
   const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
-  const double k64 = -1.0 / (2.0 * sigma * sigma);
-  const R kexp = sizeof(R) == 8 ? R(k64) : R(k64 * 1.4426950408889634074);
+  PairK<R> pk{};
+  double sd = 1.0;
+  if constexpr (sizeof(R) == 8) pk.kexp = -1.0 / (2.0 * sigma * sigma);
+  else sd = near_scale(sigma);
   const float far2 = float(P2PMath<R>::kFarSigma2 * sigma * sigma);
   const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
-  const R ka = R(1.0 / (2.0 * sigma * sigma));
   const int wpb = tuning_waves();
   // bound on the number of parts: target tiles + min(P, chunks / K) with
   // chunks <= target tiles x source tiles and K >= kP2PMinChunks
@@ -482,10 +528,9 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
   if (waves > kP2PMaxWaves) waves = kP2PMaxWaves;
   const P2PSched& s = tg.sched;
   hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st,
-                     part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.tiles, tg.tile_box,
-                     tg.perm,
-                     s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, p, le, kexp, ka,
-                     far2, ser2, nseg, cut2, parts, u, v);
+                     part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles,
+                     tg.tile_box, tg.perm, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels,
+                     p, le, pk, sd, far2, ser2, nseg, cut2, parts, u, v);
   hipLaunchKernelGGL((k_p2p_reduce<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st,
                      tpart, tg.tiles, tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, t.root,
                      levels, p, le, parts, u, v);

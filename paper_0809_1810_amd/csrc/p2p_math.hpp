@@ -63,6 +63,23 @@ template <> struct P2PMath<float> {
   __device__ __forceinline__ static float gauss(float g, float r2, float kexp) {
     return g * __builtin_amdgcn_exp2f(r2 * kexp) * __builtin_amdgcn_rcpf(r2);
   }
+  // The same in units of the Gaussian width (r'^2 = r^2 log2(e) / (2 sigma^2)):
+  // exp(-r^2 / 2 sigma^2) = exp2(-r'^2), the exponent argument is a free
+  // operand negation; the forms return Gamma (...) / r'^2.
+  __device__ __forceinline__ static float near_s(float g, float r2) {
+    const float e = __builtin_amdgcn_exp2f(-r2);
+    return __builtin_fmaf(-g, e, g) * __builtin_amdgcn_rcpf(r2);
+  }
+  __device__ __forceinline__ static float near_series_s(float g, float r2) {
+    const float a = r2 * 0.69314718055994530942f;  // r^2 / (2 sigma^2)
+    const float ser = a * (1.0f - a * (0.5f - a * (1.0f / 6.0f - a * (1.0f / 24.0f))));
+    const float e = __builtin_amdgcn_exp2f(-r2);
+    const float om = a < 0.03125f ? ser : 1.0f - e;
+    return g * om * __builtin_amdgcn_rcpf(r2);
+  }
+  __device__ __forceinline__ static float gauss_s(float g, float r2) {
+    return g * __builtin_amdgcn_exp2f(-r2) * __builtin_amdgcn_rcpf(r2);
+  }
 };
 
 

@@ -403,12 +403,17 @@ __global__ void __launch_bounds__(256) k_tile_box(const Tile* __restrict__ tiles
 __global__ void __launch_bounds__(256) k_gather_gamma(const double* __restrict__ gamma,
                                                       const int32_t* __restrict__ perm, int64_t n,
                                                       Part64* __restrict__ p64,
-                                                      Part32* __restrict__ p32) {
+                                                      Part32* __restrict__ p32,
+                                                      Part32* __restrict__ p32s, double scale) {
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
   const double g = gamma[perm[i]];
   p64[i].g = g;
   p32[i].g = float(g);
+  if (scale > 0.0) {
+    const Part64 q = p64[i];
+    p32s[i] = Part32{float(q.x * scale), float(q.y * scale), float(g), 0.0f};
+  }
 }
 
 inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -463,6 +468,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.ntiles = reinterpret_cast<int32_t*>(ws + lay.ntiles);
   t.part64 = reinterpret_cast<Part64*>(ws + lay.part64);
   t.part32 = reinterpret_cast<Part32*>(ws + lay.part32);
+  t.part32s = reinterpret_cast<Part32*>(ws + lay.part32s);
   t.me = ws + lay.me;
   t.le = ws + lay.le;
   t.ops = ws + lay.ops;
@@ -561,9 +567,11 @@ hipError_t launch_tile_box(const Tile* tiles, const int32_t* ntiles, int64_t max
   return hipGetLastError();
 }
 
-hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, hipStream_t st) {
+hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,
+                               hipStream_t st) {
+  const double scale = sigma > 0.0 ? near_scale(sigma) : 0.0;
   hipLaunchKernelGGL(k_gather_gamma, dim3(nblocks(n, 256)), dim3(256), 0, st, gamma, t.perm, n,
-                     t.part64, t.part32);
+                     t.part64, t.part32, t.part32s, scale);
   return hipGetLastError();
 }
 

@@ -131,6 +131,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
+  L.part32s = take(size_t(n) * sizeof(Part32));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
   L.le = take(size_t(nbox) * p_max * sizeof(double2));
   L.ops = take(ops_bytes(p_max));
@@ -238,12 +239,13 @@ struct Marks {
 
 // Circulations into the sorted particles, then the upward and downward sweeps
 // (Fig. 3): operator tables, P2M, M2M, M2L + L2L.  Marks phases 1 .. 5.
-vfmm_status_t sweeps(vfmm_tree_t t, const double* gamma, int32_t p, int32_t precision,
-                     int32_t parts, const Marks& mark, hipStream_t st) {
+vfmm_status_t sweeps(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
+                     int32_t precision, int32_t parts, const Marks& mark, hipStream_t st) {
   const int L = t->levels;
   // the reduced-precision M2L variants share the FP32 pipeline
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, st);
+  const bool near32 = prec == kFP32 && (parts & VFMM_PART_NEAR);
+  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, near32 ? sigma : 0.0, st);
   if (e != hipSuccess) return hip_fail(e, "gather");
   mark(1);
   const bool far = L >= 2 && (parts & VFMM_PART_FAR);
@@ -333,7 +335,7 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Marks mark(t, st);
   mark(0);
-  s = sweeps(t, gamma, p, precision, parts, mark, st);
+  s = sweeps(t, gamma, sigma, p, precision, parts, mark, st);
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
   const TargetsDev self = self_targets(t->dev, t->lay);
@@ -379,7 +381,7 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   hipError_t e = launch_build_targets(xt, yt, n_targets, t->dev, t->levels, lay,
                                       static_cast<char*>(workspace), tg, st);
   if (e != hipSuccess) return hip_fail(e, "evaluation points");
-  s = sweeps(t, gamma, p, precision, parts, mark, st);
+  s = sweeps(t, gamma, sigma, p, precision, parts, mark, st);
   if (s) return s;
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
   e = launch_p2p_schedule(t->dev, tg, t->levels, t->near_radius, st);

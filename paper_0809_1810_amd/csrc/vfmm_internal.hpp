@@ -64,6 +64,12 @@ struct __align__(16) Part32 { float x, y, g, pad; };
 
 struct Tile { int32_t leaf, start, count, pad; };
 
+// FP32 near field in units of the Gaussian width: with x' = s x,
+// s = sqrt(log2(e) / (2 sigma^2)), exp(-r^2 / 2 sigma^2) = exp2(-r'^2).
+inline __host__ __device__ double near_scale(double sigma) {
+  return sqrt(1.4426950408889634074 / (2.0 * sigma * sigma));
+}
+
 // One near-field work part: chunks [v0, v1) of the target tile's sequence of
 // source chunks (its local list row by row); slot >= 0 when the tile is split
 // and the part writes partial sums instead of the result.
@@ -95,7 +101,7 @@ struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum;
-  size_t part64, part32, me, le, ops, reduce, total;
+  size_t part64, part32, part32s, me, le, ops, reduce, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
 };
@@ -116,6 +122,7 @@ struct TreeDev {
   float4* tile_box;      // per tile: (xmin, xmax, ymin, ymax) in its leaf's local frame
   Part64* part64;
   Part32* part32;
+  Part32* part32s;       // FP32 near-field sources in units of the Gaussian width (per evaluation)
   void* me;
   void* le;
   void* ops;
@@ -162,7 +169,9 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
 // workgroup for launches.
 int tuning_tile();
 int tuning_waves();
-hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n,
+// Circulations into the sorted particle records; with sigma > 0 also the
+// FP32 near-field sources scaled by sqrt(log2(e) / (2 sigma^2)) (part32s).
+hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,
                                hipStream_t stream);
 hipError_t launch_build_ops(const TreeDev& t, int p, int prec, hipStream_t stream);
 hipError_t launch_p2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
