@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the second N = 1M input (the 1024^2 lattice)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (float64), "
                          "used to scale HBM byte counters")
@@ -307,7 +309,63 @@ def main():
         out["speedup_vs_plain"] = round(plain["ms"] / tuned["ms"], 3)
     out["phases_ms"] = {k: round(float(np.mean([ph[k] for ph in tuned["phases"]])), 4)
                         for k in tuned["phases"][0]}
+    if not a.no_lattice and a.workload == "clusters_1m":
+        out["lattice_1m"] = second_input(a, torch, vf, "lattice_1024")
     print(json.dumps(out), flush=True)
+
+
+def second_input(a, torch, vf, name):
+    """The same metric on the second N = 1M input: selection with audit (and the
+    cut-off comparison), then K timed rebuild + evaluation steps of the tuned
+    path and of the plain FP64 path; errors against the FP64 direct sum on 4096
+    sampled targets."""
+    from paper_0809_1810_amd import autotune as AT
+    from paper_0809_1810_amd import selector as S
+    P = W.config(name)
+    n = P.n
+    x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
+    g = torch.from_numpy(P.gamma).cuda()
+    probe = vf.Tree(x, y, 0, p_max=1)
+    side = float(probe.arrays()[0][2].item())
+    probe.close()
+    tg = torch.from_numpy(W.sample_targets(n, AUDIT_TARGETS, seed=2024)).cuda()
+    ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg)
+    r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights(), targets=tg,
+                           reference=(ud, vd))
+    prec = vf.FP64 if r["precision"] == "fp64" else vf.FP32
+
+    def run(L, p, pr, radius):
+        AT.apply_for(n, L)
+        override_tuning(a, vf)
+        t = vf.Tree(x, y, L, p_max=p)
+        t.set_near_radius(radius)
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        v = torch.empty(n, dtype=torch.float64, device="cuda")
+        for _ in range(a.warmup):
+            t.rebuild(x, y)
+            t.velocity(g, P.sigma, p, pr, out=(u, v))
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            t.rebuild(x, y)
+            t.velocity(g, P.sigma, p, pr, out=(u, v))
+        e1.record()
+        torch.cuda.synchronize()
+        emax, _, _ = vf.error_metrics(u[tg].contiguous(), v[tg].contiguous(), ud, vd)
+        t.close()
+        return e0.elapsed_time(e1) / a.steps, emax
+
+    ms_t, e_t = run(r["levels"], r["p"], prec, r["radius"])
+    Lp = largest_level(side, P.sigma, 8.0)
+    ms_p, e_p = run(Lp, 20, vf.FP64, 0.0)
+    return {"workload": f"{name}: {int(round(n ** 0.5))}^2 cell-centred lattice in [-1,1]^2, "
+                        f"Lamb-Oseen pair, sigma = h/0.8 = {P.sigma:.4g}",
+            "value": round(n / (ms_t * 1e-3), 1), "unit": "particles/s",
+            "ms_per_step": round(ms_t, 4), "p": r["p"], "levels": r["levels"],
+            "precision": r["precision"], "near_radius": "auto" if r["radius"] < 0 else r["radius"],
+            "emax": e_t, "audit_trail": r["trail"],
+            "plain_fp64": {"ms_per_step": round(ms_p, 4), "p": 20, "levels": Lp, "emax": e_p},
+            "speedup_vs_plain": round(ms_p / ms_t, 3)}
 
 
 def override_tuning(a, vf):
