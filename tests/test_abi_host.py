@@ -18,7 +18,7 @@ def _lib():
     try:
         return vf.lib()
     except vf.VfmmUnavailable:
-        pytest.skip("libvfmm.so not built (run __graft_entry__.build())")
+        pytest.skip("libvfmm.so not built (python -m paper_0809_1810_amd.build)")
 
 
 def test_exports_every_header_symbol():
