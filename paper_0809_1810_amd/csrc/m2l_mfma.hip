@@ -12,7 +12,10 @@
 // depends only on the multipoles of the upward sweep, so all levels run in one
 // launch.  The L2L chain (Section 3.3.3) then adds each parent's LE top-down.
 //
-// One wave computes a 32-box column tile with 32 x 32 matrix instructions:
+// A 32-box column tile is computed with 32 x 32 matrix instructions (FP32: by
+// the 4 waves of a workgroup, each taking every 4th of the 27 offsets with the
+// next offset's operands loaded while the current ones multiply, the partial
+// tiles added through LDS; 16-bit formats: by one wave):
 //   FP32  v_mfma_f32_32x32x2_f32  (A, B in float32)
 //   BF16  v_mfma_f32_32x32x16_bf16 (A, B rounded to bfloat16, RNE)
 //   FP16  v_mfma_f32_32x32x16_f16  (A, B rounded to float16, RNE)
@@ -109,6 +112,136 @@ __device__ __forceinline__ float level_scale(const uint32_t* scales, int lev) {
   return ldexpf(1.f, -e);
 }
 
+// j-th (0..26) interaction offset of a box of child class (cx, cy): the cells
+// of [cx - 3, cx + 2] x [cy - 3, cy + 2] outside [-1, 1]^2, row by row.
+__device__ __forceinline__ void nth_offset(int j, int cx, int cy, int& ox, int& oy) {
+  int c = 0;
+  for (int dy = 0; dy < 6; ++dy)
+    for (int dx = 0; dx < 6; ++dx) {
+      const int x = cx - 3 + dx, y = cy - 3 + dy;
+      if (x >= -1 && x <= 1 && y >= -1 && y <= 1) continue;
+      if (c == j) {
+        ox = x;
+        oy = y;
+        return;
+      }
+      ++c;
+    }
+}
+
+// Operands of one interaction offset for the FP32 matrix instruction: the
+// packed operator column (MT row tiles x ks_n K-steps) and the lanes' source
+// vector entries, all loaded up front so that the loads of the next offset
+// are in flight while this offset's matrix instructions run.
+template <int MT>
+struct OffsetF32 {
+  static constexpr int KMAX = 16 * MT;  // ks_n = p <= 16 MT
+  float a[MT][KMAX];
+  float b[KMAX];
+  // src points at a valid box for every lane (a lane without a source box reads
+  // box 0 and keeps zeros); k = 2 ks + hi < 2p always, so the loads carry no
+  // per-lane condition and need no branch.
+  __device__ __forceinline__ void load(const float* __restrict__ A, const float* src, bool sv,
+                                       int ks_n, int hi, int lane) {
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (ks < ks_n) {
+        const float v = src[2 * ks + hi];
+        b[ks] = sv ? v : 0.f;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64 + lane];
+      }
+    }
+  }
+};
+
+// FP32 variant with the 27 offsets of a tile split over the 4 waves of a
+// workgroup (offsets j = w, w + 4, ...), each wave software-pipelined over its
+// offsets; the four partial 32 x 32 tiles are added through LDS.
+template <int MT>
+__global__ void __launch_bounds__(256) k_m2l_mfma_f32(const float2* __restrict__ me,
+                                                      float2* __restrict__ le, int levels, int p,
+                                                      LevelTiles lt, const float* __restrict__ packA) {
+  __shared__ float part[3][MT][16][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int tile = blockIdx.x;
+  if (tile >= lt.first[levels + 1]) return;
+  int lev = 2;
+  while (tile >= lt.first[lev + 1]) ++lev;
+  const int half = 1 << (lev - 1), m = 1 << lev;
+  const int per_class = half * half;
+  const int tiles_pc = (per_class + 31) / 32;
+  const int local = tile - lt.first[lev];
+  const int c = local / tiles_pc, tt = local % tiles_pc;
+  const int cx = c & 1, cy = c >> 1;
+  const int col = lane & 31, hi = lane >> 5;
+  const int q = tt * 32 + col;
+  const bool valid = q < per_class;
+  const int qq = valid ? q : 0;
+  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
+  const int twop = 2 * p;
+  const float2* me_l = me + level_offset(lev) * p;
+  const int ks_n = p;
+
+  v16f acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  auto src_of = [&](int ox, int oy, bool& sv) {
+    const int sx = bx - ox, sy = by - oy;
+    sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+    return reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
+  };
+  auto a_of = [&](int ox, int oy) {
+    return packA + int64_t(m2l_index(ox, oy)) * MT * ks_n * 64;
+  };
+  OffsetF32<MT> cur, nxt;
+  int ox, oy;
+  bool sv;
+  nth_offset(wv, cx, cy, ox, oy);
+  cur.load(a_of(ox, oy), src_of(ox, oy, sv), sv, ks_n, hi, lane);
+  for (int j = wv; j < 27; j += 4) {
+    if (j + 4 < 27) {
+      nth_offset(j + 4, cx, cy, ox, oy);
+      const float* s2 = src_of(ox, oy, sv);
+      nxt.load(a_of(ox, oy), s2, sv, ks_n, hi, lane);
+    }
+#pragma unroll
+    for (int ks = 0; ks < OffsetF32<MT>::KMAX; ++ks) {
+      if (ks < ks_n) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.a[t][ks], cur.b[ks], acc[t], 0, 0, 0);
+      }
+    }
+    cur = nxt;
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[wv - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wv > 0 || !valid) return;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      acc[t][r] += part[0][t][r][lane] + part[1][t][r][lane] + part[2][t][r][lane];
+  float* out = reinterpret_cast<float*>(le + level_offset(lev) * p + (int64_t(by) * m + bx) * p);
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = t * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+      if (i < twop) out[i] = acc[t][r];
+    }
+}
+
 template <int MODE, int MT>
 __global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
                                                   float2* __restrict__ le, int levels, int p,
@@ -132,9 +265,8 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
   const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
   const int twop = 2 * p;
   const float2* me_l = me + level_offset(lev) * p;
-  constexpr int KPI = MODE == kModeF32 ? 2 : 16;
-  const int ks_n = (twop + KPI - 1) / KPI;
-  const float sc = MODE == kModeF32 ? 1.f : level_scale(scales, lev);
+  const int ks_n = (twop + 15) / 16;
+  const float sc = level_scale(scales, lev);
 
   v16f acc[MT];
 #pragma unroll
@@ -150,39 +282,30 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
       const float* src = reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
       const int oi = m2l_index(ox, oy);
       for (int ks = 0; ks < ks_n; ++ks) {
-        if constexpr (MODE == kModeF32) {
-          const int k = 2 * ks + hi;
-          const float b = (sv && k < twop) ? src[k] : 0.f;
-          const float* A = static_cast<const float*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
+        const int k0 = 16 * ks + 8 * hi;
+        float f[8];
 #pragma unroll
-          for (int t = 0; t < MT; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[int64_t(t) * ks_n * 64], b, acc[t], 0, 0, 0);
+        for (int s = 0; s < 8; ++s) f[s] = (sv && k0 + s < twop) ? src[k0 + s] * sc : 0.f;
+        const uint4* A = static_cast<const uint4*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
+        if constexpr (MODE == kModeBF16) {
+          v8bf b;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) b[s] = __bf16(f[s]);
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const uint4 a4 = A[int64_t(t) * ks_n * 64];
+            const v8bf a = __builtin_bit_cast(v8bf, a4);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+          }
         } else {
-          const int k0 = 16 * ks + 8 * hi;
-          float f[8];
+          v8h b;
 #pragma unroll
-          for (int s = 0; s < 8; ++s) f[s] = (sv && k0 + s < twop) ? src[k0 + s] * sc : 0.f;
-          const uint4* A = static_cast<const uint4*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
-          if constexpr (MODE == kModeBF16) {
-            v8bf b;
+          for (int s = 0; s < 8; ++s) b[s] = _Float16(f[s]);
 #pragma unroll
-            for (int s = 0; s < 8; ++s) b[s] = __bf16(f[s]);
-#pragma unroll
-            for (int t = 0; t < MT; ++t) {
-              const uint4 a4 = A[int64_t(t) * ks_n * 64];
-              const v8bf a = __builtin_bit_cast(v8bf, a4);
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
-            }
-          } else {
-            v8h b;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) b[s] = _Float16(f[s]);
-#pragma unroll
-            for (int t = 0; t < MT; ++t) {
-              const uint4 a4 = A[int64_t(t) * ks_n * 64];
-              const v8h a = __builtin_bit_cast(v8h, a4);
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[t], 0, 0, 0);
-            }
+          for (int t = 0; t < MT; ++t) {
+            const uint4 a4 = A[int64_t(t) * ks_n * 64];
+            const v8h a = __builtin_bit_cast(v8h, a4);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[t], 0, 0, 0);
           }
         }
       }
@@ -227,12 +350,23 @@ void launch_mode(const TreeDev& t, int levels, int p, const LevelTiles& lt, cons
   const unsigned blocks = unsigned((lt.first[levels + 1] + 3) / 4);
   const float2* me = static_cast<const float2*>(t.me);
   float2* le = static_cast<float2*>(t.le);
-  if (mt == 1)
-    hipLaunchKernelGGL((k_m2l_mfma<MODE, 1>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
-  else if (mt == 2)
-    hipLaunchKernelGGL((k_m2l_mfma<MODE, 2>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
-  else
-    hipLaunchKernelGGL((k_m2l_mfma<MODE, 3>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+  if constexpr (MODE == kModeF32) {
+    const unsigned tiles = unsigned(lt.first[levels + 1]);
+    const float* A = static_cast<const float*>(pack);
+    if (mt == 1)
+      hipLaunchKernelGGL((k_m2l_mfma_f32<1>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);
+    else if (mt == 2)
+      hipLaunchKernelGGL((k_m2l_mfma_f32<2>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);
+    else
+      hipLaunchKernelGGL((k_m2l_mfma_f32<3>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);
+  } else {
+    if (mt == 1)
+      hipLaunchKernelGGL((k_m2l_mfma<MODE, 1>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+    else if (mt == 2)
+      hipLaunchKernelGGL((k_m2l_mfma<MODE, 2>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+    else
+      hipLaunchKernelGGL((k_m2l_mfma<MODE, 3>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+  }
 }
 
 }  // namespace
