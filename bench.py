@@ -57,6 +57,21 @@ def largest_level(side, sigma, ratio=8.0, lmax=12):
     return L
 
 
+def m2l_pairs(levels):
+    """(box, interaction-list box) pairs of levels 2..L: children of the
+    parent's neighbours that are not adjacent, within the level's grid."""
+    total = 0
+    for lev in range(2, levels + 1):
+        m = 1 << lev
+        i = np.arange(m)
+        # along one axis: count of j in [2(i//2) - 2, 2(i//2) + 3] within [0, m)
+        lo = np.maximum(2 * (i // 2) - 2, 0); hi = np.minimum(2 * (i // 2) + 3, m - 1)
+        span = hi - lo + 1
+        near = np.minimum(i + 1, m - 1) - np.maximum(i - 1, 0) + 1
+        total += int(np.sum(np.outer(span, span) - np.outer(near, near)))
+    return total
+
+
 def p2p_pairs(leaf_start, levels):
     """Ordered (target, source) pairs of the near field, self pairs included."""
     m = 1 << levels
@@ -309,6 +324,27 @@ def main():
         out["speedup_vs_plain"] = round(plain["ms"] / tuned["ms"], 3)
     out["phases_ms"] = {k: round(float(np.mean([ph[k] for ph in tuned["phases"]])), 4)
                         for k in tuned["phases"][0]}
+    if prec_t != vf.FP64 and L_t >= 2:
+        # M2L on the matrix cores: 8 p^2 FLOP per (box, interaction box) pair,
+        # over the M2L + L2L phase (the L2L adds are a few us of it)
+        ph = out["phases_ms"]
+        m2l_flop = 8.0 * p_t * p_t * m2l_pairs(L_t)
+        ach = m2l_flop / (ph["m2l_l2l"] * 1e-3) / 1e12
+        out["m2l_roofline"] = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                               "kernel": "k_m2l_mfma_f32 (+ k_l2l_add)", "ms": ph["m2l_l2l"],
+                               "pairs": m2l_pairs(L_t), "flops_per_pair": 8 * p_t * p_t}
+        # expansion sweeps: P2M reads the sorted particles (16 B) and writes the
+        # leaf MEs; M2M reads 4 children and writes one parent per level (8 B / coefficient)
+        nb = sum(4 ** l for l in range(2, L_t + 1))
+        p2m_b = 16.0 * n + 8.0 * p_t * 4 ** L_t
+        m2m_b = 8.0 * p_t * (nb - 4 ** 2 + nb - 4 ** L_t)
+        sw_ms = ph["p2m"] + ph["m2m"]
+        out["sweeps_hbm"] = {"bound": "hbm", "achieved": round((p2m_b + m2m_b) / (sw_ms * 1e-3) / 1e9, 1),
+                             "peak": 8000.0, "unit": "GB/s",
+                             "frac": round((p2m_b + m2m_b) / (sw_ms * 1e-3) / 8e12, 4),
+                             "kernel": "k_p2m + k_m2m", "ms": round(sw_ms, 4),
+                             "bytes": p2m_b + m2m_b}
     if not a.no_lattice and a.workload == "clusters_1m":
         out["lattice_1m"] = second_input(a, torch, vf, "lattice_1024")
     print(json.dumps(out), flush=True)
