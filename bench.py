@@ -81,7 +81,18 @@ def p2p_pairs(leaf_start, levels):
     return int(np.sum(cnt * nb))
 
 
-def recorded_traffic(workload, p, levels, radius=0.0):
+def fixed_radius(a, sigma, vf):
+    if a.radius_sigma > 0:
+        return a.radius_sigma * sigma
+    return vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
+
+
+def radius_tag(radius, sigma):
+    """The near radius as recorded with measurements: "auto", 0, or in sigma (3 decimals)."""
+    return "auto" if radius < 0 else (0.0 if radius == 0 else round(radius / sigma, 3))
+
+
+def recorded_traffic(workload, p, levels, radius=0.0, sigma=1.0):
     """HBM bytes per P2P launch from the committed rocprofv3 counter runs, or None
     when the kernel source or the configuration differs from the measured one."""
     import hashlib
@@ -96,7 +107,7 @@ def recorded_traffic(workload, p, levels, radius=0.0):
     if (rec.get("p2p_source_sha256") != cur or rec.get("p2p_math_sha256") != cur_math
             or rec.get("workload") != workload
             or rec.get("p") != p or rec.get("levels") != levels
-            or rec.get("near_radius", 0.0) != ("auto" if radius < 0 else radius)):
+            or rec.get("near_radius_sigma", 0.0) != radius_tag(radius, sigma)):
         return None
     return float(rec["traffic_bytes"])
 
@@ -112,6 +123,8 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--cutoff", action="store_true",
                     help="with --p/--levels: use the automatic distance cut-off of the near field")
+    ap.add_argument("--radius-sigma", type=float, default=0.0,
+                    help="with --p/--levels: distance cut-off radius in units of sigma")
     ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -187,7 +200,7 @@ def main():
     radius_t = 0.0
     if a.p is not None and a.levels is not None:
         p_t, L_t, selector = a.p, a.levels, "fixed"
-        radius_t = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
+        radius_t = fixed_radius(a, P.sigma, vf)
     else:
         from paper_0809_1810_amd import selector as S
         weights = S.load_weights()
@@ -253,7 +266,7 @@ def main():
     achieved = P2P_FLOPS_PER_PAIR * tuned["pairs"] / (p2p_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t),
+                "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t, P.sigma),
                 "kernel": "k_p2p_l2p<float>", "kernel_ms": round(p2p_ms, 4),
                 "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR,
                 "work_counted": "local-list pairs only (cut-off ring pairs not counted)"
@@ -312,6 +325,7 @@ def main():
             "p2p_tile_waves": tuned["tile_waves"],
             "near_radius": ("auto: min(6 sigma, 2 w_L), distance cut-off of the near field"
                             if radius_t < 0 else radius_t),
+            "near_radius_sigma": radius_tag(radius_t, P.sigma),
         },
         "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
         "roofline": roofline,
@@ -447,7 +461,7 @@ def bench_eval_points(a, torch, vf):
     ud, vd = vf.direct_velocity_at(x, y, g, P.sigma, xs, ys)
     if a.p is not None and a.levels is not None:
         p, L, prec, how = a.p, a.levels, vf.PRECISIONS[a.precision], "fixed"
-        radius = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
+        radius = fixed_radius(a, P.sigma, vf)
     else:
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]
@@ -522,7 +536,7 @@ def bench_advect(a, torch, vf):
     probe.close()
     if a.p is not None and a.levels is not None:
         p, L = a.p, a.levels
-        radius = vf.NEAR_RADIUS_AUTO if a.cutoff else 0.0
+        radius = fixed_radius(a, P.sigma, vf)
     else:
         r = S.select_and_audit(x0, y0, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]

@@ -208,11 +208,13 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
 
     With ``cutoff``, an accepted FP32 choice (p, L) is compared with the same p
     one or two levels deeper with the distance cut-off of the near field
-    (Section 4.1's distance a; automatic radius, 6 sigma in FP32), for the
-    levels whose leaf side is still >= 3 sigma (so that the clamp 2 w_L does
-    not cut the radius): each such candidate is audited, the passing ones are
-    timed (median of ``time_reps`` rebuild + evaluation runs, HIP events) and
-    the fastest is kept.
+    (Section 4.1's distance a), for the levels whose leaf side is still
+    >= 3 sigma (so that the clamp 2 w_L does not cut the radius), at two
+    radii: the automatic one (6 sigma in FP32) and sigma sqrt(2 ln(1/tol)),
+    where one pair's kernel difference falls to the tolerance.  Each such
+    candidate is audited, the passing ones are timed (median of
+    ``time_reps`` rebuild + evaluation runs, HIP events) and the fastest is
+    kept.
 
     ``targets`` (device int64) and ``reference`` ((u, v) of the direct sum
     there) may be supplied; otherwise n_audit targets are drawn with ``seed``.
@@ -283,11 +285,17 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     _, ms0 = run(p, L, V.FP32, timed=True)
     trail[-1][4] = ms0
     best = (ms0, L, 0.0, e)
+    # radii: the automatic one (no kernel difference left in FP32) and the
+    # distance at which one pair's kernel difference e^{-a^2 / 2 sigma^2}
+    # falls to the tolerance
+    radii = [V.NEAR_RADIUS_AUTO, sigma * math.sqrt(2.0 * math.log(1.0 / tol))]
     for LL in deeper:
-        ec, msc = run(p, LL, V.FP32, radius=V.NEAR_RADIUS_AUTO, timed=True)
-        trail.append([p, LL, "fp32+cutoff", ec, msc])
-        if ec <= slack * tol and msc < best[0]:
-            best = (msc, LL, V.NEAR_RADIUS_AUTO, ec)
+        for rad in radii:
+            ec, msc = run(p, LL, V.FP32, radius=rad, timed=True)
+            trail.append([p, LL, "fp32+cutoff " + ("auto" if rad < 0 else f"{rad / sigma:.2f} sigma"),
+                          ec, msc])
+            if ec <= slack * tol and msc < best[0]:
+                best = (msc, LL, rad, ec)
     out.update(levels=best[1], radius=best[2], audit_emax=best[3])
     return out
 
