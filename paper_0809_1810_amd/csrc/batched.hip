@@ -11,7 +11,10 @@
 //
 // Arithmetic per instance: P2P in FP32 (as in p2p.hip); expansions (P2M, M2M,
 // M2L, L2L, L2P) in FP32 for p <= 16 and in FP64 for p > 16, on the scaled,
-// level-independent operators of expansions.hip (one table set per p).
+// level-independent operators of expansions.hip (one table set per p).  The
+// M2L runs on the matrix cores (m2l_tile.hpp): one launch for the FP32
+// instances, one for the FP64 instances, each covering all their levels; the
+// L2L chain then runs one coefficient per thread, one launch per level.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -19,6 +22,7 @@
 #include <vector>
 
 #include "../../include/vfmm.h"
+#include "m2l_tile.hpp"
 #include "p2p_math.hpp"
 
 namespace vfmm {
@@ -288,9 +292,11 @@ __global__ void __launch_bounds__(256) k_b_m2m(const BatchInst* __restrict__ I,
   else m2m_item<float>(in, lev, item, me, tab, tab_off);
 }
 
+// le[lev] += L2L(le[lev - 1]) (Section 3.3.3), the M2L part of le[lev] being
+// already there (lev >= 3); one output coefficient per item.
 template <typename R>
-__device__ void m2l_item(const BatchInst& in, int lev, int64_t item, char* me, char* le,
-                         const char* tab, const int64_t* tab_off) {
+__device__ void l2l_item(const BatchInst& in, int lev, int64_t item, char* le, const char* tab,
+                         const int64_t* tab_off) {
   using C = typename Types<R>::C;
   const int p = in.p;
   const int64_t box = item / p;
@@ -298,42 +304,67 @@ __device__ void m2l_item(const BatchInst& in, int lev, int64_t item, char* me, c
   const int m = 1 << lev;
   const int bx = int(box & (m - 1)), by = int(box >> lev);
   const OpsLayout ol = ops_layout(p);
-  const C* T = reinterpret_cast<const C*>(tab + tab_off[p] + (sizeof(R) == 8 ? ol.m2l64 : ol.m2l32));
   const C* B = reinterpret_cast<const C*>(tab + tab_off[p] + (sizeof(R) == 8 ? ol.l2l64 : ol.l2l32));
-  C acc = cmake<C>(R(0), R(0));
-  if (lev > 2) {
-    const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
-    const int q = ((by & 1) << 1) | (bx & 1);
-    const C* lp = coef<R>(le, in, lev - 1) + pb * p;
-    const C* b = B + (q * p + n) * p;
-    for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
-  }
-  const C* mel = coef<R>(me, in, lev);
-  const int px = bx >> 1, py = by >> 1;
-  const int x0 = max(2 * px - 2, 0), x1 = min(2 * px + 3, m - 1);
-  const int y0 = max(2 * py - 2, 0), y1 = min(2 * py + 3, m - 1);
-  for (int sy = y0; sy <= y1; ++sy)
-    for (int sx = x0; sx <= x1; ++sx) {
-      const int ox = bx - sx, oy = by - sy;
-      if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
-      const C* ms = mel + (int64_t(sy) * m + sx) * p;
-      const C* tr = T + (m2l_index(ox, oy) * p + n) * p;
-      for (int k = 0; k < p; ++k) cfma(acc, tr[k], ms[k]);
-    }
-  coef<R>(le, in, lev)[box * p + n] = acc;
+  const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
+  const int q = ((by & 1) << 1) | (bx & 1);
+  const C* lp = coef<R>(le, in, lev - 1) + pb * p;
+  const C* b = B + (q * p + n) * p;
+  C* out = coef<R>(le, in, lev) + box * p + n;
+  C acc = *out;
+  for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
+  *out = acc;
 }
 
-__global__ void __launch_bounds__(256) k_b_m2l(const BatchInst* __restrict__ I,
+__global__ void __launch_bounds__(256) k_b_l2l(const BatchInst* __restrict__ I,
                                                const int64_t* __restrict__ items, int count,
-                                               int lev, char* me, char* le, const char* tab,
+                                               int lev, char* le, const char* tab,
                                                const int64_t* __restrict__ tab_off) {
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
   if (t >= items[count]) return;
   const int c = find_seg(items, count, t);
   const BatchInst in = I[c];
   const int64_t item = t - items[c];
-  if (in.fp64) m2l_item<double>(in, lev, item, me, le, tab, tab_off);
-  else m2l_item<float>(in, lev, item, me, le, tab, tab_off);
+  if (in.fp64) l2l_item<double>(in, lev, item, le, tab, tab_off);
+  else l2l_item<float>(in, lev, item, le, tab, tab_off);
+}
+
+// M2L of the FP32 instances on the matrix cores: one workgroup per 32-box tile.
+// Segment s = one (instance, level) pair, its tiles seg_off[s] .. seg_off[s+1)
+// (4 classes x ceil(4^(lev-1) / 32) tiles), seg_il[s] = instance << 8 | level.
+// The FP64 instances likewise, with 16-box tiles.
+__global__ void __launch_bounds__(256) k_b_m2l_mfma(const BatchInst* __restrict__ I,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int32_t* __restrict__ seg_il, int nseg,
+                                                    char* me, char* le, const char* tab,
+                                                    const int64_t* __restrict__ tab_off) {
+  __shared__ M2LTileLds<1> sh;
+  const int64_t tile = blockIdx.x;
+  const int s = __builtin_amdgcn_readfirstlane(find_seg(seg_off, nseg, tile));
+  const int il = __builtin_amdgcn_readfirstlane(seg_il[s]);
+  const int c = il >> 8, lev = il & 255;
+  const BatchInst in = I[c];
+  const int p = __builtin_amdgcn_readfirstlane(in.p);
+  const float* A = reinterpret_cast<const float*>(tab + tab_off[p] + ops_layout(p).mfma32);
+  m2l_f32_tile<1>(coef<float>(me, in, lev), coef<float>(le, in, lev), lev, p,
+                  int(tile - seg_off[s]), A, sh);
+}
+
+__global__ void __launch_bounds__(256) k_b_m2l_mfma64(const BatchInst* __restrict__ I,
+                                                      const int64_t* __restrict__ seg_off,
+                                                      const int32_t* __restrict__ seg_il, int nseg,
+                                                      char* me, char* le, const char* tab,
+                                                      const int64_t* __restrict__ tab_off) {
+  __shared__ M2LTileLds64 sh;
+  const int64_t tile = blockIdx.x;
+  const int s = __builtin_amdgcn_readfirstlane(find_seg(seg_off, nseg, tile));
+  const int il = __builtin_amdgcn_readfirstlane(seg_il[s]);
+  const int c = il >> 8, lev = il & 255;
+  const BatchInst in = I[c];
+  const int p = __builtin_amdgcn_readfirstlane(in.p);
+  // packed operands follow the order-p table set (its size is a multiple of 256)
+  const double* A = reinterpret_cast<const double*>(tab + tab_off[p] + ops_layout(p).total);
+  m2l_f64_tile(coef<double>(me, in, lev), coef<double>(le, in, lev), lev, p,
+               int(tile - seg_off[s]), A, sh);
 }
 
 // ------------------------------------------------------------------ near field + evaluation
@@ -462,7 +493,11 @@ struct BatchPlanDev {
   BatchInst* inst;
   int64_t *part_off, *leaf_off, *ls_off, *tab_off;
   int64_t* m2m_items;  // [kBatchMaxLevels + 1][count + 1]
-  int64_t* m2l_items;
+  int64_t* l2l_items;
+  int64_t* seg_off;  // matrix-core M2L: first tile of each (instance, level), FP32
+  int32_t* seg_il;
+  int64_t* seg_off64;  // and FP64
+  int32_t* seg_il64;
   double* roots;
   uint32_t *k0, *k1, *counts, *tmp, *toff;
   int32_t *i0, *i1, *start, *ntiles;
@@ -473,8 +508,9 @@ struct BatchPlanDev {
 };
 
 hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int64_t nleaves,
-                            int64_t max_tiles, const int64_t* m2m_tot, const int64_t* m2l_tot,
-                            int maxL, hipStream_t st) {
+                            int64_t max_tiles, const int64_t* m2m_tot, const int64_t* l2l_tot,
+                            int maxL, int nseg, int64_t mfma_tiles, int nseg64,
+                            int64_t mfma_tiles64, hipStream_t st) {
   auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
   hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots);
   hipLaunchKernelGGL(k_b_keys, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, d.part_off, count,
@@ -503,10 +539,16 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
     if (m2m_tot[l] > 0)
       hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, st, d.inst,
                          d.m2m_items + int64_t(l) * (count + 1), count, l, d.me, d.tab, d.tab_off);
-  for (int l = 2; l <= maxL; ++l)
-    if (m2l_tot[l] > 0)
-      hipLaunchKernelGGL(k_b_m2l, dim3(nb(m2l_tot[l], 256)), dim3(256), 0, st, d.inst,
-                         d.m2l_items + int64_t(l) * (count + 1), count, l, d.me, d.le, d.tab,
+  if (mfma_tiles > 0)
+    hipLaunchKernelGGL(k_b_m2l_mfma, dim3(unsigned(mfma_tiles)), dim3(256), 0, st, d.inst,
+                       d.seg_off, d.seg_il, nseg, d.me, d.le, d.tab, d.tab_off);
+  if (mfma_tiles64 > 0)
+    hipLaunchKernelGGL(k_b_m2l_mfma64, dim3(unsigned(mfma_tiles64)), dim3(256), 0, st, d.inst,
+                       d.seg_off64, d.seg_il64, nseg64, d.me, d.le, d.tab, d.tab_off);
+  for (int l = 3; l <= maxL; ++l)
+    if (l2l_tot[l] > 0)
+      hipLaunchKernelGGL(k_b_l2l, dim3(nb(l2l_tot[l], 256)), dim3(256), 0, st, d.inst,
+                         d.l2l_items + int64_t(l) * (count + 1), count, l, d.le, d.tab,
                          d.tab_off);
   hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.start,
                      d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.le, i0);
@@ -523,7 +565,9 @@ struct vfmm_batch_s {
   int count;
   int64_t ntot, nleaves, max_tiles;
   int maxL;
-  int64_t m2m_tot[kBatchMaxLevels + 1], m2l_tot[kBatchMaxLevels + 1];
+  int64_t m2m_tot[kBatchMaxLevels + 1], l2l_tot[kBatchMaxLevels + 1];
+  int nseg, nseg64;              // (instance, level) segments of the matrix-core M2L
+  int64_t mfma_tiles, mfma_tiles64;  // their tiles (workgroups), FP32 and FP64
   std::vector<int> ps;  // distinct expansion orders
   int64_t tab_at[VFMM_MAX_P + 1];  // byte offset of each order's table set
   BatchPlanDev d;
@@ -548,7 +592,8 @@ vfmm_status_t bfail(vfmm_status_t s, const char* fmt, ...) {
 inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct BatchLayout {
-  size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, m2l_items, roots, k0, k1, i0, i1,
+  size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
+      seg_off64, seg_il64, roots, k0, k1, i0, i1,
       counts, tmp, toff, start, ntiles, tiles, tile_box, p32, me, le, tab, total;
   int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
   int maxL;
@@ -593,7 +638,7 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   int64_t tb = 0;
   for (int p = 0; p <= VFMM_MAX_P; ++p) {
     L.tab_at[p] = tb;
-    if (has_p[p]) tb += int64_t(al(ops_bytes(p)));
+    if (has_p[p]) tb += int64_t(al(ops_bytes(p)) + (p > 16 ? al(m2l64_pack_bytes(p)) : 0));
   }
   L.tab_bytes = tb;
   const int64_t sort_blocks = (L.ntot + kSortPerBlock - 1) / kSortPerBlock;
@@ -606,7 +651,11 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.ls_off = take(8 * (count + 1));
   L.tab_off = take(8 * (VFMM_MAX_P + 1));
   L.m2m_items = take(8 * size_t(kBatchMaxLevels + 1) * (count + 1));
-  L.m2l_items = take(8 * size_t(kBatchMaxLevels + 1) * (count + 1));
+  L.l2l_items = take(8 * size_t(kBatchMaxLevels + 1) * (count + 1));
+  L.seg_off = take(8 * (size_t(kBatchMaxLevels) * count + 1));
+  L.seg_il = take(4 * size_t(kBatchMaxLevels) * count);
+  L.seg_off64 = take(8 * (size_t(kBatchMaxLevels) * count + 1));
+  L.seg_il64 = take(4 * size_t(kBatchMaxLevels) * count);
   L.roots = take(32 * size_t(count));
   L.k0 = take(4 * L.ntot); L.k1 = take(4 * L.ntot);
   L.i0 = take(4 * L.ntot); L.i1 = take(4 * L.ntot);
@@ -650,7 +699,7 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   // host tables
   std::vector<BatchInst> hi(count);
   std::vector<int64_t> part_off(count + 1), leaf_off(count + 1), ls_off(count + 1), tab_off(VFMM_MAX_P + 1);
-  std::vector<int64_t> m2m(size_t(kBatchMaxLevels + 1) * (count + 1), 0), m2l(size_t(kBatchMaxLevels + 1) * (count + 1), 0);
+  std::vector<int64_t> m2m(size_t(kBatchMaxLevels + 1) * (count + 1), 0), l2l(size_t(kBatchMaxLevels + 1) * (count + 1), 0);
   for (int c = 0; c < count; ++c) {
     const vfmm_instance& a = inst[c];
     part_off[c + 1] = part_off[c] + a.n;
@@ -673,16 +722,32 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
     int64_t a = 0, bb = 0;
     for (int c = 0; c < count; ++c) {
       m2m[size_t(l) * (count + 1) + c] = a;
-      m2l[size_t(l) * (count + 1) + c] = bb;
+      l2l[size_t(l) * (count + 1) + c] = bb;
       const int64_t items = (int64_t(1) << (2 * l)) * inst[c].p;
       if (l >= 2 && inst[c].levels > l) a += items;
-      if (l >= 2 && inst[c].levels >= l) bb += items;
+      if (l >= 3 && inst[c].levels >= l) bb += items;
     }
     m2m[size_t(l) * (count + 1) + count] = a;
-    m2l[size_t(l) * (count + 1) + count] = bb;
+    l2l[size_t(l) * (count + 1) + count] = bb;
     b->m2m_tot[l] = a;
-    b->m2l_tot[l] = bb;
+    b->l2l_tot[l] = bb;
   }
+  std::vector<int64_t> seg_off(1, 0), seg_off64(1, 0);
+  std::vector<int32_t> seg_il, seg_il64;
+  for (int c = 0; c < count; ++c) {
+    const bool f64 = inst[c].p > 16;
+    const int bw = f64 ? 16 : 32;  // boxes per tile
+    std::vector<int64_t>& so = f64 ? seg_off64 : seg_off;
+    std::vector<int32_t>& si = f64 ? seg_il64 : seg_il;
+    for (int l = 2; l <= inst[c].levels; ++l) {
+      si.push_back(int32_t(c) << 8 | l);
+      so.push_back(so.back() + 4 * (((int64_t(1) << (2 * (l - 1))) + bw - 1) / bw));
+    }
+  }
+  b->nseg = int(seg_il.size());
+  b->mfma_tiles = seg_off.back();
+  b->nseg64 = int(seg_il64.size());
+  b->mfma_tiles64 = seg_off64.back();
   for (int c = 0; c < count; ++c) {
     bool seen = false;
     for (int q : b->ps) seen |= q == inst[c].p;
@@ -696,7 +761,11 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   d.ls_off = reinterpret_cast<int64_t*>(ws + L.ls_off);
   d.tab_off = reinterpret_cast<int64_t*>(ws + L.tab_off);
   d.m2m_items = reinterpret_cast<int64_t*>(ws + L.m2m_items);
-  d.m2l_items = reinterpret_cast<int64_t*>(ws + L.m2l_items);
+  d.l2l_items = reinterpret_cast<int64_t*>(ws + L.l2l_items);
+  d.seg_off = reinterpret_cast<int64_t*>(ws + L.seg_off);
+  d.seg_il = reinterpret_cast<int32_t*>(ws + L.seg_il);
+  d.seg_off64 = reinterpret_cast<int64_t*>(ws + L.seg_off64);
+  d.seg_il64 = reinterpret_cast<int32_t*>(ws + L.seg_il64);
   d.roots = reinterpret_cast<double*>(ws + L.roots);
   d.k0 = reinterpret_cast<uint32_t*>(ws + L.k0); d.k1 = reinterpret_cast<uint32_t*>(ws + L.k1);
   d.i0 = reinterpret_cast<int32_t*>(ws + L.i0); d.i1 = reinterpret_cast<int32_t*>(ws + L.i1);
@@ -717,7 +786,13 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   if (e == hipSuccess) e = hipMemcpy(d.ls_off, ls_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.tab_off, tab_off.data(), 8 * (VFMM_MAX_P + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.m2m_items, m2m.data(), 8 * m2m.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(d.m2l_items, m2l.data(), 8 * m2l.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.l2l_items, l2l.data(), 8 * l2l.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.seg_off, seg_off.data(), 8 * seg_off.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !seg_il.empty())
+    e = hipMemcpy(d.seg_il, seg_il.data(), 4 * seg_il.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.seg_off64, seg_off64.data(), 8 * seg_off64.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !seg_il64.empty())
+    e = hipMemcpy(d.seg_il64, seg_il64.data(), 4 * seg_il64.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete b;
     return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
@@ -736,21 +811,26 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
       TreeDev t{};
       t.ops = b->d.tab + b->tab_at[p];  // translation tables of order p
       e = launch_build_ops(t, p, kFP64, st);
+      if (e == hipSuccess && p <= 16) e = launch_pack_m2l_mfma(t, p, kFP32, st);
+      if (e == hipSuccess && p > 16)
+        e = launch_pack_m2l_mfma64(t.ops, p,
+                                   reinterpret_cast<double*>(static_cast<char*>(t.ops) + ops_bytes(p)), st);
       if (e != hipSuccess) break;
     }
     if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
     b->tables_built = true;
   }
   if (!use_graph) {
-    e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->m2l_tot,
-                         b->maxL, st);
+    e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->l2l_tot,
+                         b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st);
     return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "batch run: %s", hipGetErrorString(e));
   }
   if (!b->exec) {
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
     hipError_t le = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot,
-                                     b->m2l_tot, b->maxL, st);
+                                     b->l2l_tot, b->maxL, b->nseg, b->mfma_tiles, b->nseg64,
+                                     b->mfma_tiles64, st);
     e = hipStreamEndCapture(st, &b->graph);
     if (le != hipSuccess || e != hipSuccess)
       return bfail(VFMM_ERR_HIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));

@@ -26,13 +26,12 @@
 // For BF16/FP16 the source vectors of a level are multiplied by a power of two
 // 2^-e (e from the largest magnitude of that level's coefficients) so that
 // every input lies in [-1, 1]; the result is divided by the same power of two.
-#include "vfmm_device.hpp"
+#include "m2l_tile.hpp"
 
 namespace vfmm {
 
 namespace {
 
-typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
@@ -50,6 +49,28 @@ __device__ __forceinline__ float real_block(const double2* T, int p, int i, int 
   if (a == 0) v = b == 0 ? t.x : -t.y;
   else v = b == 0 ? t.y : t.x;
   return float(v);
+}
+
+// FP64 operands in the lane order of m2l_f64_tile: element (offset, row tile t,
+// K-step ks, lane) = R[16 t + lane % 16][(lane / 16) KS + ks], zero outside 2p.
+__global__ void __launch_bounds__(256) k_pack_f64(const double2* __restrict__ m2l64, int p,
+                                                  double* __restrict__ out) {
+  const int ks_n = m2l64_ks(p);
+  const int64_t total = int64_t(kM2LOffsets) * kM2L64Rows * ks_n * 64;
+  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= total) return;
+  const int lane = int(e % 64);
+  const int ks = int((e / 64) % ks_n);
+  const int t = int((e / (64LL * ks_n)) % kM2L64Rows);
+  const int o = int(e / (64LL * ks_n * kM2L64Rows));
+  const int i = t * 16 + (lane & 15), k = (lane >> 4) * ks_n + ks;
+  double v = 0.0;
+  if (i < 2 * p && k < 2 * p) {
+    const double2 c = m2l64[int64_t(o) * p * p + (i >> 1) * p + (k >> 1)];
+    if ((i & 1) == 0) v = (k & 1) == 0 ? c.x : -c.y;
+    else v = (k & 1) == 0 ? c.y : c.x;
+  }
+  out[e] = v;
 }
 
 __global__ void __launch_bounds__(256) k_pack_f32(const double2* __restrict__ m2l64, int p, int mt,
@@ -112,134 +133,18 @@ __device__ __forceinline__ float level_scale(const uint32_t* scales, int lev) {
   return ldexpf(1.f, -e);
 }
 
-// j-th (0..26) interaction offset of a box of child class (cx, cy): the cells
-// of [cx - 3, cx + 2] x [cy - 3, cy + 2] outside [-1, 1]^2, row by row.
-__device__ __forceinline__ void nth_offset(int j, int cx, int cy, int& ox, int& oy) {
-  int c = 0;
-  for (int dy = 0; dy < 6; ++dy)
-    for (int dx = 0; dx < 6; ++dx) {
-      const int x = cx - 3 + dx, y = cy - 3 + dy;
-      if (x >= -1 && x <= 1 && y >= -1 && y <= 1) continue;
-      if (c == j) {
-        ox = x;
-        oy = y;
-        return;
-      }
-      ++c;
-    }
-}
-
-// Operands of one interaction offset for the FP32 matrix instruction: the
-// packed operator column (MT row tiles x ks_n K-steps) and the lanes' source
-// vector entries, all loaded up front so that the loads of the next offset
-// are in flight while this offset's matrix instructions run.
-template <int MT>
-struct OffsetF32 {
-  static constexpr int KMAX = 16 * MT;  // ks_n = p <= 16 MT
-  float a[MT][KMAX];
-  float b[KMAX];
-  // src points at a valid box for every lane (a lane without a source box reads
-  // box 0 and keeps zeros); k = 2 ks + hi < 2p always, so the loads carry no
-  // per-lane condition and need no branch.
-  __device__ __forceinline__ void load(const float* __restrict__ A, const float* src, bool sv,
-                                       int ks_n, int hi, int lane) {
-#pragma unroll
-    for (int ks = 0; ks < KMAX; ++ks) {
-      if (ks < ks_n) {
-        const float v = src[2 * ks + hi];
-        b[ks] = sv ? v : 0.f;
-#pragma unroll
-        for (int t = 0; t < MT; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64 + lane];
-      }
-    }
-  }
-};
-
-// FP32 variant with the 27 offsets of a tile split over the 4 waves of a
-// workgroup (offsets j = w, w + 4, ...), each wave software-pipelined over its
-// offsets; the four partial 32 x 32 tiles are added through LDS.
+// FP32: one workgroup per tile (m2l_tile.hpp).
 template <int MT>
 __global__ void __launch_bounds__(256) k_m2l_mfma_f32(const float2* __restrict__ me,
                                                       float2* __restrict__ le, int levels, int p,
                                                       LevelTiles lt, const float* __restrict__ packA) {
-  __shared__ float part[3][MT][16][64];
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  __shared__ M2LTileLds<MT> sh;
   const int tile = blockIdx.x;
   if (tile >= lt.first[levels + 1]) return;
   int lev = 2;
   while (tile >= lt.first[lev + 1]) ++lev;
-  const int half = 1 << (lev - 1), m = 1 << lev;
-  const int per_class = half * half;
-  const int tiles_pc = (per_class + 31) / 32;
-  const int local = tile - lt.first[lev];
-  const int c = local / tiles_pc, tt = local % tiles_pc;
-  const int cx = c & 1, cy = c >> 1;
-  const int col = lane & 31, hi = lane >> 5;
-  const int q = tt * 32 + col;
-  const bool valid = q < per_class;
-  const int qq = valid ? q : 0;
-  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
-  const int twop = 2 * p;
-  const float2* me_l = me + level_offset(lev) * p;
-  const int ks_n = p;
-
-  v16f acc[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-
-  auto src_of = [&](int ox, int oy, bool& sv) {
-    const int sx = bx - ox, sy = by - oy;
-    sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
-    return reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
-  };
-  auto a_of = [&](int ox, int oy) {
-    return packA + int64_t(m2l_index(ox, oy)) * MT * ks_n * 64;
-  };
-  OffsetF32<MT> cur, nxt;
-  int ox, oy;
-  bool sv;
-  nth_offset(wv, cx, cy, ox, oy);
-  cur.load(a_of(ox, oy), src_of(ox, oy, sv), sv, ks_n, hi, lane);
-  for (int j = wv; j < 27; j += 4) {
-    if (j + 4 < 27) {
-      nth_offset(j + 4, cx, cy, ox, oy);
-      const float* s2 = src_of(ox, oy, sv);
-      nxt.load(a_of(ox, oy), s2, sv, ks_n, hi, lane);
-    }
-#pragma unroll
-    for (int ks = 0; ks < OffsetF32<MT>::KMAX; ++ks) {
-      if (ks < ks_n) {
-#pragma unroll
-        for (int t = 0; t < MT; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.a[t][ks], cur.b[ks], acc[t], 0, 0, 0);
-      }
-    }
-    cur = nxt;
-  }
-  if (wv > 0) {
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) part[wv - 1][t][r][lane] = acc[t][r];
-  }
-  __syncthreads();
-  if (wv > 0 || !valid) return;
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      acc[t][r] += part[0][t][r][lane] + part[1][t][r][lane] + part[2][t][r][lane];
-  float* out = reinterpret_cast<float*>(le + level_offset(lev) * p + (int64_t(by) * m + bx) * p);
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = t * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-      if (i < twop) out[i] = acc[t][r];
-    }
+  m2l_f32_tile<MT>(me + level_offset(lev) * p, le + level_offset(lev) * p, lev, p,
+                   tile - lt.first[lev], packA, sh);
 }
 
 template <int MODE, int MT>
@@ -388,6 +293,15 @@ hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t s
       hipLaunchKernelGGL(k_pack_16<kModeF16>, dim3(unsigned((total + 255) / 256)), dim3(256), 0,
                          st, m2l64, p, ol.mt, reinterpret_cast<uint16_t*>(ops + ol.mfma16));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_m2l_mfma64(const void* ops, int p, double* out, hipStream_t st) {
+  if (2 * p > 16 * kM2L64Rows) return hipErrorInvalidValue;
+  const double2* m2l64 =
+      reinterpret_cast<const double2*>(static_cast<const char*>(ops) + ops_layout(p).m2l64);
+  const int64_t total = int64_t(kM2LOffsets) * kM2L64Rows * m2l64_ks(p) * 64;
+  hipLaunchKernelGGL(k_pack_f64, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, m2l64, p, out);
   return hipGetLastError();
 }
 

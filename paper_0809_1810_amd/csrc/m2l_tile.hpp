@@ -1,0 +1,251 @@
+// One column tile of the M2L on the matrix cores (eq. 22): 32 boxes in FP32
+// (shared by the single-tree kernel in m2l_mfma.hip and the batched kernel in
+// batched.hip), 16 boxes in FP64 (batched kernel).
+//
+// For a target box b of child class c = (bx & 1, by & 1) the 27 interaction
+// offsets t are fixed, so l_b = sum_{t in IL(c)} R_t m_{b - t} with R_t the real
+// 2p x 2p block form of the complex M2L operator of offset t.  A tile holds 32
+// target boxes of one (level, class); the 4 waves of the workgroup take every
+// 4th of the 27 offsets, each software-pipelined (the next offset's operands
+// are loaded while this offset's v_mfma_f32_32x32x2_f32 instructions run), and
+// the 4 partial 32 x 32 tiles are added through LDS.
+//
+// Lane layout of the 32x32x2 instruction: A[i][k] with i = lane % 32 and
+// B[k][j] with j = lane % 32, K-slot k = lane / 32; D[i][j] in 16 registers per
+// lane, row i = 8 (r / 4) + 4 (lane / 32) + r % 4, column j = lane % 32.
+#pragma once
+
+#include "vfmm_device.hpp"
+
+namespace vfmm {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// j-th (0..26) interaction offset of a box of child class (cx, cy): the cells
+// of [cx - 3, cx + 2] x [cy - 3, cy + 2] outside [-1, 1]^2, row by row.
+__device__ __forceinline__ void nth_offset(int j, int cx, int cy, int& ox, int& oy) {
+  int c = 0;
+  for (int dy = 0; dy < 6; ++dy)
+    for (int dx = 0; dx < 6; ++dx) {
+      const int x = cx - 3 + dx, y = cy - 3 + dy;
+      if (x >= -1 && x <= 1 && y >= -1 && y <= 1) continue;
+      if (c == j) {
+        ox = x;
+        oy = y;
+        return;
+      }
+      ++c;
+    }
+}
+
+// Operands of one interaction offset: the packed operator column (MT row
+// tiles x ks_n K-steps) and the lanes' source vector entries.
+template <int MT>
+struct OffsetF32 {
+  static constexpr int KMAX = 16 * MT;  // ks_n = p <= 16 MT
+  float a[MT][KMAX];
+  float b[KMAX];
+  // src points at a valid box for every lane (a lane without a source box reads
+  // box 0 and keeps zeros); k = 2 ks + hi < 2p always, so the loads carry no
+  // per-lane condition and need no branch.
+  __device__ __forceinline__ void load(const float* __restrict__ A, const float* src, bool sv,
+                                       int ks_n, int hi, int lane) {
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (ks < ks_n) {
+        const float v = src[2 * ks + hi];
+        b[ks] = sv ? v : 0.f;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64 + lane];
+      }
+    }
+  }
+};
+
+// LDS of one workgroup: partial tiles of waves 1..3.
+template <int MT>
+struct M2LTileLds {
+  float part[3][MT][16][64];
+};
+
+// Tile `local` (class-major: local = class * tiles_per_class + column tile) of
+// level lev.  me_l / le_l: the level's multipole / local coefficients (4^lev
+// boxes x p, row-major box order); packA: the 40 offsets' operators packed in
+// lane order (40 x MT x p x 64 floats).  Called by all 256 threads of the
+// workgroup (it synchronises once); writes the M2L sum of the tile's boxes.
+template <int MT>
+__device__ __forceinline__ void m2l_f32_tile(const float2* __restrict__ me_l,
+                                             float2* __restrict__ le_l, int lev, int p, int local,
+                                             const float* __restrict__ packA, M2LTileLds<MT>& sh) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int half = 1 << (lev - 1), m = 1 << lev;
+  const int per_class = half * half;
+  const int tiles_pc = (per_class + 31) / 32;
+  const int c = local / tiles_pc, tt = local % tiles_pc;
+  const int cx = c & 1, cy = c >> 1;
+  const int col = lane & 31, hi = lane >> 5;
+  const int q = tt * 32 + col;
+  const bool valid = q < per_class;
+  const int qq = valid ? q : 0;
+  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
+  const int twop = 2 * p;
+  const int ks_n = p;
+
+  v16f acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+  auto src_of = [&](int ox, int oy, bool& sv) {
+    const int sx = bx - ox, sy = by - oy;
+    sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+    return reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
+  };
+  auto a_of = [&](int ox, int oy) {
+    return packA + int64_t(m2l_index(ox, oy)) * MT * ks_n * 64;
+  };
+  OffsetF32<MT> cur, nxt;
+  int ox, oy;
+  bool sv;
+  nth_offset(wv, cx, cy, ox, oy);
+  cur.load(a_of(ox, oy), src_of(ox, oy, sv), sv, ks_n, hi, lane);
+  for (int j = wv; j < 27; j += 4) {
+    if (j + 4 < 27) {
+      nth_offset(j + 4, cx, cy, ox, oy);
+      const float* s2 = src_of(ox, oy, sv);
+      nxt.load(a_of(ox, oy), s2, sv, ks_n, hi, lane);
+    }
+#pragma unroll
+    for (int ks = 0; ks < OffsetF32<MT>::KMAX; ++ks) {
+      if (ks < ks_n) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.a[t][ks], cur.b[ks], acc[t], 0, 0, 0);
+      }
+    }
+    cur = nxt;
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sh.part[wv - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wv > 0 || !valid) return;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      acc[t][r] += sh.part[0][t][r][lane] + sh.part[1][t][r][lane] + sh.part[2][t][r][lane];
+  float* out = reinterpret_cast<float*>(le_l + (int64_t(by) * m + bx) * p);
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = t * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+      if (i < twop) out[i] = acc[t][r];
+    }
+}
+
+// ---------------------------------------------------------------- FP64 variant
+//
+// v_mfma_f64_16x16x4f64: A[i][k] with i = lane % 16, k-slot lane / 16; B[k][j]
+// with j = lane % 16, k-slot lane / 16; D[i][j] in 4 double registers per lane,
+// row i = 4 r + lane / 16 (register r), column j = lane % 16.  A tile holds 16 target boxes;
+// the 2p rows of the real block form are covered by 3 row tiles of 16
+// (2p <= 48, p <= 24); K = 2p runs in KS = ceil(2p / 4) instructions, K-slot h
+// of instruction ks taking component k = h KS + ks, so that a lane reads a
+// contiguous run of its source box's coefficients.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kM2L64Rows = 3;   // 16-row tiles
+constexpr int kM2L64KsMax = 12; // p <= 24
+
+__host__ __device__ inline int m2l64_ks(int p) { return (2 * p + 3) / 4; }
+__host__ __device__ inline size_t m2l64_pack_bytes(int p) {
+  return size_t(kM2LOffsets) * kM2L64Rows * m2l64_ks(p) * 64 * sizeof(double);
+}
+
+struct M2LTileLds64 {
+  double part[3][kM2L64Rows][4][64];
+};
+
+// As m2l_f32_tile, in FP64, for tiles of 16 boxes (local = class * tiles per
+// class + column tile, tiles per class = ceil(4^(lev-1) / 16)); packA holds
+// kM2LOffsets x 3 x KS x 64 doubles.
+__device__ __forceinline__ void m2l_f64_tile(const double2* __restrict__ me_l,
+                                             double2* __restrict__ le_l, int lev, int p, int local,
+                                             const double* __restrict__ packA, M2LTileLds64& sh) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int half = 1 << (lev - 1), m = 1 << lev;
+  const int per_class = half * half;
+  const int tiles_pc = (per_class + 15) / 16;
+  const int c = local / tiles_pc, tt = local % tiles_pc;
+  const int cx = c & 1, cy = c >> 1;
+  const int col = lane & 15, h = lane >> 4;
+  const int q = tt * 16 + col;
+  const bool valid = q < per_class;
+  const int qq = valid ? q : 0;
+  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
+  const int twop = 2 * p;
+  const int ks_n = m2l64_ks(p);
+
+  v4d acc[kM2L64Rows];
+#pragma unroll
+  for (int t = 0; t < kM2L64Rows; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
+
+  for (int j = wv; j < 27; j += 4) {
+    int ox, oy;
+    nth_offset(j, cx, cy, ox, oy);
+    const int sx = bx - ox, sy = by - oy;
+    const bool sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+    const double* src = reinterpret_cast<const double*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
+    const double* A = packA + int64_t(m2l_index(ox, oy)) * kM2L64Rows * ks_n * 64 + lane;
+    double a[kM2L64Rows][kM2L64KsMax], b[kM2L64KsMax];
+#pragma unroll
+    for (int ks = 0; ks < kM2L64KsMax; ++ks) {
+      if (ks < ks_n) {
+        const int k = h * ks_n + ks;
+        const double v = src[k < twop ? k : twop - 1];
+        b[ks] = (sv && k < twop) ? v : 0.0;
+#pragma unroll
+        for (int t = 0; t < kM2L64Rows; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64];
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < kM2L64KsMax; ++ks) {
+      if (ks < ks_n) {
+#pragma unroll
+        for (int t = 0; t < kM2L64Rows; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][ks], b[ks], acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < kM2L64Rows; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sh.part[wv - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wv > 0 || !valid) return;
+  double* out = reinterpret_cast<double*>(le_l + (int64_t(by) * m + bx) * p);
+#pragma unroll
+  for (int t = 0; t < kM2L64Rows; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = t * 16 + 4 * r + h;
+      const double s = acc[t][r] + sh.part[0][t][r][lane] + sh.part[1][t][r][lane] +
+                       sh.part[2][t][r][lane];
+      if (i < twop) out[i] = s;
+    }
+}
+
+}  // namespace vfmm
