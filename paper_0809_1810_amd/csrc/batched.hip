@@ -66,12 +66,28 @@ __device__ inline uint32_t spread4b(uint32_t v) {
 }
 
 __global__ void __launch_bounds__(256) k_b_bbox(const BatchInst* __restrict__ I,
-                                                double* __restrict__ roots) {
+                                                double* __restrict__ roots,
+                                                int32_t* __restrict__ nbig) {
 #pragma clang fp contract(off)
   __shared__ double s[4][256];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nbig = 0;  // big-leaf list of this run
   const BatchInst in = I[blockIdx.x];
   double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
-  for (int64_t i = threadIdx.x; i < in.n; i += 256) {
+  // 8 particles per thread and pass: their loads are issued together
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 256 < in.n; i += 8 * 256) {
+    double xs[8], ys[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      xs[k] = in.x[i + k * 256];
+      ys[k] = in.y[i + k * 256];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a = fmin(a, xs[k]); b = fmax(b, xs[k]); c = fmin(c, ys[k]); d = fmax(d, ys[k]);
+    }
+  }
+  for (; i < in.n; i += 256) {
     const double xi = in.x[i], yi = in.y[i];
     a = fmin(a, xi); b = fmax(b, xi); c = fmin(c, yi); d = fmax(d, yi);
   }
@@ -156,7 +172,9 @@ __global__ void __launch_bounds__(256) k_b_local(const BatchInst* __restrict__ I
   const double cx = r[0] + (double(ix) + 0.5) * r[3];
   const double cy = r[1] + (double(iy) + 0.5) * r[3];
   const int64_t j = int64_t(perm[i]) - in.part_off;
-  p32[i] = Part32{float(in.x[j] - cx), float(in.y[j] - cy), float(in.g[j]), 0.0f};
+  // leaf-local, in units of the instance's Gaussian width (as in the single tree)
+  const double sd = near_scale(in.sigma);
+  p32[i] = Part32{float((in.x[j] - cx) * sd), float((in.y[j] - cy) * sd), float(in.g[j]), 0.0f};
 }
 
 __global__ void __launch_bounds__(256) k_b_tile_counts(const int64_t* __restrict__ leaf_off,
@@ -202,11 +220,22 @@ __device__ __forceinline__ typename Types<R>::C* coef(char* base, const BatchIns
   return reinterpret_cast<typename Types<R>::C*>(base + in.me_off) + level_offset(lev) * in.p;
 }
 
+// Sum of the wave's values when only lanes 0 .. 2^steps - 1 hold non-zeros:
+// butterfly within those lanes, then lane 0's total to every lane.
+template <typename R>
+__device__ __forceinline__ R lanes_sum(R v, int steps) {
+  for (int o = 0; o < steps; ++o) v += __shfl_xor(v, 1 << o, 64);
+  return __shfl(v, 0, 64);
+}
+
+// P2M of one leaf by one wave (eq. 13 on the scaled coefficients): lanes take
+// every 64th particle, the partial sums are combined with shuffles (as many
+// steps as the leaf's particle count needs), lane c writes component c.
 template <typename R>
 __device__ void p2m_leaf(const BatchInst& in, const Part32* __restrict__ p32, int32_t s, int32_t e,
-                         double w, int leaf, char* me, double* red) {
+                         double w, int leaf, char* me) {
   using C = typename Types<R>::C;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const R inv_w = R(1.0 / w);
   C acc[kBatchPMax];
 #pragma unroll
@@ -224,36 +253,105 @@ __device__ void p2m_leaf(const BatchInst& in, const Part32* __restrict__ p32, in
       }
     }
   }
-  // reduce over lanes: 2 p values per lane, through LDS (stride 65)
+  const int n = e - s;
+  int steps = 0;
+  while (steps < 6 && (1 << steps) < n) ++steps;
+  R mine = R(0);
 #pragma unroll
   for (int k = 0; k < kBatchPMax; ++k) {
-    red[(2 * k) * 65 + lane] = double(acc[k].x);
-    red[(2 * k + 1) * 65 + lane] = double(acc[k].y);
+    if (k < in.p) {
+      const R re = lanes_sum(acc[k].x, steps), im = lanes_sum(acc[k].y, steps);
+      if (lane == 2 * k) mine = re;
+      if (lane == 2 * k + 1) mine = im;
+    }
   }
-  __syncthreads();
-  R* out = reinterpret_cast<R*>(coef<R>(me, in, in.L) + int64_t(leaf) * in.p);
-  for (int cc = lane; cc < 2 * in.p; cc += 64) {
-    double t = 0.0;
-    for (int l = 0; l < 64; ++l) t += red[cc * 65 + l];
-    out[cc] = R(t);
+  if (lane < 2 * in.p) reinterpret_cast<R*>(coef<R>(me, in, in.L) + int64_t(leaf) * in.p)[lane] = mine;
+}
+
+// P2M of one leaf by one lane: the leaf's particles in order.
+template <typename R>
+__device__ void p2m_serial(const BatchInst& in, const Part32* __restrict__ p32, int32_t s,
+                           int32_t e, double w, int leaf, char* me) {
+  using C = typename Types<R>::C;
+  const R inv_w = R(1.0 / w);
+  C acc[kBatchPMax];
+#pragma unroll
+  for (int k = 0; k < kBatchPMax; ++k) acc[k] = cmake<C>(R(0), R(0));
+  for (int32_t i = s; i < e; ++i) {
+    const Part32 q = p32[i];
+    const C z = cmake<C>(R(q.x) * inv_w, R(q.y) * inv_w);
+    C pw = cmake<C>(R(q.g), R(0));
+#pragma unroll
+    for (int k = 0; k < kBatchPMax; ++k) {
+      if (k < in.p) {
+        acc[k].x += pw.x;
+        acc[k].y += pw.y;
+        pw = cmul(pw, z);
+      }
+    }
+  }
+  C* out = coef<R>(me, in, in.L) + int64_t(leaf) * in.p;
+#pragma unroll
+  for (int k = 0; k < kBatchPMax; ++k)
+    if (k < in.p) out[k] = acc[k];
+}
+
+// One lane per leaf, 64 consecutive (global) leaves per wave: a leaf of at
+// most kTile particles is summed by its lane (empty leaves get zeros); larger
+// leaves are appended to big (global leaf, instance) for k_b_p2m_big.
+__global__ void __launch_bounds__(256) k_b_p2m(const BatchInst* __restrict__ I,
+                                               const int64_t* __restrict__ leaf_off, int count,
+                                               const int32_t* __restrict__ start,
+                                               const Part32* __restrict__ p32,
+                                               const double* __restrict__ roots, char* me,
+                                               int2* __restrict__ big, int32_t* __restrict__ nbig) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = int64_t(__builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6))) * 64;
+  const int64_t nl = leaf_off[count];
+  if (base >= nl) return;
+  const int64_t gl = base + lane;
+  const int c = gl < nl ? find_seg(leaf_off, count, gl) : 0;
+  const BatchInst in = I[c];
+  const bool mine = gl < nl && in.L >= 2;
+  int32_t s = 0, e = 0;
+  if (mine) {
+    s = start[gl + c];
+    e = start[gl + c + 1];
+  }
+  if (mine && e - s <= kTile) {
+    const double w = roots[4 * c + 3] * near_scale(in.sigma);  // leaf side in the particles' units
+    const int leaf = int(gl - in.leaf_off);
+    if (in.fp64) p2m_serial<double>(in, p32, s, e, w, leaf, me);
+    else p2m_serial<float>(in, p32, s, e, w, leaf, me);
+  }
+  const bool is_big = mine && e - s > kTile;
+  const uint64_t bm = __ballot(is_big);
+  if (bm) {
+    int32_t first = 0;
+    if (lane == __builtin_ctzll(bm)) first = atomicAdd(nbig, int32_t(__popcll(bm)));
+    first = __shfl(first, __builtin_ctzll(bm), 64);
+    if (is_big) big[first + __popcll(bm & ((uint64_t(1) << lane) - 1))] = make_int2(int(gl), c);
   }
 }
 
-__global__ void __launch_bounds__(64) k_b_p2m(const BatchInst* __restrict__ I,
-                                              const int64_t* __restrict__ leaf_off, int count,
-                                              const int32_t* __restrict__ start,
-                                              const Part32* __restrict__ p32,
-                                              const double* __restrict__ roots, char* me) {
-  __shared__ double red[2 * kBatchPMax * 65];
-  const int64_t gl = blockIdx.x;
-  const int c = find_seg(leaf_off, count, gl);
+// The leaves of more than kTile particles: one wave each (grid: an upper bound
+// on their number; waves beyond *nbig exit).
+__global__ void __launch_bounds__(256) k_b_p2m_big(const BatchInst* __restrict__ I,
+                                                   const int32_t* __restrict__ start,
+                                                   const Part32* __restrict__ p32,
+                                                   const double* __restrict__ roots, char* me,
+                                                   const int2* __restrict__ big,
+                                                   const int32_t* __restrict__ nbig) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *nbig) return;
+  const int2 b = big[wid];
+  const int gl = __builtin_amdgcn_readfirstlane(b.x), c = __builtin_amdgcn_readfirstlane(b.y);
   const BatchInst in = I[c];
-  const int leaf = int(gl - in.leaf_off);
-  if (in.L < 2) return;
   const int32_t s = start[gl + c], e = start[gl + c + 1];
-  const double w = roots[4 * c + 3];
-  if (in.fp64) p2m_leaf<double>(in, p32, s, e, w, leaf, me, red);
-  else p2m_leaf<float>(in, p32, s, e, w, leaf, me, red);
+  const int leaf = int(gl - in.leaf_off);
+  const double w = roots[4 * c + 3] * near_scale(in.sigma);
+  if (in.fp64) p2m_leaf<double>(in, p32, s, e, w, leaf, me);
+  else p2m_leaf<float>(in, p32, s, e, w, leaf, me);
 }
 
 template <typename R>
@@ -369,11 +467,13 @@ __global__ void __launch_bounds__(256) k_b_m2l_mfma64(const BatchInst* __restric
 
 // ------------------------------------------------------------------ near field + evaluation
 
+// zx, zy: leaf-local target in units of the Gaussian width, wsd the leaf side
+// in the same units, w in plain units.
 template <typename R>
 __device__ __forceinline__ void l2p_eval(const BatchInst& in, const char* le, int leaf, float zx,
-                                         float zy, double w, double& fu, double& fv) {
+                                         float zy, double wsd, double w, double& fu, double& fv) {
   using C = typename Types<R>::C;
-  const R inv_w = R(1.0 / w);
+  const R inv_w = R(1.0 / wsd);
   const C z = cmake<C>(R(zx) * inv_w, R(zy) * inv_w);
   const C* Lc = reinterpret_cast<const C*>(le + in.me_off) + level_offset(in.L) * in.p +
                 int64_t(leaf) * in.p;
@@ -412,12 +512,12 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
   const int leaf = int(tile.leaf - in.leaf_off);
   const int bx = leaf & (m - 1), by = leaf >> L;
   const double w = roots[4 * c + 3];
-  const double sg = in.sigma;
-  const float kexp = float(-1.4426950408889634074 / (2.0 * sg * sg));
-  const float ka = float(1.0 / (2.0 * sg * sg));
-  const float far2 = float(P2PMath<float>::kFarSigma2 * sg * sg);
-  const float ser2 = float(P2PMath<float>::kSeriesSigma2 * sg * sg);
-  const float tiny = float(w * w * 0x1p-80);
+  // positions are in units of the Gaussian width: r'^2 = r^2 log2(e) / (2 sigma^2)
+  const double sd = near_scale(in.sigma);
+  const double wsd = w * sd;
+  const float far2 = float(P2PMath<float>::kFarSigma2 * 1.4426950408889634074 / 2.0);
+  const float ser2 = float(P2PMath<float>::kSeriesSigma2 * 1.4426950408889634074 / 2.0);
+  const float tiny = float(wsd * wsd * 0x1p-80);
   const float4 tb = tile_box[wid];
   Acc32 au{0.f, 0.f}, av{0.f, 0.f};
   for (int oy = -1; oy <= 1; ++oy) {
@@ -428,10 +528,10 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
       if (sx < 0 || sx >= m) continue;
       const int64_t gsl = in.leaf_off + sy * m + sx;
       const int32_t js = start[gsl + c], je = start[gsl + c + 1];
-      const float tx = tp.x - float(double(ox) * w);
-      const float ty = tp.y - float(double(oy) * w);
-      const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
-      const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
+      const float tx = tp.x - float(double(ox) * wsd);
+      const float ty = tp.y - float(double(oy) * wsd);
+      const float bx0 = tb.x - float(double(ox) * wsd), bx1 = tb.y - float(double(ox) * wsd);
+      const float by0 = tb.z - float(double(oy) * wsd), by1 = tb.w - float(double(oy) * wsd);
       uint32_t ci = tile_off[gsl];
       for (int32_t j0 = js; j0 < je; j0 += 64, ++ci) {
         const int32_t j1 = min(j0 + 64, je);
@@ -454,7 +554,7 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
           for (int32_t j = j0; j < j1; ++j) {
             const Part32 s = part[j];
             const float dx = tx - s.x, dy = ty - s.y;
-            const float f = P2PMath<float>::near(s.g, dx * dx + (dy * dy + tiny), kexp);
+            const float f = P2PMath<float>::near_s(s.g, dx * dx + (dy * dy + tiny));
             cu -= f * dy;
             cv += f * dx;
           }
@@ -463,7 +563,7 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
           for (int32_t j = j0; j < j1; ++j) {
             const Part32 s = part[j];
             const float dx = tx - s.x, dy = ty - s.y;
-            const float f = P2PMath<float>::near_series(s.g, dx * dx + (dy * dy + tiny), kexp, ka);
+            const float f = P2PMath<float>::near_series_s(s.g, dx * dx + (dy * dy + tiny));
             cu -= f * dy;
             cv += f * dx;
           }
@@ -475,13 +575,14 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
   }
   double fu = 0.0, fv = 0.0;
   if (L >= 2) {
-    if (in.fp64) l2p_eval<double>(in, le, leaf, tp.x, tp.y, w, fu, fv);
-    else l2p_eval<float>(in, le, leaf, tp.x, tp.y, w, fu, fv);
+    if (in.fp64) l2p_eval<double>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
+    else l2p_eval<float>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
   }
   if (active) {
+    // each pair term is Gamma (...) d' / r'^2 = (1 / sd) Gamma (...) d / r^2
     const int64_t o = int64_t(perm[i]) - in.part_off;
-    in.u[o] = au.value() * kInv2Pi + fu;
-    in.v[o] = av.value() * kInv2Pi + fv;
+    in.u[o] = au.value() * (kInv2Pi * sd) + fu;
+    in.v[o] = av.value() * (kInv2Pi * sd) + fv;
   }
 }
 
@@ -501,6 +602,8 @@ struct BatchPlanDev {
   double* roots;
   uint32_t *k0, *k1, *counts, *tmp, *toff;
   int32_t *i0, *i1, *start, *ntiles;
+  int2* big;      // leaves of more than kTile particles (global leaf, instance)
+  int32_t* nbig;  // their number
   Tile* tiles;
   float4* tile_box;
   Part32* p32;
@@ -512,7 +615,7 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                             int maxL, int nseg, int64_t mfma_tiles, int nseg64,
                             int64_t mfma_tiles64, hipStream_t st) {
   auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
-  hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots);
+  hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots, d.nbig);
   hipLaunchKernelGGL(k_b_keys, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, d.part_off, count,
                      ntot, d.roots, d.k0, d.i0);
   uint32_t* k0 = d.k0; uint32_t* k1 = d.k1;
@@ -533,8 +636,10 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                      d.toff, ntot, nleaves, d.tiles, d.ntiles);
   e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_p2m, dim3(unsigned(nleaves)), dim3(64), 0, st, d.inst, d.leaf_off, count,
-                     d.start, d.p32, d.roots, d.me);
+  hipLaunchKernelGGL(k_b_p2m, dim3(nb(nleaves, 256)), dim3(256), 0, st, d.inst, d.leaf_off, count,
+                     d.start, d.p32, d.roots, d.me, d.big, d.nbig);
+  hipLaunchKernelGGL(k_b_p2m_big, dim3(nb(ntot / (kTile + 1) + 1, 4)), dim3(256), 0, st, d.inst,
+                     d.start, d.p32, d.roots, d.me, d.big, d.nbig);
   for (int l = maxL - 1; l >= 2; --l)
     if (m2m_tot[l] > 0)
       hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, st, d.inst,
@@ -594,7 +699,7 @@ inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 struct BatchLayout {
   size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
       seg_off64, seg_il64, roots, k0, k1, i0, i1,
-      counts, tmp, toff, start, ntiles, tiles, tile_box, p32, me, le, tab, total;
+      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, total;
   int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
   int maxL;
   std::vector<int64_t> me_off;
@@ -664,6 +769,8 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.toff = take(4 * size_t(L.nleaves + 1));
   L.start = take(4 * size_t(L.nleaves + count));
   L.ntiles = take(4);
+  L.big = take(sizeof(int2) * size_t(L.ntot / (kTile + 1) + 1));
+  L.nbig = take(4);
   L.tiles = take(sizeof(Tile) * size_t(L.max_tiles));
   L.tile_box = take(sizeof(float4) * size_t(L.max_tiles));
   L.p32 = take(sizeof(Part32) * size_t(L.ntot));
@@ -774,6 +881,8 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   d.toff = reinterpret_cast<uint32_t*>(ws + L.toff);
   d.start = reinterpret_cast<int32_t*>(ws + L.start);
   d.ntiles = reinterpret_cast<int32_t*>(ws + L.ntiles);
+  d.big = reinterpret_cast<int2*>(ws + L.big);
+  d.nbig = reinterpret_cast<int32_t*>(ws + L.nbig);
   d.tiles = reinterpret_cast<Tile*>(ws + L.tiles);
   d.tile_box = reinterpret_cast<float4*>(ws + L.tile_box);
   d.p32 = reinterpret_cast<Part32*>(ws + L.p32);
