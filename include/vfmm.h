@@ -124,6 +124,12 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
  *   sigma     : Gaussian core size (eq. 3, 6), finite and > 0.
  *   p         : expansion terms, 1 <= p <= p_max of the tree (eq. 21).
  *   precision : VFMM_FP64, VFMM_FP32, VFMM_M2L_BF16 or VFMM_M2L_FP16.
+ * Streams: the call is ordered on `stream` (after the work queued on it before
+ * the call, before the work queued after it).  Inside, the expansion sweeps
+ * (tables, P2M, M2M, M2L + L2L) run on a stream owned by the tree (created with
+ * it, default priority), concurrently with the near field on `stream`; `stream`
+ * waits for them (an event) before the far field is added.  Calls on one tree
+ * from different streams race, as they share the tree's workspace.
  * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
 vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
                                 int32_t precision, double* u, double* v, void* stream);
@@ -228,19 +234,21 @@ vfmm_status_t vfmm_tree_expansions(vfmm_tree_t tree, int32_t kind, int32_t level
 vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double* y,
                                 const double* domain, void* stream);
 
-/* Phase timing.  Phases of one vfmm_fmm_velocity call, in order:
+/* Phase timing.  Phases of one vfmm_fmm_velocity call:
  * 0 gather circulations (and, for vfmm_fmm_velocity_at, the sort of the
  * evaluation points), 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
- * 4 M2L + L2L (levels 2..L), 5 near-field work schedule, 6 P2P + L2P +
- * combine (the near-field kernel and the sum of the parts of split tiles).
- * After
+ * 4 M2L + L2L (levels 2..L), 5 near-field work schedule, 6 near field (P2P
+ * kernel and the sum of the parts of split tiles), 7 L2P (adds the far field,
+ * after waiting for phases 1-4).  Phases 1-4 run on the tree's stream while
+ * 5-6 run on the caller's, so their times overlap.  After
  * vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
- * next max_calls evaluations record HIP events at the phase boundaries on their
- * stream (no synchronisation).  vfmm_tree_read_timing waits for the recorded
- * events, writes ms[call * VFMM_N_PHASES + phase] (host, max_calls *
- * VFMM_N_PHASES doubles) and *n_calls (host), and starts a new recording.
- * Phases skipped by a call read 0. */
-#define VFMM_N_PHASES 7
+ * next max_calls evaluations record HIP events at the beginning and end of
+ * each phase on the stream that runs it (no synchronisation).
+ * vfmm_tree_read_timing waits for the recorded events, writes
+ * ms[call * VFMM_N_PHASES + phase] (host, max_calls * VFMM_N_PHASES doubles)
+ * and *n_calls (host), and starts a new recording.  Phases skipped by a call
+ * read 0. */
+#define VFMM_N_PHASES 8
 vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t tree, int32_t max_calls);
 vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t tree, double* ms, int32_t* n_calls);
 

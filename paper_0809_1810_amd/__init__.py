@@ -8,7 +8,8 @@ from .vfmm import (Batch, FP32, FP64, M2L_BF16, M2L_FP16, MAX_LEVELS, MAX_P, MLP
                    VfmmUnavailable, build_tree, direct_velocity, error_metrics, fmm_velocity,
                    header_symbols, lib, mlp_forward, particle_stats, select_params,
                    selector_features, set_tuning, get_tuning, workspace_bytes,
-                   direct_velocity_at, error_field, targets_workspace_bytes, NEAR_RADIUS_AUTO)
+                   direct_velocity_at, error_field, targets_workspace_bytes, NEAR_RADIUS_AUTO,
+                   N_PHASES, PHASES)
 
 __all__ = [
     "Batch", "FP32", "FP64", "M2L_BF16", "M2L_FP16", "MAX_LEVELS", "MAX_P", "MLP_PARAMS", "N_FEATURES",
@@ -17,4 +18,5 @@ __all__ = [
     "header_symbols", "lib", "mlp_forward", "particle_stats", "select_params",
     "selector_features", "set_tuning", "get_tuning", "workspace_bytes",
     "direct_velocity_at", "error_field", "targets_workspace_bytes", "NEAR_RADIUS_AUTO",
+    "N_PHASES", "PHASES",
 ]

@@ -37,7 +37,7 @@ def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5):
     t.enable_timing(reps)
     for _ in range(reps):
         t.velocity(g, sigma, p, V.FP32)
-    ms = float(np.median([ph["p2p_l2p"] for ph in t.read_timing()]))
+    ms = float(np.median([ph["p2p"] for ph in t.read_timing()]))
     t.close()
     return ms
 

@@ -235,18 +235,16 @@ template <> struct PairK<double> {
   }
 };
 
-template <typename R, int PMAX, int LPT>
-__global__ void __launch_bounds__(512) k_p2p_l2p(
+template <typename R, int LPT>
+__global__ void __launch_bounds__(512) k_p2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
     const typename Types<R>::Part* __restrict__ tpart, const Part64* __restrict__ tpart64,
     const Tile* __restrict__ ttiles, const float4* __restrict__ ttile_box,
     const int32_t* __restrict__ tperm, const P2PPart* __restrict__ parts,
     const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
-    const double* __restrict__ root, int levels, int p,
-    const typename Types<R>::C* __restrict__ le_leaf, PairK<R> pk, double sd, float far2,
-    float ser2, int nseg, double cut2, int parts_mask, double* __restrict__ u,
-    double* __restrict__ v) {
+    const double* __restrict__ root, int levels, PairK<R> pk, double sd, float far2, float ser2,
+    int nseg, double cut2, double* __restrict__ u, double* __restrict__ v) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   // FP32: sources and targets in units of the Gaussian width (factor sd);
   // FP64: plain units (sd = 1)
@@ -295,7 +293,7 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
     const int bx = t_leaf & (m - 1), by = t_leaf >> levels;
 
     double nu = 0.0, nv = 0.0;
-    if (parts_mask & 1) {
+    {
       const R tiny = R(wsd * wsd * 0x1p-80);
       const float4 tb = ttile_box[pt_tile];
       Acc32 au{0.f, 0.f}, av{0.f, 0.f};
@@ -433,28 +431,20 @@ __global__ void __launch_bounds__(512) k_p2p_l2p(
       if (active && grp == 0) partial[int64_t(slot) * kTile + tl] = make_double2(nu, nv);
       continue;
     }
-    double fu = 0.0, fv = 0.0;
-    if ((parts_mask & 2) && levels >= 2) {
-      const auto tp = tpart[i];  // plain units, reloaded rather than kept live
-      l2p<R, PMAX>(le_leaf + int64_t(t_leaf) * p, tp.x, tp.y, w, p, fu, fv);
-    }
     if (active && grp == 0) {
       const int32_t o = tperm[i];
-      u[o] = nu * kInv2Pi + fu;
-      v[o] = nv * kInv2Pi + fv;
+      u[o] = nu * kInv2Pi;
+      v[o] = nv * kInv2Pi;
     }
   }
 }
 
-// Split tiles: add the partial sums of their parts in part order, then L2P.
-template <typename R, int PMAX>
+// Split tiles: add the partial sums of their parts in part order.
 __global__ void __launch_bounds__(256) k_p2p_reduce(
-    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
-    const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
-    const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
-    const double2* __restrict__ partial, const double* __restrict__ root, int levels, int p,
-    const typename Types<R>::C* __restrict__ le_leaf, int parts_mask, double* __restrict__ u,
-    double* __restrict__ v) {
+    const Tile* __restrict__ ttiles, const int32_t* __restrict__ tntiles,
+    const int32_t* __restrict__ tperm, const uint32_t* __restrict__ p_off,
+    const uint32_t* __restrict__ s_off, const double2* __restrict__ partial,
+    double* __restrict__ u, double* __restrict__ v) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= *tntiles) return;
   const uint32_t np = p_off[wid + 1] - p_off[wid];
@@ -469,15 +459,32 @@ __global__ void __launch_bounds__(256) k_p2p_reduce(
     nu += q.x;
     nv += q.y;
   }
+  const int32_t o = tperm[tile.start + lane];
+  u[o] = nu * kInv2Pi;
+  v[o] = nv * kInv2Pi;
+}
+
+// Far field at the targets (L2P, eq. 25 on the scaled LEs of the leaves): one
+// wave per target tile; adds to the near field already in u, v (add != 0) or
+// writes the far field alone.
+template <typename R, int PMAX>
+__global__ void __launch_bounds__(256) k_l2p(
+    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
+    const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
+    const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
+    int add, double* __restrict__ u, double* __restrict__ v) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *tntiles) return;
+  const int lane = threadIdx.x & 63;
+  const Tile tile = ttiles[wid];
+  if (lane >= tile.count) return;
   const int32_t i = tile.start + lane;
-  const auto tp = tpart[i];
-  const double w = root[3];
-  double fu = 0.0, fv = 0.0;
-  if ((parts_mask & 2) && levels >= 2)
-    l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, w, p, fu, fv);
+  const auto tp = tpart[i];  // leaf-local, plain units
+  double fu, fv;
+  l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, root[3], p, fu, fv);
   const int32_t o = tperm[i];
-  u[o] = nu * kInv2Pi + fu;
-  v[o] = nv * kInv2Pi + fv;
+  u[o] = add ? u[o] + fu : fu;
+  v[o] = add ? v[o] + fv : fv;
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -503,16 +510,14 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, in
   return hipGetLastError();
 }
 
-template <typename R, int PMAX, int LPT>
-void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              int nseg, double cut2, double* u, double* v, hipStream_t st) {
-  using C = typename Types<R>::C;
+template <typename R, int LPT>
+void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, int nseg,
+              double cut2, double* u, double* v, hipStream_t st) {
   using Part = typename Types<R>::Part;
   const auto* part = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32s));
   const auto* tpart = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
-  const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
   PairK<R> pk{};
   double sd = 1.0;
   if constexpr (sizeof(R) == 8) pk.kexp = -1.0 / (2.0 * sigma * sigma);
@@ -527,35 +532,46 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, double 
   int64_t waves = tg.max_tiles + (pairs_bound < P ? pairs_bound : P);
   if (waves > kP2PMaxWaves) waves = kP2PMaxWaves;
   const P2PSched& s = tg.sched;
-  hipLaunchKernelGGL((k_p2p_l2p<R, PMAX, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st,
-                     part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles,
-                     tg.tile_box, tg.perm, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels,
-                     p, le, pk, sd, far2, ser2, nseg, cut2, parts, u, v);
-  hipLaunchKernelGGL((k_p2p_reduce<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st,
-                     tpart, tg.tiles, tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, t.root,
-                     levels, p, le, parts, u, v);
-}
-
-template <typename R, int PMAX>
-void launch_l(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              int nseg, double cut2, double* u, double* v, hipStream_t st) {
-  if (t.tile == 16) launch_t<R, PMAX, 4>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else if (t.tile == 32) launch_t<R, PMAX, 2>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else launch_t<R, PMAX, 1>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  hipLaunchKernelGGL((k_p2p<R, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st, part,
+                     t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles, tg.tile_box,
+                     tg.perm, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
+                     far2, ser2, nseg, cut2, u, v);
+  hipLaunchKernelGGL(k_p2p_reduce, dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st, tg.tiles,
+                     tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, u, v);
 }
 
 template <typename R>
-void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, double sigma, int parts,
-              double radius, double* u, double* v, hipStream_t st) {
+void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, double radius,
+              double* u, double* v, hipStream_t st) {
   // radius 0: the paper's split; < 0: the distance beyond which the two kernels
   // agree in this precision; the kernel clamps it to 2 w_L
   const int nseg = radius == 0.0 ? kSegNear : kSegRing;
   const double cut2 = radius > 0.0 ? radius * radius : P2PMath<R>::kFarSigma2 * sigma * sigma;
-  if (p <= 8) launch_l<R, 8>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else if (p <= 16) launch_l<R, 16>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else if (p <= 24) launch_l<R, 24>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else if (p <= 32) launch_l<R, 32>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
-  else launch_l<R, 40>(t, tg, levels, p, sigma, parts, nseg, cut2, u, v, st);
+  if (t.tile == 16) launch_t<R, 4>(t, tg, levels, sigma, nseg, cut2, u, v, st);
+  else if (t.tile == 32) launch_t<R, 2>(t, tg, levels, sigma, nseg, cut2, u, v, st);
+  else launch_t<R, 1>(t, tg, levels, sigma, nseg, cut2, u, v, st);
+}
+
+template <typename R, int PMAX>
+void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int add, double* u,
+                  double* v, hipStream_t st) {
+  using C = typename Types<R>::C;
+  using Part = typename Types<R>::Part;
+  const auto* tpart = reinterpret_cast<const Part*>(
+      sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
+  const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
+  hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st, tpart,
+                     tg.tiles, tg.ntiles, tg.perm, t.root, p, le, add, u, v);
+}
+
+template <typename R>
+void launch_l2p_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, int add, double* u,
+                  double* v, hipStream_t st) {
+  if (p <= 8) launch_l2p_t<R, 8>(t, tg, levels, p, add, u, v, st);
+  else if (p <= 16) launch_l2p_t<R, 16>(t, tg, levels, p, add, u, v, st);
+  else if (p <= 24) launch_l2p_t<R, 24>(t, tg, levels, p, add, u, v, st);
+  else if (p <= 32) launch_l2p_t<R, 32>(t, tg, levels, p, add, u, v, st);
+  else launch_l2p_t<R, 40>(t, tg, levels, p, add, u, v, st);
 }
 
 }  // namespace
@@ -565,11 +581,17 @@ hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int level
   return build_schedule(t, tg, levels, radius == 0.0 ? kSegNear : kSegRing, st);
 }
 
-hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
-                          double sigma, int parts, double radius, double* u, double* v,
-                          hipStream_t st) {
-  if (prec == kFP64) launch_r<double>(t, tg, levels, p, sigma, parts, radius, u, v, st);
-  else launch_r<float>(t, tg, levels, p, sigma, parts, radius, u, v, st);
+hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,
+                      double radius, double* u, double* v, hipStream_t st) {
+  if (prec == kFP64) launch_r<double>(t, tg, levels, sigma, radius, u, v, st);
+  else launch_r<float>(t, tg, levels, sigma, radius, u, v, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec, int add,
+                      double* u, double* v, hipStream_t st) {
+  if (prec == kFP64) launch_l2p_r<double>(t, tg, levels, p, add, u, v, st);
+  else launch_l2p_r<float>(t, tg, levels, p, add, u, v, st);
   return hipGetLastError();
 }
 

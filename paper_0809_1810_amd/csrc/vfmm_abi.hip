@@ -28,11 +28,18 @@ struct vfmm_tree_s {
   int last_p;       // order / precision of the last evaluation
   int last_prec;
   double near_radius;  // distance cut-off of the near field (0 = the paper's split)
-  std::vector<hipEvent_t> ev;  // phase-timing ring: (VFMM_N_PHASES + 1) per call
+  std::vector<hipEvent_t> ev;  // phase-timing ring: begin and end of each phase, per call
   int t_slots;
   int t_used;
+  // the expansion sweeps run on `side` (default priority), concurrently with
+  // the near field on the caller's stream: fork after the gather, join before L2P
+  hipStream_t side;
+  hipEvent_t fork, join;
   ~vfmm_tree_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -60,6 +67,7 @@ std::atomic<int> g_tile{kTile};
 std::atomic<int> g_waves{4};
 int tuning_tile() { return g_tile.load(); }
 int tuning_waves() { return g_waves.load(); }
+
 }  // namespace vfmm
 
 namespace {
@@ -195,7 +203,14 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   t->pack_mode = -1;
   t->last_p = -1;
   t->last_prec = -1;
-  hipError_t e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, tuning_tile(), t->dev,
+  hipError_t e = hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&t->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&t->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete t;
+    return hip_fail(e, "tree stream / events");
+  }
+  e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, tuning_tile(), t->dev,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     delete t;
@@ -225,61 +240,114 @@ vfmm_status_t check_eval(vfmm_tree_t t, const double* gamma, double sigma, int32
   return VFMM_OK;
 }
 
-// Phase-timing marks of one evaluation (no-op when timing is off or the ring is full).
+// Phase-timing marks of one evaluation (no-op when timing is off or the ring
+// is full): begin / end events of each phase, on the stream that runs it.
 struct Marks {
   hipEvent_t* ev = nullptr;
-  hipStream_t st;
-  Marks(vfmm_tree_t t, hipStream_t s) : st(s) {
-    if (t->t_used < t->t_slots) ev = &t->ev[size_t(t->t_used++) * (VFMM_N_PHASES + 1)];
+  Marks(vfmm_tree_t t) {
+    if (t->t_used < t->t_slots) ev = &t->ev[size_t(t->t_used++) * 2 * VFMM_N_PHASES];
   }
-  void operator()(int k) const {
-    if (ev) (void)hipEventRecord(ev[k], st);
+  void begin(int k, hipStream_t s) const {
+    if (ev) (void)hipEventRecord(ev[2 * k], s);
+  }
+  void end(int k, hipStream_t s) const {
+    if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+  }
+  void skip(int k, hipStream_t s) const {
+    begin(k, s);
+    end(k, s);
   }
 };
 
-// Circulations into the sorted particles, then the upward and downward sweeps
-// (Fig. 3): operator tables, P2M, M2M, M2L + L2L.  Marks phases 1 .. 5.
-vfmm_status_t sweeps(vfmm_tree_t t, const double* gamma, double sigma, int32_t p,
-                     int32_t precision, int32_t parts, const Marks& mark, hipStream_t st) {
+enum Phase { kPhGather = 0, kPhTables, kPhP2M, kPhM2M, kPhM2L, kPhSched, kPhP2P, kPhL2P };
+
+// One evaluation on target set tg (Fig. 3): circulations into the sorted
+// particles; then, on the tree's side stream, the operator tables, P2M, M2M and
+// M2L + L2L while the caller's stream builds the near-field schedule and runs
+// the near field; after both, L2P adds the far field.  Every launch is ordered
+// after the work queued on st before the call, and st waits for the side
+// stream before L2P, so the call behaves as one ordered sequence on st.
+vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma, double sigma,
+                       int32_t p, int32_t precision, int32_t parts, double* u, double* v,
+                       const Marks& mark, hipStream_t st) {
   const int L = t->levels;
   // the reduced-precision M2L variants share the FP32 pipeline
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  const bool near32 = prec == kFP32 && (parts & VFMM_PART_NEAR);
-  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, near32 ? sigma : 0.0, st);
-  if (e != hipSuccess) return hip_fail(e, "gather");
-  mark(1);
+  const bool near = parts & VFMM_PART_NEAR;
   const bool far = L >= 2 && (parts & VFMM_PART_FAR);
+  // (the caller has opened the gather phase)
+  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, st);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  mark.end(kPhGather, st);
+  // the sweeps go to the side stream only when there is near-field work to overlap
+  hipStream_t sw = near && far ? t->side : st;
+  if (sw != st) {
+    e = hipEventRecord(t->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sw, t->fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "fork");
+  }
+  mark.begin(kPhTables, sw);
   if (far && t->ops_p != p) {
-    e = launch_build_ops(t->dev, p, prec, st);
+    e = launch_build_ops(t->dev, p, prec, sw);
     if (e != hipSuccess) return hip_fail(e, "operator tables");
     t->ops_p = p;
     t->pack_p = -1;
   }
   if (far && prec != kFP64 && (t->pack_p != p || t->pack_mode != precision)) {
-    e = launch_pack_m2l_mfma(t->dev, p, precision, st);
+    e = launch_pack_m2l_mfma(t->dev, p, precision, sw);
     if (e != hipSuccess) return hip_fail(e, "matrix-core operands");
     t->pack_p = p;
     t->pack_mode = precision;
   }
-  mark(2);
+  mark.end(kPhTables, sw);
+  mark.begin(kPhP2M, sw);
   if (far) {
-    e = launch_p2m(t->dev, L, p, prec, st);
+    e = launch_p2m(t->dev, L, p, prec, sw);
     if (e != hipSuccess) return hip_fail(e, "P2M");
   }
-  mark(3);
+  mark.end(kPhP2M, sw);
+  mark.begin(kPhM2M, sw);
   if (far) {
-    e = launch_m2m(t->dev, L, p, prec, st);
+    e = launch_m2m(t->dev, L, p, prec, sw);
     if (e != hipSuccess) return hip_fail(e, "M2M");
   }
-  mark(4);
+  mark.end(kPhM2M, sw);
+  mark.begin(kPhM2L, sw);
   if (far) {
-    e = prec == kFP64 ? launch_downward(t->dev, L, p, prec, st)
-                      : launch_downward_mfma(t->dev, L, p, precision, st);
+    e = prec == kFP64 ? launch_downward(t->dev, L, p, prec, sw)
+                      : launch_downward_mfma(t->dev, L, p, precision, sw);
     if (e != hipSuccess) return hip_fail(e, "M2L/L2L");
     t->last_p = p;
     t->last_prec = prec;
   }
-  mark(5);
+  mark.end(kPhM2L, sw);
+  if (sw != st) {
+    e = hipEventRecord(t->join, sw);
+    if (e != hipSuccess) return hip_fail(e, "join");
+  }
+  mark.begin(kPhSched, st);
+  if (near) {
+    e = launch_p2p_schedule(t->dev, tg, L, t->near_radius, st);
+    if (e != hipSuccess) return hip_fail(e, "P2P schedule");
+  }
+  mark.end(kPhSched, st);
+  mark.begin(kPhP2P, st);
+  if (near) {
+    e = launch_p2p(t->dev, tg, L, prec, sigma, t->near_radius, u, v, st);
+    if (e != hipSuccess) return hip_fail(e, "P2P");
+  }
+  mark.end(kPhP2P, st);
+  mark.begin(kPhL2P, st);
+  if (sw != st) {
+    e = hipStreamWaitEvent(st, t->join, 0);
+    if (e != hipSuccess) return hip_fail(e, "join");
+  }
+  if (far || !near) {
+    // the far field; asked alone of a tree without one (L < 2), zeros (order 0)
+    e = launch_l2p(t->dev, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
+    if (e != hipSuccess) return hip_fail(e, "L2P");
+  }
+  mark.end(kPhL2P, st);
   return VFMM_OK;
 }
 
@@ -333,19 +401,9 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, parts, u, v);
   if (s) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Marks mark(t, st);
-  mark(0);
-  s = sweeps(t, gamma, sigma, p, precision, parts, mark, st);
-  if (s) return s;
-  const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  const TargetsDev self = self_targets(t->dev, t->lay);
-  hipError_t e = launch_p2p_schedule(t->dev, self, t->levels, t->near_radius, st);
-  if (e != hipSuccess) return hip_fail(e, "P2P schedule");
-  mark(6);
-  e = launch_p2p_l2p(t->dev, self, t->levels, p, prec, sigma, parts, t->near_radius, u, v, st);
-  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
-  mark(7);
-  return VFMM_OK;
+  const Marks mark(t);
+  mark.begin(kPhGather, st);
+  return evaluate(t, self_targets(t->dev, t->lay), gamma, sigma, p, precision, parts, u, v, mark, st);
 }
 
 vfmm_status_t vfmm_targets_workspace_bytes(int64_t n_targets, int32_t levels, size_t* bytes) {
@@ -375,22 +433,13 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   if (reinterpret_cast<uintptr_t>(workspace) & 255)
     return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Marks mark(t, st);
-  mark(0);
+  const Marks mark(t);
+  mark.begin(kPhGather, st);
   TargetsDev tg{};
   hipError_t e = launch_build_targets(xt, yt, n_targets, t->dev, t->levels, lay,
                                       static_cast<char*>(workspace), tg, st);
   if (e != hipSuccess) return hip_fail(e, "evaluation points");
-  s = sweeps(t, gamma, sigma, p, precision, parts, mark, st);
-  if (s) return s;
-  const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
-  e = launch_p2p_schedule(t->dev, tg, t->levels, t->near_radius, st);
-  if (e != hipSuccess) return hip_fail(e, "P2P schedule");
-  mark(6);
-  e = launch_p2p_l2p(t->dev, tg, t->levels, p, prec, sigma, parts, t->near_radius, u, v, st);
-  if (e != hipSuccess) return hip_fail(e, "P2P/L2P");
-  mark(7);
-  return VFMM_OK;
+  return evaluate(t, tg, gamma, sigma, p, precision, parts, u, v, mark, st);
 }
 
 vfmm_status_t vfmm_error_field(const double* u, const double* v, const double* ur,
@@ -552,7 +601,7 @@ vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t t, double radius) {
 vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t t, int32_t max_calls) {
   if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
   if (max_calls < 0 || max_calls > 100000) return fail(VFMM_ERR_INVALID_ARG, "max_calls out of range");
-  const size_t need = size_t(max_calls) * (VFMM_N_PHASES + 1);
+  const size_t need = size_t(max_calls) * 2 * VFMM_N_PHASES;
   while (t->ev.size() < need) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -568,12 +617,12 @@ vfmm_status_t vfmm_tree_read_timing(vfmm_tree_t t, double* ms, int32_t* n_calls)
   if (!t || !ms || !n_calls) return fail(VFMM_ERR_INVALID_ARG, "null pointer");
   const int used = t->t_used;
   for (int c = 0; c < used; ++c) {
-    hipEvent_t* ev = &t->ev[size_t(c) * (VFMM_N_PHASES + 1)];
-    hipError_t r = hipEventSynchronize(ev[VFMM_N_PHASES]);
-    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+    hipEvent_t* ev = &t->ev[size_t(c) * 2 * VFMM_N_PHASES];
     for (int k = 0; k < VFMM_N_PHASES; ++k) {
+      hipError_t r = hipEventSynchronize(ev[2 * k + 1]);
+      if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
       float f = 0.f;
-      r = hipEventElapsedTime(&f, ev[k], ev[k + 1]);
+      r = hipEventElapsedTime(&f, ev[2 * k], ev[2 * k + 1]);
       if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
       ms[size_t(c) * VFMM_N_PHASES + k] = double(f);
     }

@@ -187,12 +187,15 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
 // radius: distance cut-off of the near field (0 = off, < 0 = the distance at
 // which the regularised and singular kernels agree in this precision).
 // The near-field work schedule of target set tg (launch_p2p_schedule), then
-// the near-field + L2P kernels over it (launch_p2p_l2p, same radius).
+// the near-field kernels over it (launch_p2p, same radius), which write u, v.
 hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
                                hipStream_t stream);
-hipError_t launch_p2p_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
-                          double sigma, int parts, double radius, double* u, double* v,
-                          hipStream_t stream);
+hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,
+                      double radius, double* u, double* v, hipStream_t stream);
+// Far field of the leaves' LEs at the targets: added to u, v (add != 0) or
+// written; p = 0 writes (or adds) zeros.
+hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec, int add,
+                      double* u, double* v, hipStream_t stream);
 // Sorts nt evaluation points into the leaves of tree t (built with `levels`),
 // with leaf-local coordinates (NaN outside the closed root square) and tiles of
 // t.tile points.

@@ -114,8 +114,8 @@ class Instance(C.Structure):
 
 TUNE_P2P_TILE, TUNE_P2P_WAVES = 1, 2
 
-N_PHASES = 7
-PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_sched", "p2p_l2p")
+N_PHASES = 8
+PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_sched", "p2p", "l2p")
 
 
 def header_symbols(path: str = HEADER_PATH):

@@ -32,6 +32,15 @@ def test_exports_every_header_symbol():
     assert set(B._SIGS) == declared  # the binding covers exactly the header
 
 
+def test_header_constants_match_the_binding():
+    import re
+    text = open(B.HEADER_PATH).read()
+    consts = dict(re.findall(r"#define\s+(VFMM_[A-Z0-9_]+)\s+\(?(-?[0-9.]+)\)?", text))
+    assert int(consts["VFMM_N_PHASES"]) == vf.N_PHASES == len(vf.PHASES)
+    assert int(consts["VFMM_PART_NEAR"]) == vf.PART_NEAR and int(consts["VFMM_PART_FAR"]) == vf.PART_FAR
+    assert float(consts["VFMM_NEAR_RADIUS_AUTO"]) == vf.NEAR_RADIUS_AUTO
+
+
 def test_workspace_bytes_host_only():
     l = _lib()
     b = C.c_size_t(0)

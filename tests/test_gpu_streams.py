@@ -1,0 +1,78 @@
+"""Ordering of an evaluation whose expansion sweeps run on the tree's own
+stream, concurrently with the near field on the caller's stream, through the
+C ABI.
+
+* Back-to-back evaluations on a non-default stream with no host
+  synchronisation between them (circulations changed in place between calls,
+  results copied on the same stream) give the results of separate,
+  synchronised evaluations; the sum is checked against the float64 oracle.
+* Phase timing records 8 phases; a far-only evaluation skips the near-field
+  phases.
+* The far part alone of a tree without far field (L < 2) is zeros.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fmm as F
+from tests.gpu_util import dev, host, print_case, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vf():
+    return require_gpu()
+
+
+def test_back_to_back_calls_on_a_stream(vf):
+    P = W.clusters(30000, seed=12, sigma=0.01)
+    L, p = 5, 12
+    print_case("streams_back_to_back", n=P.n, levels=L, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    ref = [host(a).copy() for a in t.velocity(g, P.sigma, p, vf.FP32)]
+    s = torch.cuda.Stream()
+    u = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    outs = []
+    with torch.cuda.stream(s):
+        for k in range(6):
+            t.velocity(g, P.sigma, p, vf.FP32, out=(u, v))
+            outs.append((u.clone(), v.clone()))
+            g.mul_(-1.0)  # the next call must see the new circulations
+    s.synchronize()
+    for k, (uk, vk) in enumerate(outs):
+        sign = 1.0 if k % 2 == 0 else -1.0
+        assert np.array_equal(host(uk), sign * ref[0]) and np.array_equal(host(vk), sign * ref[1]), k
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L)
+    assert rel_err(ref[0], ref[1], r.u, r.v)[0] < 1e-6
+    t.close()
+
+
+def test_phase_timing(vf):
+    P = W.uniform(20000, seed=13, sigma=0.01)
+    t = vf.Tree(dev(P.x), dev(P.y), 5, p_max=10)
+    g = dev(P.gamma)
+    t.velocity(g, P.sigma, 10, vf.FP32)
+    t.enable_timing(3)
+    for _ in range(2):
+        t.velocity(g, P.sigma, 10, vf.FP32)
+    t.velocity(g, P.sigma, 10, vf.FP32, parts=vf.PART_FAR)
+    ph = t.read_timing()
+    assert len(ph) == 3 and all(len(x) == vf.N_PHASES == 8 for x in ph)
+    assert all(val >= 0.0 for x in ph for val in x.values())
+    assert ph[0]["p2p"] > 0.0 and ph[0]["l2p"] > 0.0 and ph[0]["m2l_l2l"] > 0.0
+    assert ph[2]["p2p"] < 0.02 and ph[2]["p2p_sched"] < 0.02  # skipped: begin and end together
+    t.close()
+
+
+def test_far_part_of_a_shallow_tree_is_zero(vf):
+    P = W.uniform(500, seed=14, sigma=0.05)
+    t = vf.Tree(dev(P.x), dev(P.y), 1, p_max=8)
+    u = torch.full((P.n,), float("nan"), dtype=torch.float64, device="cuda")
+    v = torch.full_like(u, float("nan"))
+    t.velocity(dev(P.gamma), P.sigma, 8, vf.FP32, parts=vf.PART_FAR, out=(u, v))
+    assert np.all(host(u) == 0.0) and np.all(host(v) == 0.0)
+    t.close()
