@@ -76,3 +76,45 @@ def test_far_part_of_a_shallow_tree_is_zero(vf):
     t.velocity(dev(P.gamma), P.sigma, 8, vf.FP32, parts=vf.PART_FAR, out=(u, v))
     assert np.all(host(u) == 0.0) and np.all(host(v) == 0.0)
     t.close()
+
+
+def test_graph_capture_of_rebuild_and_velocity(vf):
+    """The fork / join of the two streams is captured into a graph; every replay
+    (eager work and synchronisation between replays) equals the eager result,
+    also after the inputs change in place."""
+    P = W.clusters(40000, seed=15, sigma=0.01)
+    L, p = 5, 12
+    print_case("streams_graph", n=P.n, levels=L, p=p)
+    x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
+    t = vf.Tree(x, y, L, p_max=p)
+    u = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+
+    def step():
+        t.rebuild(x, y)
+        t.velocity(g, P.sigma, p, vf.FP32, out=(u, v))
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    eager = (host(u).copy(), host(v).copy())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        u.zero_()
+        v.fill_(1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(u), eager[0]) and np.array_equal(host(v), eager[1]), rep
+    # new positions and circulations, same buffers: replay = eager evaluation
+    x.add_(1e-3)
+    g.mul_(-0.5)
+    graph.replay()
+    torch.cuda.synchronize()
+    got = (host(u).copy(), host(v).copy())
+    step()
+    assert np.array_equal(got[0], host(u)) and np.array_equal(got[1], host(v))
+    t.close()
