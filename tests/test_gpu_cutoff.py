@@ -111,3 +111,37 @@ def test_clusters_full_size_deeper_tree(vf):
     e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
     print(f"clusters_1m L7 p14 fp32: paper split {e_paper:.3e}, with cut-off {e32:.3e}")
     assert e32 < 1e-6 < e_paper
+
+
+def test_clusters_full_size_benchmark_configuration(vf):
+    """The configuration the benchmark times on N = 2^20 clustered particles:
+    p = 14, L = 7, FP32, radius sigma sqrt(2 ln 1e6) (where one pair's kernel
+    difference equals the 1e-6 tolerance), the autotuned near-field launch
+    shape; 256 sampled targets against the oracle FMM with that radius (float64
+    path 1e-12, FP32 path 1e-6) and the oracle direct sum (FP32 path, 1e-6)."""
+    from paper_0809_1810_amd import autotune as AT
+    P = W.config("clusters_1m")
+    L, p = 7, 14
+    radius = P.sigma * math.sqrt(2.0 * math.log(1e6))
+    assert radius < 2 * _w(P, L)  # not clamped
+    saved = vf.get_tuning()
+    AT.apply_for(P.n, L)
+    try:
+        print_case("clusters_1m_bench_config", n=P.n, levels=L, p=p, radius=radius,
+                   tuning=vf.get_tuning())
+        t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+        t.set_near_radius(radius)
+        g = dev(P.gamma)
+        u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+        u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+        t.close()
+    finally:
+        vf.set_tuning(tile=saved["tile"], waves=saved["waves"])
+    tg = W.sample_targets(P.n, 256, seed=32)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=tg, radius=radius)
+    assert rel_err(u64[tg], v64[tg], r.u, r.v)[0] < 1e-12
+    assert rel_err(u32[tg], v32[tg], r.u, r.v)[0] < 1e-6
+    ud, vd = K.direct_velocity(P.x, P.y, P.gamma, P.sigma, targets=tg)
+    e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
+    print(f"clusters_1m benchmark configuration: fp32 vs direct {e32:.3e}")
+    assert e32 < 1e-6
