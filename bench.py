@@ -4,7 +4,7 @@
 
 A step is one pass of the whole method on device-resident float64 inputs:
 quadtree rebuild (root box, keys, sort, leaf ranges) + FMM velocity (gather,
-P2M, M2M, M2L + L2L, P2P + L2P + combine), i.e. N / t particles per second.
+P2M, M2M, M2L + L2L, P2P, L2P), i.e. N / t particles per second.
 Two paths are timed on the same particles:
 
 * tuned: float32 arithmetic on scaled coefficients, (p, levels) chosen by the

@@ -1,7 +1,8 @@
-// Near field (P2P) with the far-field evaluation (L2P), the near + far sum and
-// the scatter back to the caller's order fused into one kernel
-// (Cruz & Barba 2008, eq. 10: f = f_near + f_far), at the particles (eq. 9) or
-// at a separate set of evaluation points sorted into the same leaves (eq. 8).
+// Near field (P2P), written in the caller's order, and the far-field
+// evaluation (L2P) that adds to it (Cruz & Barba 2008, eq. 10: f = f_near +
+// f_far; two launches, so that the expansion sweeps can run beside the near
+// field), at the particles (eq. 9) or at a separate set of evaluation points
+// sorted into the same leaves (eq. 8).
 //
 // P2P: for each target, the regularised Biot-Savart sum (eq. 6) over the
 // particles of the 3 x 3 local list of its leaf (Section 3.3.1); a source at
@@ -20,8 +21,8 @@
 // clustered particles, or on a lattice of evaluation points, a few leaves hold
 // most of the pairs.  One wave per part; a tile with one part writes its
 // result directly, the parts of a split tile write partial sums that a second
-// kernel adds in part order (so results do not depend on timing) before the
-// L2P.  The parts of the tiles of one leaf are interleaved so that
+// kernel adds in part order (so results do not depend on timing).  The parts
+// of the tiles of one leaf are interleaved so that
 // neighbouring waves read the same sources.  Workgroups keep the hardware's
 // round-robin dealing to the 8 XCDs (contiguous per-XCD ranges, or ordering
 // tiles by cost, were measured 1.7-2x slower on clustered inputs).

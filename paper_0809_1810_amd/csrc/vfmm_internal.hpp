@@ -130,7 +130,7 @@ struct TreeDev {
   P2PSched sched;        // near-field schedule of the particles as targets
 };
 
-// Evaluation points of the near-field + L2P kernel: the tree's own particles,
+// Evaluation points of the near-field and L2P kernels: the tree's own particles,
 // or a separate point set sorted into the tree's leaves (same tile size).
 // Points with NaN coordinates produce NaN velocities.
 struct TargetsDev {
