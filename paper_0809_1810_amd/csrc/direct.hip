@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_metrics_partial(const double* __restric
   s[0][threadIdx.x] = mx; s[1][threadIdx.x] = ss; s[2][threadIdx.x] = mr;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
+    if (int(threadIdx.x) < st) {
       s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + st]);
       s[1][threadIdx.x] += s[1][threadIdx.x + st];
       s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + st]);
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_metrics_final(const double* __restrict_
   s[0][threadIdx.x] = mx; s[1][threadIdx.x] = ss; s[2][threadIdx.x] = mr;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
+    if (int(threadIdx.x) < st) {
       s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + st]);
       s[1][threadIdx.x] += s[1][threadIdx.x + st];
       s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + st]);

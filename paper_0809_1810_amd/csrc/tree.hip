@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const double* __restrict__
   s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c; s[3][threadIdx.x] = d;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
+    if (int(threadIdx.x) < st) {
       int o = threadIdx.x + st;
       s[0][threadIdx.x] = dmin(s[0][threadIdx.x], s[0][o]);
       s[1][threadIdx.x] = dmax(s[1][threadIdx.x], s[1][o]);
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_root(const double* __restrict__ part, i
   s[0][threadIdx.x] = a; s[1][threadIdx.x] = b; s[2][threadIdx.x] = c; s[3][threadIdx.x] = d;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
+    if (int(threadIdx.x) < st) {
       int o = threadIdx.x + st;
       s[0][threadIdx.x] = dmin(s[0][threadIdx.x], s[0][o]);
       s[1][threadIdx.x] = dmax(s[1][threadIdx.x], s[1][o]);
