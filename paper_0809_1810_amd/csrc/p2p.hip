@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
   red[threadIdx.x] = c;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_sched_total(uint64_t* __restrict__ bsum
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) bsum[nb] = red[0];
