@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--radius-sigma", type=float, default=0.0,
                     help="with --p/--levels: distance cut-off radius in units of sigma")
     ap.add_argument("--cpu-targets", type=int, default=65536)
+    ap.add_argument("--audit-targets", type=int, default=0,
+                    help="sampled targets of the FP64 direct-sum audit (default 8192 for the "
+                         "2048^2 lattice, the selection workload, else 4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-lattice", action="store_true",
@@ -179,6 +182,7 @@ def main():
 
     P = W.config(a.workload)
     n = P.n
+    n_audit = a.audit_targets or (8192 if a.workload == "lattice_2048" else AUDIT_TARGETS)
     log(f"[bench] workload {P.name} n={n} sigma={P.sigma}")
     x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
     g = torch.from_numpy(P.gamma).cuda()
@@ -187,7 +191,7 @@ def main():
     probe.close()
 
     # ---------------- audit targets and FP64 direct reference
-    tg = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
+    tg = W.sample_targets(n, n_audit, seed=2024)
     tg_d = torch.from_numpy(tg).cuda()
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg_d)
     torch.cuda.synchronize()
@@ -329,7 +333,7 @@ def main():
         "config": {
             "workload": f"{P.name}: N={n}, sigma={P.sigma}, seeded synthetic",
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
-            "selector": selector, "selector_info": sel_info, "audit_targets": AUDIT_TARGETS,
+            "selector": selector, "selector_info": sel_info, "audit_targets": n_audit,
             "p2p_tile_waves": tuned["tile_waves"],
             "near_radius": ("auto: min(6 sigma, 2 w_L), distance cut-off of the near field"
                             if radius_t < 0 else radius_t),

@@ -156,3 +156,30 @@ def test_selector_gain_over_conservative_choice(vf):
     print(f"selected total {t_sel:.2f} ms vs conservative FP64 {t_cons:.2f} ms; network choices {chosen}/12")
     assert chosen >= 6
     assert t_sel < 0.7 * t_cons
+
+
+def test_selection_on_the_2048_lattice(vf):
+    """The selection workload at its own size: the Lamb-Oseen pair on a 2048^2
+    lattice (N = 4,194,304), tol = 1e-6, audited by the FP64 direct sum on 8192
+    sampled targets; the chosen evaluation is also checked against the oracle
+    direct sum on 32 other targets."""
+    from paper_0809_1810_amd import selector as S
+    from oracle import kernel as K
+    P = W.config("lattice_2048")
+    x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
+    r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights(), n_audit=8192, seed=7)
+    print_case("selector_lattice_2048", n=P.n,
+               **{k: r[k] for k in ("p", "levels", "radius", "fallback", "precision")},
+               emax=f"{r['audit_emax']:.2e}")
+    assert r["audit_emax"] <= 1e-6
+    prec = vf.FP32 if r["precision"] == "fp32" else vf.FP64
+    t = vf.Tree(x, y, r["levels"], p_max=r["p"])
+    t.set_near_radius(r["radius"])
+    u, v = (host(a) for a in t.velocity(g, P.sigma, r["p"], prec))
+    t.close()
+    tg = W.sample_targets(P.n, 32, seed=8)
+    ud, vd = K.direct_velocity(P.x, P.y, P.gamma, P.sigma, targets=tg)
+    # normalised by the largest velocity of the whole field (the audit's
+    # denominator comes from its own 8192 targets)
+    umax = float(np.max(np.hypot(u, v)))
+    assert float(np.max(np.hypot(u[tg] - ud, v[tg] - vd))) / umax <= 1e-6
