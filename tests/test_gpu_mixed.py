@@ -18,6 +18,7 @@ from oracle import fmm as F
 from tests.gpu_util import dev, host, print_case, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(scope="module")
@@ -82,3 +83,35 @@ def test_mode_switching_keeps_tables_consistent(vf):
             out = [host(a) for a in t.velocity(g, P.sigma, p, prec)]
             if p == 10:
                 assert np.array_equal(out[0], ref[prec][0]) and np.array_equal(out[1], ref[prec][1])
+
+
+def test_mixed_precision_full_size_clusters(vf):
+    """The mixed-precision configuration at its own size: N = 2^20 clustered
+    particles, L = 7, p = 12, the paper's split, M2L in FP32, FP16 and BF16 on
+    the matrix cores (FP32 accumulation) with FP32 near field.  Error bars
+    against the FP64 FMM at the same (p, L) over all particles and against the
+    FP64 direct sum on 4096 sampled targets; the 16-bit formats' error is bounded
+    by their rounding of the far field's inputs."""
+    P = W.config("clusters_1m")
+    L, p = 7, 12
+    print_case("mixed_full_size", n=P.n, levels=L, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    g = dev(P.gamma)
+    u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    fu, fv = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_FAR))
+    far_share = np.max(np.hypot(fu, fv)) / np.max(np.hypot(u64, v64))
+    tg = torch.from_numpy(W.sample_targets(P.n, 4096, seed=3)).cuda()
+    ud, vd = (host(a) for a in vf.direct_velocity(dev(P.x), dev(P.y), g, P.sigma, targets=tg))
+    tgh = tg.cpu().numpy()
+    errs = {}
+    for name, prec in (("fp32", vf.FP32), ("fp16", vf.M2L_FP16), ("bf16", vf.M2L_BF16)):
+        u, v = (host(a) for a in t.velocity(g, P.sigma, p, prec))
+        errs[name] = (rel_err(u, v, u64, v64), rel_err(u[tgh], v[tgh], ud, vd))
+    t.close()
+    print("far share", far_share, {k: f"vs FMM64 max {e[0][0]:.2e} rms {e[0][1]:.2e}; "
+                                      f"vs direct max {e[1][0]:.2e} rms {e[1][1]:.2e}"
+                                   for k, e in errs.items()})
+    assert errs["fp32"][0][0] < 1e-6
+    assert errs["fp32"][0][0] < errs["fp16"][0][0] < errs["bf16"][0][0]
+    assert errs["fp16"][0][0] < 30 * 2.0 ** -11 * far_share
+    assert errs["bf16"][0][0] < 30 * 2.0 ** -8 * far_share
