@@ -12,10 +12,10 @@
 // depends only on the multipoles of the upward sweep, so all levels run in one
 // launch.  The L2L chain (Section 3.3.3) then adds each parent's LE top-down.
 //
-// A 32-box column tile is computed with 32 x 32 matrix instructions (FP32: by
-// the 4 waves of a workgroup, each taking every 4th of the 27 offsets with the
-// next offset's operands loaded while the current ones multiply, the partial
-// tiles added through LDS; 16-bit formats: by one wave):
+// A 32-box column tile is computed with 32 x 32 matrix instructions by the 4
+// waves of a workgroup, each taking every 4th of the 27 offsets with the next
+// offset's operands loaded while the current ones multiply, the partial tiles
+// added through LDS:
 //   FP32  v_mfma_f32_32x32x2_f32  (A, B in float32)
 //   BF16  v_mfma_f32_32x32x16_bf16 (A, B rounded to bfloat16, RNE)
 //   FP16  v_mfma_f32_32x32x16_f16  (A, B rounded to float16, RNE)
@@ -147,13 +147,57 @@ __global__ void __launch_bounds__(256) k_m2l_mfma_f32(const float2* __restrict__
                    tile - lt.first[lev], packA, sh);
 }
 
+// 16-bit operands of one interaction offset: the packed operator columns (MT
+// row tiles x ks_n K-steps of 8 values per lane) and the lane's 8 source
+// entries per K-step, multiplied by the level's power of two and rounded.
 template <int MODE, int MT>
-__global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
-                                                  float2* __restrict__ le, int levels, int p,
-                                                  LevelTiles lt, const void* __restrict__ packA,
-                                                  const uint32_t* __restrict__ scales) {
+struct Offset16 {
+  static constexpr int KS = 2 * MT;  // ks_n = ceil(2p / 16) <= 2 MT
+  uint4 a[MT][KS];
+  uint4 b[KS];
+  __device__ __forceinline__ void load(const uint4* __restrict__ A, const float* src, bool sv,
+                                       int ks_n, int twop, int hi, int lane, float sc) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < ks_n) {
+        const int k0 = 16 * ks + 8 * hi;
+        float f[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = k0 + s;
+          const float v = src[k < twop ? k : twop - 1];  // in bounds; zero past 2p
+          f[s] = (sv && k < twop) ? v * sc : 0.f;
+        }
+        if constexpr (MODE == kModeBF16) {
+          v8bf h;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) h[s] = __bf16(f[s]);
+          b[ks] = __builtin_bit_cast(uint4, h);
+        } else {
+          v8h h;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) h[s] = _Float16(f[s]);
+          b[ks] = __builtin_bit_cast(uint4, h);
+        }
+#pragma unroll
+        for (int t = 0; t < MT; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64 + lane];
+      }
+    }
+  }
+};
+
+// BF16 / FP16: one workgroup per tile, the 27 offsets split over its 4 waves
+// (next offset's operands loaded while the current ones multiply), partial
+// tiles added through LDS, as the FP32 tile.
+template <int MODE, int MT>
+__global__ void __launch_bounds__(256) k_m2l_mfma16(const float2* __restrict__ me,
+                                                    float2* __restrict__ le, int levels, int p,
+                                                    LevelTiles lt, const uint4* __restrict__ packA,
+                                                    const uint32_t* __restrict__ scales) {
+  __shared__ float part[3][MT][16][64];
   const int lane = threadIdx.x & 63;
-  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = blockIdx.x;
   if (tile >= lt.first[levels + 1]) return;
   int lev = 2;
   while (tile >= lt.first[lev + 1]) ++lev;
@@ -179,44 +223,49 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 
-  for (int oy = cy - 3; oy <= cy + 2; ++oy) {
-    for (int ox = cx - 3; ox <= cx + 2; ++ox) {
-      if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
-      const int sx = bx - ox, sy = by - oy;
-      const bool sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
-      const float* src = reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
-      const int oi = m2l_index(ox, oy);
-      for (int ks = 0; ks < ks_n; ++ks) {
-        const int k0 = 16 * ks + 8 * hi;
-        float f[8];
+  auto src_of = [&](int ox, int oy, bool& sv) {
+    const int sx = bx - ox, sy = by - oy;
+    sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+    return reinterpret_cast<const float*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
+  };
+  auto a_of = [&](int ox, int oy) { return packA + int64_t(m2l_index(ox, oy)) * MT * ks_n * 64; };
+  Offset16<MODE, MT> cur, nxt;
+  int ox, oy;
+  bool sv;
+  nth_offset(wv, cx, cy, ox, oy);
+  cur.load(a_of(ox, oy), src_of(ox, oy, sv), sv, ks_n, twop, hi, lane, sc);
+  for (int j = wv; j < 27; j += 4) {
+    if (j + 4 < 27) {
+      nth_offset(j + 4, cx, cy, ox, oy);
+      const float* s2 = src_of(ox, oy, sv);
+      nxt.load(a_of(ox, oy), s2, sv, ks_n, twop, hi, lane, sc);
+    }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) f[s] = (sv && k0 + s < twop) ? src[k0 + s] * sc : 0.f;
-        const uint4* A = static_cast<const uint4*>(packA) + (int64_t(oi) * MT * ks_n + ks) * 64 + lane;
-        if constexpr (MODE == kModeBF16) {
-          v8bf b;
+    for (int ks = 0; ks < Offset16<MODE, MT>::KS; ++ks) {
+      if (ks < ks_n) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) b[s] = __bf16(f[s]);
-#pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            const uint4 a4 = A[int64_t(t) * ks_n * 64];
-            const v8bf a = __builtin_bit_cast(v8bf, a4);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
-          }
-        } else {
-          v8h b;
-#pragma unroll
-          for (int s = 0; s < 8; ++s) b[s] = _Float16(f[s]);
-#pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            const uint4 a4 = A[int64_t(t) * ks_n * 64];
-            const v8h a = __builtin_bit_cast(v8h, a4);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[t], 0, 0, 0);
-          }
+        for (int t = 0; t < MT; ++t) {
+          if constexpr (MODE == kModeBF16)
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, cur.a[t][ks]),
+                                                             __builtin_bit_cast(v8bf, cur.b[ks]),
+                                                             acc[t], 0, 0, 0);
+          else
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, cur.a[t][ks]),
+                                                            __builtin_bit_cast(v8h, cur.b[ks]),
+                                                            acc[t], 0, 0, 0);
         }
       }
     }
+    cur = nxt;
   }
-  if (!valid) return;
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[wv - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wv > 0 || !valid) return;
   const float inv = 1.f / sc;
   float* out = reinterpret_cast<float*>(le + level_offset(lev) * p + (int64_t(by) * m + bx) * p);
 #pragma unroll
@@ -224,7 +273,8 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(const float2* __restrict__ me,
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = t * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-      if (i < twop) out[i] = acc[t][r] * inv;
+      const float sum = acc[t][r] + part[0][t][r][lane] + part[1][t][r][lane] + part[2][t][r][lane];
+      if (i < twop) out[i] = sum * inv;
     }
 }
 
@@ -252,7 +302,6 @@ template <int MODE>
 void launch_mode(const TreeDev& t, int levels, int p, const LevelTiles& lt, const void* pack,
                  const uint32_t* scales, hipStream_t st) {
   const int mt = (2 * p + 31) / 32;
-  const unsigned blocks = unsigned((lt.first[levels + 1] + 3) / 4);
   const float2* me = static_cast<const float2*>(t.me);
   float2* le = static_cast<float2*>(t.le);
   if constexpr (MODE == kModeF32) {
@@ -265,12 +314,14 @@ void launch_mode(const TreeDev& t, int levels, int p, const LevelTiles& lt, cons
     else
       hipLaunchKernelGGL((k_m2l_mfma_f32<3>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);
   } else {
+    const unsigned tiles = unsigned(lt.first[levels + 1]);
+    const uint4* A = static_cast<const uint4*>(pack);
     if (mt == 1)
-      hipLaunchKernelGGL((k_m2l_mfma<MODE, 1>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+      hipLaunchKernelGGL((k_m2l_mfma16<MODE, 1>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A, scales);
     else if (mt == 2)
-      hipLaunchKernelGGL((k_m2l_mfma<MODE, 2>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+      hipLaunchKernelGGL((k_m2l_mfma16<MODE, 2>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A, scales);
     else
-      hipLaunchKernelGGL((k_m2l_mfma<MODE, 3>), dim3(blocks), dim3(256), 0, st, me, le, levels, p, lt, pack, scales);
+      hipLaunchKernelGGL((k_m2l_mfma16<MODE, 3>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A, scales);
   }
 }
 
