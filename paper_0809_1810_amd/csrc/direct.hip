@@ -3,9 +3,10 @@
 // Direct: u(x_i) = sum_{j != i} Gamma_j K_sigma(x_i - x_j) with the regularised
 // kernel of eq. 6, evaluated at all particles, at a list of particle indices, or
 // at separate evaluation points (eq. 8).
-// One thread per target; each block stages 256 sources at a time through LDS,
-// so every source is read once per block.  The self pair (and any coincident
-// pair) has a zero offset and contributes exactly zero.
+// 16 targets per workgroup, the sources split over its 16 waves and 4 lanes
+// per target, so that a few thousand audit targets still keep several waves
+// on every SIMD.  The self pair (and any coincident pair)
+// has a zero offset and contributes exactly zero.
 //
 // Metrics (Section 5.1, errors normalised by the maximum velocity):
 // out[0] = max_i |dW_i|, out[1] = sum_i |dW_i|^2, out[2] = max_i |W_ref,i|; and
@@ -19,15 +20,24 @@ namespace {
 
 constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
 
-__global__ void __launch_bounds__(256) k_direct(const double* __restrict__ x,
-                                                const double* __restrict__ y,
-                                                const double* __restrict__ g, int64_t n,
-                                                double kexp, const int64_t* __restrict__ targets,
-                                                const double* __restrict__ xt,
-                                                const double* __restrict__ yt, int64_t nt,
-                                                double* __restrict__ u, double* __restrict__ v) {
-  __shared__ double sx[256], sy[256], sg[256];
-  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+constexpr int kDirectWaves = 16;  // waves per workgroup, each a share of the sources
+constexpr int kDirectT = 16;      // targets per workgroup; 4 lanes per target
+
+// 16 targets per workgroup: lane = target (lane % 16) + 16 x sub-stream; wave w
+// takes the 64-source chunks w, w + 16, ..., sub-stream s every 4th source of
+// a chunk.  The 4 x 16 partial sums of a target are added in a fixed order
+// (shuffles, then waves in order through LDS): deterministic.  The FP64 pair
+// term is a long dependent chain (exp, division), so the parallelism is spread
+// over 4 lanes per target to keep several waves on every SIMD.
+__global__ void __launch_bounds__(64 * kDirectWaves) k_direct(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ g,
+    int64_t n, double kexp, const int64_t* __restrict__ targets, const double* __restrict__ xt,
+    const double* __restrict__ yt, int64_t nt, double* __restrict__ u, double* __restrict__ v) {
+  __shared__ double part[2][kDirectWaves][kDirectT];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tl = lane & (kDirectT - 1), sub = lane / kDirectT;
+  const int64_t t = blockIdx.x * int64_t(kDirectT) + tl;
   const bool valid = t < nt;
   double xi, yi;
   bool in_range = true;
@@ -42,26 +52,37 @@ __global__ void __launch_bounds__(256) k_direct(const double* __restrict__ x,
     yi = y[i];
   }
   double au = 0.0, av = 0.0;
-  for (int64_t base = 0; base < n; base += 256) {
-    const int64_t j = base + threadIdx.x;
-    __syncthreads();
-    sx[threadIdx.x] = j < n ? x[j] : 0.0;
-    sy[threadIdx.x] = j < n ? y[j] : 0.0;
-    sg[threadIdx.x] = j < n ? g[j] : 0.0;
-    __syncthreads();
-    const int cnt = int(n - base < 256 ? n - base : 256);
-    for (int k = 0; k < cnt; ++k) {
-      const double dx = xi - sx[k];
-      const double dy = yi - sy[k];
+  for (int64_t base = int64_t(wv) * 64; base < n; base += 64LL * kDirectWaves) {
+    const int64_t end = base + 64 < n ? base + 64 : n;
+    for (int64_t j = base + sub; j < end; j += 64 / kDirectT) {
+      const double dx = xi - x[j];
+      const double dy = yi - y[j];
       const double r2 = dx * dx + dy * dy;
-      const double f = r2 > 0.0 ? sg[k] * (-expm1(r2 * kexp) / r2) : 0.0;
+      const double f = r2 > 0.0 ? g[j] * (-expm1(r2 * kexp) / r2) : 0.0;
       au -= f * dy;
       av += f * dx;
     }
   }
+  // sub-streams of a target: lanes tl, tl + 16, tl + 32, tl + 48
+  for (int o = kDirectT; o < 64; o <<= 1) {
+    au += __shfl_xor(au, o, 64);
+    av += __shfl_xor(av, o, 64);
+  }
+  if (sub == 0) {
+    part[0][wv][tl] = au;
+    part[1][wv][tl] = av;
+  }
+  __syncthreads();
+  if (wv != 0 || sub != 0) return;
+  double su = 0.0, sv = 0.0;
+#pragma unroll
+  for (int w = 0; w < kDirectWaves; ++w) {
+    su += part[0][w][tl];
+    sv += part[1][w][tl];
+  }
   if (valid) {
-    u[t] = in_range ? au * kInv2Pi : __builtin_nan("");
-    v[t] = in_range ? av * kInv2Pi : __builtin_nan("");
+    u[t] = in_range ? su * kInv2Pi : __builtin_nan("");
+    v[t] = in_range ? sv * kInv2Pi : __builtin_nan("");
   }
 }
 
@@ -142,8 +163,8 @@ hipError_t launch_direct(const double* x, const double* y, const double* g, int6
                          double sigma, const int64_t* targets, const double* xt,
                          const double* yt, int64_t nt, double* u, double* v, hipStream_t st) {
   const double kexp = -1.0 / (2.0 * sigma * sigma);
-  hipLaunchKernelGGL(k_direct, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st, x, y, g, n,
-                     kexp, targets, xt, yt, nt, u, v);
+  hipLaunchKernelGGL(k_direct, dim3(unsigned((nt + kDirectT - 1) / kDirectT)),
+                     dim3(64 * kDirectWaves), 0, st, x, y, g, n, kexp, targets, xt, yt, nt, u, v);
   return hipGetLastError();
 }
 
