@@ -134,6 +134,16 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
 vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
                                 int32_t precision, double* u, double* v, void* stream);
 
+/* One call for one evaluation (eq. 9-10): vfmm_build_tree over (x, y) with the
+ * bounding square and p_max = p, vfmm_fmm_velocity, then the tree handle is
+ * released (the enqueued work still completes on `stream`).  workspace: at
+ * least vfmm_workspace_bytes(n, levels, p) bytes, as for vfmm_build_tree.
+ * Errors: those of the two calls. */
+vfmm_status_t vfmm_fmm_velocity_oneshot(const double* x, const double* y, const double* gamma,
+                                        int64_t n, double sigma, int32_t p, int32_t levels,
+                                        int32_t precision, double* u, double* v, void* workspace,
+                                        size_t ws_bytes, void* stream);
+
 /* As vfmm_fmm_velocity, writing only the near part (P2P over the local list,
  * eq. 10 first sum), only the far part (the expansions, eq. 10 second sum) or
  * both (`parts` = VFMM_PART_NEAR, VFMM_PART_FAR or VFMM_PART_ALL). */
@@ -363,6 +373,15 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream
 
 /* Releases the plan and its graph (not the workspace).  NULL is ignored. */
 void vfmm_batch_destroy(vfmm_batch_t batch);
+
+/* One call for one batched evaluation (Sections 3.1-3.3 per instance):
+ * vfmm_batch_create, vfmm_batch_run without a graph on `stream`, then the plan
+ * is released (the enqueued work still completes).  workspace: at least
+ * vfmm_batch_workspace_bytes(inst, count) bytes.  The plan's tables are
+ * uploaded synchronously, so this call blocks the host briefly.
+ * Errors: those of the two calls. */
+vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count, void* workspace,
+                                        size_t ws_bytes, void* stream);
 
 /* Distance cut-off of the near field (Section 4.1: the error of taking the
  * singular kernel for a far pair is bounded through the distance a of the

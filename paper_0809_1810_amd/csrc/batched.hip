@@ -957,4 +957,14 @@ void vfmm_batch_destroy(vfmm_batch_t b) {
   delete b;
 }
 
+vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count, void* workspace,
+                                        size_t ws_bytes, void* stream) {
+  vfmm_batch_t b = nullptr;
+  vfmm_status_t s = vfmm_batch_create(inst, count, workspace, ws_bytes, &b);
+  if (s) return s;
+  s = vfmm_batch_run(b, 0, stream);
+  vfmm_batch_destroy(b);
+  return s;
+}
+
 }  // extern "C"

@@ -457,6 +457,18 @@ vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t t, const double* gamma, double sigma
   return vfmm_fmm_velocity_parts(t, gamma, sigma, p, precision, VFMM_PART_ALL, u, v, stream);
 }
 
+vfmm_status_t vfmm_fmm_velocity_oneshot(const double* x, const double* y, const double* gamma,
+                                        int64_t n, double sigma, int32_t p, int32_t levels,
+                                        int32_t precision, double* u, double* v, void* workspace,
+                                        size_t ws_bytes, void* stream) {
+  vfmm_tree_t t = nullptr;
+  vfmm_status_t s = vfmm_build_tree(x, y, n, levels, nullptr, p, workspace, ws_bytes, stream, &t);
+  if (s) return s;
+  s = vfmm_fmm_velocity(t, gamma, sigma, p, precision, u, v, stream);
+  vfmm_tree_destroy(t);
+  return s;
+}
+
 vfmm_status_t vfmm_direct_velocity(const double* x, const double* y, const double* gamma,
                                    int64_t n, double sigma, const int64_t* targets,
                                    int64_t n_targets, double* u, double* v, void* stream) {

@@ -46,6 +46,12 @@ _SIGS = {
                                     C.POINTER(C.c_void_p)]),
     "vfmm_fmm_velocity": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_fmm_velocity_oneshot": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                              C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                              C.c_void_p]),
+    "vfmm_fmm_velocity_batched": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                                              C.c_void_p]),
     "vfmm_fmm_velocity_parts": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                             C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                             C.c_void_p]),
@@ -339,6 +345,29 @@ def fmm_velocity(x, y, gamma, sigma: float, p: int, levels: int, precision=FP64,
     return t.velocity(gamma, sigma, p, precision)
 
 
+def fmm_velocity_oneshot(x, y, gamma, sigma: float, p: int, levels: int, precision=FP64,
+                         out=None):
+    """vfmm_fmm_velocity_oneshot: tree build + evaluation in one library call
+    (bounding-square root); the workspace is allocated here, by the caller."""
+    torch = _torch()
+    x = _dev_f64(x, "x"); y = _dev_f64(y, "y"); gamma = _dev_f64(gamma, "gamma")
+    n = int(x.shape[0])
+    precision = PRECISIONS.get(precision, precision)
+    nb = C.c_size_t(0)
+    _check(lib().vfmm_workspace_bytes(n, int(levels), int(p), C.byref(nb)), "vfmm_workspace_bytes")
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=x.device)
+    if out is None:
+        u = torch.empty(n, dtype=torch.float64, device=x.device)
+        v = torch.empty(n, dtype=torch.float64, device=x.device)
+    else:
+        u, v = out
+    _check(lib().vfmm_fmm_velocity_oneshot(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n,
+                                           float(sigma), int(p), int(levels), int(precision),
+                                           u.data_ptr(), v.data_ptr(), ws.data_ptr(), ws.numel(),
+                                           _stream()), "vfmm_fmm_velocity_oneshot")
+    return u, v  # ws is freed on the current stream, after the call's work
+
+
 def direct_velocity(x, y, gamma, sigma: float, targets=None, out=None):
     torch = _torch()
     x = _dev_f64(x, "x"); y = _dev_f64(y, "y"); gamma = _dev_f64(gamma, "gamma")
@@ -548,6 +577,13 @@ class Batch:
 
     def run(self, use_graph=False):
         _check(lib().vfmm_batch_run(self._h, int(bool(use_graph)), _stream()), "vfmm_batch_run")
+
+    def run_oneshot(self):
+        """vfmm_fmm_velocity_batched on the same instances and workspace: plan,
+        run and release in one library call (this object's plan is untouched)."""
+        _check(lib().vfmm_fmm_velocity_batched(self._arr, len(self.u), self.workspace.data_ptr(),
+                                               self.workspace.numel(), _stream()),
+               "vfmm_fmm_velocity_batched")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -155,3 +155,15 @@ def test_advect_calls_reject_before_device_work():
     assert l.vfmm_advect(None, fake, fake, fake, 0.1, 5, 0, 0.01, 1, fake, 1 << 30,
                          None) == B.ERR_INVALID_ARG
     assert l.vfmm_tree_set_near_radius(None, 0.1) == B.ERR_INVALID_ARG
+
+
+def test_one_call_entry_points_reject_before_device_work():
+    lib = _lib()
+    fake = C.c_void_p(256)  # never dereferenced: the checks fail first
+    assert lib.vfmm_fmm_velocity_oneshot(None, fake, fake, 10, 0.1, 5, 3, 1, fake, fake, fake,
+                                         1 << 20, None) == -1
+    assert lib.vfmm_fmm_velocity_oneshot(fake, fake, fake, 0, 0.1, 5, 3, 1, fake, fake, fake,
+                                         1 << 20, None) == -1
+    assert lib.vfmm_fmm_velocity_batched(None, 1, fake, 1 << 20, None) == -1
+    arr = (B.Instance * 1)()
+    assert lib.vfmm_fmm_velocity_batched(arr, 0, fake, 1 << 20, None) == -1

@@ -91,3 +91,18 @@ def test_batch_rejects_bad_instances(vf):
     bad[0]["p"] = 8; bad[0]["levels"] = 7
     with pytest.raises(vf.VfmmError):
         vf.Batch(bad)
+
+
+def test_one_call_batched_equals_plan_and_run(vf):
+    """vfmm_fmm_velocity_batched (plan, run, release in one call) gives the same
+    bits as vfmm_batch_create + vfmm_batch_run."""
+    insts = _instances(12, seed=43, n_range=(500, 6000), levels=(2, 5))
+    b = vf.Batch(insts)
+    b.run()
+    ref = [(host(u).copy(), host(v).copy()) for u, v in zip(b.u, b.v)]
+    for u in b.u:
+        u.zero_()
+    torch.cuda.synchronize()
+    b.run_oneshot()
+    for i, (u, v) in enumerate(zip(b.u, b.v)):
+        assert np.array_equal(host(u), ref[i][0]) and np.array_equal(host(v), ref[i][1]), i

@@ -234,3 +234,17 @@ def test_tile_shapes_match_oracle(vf, tile, waves):
     assert np.max(np.hypot(un[idx] - r.near_u, vn[idx] - r.near_v)) / den < 1e-13
     assert rel_err(u, v, u0, v0)[0] < 1e-6
     assert np.array_equal(u, u2) and np.array_equal(v, v2)
+
+
+def test_oneshot_equals_tree_path(vf):
+    """vfmm_fmm_velocity_oneshot (build + evaluate + release in one call) gives
+    the same bits as vfmm_build_tree + vfmm_fmm_velocity."""
+    P = W.clusters(20000, seed=17, sigma=0.01)
+    x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
+    for prec in (vf.FP64, vf.FP32):
+        print_case("oneshot", n=P.n, levels=5, p=12, precision=prec)
+        u1, v1 = (host(a) for a in vf.fmm_velocity_oneshot(x, y, g, P.sigma, 12, 5, prec))
+        t = vf.Tree(x, y, 5, p_max=12)
+        u2, v2 = (host(a) for a in t.velocity(g, P.sigma, 12, prec))
+        t.close()
+        assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
