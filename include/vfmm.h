@@ -125,10 +125,12 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
  *   p         : expansion terms, 1 <= p <= p_max of the tree (eq. 21).
  *   precision : VFMM_FP64, VFMM_FP32, VFMM_M2L_BF16 or VFMM_M2L_FP16.
  * Streams: the call is ordered on `stream` (after the work queued on it before
- * the call, before the work queued after it).  Inside, the expansion sweeps
- * (tables, P2M, M2M, M2L + L2L) run on a stream owned by the tree (created with
- * it, default priority), concurrently with the near field on `stream`; `stream`
- * waits for them (an event) before the far field is added.  Calls on one tree
+ * the call, before the work queued after it).  Inside, the gather of the
+ * circulations and the expansion sweeps (tables, P2M, M2M, M2L + L2L) run on a
+ * stream owned by the tree (created with it, default priority), concurrently
+ * with the near-field schedule and the near field on `stream`; `stream` waits
+ * for the gather (an event) before the near field and for the sweeps before
+ * the far field is added.  Calls on one tree
  * from different streams race, as they share the tree's workspace.
  * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
 vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
@@ -248,9 +250,11 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
  * 0 gather circulations (and, for vfmm_fmm_velocity_at, the sort of the
  * evaluation points), 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
  * 4 M2L + L2L (levels 2..L), 5 near-field work schedule, 6 near field (P2P
- * kernel and the sum of the parts of split tiles), 7 L2P (adds the far field,
- * after waiting for phases 1-4).  Phases 1-4 run on the tree's stream while
- * 5-6 run on the caller's, so their times overlap.  After
+ * kernel, after waiting for the gather), 7 L2P (after waiting for phases 1-4:
+ * sums the parts of split near-field tiles, adds the far field and writes the
+ * result).  When a call evaluates both parts, the gather and phases 1-4 run
+ * on the tree's stream while 5-6 run on the caller's, so their times
+ * overlap.  After
  * vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
  * next max_calls evaluations record HIP events at the beginning and end of
  * each phase on the stream that runs it (no synchronisation).

@@ -1,8 +1,11 @@
-// Near field (P2P), written in the caller's order, and the far-field
-// evaluation (L2P) that adds to it (Cruz & Barba 2008, eq. 10: f = f_near +
-// f_far; two launches, so that the expansion sweeps can run beside the near
-// field), at the particles (eq. 9) or at a separate set of evaluation points
-// sorted into the same leaves (eq. 8).
+// Near field (P2P) and far-field evaluation (L2P) (Cruz & Barba 2008, eq. 10:
+// f = f_near + f_far), at the particles (eq. 9) or at a separate set of
+// evaluation points sorted into the same leaves (eq. 8).  Two launches, so
+// that the expansion sweeps can run beside the near field: the P2P kernel
+// leaves its sums in sorted order (one value per target of a single-part
+// tile, one partial sum per part of a split tile); the L2P kernel adds the
+// parts of split tiles in part order, adds the far field and writes u, v once,
+// in the caller's order.
 //
 // P2P: for each target, the regularised Biot-Savart sum (eq. 6) over the
 // particles of the 3 x 3 local list of its leaf (Section 3.3.1); a source at
@@ -21,7 +24,7 @@
 // clustered particles, or on a lattice of evaluation points, a few leaves hold
 // most of the pairs.  One wave per part; a tile with one part writes its
 // result directly, the parts of a split tile write partial sums that a second
-// kernel adds in part order (so results do not depend on timing).  The parts
+// L2P kernel adds in part order (so results do not depend on timing).  The parts
 // of the tiles of one leaf are interleaved so that
 // neighbouring waves read the same sources.  Workgroups keep the hardware's
 // round-robin dealing to the 8 XCDs (contiguous per-XCD ranges, or ordering
@@ -242,10 +245,9 @@ __global__ void __launch_bounds__(512) k_p2p(
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
     const typename Types<R>::Part* __restrict__ tpart, const Part64* __restrict__ tpart64,
     const Tile* __restrict__ ttiles, const float4* __restrict__ ttile_box,
-    const int32_t* __restrict__ tperm, const P2PPart* __restrict__ parts,
-    const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
+    const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
     const double* __restrict__ root, int levels, PairK<R> pk, double sd, float far2, float ser2,
-    int nseg, double cut2, double* __restrict__ u, double* __restrict__ v) {
+    int nseg, double cut2, double2* __restrict__ nearv) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   // FP32: sources and targets in units of the Gaussian width (factor sd);
   // FP64: plain units (sd = 1)
@@ -432,60 +434,59 @@ __global__ void __launch_bounds__(512) k_p2p(
       if (active && grp == 0) partial[int64_t(slot) * kTile + tl] = make_double2(nu, nv);
       continue;
     }
-    if (active && grp == 0) {
-      const int32_t o = tperm[i];
-      u[o] = nu * kInv2Pi;
-      v[o] = nv * kInv2Pi;
-    }
+    if (active && grp == 0) nearv[i] = make_double2(nu * kInv2Pi, nv * kInv2Pi);
   }
 }
 
-// Split tiles: add the partial sums of their parts in part order.
-__global__ void __launch_bounds__(256) k_p2p_reduce(
-    const Tile* __restrict__ ttiles, const int32_t* __restrict__ tntiles,
-    const int32_t* __restrict__ tperm, const uint32_t* __restrict__ p_off,
-    const uint32_t* __restrict__ s_off, const double2* __restrict__ partial,
-    double* __restrict__ u, double* __restrict__ v) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= *tntiles) return;
-  const uint32_t np = p_off[wid + 1] - p_off[wid];
-  if (np <= 1) return;
-  const int lane = threadIdx.x & 63;
-  const Tile tile = ttiles[wid];
-  if (lane >= tile.count) return;
-  const uint32_t s0 = s_off[wid];
-  double nu = 0.0, nv = 0.0;
-  for (uint32_t k = 0; k < np; ++k) {
-    const double2 q = partial[int64_t(s0 + k) * kTile + lane];
-    nu += q.x;
-    nv += q.y;
-  }
-  const int32_t o = tperm[tile.start + lane];
-  u[o] = nu * kInv2Pi;
-  v[o] = nv * kInv2Pi;
-}
-
-// Far field at the targets (L2P, eq. 25 on the scaled LEs of the leaves): one
-// wave per target tile; adds to the near field already in u, v (add != 0) or
-// writes the far field alone.
+// Result at the targets, one wave per target tile: the near field (near != 0)
+// of a single-part tile from nearv, of a split tile the sum of its parts'
+// partial sums in part order; plus the far field (L2P, eq. 25 on the scaled
+// LEs of the leaves; p = 0: none); written in the caller's order.
 template <typename R, int PMAX>
 __global__ void __launch_bounds__(256) k_l2p(
     const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
     const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
     const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
-    int add, double* __restrict__ u, double* __restrict__ v) {
+    int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
+    const double2* __restrict__ partial, const double2* __restrict__ nearv,
+    double* __restrict__ u, double* __restrict__ v) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= *tntiles) return;
   const int lane = threadIdx.x & 63;
   const Tile tile = ttiles[wid];
   if (lane >= tile.count) return;
   const int32_t i = tile.start + lane;
-  const auto tp = tpart[i];  // leaf-local, plain units
-  double fu, fv;
-  l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, root[3], p, fu, fv);
+  double fu = 0.0, fv = 0.0;
+  if (p > 0) {
+    const auto tp = tpart[i];  // leaf-local, plain units
+    l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, root[3], p, fu, fv);
+  }
   const int32_t o = tperm[i];
-  u[o] = add ? u[o] + fu : fu;
-  v[o] = add ? v[o] + fv : fv;
+  if (!near) {
+    u[o] = fu;
+    v[o] = fv;
+    return;
+  }
+  double nu, nv;
+  const uint32_t np = p_off[wid + 1] - p_off[wid];
+  if (np > 1) {
+    const uint32_t s0 = s_off[wid];
+    nu = 0.0;
+    nv = 0.0;
+    for (uint32_t k = 0; k < np; ++k) {
+      const double2 q = partial[int64_t(s0 + k) * kTile + lane];
+      nu += q.x;
+      nv += q.y;
+    }
+    nu *= kInv2Pi;
+    nv *= kInv2Pi;
+  } else {
+    const double2 q = nearv[i];
+    nu = q.x;
+    nv = q.y;
+  }
+  u[o] = p > 0 ? nu + fu : nu;
+  v[o] = p > 0 ? nv + fv : nv;
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -513,7 +514,7 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, in
 
 template <typename R, int LPT>
 void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, int nseg,
-              double cut2, double* u, double* v, hipStream_t st) {
+              double cut2, hipStream_t st) {
   using Part = typename Types<R>::Part;
   const auto* part = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32s));
@@ -535,26 +536,24 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   const P2PSched& s = tg.sched;
   hipLaunchKernelGGL((k_p2p<R, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st, part,
                      t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles, tg.tile_box,
-                     tg.perm, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
-                     far2, ser2, nseg, cut2, u, v);
-  hipLaunchKernelGGL(k_p2p_reduce, dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st, tg.tiles,
-                     tg.ntiles, tg.perm, s.p_off, s.s_off, s.partial, u, v);
+                     s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
+                     far2, ser2, nseg, cut2, s.near);
 }
 
 template <typename R>
 void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, double radius,
-              double* u, double* v, hipStream_t st) {
+              hipStream_t st) {
   // radius 0: the paper's split; < 0: the distance beyond which the two kernels
   // agree in this precision; the kernel clamps it to 2 w_L
   const int nseg = radius == 0.0 ? kSegNear : kSegRing;
   const double cut2 = radius > 0.0 ? radius * radius : P2PMath<R>::kFarSigma2 * sigma * sigma;
-  if (t.tile == 16) launch_t<R, 4>(t, tg, levels, sigma, nseg, cut2, u, v, st);
-  else if (t.tile == 32) launch_t<R, 2>(t, tg, levels, sigma, nseg, cut2, u, v, st);
-  else launch_t<R, 1>(t, tg, levels, sigma, nseg, cut2, u, v, st);
+  if (t.tile == 16) launch_t<R, 4>(t, tg, levels, sigma, nseg, cut2, st);
+  else if (t.tile == 32) launch_t<R, 2>(t, tg, levels, sigma, nseg, cut2, st);
+  else launch_t<R, 1>(t, tg, levels, sigma, nseg, cut2, st);
 }
 
 template <typename R, int PMAX>
-void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int add, double* u,
+void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int near, double* u,
                   double* v, hipStream_t st) {
   using C = typename Types<R>::C;
   using Part = typename Types<R>::Part;
@@ -562,17 +561,18 @@ void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int
       sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
   const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
   hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st, tpart,
-                     tg.tiles, tg.ntiles, tg.perm, t.root, p, le, add, u, v);
+                     tg.tiles, tg.ntiles, tg.perm, t.root, p, le, near, tg.sched.p_off,
+                     tg.sched.s_off, tg.sched.partial, tg.sched.near, u, v);
 }
 
 template <typename R>
-void launch_l2p_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, int add, double* u,
+void launch_l2p_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, int near, double* u,
                   double* v, hipStream_t st) {
-  if (p <= 8) launch_l2p_t<R, 8>(t, tg, levels, p, add, u, v, st);
-  else if (p <= 16) launch_l2p_t<R, 16>(t, tg, levels, p, add, u, v, st);
-  else if (p <= 24) launch_l2p_t<R, 24>(t, tg, levels, p, add, u, v, st);
-  else if (p <= 32) launch_l2p_t<R, 32>(t, tg, levels, p, add, u, v, st);
-  else launch_l2p_t<R, 40>(t, tg, levels, p, add, u, v, st);
+  if (p <= 8) launch_l2p_t<R, 8>(t, tg, levels, p, near, u, v, st);
+  else if (p <= 16) launch_l2p_t<R, 16>(t, tg, levels, p, near, u, v, st);
+  else if (p <= 24) launch_l2p_t<R, 24>(t, tg, levels, p, near, u, v, st);
+  else if (p <= 32) launch_l2p_t<R, 32>(t, tg, levels, p, near, u, v, st);
+  else launch_l2p_t<R, 40>(t, tg, levels, p, near, u, v, st);
 }
 
 }  // namespace
@@ -583,16 +583,16 @@ hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int level
 }
 
 hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,
-                      double radius, double* u, double* v, hipStream_t st) {
-  if (prec == kFP64) launch_r<double>(t, tg, levels, sigma, radius, u, v, st);
-  else launch_r<float>(t, tg, levels, sigma, radius, u, v, st);
+                      double radius, hipStream_t st) {
+  if (prec == kFP64) launch_r<double>(t, tg, levels, sigma, radius, st);
+  else launch_r<float>(t, tg, levels, sigma, radius, st);
   return hipGetLastError();
 }
 
-hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec, int add,
-                      double* u, double* v, hipStream_t st) {
-  if (prec == kFP64) launch_l2p_r<double>(t, tg, levels, p, add, u, v, st);
-  else launch_l2p_r<float>(t, tg, levels, p, add, u, v, st);
+hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
+                      int near, double* u, double* v, hipStream_t st) {
+  if (prec == kFP64) launch_l2p_r<double>(t, tg, levels, p, near, u, v, st);
+  else launch_l2p_r<float>(t, tg, levels, p, near, u, v, st);
   return hipGetLastError();
 }
 

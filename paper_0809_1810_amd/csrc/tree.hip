@@ -223,9 +223,46 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t* __restrict_
   }
 }
 
+// As k_scan_apply, with tmp holding the block totals themselves: each block
+// adds up the totals of the blocks before it (a fixed order, so the result
+// equals the three-phase scan's).  For up to kScanFusedBlocks blocks.
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply_totals(uint32_t* __restrict__ a,
+                                                                  int64_t n,
+                                                                  const uint32_t* __restrict__ tmp) {
+  uint32_t before = 0;
+  for (int k = threadIdx.x; k < int(blockIdx.x); k += kScanBlock) before += tmp[k];
+  uint32_t pre;
+  block_excl_scan(before, &pre);
+  const int64_t base = blockIdx.x * int64_t(kScanPerBlock) + threadIdx.x * int64_t(kScanItems);
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? a[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + pre;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) a[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+constexpr int64_t kScanFusedBlocks = 2048;
+
+// Up to kScanFusedBlocks blocks of kScanPerBlock elements: block totals, then
+// one pass that scans each block after its predecessors' totals (two launches,
+// one if the array fits one block); beyond that the three-phase scan.
 hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
+  if (nb <= kScanFusedBlocks) {
+    if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+    hipLaunchKernelGGL(k_scan_apply_totals, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
   hipLaunchKernelGGL(k_scan_tmp, dim3(1), dim3(kScanBlock), 0, st, tmp, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
@@ -487,7 +524,8 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
                      reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
                      reinterpret_cast<double2*>(ws + lay.sched_partial),
-                     reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp};
+                     reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp,
+                     reinterpret_cast<double2*>(ws + lay.sched_near)};
   t.max_tiles = lay.max_tiles;
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
                      tile, t.tiles, t.ntiles);
@@ -534,7 +572,8 @@ hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, 
                        reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
                        reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
                        reinterpret_cast<double2*>(ws + lay.sched_partial),
-                       reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp};
+                       reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp,
+                     reinterpret_cast<double2*>(ws + lay.sched_near)};
   out = TargetsDev{p64, p32, tiles, ntiles, tbox, toff, i0, lay.max_tiles, sched};
   return hipGetLastError();
 }

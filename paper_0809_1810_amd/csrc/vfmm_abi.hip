@@ -31,13 +31,16 @@ struct vfmm_tree_s {
   std::vector<hipEvent_t> ev;  // phase-timing ring: begin and end of each phase, per call
   int t_slots;
   int t_used;
-  // the expansion sweeps run on `side` (default priority), concurrently with
-  // the near field on the caller's stream: fork after the gather, join before L2P
+  // the gather and the expansion sweeps run on `side` (default priority),
+  // concurrently with the near-field schedule and the near field on the
+  // caller's stream: fork at the start, the near field waits for the gather
+  // (gathered), L2P for the sweeps (join)
   hipStream_t side;
-  hipEvent_t fork, join;
+  hipEvent_t fork, gathered, join;
   ~vfmm_tree_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
+    if (gathered) (void)hipEventDestroy(gathered);
     if (join) (void)hipEventDestroy(join);
     if (side) (void)hipStreamDestroy(side);
   }
@@ -137,6 +140,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
   L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
   L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
+  L.sched_near = take(size_t(n) * sizeof(double2));
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
   L.part32s = take(size_t(n) * sizeof(Part32));
@@ -205,6 +209,7 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   t->last_prec = -1;
   hipError_t e = hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&t->gathered, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->join, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete t;
@@ -261,12 +266,13 @@ struct Marks {
 
 enum Phase { kPhGather = 0, kPhTables, kPhP2M, kPhM2M, kPhM2L, kPhSched, kPhP2P, kPhL2P };
 
-// One evaluation on target set tg (Fig. 3): circulations into the sorted
-// particles; then, on the tree's side stream, the operator tables, P2M, M2M and
-// M2L + L2L while the caller's stream builds the near-field schedule and runs
-// the near field; after both, L2P adds the far field.  Every launch is ordered
-// after the work queued on st before the call, and st waits for the side
-// stream before L2P, so the call behaves as one ordered sequence on st.
+// One evaluation on target set tg (Fig. 3): on the tree's side stream, the
+// circulations into the sorted particles, the operator tables, P2M, M2M and
+// M2L + L2L, while the caller's stream builds the near-field schedule and,
+// once the circulations are in place, runs the near field; after both, L2P
+// adds the far field to the near field and writes the result.  Every launch is
+// ordered after the work queued on st before the call, and st waits for the
+// side stream before L2P, so the call behaves as one ordered sequence on st.
 vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma, double sigma,
                        int32_t p, int32_t precision, int32_t parts, double* u, double* v,
                        const Marks& mark, hipStream_t st) {
@@ -275,16 +281,22 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
   const bool near = parts & VFMM_PART_NEAR;
   const bool far = L >= 2 && (parts & VFMM_PART_FAR);
-  // (the caller has opened the gather phase)
-  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, st);
-  if (e != hipSuccess) return hip_fail(e, "gather");
-  mark.end(kPhGather, st);
-  // the sweeps go to the side stream only when there is near-field work to overlap
+  // the gather and the sweeps go to the side stream only when there is
+  // near-field work to overlap
   hipStream_t sw = near && far ? t->side : st;
+  hipError_t e = hipSuccess;
   if (sw != st) {
     e = hipEventRecord(t->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(sw, t->fork, 0);
     if (e != hipSuccess) return hip_fail(e, "fork");
+  }
+  // (the caller has opened the gather phase on st)
+  e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, sw);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  mark.end(kPhGather, sw);
+  if (sw != st) {
+    e = hipEventRecord(t->gathered, sw);
+    if (e != hipSuccess) return hip_fail(e, "gather event");
   }
   mark.begin(kPhTables, sw);
   if (far && t->ops_p != p) {
@@ -331,9 +343,13 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
     if (e != hipSuccess) return hip_fail(e, "P2P schedule");
   }
   mark.end(kPhSched, st);
+  if (sw != st) {
+    e = hipStreamWaitEvent(st, t->gathered, 0);
+    if (e != hipSuccess) return hip_fail(e, "gather event");
+  }
   mark.begin(kPhP2P, st);
   if (near) {
-    e = launch_p2p(t->dev, tg, L, prec, sigma, t->near_radius, u, v, st);
+    e = launch_p2p(t->dev, tg, L, prec, sigma, t->near_radius, st);
     if (e != hipSuccess) return hip_fail(e, "P2P");
   }
   mark.end(kPhP2P, st);
@@ -342,11 +358,10 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
     e = hipStreamWaitEvent(st, t->join, 0);
     if (e != hipSuccess) return hip_fail(e, "join");
   }
-  if (far || !near) {
-    // the far field; asked alone of a tree without one (L < 2), zeros (order 0)
-    e = launch_l2p(t->dev, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
-    if (e != hipSuccess) return hip_fail(e, "L2P");
-  }
+  // near field plus far field (order 0: none, e.g. the far part alone of a
+  // tree without one, L < 2, which is zeros), in the caller's order
+  e = launch_l2p(t->dev, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
+  if (e != hipSuccess) return hip_fail(e, "L2P");
   mark.end(kPhL2P, st);
   return VFMM_OK;
 }
@@ -385,6 +400,7 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
   L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
   L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
+  L.sched_near = take(size_t(nt) * sizeof(double2));
   L.part64 = take(size_t(nt) * sizeof(Part64));
   L.part32 = take(size_t(nt) * sizeof(Part32));
   L.total = off;

@@ -83,6 +83,7 @@ struct P2PSched {
   double2* partial;   // [2 p2p_parts(max_tiles)][kTile] near-field sums (u, v) of one part
   uint64_t* bsum;     // [ceil((max_tiles + 1) / 256) + 1] chunk sums per block, then total
   uint32_t* scan_tmp;
+  double2* near;      // [targets] near field (times 1 / 2 pi) of single-part tiles, sorted order
 };
 inline int64_t sched_bsum_len(int64_t max_tiles) { return (max_tiles + 1 + 255) / 256 + 1; }
 
@@ -100,7 +101,7 @@ inline __host__ __device__ int64_t n_boxes_2_to(int L) {
 struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
-  size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum;
+  size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, sched_near;
   size_t part64, part32, part32s, me, le, ops, reduce, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
@@ -153,7 +154,8 @@ inline TargetsDev self_targets(const TreeDev& t, const Layout& lay) {
 // Workspace of a separate evaluation-point set of nt points at leaf level L.
 struct TargetLayout {
   size_t keys0, keys1, idx0, idx1, counts, scan_tmp, leaf_start, tile_off, tiles, ntiles,
-      tile_box, sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, part64,
+      tile_box, sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum,
+      sched_near, part64,
       part32, total;
   int64_t nt, nleaves, max_tiles, sort_blocks, count_len;
 };
@@ -187,15 +189,17 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
 // radius: distance cut-off of the near field (0 = off, < 0 = the distance at
 // which the regularised and singular kernels agree in this precision).
 // The near-field work schedule of target set tg (launch_p2p_schedule), then
-// the near-field kernels over it (launch_p2p, same radius), which write u, v.
+// the near-field kernel over it (launch_p2p, same radius), which leaves its
+// sums in the schedule's buffers (tg.sched.near, tg.sched.partial).
 hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
                                hipStream_t stream);
 hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,
-                      double radius, double* u, double* v, hipStream_t stream);
-// Far field of the leaves' LEs at the targets: added to u, v (add != 0) or
-// written; p = 0 writes (or adds) zeros.
-hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec, int add,
-                      double* u, double* v, hipStream_t stream);
+                      double radius, hipStream_t stream);
+// Writes u, v in the caller's order: the near-field sums of launch_p2p
+// (near != 0; the parts of split tiles added in part order) plus the far field
+// of the leaves' LEs of order p (p = 0: none; with neither, zeros).
+hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p, int prec,
+                      int near, double* u, double* v, hipStream_t stream);
 // Sorts nt evaluation points into the leaves of tree t (built with `levels`),
 // with leaf-local coordinates (NaN outside the closed root square) and tiles of
 // t.tile points.
