@@ -297,7 +297,7 @@ def main():
         r_cpu = 0.0
         if radius_t != 0.0:
             r_auto = (6.0 if prec_t != vf.FP64 else math.sqrt(76.0)) * P.sigma
-            r_cpu = min(r_auto if radius_t < 0 else radius_t, 2.0 * side / 2 ** L_t)
+            r_cpu = min(r_auto if radius_t < 0 else radius_t, vf.NEAR_RINGS_MAX * side / 2 ** L_t)
         log(f"[bench] cpu baseline: oracle FMM (p={p_t}, L={L_t}, radius={r_cpu:.4g}) "
             f"on {len(ts)} targets")
         ctx = threadpool_limits(1) if threadpool_limits else None
@@ -335,7 +335,7 @@ def main():
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
             "selector": selector, "selector_info": sel_info, "audit_targets": n_audit,
             "p2p_tile_waves": tuned["tile_waves"],
-            "near_radius": ("auto: min(6 sigma, 2 w_L), distance cut-off of the near field"
+            "near_radius": ("auto: min(6 sigma, 4 w_L), distance cut-off of the near field"
                             if radius_t < 0 else radius_t),
             "near_radius_sigma": radius_tag(radius_t, P.sigma),
         },
@@ -522,7 +522,7 @@ def bench_eval_points(a, torch, vf):
            "config": {"workload": f"{P.name}: N={n}, sigma={P.sigma}; {a.eval_lattice}^2 "
                                   "cell-centred lattice of evaluation points on the root square",
                       "p": p, "levels": L, "selector": how,
-                      "near_radius": "auto: min(6 sigma, 2 w_L)" if radius < 0 else radius,
+                      "near_radius": "auto: min(6 sigma, 4 w_L)" if radius < 0 else radius,
                       "p2p_tile_waves": list(vf.get_tuning().values())},
            "accuracy": {"emax": emax, "erms": erms, "sample": AUDIT_TARGETS,
                         "log10_error_quantiles": {q: float(np.quantile(field, float(q)))

@@ -394,17 +394,19 @@ vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count
  * closer than the radius a also interacts through the regularised kernel
  * (eq. 6): Gamma (K_sigma - K') is added to the expansion result.
  *   radius = 0 (the default): the paper's split (local list only);
- *   radius > 0: a = min(radius, 2 w_L), w_L the leaf side (every particle
- *               closer than 2 w_L lies in the local list or in the ring of
- *               leaves at distance 2, which is searched);
- *   radius < 0 (VFMM_NEAR_RADIUS_AUTO): a = min(r_p, 2 w_L) with r_p the
- *               distance beyond which exp(-r^2 / 2 sigma^2) is below half an
- *               ulp of the evaluation's precision (6 sigma in FP32, sqrt(76)
- *               sigma in FP64), so that up to 2 w_L no kernel substitution
- *               error remains at that precision.
+ *   radius > 0: a = min(radius, VFMM_NEAR_RINGS_MAX w_L), w_L the leaf side;
+ *               the rings of leaves at Chebyshev distance 2 .. D are
+ *               searched, D the smallest with D w_L >= a (every particle
+ *               closer than D w_L lies in the local list or in those rings);
+ *   radius < 0 (VFMM_NEAR_RADIUS_AUTO): a = min(r_p, VFMM_NEAR_RINGS_MAX w_L)
+ *               with r_p the distance beyond which exp(-r^2 / 2 sigma^2) is
+ *               below half an ulp of the evaluation's precision (6 sigma in
+ *               FP32, sqrt(76) sigma in FP64), so that up to a no kernel
+ *               substitution error remains at that precision.
  * The batched evaluation always uses the paper's split.
  * Errors: VFMM_ERR_INVALID_ARG (NULL tree, radius not finite). */
 #define VFMM_NEAR_RADIUS_AUTO (-1.0)
+#define VFMM_NEAR_RINGS_MAX 4
 vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t tree, double radius);
 
 /* Advection of the particles with their own velocity (eq. 5, dx_i/dt = u(x_i);

@@ -37,12 +37,16 @@
 // exact centre offset.
 //
 // Distance cut-off (optional; the distance a of Section 4.1): the chunk
-// sequence also holds the ring of leaves at distance 2, whose particles the
-// expansions already carry with the singular kernel; a ring chunk whose box
-// gap to the target tile is below the radius adds Gamma (K_sigma - K') for its
-// pairs closer than the radius (Gamma exp(-r^2 / 2 sigma^2) / r^2 in complex
-// form); the radius is clamped to 2 w_L, the distance beyond which no particle
-// is outside the ring and the local list.  With one lane per target, the
+// sequence also holds the rings of leaves at Chebyshev distance 2 .. D, whose
+// particles the expansions already carry with the singular kernel; a ring
+// chunk whose box gap to the target tile is below the radius adds
+// Gamma (K_sigma - K') for its pairs closer than the radius
+// (Gamma exp(-r^2 / 2 sigma^2) / r^2 in complex form).  A particle outside the
+// rings up to D is at least D w_L from every point of the target leaf, so D is
+// the smallest number of rings with D w_L >= radius, at most kMaxRings; the
+// radius is clamped to kMaxRings w_L.  Every kernel takes D from the leaf side
+// on the device, so the schedule and the near field agree.  With one lane per
+// target, the
 // sources of such a chunk are first tested in parallel (one per lane) against
 // the tile's box, and the wave visits only those within the radius (about 45 %
 // on clustered particles).
@@ -70,9 +74,9 @@ namespace {
 // run of consecutive leaves lo .. hi of one row sy, whose chunks are
 // tile_off[sy m + lo] .. tile_off[sy m + hi + 1] - 1:
 //   s = 0, 1, 2: the local list, rows by - 1 .. by + 1, leaves bx - 1 .. bx + 1;
-//   with the distance cut-off, the ring of leaves at distance 2:
-//   s = 3: row by - 2, leaves bx - 2 .. bx + 2;  s = 4 .. 9: rows by - 1, by,
-//   by + 1, leaf bx - 2 then leaf bx + 2;  s = 10: row by + 2, bx - 2 .. bx + 2;
+//   with the distance cut-off, the rings d = 2 .. D in turn, 4 d segments each:
+//   first row by - d, leaves bx - d .. bx + d; then rows by - d + 1 .. by + d - 1,
+//   leaf bx - d then leaf bx + d; last row by + d, leaves bx - d .. bx + d;
 // all clipped to the level.  Returns false for an empty segment.
 __device__ __forceinline__ bool segment(int s, int bx, int by, int m, int& sy, int& lo, int& hi) {
   int d0, d1;
@@ -80,21 +84,47 @@ __device__ __forceinline__ bool segment(int s, int bx, int by, int m, int& sy, i
     sy = by - 1 + s;
     d0 = -1;
     d1 = 1;
-  } else if (s == 3 || s == 10) {
-    sy = s == 3 ? by - 2 : by + 2;
-    d0 = -2;
-    d1 = 2;
   } else {
-    const int k = s - 4;
-    sy = by - 1 + (k >> 1);
-    d0 = d1 = (k & 1) ? 2 : -2;
+    int d = 2, base = 3;
+    while (s >= base + 4 * d) {
+      base += 4 * d;
+      ++d;
+    }
+    const int j = s - base;
+    if (j == 0 || j == 4 * d - 1) {
+      sy = j == 0 ? by - d : by + d;
+      d0 = -d;
+      d1 = d;
+    } else {
+      const int k = j - 1;
+      sy = by - d + 1 + (k >> 1);
+      d0 = d1 = (k & 1) ? d : -d;
+    }
   }
   lo = bx + d0 < 0 ? 0 : bx + d0;
   hi = bx + d1 > m - 1 ? m - 1 : bx + d1;
   return sy >= 0 && sy < m && lo <= hi;
 }
 
-constexpr int kSegNear = 3, kSegRing = 11;
+constexpr int kSegNear = 3;
+constexpr int kMaxRings = 4;  // rings of the distance cut-off: Chebyshev distance 2 .. 4
+
+// Segments of the chunk sequence and the effective cut-off radius^2 for the
+// requested radius^2 cut2 (0: the paper's split, no rings) at leaf side w.
+struct NearRings {
+  int nseg;
+  double rc2;
+};
+__device__ __forceinline__ NearRings near_rings(double cut2, double w) {
+  if (cut2 <= 0.0) return NearRings{kSegNear, 0.0};
+  int d = 2, nseg = kSegNear + 4 * 2;
+  while (d < kMaxRings && cut2 > (d * w) * (d * w)) {
+    ++d;
+    nseg += 4 * d;
+  }
+  const double cap = (d * w) * (d * w);
+  return NearRings{nseg, cut2 < cap ? cut2 : cap};
+}
 
 __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int nseg,
                                                     const uint32_t* __restrict__ tile_off) {
@@ -113,10 +143,12 @@ __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int ns
 __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ ttiles,
                                                      const int32_t* __restrict__ tntiles,
                                                      const uint32_t* __restrict__ tile_off,
-                                                     int levels, int nseg, int64_t max_tiles,
+                                                     const double* __restrict__ root, int levels,
+                                                     double cut2, int64_t max_tiles,
                                                      uint32_t* __restrict__ cnt,
                                                      uint64_t* __restrict__ bsum) {
   __shared__ uint64_t red[256];
+  const int nseg = near_rings(cut2, root[3]).nseg;
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
   uint32_t c = 0;
   if (t < *tntiles) c = sequence_chunks(ttiles[t].leaf, levels, nseg, tile_off);
@@ -247,7 +279,7 @@ __global__ void __launch_bounds__(512) k_p2p(
     const Tile* __restrict__ ttiles, const float4* __restrict__ ttile_box,
     const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
     const double* __restrict__ root, int levels, PairK<R> pk, double sd, float far2, float ser2,
-    int nseg, double cut2, double2* __restrict__ nearv) {
+    double cut2, double2* __restrict__ nearv) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   // FP32: sources and targets in units of the Gaussian width (factor sd);
   // FP64: plain units (sd = 1)
@@ -258,9 +290,11 @@ __global__ void __launch_bounds__(512) k_p2p(
   const int m = 1 << levels;
   const double w = root[3];
   const int np_total = int(*nparts);
-  // distance cut-off radius^2, at most (2 w)^2: only the ring of leaves at
-  // distance 2 is searched, and every farther particle is >= 2 w away
-  const double rc2d = cut2 < 4.0 * w * w ? cut2 : 4.0 * w * w;
+  // segments of the chunk sequence and the cut-off radius^2, at most (D w)^2
+  // with D the number of rings searched
+  const NearRings nr = near_rings(cut2, w);
+  const int nseg = nr.nseg;
+  const double rc2d = nr.rc2;
   const float rc2f = float(rc2d);
   const R rc2 = R(rc2d * sd * sd);
   const float rc2s = float(rc2d * sd * sd);
@@ -491,13 +525,13 @@ __global__ void __launch_bounds__(256) k_l2p(
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, int nseg,
+hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double cut2,
                           hipStream_t st) {
   const P2PSched& s = tg.sched;
   const int64_t mt = tg.max_tiles;
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, levels, nseg, mt, s.cnt, s.bsum);
+                     t.tile_off, t.root, levels, cut2, mt, s.cnt, s.bsum);
   hipLaunchKernelGGL(k_sched_total, dim3(1), dim3(256), 0, st, s.bsum, nb);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
@@ -513,8 +547,8 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, in
 }
 
 template <typename R, int LPT>
-void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, int nseg,
-              double cut2, hipStream_t st) {
+void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, double cut2,
+              hipStream_t st) {
   using Part = typename Types<R>::Part;
   const auto* part = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(t.part64) : static_cast<const void*>(t.part32s));
@@ -537,19 +571,16 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   hipLaunchKernelGGL((k_p2p<R, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st, part,
                      t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles, tg.tile_box,
                      s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
-                     far2, ser2, nseg, cut2, s.near);
+                     far2, ser2, cut2, s.near);
 }
 
 template <typename R>
 void launch_r(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, double radius,
               hipStream_t st) {
-  // radius 0: the paper's split; < 0: the distance beyond which the two kernels
-  // agree in this precision; the kernel clamps it to 2 w_L
-  const int nseg = radius == 0.0 ? kSegNear : kSegRing;
-  const double cut2 = radius > 0.0 ? radius * radius : P2PMath<R>::kFarSigma2 * sigma * sigma;
-  if (t.tile == 16) launch_t<R, 4>(t, tg, levels, sigma, nseg, cut2, st);
-  else if (t.tile == 32) launch_t<R, 2>(t, tg, levels, sigma, nseg, cut2, st);
-  else launch_t<R, 1>(t, tg, levels, sigma, nseg, cut2, st);
+  const double cut2 = near_cut2(radius, sigma, sizeof(R) == 8 ? kFP64 : kFP32);
+  if (t.tile == 16) launch_t<R, 4>(t, tg, levels, sigma, cut2, st);
+  else if (t.tile == 32) launch_t<R, 2>(t, tg, levels, sigma, cut2, st);
+  else launch_t<R, 1>(t, tg, levels, sigma, cut2, st);
 }
 
 template <typename R, int PMAX>
@@ -577,9 +608,18 @@ void launch_l2p_r(const TreeDev& t, const TargetsDev& tg, int levels, int p, int
 
 }  // namespace
 
-hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
-                               hipStream_t st) {
-  return build_schedule(t, tg, levels, radius == 0.0 ? kSegNear : kSegRing, st);
+// Requested cut-off radius^2: 0 for the paper's split (radius 0); for radius
+// < 0 the distance beyond which the two kernels agree in this precision; the
+// kernels clamp it to (kMaxRings w_L)^2.
+double near_cut2(double radius, double sigma, int prec) {
+  if (radius == 0.0) return 0.0;
+  if (radius > 0.0) return radius * radius;
+  return (prec == kFP64 ? P2PMath<double>::kFarSigma2 : P2PMath<float>::kFarSigma2) * sigma * sigma;
+}
+
+hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, int prec,
+                               double sigma, double radius, hipStream_t st) {
+  return build_schedule(t, tg, levels, near_cut2(radius, sigma, prec), st);
 }
 
 hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,

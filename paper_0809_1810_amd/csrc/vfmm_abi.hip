@@ -339,7 +339,7 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   }
   mark.begin(kPhSched, st);
   if (near) {
-    e = launch_p2p_schedule(t->dev, tg, L, t->near_radius, st);
+    e = launch_p2p_schedule(t->dev, tg, L, prec, sigma, t->near_radius, st);
     if (e != hipSuccess) return hip_fail(e, "P2P schedule");
   }
   mark.end(kPhSched, st);

@@ -191,8 +191,10 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
 // The near-field work schedule of target set tg (launch_p2p_schedule), then
 // the near-field kernel over it (launch_p2p, same radius), which leaves its
 // sums in the schedule's buffers (tg.sched.near, tg.sched.partial).
-hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double radius,
-                               hipStream_t stream);
+hipError_t launch_p2p_schedule(const TreeDev& t, const TargetsDev& tg, int levels, int prec,
+                               double sigma, double radius, hipStream_t stream);
+// The requested cut-off radius^2 of the kernels (0: the paper's split).
+double near_cut2(double radius, double sigma, int prec);
 hipError_t launch_p2p(const TreeDev& t, const TargetsDev& tg, int levels, int prec, double sigma,
                       double radius, hipStream_t stream);
 // Writes u, v in the caller's order: the near-field sums of launch_p2p

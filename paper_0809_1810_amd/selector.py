@@ -209,7 +209,8 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     With ``cutoff``, an accepted FP32 choice (p, L) is compared with the same p
     one or two levels deeper with the distance cut-off of the near field
     (Section 4.1's distance a), for the levels whose leaf side is still
-    >= 3 sigma (so that the clamp 2 w_L does not cut the radius), at two
+    >= 6 sigma / NEAR_RINGS_MAX (so that the clamp NEAR_RINGS_MAX w_L does not
+    cut the radius), at two
     radii: the automatic one (6 sigma in FP32) and sigma sqrt(2 ln(1/tol)),
     where one pair's kernel difference falls to the tolerance.  Each such
     candidate is audited, the passing ones are timed (median of
@@ -279,7 +280,8 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     side = float(root.arrays()[0][2].item())
     root.close()
     deeper = [LL for LL in (L + 1, L + 2)
-              if LL <= min(V.MAX_LEVELS, 10) and side / 2 ** LL >= 3.0 * sigma and 4 ** LL <= 4 * n]
+              if LL <= min(V.MAX_LEVELS, 10) and side / 2 ** LL >= 6.0 * sigma / V.NEAR_RINGS_MAX
+              and 4 ** LL <= 4 * n]
     if not deeper:
         return out
     _, ms0 = run(p, L, V.FP32, timed=True)

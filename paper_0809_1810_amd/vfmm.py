@@ -108,6 +108,7 @@ _SIGS = {
 }
 
 NEAR_RADIUS_AUTO = -1.0
+NEAR_RINGS_MAX = 4  # the cut-off radius is clamped to NEAR_RINGS_MAX leaf sides
 MLP_PARAMS = 4929
 N_FEATURES = 10
 
@@ -288,7 +289,8 @@ class Tree:
 
     def set_near_radius(self, radius: float):
         """Distance cut-off of the near field for later evaluations: 0 = the
-        paper's split, > 0 = min(radius, 2 w_L), NEAR_RADIUS_AUTO = automatic."""
+        paper's split, > 0 = min(radius, NEAR_RINGS_MAX w_L), NEAR_RADIUS_AUTO =
+        automatic (6 sigma in FP32, sqrt(76) sigma in FP64, same clamp)."""
         _check(lib().vfmm_tree_set_near_radius(self._h, float(radius)), "vfmm_tree_set_near_radius")
         self.near_radius = float(radius)
 

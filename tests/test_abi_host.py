@@ -39,6 +39,7 @@ def test_header_constants_match_the_binding():
     assert int(consts["VFMM_N_PHASES"]) == vf.N_PHASES == len(vf.PHASES)
     assert int(consts["VFMM_PART_NEAR"]) == vf.PART_NEAR and int(consts["VFMM_PART_FAR"]) == vf.PART_FAR
     assert float(consts["VFMM_NEAR_RADIUS_AUTO"]) == vf.NEAR_RADIUS_AUTO
+    assert int(consts["VFMM_NEAR_RINGS_MAX"]) == vf.NEAR_RINGS_MAX
     for name in ("FP64", "FP32", "M2L_BF16", "M2L_FP16"):
         assert int(consts["VFMM_" + name]) == getattr(vf, name)
 

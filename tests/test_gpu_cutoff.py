@@ -1,7 +1,9 @@
 """Distance cut-off of the near field (Section 4.1's distance a), GPU vs the
 float64 oracle, through the C ABI.
 
-The library clamps the radius to 2 w_L; the oracle takes the effective radius.
+The library searches the rings of leaves at Chebyshev distance 2 .. D (D <= 4,
+the smallest with D w_L >= radius) and clamps the radius to 4 w_L; the oracle
+takes the effective radius and tests every pair.
 Tolerances (normalised by the maximum velocity, Section 5.1): float64 vs the
 oracle FMM with the same radius 1e-12 (near part 1e-13); float32 vs the
 oracle 1e-6.  Radius 0 is bit-identical to the paper's split.
@@ -29,14 +31,17 @@ def _w(P, levels):
     return qt.box_side(qt.root_square(P.x, P.y), levels)
 
 
-@pytest.mark.parametrize("levels,radius", [(3, 0.3), (3, 10.0), (4, 0.2), (3, "auto"), (2, "auto")])
+@pytest.mark.parametrize("levels,radius", [(3, 0.3), (3, 10.0), (4, 0.2), (3, "auto"), (2, "auto"),
+                                           (4, 0.3), (4, 0.45), (5, 10.0), (5, "auto")])
 def test_cutoff_fp64_matches_oracle(vf, levels, radius):
-    """2000 uniform particles with sigma = 0.08: the leaf side is 1.6 to 6
-    sigma, so the ring of leaves holds many pairs closer than the radius."""
+    """2000 uniform particles with sigma = 0.08: the leaf side is 0.8 to 6
+    sigma, so the rings of leaves hold many pairs closer than the radius; the
+    cases take 2, 3 and 4 rings (w_L = 0.25 at L = 3, 0.125 at L = 4, 0.0625 at
+    L = 5, the square being about [-1, 1]^2)."""
     P = W.uniform(2000, seed=5, sigma=0.08)
     w = _w(P, levels)
     r_lib = vf.NEAR_RADIUS_AUTO if radius == "auto" else radius
-    r_eff = min(math.sqrt(76.0) * P.sigma if radius == "auto" else radius, 2.0 * w)
+    r_eff = min(math.sqrt(76.0) * P.sigma if radius == "auto" else radius, vf.NEAR_RINGS_MAX * w)
     print_case("cutoff_fp64", levels=levels, radius=radius, r_eff=r_eff)
     t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=20)
     t.set_near_radius(r_lib)
@@ -64,12 +69,12 @@ def test_cutoff_at_points_and_fp32(vf):
     g = dev(P.gamma)
     u, v = (host(a) for a in t.velocity_at(g, P.sigma, p, dev(xe), dev(ye), vf.FP64))
     r = F.fmm_velocity_at(P.x, P.y, P.gamma, P.sigma, p, L, xe, ye,
-                          radius=min(math.sqrt(76.0) * P.sigma, 2 * w))
+                          radius=min(math.sqrt(76.0) * P.sigma, vf.NEAR_RINGS_MAX * w))
     assert rel_err(u, v, r.u, r.v)[0] < 1e-12
     u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
     idx = W.sample_targets(P.n, 500, 6)
     r32 = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=idx,
-                         radius=min(6.0 * P.sigma, 2 * w))
+                         radius=min(6.0 * P.sigma, vf.NEAR_RINGS_MAX * w))
     assert rel_err(u32[idx], v32[idx], r32.u, r32.v)[0] < 1e-6
 
 
@@ -106,7 +111,7 @@ def test_clusters_full_size_deeper_tree(vf):
     u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
     u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
     r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=tg,
-                       radius=min(math.sqrt(76.0) * P.sigma, 2 * w))
+                       radius=min(math.sqrt(76.0) * P.sigma, vf.NEAR_RINGS_MAX * w))
     assert rel_err(u64[tg], v64[tg], r.u, r.v)[0] < 1e-12
     e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
     print(f"clusters_1m L7 p14 fp32: paper split {e_paper:.3e}, with cut-off {e32:.3e}")
