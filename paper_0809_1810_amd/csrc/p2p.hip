@@ -162,8 +162,18 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
   if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
 }
 
-// Total chunk count: bsum[nb] = sum of the nb block sums (fixed order).
-__global__ void __launch_bounds__(256) k_sched_total(uint64_t* __restrict__ bsum, int64_t nb) {
+// Parts per tile: part size K = max(kP2PMinChunks, ceil(total / P)) with
+// P = p2p_parts(max_tiles), parts = max(1, ceil(ch / K)); so the parts number
+// at most max_tiles + P and the parts of split tiles at most 2 P.  The total
+// chunk count is the sum of the nb block sums of k_sched_count, which every
+// block forms itself; ch is the difference of the scanned counts (exact
+// modulo 2^32).
+__global__ void __launch_bounds__(256) k_sched_parts(const int32_t* __restrict__ tntiles,
+                                                     const uint32_t* __restrict__ cnt,
+                                                     const uint64_t* __restrict__ bsum, int64_t nb,
+                                                     int64_t max_tiles,
+                                                     uint32_t* __restrict__ pcnt,
+                                                     uint32_t* __restrict__ scnt) {
   __shared__ uint64_t red[256];
   uint64_t s = 0;
   for (int64_t b = threadIdx.x; b < nb; b += 256) s += bsum[b];
@@ -173,24 +183,11 @@ __global__ void __launch_bounds__(256) k_sched_total(uint64_t* __restrict__ bsum
     if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[nb] = red[0];
-}
-
-// Parts per tile: part size K = max(kP2PMinChunks, ceil(total / P)) with
-// P = p2p_parts(max_tiles), parts = max(1, ceil(ch / K)); so the parts number
-// at most max_tiles + P and the parts of split tiles at most 2 P.
-// ch is the difference of the scanned counts (exact modulo 2^32).
-__global__ void __launch_bounds__(256) k_sched_parts(const int32_t* __restrict__ tntiles,
-                                                     const uint32_t* __restrict__ cnt,
-                                                     const uint64_t* __restrict__ total_p,
-                                                     int64_t max_tiles,
-                                                     uint32_t* __restrict__ pcnt,
-                                                     uint32_t* __restrict__ scnt) {
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
   if (t > max_tiles) return;
   uint32_t np = 0;
   if (t < *tntiles) {
-    const uint64_t total = *total_p;
+    const uint64_t total = red[0];
     const uint64_t P = uint64_t(p2p_parts(max_tiles));
     uint64_t k = (total + P - 1) / P;
     if (k < kP2PMinChunks) k = kP2PMinChunks;
@@ -532,14 +529,11 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, do
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
                      t.tile_off, t.root, levels, cut2, mt, s.cnt, s.bsum);
-  hipLaunchKernelGGL(k_sched_total, dim3(1), dim3(256), 0, st, s.bsum, nb);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,
-                     s.bsum + nb, mt, s.p_off, s.s_off);
-  e = scan_exclusive(s.p_off, mt + 1, s.scan_tmp, st);
-  if (e != hipSuccess) return e;
-  e = scan_exclusive(s.s_off, mt + 1, s.scan_tmp, st);
+                     s.bsum, nb, mt, s.p_off, s.s_off);
+  e = scan_exclusive2(s.p_off, s.s_off, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sched_fill, dim3(nblk(mt, 256)), dim3(256), 0, st, tg.tiles, tg.ntiles,
                      tg.tile_off, s.cnt, s.p_off, s.s_off, s.parts);

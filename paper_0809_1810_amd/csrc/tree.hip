@@ -175,8 +175,13 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
   return pre + incl - v;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t* __restrict__ a,
+// Block totals; with gridDim.y = 2 the blocks of row 1 take array a1 and write
+// their totals after the nb = gridDim.x of row 0.
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t* __restrict__ a0,
+                                                            const uint32_t* __restrict__ a1,
                                                             int64_t n, uint32_t* __restrict__ tmp) {
+  const uint32_t* a = blockIdx.y ? a1 : a0;
+  tmp += blockIdx.y * gridDim.x;
   const int64_t base = blockIdx.x * int64_t(kScanPerBlock) + threadIdx.x * int64_t(kScanItems);
   uint32_t s = 0;
 #pragma unroll
@@ -225,10 +230,14 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t* __restrict_
 
 // As k_scan_apply, with tmp holding the block totals themselves: each block
 // adds up the totals of the blocks before it (a fixed order, so the result
-// equals the three-phase scan's).  For up to kScanFusedBlocks blocks.
-__global__ void __launch_bounds__(kScanBlock) k_scan_apply_totals(uint32_t* __restrict__ a,
+// equals the three-phase scan's).  For up to kScanFusedBlocks blocks; rows of
+// the grid as in k_scan_reduce.
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply_totals(uint32_t* __restrict__ a0,
+                                                                  uint32_t* __restrict__ a1,
                                                                   int64_t n,
                                                                   const uint32_t* __restrict__ tmp) {
+  uint32_t* a = blockIdx.y ? a1 : a0;
+  tmp += blockIdx.y * gridDim.x;
   uint32_t before = 0;
   for (int k = threadIdx.x; k < int(blockIdx.x); k += kScanBlock) before += tmp[k];
   uint32_t pre;
@@ -259,13 +268,27 @@ hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st)
   if (n <= 0) return hipSuccess;
   int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
   if (nb <= kScanFusedBlocks) {
-    if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
-    hipLaunchKernelGGL(k_scan_apply_totals, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+    if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, a, n, tmp);
+    hipLaunchKernelGGL(k_scan_apply_totals, dim3(nb), dim3(kScanBlock), 0, st, a, a, n, tmp);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, a, n, tmp);
   hipLaunchKernelGGL(k_scan_tmp, dim3(1), dim3(kScanBlock), 0, st, tmp, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, st, a, n, tmp);
+  return hipGetLastError();
+}
+
+// Two arrays of n elements scanned by the same launches (tmp: 2 nb totals);
+// beyond kScanFusedBlocks blocks, one after the other.
+hipError_t scan_exclusive2(uint32_t* a, uint32_t* b, int64_t n, uint32_t* tmp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
+  if (nb > kScanFusedBlocks) {
+    hipError_t e = scan_exclusive(a, n, tmp, st);
+    return e == hipSuccess ? scan_exclusive(b, n, tmp, st) : e;
+  }
+  if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb, 2), dim3(kScanBlock), 0, st, a, b, n, tmp);
+  hipLaunchKernelGGL(k_scan_apply_totals, dim3(nb, 2), dim3(kScanBlock), 0, st, a, b, n, tmp);
   return hipGetLastError();
 }
 

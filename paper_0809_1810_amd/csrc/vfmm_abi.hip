@@ -117,7 +117,8 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.max_tiles = (n + kTileMin - 1) / kTileMin + nonempty;  // any tunable tile size fits
   int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
   if (scan_src < L.max_tiles + 1) scan_src = L.max_tiles + 1;
-  const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
+  // block totals of a scan of up to scan_src elements, or of two scans at once
+  const int64_t scan_tmp = 2 * ((scan_src + kScanPerBlock - 1) / kScanPerBlock) + 2;
   const int64_t nbox = n_boxes_2_to(levels);
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
@@ -380,7 +381,8 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   L.max_tiles = (nt + kTileMin - 1) / kTileMin + nonempty;
   int64_t scan_src = L.count_len > L.nleaves + 1 ? L.count_len : L.nleaves + 1;
   if (scan_src < L.max_tiles + 1) scan_src = L.max_tiles + 1;
-  const int64_t scan_tmp = (scan_src + kScanPerBlock - 1) / kScanPerBlock + 1;
+  // block totals of a scan of up to scan_src elements, or of two scans at once
+  const int64_t scan_tmp = 2 * ((scan_src + kScanPerBlock - 1) / kScanPerBlock) + 2;
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
   L.keys0 = take(size_t(nt) * 4);

@@ -81,7 +81,7 @@ struct P2PSched {
   uint32_t* s_off;    // [max_tiles + 1] first partial slot of each split tile
   P2PPart* parts;     // [max_tiles + p2p_parts(max_tiles)]
   double2* partial;   // [2 p2p_parts(max_tiles)][kTile] near-field sums (u, v) of one part
-  uint64_t* bsum;     // [ceil((max_tiles + 1) / 256) + 1] chunk sums per block, then total
+  uint64_t* bsum;     // [ceil((max_tiles + 1) / 256) + 1] chunk sums per block of k_sched_count
   uint32_t* scan_tmp;
   double2* near;      // [targets] near field (times 1 / 2 pi) of single-part tiles, sorted order
 };
@@ -229,6 +229,8 @@ hipError_t launch_heun_correct(double* x, double* y, const double* u1, const dou
 size_t ops_bytes(int p);
 // Shared building blocks (tree.hip).
 hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st);
+// Two arrays of n elements at once; tmp holds 2 ceil(n / kScanPerBlock) entries.
+hipError_t scan_exclusive2(uint32_t* a, uint32_t* b, int64_t n, uint32_t* tmp, hipStream_t st);
 // Stable LSD radix sort of (key, index) pairs on the low `bits` key bits; on
 // return k0/i0 point to the sorted arrays (the other pair is scratch).
 hipError_t radix_sort_pairs(uint32_t*& k0, uint32_t*& k1, int32_t*& i0, int32_t*& i1, int64_t n,
