@@ -54,10 +54,16 @@ def _tree_check(vf, P, levels, domain=None):
 
 
 @pytest.mark.parametrize("case", ["uniform_1k_L3", "uniform_1k_L0", "clusters_64k_L5",
-                                  "lattice_320_L6", "edges_L2"])
+                                  "lattice_320_L6", "edges_L2", "uniform_33m_L8"])
 def test_tree_bit_exact(vf, case):
     print_case("tree", case=case)
-    if case.startswith("uniform_1k"):
+    if case == "uniform_33m_L8":
+        # 2^25 + 4097 particles: the radix counts (256 per block of 2048 keys)
+        # need 2049 scan blocks, past the two-launch scan's limit of 2048, so
+        # the sort takes the three-phase scan
+        t = _tree_check(vf, W.uniform(2 ** 25 + 4097, seed=9), 8)
+        t.close()
+    elif case.startswith("uniform_1k"):
         P = W.config("uniform_1k"); L = int(case[-1])
         _tree_check(vf, P, L)
     elif case == "clusters_64k_L5":
