@@ -28,9 +28,6 @@ template <> struct P2PMath<double> {
   __device__ __forceinline__ static double near(double g, double r2, double kexp) {
     return g * (-expm1(r2 * kexp) / r2);
   }
-  __device__ __forceinline__ static double near_series(double g, double r2, double kexp, double) {
-    return near(g, r2, kexp);
-  }
   __device__ __forceinline__ static double far(double g, double r2) { return g / r2; }
   // Gamma exp(r2 kexp) / r2: the regularised kernel minus the singular one
   // (up to sign), for the distance cut-off beyond the local list
@@ -41,41 +38,33 @@ template <> struct P2PMath<double> {
 
 template <> struct P2PMath<float> {
   static constexpr double kFarSigma2 = 36.0;  // exp(-18) < 2^-25
-  static constexpr double kSeriesSigma2 = 1.0 / 16.0;  // a = r^2 / 2 sigma^2 < 1/32
-  // kexp = -log2(e) / (2 sigma^2); Gamma (1 - e) computed as one fused op
-  __device__ __forceinline__ static float near(float g, float r2, float kexp) {
-    const float e = __builtin_amdgcn_exp2f(r2 * kexp);
-    return __builtin_fmaf(-g, e, g) * __builtin_amdgcn_rcpf(r2);
-  }
-  // Close pairs: 1 - exp(-a) from the hardware exp has an absolute error of
-  // ~2^-24, which divided by r would dominate for r << sigma; below a = 1/32
-  // the series a (1 - a/2 + a^2/6 - a^3/24) is used (truncation < 8e-9).
-  __device__ __forceinline__ static float near_series(float g, float r2, float kexp, float ka) {
-    const float a = r2 * ka;
-    const float ser = a * (1.0f - a * (0.5f - a * (1.0f / 6.0f - a * (1.0f / 24.0f))));
-    const float e = __builtin_amdgcn_exp2f(r2 * kexp);
-    const float om = a < 0.03125f ? ser : 1.0f - e;
-    return g * om * __builtin_amdgcn_rcpf(r2);
-  }
+  // chunks whose box comes closer than sigma / 4 to the target tile take the
+  // series form below (a = r^2 / 2 sigma^2 < 1/32 is possible there only)
+  static constexpr double kSeriesSigma2 = 1.0 / 16.0;
   __device__ __forceinline__ static float far(float g, float r2) {
     return g * __builtin_amdgcn_rcpf(r2);
   }
-  __device__ __forceinline__ static float gauss(float g, float r2, float kexp) {
-    return g * __builtin_amdgcn_exp2f(r2 * kexp) * __builtin_amdgcn_rcpf(r2);
-  }
-  // The same in units of the Gaussian width (r'^2 = r^2 log2(e) / (2 sigma^2)):
-  // exp(-r^2 / 2 sigma^2) = exp2(-r'^2), the exponent argument is a free
-  // operand negation; the forms return Gamma (...) / r'^2.
+  // The regularised forms in units of the Gaussian width
+  // (r'^2 = r^2 log2(e) / (2 sigma^2)): exp(-r^2 / 2 sigma^2) = exp2(-r'^2), the
+  // exponent argument is a free operand negation; they return Gamma (...) / r'^2,
+  // with Gamma (1 - e) computed as one fused op.
   __device__ __forceinline__ static float near_s(float g, float r2) {
     const float e = __builtin_amdgcn_exp2f(-r2);
     return __builtin_fmaf(-g, e, g) * __builtin_amdgcn_rcpf(r2);
   }
+  // Close pairs: 1 - e^-a from the hardware exp has an absolute error of
+  // ~2^-24, which divided by r'^2 would dominate for r << sigma.  With
+  // a = r'^2 ln 2 = r^2 / (2 sigma^2), below a = 1/32 the kernel
+  // (1 - e^-a) / r'^2 = ln 2 (1 - a/2 + a^2/6 - a^3/24) is taken as that cubic in
+  // r'^2 (truncation < 8e-9 relative), which needs neither the exponential nor
+  // the reciprocal; above it the near form.
+  static constexpr float kSeriesR2s = 0.045084220027780106f;  // (1/32) / ln 2
   __device__ __forceinline__ static float near_series_s(float g, float r2) {
-    const float a = r2 * 0.69314718055994530942f;  // r^2 / (2 sigma^2)
-    const float ser = a * (1.0f - a * (0.5f - a * (1.0f / 6.0f - a * (1.0f / 24.0f))));
-    const float e = __builtin_amdgcn_exp2f(-r2);
-    const float om = a < 0.03125f ? ser : 1.0f - e;
-    return g * om * __builtin_amdgcn_rcpf(r2);
+    const float ser = 0.6931471805599453f +
+                      r2 * (-0.2402265069591007f + r2 * (0.05550410866482158f +
+                                                         r2 * -0.009618129107628477f));
+    const float fn = __builtin_fmaf(-g, __builtin_amdgcn_exp2f(-r2), g) * __builtin_amdgcn_rcpf(r2);
+    return r2 < kSeriesR2s ? g * ser : fn;
   }
   __device__ __forceinline__ static float gauss_s(float g, float r2) {
     return g * __builtin_amdgcn_exp2f(-r2) * __builtin_amdgcn_rcpf(r2);
