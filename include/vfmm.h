@@ -372,7 +372,12 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
 /* Evaluates every instance.  use_graph = 0: enqueue the kernels on `stream`.
  * use_graph = 1: the first call captures the sequence in a hipGraph on
  * `stream` (which must not be the NULL stream) and every call replays it.
- * The first call also builds the translation tables (outside any capture). */
+ * The first call also builds the translation tables (outside any capture).
+ * Streams: after the tree build, the expansion sweeps (P2M, M2M, M2L, L2L) run
+ * on a stream owned by the plan (created with it, default priority) beside the
+ * near field on `stream`, which waits for them (events) before L2P; captured,
+ * the two become branches of the graph.  The call behaves as one ordered
+ * sequence on `stream`; runs of one plan from different streams race. */
 vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream);
 
 /* Releases the plan and its graph (not the workspace).  NULL is ignored. */

@@ -2,12 +2,13 @@
 //
 // Each phase of the method (Section 3.1, Fig. 3) runs ONCE for all instances:
 // bounding squares, one global stable radix sort on (instance, leaf, sub-cell)
-// keys, leaf ranges, tiles, P2M, M2M (one launch per level), M2L + L2L (one
-// launch per level), and P2P + L2P + combine.  A work item (particle, leaf,
-// box coefficient, tile) finds its instance by binary search in a small table of
-// per-instance offsets, so the launch count does not depend on the number of
-// instances, and the whole sequence can be captured once in a hipGraph and
-// replayed.
+// keys, leaf ranges, tiles; then P2M, M2M (one launch per level), M2L and L2L
+// (one launch per level) on a second stream while the near field (P2P) runs;
+// after both, L2P adds the far field and writes the result.  A work item
+// (particle, leaf, box coefficient, tile) finds its instance by binary search
+// in a small table of per-instance offsets, so the launch count does not
+// depend on the number of instances, and the whole sequence can be captured
+// once in a hipGraph (two branches) and replayed.
 //
 // Arithmetic per instance: P2P in FP32 (as in p2p.hip); expansions (P2M, M2M,
 // M2L, L2L, L2P) in FP32 for p <= 16 and in FP64 for p > 16, on the scaled,
@@ -497,8 +498,7 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
                                                const uint32_t* __restrict__ tile_off,
                                                const float4* __restrict__ tile_box,
                                                const double* __restrict__ roots,
-                                               const char* __restrict__ le,
-                                               const int32_t* __restrict__ perm) {
+                                               double2* __restrict__ nearv) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= *ntiles) return;
   const int lane = threadIdx.x & 63;
@@ -573,17 +573,44 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
       }
     }
   }
+  // the near sums in the kernel's units (the L2P kernel scales them)
+  if (active) nearv[i] = make_double2(au.value(), av.value());
+}
+
+// One wave per tile, after the near field and the expansion sweeps: the near
+// sums of k_b_p2p scaled to velocities (each pair term is
+// Gamma (...) d' / r'^2 = (1 / sd) Gamma (...) d / r^2) plus the far field (L2P),
+// in one fused multiply-add, written in the instance's input order.
+__global__ void __launch_bounds__(256) k_b_l2p(const BatchInst* __restrict__ I,
+                                               const Part32* __restrict__ part,
+                                               const Tile* __restrict__ tiles,
+                                               const int32_t* __restrict__ ntiles,
+                                               const double* __restrict__ roots,
+                                               const char* __restrict__ le,
+                                               const double2* __restrict__ nearv,
+                                               const int32_t* __restrict__ perm) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= *ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const Tile tile = tiles[wid];
+  if (lane >= tile.count) return;
+  const int c = __builtin_amdgcn_readfirstlane(tile.pad);
+  const BatchInst in = I[c];
+  const int32_t i = tile.start + lane;
   double fu = 0.0, fv = 0.0;
-  if (L >= 2) {
+  if (in.L >= 2) {
+    const Part32 tp = part[i];
+    const int leaf = int(tile.leaf - in.leaf_off);
+    const double w = roots[4 * c + 3];
+    const double wsd = w * near_scale(in.sigma);
     if (in.fp64) l2p_eval<double>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
     else l2p_eval<float>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
   }
-  if (active) {
-    // each pair term is Gamma (...) d' / r'^2 = (1 / sd) Gamma (...) d / r^2
-    const int64_t o = int64_t(perm[i]) - in.part_off;
-    in.u[o] = au.value() * (kInv2Pi * sd) + fu;
-    in.v[o] = av.value() * (kInv2Pi * sd) + fv;
-  }
+  const double2 q = nearv[i];
+  const double k = kInv2Pi * near_scale(in.sigma);
+  const int64_t o = int64_t(perm[i]) - in.part_off;
+  in.u[o] = __builtin_fma(q.x, k, fu);
+  in.v[o] = __builtin_fma(q.y, k, fv);
 }
 
 }  // namespace
@@ -608,12 +635,17 @@ struct BatchPlanDev {
   float4* tile_box;
   Part32* p32;
   char *me, *le, *tab;
+  double2* nearv;  // near field of every particle, sorted order
 };
 
+// The build, then the expansion sweeps on the side stream sw (after an event
+// recorded on st) while st runs the near field; st waits for the sweeps
+// before L2P.  Captured into a graph, the two streams become two branches.
 hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int64_t nleaves,
                             int64_t max_tiles, const int64_t* m2m_tot, const int64_t* l2l_tot,
                             int maxL, int nseg, int64_t mfma_tiles, int nseg64,
-                            int64_t mfma_tiles64, hipStream_t st) {
+                            int64_t mfma_tiles64, hipStream_t st, hipStream_t sw,
+                            hipEvent_t fork, hipEvent_t join) {
   auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
   hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots, d.nbig);
   hipLaunchKernelGGL(k_b_keys, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, d.part_off, count,
@@ -636,27 +668,36 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                      d.toff, ntot, nleaves, d.tiles, d.ntiles);
   e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_p2m, dim3(nb(nleaves, 256)), dim3(256), 0, st, d.inst, d.leaf_off, count,
+  e = hipEventRecord(fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(sw, fork, 0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_p2m, dim3(nb(nleaves, 256)), dim3(256), 0, sw, d.inst, d.leaf_off, count,
                      d.start, d.p32, d.roots, d.me, d.big, d.nbig);
-  hipLaunchKernelGGL(k_b_p2m_big, dim3(nb(ntot / (kTile + 1) + 1, 4)), dim3(256), 0, st, d.inst,
+  hipLaunchKernelGGL(k_b_p2m_big, dim3(nb(ntot / (kTile + 1) + 1, 4)), dim3(256), 0, sw, d.inst,
                      d.start, d.p32, d.roots, d.me, d.big, d.nbig);
   for (int l = maxL - 1; l >= 2; --l)
     if (m2m_tot[l] > 0)
-      hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, st, d.inst,
+      hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, sw, d.inst,
                          d.m2m_items + int64_t(l) * (count + 1), count, l, d.me, d.tab, d.tab_off);
   if (mfma_tiles > 0)
-    hipLaunchKernelGGL(k_b_m2l_mfma, dim3(unsigned(mfma_tiles)), dim3(256), 0, st, d.inst,
+    hipLaunchKernelGGL(k_b_m2l_mfma, dim3(unsigned(mfma_tiles)), dim3(256), 0, sw, d.inst,
                        d.seg_off, d.seg_il, nseg, d.me, d.le, d.tab, d.tab_off);
   if (mfma_tiles64 > 0)
-    hipLaunchKernelGGL(k_b_m2l_mfma64, dim3(unsigned(mfma_tiles64)), dim3(256), 0, st, d.inst,
+    hipLaunchKernelGGL(k_b_m2l_mfma64, dim3(unsigned(mfma_tiles64)), dim3(256), 0, sw, d.inst,
                        d.seg_off64, d.seg_il64, nseg64, d.me, d.le, d.tab, d.tab_off);
   for (int l = 3; l <= maxL; ++l)
     if (l2l_tot[l] > 0)
-      hipLaunchKernelGGL(k_b_l2l, dim3(nb(l2l_tot[l], 256)), dim3(256), 0, st, d.inst,
+      hipLaunchKernelGGL(k_b_l2l, dim3(nb(l2l_tot[l], 256)), dim3(256), 0, sw, d.inst,
                          d.l2l_items + int64_t(l) * (count + 1), count, l, d.le, d.tab,
                          d.tab_off);
+  e = hipEventRecord(join, sw);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.start,
-                     d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.le, i0);
+                     d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.nearv);
+  e = hipStreamWaitEvent(st, join, 0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_l2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.tiles,
+                     d.ntiles, d.roots, d.le, d.nearv, i0);
   return hipGetLastError();
 }
 
@@ -679,6 +720,16 @@ struct vfmm_batch_s {
   bool tables_built;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  // the expansion sweeps run on `side` (default priority) beside the near field
+  hipStream_t side;
+  hipEvent_t fork, join;
+  ~vfmm_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace {
@@ -699,7 +750,8 @@ inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 struct BatchLayout {
   size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
       seg_off64, seg_il64, roots, k0, k1, i0, i1,
-      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, total;
+      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, nearv,
+      total;
   int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
   int maxL;
   std::vector<int64_t> me_off;
@@ -777,6 +829,7 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.me = take(size_t(L.me_bytes));
   L.le = take(size_t(L.me_bytes));
   L.tab = take(size_t(L.tab_bytes));
+  L.nearv = take(sizeof(double2) * size_t(L.ntot));
   L.total = off;
   return L;
 }
@@ -819,6 +872,13 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
   vfmm_batch_s* b = new (std::nothrow) vfmm_batch_s{};
   if (!b) return bfail(VFMM_ERR_INVALID_ARG, "host allocation failed");
+  hipError_t es = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  if (es == hipSuccess) es = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (es == hipSuccess) es = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  if (es != hipSuccess) {
+    delete b;
+    return bfail(VFMM_ERR_HIP, "batch stream / events: %s", hipGetErrorString(es));
+  }
   for (int p = 0; p <= VFMM_MAX_P; ++p) b->tab_at[p] = L.tab_at[p];
   b->count = count;
   b->ntot = L.ntot;
@@ -889,6 +949,7 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   d.me = ws + L.me;
   d.le = ws + L.le;
   d.tab = ws + L.tab;
+  d.nearv = reinterpret_cast<double2*>(ws + L.nearv);
   hipError_t e = hipMemcpy(d.inst, hi.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.part_off, part_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.leaf_off, leaf_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
@@ -931,7 +992,8 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
   }
   if (!use_graph) {
     e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->l2l_tot,
-                         b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st);
+                         b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st,
+                         b->side, b->fork, b->join);
     return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "batch run: %s", hipGetErrorString(e));
   }
   if (!b->exec) {
@@ -939,7 +1001,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
     if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
     hipError_t le = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot,
                                      b->l2l_tot, b->maxL, b->nseg, b->mfma_tiles, b->nseg64,
-                                     b->mfma_tiles64, st);
+                                     b->mfma_tiles64, st, b->side, b->fork, b->join);
     e = hipStreamEndCapture(st, &b->graph);
     if (le != hipSuccess || e != hipSuccess)
       return bfail(VFMM_ERR_HIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
@@ -950,12 +1012,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
   return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
 }
 
-void vfmm_batch_destroy(vfmm_batch_t b) {
-  if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  delete b;
-}
+void vfmm_batch_destroy(vfmm_batch_t b) { delete b; }
 
 vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count, void* workspace,
                                         size_t ws_bytes, void* stream) {
