@@ -581,17 +581,13 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
 // sums of k_b_p2p scaled to velocities (each pair term is
 // Gamma (...) d' / r'^2 = (1 / sd) Gamma (...) d / r^2) plus the far field (L2P),
 // in one fused multiply-add, written in the instance's input order.
-__global__ void __launch_bounds__(256) k_b_l2p(const BatchInst* __restrict__ I,
-                                               const Part32* __restrict__ part,
-                                               const Tile* __restrict__ tiles,
-                                               const int32_t* __restrict__ ntiles,
-                                               const double* __restrict__ roots,
-                                               const char* __restrict__ le,
-                                               const double2* __restrict__ nearv,
-                                               const int32_t* __restrict__ perm) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= *ntiles) return;
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void b_l2p_tile(int wid, int lane, const BatchInst* __restrict__ I,
+                                           const Part32* __restrict__ part,
+                                           const Tile* __restrict__ tiles,
+                                           const double* __restrict__ roots,
+                                           const char* __restrict__ le,
+                                           const double2* __restrict__ nearv,
+                                           const int32_t* __restrict__ perm) {
   const Tile tile = tiles[wid];
   if (lane >= tile.count) return;
   const int c = __builtin_amdgcn_readfirstlane(tile.pad);
@@ -611,6 +607,22 @@ __global__ void __launch_bounds__(256) k_b_l2p(const BatchInst* __restrict__ I,
   const int64_t o = int64_t(perm[i]) - in.part_off;
   in.u[o] = __builtin_fma(q.x, k, fu);
   in.v[o] = __builtin_fma(q.y, k, fv);
+}
+
+// b_l2p_tile for every tile, the waves looping over the tiles.
+__global__ void __launch_bounds__(256) k_b_l2p(const BatchInst* __restrict__ I,
+                                               const Part32* __restrict__ part,
+                                               const Tile* __restrict__ tiles,
+                                               const int32_t* __restrict__ ntiles,
+                                               const double* __restrict__ roots,
+                                               const char* __restrict__ le,
+                                               const double2* __restrict__ nearv,
+                                               const int32_t* __restrict__ perm) {
+  const int nt = *ntiles;
+  const int lane = threadIdx.x & 63;
+  for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
+       wid += 4 * gridDim.x)
+    b_l2p_tile(wid, lane, I, part, tiles, roots, le, nearv, perm);
 }
 
 }  // namespace
@@ -638,9 +650,10 @@ struct BatchPlanDev {
   double2* nearv;  // near field of every particle, sorted order
 };
 
-// The build, then the expansion sweeps on the side stream sw (after an event
-// recorded on st) while st runs the near field; st waits for the sweeps
-// before L2P.  Captured into a graph, the two streams become two branches.
+// The sort, leaf ranges and particle records, then the expansion sweeps on the
+// side stream sw (after an event recorded on st) while st builds the tiles and
+// runs the near field; st waits for the sweeps before L2P.  Captured into a
+// graph, the two streams become two branches.
 hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int64_t nleaves,
                             int64_t max_tiles, const int64_t* m2m_tot, const int64_t* l2l_tot,
                             int maxL, int nseg, int64_t mfma_tiles, int nseg64,
@@ -660,14 +673,6 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                      count, k0, ntot, d.start);
   hipLaunchKernelGGL(k_b_local, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, i0, ntot,
                      d.roots, d.p32);
-  hipLaunchKernelGGL(k_b_tile_counts, dim3(nb(nleaves + 1, 256)), dim3(256), 0, st, d.leaf_off,
-                     count, d.start, d.toff);
-  e = scan_exclusive(d.toff, nleaves + 1, d.tmp, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_tile_fill, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, d.start,
-                     d.toff, ntot, nleaves, d.tiles, d.ntiles);
-  e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
-  if (e != hipSuccess) return e;
   e = hipEventRecord(fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(sw, fork, 0);
   if (e != hipSuccess) return e;
@@ -692,12 +697,21 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                          d.tab_off);
   e = hipEventRecord(join, sw);
   if (e != hipSuccess) return e;
+  // the near-field tiles, beside the sweeps
+  hipLaunchKernelGGL(k_b_tile_counts, dim3(nb(nleaves + 1, 256)), dim3(256), 0, st, d.leaf_off,
+                     count, d.start, d.toff);
+  e = scan_exclusive(d.toff, nleaves + 1, d.tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_b_tile_fill, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, d.start,
+                     d.toff, ntot, nleaves, d.tiles, d.ntiles);
+  e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.start,
                      d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.nearv);
   e = hipStreamWaitEvent(st, join, 0);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_l2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.tiles,
-                     d.ntiles, d.roots, d.le, d.nearv, i0);
+  hipLaunchKernelGGL(k_b_l2p, dim3(tile_loop_blocks(max_tiles)), dim3(256), 0, st, d.inst,
+                     d.p32, d.tiles, d.ntiles, d.roots, d.le, d.nearv, i0);
   return hipGetLastError();
 }
 

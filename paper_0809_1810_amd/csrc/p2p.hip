@@ -469,21 +469,18 @@ __global__ void __launch_bounds__(512) k_p2p(
   }
 }
 
-// Result at the targets, one wave per target tile: the near field (near != 0)
-// of a single-part tile from nearv, of a split tile the sum of its parts'
-// partial sums in part order; plus the far field (L2P, eq. 25 on the scaled
-// LEs of the leaves; p = 0: none); written in the caller's order.
+// Result at the targets of one tile (one wave): the near field (near != 0) of
+// a single-part tile from nearv, of a split tile the sum of its parts' partial
+// sums in part order; plus the far field (L2P, eq. 25 on the scaled LEs of the
+// leaves; p = 0: none); written in the caller's order.
 template <typename R, int PMAX>
-__global__ void __launch_bounds__(256) k_l2p(
-    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
-    const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
+__device__ __forceinline__ void l2p_tile(
+    int wid, int lane, const typename Types<R>::Part* __restrict__ tpart,
+    const Tile* __restrict__ ttiles, const int32_t* __restrict__ tperm,
     const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
     int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
     const double2* __restrict__ partial, const double2* __restrict__ nearv,
     double* __restrict__ u, double* __restrict__ v) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= *tntiles) return;
-  const int lane = threadIdx.x & 63;
   const Tile tile = ttiles[wid];
   if (lane >= tile.count) return;
   const int32_t i = tile.start + lane;
@@ -518,6 +515,23 @@ __global__ void __launch_bounds__(256) k_l2p(
   }
   u[o] = p > 0 ? nu + fu : nu;
   v[o] = p > 0 ? nv + fv : nv;
+}
+
+// l2p_tile for every target tile, the waves looping over the tiles.
+template <typename R, int PMAX>
+__global__ void __launch_bounds__(256) k_l2p(
+    const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
+    const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
+    const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
+    int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
+    const double2* __restrict__ partial, const double2* __restrict__ nearv,
+    double* __restrict__ u, double* __restrict__ v) {
+  const int nt = *tntiles;
+  const int lane = threadIdx.x & 63;
+  for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
+       wid += 4 * gridDim.x)
+    l2p_tile<R, PMAX>(wid, lane, tpart, ttiles, tperm, root, p, le_leaf, near, p_off, s_off,
+                      partial, nearv, u, v);
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -585,7 +599,8 @@ void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int
   const auto* tpart = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
   const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
-  hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(nblk(tg.max_tiles, 4)), dim3(256), 0, st, tpart,
+  hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(tile_loop_blocks(tg.max_tiles)), dim3(256), 0, st,
+                     tpart,
                      tg.tiles, tg.ntiles, tg.perm, t.root, p, le, near, tg.sched.p_off,
                      tg.sched.s_off, tg.sched.partial, tg.sched.near, u, v);
 }

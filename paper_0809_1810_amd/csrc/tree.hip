@@ -440,24 +440,27 @@ __global__ void __launch_bounds__(256) k_tile_fill(const uint32_t* __restrict__ 
   tiles[off[leaf] + r / tile] = Tile{int32_t(leaf), int32_t(i), cc < tile ? cc : tile, 0};
 }
 
-// One wave per tile: bounding box of its particles in the leaf's local frame.
+// Bounding box of each tile's particles in the leaf's local frame, one wave
+// per tile, the waves looping over the tiles.
 __global__ void __launch_bounds__(256) k_tile_box(const Tile* __restrict__ tiles,
                                                   const int32_t* __restrict__ ntiles,
                                                   const Part32* __restrict__ p32,
                                                   float4* __restrict__ box) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= *ntiles) return;
+  const int nt = *ntiles;
   const int lane = threadIdx.x & 63;
-  const Tile t = tiles[wid];
-  const Part32 q = p32[t.start + (lane < t.count ? lane : 0)];
-  float x0 = q.x, x1 = q.x, y0 = q.y, y1 = q.y;
-  for (int o = 32; o > 0; o >>= 1) {
-    x0 = fminf(x0, __shfl_xor(x0, o, 64));
-    x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
-    y0 = fminf(y0, __shfl_xor(y0, o, 64));
-    y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
+  for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
+       wid += 4 * gridDim.x) {
+    const Tile t = tiles[wid];
+    const Part32 q = p32[t.start + (lane < t.count ? lane : 0)];
+    float x0 = q.x, x1 = q.x, y0 = q.y, y1 = q.y;
+    for (int o = 32; o > 0; o >>= 1) {
+      x0 = fminf(x0, __shfl_xor(x0, o, 64));
+      x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
+      y0 = fminf(y0, __shfl_xor(y0, o, 64));
+      y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
+    }
+    if (lane == 0) box[wid] = make_float4(x0, x1, y0, y1);
   }
-  if (lane == 0) box[wid] = make_float4(x0, x1, y0, y1);
 }
 
 __global__ void __launch_bounds__(256) k_gather_gamma(const double* __restrict__ gamma,
@@ -552,7 +555,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.max_tiles = lay.max_tiles;
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
                      tile, t.tiles, t.ntiles);
-  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_tile_box, dim3(tile_loop_blocks(lay.max_tiles)), dim3(256), 0, st,
                      t.tiles, t.ntiles, t.part32, t.tile_box);
   return hipGetLastError();
 }
@@ -588,7 +591,7 @@ hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(nt, 256)), dim3(256), 0, st, k0, lstart, toff, nt,
                      nl, t.tile, tiles, ntiles);
-  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((lay.max_tiles + 3) / 4)), dim3(256), 0, st, tiles,
+  hipLaunchKernelGGL(k_tile_box, dim3(tile_loop_blocks(lay.max_tiles)), dim3(256), 0, st, tiles,
                      ntiles, p32, tbox);
   const P2PSched sched{reinterpret_cast<uint32_t*>(ws + lay.sched_cnt),
                        reinterpret_cast<uint32_t*>(ws + lay.sched_poff),
@@ -624,7 +627,7 @@ hipError_t radix_sort_pairs(uint32_t*& k0, uint32_t*& k1, int32_t*& i0, int32_t*
 
 hipError_t launch_tile_box(const Tile* tiles, const int32_t* ntiles, int64_t max_tiles,
                            const Part32* p32, float4* box, hipStream_t st) {
-  hipLaunchKernelGGL(k_tile_box, dim3(unsigned((max_tiles + 3) / 4)), dim3(256), 0, st, tiles,
+  hipLaunchKernelGGL(k_tile_box, dim3(tile_loop_blocks(max_tiles)), dim3(256), 0, st, tiles,
                      ntiles, p32, box);
   return hipGetLastError();
 }

@@ -45,6 +45,14 @@ constexpr int kM2LOffsets = 49;      // 7x7 table indexed by t = (ox, oy) in [-3
 constexpr int64_t kP2PPartsMin = 4096;
 constexpr int64_t kP2PPartsMax = 65536;
 constexpr int kP2PMinChunks = 8;      // smallest part worth a wave (source chunks)
+// Per-tile kernels of uniform cost (tile boxes, L2P) loop over the tiles with
+// at most this many workgroups of 4 waves, instead of one wave per tile of
+// capacity (most of which would find no tile).
+constexpr int kTileLoopBlocks = 4096;
+inline unsigned tile_loop_blocks(int64_t max_tiles) {
+  const int64_t b = (max_tiles + 3) / 4;
+  return unsigned(b < kTileLoopBlocks ? (b > 0 ? b : 1) : kTileLoopBlocks);
+}
 constexpr int kP2PMaxWaves = 262144;  // near-field grid cap (waves loop over the parts)
 inline __host__ __device__ int64_t p2p_parts(int64_t max_tiles) {
   const int64_t t = 4 * max_tiles;
