@@ -226,7 +226,7 @@ def main():
     from paper_0809_1810_amd import autotune as AT
 
     def run_path(L, p, prec, steps, warmup, timing=False, radius=0.0):
-        AT.apply_for(n, L)  # near-field launch shape from the autotuner's table
+        AT.apply_for(n, L, cutoff=radius != 0.0)  # near-field launch shape from the autotuner's table
         override_tuning(a, vf)
         tree = vf.Tree(x, y, L, p_max=p)
         tree.set_near_radius(radius)
@@ -401,7 +401,7 @@ def second_input(a, torch, vf, name):
     prec = vf.FP64 if r["precision"] == "fp64" else vf.FP32
 
     def run(L, p, pr, radius):
-        AT.apply_for(n, L)
+        AT.apply_for(n, L, cutoff=radius != 0.0)
         override_tuning(a, vf)
         t = vf.Tree(x, y, L, p_max=p)
         t.set_near_radius(radius)
@@ -486,7 +486,7 @@ def bench_eval_points(a, torch, vf):
         how = "learned" if not r["fallback"] else "fallback"
     log(f"[bench] evaluation points: {nt} on the root square, p={p} L={L} ({how}), "
         f"near radius {radius}")
-    AT.apply_for(n, L)
+    AT.apply_for(n, L, cutoff=radius != 0.0)
     override_tuning(a, vf)
     tree = vf.Tree(x, y, L, p_max=p)
     tree.set_near_radius(radius)
@@ -566,7 +566,7 @@ def bench_advect(a, torch, vf):
     ws = None
 
     def run(pp, LL, prec, rad, steps):
-        AT.apply_for(n, LL)
+        AT.apply_for(n, LL, cutoff=rad != 0.0)
         override_tuning(a, vf)
         x = x0.clone(); y = y0.clone()
         tree = vf.Tree(x, y, LL, p_max=pp)

@@ -6,7 +6,10 @@ have tighter bounding boxes) and waves per workgroup (1, 2, 4, 8).  For each
 workload the tuner times the P2P phase of FP32 evaluations with HIP events
 (median of repeated calls) for every shape, keeps the fastest, and writes a
 table keyed by log2 of the mean particles per leaf.  ``apply_for(n, levels)``
-sets the library's tuning from the nearest table entry.
+sets the library's tuning from the nearest table entry.  The table is measured
+with the paper's split; with the distance cut-off (``cutoff=True``) only
+64-target tiles (one lane per target) cull the ring sources lane-parallel, so
+the fastest 64-target shape of the entry is taken instead.
 
     python -m paper_0809_1810_amd.autotune --out tuning.json
 """
@@ -83,19 +86,25 @@ def tune(out=TABLE_PATH, log=print):
     return table
 
 
-def lookup(n, levels, path=TABLE_PATH):
-    """(tile, waves) of the table entry nearest in log2 particles per leaf."""
+def lookup(n, levels, path=TABLE_PATH, cutoff=False):
+    """(tile, waves) of the table entry nearest in log2 particles per leaf; with
+    ``cutoff`` the entry's fastest 64-target shape."""
     try:
         table = json.load(open(path))
     except (OSError, ValueError):
         return 64, 4
     ppl = math.log2(max(n, 1)) - 2 * levels
     e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
+    if cutoff:
+        t64 = {k: v for k, v in e.get("all_ms", {}).items() if k.startswith("64x")}
+        if t64:
+            return 64, int(min(t64, key=t64.get).split("x")[1])
+        return 64, int(e["waves"]) if int(e["tile"]) == 64 else 4
     return int(e["tile"]), int(e["waves"])
 
 
-def apply_for(n, levels, path=TABLE_PATH):
-    tile, waves = lookup(n, levels, path)
+def apply_for(n, levels, path=TABLE_PATH, cutoff=False):
+    tile, waves = lookup(n, levels, path, cutoff)
     V.set_tuning(tile=tile, waves=waves)
     return tile, waves
 

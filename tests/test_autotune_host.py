@@ -1,0 +1,38 @@
+"""Host logic of the near-field launch-shape table (no GPU): nearest entry by
+log2 of the mean particles per leaf; with the distance cut-off the entry's
+fastest 64-target shape (only one lane per target culls ring sources)."""
+import json
+
+from paper_0809_1810_amd import autotune as AT
+
+
+def _table(tmp_path):
+    entries = [
+        {"ppl_log2": 8.0, "tile": 64, "waves": 4,
+         "all_ms": {"64x2": 5.1, "64x4": 4.9, "32x4": 8.5, "16x4": 12.8}},
+        {"ppl_log2": 4.0, "tile": 16, "waves": 4,
+         "all_ms": {"64x1": 3.3, "64x2": 3.0, "64x4": 3.1, "16x4": 2.0, "32x2": 2.4}},
+        {"ppl_log2": 2.0, "tile": 32, "waves": 2},
+    ]
+    p = tmp_path / "tuning.json"
+    p.write_text(json.dumps({"entries": entries}))
+    return str(p)
+
+
+def test_nearest_entry(tmp_path):
+    path = _table(tmp_path)
+    assert AT.lookup(1 << 20, 6, path) == (64, 4)   # 2^20 / 4^6 = 2^8 per leaf
+    assert AT.lookup(1 << 20, 8, path) == (16, 4)   # 2^4 per leaf
+    assert AT.lookup(1 << 20, 9, path) == (32, 2)   # 2^2 per leaf
+
+
+def test_cutoff_takes_fastest_64_target_shape(tmp_path):
+    path = _table(tmp_path)
+    assert AT.lookup(1 << 20, 6, path, cutoff=True) == (64, 4)
+    assert AT.lookup(1 << 20, 8, path, cutoff=True) == (64, 2)
+    # an entry without timings of every shape keeps its waves or the default
+    assert AT.lookup(1 << 20, 9, path, cutoff=True) == (64, 4)
+
+
+def test_missing_table_defaults(tmp_path):
+    assert AT.lookup(1000, 3, str(tmp_path / "absent.json")) == (64, 4)

@@ -130,7 +130,7 @@ def test_clusters_full_size_benchmark_configuration(vf):
     radius = P.sigma * math.sqrt(2.0 * math.log(1e6))
     assert radius < 2 * _w(P, L)  # not clamped
     saved = vf.get_tuning()
-    AT.apply_for(P.n, L)
+    AT.apply_for(P.n, L, cutoff=True)
     try:
         print_case("clusters_1m_bench_config", n=P.n, levels=L, p=p, radius=radius,
                    tuning=vf.get_tuning())
