@@ -21,7 +21,8 @@
  *     contribute zero.
  *   - Array arguments are DEVICE pointers unless marked (host).  The caller owns
  *     every input, output and workspace buffer; the library never allocates
- *     device memory.  The library owns only the opaque tree handle.
+ *     device memory.  The library owns only the opaque tree and batch handles,
+ *     each with the HIP stream and events it creates (released with it).
  *   - Calls that take a `stream` (a hipStream_t passed as void*, NULL = the
  *     default stream) are asynchronous: they validate arguments on the host,
  *     enqueue kernels and return.  The caller synchronises before reading
@@ -130,8 +131,8 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
  * stream owned by the tree (created with it, default priority), concurrently
  * with the near-field schedule and the near field on `stream`; `stream` waits
  * for the gather (an event) before the near field and for the sweeps before
- * the far field is added.  Calls on one tree
- * from different streams race, as they share the tree's workspace.
+ * the far field is added.  Calls on one tree from different streams race, as
+ * they share the tree's workspace.
  * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_HIP. */
 vfmm_status_t vfmm_fmm_velocity(vfmm_tree_t tree, const double* gamma, double sigma, int32_t p,
                                 int32_t precision, double* u, double* v, void* stream);
@@ -253,9 +254,8 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
  * kernel, after waiting for the gather), 7 L2P (after waiting for phases 1-4:
  * sums the parts of split near-field tiles, adds the far field and writes the
  * result).  When a call evaluates both parts, the gather and phases 1-4 run
- * on the tree's stream while 5-6 run on the caller's, so their times
- * overlap.  After
- * vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
+ * on the tree's stream while 5-6 run on the caller's, so their times overlap.
+ * After vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
  * next max_calls evaluations record HIP events at the beginning and end of
  * each phase on the stream that runs it (no synchronisation).
  * vfmm_tree_read_timing waits for the recorded events, writes
@@ -373,14 +373,16 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
  * use_graph = 1: the first call captures the sequence in a hipGraph on
  * `stream` (which must not be the NULL stream) and every call replays it.
  * The first call also builds the translation tables (outside any capture).
- * Streams: after the tree build, the expansion sweeps (P2M, M2M, M2L, L2L) run
- * on a stream owned by the plan (created with it, default priority) beside the
- * near field on `stream`, which waits for them (events) before L2P; captured,
+ * Streams: once the particles are sorted into their leaves, the expansion
+ * sweeps (P2M, M2M, M2L, L2L) run on a stream owned by the plan (created with
+ * it, default priority) beside the near-field tiles and the near field on
+ * `stream`, which waits for them (events) before L2P; captured,
  * the two become branches of the graph.  The call behaves as one ordered
  * sequence on `stream`; runs of one plan from different streams race. */
 vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream);
 
-/* Releases the plan and its graph (not the workspace).  NULL is ignored. */
+/* Releases the plan with its graph, stream and events (not the workspace).
+ * NULL is ignored. */
 void vfmm_batch_destroy(vfmm_batch_t batch);
 
 /* One call for one batched evaluation (Sections 3.1-3.3 per instance):
