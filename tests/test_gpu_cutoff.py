@@ -150,3 +150,38 @@ def test_clusters_full_size_benchmark_configuration(vf):
     e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
     print(f"clusters_1m benchmark configuration: fp32 vs direct {e32:.3e}")
     assert e32 < 1e-6
+
+
+@pytest.mark.parametrize("tile,waves", [(32, 2), (16, 4)])
+def test_cutoff_on_every_tile_shape(vf, tile, waves):
+    """The distance cut-off with two and four lanes per target (each source
+    sub-stream tests its ring sources pair by pair): FP64 against the oracle
+    FMM with the same radius (1e-12), FP32 within FP32 rounding of the
+    64-target shape.  4000 uniform particles, L = 4 (leaf side
+    2.5 sigma), radius 2.5 leaf sides: three rings of leaves."""
+    P = W.uniform(4000, seed=21, sigma=0.05)
+    L, p = 4, 16
+    radius = 2.5 * _w(P, L)
+    print_case("cutoff_tile_shape", tile=tile, waves=waves, radius=radius)
+    g = dev(P.gamma)
+    saved = vf.get_tuning()
+    try:
+        vf.set_tuning(tile=64, waves=4)
+        t0 = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+        t0.set_near_radius(radius)
+        u0, v0 = (host(a) for a in t0.velocity(g, P.sigma, p, vf.FP32))
+        t0.close()
+        vf.set_tuning(tile=tile, waves=waves)
+        t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+        t.set_near_radius(radius)
+        u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+        u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+        t.close()
+    finally:
+        vf.set_tuning(tile=saved["tile"], waves=saved["waves"])
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, radius=radius)
+    assert rel_err(u64, v64, r.u, r.v)[0] < 1e-12
+    assert rel_err(u32, v32, u0, v0)[0] < 1e-6
+    r0 = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L)
+    den = np.max(np.hypot(r.u, r.v))
+    assert np.max(np.hypot(r.u - r0.u, r.v - r0.v)) / den > 1e-9  # the rings matter here
