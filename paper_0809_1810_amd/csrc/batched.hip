@@ -44,7 +44,12 @@ struct BatchInst {
 };
 
 constexpr int kBatchMaxLevels = 6;   // leaf index fits 12 key bits
-constexpr int kBatchKeyInst = 20;    // key = inst << 20 | leaf << 8 | sub-cell
+// Inside a leaf, particles are ordered by their cell kBatchSub levels deeper
+// (leaves here hold up to about a thousand particles, so 16 cells of tile
+// size keep the tiles compact; the single tree's clustered leaves need more)
+constexpr int kBatchSub = 2;
+constexpr int kBatchKeyInst = 12 + 2 * kBatchSub;  // key = inst << 16 | leaf << 4 | sub-cell
+constexpr int kBatchMaxCount = 4096;
 constexpr int kBatchPMax = 24;
 
 namespace {
@@ -127,14 +132,15 @@ __global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
   const BatchInst in = I[c];
   const int64_t j = i - in.part_off;
   const double* r = roots + 4 * c;
-  const int mf = 1 << (in.L + kSubLevels);
+  const int mf = 1 << (in.L + kBatchSub);
   const double fx = floor(((in.x[j] - r[0]) / r[2]) * double(mf));
   const double fy = floor(((in.y[j] - r[1]) / r[2]) * double(mf));
   const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
   const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
-  const uint32_t leaf = (uint32_t(iy >> kSubLevels) << in.L) | uint32_t(ix >> kSubLevels);
-  const uint32_t sub = spread4b(uint32_t(ix)) | (spread4b(uint32_t(iy)) << 1);
-  keys[i] = (uint32_t(c) << kBatchKeyInst) | (leaf << (2 * kSubLevels)) | sub;
+  const uint32_t leaf = (uint32_t(iy >> kBatchSub) << in.L) | uint32_t(ix >> kBatchSub);
+  const uint32_t cm = (1u << kBatchSub) - 1u;
+  const uint32_t sub = spread4b(uint32_t(ix) & cm) | (spread4b(uint32_t(iy) & cm) << 1);
+  keys[i] = (uint32_t(c) << kBatchKeyInst) | (leaf << (2 * kBatchSub)) | sub;
   idx[i] = int32_t(i);
 }
 
@@ -147,7 +153,7 @@ __global__ void __launch_bounds__(256) k_b_leaf_start(const int64_t* __restrict_
   if (q >= ls_off[count]) return;
   const int c = find_seg(ls_off, count, q);
   const int64_t k = q - ls_off[c];
-  const uint64_t key = (uint64_t(c) << kBatchKeyInst) + (uint64_t(k) << (2 * kSubLevels));
+  const uint64_t key = (uint64_t(c) << kBatchKeyInst) + (uint64_t(k) << (2 * kBatchSub));
   int64_t lo = 0, hi = ntot;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -167,7 +173,7 @@ __global__ void __launch_bounds__(256) k_b_local(const BatchInst* __restrict__ I
   const uint32_t key = keys[i];
   const int c = int(key >> kBatchKeyInst);
   const BatchInst in = I[c];
-  const uint32_t leaf = (key >> (2 * kSubLevels)) & 0xFFFu;
+  const uint32_t leaf = (key >> (2 * kBatchSub)) & 0xFFFu;
   const int ix = int(leaf & ((1u << in.L) - 1u)), iy = int(leaf >> in.L);
   const double* r = roots + 4 * c;
   const double cx = r[0] + (double(ix) + 0.5) * r[3];
@@ -206,7 +212,7 @@ __global__ void __launch_bounds__(256) k_b_tile_fill(const BatchInst* __restrict
   if (i >= ntot) return;
   const uint32_t key = keys[i];
   const int c = int(key >> kBatchKeyInst);
-  const int64_t gl = I[c].leaf_off + ((key >> (2 * kSubLevels)) & 0xFFFu);
+  const int64_t gl = I[c].leaf_off + ((key >> (2 * kBatchSub)) & 0xFFFu);
   const int32_t s = start[gl + c], cnt = start[gl + c + 1] - s;
   const int32_t r = int32_t(i) - s;
   if (r % kTile != 0) return;
@@ -773,8 +779,9 @@ struct BatchLayout {
 };
 
 vfmm_status_t check_instances(const vfmm_instance* in, int count) {
-  if (!in || count < 1 || count > (1 << (32 - kBatchKeyInst)))
-    return bfail(VFMM_ERR_INVALID_ARG, "count must be in [1, %d]", 1 << (32 - kBatchKeyInst));
+  static_assert(kBatchMaxCount <= (1 << (32 - kBatchKeyInst)), "instance index must fit the key");
+  if (!in || count < 1 || count > kBatchMaxCount)
+    return bfail(VFMM_ERR_INVALID_ARG, "count must be in [1, %d]", kBatchMaxCount);
   int64_t ntot = 0;
   for (int c = 0; c < count; ++c) {
     const vfmm_instance& a = in[c];
