@@ -6,10 +6,12 @@ have tighter bounding boxes) and waves per workgroup (1, 2, 4, 8).  For each
 workload the tuner times the P2P phase of FP32 evaluations with HIP events
 (median of repeated calls) for every shape, keeps the fastest, and writes a
 table keyed by log2 of the mean particles per leaf.  ``apply_for(n, levels)``
-sets the library's tuning from the nearest table entry.  The table is measured
-with the paper's split; with the distance cut-off (``cutoff=True``) only
-64-target tiles (one lane per target) cull the ring sources lane-parallel, so
-the fastest 64-target shape of the entry is taken instead.
+sets the library's tuning from the nearest table entry.  With the distance
+cut-off only 64-target tiles (one lane per target) cull the ring sources
+lane-parallel, so the tuner also times the 64-target shapes with the cut-off
+at the radius where one pair's kernel difference is 1e-6 (``cutoff_ms``), and
+``apply_for(..., cutoff=True)`` takes the fastest of those (or, for an entry
+without them, the fastest 64-target shape of the paper's split).
 
     python -m paper_0809_1810_amd.autotune --out tuning.json
 """
@@ -32,10 +34,14 @@ TILES = (64, 32, 16)
 WAVES = (1, 2, 4, 8)
 
 
-def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5):
-    """Median P2P phase time (ms) for one launch shape."""
+CUTOFF_TOL = 1e-6
+
+
+def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5, radius=0.0):
+    """Median P2P phase time (ms) for one launch shape (radius: near cut-off)."""
     V.set_tuning(tile=tile, waves=waves)
     t = V.Tree(x, y, levels, p_max=p)
+    t.set_near_radius(radius)
     t.velocity(g, sigma, p, V.FP32)
     t.enable_timing(reps)
     for _ in range(reps):
@@ -53,12 +59,17 @@ def tune_workload(name, P, p, levels, log=print):
         for waves in WAVES:
             res[(tile, waves)] = time_p2p(x, y, g, P.sigma, p, levels, tile, waves)
     best = min(res, key=res.get)
+    radius = P.sigma * math.sqrt(2.0 * math.log(1.0 / CUTOFF_TOL))
+    cut = {w: time_p2p(x, y, g, P.sigma, p, levels, 64, w, radius=radius) for w in WAVES}
+    cbest = min(cut, key=cut.get)
     entry = {"workload": name, "n": P.n, "levels": levels, "p": p,
              "ppl_log2": math.log2(P.n) - 2 * levels, "tile": best[0], "waves": best[1],
              "p2p_ms": res[best], "default_ms": res[(64, 4)],
-             "all_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in sorted(res.items())}}
+             "all_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in sorted(res.items())},
+             "cutoff_radius_sigma": round(radius / P.sigma, 4),
+             "cutoff_ms": {f"64x{w}": round(v, 4) for w, v in sorted(cut.items())}}
     log(f"[tune] {name} L={levels}: best tile {best[0]} waves {best[1]} {res[best]:.3f} ms "
-        f"(default 64x4 {res[(64, 4)]:.3f} ms)")
+        f"(default 64x4 {res[(64, 4)]:.3f} ms); with the cut-off 64x{cbest} {cut[cbest]:.3f} ms")
     return entry
 
 
@@ -96,7 +107,8 @@ def lookup(n, levels, path=TABLE_PATH, cutoff=False):
     ppl = math.log2(max(n, 1)) - 2 * levels
     e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
     if cutoff:
-        t64 = {k: v for k, v in e.get("all_ms", {}).items() if k.startswith("64x")}
+        t64 = e.get("cutoff_ms") or {k: v for k, v in e.get("all_ms", {}).items()
+                                     if k.startswith("64x")}
         if t64:
             return 64, int(min(t64, key=t64.get).split("x")[1])
         return 64, int(e["waves"]) if int(e["tile"]) == 64 else 4

@@ -13,6 +13,9 @@ def _table(tmp_path):
         {"ppl_log2": 4.0, "tile": 16, "waves": 4,
          "all_ms": {"64x1": 3.3, "64x2": 3.0, "64x4": 3.1, "16x4": 2.0, "32x2": 2.4}},
         {"ppl_log2": 2.0, "tile": 32, "waves": 2},
+        {"ppl_log2": 6.0, "tile": 64, "waves": 2,
+         "all_ms": {"64x1": 2.2, "64x2": 2.1, "16x4": 3.0},
+         "cutoff_ms": {"64x1": 2.08, "64x2": 2.11, "64x4": 2.24, "64x8": 2.5}},
     ]
     p = tmp_path / "tuning.json"
     p.write_text(json.dumps({"entries": entries}))
@@ -32,6 +35,9 @@ def test_cutoff_takes_fastest_64_target_shape(tmp_path):
     assert AT.lookup(1 << 20, 8, path, cutoff=True) == (64, 2)
     # an entry without timings of every shape keeps its waves or the default
     assert AT.lookup(1 << 20, 9, path, cutoff=True) == (64, 4)
+    # timings taken with the cut-off take precedence over the paper split's
+    assert AT.lookup(1 << 20, 7, path) == (64, 2)
+    assert AT.lookup(1 << 20, 7, path, cutoff=True) == (64, 1)
 
 
 def test_missing_table_defaults(tmp_path):
