@@ -50,6 +50,7 @@ constexpr int kBatchMaxLevels = 6;   // leaf index fits 12 key bits
 constexpr int kBatchSub = 2;
 constexpr int kBatchKeyInst = 12 + 2 * kBatchSub;  // key = inst << 16 | leaf << 4 | sub-cell
 constexpr int kBatchMaxCount = 4096;
+constexpr int kBatchP2PWaves = 4;  // near-field waves (tiles) per workgroup
 constexpr int kBatchPMax = 24;
 
 namespace {
@@ -505,7 +506,8 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
                                                const float4* __restrict__ tile_box,
                                                const double* __restrict__ roots,
                                                double2* __restrict__ nearv) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int wid =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wid >= *ntiles) return;
   const int lane = threadIdx.x & 63;
   const Tile tile = tiles[wid];
@@ -712,8 +714,9 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                      d.toff, ntot, nleaves, d.tiles, d.ntiles);
   e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, 4)), dim3(256), 0, st, d.inst, d.p32, d.start,
-                     d.tiles, d.ntiles, d.toff, d.tile_box, d.roots, d.nearv);
+  hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, kBatchP2PWaves)), dim3(64 * kBatchP2PWaves), 0, st,
+                     d.inst, d.p32, d.start, d.tiles, d.ntiles, d.toff, d.tile_box, d.roots,
+                     d.nearv);
   e = hipStreamWaitEvent(st, join, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_l2p, dim3(tile_loop_blocks(max_tiles)), dim3(256), 0, st, d.inst,
