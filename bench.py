@@ -43,6 +43,8 @@ METRIC = "particles/s at N=1M, max rel err ≤1e-6 vs FP64 direct; tuned vs plai
 FP32_PEAK_TFLOPS = 157.3
 P2P_FLOPS_PER_PAIR = 15
 AUDIT_TARGETS = 4096
+HOLDOUT_SEED = 7919
+CPU_MAX_WORKERS = 16
 
 
 def log(msg):
@@ -79,6 +81,93 @@ def p2p_pairs(leaf_start, levels):
     pad = np.pad(cnt, 1)
     nb = sum(pad[1 + dy:1 + dy + m, 1 + dx:1 + dx + m] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
     return int(np.sum(cnt * nb))
+
+
+def holdout_targets(n, k, exclude, seed):
+    """k distinct indices in [0, n) outside ``exclude``, drawn with another seed
+    (sorted int64): the sample on which the tuned accuracy is reported."""
+    pool = np.setdiff1d(np.arange(n, dtype=np.int64), np.asarray(exclude, np.int64))
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(pool, size=min(k, pool.size), replace=False)).astype(np.int64)
+
+
+_CPU = {}
+
+
+def _cpu_chunk(idx):
+    """One worker's share of the CPU baseline: the oracle's evaluation after the
+    upward sweep (downward sweep, L2P, near field, cut-off) at whole leaves."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fmm as OF
+    s = _CPU
+    with threadpool_limits(1):
+        OF.evaluate_targets(s["x"], s["y"], s["g"], s["sigma"], s["p"], s["tree"], s["me"], idx,
+                            s["radius"])
+    return len(idx)
+
+
+def cpu_oracle_child(spec):
+    """Runs in a child process (no GPU): times the float64 NumPy oracle FMM at
+    sampled targets, once on one thread and once over all usable cores (the
+    tree and upward sweep in this process, then whole target leaves spread over
+    forked workers), and prints the timings as one JSON line."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import fmm as OF
+    P = W.config(spec["workload"])
+    ts = W.sample_targets(P.n, spec["targets"], seed=99)
+    p, L, radius = spec["p"], spec["levels"], spec["radius"]
+    cores = max(1, min(CPU_MAX_WORKERS, len(os.sched_getaffinity(0))))
+    res = {}
+    for workers in (1, cores):
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            tree = OF.build_tree(P.x, P.y, L)
+            me = OF.upward_sweep(P.x + 1j * P.y, P.gamma, tree, p) if L >= 2 else {}
+            t_up = time.perf_counter() - t0
+            key = tree.leaf_key()[ts]
+            order = np.argsort(key, kind="stable")
+            cuts = np.nonzero(np.diff(key[order]))[0] + 1
+            leaves = np.split(ts[order], cuts)
+            # whole leaves per chunk, about 8 chunks per worker
+            nchunk = max(1, min(len(leaves), 8 * workers))
+            chunks = [np.concatenate(leaves[b[0]:b[-1] + 1])
+                      for b in np.array_split(np.arange(len(leaves)), nchunk) if len(b)]
+            _CPU.update(x=P.x, y=P.y, g=P.gamma, sigma=P.sigma, p=p, tree=tree, me=me,
+                        radius=radius)
+            if workers == 1:
+                for c in chunks:
+                    _cpu_chunk(c)
+            else:
+                with mp.get_context("fork").Pool(workers) as pool:
+                    pool.map(_cpu_chunk, chunks, chunksize=1)
+            dt = time.perf_counter() - t0
+        res[workers] = (dt, t_up)
+    print(json.dumps({"n_targets": int(len(ts)), "cores": cores,
+                      "one": res[1], "all": res[cores]}), flush=True)
+
+
+def cpu_baseline(workload, p, levels, radius, n_targets):
+    """The oracle timed in a child process (see cpu_oracle_child)."""
+    import subprocess
+    spec = json.dumps({"workload": workload, "p": p, "levels": levels, "radius": radius,
+                       "targets": n_targets})
+    r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--cpu-oracle-child", spec],
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU oracle child failed ({r.returncode}): {r.stderr[-2000:]}")
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    nt, cores = d["n_targets"], d["cores"]
+    (t1, up1), (tc, upc) = d["one"], d["all"]
+    what = (f"float64 NumPy oracle FMM (p={p}, levels={levels}, near cut-off radius {radius:.4g}) "
+            f"evaluated at {nt} sampled targets of the same workload, tree and full upward sweep "
+            f"included")
+    return {"value": round(nt / tc, 2), "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "sample": f"{what}; {tc:.1f} s on {cores} cores (upward sweep {upc:.1f} s in one "
+                      f"process, then whole target leaves over {cores} forked workers, one "
+                      f"thread each)",
+            "one_core": {"value": round(nt / t1, 2), "cores": 1,
+                         "sample": f"{what}; {t1:.1f} s on 1 thread (upward sweep {up1:.1f} s)"}}
 
 
 def fixed_radius(a, sigma, vf):
@@ -146,10 +235,14 @@ def main():
     ap.add_argument("--advect", type=int, default=0, metavar="K",
                     help="instead of the N=1M line, time K steps of advecting the particles with "
                          "their FMM velocity (Heun's method, two evaluations and rebuilds per step)")
+    ap.add_argument("--cpu-oracle-child", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--batched", action="store_true",
                     help="instead of the N=1M line, time 256 uneven instances evaluated as one "
                          "batch (graph replay) against one call per instance")
     a = ap.parse_args()
+
+    if a.cpu_oracle_child is not None:  # the CPU baseline's child process (no GPU)
+        return cpu_oracle_child(json.loads(a.cpu_oracle_child))
 
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU "
@@ -190,10 +283,14 @@ def main():
     side = float(probe.arrays()[0][2].item())
     probe.close()
 
-    # ---------------- audit targets and FP64 direct reference
+    # ---------------- audit targets and FP64 direct reference; a second,
+    # disjoint hold-out sample (another seed) on which the accuracy is reported
     tg = W.sample_targets(n, n_audit, seed=2024)
     tg_d = torch.from_numpy(tg).cuda()
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg_d)
+    th = holdout_targets(n, n_audit, tg, HOLDOUT_SEED)
+    th_d = torch.from_numpy(th).cuda()
+    uh, vh = vf.direct_velocity(x, y, g, P.sigma, targets=th_d)
     torch.cuda.synchronize()
 
     # ---------------- parameter choice
@@ -250,6 +347,7 @@ def main():
         ms = e0.elapsed_time(e1) / steps
         phases = tree.read_timing() if timing else []
         emax, erms, _ = vf.error_metrics(u[tg_d].contiguous(), v[tg_d].contiguous(), ud, vd)
+        hmax, hrms, _ = vf.error_metrics(u[th_d].contiguous(), v[th_d].contiguous(), uh, vh)
         far_phases = []
         if timing and L >= 2:
             # the expansion sweeps alone (far part only: no near field runs
@@ -260,13 +358,16 @@ def main():
             far_phases = tree.read_timing()
         _, _, ls = tree.arrays()
         pairs = p2p_pairs(ls.cpu().numpy(), L)
+        tw = tree.tuning()
         tree.close()
         return dict(ms=ms, wall_s=wall, phases=phases, far_phases=far_phases, emax=emax, erms=erms,
-                    pairs=pairs, tile_waves=list(vf.get_tuning().values()))
+                    holdout_emax=hmax, holdout_erms=hrms,
+                    pairs=pairs, tile_waves=[tw["tile"], tw["waves"]])
 
     log(f"[bench] tuned: p={p_t} L={L_t} precision={a.precision} near radius={radius_t}")
     tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True, radius=radius_t)
-    log(f"[bench] tuned {tuned['ms']:.3f} ms/step emax={tuned['emax']:.3e}")
+    log(f"[bench] tuned {tuned['ms']:.3f} ms/step emax={tuned['emax']:.3e} "
+        f"(hold-out {tuned['holdout_emax']:.3e})")
     plain = None
     if not a.no_plain:
         log(f"[bench] plain: p={p_plain} L={L_plain} fp64")
@@ -284,37 +385,19 @@ def main():
                 "work_counted": "local-list pairs only (cut-off ring pairs not counted)"
                 if radius_t else "local-list pairs"}
 
-    # ---------------- CPU baseline: the oracle on a bounded sample of targets
+    # ---------------- CPU baseline: the oracle on a bounded sample of targets,
+    # in a child process that never touches the GPU (it forks its own workers)
     cpu = None
     if not a.no_cpu_baseline:
-        try:
-            from threadpoolctl import threadpool_limits
-        except ImportError:
-            threadpool_limits = None
-        from oracle import fmm as OF
-        ts = W.sample_targets(n, a.cpu_targets, seed=99)
-        # the same method as the tuned path: its effective cut-off radius
         r_cpu = 0.0
         if radius_t != 0.0:
             r_auto = (6.0 if prec_t != vf.FP64 else math.sqrt(76.0)) * P.sigma
             r_cpu = min(r_auto if radius_t < 0 else radius_t, vf.NEAR_RINGS_MAX * side / 2 ** L_t)
         log(f"[bench] cpu baseline: oracle FMM (p={p_t}, L={L_t}, radius={r_cpu:.4g}) "
-            f"on {len(ts)} targets")
-        ctx = threadpool_limits(1) if threadpool_limits else None
-        if ctx:
-            ctx.__enter__()
-        c0 = time.perf_counter()
-        OF.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p_t, L_t, targets=ts, radius=r_cpu)
-        cdt = time.perf_counter() - c0
-        if ctx:
-            ctx.__exit__(None, None, None)
-        cpu = {"value": round(len(ts) / cdt, 2), "unit": "particles/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"float64 NumPy oracle FMM (p={p_t}, levels={L_t}, near cut-off "
-                         f"radius {r_cpu:.4g}) evaluated at {len(ts)} sampled targets of the "
-                         f"same {n}-particle workload, including its full upward sweep; "
-                         f"{cdt:.1f} s on 1 thread"}
-        log(f"[bench] cpu {cpu['value']} particles/s")
+            f"on {a.cpu_targets} targets, 1 thread and all cores")
+        cpu = cpu_baseline(a.workload, p_t, L_t, r_cpu, a.cpu_targets)
+        log(f"[bench] cpu {cpu['value']} particles/s ({cpu['cores']} cores), "
+            f"1 thread {cpu['one_core']['value']}")
 
     value = n / (tuned["ms"] * 1e-3)
     out = {
@@ -339,13 +422,20 @@ def main():
                             if radius_t < 0 else radius_t),
             "near_radius_sigma": radius_tag(radius_t, P.sigma),
         },
-        "accuracy": {"tuned_emax": tuned["emax"], "tuned_erms": tuned["erms"]},
+        "accuracy": {"tuned_emax": tuned["holdout_emax"], "tuned_erms": tuned["holdout_erms"],
+                     "holdout_emax": tuned["holdout_emax"], "holdout_erms": tuned["holdout_erms"],
+                     "holdout_targets": int(len(th)), "holdout_seed": HOLDOUT_SEED,
+                     "selection_sample_emax": tuned["emax"],
+                     "selection_sample_erms": tuned["erms"],
+                     "note": "tuned_emax is measured on the hold-out sample, disjoint from "
+                             "the targets the selector's audit used"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     if plain is not None:
         out["plain_fp64"] = {"value": round(n / (plain["ms"] * 1e-3), 1), "ms_per_step": round(plain["ms"], 4),
-                             "p": p_plain, "levels": L_plain, "emax": plain["emax"], "erms": plain["erms"],
+                             "p": p_plain, "levels": L_plain, "emax": plain["holdout_emax"],
+                             "erms": plain["holdout_erms"],
                              "p2p_ms": round(float(np.mean([ph["p2p"] for ph in plain["phases"]])), 4)}
         out["speedup_vs_plain"] = round(plain["ms"] / tuned["ms"], 3)
     out["phases_ms"] = {k: round(float(np.mean([ph[k] for ph in tuned["phases"]])), 4)
@@ -394,8 +484,11 @@ def second_input(a, torch, vf, name):
     probe = vf.Tree(x, y, 0, p_max=1)
     side = float(probe.arrays()[0][2].item())
     probe.close()
-    tg = torch.from_numpy(W.sample_targets(n, AUDIT_TARGETS, seed=2024)).cuda()
+    tg_h = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
+    tg = torch.from_numpy(tg_h).cuda()
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg)
+    th = torch.from_numpy(holdout_targets(n, AUDIT_TARGETS, tg_h, HOLDOUT_SEED)).cuda()
+    uh, vh = vf.direct_velocity(x, y, g, P.sigma, targets=th)
     r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights(), targets=tg,
                            reference=(ud, vd))
     prec = vf.FP64 if r["precision"] == "fp64" else vf.FP32
@@ -417,7 +510,7 @@ def second_input(a, torch, vf, name):
             t.velocity(g, P.sigma, p, pr, out=(u, v))
         e1.record()
         torch.cuda.synchronize()
-        emax, _, _ = vf.error_metrics(u[tg].contiguous(), v[tg].contiguous(), ud, vd)
+        emax, _, _ = vf.error_metrics(u[th].contiguous(), v[th].contiguous(), uh, vh)
         t.close()
         return e0.elapsed_time(e1) / a.steps, emax
 
@@ -429,7 +522,8 @@ def second_input(a, torch, vf, name):
             "value": round(n / (ms_t * 1e-3), 1), "unit": "particles/s",
             "ms_per_step": round(ms_t, 4), "p": r["p"], "levels": r["levels"],
             "precision": r["precision"], "near_radius": "auto" if r["radius"] < 0 else r["radius"],
-            "emax": e_t, "audit_trail": r["trail"],
+            "emax": e_t, "emax_sample": "hold-out: 4096 targets disjoint from the audit's",
+            "audit_emax": r["audit_emax"], "audit_trail": r["trail"],
             "plain_fp64": {"ms_per_step": round(ms_p, 4), "p": 20, "levels": Lp, "emax": e_p},
             "speedup_vs_plain": round(ms_p / ms_t, 3)}
 

@@ -30,7 +30,10 @@
  *   - Every entry point returns a status; 0 (VFMM_OK) is success and negative
  *     values are errors.  On error nothing has been enqueued (argument errors)
  *     or the outputs are unspecified (HIP errors); vfmm_last_error() returns a
- *     thread-local message.  No entry point aborts or throws.
+ *     thread-local message.  No entry point aborts or throws.  A HIP call that
+ *     runs out of memory, or a host handle that cannot be allocated, gives
+ *     VFMM_ERR_OUT_OF_MEMORY; NaN and infinite values are reported only by the
+ *     opt-in check of vfmm_tree_set_check_finite (VFMM_ERR_NONFINITE).
  *
  * Tree conventions (the paper leaves them open; fixed here):
  *   - root box: the bounding square of the particles, side
@@ -55,8 +58,10 @@ typedef int32_t vfmm_status_t;
 
 #define VFMM_OK 0
 #define VFMM_ERR_INVALID_ARG (-1)
+#define VFMM_ERR_OUT_OF_MEMORY (-2) /* a host handle or a HIP object could not be allocated */
 #define VFMM_ERR_HIP (-3)
 #define VFMM_ERR_UNSUPPORTED (-4)
+#define VFMM_ERR_NONFINITE (-5)     /* opt-in finiteness check found NaN or infinity */
 #define VFMM_ERR_WORKSPACE (-6)
 
 /* Arithmetic of the evaluation (vfmm_fmm_velocity `precision`).
@@ -437,16 +442,34 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
                           void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Tuning (process-wide settings chosen by the autotuner).
- *   VFMM_TUNE_P2P_TILE : particles per near-field tile for trees built from now
- *                        on: 64, 32 or 16 (one, two or four lanes per target;
- *                        also the source-chunk size of the far-pair test).
+ * Tuning (process-wide settings chosen by the autotuner).  Both are read when a
+ * tree is built (vfmm_build_tree); the tree keeps them for its lifetime, so
+ * trees tuned differently can be evaluated side by side.
+ *   VFMM_TUNE_P2P_TILE : particles per near-field tile: 64, 32 or 16 (one, two
+ *                        or four lanes per target; also the source-chunk size
+ *                        of the far-pair test).
  *   VFMM_TUNE_P2P_WAVES: waves per workgroup of the near-field launch: 1, 2, 4, 8.
  * Results do not depend on the settings beyond float32 summation order. */
 #define VFMM_TUNE_P2P_TILE 1
 #define VFMM_TUNE_P2P_WAVES 2
 vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value);
 int32_t vfmm_get_tuning(int32_t param); /* -1 for an unknown parameter */
+/* The setting a tree was built with (-1 for a NULL tree or an unknown parameter). */
+int32_t vfmm_tree_get_tuning(vfmm_tree_t tree, int32_t param);
+
+/* Opt-in finiteness check (enable != 0; 0 turns it off, the default).  After
+ * every later evaluation of this tree (vfmm_fmm_velocity*, vfmm_fmm_velocity_at,
+ * vfmm_advect's evaluations) the library counts NaN and infinite values among
+ * the circulations, the particle positions the tree was built on, and the
+ * velocities written, synchronises `stream` and returns VFMM_ERR_NONFINITE
+ * (with both counts in vfmm_last_error) if any was found; the outputs are
+ * written either way.  Points of vfmm_fmm_velocity_at outside the root square
+ * receive NaN by definition and therefore fail the check.  Because it
+ * synchronises, an evaluation on a stream under graph capture is refused
+ * (VFMM_ERR_INVALID_ARG) while the check is on.  The first enable allocates two
+ * counters of pinned host memory, freed with the tree.
+ * Errors: VFMM_ERR_INVALID_ARG (NULL tree), VFMM_ERR_OUT_OF_MEMORY. */
+vfmm_status_t vfmm_tree_set_check_finite(vfmm_tree_t tree, int32_t enable);
 
 /* Releases the tree handle (not the caller's workspace).  NULL is ignored. */
 void vfmm_tree_destroy(vfmm_tree_t tree);

@@ -302,14 +302,23 @@ def fmm_velocity(x, y, gamma, sigma, p, levels, domain=None, targets=None,
     (``cutoff_correction``), counted in the near part."""
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
     gamma = np.asarray(gamma, np.float64)
-    z = x + 1j * y
     tree = build_tree(x, y, levels, domain)
     tidx = np.arange(len(x)) if targets is None else np.asarray(targets, np.int64)
+    me = upward_sweep(x + 1j * y, gamma, tree, p) if levels >= 2 else {}
+    return evaluate_targets(x, y, gamma, sigma, p, tree, me, tidx, radius, keep_expansions)
+
+
+def evaluate_targets(x, y, gamma, sigma, p, tree: Tree, me, tidx, radius=0.0,
+                     keep_expansions=False) -> FMMResult:
+    """Everything of ``fmm_velocity`` after the upward sweep, for the particles
+    ``tidx``: the downward sweep of their leaves and ancestors, L2P, the near
+    field and the cut-off correction.  Disjoint target sets can be evaluated
+    separately (in parallel) from one tree and one upward sweep ``me``."""
+    z = x + 1j * y
     fu = np.zeros(len(tidx)); fv = np.zeros(len(tidx))
-    me = le = {}
-    L = levels
+    le = {}
+    L = tree.levels
     if L >= 2:
-        me = upward_sweep(z, gamma, tree, p)
         leaves = {(int(tree.ix[i]), int(tree.iy[i])) for i in tidx}
         le = downward_sweep(me, tree, p, leaves)
         for box in leaves:

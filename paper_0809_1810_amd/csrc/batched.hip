@@ -136,8 +136,8 @@ __global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
   const int mf = 1 << (in.L + kBatchSub);
   const double fx = floor(((in.x[j] - r[0]) / r[2]) * double(mf));
   const double fy = floor(((in.y[j] - r[1]) / r[2]) * double(mf));
-  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
-  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
+  const int ix = !(fx >= 0.0) ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
+  const int iy = !(fy >= 0.0) ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
   const uint32_t leaf = (uint32_t(iy >> kBatchSub) << in.L) | uint32_t(ix >> kBatchSub);
   const uint32_t cm = (1u << kBatchSub) - 1u;
   const uint32_t sub = spread4b(uint32_t(ix) & cm) | (spread4b(uint32_t(iy) & cm) << 1);
@@ -901,7 +901,7 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   if (es == hipSuccess) es = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
   if (es != hipSuccess) {
     delete b;
-    return bfail(VFMM_ERR_HIP, "batch stream / events: %s", hipGetErrorString(es));
+    return bfail(hip_status(es), "batch stream / events: %s", hipGetErrorString(es));
   }
   for (int p = 0; p <= VFMM_MAX_P; ++p) b->tab_at[p] = L.tab_at[p];
   b->count = count;
@@ -989,7 +989,7 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
     e = hipMemcpy(d.seg_il64, seg_il64.data(), 4 * seg_il64.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete b;
-    return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
+    return bfail(hip_status(e), "batch tables: %s", hipGetErrorString(e));
   }
   *out = b;
   return VFMM_OK;
@@ -1011,29 +1011,29 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
                                    reinterpret_cast<double*>(static_cast<char*>(t.ops) + ops_bytes(p)), st);
       if (e != hipSuccess) break;
     }
-    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "batch tables: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return bfail(hip_status(e), "batch tables: %s", hipGetErrorString(e));
     b->tables_built = true;
   }
   if (!use_graph) {
     e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->l2l_tot,
                          b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st,
                          b->side, b->fork, b->join);
-    return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "batch run: %s", hipGetErrorString(e));
+    return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "batch run: %s", hipGetErrorString(e));
   }
   if (!b->exec) {
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return bfail(hip_status(e), "begin capture: %s", hipGetErrorString(e));
     hipError_t le = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot,
                                      b->l2l_tot, b->maxL, b->nseg, b->mfma_tiles, b->nseg64,
                                      b->mfma_tiles64, st, b->side, b->fork, b->join);
     e = hipStreamEndCapture(st, &b->graph);
     if (le != hipSuccess || e != hipSuccess)
-      return bfail(VFMM_ERR_HIP, "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+      return bfail(hip_status(le != hipSuccess ? le : e), "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
     e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) return bfail(VFMM_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return bfail(hip_status(e), "instantiate: %s", hipGetErrorString(e));
   }
   e = hipGraphLaunch(b->exec, st);
-  return e == hipSuccess ? VFMM_OK : bfail(VFMM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+  return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "graph launch: %s", hipGetErrorString(e));
 }
 
 void vfmm_batch_destroy(vfmm_batch_t b) { delete b; }

@@ -86,6 +86,12 @@ __global__ void __launch_bounds__(64 * kDirectWaves) k_direct(
   }
 }
 
+// Maximum that keeps a NaN: fmax would return the other argument and drop it,
+// so a NaN velocity would vanish from the error instead of poisoning it.
+__device__ __forceinline__ double max_nan(double a, double b) {
+  return (a > b || a != a) ? a : b;
+}
+
 __global__ void __launch_bounds__(256) k_metrics_partial(const double* __restrict__ u,
                                                          const double* __restrict__ v,
                                                          const double* __restrict__ ur,
@@ -95,17 +101,17 @@ __global__ void __launch_bounds__(256) k_metrics_partial(const double* __restric
   double mx = 0.0, ss = 0.0, mr = 0.0;
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
     const double d = hypot(u[i] - ur[i], v[i] - vr[i]);
-    mx = fmax(mx, d);
+    mx = max_nan(mx, d);
     ss += d * d;
-    mr = fmax(mr, hypot(ur[i], vr[i]));
+    mr = max_nan(mr, hypot(ur[i], vr[i]));
   }
   s[0][threadIdx.x] = mx; s[1][threadIdx.x] = ss; s[2][threadIdx.x] = mr;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (int(threadIdx.x) < st) {
-      s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + st]);
+      s[0][threadIdx.x] = max_nan(s[0][threadIdx.x], s[0][threadIdx.x + st]);
       s[1][threadIdx.x] += s[1][threadIdx.x + st];
-      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + st]);
+      s[2][threadIdx.x] = max_nan(s[2][threadIdx.x], s[2][threadIdx.x + st]);
     }
     __syncthreads();
   }
@@ -117,17 +123,17 @@ __global__ void __launch_bounds__(256) k_metrics_final(const double* __restrict_
   __shared__ double s[3][256];
   double mx = 0.0, ss = 0.0, mr = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) {
-    mx = fmax(mx, part[3 * b]);
+    mx = max_nan(mx, part[3 * b]);
     ss += part[3 * b + 1];
-    mr = fmax(mr, part[3 * b + 2]);
+    mr = max_nan(mr, part[3 * b + 2]);
   }
   s[0][threadIdx.x] = mx; s[1][threadIdx.x] = ss; s[2][threadIdx.x] = mr;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (int(threadIdx.x) < st) {
-      s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + st]);
+      s[0][threadIdx.x] = max_nan(s[0][threadIdx.x], s[0][threadIdx.x + st]);
       s[1][threadIdx.x] += s[1][threadIdx.x + st];
-      s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + st]);
+      s[2][threadIdx.x] = max_nan(s[2][threadIdx.x], s[2][threadIdx.x + st]);
     }
     __syncthreads();
   }
@@ -149,7 +155,37 @@ __global__ void __launch_bounds__(256) k_error_field(const double* __restrict__ 
   out[i] = log10(d > 1e-300 ? d : (d == d ? 1e-300 : d));
 }
 
+__global__ void k_clear_counter(unsigned long long* c) {
+  if (threadIdx.x == 0) c[0] = 0ull;
+}
+
+// One atomic per wave: the wave's count of NaN / infinite values.
+__global__ void __launch_bounds__(256) k_count_nonfinite(const double* __restrict__ a, int64_t n,
+                                                         int64_t stride,
+                                                         unsigned long long* __restrict__ c) {
+  unsigned long long cnt = 0;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    cnt += __builtin_isfinite(a[i * stride]) ? 0 : 1;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(c, cnt);
+}
+
 }  // namespace
+
+hipError_t launch_clear_counter(unsigned long long* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_counter, dim3(1), dim3(64), 0, st, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const double* a, int64_t n, int64_t stride,
+                                  unsigned long long* counter, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > kReduceBlocks) nb = kReduceBlocks;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(unsigned(nb)), dim3(256), 0, st, a, n, stride,
+                     counter);
+  return hipGetLastError();
+}
 
 hipError_t launch_error_field(const double* u, const double* v, const double* ur,
                               const double* vr, int64_t n, const double* metrics, double* out,

@@ -228,8 +228,8 @@ __global__ void __launch_bounds__(256) k_leaf_hist(const double* __restrict__ x,
   const int m = 1 << lev;
   const double fx = floor(((x[i] - x0) / S) * double(m));
   const double fy = floor(((y[i] - y0) / S) * double(m));
-  const int ix = fx < 0.0 ? 0 : (fx > double(m - 1) ? m - 1 : int(fx));
-  const int iy = fy < 0.0 ? 0 : (fy > double(m - 1) ? m - 1 : int(fy));
+  const int ix = !(fx >= 0.0) ? 0 : (fx > double(m - 1) ? m - 1 : int(fx));
+  const int iy = !(fy >= 0.0) ? 0 : (fy > double(m - 1) ? m - 1 : int(fy));
   atomicAdd(&counts[int64_t(iy) * m + ix], 1u);
 }
 

@@ -568,7 +568,7 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   else sd = near_scale(sigma);
   const float far2 = float(P2PMath<R>::kFarSigma2 * sigma * sigma);
   const float ser2 = float(P2PMath<R>::kSeriesSigma2 * sigma * sigma);
-  const int wpb = tuning_waves();
+  const int wpb = t.waves;
   // bound on the number of parts: target tiles + min(P, chunks / K) with
   // chunks <= target tiles x source tiles and K >= kP2PMinChunks
   const int64_t pairs_bound = tg.max_tiles * t.max_tiles / kP2PMinChunks + 1;

@@ -105,7 +105,7 @@ vfmm_status_t vfmm_mlp_forward(const float* params, int32_t bf16, const float* x
   if (!params || !x || !y) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
   if (batch < 1 || batch > (int64_t(1) << 30)) return sfail(VFMM_ERR_INVALID_ARG, "bad batch");
   hipError_t e = launch_mlp_forward(params, bf16 != 0, x, batch, y, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "mlp forward: %s", hipGetErrorString(e));
+  return e == hipSuccess ? VFMM_OK : sfail(hip_status(e), "mlp forward: %s", hipGetErrorString(e));
 }
 
 vfmm_status_t vfmm_mlp_gradient(const float* params, int32_t bf16, const float* x,
@@ -122,7 +122,7 @@ vfmm_status_t vfmm_mlp_gradient(const float* params, int32_t bf16, const float* 
   float* yv = reinterpret_cast<float*>(s + a256(size_t(nb) * mlp_param_count() * 4) + a256(size_t(nb) * 4));
   hipError_t e = launch_mlp_gradient(params, bf16 != 0, x, target, batch, yv, part, lpart, grad,
                                      loss, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "mlp gradient: %s", hipGetErrorString(e));
+  return e == hipSuccess ? VFMM_OK : sfail(hip_status(e), "mlp gradient: %s", hipGetErrorString(e));
 }
 
 vfmm_status_t vfmm_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
@@ -130,7 +130,7 @@ vfmm_status_t vfmm_mlp_adam(float* params, float* m, float* v, const float* grad
   if (!params || !m || !v || !grad) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
   if (step < 1 || !(lr > 0.f)) return sfail(VFMM_ERR_INVALID_ARG, "step >= 1 and lr > 0 required");
   hipError_t e = launch_adam(params, m, v, grad, step, lr, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "adam: %s", hipGetErrorString(e));
+  return e == hipSuccess ? VFMM_OK : sfail(hip_status(e), "adam: %s", hipGetErrorString(e));
 }
 
 size_t vfmm_select_scratch_bytes(int64_t n) { return select_scratch(n < 1 ? 1 : n); }
@@ -149,7 +149,7 @@ vfmm_status_t vfmm_particle_stats(const double* x, const double* y, const double
   hipError_t e = launch_stats(x, y, gamma, n, part, out, st);
   if (e == hipSuccess) e = hipMemcpyAsync(stats, out, 12 * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  return e == hipSuccess ? VFMM_OK : sfail(VFMM_ERR_HIP, "stats: %s", hipGetErrorString(e));
+  return e == hipSuccess ? VFMM_OK : sfail(hip_status(e), "stats: %s", hipGetErrorString(e));
 }
 
 vfmm_status_t vfmm_selector_features(const double* st, int64_t n, double sigma, int32_t p,
@@ -204,7 +204,7 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
   hipError_t e = launch_stats(x, y, gamma, n, part, sout, st);
   if (e == hipSuccess) e = hipMemcpyAsync(stats, sout, sizeof(stats), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select stats: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return sfail(hip_status(e), "select stats: %s", hipGetErrorString(e));
   const double S = root_side(stats);
   const double root3[3] = {0.5 * (stats[8] + stats[9]) - 0.5 * S, 0.5 * (stats[10] + stats[11]) - 0.5 * S, S};
   const size_t nl = size_t(1) << (2 * lh);
@@ -213,7 +213,7 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
   std::vector<uint32_t> hc(nl);
   if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), counts, nl * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select histogram: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return sfail(hip_status(e), "select histogram: %s", hipGetErrorString(e));
 
   // occupancy at every level <= lh by 2 x 2 pooling; near-field pair counts
   std::vector<std::vector<double>> occ(lh + 1);
@@ -241,7 +241,7 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
   if (e == hipSuccess) e = launch_mlp_forward(params, true, xd, ncand, yd, st);
   if (e == hipSuccess) e = hipMemcpyAsync(pred.data(), yd, size_t(ncand) * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return sfail(VFMM_ERR_HIP, "select network: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return sfail(hip_status(e), "select network: %s", hipGetErrorString(e));
 
   // cost model (seconds on one MI355X, FP32 evaluation): near-field pairs,
   // per-particle expansion work, per-box translations, per-level launches

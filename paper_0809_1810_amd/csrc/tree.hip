@@ -105,8 +105,9 @@ __device__ inline uint32_t point_key(double x, double y, const double* __restric
   // floor(t 2^(L+4)) >> 4 == floor(t 2^L): the leaf decision is unchanged
   double fx = floor(((x - x0) / S) * scale);
   double fy = floor(((y - y0) / S) * scale);
-  const int ix = fx < 0.0 ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
-  const int iy = fy < 0.0 ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
+  // clamped before the conversion; a NaN coordinate goes to cell 0
+  const int ix = !(fx >= 0.0) ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
+  const int iy = !(fy >= 0.0) ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
   const uint32_t leaf = (uint32_t(iy >> kSubLevels) << levels) | uint32_t(ix >> kSubLevels);
   const uint32_t sub = spread4(uint32_t(ix)) | (spread4(uint32_t(iy)) << 1);
   return (leaf << (2 * kSubLevels)) | sub;
@@ -535,7 +536,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.me = ws + lay.me;
   t.le = ws + lay.le;
   t.ops = ws + lay.ops;
-  t.reduce = reinterpret_cast<double*>(ws + lay.reduce);
+  t.check = reinterpret_cast<unsigned long long*>(ws + lay.check);
   hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, k0, i0, n,
                      root, levels, t.part64, t.part32);
   t.tile = tile;

@@ -37,7 +37,12 @@ struct vfmm_tree_s {
   // (gathered), L2P for the sweeps (join)
   hipStream_t side;
   hipEvent_t fork, gathered, join;
+  // opt-in finiteness check of evaluations (vfmm_tree_set_check_finite):
+  // the two device counters are read back into this pinned host pair
+  int check_finite;
+  unsigned long long* check_host;
   ~vfmm_tree_s() {
+    if (check_host) (void)hipHostFree(check_host);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     if (gathered) (void)hipEventDestroy(gathered);
@@ -76,7 +81,7 @@ int tuning_waves() { return g_waves.load(); }
 namespace {
 
 vfmm_status_t hip_fail(hipError_t e, const char* where) {
-  return fail(VFMM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+  return fail(hip_status(e), "%s: %s", where, hipGetErrorString(e));
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -148,7 +153,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
   L.le = take(size_t(nbox) * p_max * sizeof(double2));
   L.ops = take(ops_bytes(p_max));
-  L.reduce = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+  L.check = take(2 * sizeof(unsigned long long));
   L.total = off;
   return L;
 }
@@ -163,6 +168,8 @@ const char* vfmm_status_string(vfmm_status_t s) {
   switch (s) {
     case VFMM_OK: return "ok";
     case VFMM_ERR_INVALID_ARG: return "invalid argument";
+    case VFMM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case VFMM_ERR_NONFINITE: return "non-finite value";
     case VFMM_ERR_HIP: return "HIP runtime error";
     case VFMM_ERR_UNSUPPORTED: return "unsupported";
     case VFMM_ERR_WORKSPACE: return "workspace too small or misaligned";
@@ -197,7 +204,7 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   if (reinterpret_cast<uintptr_t>(workspace) & 255)
     return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   vfmm_tree_s* t = new (std::nothrow) vfmm_tree_s{};
-  if (!t) return fail(VFMM_ERR_INVALID_ARG, "host allocation of the tree handle failed");
+  if (!t) return fail(VFMM_ERR_OUT_OF_MEMORY, "host allocation of the tree handle failed");
   t->lay = lay;
   t->ws = static_cast<char*>(workspace);
   t->n = n;
@@ -216,8 +223,9 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
     delete t;
     return hip_fail(e, "tree stream / events");
   }
+  t->dev.waves = tuning_waves();  // the launch shape is the tree's from now on
   e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, tuning_tile(), t->dev,
-                                   static_cast<hipStream_t>(stream));
+                        static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     delete t;
     return hip_fail(e, "vfmm_build_tree");
@@ -243,6 +251,46 @@ vfmm_status_t check_eval(vfmm_tree_t t, const double* gamma, double sigma, int32
   if (precision < VFMM_FP64 || precision > VFMM_M2L_FP16)
     return fail(VFMM_ERR_INVALID_ARG, "unknown precision %d", precision);
   if (parts < 1 || parts > 3) return fail(VFMM_ERR_INVALID_ARG, "parts must be 1, 2 or 3");
+  return VFMM_OK;
+}
+
+// The opt-in finiteness check needs a synchronisation, which a stream under
+// graph capture cannot take: refuse before anything is enqueued.
+vfmm_status_t check_capture(vfmm_tree_t t, hipStream_t st) {
+  if (!t->check_finite) return VFMM_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(VFMM_ERR_INVALID_ARG,
+                "the finiteness check synchronises the stream; disable it under graph capture");
+  return VFMM_OK;
+}
+
+// After an evaluation on st: counts NaN and infinite values among the inputs
+// (circulations, the tree's box-local particle positions) and the nout
+// velocities written, waits for the stream and reports them.
+vfmm_status_t finite_check(vfmm_tree_t t, const double* gamma, const double* u, const double* v,
+                           int64_t nout, hipStream_t st) {
+  if (!t->check_finite) return VFMM_OK;
+  unsigned long long* c = t->dev.check;
+  hipError_t e = launch_clear_counter(c, st);
+  if (e == hipSuccess) e = launch_clear_counter(c + 1, st);
+  if (e == hipSuccess) e = launch_count_nonfinite(gamma, t->n, 1, c, st);
+  const double* pos = reinterpret_cast<const double*>(t->dev.part64);
+  const int64_t stride = sizeof(Part64) / sizeof(double);
+  if (e == hipSuccess) e = launch_count_nonfinite(pos, t->n, stride, c, st);
+  if (e == hipSuccess) e = launch_count_nonfinite(pos + 1, t->n, stride, c, st);
+  if (e == hipSuccess) e = launch_count_nonfinite(u, nout, 1, c + 1, st);
+  if (e == hipSuccess) e = launch_count_nonfinite(v, nout, 1, c + 1, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(t->check_host, c, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "finiteness check");
+  const unsigned long long nin = t->check_host[0], nvel = t->check_host[1];
+  if (nin || nvel)
+    return fail(VFMM_ERR_NONFINITE, "%llu non-finite input values (circulations, positions), "
+                "%llu non-finite velocity components", nin, nvel);
   return VFMM_OK;
 }
 
@@ -419,9 +467,12 @@ vfmm_status_t vfmm_fmm_velocity_parts(vfmm_tree_t t, const double* gamma, double
   vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, parts, u, v);
   if (s) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = check_capture(t, st))) return s;
   const Marks mark(t);
   mark.begin(kPhGather, st);
-  return evaluate(t, self_targets(t->dev, t->lay), gamma, sigma, p, precision, parts, u, v, mark, st);
+  s = evaluate(t, self_targets(t->dev, t->lay), gamma, sigma, p, precision, parts, u, v, mark, st);
+  if (s) return s;
+  return finite_check(t, gamma, u, v, t->n, st);
 }
 
 vfmm_status_t vfmm_targets_workspace_bytes(int64_t n_targets, int32_t levels, size_t* bytes) {
@@ -451,13 +502,16 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   if (reinterpret_cast<uintptr_t>(workspace) & 255)
     return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = check_capture(t, st))) return s;
   const Marks mark(t);
   mark.begin(kPhGather, st);
   TargetsDev tg{};
   hipError_t e = launch_build_targets(xt, yt, n_targets, t->dev, t->levels, lay,
                                       static_cast<char*>(workspace), tg, st);
   if (e != hipSuccess) return hip_fail(e, "evaluation points");
-  return evaluate(t, tg, gamma, sigma, p, precision, parts, u, v, mark, st);
+  s = evaluate(t, tg, gamma, sigma, p, precision, parts, u, v, mark, st);
+  if (s) return s;
+  return finite_check(t, gamma, u, v, n_targets, st);
 }
 
 vfmm_status_t vfmm_error_field(const double* u, const double* v, const double* ur,
@@ -632,6 +686,11 @@ vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t t, int32_t max_calls) {
   if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
   if (max_calls < 0 || max_calls > 100000) return fail(VFMM_ERR_INVALID_ARG, "max_calls out of range");
   const size_t need = size_t(max_calls) * 2 * VFMM_N_PHASES;
+  try {
+    t->ev.reserve(need);
+  } catch (const std::bad_alloc&) {
+    return fail(VFMM_ERR_OUT_OF_MEMORY, "host allocation of %zu timing events failed", need);
+  }
   while (t->ev.size() < need) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -682,6 +741,25 @@ int32_t vfmm_get_tuning(int32_t param) {
   if (param == VFMM_TUNE_P2P_TILE) return g_tile.load();
   if (param == VFMM_TUNE_P2P_WAVES) return g_waves.load();
   return -1;
+}
+
+int32_t vfmm_tree_get_tuning(vfmm_tree_t t, int32_t param) {
+  if (!t) return -1;
+  if (param == VFMM_TUNE_P2P_TILE) return t->dev.tile;
+  if (param == VFMM_TUNE_P2P_WAVES) return t->dev.waves;
+  return -1;
+}
+
+vfmm_status_t vfmm_tree_set_check_finite(vfmm_tree_t t, int32_t enable) {
+  if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
+  if (enable && !t->check_host) {
+    void* h = nullptr;
+    hipError_t e = hipHostMalloc(&h, 2 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned host counters");
+    t->check_host = static_cast<unsigned long long*>(h);
+  }
+  t->check_finite = enable ? 1 : 0;
+  return VFMM_OK;
 }
 
 void vfmm_tree_destroy(vfmm_tree_t t) { delete t; }

@@ -22,7 +22,15 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include "../../include/vfmm.h"
+
 namespace vfmm {
+
+// Status of a failed HIP call: running out of device memory is reported as
+// such, every other runtime error as VFMM_ERR_HIP.
+inline vfmm_status_t hip_status(hipError_t e) {
+  return e == hipErrorOutOfMemory ? VFMM_ERR_OUT_OF_MEMORY : VFMM_ERR_HIP;
+}
 
 constexpr int kMaxP = 40;
 constexpr int kMaxLevels = 12;
@@ -110,7 +118,7 @@ struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, sched_near;
-  size_t part64, part32, part32s, me, le, ops, reduce, total;
+  size_t part64, part32, part32s, me, le, ops, check, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
 };
@@ -124,6 +132,7 @@ struct TreeDev {
   int32_t* perm;         // sorted position -> input index
   int32_t* leaf_start;   // [nleaves + 1]
   int tile;              // particles per P2P tile: 64, 32 or 16 (64 / lanes per target)
+  int waves;             // waves per workgroup of the near-field launch: 1, 2, 4 or 8
   int64_t max_tiles;     // capacity of the tile arrays
   Tile* tiles;           // P2P target tiles (<= tile consecutive particles of one leaf)
   int32_t* ntiles;       // device count of tiles
@@ -135,7 +144,7 @@ struct TreeDev {
   void* me;
   void* le;
   void* ops;
-  double* reduce;
+  unsigned long long* check;  // [2] counters of the opt-in finiteness check
   P2PSched sched;        // near-field schedule of the particles as targets
 };
 
@@ -175,8 +184,8 @@ TargetLayout make_target_layout(int64_t nt, int levels);
 hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
                              const double* domain, const Layout& lay, char* ws, int tile,
                              TreeDev& t, hipStream_t stream);
-// Tuning parameters (process-wide): P2P tile size for new trees, P2P waves per
-// workgroup for launches.
+// Tuning parameters (process-wide): the P2P tile size and waves per workgroup
+// that trees built from now on take (each tree keeps its own).
 int tuning_tile();
 int tuning_waves();
 // Circulations into the sorted particle records; with sigma > 0 also the
@@ -225,6 +234,12 @@ hipError_t launch_error_field(const double* u, const double* v, const double* ur
 hipError_t launch_direct(const double* x, const double* y, const double* g, int64_t n,
                          double sigma, const int64_t* targets, const double* xt,
                          const double* yt, int64_t nt, double* u, double* v, hipStream_t stream);
+// Finiteness check: counter[0] = 0 (a fill kernel, so that the clear can be
+// captured in a graph), then counter[0] += number of non-finite values among
+// a[k * stride], k < n (one launch per array).
+hipError_t launch_clear_counter(unsigned long long* counter, hipStream_t stream);
+hipError_t launch_count_nonfinite(const double* a, int64_t n, int64_t stride,
+                                  unsigned long long* counter, hipStream_t stream);
 hipError_t launch_error_metrics(const double* u, const double* v, const double* ur,
                                 const double* vr, int64_t n, double* partial, double* out,
                                 hipStream_t stream);

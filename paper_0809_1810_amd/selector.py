@@ -260,12 +260,13 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     trail = []
     e, _ = run(p, L, V.FP32)
     trail.append([p, L, "fp32", e, None])
-    while e > slack * tol and p < 20:
+    # a non-finite error (NaN or infinity) fails the audit
+    while not (e <= slack * tol) and p < 20:
         p = min(20, p + 2)
         e, _ = run(p, L, V.FP32)
         trail.append([p, L, "fp32", e, None])
     out.update(p=p, levels=L, audited=True, audit_emax=e, trail=trail)
-    if e > slack * tol:
+    if not (e <= slack * tol):
         root = V.Tree(x, y, 0, p_max=1)
         side = float(root.arrays()[0][2].item())
         root.close()

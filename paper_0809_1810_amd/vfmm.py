@@ -8,6 +8,7 @@ raises ``VfmmUnavailable``: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 
@@ -21,7 +22,8 @@ PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 MAX_P, MAX_LEVELS = 40, 12
 
 OK = 0
-ERR_INVALID_ARG, ERR_HIP, ERR_UNSUPPORTED, ERR_WORKSPACE = -1, -3, -4, -6
+ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_WORKSPACE = (
+    -1, -2, -3, -4, -5, -6)
 
 
 class VfmmUnavailable(ImportError):
@@ -95,6 +97,8 @@ _SIGS = {
     "vfmm_batch_destroy": (None, [C.c_void_p]),
     "vfmm_set_tuning": (C.c_int32, [C.c_int32, C.c_int32]),
     "vfmm_get_tuning": (C.c_int32, [C.c_int32]),
+    "vfmm_tree_get_tuning": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "vfmm_tree_set_check_finite": (C.c_int32, [C.c_void_p, C.c_int32]),
     "vfmm_select_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "vfmm_particle_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
@@ -294,6 +298,17 @@ class Tree:
         _check(lib().vfmm_tree_set_near_radius(self._h, float(radius)), "vfmm_tree_set_near_radius")
         self.near_radius = float(radius)
 
+    def set_check_finite(self, enable: bool = True):
+        """Opt-in finiteness check of later evaluations (raises VfmmError with
+        status ERR_NONFINITE when an input or output holds NaN or infinity)."""
+        _check(lib().vfmm_tree_set_check_finite(self._h, 1 if enable else 0),
+               "vfmm_tree_set_check_finite")
+
+    def tuning(self):
+        """The near-field launch shape this tree was built with: {tile, waves}."""
+        return {"tile": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_TILE)),
+                "waves": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_WAVES))}
+
     def enable_timing(self, max_calls: int):
         _check(lib().vfmm_tree_enable_timing(self._h, int(max_calls)), "vfmm_tree_enable_timing")
         self._tslots = int(max_calls)
@@ -443,8 +458,9 @@ def error_metrics(u, v, u_ref, v_ref):
                                     v_ref.data_ptr(), n, scratch.data_ptr(), out.data_ptr(),
                                     _stream()), "vfmm_error_metrics")
     mx, ss, den = out.cpu().tolist()
-    den = den if den > 0 else 1.0
-    return mx / den, (ss / n) ** 0.5 / den, den
+    if den == 0.0:  # an all-zero reference: absolute errors (a NaN maximum stays NaN)
+        den = 1.0
+    return mx / den, math.sqrt(ss / n) / den, den
 
 
 # ----------------------------------------------------------------- selector network

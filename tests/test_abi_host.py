@@ -94,9 +94,38 @@ def test_build_tree_rejects_before_device_work():
 
 def test_status_strings():
     l = _lib()
-    for s in (0, -1, -3, -4, -6, -99):
-        assert len(l.vfmm_status_string(s)) > 0
+    names = {}
+    for s in (0, -1, -2, -3, -4, -5, -6, -99):
+        names[s] = l.vfmm_status_string(s).decode()
+        assert len(names[s]) > 0
+    # every documented status has its own name
+    assert len({names[s] for s in (0, -1, -2, -3, -4, -5, -6)}) == 7
+    assert names[-99] == "unknown status"
+    assert "memory" in names[B.ERR_OUT_OF_MEMORY] and "finite" in names[B.ERR_NONFINITE]
     assert l.vfmm_version() >= 100
+
+
+def test_status_codes_match_the_header():
+    import re
+    text = open(B.HEADER_PATH).read()
+    consts = dict(re.findall(r"#define\s+(VFMM_(?:OK|ERR_[A-Z_]+))\s+\(?(-?[0-9]+)\)?", text))
+    for name in ("INVALID_ARG", "OUT_OF_MEMORY", "HIP", "UNSUPPORTED", "NONFINITE", "WORKSPACE"):
+        assert int(consts["VFMM_ERR_" + name]) == getattr(B, "ERR_" + name)
+    assert int(consts["VFMM_OK"]) == B.OK
+
+
+def test_tree_settings_reject_null_tree():
+    l = _lib()
+    assert l.vfmm_tree_set_check_finite(None, 1) == B.ERR_INVALID_ARG
+    assert l.vfmm_tree_get_tuning(None, B.TUNE_P2P_TILE) == -1
+    assert l.vfmm_tree_get_tuning(None, B.TUNE_P2P_WAVES) == -1
+    # process-wide settings: validated, read back
+    old = (l.vfmm_get_tuning(B.TUNE_P2P_TILE), l.vfmm_get_tuning(B.TUNE_P2P_WAVES))
+    assert l.vfmm_set_tuning(B.TUNE_P2P_TILE, 48) == B.ERR_INVALID_ARG
+    assert l.vfmm_set_tuning(B.TUNE_P2P_WAVES, 3) == B.ERR_INVALID_ARG
+    assert l.vfmm_set_tuning(99, 1) == B.ERR_INVALID_ARG
+    assert l.vfmm_get_tuning(99) == -1
+    assert (l.vfmm_get_tuning(B.TUNE_P2P_TILE), l.vfmm_get_tuning(B.TUNE_P2P_WAVES)) == old
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

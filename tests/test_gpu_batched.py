@@ -106,3 +106,30 @@ def test_one_call_batched_equals_plan_and_run(vf):
     b.run_oneshot()
     for i, (u, v) in enumerate(zip(b.u, b.v)):
         assert np.array_equal(host(u), ref[i][0]) and np.array_equal(host(v), ref[i][1]), i
+
+
+def test_full_sweep_batch_against_oracle(vf):
+    """The parameter-sweep batch at its own size: 256 instances (N log-uniform in
+    [2048, 65536], uniform or lattice, p in 5..20, L in 3..6; 4.9M particles)
+    evaluated as one batch.  Every instance is compared with the float64 oracle
+    FMM at its own (p, L) on 64 sampled targets, to 1e-6 of the sample's
+    maximum velocity; the 64 instances with p > 16 take the float64 expansion
+    path."""
+    insts = _instances(256, seed=4, n_range=(2048, 65536), levels=(3, 6))
+    b = vf.Batch(insts)
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    worst = {False: 0.0, True: 0.0}
+    for i, d in enumerate(insts):
+        P = d["P"]
+        if i % 32 == 0:
+            print_case("batch_c4", i=i, n=P.n, p=d["p"], levels=d["levels"])
+        tg = W.sample_targets(P.n, 64, seed=1000 + i)
+        r = F.fmm_velocity(P.x, P.y, P.gamma, d["sigma"], d["p"], d["levels"], targets=tg)
+        u, v = host(b.u[i]), host(b.v[i])
+        e = rel_err(u[tg], v[tg], r.u, r.v)[0]
+        worst[d["p"] > 16] = max(worst[d["p"] > 16], e)
+        assert e < 1e-6, (i, P.n, d["p"], d["levels"], e)
+    print("worst e_max: p <= 16 %.2e, p > 16 %.2e" % (worst[False], worst[True]))
+    assert sum(d["p"] > 16 for d in insts) == 64
+    b.close()

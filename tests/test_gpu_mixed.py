@@ -115,3 +115,33 @@ def test_mixed_precision_full_size_clusters(vf):
     assert errs["fp32"][0][0] < errs["fp16"][0][0] < errs["bf16"][0][0]
     assert errs["fp16"][0][0] < 30 * 2.0 ** -11 * far_share
     assert errs["bf16"][0][0] < 30 * 2.0 ** -8 * far_share
+
+
+@pytest.mark.parametrize("name,levels,p,ntg", [("lattice_320", 5, 12, 2000),
+                                               ("clusters_1m", 7, 12, 4096)])
+def test_16bit_m2l_against_oracle(vf, name, levels, p, ntg):
+    """BF16 / FP16 M2L against the float64 oracle FMM at the same (p, L) on
+    sampled targets, with per-result bars on the maximum and RMS error as a
+    fraction of the far field's share of the velocity: the input rounding
+    unit (2^-8 BF16, 2^-11 FP16) summed over up to 27 interaction-list
+    contributions per level, about 4e-3 (BF16) and 4e-4 (FP16) at most and a
+    third of that in RMS.  FP32 stays within 1e-6."""
+    P = W.config(name)
+    print_case("16bit_vs_oracle", workload=name, levels=levels, p=p, targets=ntg)
+    tg = W.sample_targets(P.n, ntg, seed=17)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, levels, targets=tg)
+    den = np.max(np.hypot(r.u, r.v))
+    far_share = np.max(np.hypot(r.far_u, r.far_v)) / den
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=p)
+    g = dev(P.gamma)
+    errs = {}
+    for nm, prec in (("fp32", vf.FP32), ("fp16", vf.M2L_FP16), ("bf16", vf.M2L_BF16)):
+        u, v = (host(a) for a in t.velocity(g, P.sigma, p, prec))
+        errs[nm] = rel_err(u[tg], v[tg], r.u, r.v)
+    t.close()
+    print("far share", far_share,
+          {k: f"max {e[0]:.2e} rms {e[1]:.2e} (of far share: {e[0] / far_share:.2e}, "
+              f"{e[1] / far_share:.2e})" for k, e in errs.items()})
+    assert errs["fp32"][0] < 1e-6
+    assert errs["fp16"][0] <= 4e-4 * far_share and errs["fp16"][1] <= 1.4e-4 * far_share
+    assert errs["bf16"][0] <= 4e-3 * far_share and errs["bf16"][1] <= 1.4e-3 * far_share

@@ -222,3 +222,19 @@ def test_planted_mistakes_are_caught(c1, monkeypatch):
         assert err() > 1e-6, name
         monkeypatch.undo()
     assert err() < 1e-13
+
+
+def test_split_target_evaluation_equals_whole():
+    """Disjoint target sets evaluated from one tree and one upward sweep (how the
+    CPU baseline spreads the oracle over processes) give exactly the values of
+    one evaluation at all targets."""
+    P = W.clusters(3000, seed=31, n_clusters=3)
+    whole = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, 9, 4, radius=3 * P.sigma)
+    tree = F.build_tree(P.x, P.y, 4)
+    me = F.upward_sweep(P.x + 1j * P.y, P.gamma, tree, 9)
+    key = tree.leaf_key()
+    leaves = np.unique(key)
+    for group in np.array_split(leaves, 5):  # whole leaves per set
+        part = np.nonzero(np.isin(key, group))[0]
+        r = F.evaluate_targets(P.x, P.y, P.gamma, P.sigma, 9, tree, me, part, radius=3 * P.sigma)
+        assert np.array_equal(r.u, whole.u[part]) and np.array_equal(r.v, whole.v[part])

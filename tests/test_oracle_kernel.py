@@ -121,3 +121,64 @@ def test_paper_lattice_sizes():
     got = [W.paper_lamb_oseen(n).n for n in want]
     assert got == want
     assert W.paper_single_source(8836).n == 8837
+
+
+# ---------------------------------------------------------------- eq. 8: separate points
+
+@pytest.mark.parametrize("r", [1e-4, 0.01, 0.03, 0.2])
+def test_direct_at_single_source_matches_stokes(r):
+    """One blob away from the origin, points on a circle around it: the
+    velocity is tangential (counter-clockwise for positive circulation) with
+    the magnitude given by Stokes' theorem on eq. 3.  A reversed offset
+    (source minus point) flips the direction and fails here."""
+    sigma, gam = 0.02, 1.7
+    xs, ys = 0.3, -0.45
+    th = np.linspace(0.0, 2 * math.pi, 7, endpoint=False) + 0.1
+    xe = xs + r * np.cos(th); ye = ys + r * np.sin(th)
+    u, v = K.direct_velocity_at(xe, ye, np.array([xs]), np.array([ys]), np.array([gam]), sigma)
+    ut = gam * _blob_azimuthal_from_vorticity(r, sigma)
+    assert np.max(np.abs(u - (-ut * np.sin(th)))) <= 1e-12 * ut
+    assert np.max(np.abs(v - ut * np.cos(th))) <= 1e-12 * ut
+
+
+def test_direct_at_equals_direct_at_the_particles():
+    """Evaluated at the particles' own positions, eq. 8 is eq. 9: the point's
+    own particle sits at zero offset and contributes nothing."""
+    P = W.clusters(900, seed=21, n_clusters=3)
+    u, v = K.direct_velocity(P.x, P.y, P.gamma, P.sigma)
+    ua, va = K.direct_velocity_at(P.x, P.y, P.x, P.y, P.gamma, P.sigma)
+    scale = np.max(np.hypot(u, v))
+    assert np.max(np.abs(ua - u)) <= 1e-14 * scale
+    assert np.max(np.abs(va - v)) <= 1e-14 * scale
+
+
+def test_direct_at_brute_force_loop():
+    """Plain Python loops over (point, particle) at off-particle points, with
+    one point exactly on a particle."""
+    P = W.uniform(40, seed=23, sigma=0.08)
+    rng = np.random.default_rng(24)
+    xe = np.append(rng.uniform(-1.2, 1.2, 15), P.x[7]); ye = np.append(rng.uniform(-1.2, 1.2, 15), P.y[7])
+    ua, va = K.direct_velocity_at(xe, ye, P.x, P.y, P.gamma, P.sigma)
+    for t in range(xe.shape[0]):
+        su = sv = 0.0
+        for j in range(P.n):
+            dx = xe[t] - P.x[j]; dy = ye[t] - P.y[j]
+            r2 = dx * dx + dy * dy
+            if r2 == 0.0:
+                continue
+            r = math.sqrt(r2)
+            mag = P.gamma[j] * (1.0 - math.exp(-r2 / (2 * P.sigma ** 2))) / (2 * math.pi * r)
+            su += -mag * dy / r; sv += mag * dx / r
+        assert abs(ua[t] - su) <= 1e-13 * max(1.0, abs(su))
+        assert abs(va[t] - sv) <= 1e-13 * max(1.0, abs(sv))
+
+
+def test_direct_at_far_point_is_point_vortex():
+    """Far from every blob the kernel of eq. 6 is the point vortex of eq. 15:
+    a single source seen from 50 sigma away gives Gamma / (2 pi r) exactly
+    (the Gaussian factor is below the float64 rounding unit)."""
+    sigma = 0.01
+    u, v = K.direct_velocity_at(np.array([0.5]), np.array([0.0]), np.array([0.0]),
+                                np.array([0.0]), np.array([2.0]), sigma)
+    assert u[0] == 0.0
+    assert abs(v[0] - 2.0 / (2 * math.pi * 0.5)) <= 2e-16 * v[0]
