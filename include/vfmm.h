@@ -68,7 +68,9 @@ typedef int32_t vfmm_status_t;
  *   VFMM_FP64      : every step in float64.
  *   VFMM_FP32      : P2M, M2M, M2L, L2L, L2P and P2P in float32 on scaled
  *                    coefficients; the P2P source loop keeps compensated float32
- *                    sums; output float64.
+ *                    sums; output float64.  For p > 16 the shifts (P2M, M2M,
+ *                    L2L) run in float64 and M2L stays float32 on the matrix
+ *                    cores (so do the two modes below).
  *   VFMM_M2L_BF16  : as VFMM_FP32 but M2L on bfloat16 matrix cores with float32
  *                    accumulation.
  *   VFMM_M2L_FP16  : as VFMM_FP32 but M2L on float16 matrix cores with float32
@@ -218,6 +220,19 @@ vfmm_status_t vfmm_error_metrics(const double* u, const double* v, const double*
                                  const double* v_ref, int64_t n, void* scratch, double* out,
                                  void* stream);
 
+/* vfmm_error_metrics without the scratch argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The partial sums go to a device array of
+ * the library (512 x 3 float64 = 12 KB per GPU, reserved when the library is
+ * loaded and held until the process ends; its address is looked up on the
+ * first call made with each device current), so the call itself allocates
+ * nothing and any n >= 1 fits.  All calls on one GPU share that array and it
+ * keeps the last call's partial sums: calls that overlap on one GPU (different
+ * streams or threads) race.  Same output and errors as vfmm_error_metrics. */
+vfmm_status_t vfmm_error_metrics_noalloc(const double* u, const double* v, const double* u_ref,
+                                         const double* v_ref, int64_t n, double* out,
+                                         void* stream);
+
 /* Per-point error field behind the paper's spatial error maps (Section 5):
  * out[i] = log10(|dW_i| / max |W_ref|) (device, n), with |dW_i| the distance
  * between (u_i, v_i) and (u_ref_i, v_ref_i), floored at log10(1e-300) = -300;
@@ -341,6 +356,71 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
                                  const float* feat_mean, const float* feat_std, double margin,
                                  void* scratch, size_t scratch_bytes, int32_t* p, int32_t* levels,
                                  double* predicted_log10, int32_t* used_fallback, void* stream);
+
+/* Selection with audit (Section 5: the error of an evaluation measured against
+ * the direct sum, eq. 7, on sampled targets and normalised by the maximum
+ * velocity, Section 5.1).  Steps:
+ *   1. the network's choice (vfmm_select_params);
+ *   2. with VFMM_SELECT_AUDIT: that (p, L) evaluated in FP32 at all particles
+ *      and its e_max taken on the n_audit targets (device int64 particle
+ *      indices) against (u_ref, v_ref) (device, n_audit each; NULL = the FP64
+ *      direct sum there, computed now).  The choice passes if
+ *      e_max <= slack * tol (a NaN or infinite error fails).  While it fails, p
+ *      is raised by 2 (up to 20) at the same L.  If p = 20 still fails, the
+ *      conservative choice (p = 20, deepest L <= max_levels with leaf side
+ *      >= 8 sigma) is evaluated in FP64 and returned (used_fallback = 1);
+ *   3. with VFMM_SELECT_CUTOFF as well, for a passing FP32 choice: the same p
+ *      one and two levels deeper (if <= max_levels, with at most about four
+ *      particles per leaf and leaf side >= 6 sigma / VFMM_NEAR_RINGS_MAX) with
+ *      the distance cut-off of the near field (Section 4.1's distance a) at
+ *      two radii, VFMM_NEAR_RADIUS_AUTO and sigma sqrt(2 ln(1/tol)) (where one
+ *      pair's kernel difference falls to the tolerance), each audited; the
+ *      passing ones and the choice of step 2 are timed (median of time_reps
+ *      tree rebuild + evaluation runs between HIP events on `stream`) and the
+ *      fastest is returned.
+ * Every evaluation is recorded in out->steps (at most VFMM_SELECT_TRAIL_MAX).
+ *   params, feat_mean, feat_std, margin: as in vfmm_select_params.
+ *   max_levels: deepest tree the workspace is sized for (<= 0: the default,
+ *             min(10, deepest L with 4^L <= 4n)); deeper candidates are
+ *             skipped and a deeper network choice is clamped to it.
+ *   workspace (device): vfmm_select_audit_workspace_bytes(n, n_audit,
+ *             max_levels) bytes, 256-byte aligned, caller-owned: the trial
+ *             trees, their velocities and the audit's buffers.
+ *   out (host): the choice (p, levels, precision VFMM_FP32 or VFMM_FP64,
+ *             near_radius 0 / > 0 / VFMM_NEAR_RADIUS_AUTO), the network's own
+ *             choice and prediction, the audited e_max of the returned choice
+ *             and the steps.  Trees are built with the process-wide tuning.
+ * Synchronises `stream` (many times).
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_WORKSPACE, VFMM_ERR_HIP and those of
+ * the calls above. */
+#define VFMM_SELECT_AUDIT 1
+#define VFMM_SELECT_CUTOFF 2
+#define VFMM_SELECT_TRAIL_MAX 16
+typedef struct vfmm_audit_step {
+  int32_t p, levels, precision;
+  double near_radius;
+  double emax;  /* e_max on the audit targets */
+  double ms;    /* median timed rebuild + evaluation, -1 if not timed */
+} vfmm_audit_step;
+typedef struct vfmm_selection {
+  int32_t p, levels, precision;
+  double near_radius;
+  int32_t used_fallback;
+  int32_t network_p, network_levels, network_fallback;
+  double predicted_log10;  /* the network's prediction for its choice (NaN for its fallback) */
+  double audit_emax;       /* audited e_max of the returned choice (NaN without audit) */
+  int32_t n_steps;
+  vfmm_audit_step steps[VFMM_SELECT_TRAIL_MAX];
+} vfmm_selection;
+vfmm_status_t vfmm_select_audit_workspace_bytes(int64_t n, int64_t n_audit, int32_t max_levels,
+                                                size_t* bytes);
+vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const double* gamma,
+                                    int64_t n, double sigma, double tol, const float* params,
+                                    const float* feat_mean, const float* feat_std, double margin,
+                                    const int64_t* targets, int64_t n_audit, const double* u_ref,
+                                    const double* v_ref, int32_t flags, double slack,
+                                    int32_t time_reps, int32_t max_levels, void* workspace,
+                                    size_t ws_bytes, vfmm_selection* out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched evaluation of many independent instances (uneven n, p, levels), the

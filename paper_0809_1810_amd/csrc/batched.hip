@@ -724,7 +724,6 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
   return hipGetLastError();
 }
 
-void set_last_error(const char* msg);
 
 }  // namespace vfmm
 

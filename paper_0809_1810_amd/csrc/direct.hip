@@ -12,7 +12,17 @@
 // out[0] = max_i |dW_i|, out[1] = sum_i |dW_i|^2, out[2] = max_i |W_ref,i|; and
 // the per-point error field log10(|dW_i| / max |W_ref|) behind the paper's
 // spatial error maps (Section 5).
+#include <cstdio>
+#include <mutex>
+
 #include "vfmm_device.hpp"
+
+// Partial sums of vfmm_error_metrics_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends (12 KB).  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address hipGetSymbolAddress gives for the
+// current device, looked up once per device.
+static __device__ __align__(256) double scratch[vfmm::kReduceBlocks * 3];
 
 namespace vfmm {
 
@@ -215,4 +225,58 @@ hipError_t launch_error_metrics(const double* u, const double* v, const double* 
   return hipGetLastError();
 }
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Address of this device's copy of `scratch` (looked up on the first call
+// made with the device current).
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return hipSuccess;
+}
+
+}  // namespace
+
 }  // namespace vfmm
+
+extern "C" vfmm_status_t vfmm_error_metrics_noalloc(const double* u, const double* v,
+                                                    const double* ur, const double* vr, int64_t n,
+                                                    double* out, void* stream) {
+  using namespace vfmm;
+  // the reduction writes at most kReduceBlocks partial triples, whatever n is
+  static_assert(sizeof(scratch) >= size_t(kReduceBlocks) * 3 * sizeof(double),
+                "scratch holds the partial sums of every block");
+  if (!u || !v || !ur || !vr || !out) {
+    set_last_error("vfmm_error_metrics_noalloc: null pointer");
+    return VFMM_ERR_INVALID_ARG;
+  }
+  if (n < 1) {
+    set_last_error("vfmm_error_metrics_noalloc: n must be >= 1");
+    return VFMM_ERR_INVALID_ARG;
+  }
+  double* part = nullptr;
+  hipError_t e = scratch_address(&part);
+  if (e == hipSuccess)
+    e = launch_error_metrics(u, v, ur, vr, n, part, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "vfmm_error_metrics_noalloc: %s", hipGetErrorString(e));
+    set_last_error(buf);
+    return hip_status(e);
+  }
+  return VFMM_OK;
+}

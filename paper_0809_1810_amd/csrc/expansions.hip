@@ -190,6 +190,38 @@ __global__ void __launch_bounds__(256) k_m2l_l2l(const typename Types<R>::C* __r
   le[box * p + n] = acc;
 }
 
+// float64 coefficients rounded to float32 (count complex values).
+__global__ void __launch_bounds__(256) k_narrow(const double2* __restrict__ a, int64_t count,
+                                                float2* __restrict__ b) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < count) b[i] = make_float2(float(a[i].x), float(a[i].y));
+}
+
+// float64 L2L at level l (l > 2 shifts the parent's float64 LE): one thread per
+// (box, n); the level's own M2L sum comes in float32 from the matrix cores.
+__global__ void __launch_bounds__(256) k_l2l64_add32(const float2* __restrict__ m2l,
+                                                     const double2* __restrict__ le_par,
+                                                     double2* __restrict__ le, int lev, int p,
+                                                     const double2* __restrict__ B) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t nb = int64_t(1) << (2 * lev);
+  if (t >= nb * p) return;
+  const int64_t box = t / p;
+  const int n = int(t % p);
+  const float2 own = m2l[box * p + n];
+  double2 acc = make_double2(double(own.x), double(own.y));
+  if (lev > 2) {
+    const int m = 1 << lev;
+    const int bx = int(box & (m - 1)), by = int(box >> lev);
+    const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
+    const int c = ((by & 1) << 1) | (bx & 1);
+    const double2* lp = le_par + pb * p;
+    const double2* b = B + (c * p + n) * p;
+    for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
+  }
+  le[box * p + n] = acc;
+}
+
 template <typename R, int PMAX>
 void launch_p2m_t(const TreeDev& t, int levels, int p, hipStream_t st) {
   using C = typename Types<R>::C;
@@ -269,6 +301,34 @@ hipError_t launch_p2m(const TreeDev& t, int levels, int p, int prec, hipStream_t
 
 hipError_t launch_m2m(const TreeDev& t, int levels, int p, int prec, hipStream_t st) {
   return prec == kFP64 ? m2m_t<double>(t, levels, p, st) : m2m_t<float>(t, levels, p, st);
+}
+
+hipError_t launch_downward_shift64(const TreeDev& t, int levels, int p, int prec,
+                                   hipStream_t st) {
+  if (levels < 2) return hipSuccess;
+  const int64_t count = n_boxes_2_to(levels) * p;
+  hipLaunchKernelGGL(k_narrow, dim3(unsigned((count + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const double2*>(t.me), count, static_cast<float2*>(t.me32));
+  TreeDev t32 = t;
+  t32.me = t.me32;
+  t32.le = t.le32;
+  hipError_t e = launch_downward_mfma(t32, levels, p, prec, st, false);
+  if (e != hipSuccess) return e;
+  const OpsLayout ol = ops_layout(p);
+  const double2* B = reinterpret_cast<const double2*>(static_cast<const char*>(t.ops) + ol.l2l64);
+  const float2* m2l = static_cast<const float2*>(t.le32);
+  double2* le = static_cast<double2*>(t.le);
+  for (int l = 2; l <= levels; ++l) {
+    const int64_t work = (int64_t(1) << (2 * l)) * p;
+    hipLaunchKernelGGL(k_l2l64_add32, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st,
+                       m2l + level_offset(l) * p, l > 2 ? le + level_offset(l - 1) * p : nullptr,
+                       le + level_offset(l) * p, l, p, B);
+  }
+  const int64_t leaf = (int64_t(1) << (2 * levels)) * p;
+  hipLaunchKernelGGL(k_narrow, dim3(unsigned((leaf + 255) / 256)), dim3(256), 0, st,
+                     le + level_offset(levels) * p, leaf,
+                     static_cast<float2*>(t.le32) + level_offset(levels) * p);
+  return hipGetLastError();
 }
 
 hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStream_t st) {

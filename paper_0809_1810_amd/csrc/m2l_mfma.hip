@@ -356,7 +356,8 @@ hipError_t launch_pack_m2l_mfma64(const void* ops, int p, double* out, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t st) {
+hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t st,
+                                bool with_l2l) {
   if (levels < 2) return hipSuccess;
   const OpsLayout ol = ops_layout(p);
   char* ops = static_cast<char*>(t.ops);
@@ -383,6 +384,7 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
   if (prec == kFP32) launch_mode<kModeF32>(t, levels, p, lt, ops + ol.mfma32, scales, st);
   else if (prec == kM2L_BF16) launch_mode<kModeBF16>(t, levels, p, lt, ops + ol.mfma16, scales, st);
   else launch_mode<kModeF16>(t, levels, p, lt, ops + ol.mfma16, scales, st);
+  if (!with_l2l) return hipGetLastError();
   const float2* B = reinterpret_cast<const float2*>(ops + ol.l2l32);
   float2* le = static_cast<float2*>(t.le);
   for (int l = 3; l <= levels; ++l) {

@@ -8,6 +8,7 @@
 // conservative choice p = 20 and the deepest level whose leaf side is at
 // least 8 sigma (keeping the kernel-substitution error of Section 4.1
 // negligible).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -30,7 +31,6 @@ hipError_t launch_stats(const double* x, const double* y, const double* g, int64
                         double* part, double* out, hipStream_t st);
 hipError_t launch_leaf_hist(const double* x, const double* y, int64_t n, const double* root3,
                             int lev, uint32_t* counts, hipStream_t st);
-void set_last_error(const char* msg);
 }  // namespace vfmm
 
 using namespace vfmm;
@@ -275,6 +275,314 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
     *pred_out = NAN;
     *fallback_out = 1;
   }
+  return VFMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Selection with audit (Section 5: the error of an evaluation is measured
+// against the direct sum of eq. 7 on sampled targets, normalised by the
+// maximum velocity, Section 5.1).
+
+namespace {
+
+// u[targets[k]], v[targets[k]] -> ut[k], vt[k]; an index outside [0, n) gives
+// NaN, which fails the audit.
+__global__ void __launch_bounds__(256) k_gather_targets(const double* __restrict__ u,
+                                                        const double* __restrict__ v,
+                                                        const int64_t* __restrict__ tg,
+                                                        int64_t nt, int64_t n,
+                                                        double* __restrict__ ut,
+                                                        double* __restrict__ vt) {
+  const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= nt) return;
+  const int64_t i = tg[k];
+  const bool ok = i >= 0 && i < n;
+  ut[k] = ok ? u[i] : __builtin_nan("");
+  vt[k] = ok ? v[i] : __builtin_nan("");
+}
+
+// Deepest level allowed by default: the candidate grid's bound and about four
+// particles per leaf.
+int default_max_levels(int64_t n) {
+  int l = 0;
+  while (l < kHistMax && (int64_t(1) << (2 * (l + 1))) <= 4 * n) ++l;
+  return l;
+}
+
+// The conservative choice: p = 20 and the deepest level whose leaf side is
+// at least 8 sigma (the kernel-substitution error of Section 4.1 is then
+// negligible), with about four particles per leaf at most.
+int conservative_levels(double S, double sigma, int64_t n, int max_levels) {
+  int L = 0;
+  while (L + 1 <= max_levels && S / std::ldexp(1.0, L + 1) / sigma >= 8.0 &&
+         (int64_t(1) << (2 * (L + 1))) <= 4 * n)
+    ++L;
+  return L;
+}
+
+struct AuditWs {
+  char* sel;
+  size_t sel_bytes;
+  char* tree;
+  size_t tree_bytes;
+  double *u, *v, *ut, *vt, *ur, *vr, *met_scratch, *met;
+  size_t total;
+};
+
+AuditWs audit_layout(char* base, int64_t n, int64_t nt, int max_levels) {
+  AuditWs w{};
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off += a256(b); return base + r; };
+  w.sel_bytes = select_scratch(n);
+  w.sel = take(w.sel_bytes);
+  size_t tb = 0;
+  vfmm_workspace_bytes(n, max_levels, kPMax, &tb);
+  w.tree_bytes = tb;
+  w.tree = take(tb);
+  w.u = reinterpret_cast<double*>(take(size_t(n) * 8));
+  w.v = reinterpret_cast<double*>(take(size_t(n) * 8));
+  w.ut = reinterpret_cast<double*>(take(size_t(nt) * 8));
+  w.vt = reinterpret_cast<double*>(take(size_t(nt) * 8));
+  w.ur = reinterpret_cast<double*>(take(size_t(nt) * 8));
+  w.vr = reinterpret_cast<double*>(take(size_t(nt) * 8));
+  w.met_scratch = reinterpret_cast<double*>(take(vfmm_metrics_scratch_bytes()));
+  w.met = reinterpret_cast<double*>(take(3 * 8));
+  w.total = off;
+  return w;
+}
+
+struct Auditor {
+  const double *x, *y, *g;
+  int64_t n;
+  double sigma;
+  const int64_t* tg;
+  int64_t nt;
+  const double *ur, *vr;
+  AuditWs w;
+  int reps;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+
+  // FMM of (p, L, precision, radius) at all particles, its error on the audit
+  // targets and, if `timed`, the median time of `reps` rebuild + evaluation
+  // runs (HIP events on the stream).
+  vfmm_status_t run(int p, int L, int prec, double radius, bool timed, double& e, double& ms) {
+    vfmm_tree_t t = nullptr;
+    vfmm_status_t s = vfmm_build_tree(x, y, n, L, nullptr, p, w.tree, w.tree_bytes, st, &t);
+    if (s) return s;
+    if (!(s = vfmm_tree_set_near_radius(t, radius)))
+      s = vfmm_fmm_velocity(t, g, sigma, p, prec, w.u, w.v, st);
+    if (!s) {
+      hipLaunchKernelGGL(k_gather_targets, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st,
+                         w.u, w.v, tg, nt, n, w.ut, w.vt);
+      hipError_t he = hipGetLastError();
+      if (he != hipSuccess) s = sfail(hip_status(he), "audit gather: %s", hipGetErrorString(he));
+    }
+    if (!s) s = vfmm_error_metrics(w.ut, w.vt, ur, vr, nt, w.met_scratch, w.met, st);
+    double m[3] = {0.0, 0.0, 0.0};
+    if (!s) {
+      hipError_t he = hipMemcpyAsync(m, w.met, sizeof(m), hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (he != hipSuccess) s = sfail(hip_status(he), "audit metrics: %s", hipGetErrorString(he));
+    }
+    ms = -1.0;
+    if (!s && timed) {
+      std::vector<float> times;
+      for (int r = 0; r < reps && !s; ++r) {
+        hipError_t he = hipEventRecord(e0, st);
+        if (he != hipSuccess) {
+          s = sfail(hip_status(he), "audit timing: %s", hipGetErrorString(he));
+          break;
+        }
+        if ((s = vfmm_tree_rebuild(t, x, y, nullptr, st))) break;
+        if ((s = vfmm_fmm_velocity(t, g, sigma, p, prec, w.u, w.v, st))) break;
+        he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&f, e0, e1);
+        if (he != hipSuccess) s = sfail(hip_status(he), "audit timing: %s", hipGetErrorString(he));
+        times.push_back(f);
+      }
+      if (!s) {
+        std::sort(times.begin(), times.end());
+        ms = double(times[times.size() / 2]);
+      }
+    }
+    vfmm_tree_destroy(t);
+    if (s) return s;
+    const double den = m[2] == 0.0 ? 1.0 : m[2];  // a NaN maximum stays NaN
+    e = m[0] / den;
+    return VFMM_OK;
+  }
+};
+
+void record(vfmm_selection* out, int p, int L, int prec, double radius, double e, double ms) {
+  if (out->n_steps >= VFMM_SELECT_TRAIL_MAX) return;
+  vfmm_audit_step& a = out->steps[out->n_steps++];
+  a.p = p;
+  a.levels = L;
+  a.precision = prec;
+  a.near_radius = radius;
+  a.emax = e;
+  a.ms = ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+vfmm_status_t vfmm_select_audit_workspace_bytes(int64_t n, int64_t n_audit, int32_t max_levels,
+                                                size_t* bytes) {
+  if (!bytes) return sfail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  if (n < 1 || n > 2147483647LL) return sfail(VFMM_ERR_INVALID_ARG, "n out of [1, 2^31-1]");
+  if (n_audit < 1 || n_audit > n) return sfail(VFMM_ERR_INVALID_ARG, "n_audit out of [1, n]");
+  if (max_levels <= 0) max_levels = default_max_levels(n);
+  if (max_levels > kMaxLevels) return sfail(VFMM_ERR_INVALID_ARG, "max_levels > %d", kMaxLevels);
+  *bytes = audit_layout(nullptr, n, n_audit, max_levels).total;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const double* gamma,
+                                    int64_t n, double sigma, double tol, const float* params,
+                                    const float* feat_mean, const float* feat_std, double margin,
+                                    const int64_t* targets, int64_t n_audit, const double* u_ref,
+                                    const double* v_ref, int32_t flags, double slack,
+                                    int32_t time_reps, int32_t max_levels, void* workspace,
+                                    size_t ws_bytes, vfmm_selection* out, void* stream) {
+  if (!x || !y || !gamma || !params || !feat_mean || !feat_std || !out || !workspace)
+    return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (n < 1 || n > 2147483647LL) return sfail(VFMM_ERR_INVALID_ARG, "n out of [1, 2^31-1]");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return sfail(VFMM_ERR_INVALID_ARG, "bad sigma");
+  if (!(tol > 0.0) || !(slack > 0.0) || !(slack <= 1.0))
+    return sfail(VFMM_ERR_INVALID_ARG, "tol > 0 and 0 < slack <= 1 required");
+  if (flags & ~(VFMM_SELECT_AUDIT | VFMM_SELECT_CUTOFF))
+    return sfail(VFMM_ERR_INVALID_ARG, "unknown flags 0x%x", unsigned(flags));
+  const bool audit = flags & VFMM_SELECT_AUDIT;
+  if (audit && (!targets || n_audit < 1 || n_audit > n))
+    return sfail(VFMM_ERR_INVALID_ARG, "audit needs 1 <= n_audit <= n targets");
+  if (!audit) n_audit = 1;
+  if ((u_ref == nullptr) != (v_ref == nullptr))
+    return sfail(VFMM_ERR_INVALID_ARG, "give both u_ref and v_ref or neither");
+  if (time_reps < 1 || time_reps > 100) return sfail(VFMM_ERR_INVALID_ARG, "time_reps out of [1, 100]");
+  if (max_levels <= 0) max_levels = default_max_levels(n);
+  if (max_levels > kMaxLevels) return sfail(VFMM_ERR_INVALID_ARG, "max_levels > %d", kMaxLevels);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return sfail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const AuditWs w = audit_layout(static_cast<char*>(workspace), n, n_audit, max_levels);
+  if (ws_bytes < w.total)
+    return sfail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  *out = vfmm_selection{};
+
+  // the network's choice
+  int32_t p = 0, L = 0, fb = 0;
+  double pred = 0.0;
+  vfmm_status_t s = vfmm_select_params(x, y, gamma, n, sigma, tol, params, feat_mean, feat_std,
+                                       margin, w.sel, w.sel_bytes, &p, &L, &pred, &fb, stream);
+  if (s) return s;
+  if (L > max_levels) L = max_levels;
+  out->network_p = p;
+  out->network_levels = L;
+  out->network_fallback = fb;
+  out->predicted_log10 = pred;
+  out->p = p;
+  out->levels = L;
+  out->precision = VFMM_FP32;
+  out->near_radius = 0.0;
+  out->used_fallback = fb;
+  out->audit_emax = NAN;
+  if (!audit) return VFMM_OK;
+
+  // the direct-sum reference on the audit targets (eq. 7)
+  if (!u_ref) {
+    if ((s = vfmm_direct_velocity(x, y, gamma, n, sigma, targets, n_audit, w.ur, w.vr, stream)))
+      return s;
+    u_ref = w.ur;
+    v_ref = w.vr;
+  }
+  Auditor a{x, y, gamma, n, sigma, targets, n_audit, u_ref, v_ref, w, time_reps, st};
+  hipError_t he = hipEventCreate(&a.e0);
+  if (he == hipSuccess) he = hipEventCreate(&a.e1);
+  if (he != hipSuccess) {
+    if (a.e0) (void)hipEventDestroy(a.e0);
+    return sfail(hip_status(he), "audit events: %s", hipGetErrorString(he));
+  }
+  struct Events {
+    Auditor& a;
+    ~Events() {
+      if (a.e0) (void)hipEventDestroy(a.e0);
+      if (a.e1) (void)hipEventDestroy(a.e1);
+    }
+  } release{a};
+  const double bar = slack * tol;
+  auto pass = [&](double e) { return e <= bar; };  // NaN or infinity fails
+
+  // FP32 at the network's (p, L); p raised by 2 (up to 20) while it fails
+  double e = 0.0, ms = 0.0;
+  if ((s = a.run(p, L, VFMM_FP32, 0.0, false, e, ms))) return s;
+  record(out, p, L, VFMM_FP32, 0.0, e, ms);
+  while (!pass(e) && p < kPMax) {
+    p = p + 2 < kPMax ? p + 2 : kPMax;
+    if ((s = a.run(p, L, VFMM_FP32, 0.0, false, e, ms))) return s;
+    record(out, p, L, VFMM_FP32, 0.0, e, ms);
+  }
+  out->p = p;
+  out->audit_emax = e;
+  // root side of the bounding square, for the level conditions below
+  double stats[12];
+  if ((s = vfmm_particle_stats(x, y, gamma, n, w.sel, w.sel_bytes, stats, stream))) return s;
+  const double S = root_side(stats);
+  if (!pass(e)) {
+    // FP32 cannot meet the tolerance here (its floor, rounding of positions
+    // and circulations amplified by cancellation, can exceed it): the
+    // conservative choice in FP64
+    const int Lc = conservative_levels(S, sigma, n, max_levels);
+    if ((s = a.run(kPMax, Lc, VFMM_FP64, 0.0, false, e, ms))) return s;
+    record(out, kPMax, Lc, VFMM_FP64, 0.0, e, ms);
+    out->p = kPMax;
+    out->levels = Lc;
+    out->precision = VFMM_FP64;
+    out->used_fallback = 1;
+    out->audit_emax = e;
+    return VFMM_OK;
+  }
+  if (!(flags & VFMM_SELECT_CUTOFF)) return VFMM_OK;
+
+  // Section 4.1's distance a as a parameter: the same p one or two levels
+  // deeper, with far pairs closer than a on the regularised kernel, where the
+  // clamp at VFMM_NEAR_RINGS_MAX leaf sides does not cut the automatic radius
+  // (6 sigma in FP32); radii: the automatic one and sigma sqrt(2 ln(1/tol)),
+  // at which one pair's kernel difference falls to the tolerance.  Passing
+  // candidates are timed against the paper's split at L; the fastest is kept.
+  int deeper[2], nd = 0;
+  for (int LL = L + 1; LL <= L + 2; ++LL)
+    if (LL <= max_levels && S / std::ldexp(1.0, LL) >= 6.0 * sigma / VFMM_NEAR_RINGS_MAX &&
+        (int64_t(1) << (2 * LL)) <= 4 * n)
+      deeper[nd++] = LL;
+  if (nd == 0) return VFMM_OK;
+  double e0 = 0.0, ms0 = 0.0;
+  if ((s = a.run(p, L, VFMM_FP32, 0.0, true, e0, ms0))) return s;
+  out->steps[out->n_steps - 1].ms = ms0;  // the accepted step, now timed
+  double best_ms = ms0, best_e = e, best_r = 0.0;
+  int best_L = L;
+  const double radii[2] = {VFMM_NEAR_RADIUS_AUTO, sigma * std::sqrt(2.0 * std::log(1.0 / tol))};
+  for (int k = 0; k < nd; ++k)
+    for (double rad : radii) {
+      double ec = 0.0, msc = 0.0;
+      if ((s = a.run(p, deeper[k], VFMM_FP32, rad, true, ec, msc))) return s;
+      record(out, p, deeper[k], VFMM_FP32, rad, ec, msc);
+      if (pass(ec) && msc < best_ms) {
+        best_ms = msc;
+        best_e = ec;
+        best_r = rad;
+        best_L = deeper[k];
+      }
+    }
+  out->levels = best_L;
+  out->near_radius = best_r;
+  out->audit_emax = best_e;
   return VFMM_OK;
 }
 

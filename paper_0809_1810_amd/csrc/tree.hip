@@ -535,6 +535,8 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.part32s = reinterpret_cast<Part32*>(ws + lay.part32s);
   t.me = ws + lay.me;
   t.le = ws + lay.le;
+  t.me32 = ws + lay.me32;
+  t.le32 = ws + lay.le32;
   t.ops = ws + lay.ops;
   t.check = reinterpret_cast<unsigned long long*>(ws + lay.check);
   hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, k0, i0, n,

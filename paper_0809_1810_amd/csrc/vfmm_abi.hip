@@ -152,6 +152,9 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.part32s = take(size_t(n) * sizeof(Part32));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
   L.le = take(size_t(nbox) * p_max * sizeof(double2));
+  const size_t nb32 = p_max > kShift64P ? size_t(nbox) * p_max * sizeof(float2) : 0;
+  L.me32 = take(nb32);
+  L.le32 = take(nb32);
   L.ops = take(ops_bytes(p_max));
   L.check = take(2 * sizeof(unsigned long long));
   L.total = off;
@@ -330,6 +333,10 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   const int prec = precision == VFMM_FP64 ? kFP64 : kFP32;
   const bool near = parts & VFMM_PART_NEAR;
   const bool far = L >= 2 && (parts & VFMM_PART_FAR);
+  // reduced precision at high order: the shifts (P2M, M2M, L2L) in float64,
+  // M2L still on the float32 / 16-bit matrix cores, L2P in float32
+  const bool shift64 = prec == kFP32 && p > kShift64P;
+  const int prec_up = shift64 ? kFP64 : prec;
   // the gather and the sweeps go to the side stream only when there is
   // near-field work to overlap
   hipStream_t sw = near && far ? t->side : st;
@@ -363,23 +370,24 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   mark.end(kPhTables, sw);
   mark.begin(kPhP2M, sw);
   if (far) {
-    e = launch_p2m(t->dev, L, p, prec, sw);
+    e = launch_p2m(t->dev, L, p, prec_up, sw);
     if (e != hipSuccess) return hip_fail(e, "P2M");
   }
   mark.end(kPhP2M, sw);
   mark.begin(kPhM2M, sw);
   if (far) {
-    e = launch_m2m(t->dev, L, p, prec, sw);
+    e = launch_m2m(t->dev, L, p, prec_up, sw);
     if (e != hipSuccess) return hip_fail(e, "M2M");
   }
   mark.end(kPhM2M, sw);
   mark.begin(kPhM2L, sw);
   if (far) {
     e = prec == kFP64 ? launch_downward(t->dev, L, p, prec, sw)
+        : shift64     ? launch_downward_shift64(t->dev, L, p, precision, sw)
                       : launch_downward_mfma(t->dev, L, p, precision, sw);
     if (e != hipSuccess) return hip_fail(e, "M2L/L2L");
     t->last_p = p;
-    t->last_prec = prec;
+    t->last_prec = prec_up;  // the float64 shift path keeps float64 ME / LE in t->dev.me, .le
   }
   mark.end(kPhM2L, sw);
   if (sw != st) {
@@ -409,7 +417,9 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   }
   // near field plus far field (order 0: none, e.g. the far part alone of a
   // tree without one, L < 2, which is zeros), in the caller's order
-  e = launch_l2p(t->dev, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
+  TreeDev tl = t->dev;
+  if (shift64) tl.le = t->dev.le32;  // the leaf LEs rounded to float32
+  e = launch_l2p(tl, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "L2P");
   mark.end(kPhL2P, st);
   return VFMM_OK;

@@ -31,6 +31,8 @@ namespace vfmm {
 inline vfmm_status_t hip_status(hipError_t e) {
   return e == hipErrorOutOfMemory ? VFMM_ERR_OUT_OF_MEMORY : VFMM_ERR_HIP;
 }
+// Message returned by vfmm_last_error() on the calling thread.
+void set_last_error(const char* msg);
 
 constexpr int kMaxP = 40;
 constexpr int kMaxLevels = 12;
@@ -46,6 +48,7 @@ constexpr int kScanPerBlock = kScanItems * kScanBlock;
 constexpr int kBBoxBlocks = 512;
 constexpr int kReduceBlocks = 512;
 constexpr int kM2LOffsets = 49;      // 7x7 table indexed by t = (ox, oy) in [-3,3]^2
+constexpr int kShift64P = 16;        // reduced precision: P2M, M2M, L2L in float64 above this p
 // Near-field schedule: the source chunks of every target tile are cut into
 // parts so that a launch has about p2p_parts(max_tiles) parts of similar size
 // (4 per target tile, at least 4096, at most 65536: measured on clustered 1M
@@ -118,7 +121,7 @@ struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, sched_near;
-  size_t part64, part32, part32s, me, le, ops, check, total;
+  size_t part64, part32, part32s, me, le, me32, le32, ops, check, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
 };
@@ -143,6 +146,8 @@ struct TreeDev {
   Part32* part32s;       // FP32 near-field sources in units of the Gaussian width (per evaluation)
   void* me;
   void* le;
+  void* me32;            // float32 copies for the float64-shift path (p > kShift64P)
+  void* le32;
   void* ops;
   unsigned long long* check;  // [2] counters of the opt-in finiteness check
   P2PSched sched;        // near-field schedule of the particles as targets
@@ -202,7 +207,17 @@ hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t s
 // FP64 M2L operands for the matrix cores (m2l_tile.hpp), from the operator
 // tables at ops; out holds m2l64_pack_bytes(p) bytes.
 hipError_t launch_pack_m2l_mfma64(const void* ops, int p, double* out, hipStream_t stream);
-hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
+// with_l2l = false: the M2L of every level only (each level's LE holds its
+// interaction-list sum), for a downward sweep whose L2L runs in float64.
+hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream,
+                                bool with_l2l = true);
+// Reduced-precision evaluation with float64 shifts (p > kShift64P): the
+// float64 multipoles of t.me (P2M and M2M in float64) rounded to float32 into
+// t.me32, M2L on the matrix cores into t.le32, the L2L chain in float64 into
+// t.le (each level: its M2L sum widened plus the shifted parent LE), and the
+// leaf level rounded back into t.le32 for the float32 L2P.
+hipError_t launch_downward_shift64(const TreeDev& t, int levels, int p, int prec,
+                                   hipStream_t stream);
 // radius: distance cut-off of the near field (0 = off, < 0 = the distance at
 // which the regularised and singular kernels agree in this precision).
 // The near-field work schedule of target set tg (launch_p2p_schedule), then

@@ -7,9 +7,9 @@ library's FP32 FMM over a grid of (p, L) on seeded synthetic particle sets,
 records log10 of the maximum error against the library's FP64 direct sum
 (normalised by the maximum velocity, Section 5.1), trains the selector
 network with the library's own forward / backward / Adam kernels, and chooses
-parameters with ``vfmm_select_params``, auditing every choice with the direct
-sum on sampled targets and falling back to the conservative choice when the
-audit fails.
+parameters with ``vfmm_select_and_audit``, which audits every choice with
+the direct sum on sampled targets and falls back to the conservative choice
+when the audit fails.
 
 Every computation runs in the HIP library; this file only drives it.
 
@@ -198,108 +198,48 @@ def conservative_choice(side, sigma, n):
 
 def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, audit=True,
                      slack=0.8, targets=None, reference=None, cutoff=True, time_reps=3):
-    """Selected (p, L), audited by the FP64 direct sum on sampled targets.
+    """Selected (p, L), audited by the FP64 direct sum on sampled targets
+    (``vfmm_select_and_audit``; this function only marshals arguments).
 
     The network's choice is evaluated in FP32 and accepted if its error on the
-    audit targets is <= slack * tol; otherwise p is raised by 2 at the same level
-    (up to 20) and audited again; if FP32 still misses, the conservative choice
-    is evaluated in FP64 (the FP32 floor -- rounding of positions and
-    circulations, amplified by mixed signs -- can exceed tol).
-
-    With ``cutoff``, an accepted FP32 choice (p, L) is compared with the same p
-    one or two levels deeper with the distance cut-off of the near field
-    (Section 4.1's distance a), for the levels whose leaf side is still
-    >= 6 sigma / NEAR_RINGS_MAX (so that the clamp NEAR_RINGS_MAX w_L does not
-    cut the radius), at two
-    radii: the automatic one (6 sigma in FP32) and sigma sqrt(2 ln(1/tol)),
-    where one pair's kernel difference falls to the tolerance.  Each such
-    candidate is audited, the passing ones are timed (median of
-    ``time_reps`` rebuild + evaluation runs, HIP events) and the fastest is
-    kept.
+    audit targets is <= slack * tol; otherwise p is raised by 2 at the same
+    level (up to 20) and audited again; if FP32 still misses, the conservative
+    choice is evaluated in FP64.  With ``cutoff``, an accepted FP32 choice is
+    compared with the same p one or two levels deeper under the distance
+    cut-off of the near field (Section 4.1's distance a) at two radii; the
+    fastest passing candidate is kept.
 
     ``targets`` (device int64) and ``reference`` ((u, v) of the direct sum
     there) may be supplied; otherwise n_audit targets are drawn with ``seed``.
-    Returns a dict with the choice (p, levels, radius: 0 or NEAR_RADIUS_AUTO,
-    precision), the audited error, the network's prediction and the audit
-    trail [p, L, mode, e_max, ms].
+    Returns a dict with the choice (p, levels, radius: 0, > 0 or
+    NEAR_RADIUS_AUTO, precision), the audited error, the network's prediction
+    and the audit trail [p, L, mode, e_max, ms].
     """
     torch = _torch()
     params, mean, std, margin = weights if weights is not None else load_weights()
-    p, L, pred, fb = V.select_params(x, y, g, sigma, tol, params, mean, std, margin)
-    out = {"p": p, "levels": L, "predicted_log10": pred, "fallback": fb, "audited": False,
-           "precision": "fp32", "radius": 0.0, "network_choice": [p, L]}
-    if not audit:
-        return out
     n = int(x.shape[0])
     if targets is None:
         rng = np.random.default_rng(seed)
-        targets = torch.from_numpy(np.sort(rng.choice(n, min(n, n_audit), replace=False)).astype(np.int64)).cuda()
-    ud, vd = reference if reference is not None else V.direct_velocity(x, y, g, sigma, targets=targets)
-
-    def run(pp, LL, prec, radius=0.0, timed=False):
-        t = V.Tree(x, y, LL, p_max=pp)
-        if radius:
-            t.set_near_radius(radius)
-        u, v = t.velocity(g, sigma, pp, prec)
-        e = V.error_metrics(u[targets].contiguous(), v[targets].contiguous(), ud, vd)[0]
-        ms = None
-        if timed:
-            times = []
-            for _ in range(time_reps):
-                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                t.rebuild(x, y)
-                t.velocity(g, sigma, pp, prec, out=(u, v))
-                e1.record()
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            ms = float(np.median(times))
-        t.close()
-        return e, ms
-
-    trail = []
-    e, _ = run(p, L, V.FP32)
-    trail.append([p, L, "fp32", e, None])
-    # a non-finite error (NaN or infinity) fails the audit
-    while not (e <= slack * tol) and p < 20:
-        p = min(20, p + 2)
-        e, _ = run(p, L, V.FP32)
-        trail.append([p, L, "fp32", e, None])
-    out.update(p=p, levels=L, audited=True, audit_emax=e, trail=trail)
-    if not (e <= slack * tol):
-        root = V.Tree(x, y, 0, p_max=1)
-        side = float(root.arrays()[0][2].item())
-        root.close()
-        pc, Lc = conservative_choice(side, sigma, n)
-        e, _ = run(pc, Lc, V.FP64)
-        trail.append([pc, Lc, "fp64", e, None])
-        out.update(p=pc, levels=Lc, fallback=True, precision="fp64", audit_emax=e)
-        return out
-    if not cutoff:
-        return out
-    root = V.Tree(x, y, 0, p_max=1)
-    side = float(root.arrays()[0][2].item())
-    root.close()
-    deeper = [LL for LL in (L + 1, L + 2)
-              if LL <= min(V.MAX_LEVELS, 10) and side / 2 ** LL >= 6.0 * sigma / V.NEAR_RINGS_MAX
-              and 4 ** LL <= 4 * n]
-    if not deeper:
-        return out
-    _, ms0 = run(p, L, V.FP32, timed=True)
-    trail[-1][4] = ms0
-    best = (ms0, L, 0.0, e)
-    # radii: the automatic one (no kernel difference left in FP32) and the
-    # distance at which one pair's kernel difference e^{-a^2 / 2 sigma^2}
-    # falls to the tolerance
-    radii = [V.NEAR_RADIUS_AUTO, sigma * math.sqrt(2.0 * math.log(1.0 / tol))]
-    for LL in deeper:
-        for rad in radii:
-            ec, msc = run(p, LL, V.FP32, radius=rad, timed=True)
-            trail.append([p, LL, "fp32+cutoff " + ("auto" if rad < 0 else f"{rad / sigma:.2f} sigma"),
-                          ec, msc])
-            if ec <= slack * tol and msc < best[0]:
-                best = (msc, LL, rad, ec)
-    out.update(levels=best[1], radius=best[2], audit_emax=best[3])
+        targets = torch.from_numpy(np.sort(rng.choice(n, min(n, n_audit), replace=False))
+                                   .astype(np.int64)).cuda()
+    r = V.select_and_audit(x, y, g, sigma, tol, params, mean, std, margin, targets,
+                           reference=reference, audit=audit, cutoff=cutoff, slack=slack,
+                           time_reps=time_reps)
+    out = {"p": r.p, "levels": r.levels, "predicted_log10": r.predicted_log10,
+           "fallback": bool(r.used_fallback), "audited": bool(audit),
+           "precision": "fp64" if r.precision == V.FP64 else "fp32",
+           "radius": r.near_radius, "network_choice": [r.network_p, r.network_levels]}
+    if audit:
+        trail = []
+        for k in range(r.n_steps):
+            st = r.steps[k]
+            mode = "fp64" if st.precision == V.FP64 else "fp32"
+            if st.near_radius != 0.0:
+                mode += " +cutoff " + ("auto" if st.near_radius < 0
+                                       else f"{st.near_radius / sigma:.2f} sigma")
+            trail.append([st.p, st.levels, mode.replace(" +", "+"), st.emax,
+                          st.ms if st.ms >= 0 else None])
+        out.update(audit_emax=r.audit_emax, trail=trail)
     return out
 
 

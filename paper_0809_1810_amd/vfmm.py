@@ -72,6 +72,8 @@ _SIGS = {
     "vfmm_metrics_scratch_bytes": (C.c_size_t, []),
     "vfmm_error_metrics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_error_metrics_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_int64, C.c_void_p, C.c_void_p]),
     "vfmm_tree_arrays": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_tree_expansions": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "vfmm_tree_destroy": (None, [C.c_void_p]),
@@ -104,6 +106,14 @@ _SIGS = {
                                         C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
     "vfmm_selector_features": (C.c_int32, [C.POINTER(C.c_double), C.c_int64, C.c_double, C.c_int32,
                                            C.c_int32, C.POINTER(C.c_float)]),
+    "vfmm_select_audit_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.c_int32,
+                                                      C.POINTER(C.c_size_t)]),
+    "vfmm_select_and_audit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.c_double, C.c_double, C.c_void_p,
+                                          C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_double,
+                                          C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "vfmm_select_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
                                        C.c_double, C.c_void_p, C.POINTER(C.c_float),
                                        C.POINTER(C.c_float), C.c_double, C.c_void_p, C.c_size_t,
@@ -124,6 +134,25 @@ class Instance(C.Structure):
                 ("levels", C.c_int32)]
 
 TUNE_P2P_TILE, TUNE_P2P_WAVES = 1, 2
+
+SELECT_AUDIT, SELECT_CUTOFF = 1, 2
+SELECT_TRAIL_MAX = 16
+
+
+class AuditStep(C.Structure):
+    """Mirror of ``vfmm_audit_step``."""
+    _fields_ = [("p", C.c_int32), ("levels", C.c_int32), ("precision", C.c_int32),
+                ("near_radius", C.c_double), ("emax", C.c_double), ("ms", C.c_double)]
+
+
+class Selection(C.Structure):
+    """Mirror of ``vfmm_selection``."""
+    _fields_ = [("p", C.c_int32), ("levels", C.c_int32), ("precision", C.c_int32),
+                ("near_radius", C.c_double), ("used_fallback", C.c_int32),
+                ("network_p", C.c_int32), ("network_levels", C.c_int32),
+                ("network_fallback", C.c_int32), ("predicted_log10", C.c_double),
+                ("audit_emax", C.c_double), ("n_steps", C.c_int32),
+                ("steps", AuditStep * SELECT_TRAIL_MAX)]
 
 N_PHASES = 8
 PHASES = ("gather", "tables", "p2m", "m2m", "m2l_l2l", "p2p_sched", "p2p", "l2p")
@@ -463,6 +492,20 @@ def error_metrics(u, v, u_ref, v_ref):
     return mx / den, math.sqrt(ss / n) / den, den
 
 
+def error_metrics_noalloc(u, v, u_ref, v_ref, out):
+    """vfmm_error_metrics_noalloc: raw (max |dW|, sum |dW|^2, max |W_ref|) into the
+    caller's device float64 tensor ``out`` (3 entries), asynchronously, with no
+    scratch argument (the library's own device array holds the partial sums)."""
+    for t, nme in ((u, "u"), (v, "v"), (u_ref, "u_ref"), (v_ref, "v_ref"), (out, "out")):
+        _dev_f64(t, nme)
+    if out.numel() < 3:
+        raise ValueError("out needs 3 entries")
+    _check(lib().vfmm_error_metrics_noalloc(u.data_ptr(), v.data_ptr(), u_ref.data_ptr(),
+                                            v_ref.data_ptr(), int(u.shape[0]), out.data_ptr(),
+                                            _stream()), "vfmm_error_metrics_noalloc")
+    return out
+
+
 # ----------------------------------------------------------------- selector network
 
 
@@ -558,6 +601,44 @@ def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0
                                     scratch.data_ptr(), scratch.numel(), C.byref(p), C.byref(L),
                                     C.byref(pred), C.byref(fb), _stream()), "vfmm_select_params")
     return int(p.value), int(L.value), float(pred.value), bool(fb.value)
+
+
+def select_and_audit(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin, targets,
+                     reference=None, audit=True, cutoff=True, slack=0.8, time_reps=3,
+                     max_levels=0):
+    """vfmm_select_and_audit: the network's (p, L), audited on ``targets`` (device
+    int64 particle indices) against ``reference`` ((u, v) of the FP64 direct sum
+    there, or None: computed by the call), escalated or replaced by the
+    conservative FP64 choice if it fails, and with ``cutoff`` compared with
+    deeper levels under the distance cut-off.  Returns the ``Selection`` struct."""
+    torch = _torch()
+    for t, nme in ((x, "x"), (y, "y"), (gamma, "gamma")):
+        _dev_f64(t, nme)
+    _dev_f32(params, "params")
+    n = int(x.shape[0])
+    if not isinstance(targets, torch.Tensor) or targets.dtype != torch.int64 or not targets.is_cuda:
+        raise TypeError("targets must be a CUDA int64 tensor")
+    nt = int(targets.shape[0])
+    ur = vr = None
+    if reference is not None:
+        ur, vr = (_dev_f64(a, "reference") for a in reference)
+    b = C.c_size_t(0)
+    _check(lib().vfmm_select_audit_workspace_bytes(n, max(1, nt), int(max_levels), C.byref(b)),
+           "vfmm_select_audit_workspace_bytes")
+    ws = torch.empty(int(b.value), dtype=torch.uint8, device=x.device)
+    fm = (C.c_float * N_FEATURES)(*[float(v) for v in feat_mean])
+    fs = (C.c_float * N_FEATURES)(*[float(v) for v in feat_std])
+    flags = (SELECT_AUDIT if audit else 0) | (SELECT_CUTOFF if audit and cutoff else 0)
+    out = Selection()
+    _check(lib().vfmm_select_and_audit(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n,
+                                       float(sigma), float(tol), params.data_ptr(), fm, fs,
+                                       float(margin), targets.data_ptr(), nt,
+                                       ur.data_ptr() if ur is not None else None,
+                                       vr.data_ptr() if vr is not None else None, flags,
+                                       float(slack), int(time_reps), int(max_levels),
+                                       ws.data_ptr(), ws.numel(), C.byref(out), _stream()),
+           "vfmm_select_and_audit")
+    return out
 
 
 # ----------------------------------------------------------------- batched instances

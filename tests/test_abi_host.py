@@ -199,3 +199,64 @@ def test_one_call_entry_points_reject_before_device_work():
     assert lib.vfmm_fmm_velocity_batched(None, 1, fake, 1 << 20, None) == -1
     arr = (B.Instance * 1)()
     assert lib.vfmm_fmm_velocity_batched(arr, 0, fake, 1 << 20, None) == -1
+
+
+def test_selection_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirrors of vfmm_audit_step / vfmm_selection have the C layout
+    (a C compiler prints sizeof and offsetof of every field)."""
+    import shutil
+    cc = shutil.which("cc") or shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in B.Selection._fields_]
+    sfields = [f for f, _ in B.AuditStep._fields_]
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{B.HEADER_PATH}"',
+             'int main(void) {',
+             '  printf("%zu %zu\\n", sizeof(vfmm_selection), sizeof(vfmm_audit_step));']
+    lines += [f'  printf("%zu\\n", offsetof(vfmm_selection, {f}));' for f in fields]
+    lines += [f'  printf("%zu\\n", offsetof(vfmm_audit_step, {f}));' for f in sfields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([cc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == C.sizeof(B.Selection) and vals[1] == C.sizeof(B.AuditStep)
+    got = [getattr(B.Selection, f).offset for f in fields] + [getattr(B.AuditStep, f).offset for f in sfields]
+    assert vals[2:] == got
+
+
+def test_select_and_audit_rejects_before_device_work():
+    l = _lib()
+    b = C.c_size_t(0)
+    assert l.vfmm_select_audit_workspace_bytes(1 << 20, 4096, 0, C.byref(b)) == 0 and b.value > 0
+    b7 = C.c_size_t(0)
+    assert l.vfmm_select_audit_workspace_bytes(1 << 20, 4096, 7, C.byref(b7)) == 0
+    assert 0 < b7.value < b.value  # sized for the deepest tree allowed
+    assert l.vfmm_select_audit_workspace_bytes(0, 1, 0, C.byref(b)) == B.ERR_INVALID_ARG
+    assert l.vfmm_select_audit_workspace_bytes(100, 101, 0, C.byref(b)) == B.ERR_INVALID_ARG
+    assert l.vfmm_select_audit_workspace_bytes(100, 10, 13, C.byref(b)) == B.ERR_INVALID_ARG
+    f = C.c_void_p(256)
+    fm = (C.c_float * 10)(*([0.0] * 10)); fs = (C.c_float * 10)(*([1.0] * 10))
+    out = B.Selection()
+
+    def call(**kw):
+        a = dict(x=f, n=1000, sigma=0.01, tol=1e-6, targets=f, nt=100, flags=3, slack=0.8,
+                 reps=3, ws=f, wsb=1 << 40, out=C.byref(out))
+        a.update(kw)
+        return l.vfmm_select_and_audit(a["x"], f, f, a["n"], a["sigma"], a["tol"], f, fm, fs, 0.3,
+                                       a["targets"], a["nt"], None, None, a["flags"], a["slack"],
+                                       a["reps"], 0, a["ws"], a["wsb"], a["out"], None)
+    assert call(x=None) == B.ERR_INVALID_ARG
+    assert call(out=None) == B.ERR_INVALID_ARG
+    assert call(n=0) == B.ERR_INVALID_ARG
+    assert call(sigma=-1.0) == B.ERR_INVALID_ARG
+    assert call(tol=0.0) == B.ERR_INVALID_ARG
+    assert call(slack=1.5) == B.ERR_INVALID_ARG
+    assert call(flags=8) == B.ERR_INVALID_ARG
+    assert call(targets=None) == B.ERR_INVALID_ARG
+    assert call(nt=1001) == B.ERR_INVALID_ARG
+    assert call(reps=0) == B.ERR_INVALID_ARG
+    assert call(ws=C.c_void_p(257)) == B.ERR_WORKSPACE
+    assert call(wsb=16) == B.ERR_WORKSPACE

@@ -145,3 +145,39 @@ def test_16bit_m2l_against_oracle(vf, name, levels, p, ntg):
     assert errs["fp32"][0] < 1e-6
     assert errs["fp16"][0] <= 4e-4 * far_share and errs["fp16"][1] <= 1.4e-4 * far_share
     assert errs["bf16"][0] <= 4e-3 * far_share and errs["bf16"][1] <= 1.4e-3 * far_share
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+@pytest.mark.parametrize("p,levels", [(17, 4), (24, 5), (40, 3)])
+def test_high_order_shifts_in_fp64(vf, prec_name, p, levels):
+    """For p > 16 the reduced-precision evaluation runs P2M, M2M and L2L in
+    float64 (M2L stays on the float32 / 16-bit matrix cores): its multipoles
+    are those of the float64 evaluation bit for bit, its locals differ only by
+    the M2L rounding, and the velocity matches the oracle FMM.  At p <= 16 the
+    multipoles are float32."""
+    P = W.clusters(30000, seed=33, sigma=0.004)
+    prec = vf.PRECISIONS[prec_name]
+    print_case("shift64", p=p, levels=levels, precision=prec_name)
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=p)
+    g = dev(P.gamma)
+    t.velocity(g, P.sigma, p, vf.FP64)
+    me64 = [host(t.expansions(0, l, p)) for l in range(2, levels + 1)]
+    le64 = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+    u, v = (host(a) for a in t.velocity(g, P.sigma, p, prec))
+    me = [host(t.expansions(0, l, p)) for l in range(2, levels + 1)]
+    le = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+    for a, b in zip(me, me64):
+        assert np.array_equal(a, b)
+    bar = 2e-6 if prec_name == "fp32" else 2e-2
+    for a, b in zip(le, le64):
+        assert np.max(np.abs(a - b)) <= bar * np.max(np.abs(b))
+    if prec_name == "fp32":
+        tg = W.sample_targets(P.n, 300, seed=p)
+        r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, levels, targets=tg)
+        assert rel_err(u[tg], v[tg], r.u, r.v)[0] < 1e-6
+        # at p = 16 the multipoles are float32: not the float64 ones
+        t.velocity(g, P.sigma, 16, vf.FP64)
+        m16 = host(t.expansions(0, levels, 16))
+        t.velocity(g, P.sigma, 16, vf.FP32)
+        assert not np.array_equal(host(t.expansions(0, levels, 16)), m16)
+    t.close()
