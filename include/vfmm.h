@@ -189,6 +189,33 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t tree, const double* gamma, double
                                    const double* yt, int64_t n_targets, void* workspace,
                                    size_t ws_bytes, double* u, double* v, void* stream);
 
+/* FMM velocity on an adaptive quadtree (the paper uses uniform trees, Section
+ * 3.3; this is the reading for leaves at different levels): a box is split
+ * while it holds more than leaf_capacity particles, down to the tree's leaf
+ * level L, so each particle's leaf lies at a level l <= L chosen by the local
+ * density.  A particle's near field sums the regularised kernel (eq. 6) over
+ * the particles of the 3 x 3 boxes of level l around its leaf (the local list
+ * at the leaf's own level, Section 3.3.1); its far field is the L2P of its
+ * leaf's local expansion, formed as in the uniform method (M2L over the
+ * interaction lists of the leaf and its ancestors, L2L down the ancestors;
+ * the multipoles are those of the tree's leaf-level boxes and their M2M
+ * parents, whatever the adaptive tree does inside them).  With the tree's
+ * near radius (vfmm_tree_set_near_radius) the cut-off uses the rings around
+ * each adaptive leaf, the radius clamped to VFMM_NEAR_RINGS_MAX sides of that
+ * leaf.  leaf_capacity = 0 puts every leaf at level L: the result is then
+ * that of vfmm_fmm_velocity_parts, bit for bit.
+ *   gamma, sigma, p, precision, parts: as in vfmm_fmm_velocity_parts.
+ *   leaf_capacity: >= 0, the largest particle count of a leaf above level L.
+ *   workspace (device): at least vfmm_adaptive_workspace_bytes(n, levels)
+ *             bytes, 256-byte aligned, caller-owned (the particles sorted into
+ *             the adaptive leaves, box counts, tiles, the near-field schedule).
+ * Errors: VFMM_ERR_INVALID_ARG, VFMM_ERR_WORKSPACE, VFMM_ERR_HIP. */
+vfmm_status_t vfmm_adaptive_workspace_bytes(int64_t n, int32_t levels, size_t* bytes);
+vfmm_status_t vfmm_fmm_velocity_adaptive(vfmm_tree_t tree, const double* gamma, double sigma,
+                                         int32_t p, int32_t precision, int32_t parts,
+                                         int64_t leaf_capacity, void* workspace, size_t ws_bytes,
+                                         double* u, double* v, void* stream);
+
 /* Float64 direct sum of eq. 7 / eq. 9 over all n particles, evaluated at the
  * particles listed in `targets` (device int64, n_targets entries, each in
  * [0, n)) or at all particles when targets is NULL (then n_targets must be n).

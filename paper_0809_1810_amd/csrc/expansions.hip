@@ -324,10 +324,9 @@ hipError_t launch_downward_shift64(const TreeDev& t, int levels, int p, int prec
                        m2l + level_offset(l) * p, l > 2 ? le + level_offset(l - 1) * p : nullptr,
                        le + level_offset(l) * p, l, p, B);
   }
-  const int64_t leaf = (int64_t(1) << (2 * levels)) * p;
-  hipLaunchKernelGGL(k_narrow, dim3(unsigned((leaf + 255) / 256)), dim3(256), 0, st,
-                     le + level_offset(levels) * p, leaf,
-                     static_cast<float2*>(t.le32) + level_offset(levels) * p);
+  // every level rounded back (the leaves of an adaptive tree lie at any level)
+  hipLaunchKernelGGL(k_narrow, dim3(unsigned((count + 255) / 256)), dim3(256), 0, st, le, count,
+                     static_cast<float2*>(t.le32));
   return hipGetLastError();
 }
 

@@ -126,14 +126,35 @@ __device__ __forceinline__ NearRings near_rings(double cut2, double w) {
   return NearRings{nseg, cut2 < cap ? cut2 : cap};
 }
 
-__device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int nseg,
+// The chunk sequence of a target leaf of level L - k (adaptive tree; k = 0 for
+// a leaf-level box) in leaf-level terms: segment sg is row sg & (2^k - 1) of the
+// 2^k leaf-level rows of the level's segment sg >> k, and spans the 2^k
+// leaf-level boxes of every box of that segment.  (bx, by) are the target
+// leaf's coordinates at its level, ml = 2^(L - k) the boxes per side there.
+__device__ __forceinline__ bool fine_segment(int sg, int k, int bx, int by, int ml, int& sy,
+                                             int& lo, int& hi) {
+  int syl, lol, hil;
+  if (!segment(sg >> k, bx, by, ml, syl, lol, hil)) return false;
+  sy = (syl << k) + (sg & ((1 << k) - 1));
+  lo = lol << k;
+  hi = ((hil + 1) << k) - 1;
+  return true;
+}
+
+// Level shift k of a target tile's leaf (0 without an adaptive tree).
+__device__ __forceinline__ int tile_shift(const uint8_t* __restrict__ leaf_shift, int leaf) {
+  return leaf_shift ? int(leaf_shift[leaf]) : 0;
+}
+
+__device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int k, int nseg,
                                                     const uint32_t* __restrict__ tile_off) {
   const int m = 1 << levels;
-  const int bx = leaf & (m - 1), by = leaf >> levels;
+  const int bx = (leaf & (m - 1)) >> k, by = (leaf >> levels) >> k;
   uint32_t c = 0;
-  for (int s = 0; s < nseg; ++s) {
+  for (int s = 0; s < (nseg << k); ++s) {
     int sy, lo, hi;
-    if (segment(s, bx, by, m, sy, lo, hi)) c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
+    if (fine_segment(s, k, bx, by, m >> k, sy, lo, hi))
+      c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
   }
   return c;
 }
@@ -145,13 +166,18 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
                                                      const uint32_t* __restrict__ tile_off,
                                                      const double* __restrict__ root, int levels,
                                                      double cut2, int64_t max_tiles,
+                                                     const uint8_t* __restrict__ leaf_shift,
                                                      uint32_t* __restrict__ cnt,
                                                      uint64_t* __restrict__ bsum) {
   __shared__ uint64_t red[256];
-  const int nseg = near_rings(cut2, root[3]).nseg;
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
   uint32_t c = 0;
-  if (t < *tntiles) c = sequence_chunks(ttiles[t].leaf, levels, nseg, tile_off);
+  if (t < *tntiles) {
+    const int leaf = ttiles[t].leaf;
+    const int k = tile_shift(leaf_shift, leaf);
+    const int nseg = near_rings(cut2, root[3] * double(1 << k)).nseg;
+    c = sequence_chunks(leaf, levels, k, nseg, tile_off);
+  }
   if (t <= max_tiles) cnt[t] = c;
   red[threadIdx.x] = c;
   __syncthreads();
@@ -276,7 +302,8 @@ __global__ void __launch_bounds__(512) k_p2p(
     const Tile* __restrict__ ttiles, const float4* __restrict__ ttile_box,
     const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
     const double* __restrict__ root, int levels, PairK<R> pk, double sd, float far2, float ser2,
-    double cut2, double2* __restrict__ nearv) {
+    double cut2, const uint8_t* __restrict__ leaf_shift, const Part64* __restrict__ fine64,
+    double2* __restrict__ nearv) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
   // FP32: sources and targets in units of the Gaussian width (factor sd);
   // FP64: plain units (sd = 1)
@@ -287,14 +314,6 @@ __global__ void __launch_bounds__(512) k_p2p(
   const int m = 1 << levels;
   const double w = root[3];
   const int np_total = int(*nparts);
-  // segments of the chunk sequence and the cut-off radius^2, at most (D w)^2
-  // with D the number of rings searched
-  const NearRings nr = near_rings(cut2, w);
-  const int nseg = nr.nseg;
-  const double rc2d = nr.rc2;
-  const float rc2f = float(rc2d);
-  const R rc2 = R(rc2d * sd * sd);
-  const float rc2s = float(rc2d * sd * sd);
   const float sdf = float(sd);
   const double wsd = w * sd;
   for (int pi = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
@@ -313,7 +332,22 @@ __global__ void __launch_bounds__(512) k_p2p(
     const bool active = tl < t_count;
     const int32_t i = t_start + (active ? tl : 0);
     R tx0, ty0;
-    if constexpr (sizeof(R) == 4) {
+    // adaptive tree: each target's own leaf-level box (fx, fy) and its
+    // coordinates there, as the tree holds them for the particle as a source
+    int fx = 0, fy = 0;
+    if (fine64) {
+      const Part64 q = fine64[i];
+      const int f = int(q.g);
+      fx = f & (m - 1);
+      fy = f >> levels;
+      if constexpr (sizeof(R) == 4) {
+        tx0 = float(q.x * sd);
+        ty0 = float(q.y * sd);
+      } else {
+        tx0 = q.x;
+        ty0 = q.y;
+      }
+    } else if constexpr (sizeof(R) == 4) {
       // the same rounding as the gather kernel's, so that a target at a
       // source's position (the self pair) has an offset of exactly zero
       const Part64 q = tpart64[i];
@@ -324,7 +358,18 @@ __global__ void __launch_bounds__(512) k_p2p(
       tx0 = q.x;
       ty0 = q.y;
     }
-    const int bx = t_leaf & (m - 1), by = t_leaf >> levels;
+    // the target leaf: level L - k, coordinates (bx, by) there
+    const int k = __builtin_amdgcn_readfirstlane(tile_shift(leaf_shift, t_leaf));
+    const int bx = (t_leaf & (m - 1)) >> k, by = (t_leaf >> levels) >> k;
+    const double half = 0.5 * double(1 << k);  // leaf centre, in leaf-level sides
+    // segments of the chunk sequence and the cut-off radius^2, at most (D w_l)^2
+    // with D the number of rings searched around the leaf of side w_l
+    const NearRings nr = near_rings(cut2, w * double(1 << k));
+    const int nseg = nr.nseg << k;
+    const double rc2d = nr.rc2;
+    const float rc2f = float(rc2d);
+    const R rc2 = R(rc2d * sd * sd);
+    const float rc2s = float(rc2d * sd * sd);
 
     double nu = 0.0, nv = 0.0;
     {
@@ -335,9 +380,13 @@ __global__ void __launch_bounds__(512) k_p2p(
       uint32_t vb = 0;  // sequence index of the current segment's first chunk
       for (int sg = 0; sg < nseg && vb < v1; ++sg) {
         int sy, lo, hi;
-        if (!segment(sg, bx, by, m, sy, lo, hi)) continue;
-        const bool ring = sg >= kSegNear;
-        const int oy = sy - by;
+        if (!fine_segment(sg, k, bx, by, m >> k, sy, lo, hi)) continue;
+        const bool ring = (sg >> k) >= kSegNear;
+        // source row centre minus target leaf centre, in leaf-level sides
+        // (sy - by exactly when k = 0); the targets themselves take the offset
+        // from their own leaf-level box (equal when k = 0)
+        const double oy = (double(sy) + 0.5) - (double(by << k) + half);
+        const double oyt = fine64 ? double(sy - fy) : oy;
         const uint32_t ra = tile_off[sy * m + lo], rb = tile_off[sy * m + hi + 1];
         const uint32_t len = rb - ra;
         const uint32_t cl = v0 > vb ? v0 - vb : 0u;
@@ -345,17 +394,18 @@ __global__ void __launch_bounds__(512) k_p2p(
         vb += len;
         if (cl >= ch) continue;
         const uint32_t cb = ra + cl, ce = ra + ch;
-        const R ty = ty0 - R(double(oy) * wsd);
-        const float by0 = tb.z - float(double(oy) * w), by1 = tb.w - float(double(oy) * w);
+        const R ty = ty0 - R(oyt * wsd);
+        const float by0 = tb.z - float(oy * w), by1 = tb.w - float(oy * w);
         for (int sx = lo; sx <= hi; ++sx) {
           const int sl = sy * m + sx;
           const uint32_t la = tile_off[sl], lb = tile_off[sl + 1];
           const uint32_t qa = la > cb ? la : cb, qb = lb < ce ? lb : ce;
           if (qa >= qb) continue;
-          const int ox = sx - bx;
+          const double ox = (double(sx) + 0.5) - (double(bx << k) + half);
+          const double oxt = fine64 ? double(sx - fx) : ox;
           // target relative to the source leaf centre
-          const R tx = tx0 - R(double(ox) * wsd);
-          const float bx0 = tb.x - float(double(ox) * w), bx1 = tb.y - float(double(ox) * w);
+          const R tx = tx0 - R(oxt * wsd);
+          const float bx0 = tb.x - float(ox * w), bx1 = tb.y - float(ox * w);
           const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
           for (uint32_t ci = qa; ci < qb; ++ci) {
             const int32_t j0 = js + int32_t(ci - la) * T;
@@ -477,7 +527,8 @@ template <typename R, int PMAX>
 __device__ __forceinline__ void l2p_tile(
     int wid, int lane, const typename Types<R>::Part* __restrict__ tpart,
     const Tile* __restrict__ ttiles, const int32_t* __restrict__ tperm,
-    const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
+    const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::C* __restrict__ le_all, const uint8_t* __restrict__ leaf_shift,
     int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
     const double2* __restrict__ partial, const double2* __restrict__ nearv,
     double* __restrict__ u, double* __restrict__ v) {
@@ -485,9 +536,14 @@ __device__ __forceinline__ void l2p_tile(
   if (lane >= tile.count) return;
   const int32_t i = tile.start + lane;
   double fu = 0.0, fv = 0.0;
-  if (p > 0) {
+  // the target leaf's level l = L - k; levels 0 and 1 have no far field
+  const int k = tile_shift(leaf_shift, tile.leaf);
+  if (p > 0 && levels - k >= 2) {
+    const int l = levels - k, m = 1 << levels;
+    const int64_t box = int64_t((tile.leaf >> levels) >> k) * (1 << l) + ((tile.leaf & (m - 1)) >> k);
     const auto tp = tpart[i];  // leaf-local, plain units
-    l2p<R, PMAX>(le_leaf + int64_t(tile.leaf) * p, tp.x, tp.y, root[3], p, fu, fv);
+    l2p<R, PMAX>(le_all + (level_offset(l) + box) * p, tp.x, tp.y, root[3] * double(1 << k), p,
+                 fu, fv);
   }
   const int32_t o = tperm[i];
   if (!near) {
@@ -522,7 +578,8 @@ template <typename R, int PMAX>
 __global__ void __launch_bounds__(256) k_l2p(
     const typename Types<R>::Part* __restrict__ tpart, const Tile* __restrict__ ttiles,
     const int32_t* __restrict__ tntiles, const int32_t* __restrict__ tperm,
-    const double* __restrict__ root, int p, const typename Types<R>::C* __restrict__ le_leaf,
+    const double* __restrict__ root, int levels, int p,
+    const typename Types<R>::C* __restrict__ le_all, const uint8_t* __restrict__ leaf_shift,
     int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
     const double2* __restrict__ partial, const double2* __restrict__ nearv,
     double* __restrict__ u, double* __restrict__ v) {
@@ -530,8 +587,8 @@ __global__ void __launch_bounds__(256) k_l2p(
   const int lane = threadIdx.x & 63;
   for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
        wid += 4 * gridDim.x)
-    l2p_tile<R, PMAX>(wid, lane, tpart, ttiles, tperm, root, p, le_leaf, near, p_off, s_off,
-                      partial, nearv, u, v);
+    l2p_tile<R, PMAX>(wid, lane, tpart, ttiles, tperm, root, levels, p, le_all, leaf_shift, near,
+                      p_off, s_off, partial, nearv, u, v);
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -542,7 +599,7 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, do
   const int64_t mt = tg.max_tiles;
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, t.root, levels, cut2, mt, s.cnt, s.bsum);
+                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, s.cnt, s.bsum);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,
@@ -579,7 +636,7 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   hipLaunchKernelGGL((k_p2p<R, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st, part,
                      t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles, tg.tile_box,
                      s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
-                     far2, ser2, cut2, s.near);
+                     far2, ser2, cut2, tg.leaf_shift, tg.fine64, s.near);
 }
 
 template <typename R>
@@ -598,11 +655,10 @@ void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int
   using Part = typename Types<R>::Part;
   const auto* tpart = reinterpret_cast<const Part*>(
       sizeof(R) == 8 ? static_cast<const void*>(tg.part64) : static_cast<const void*>(tg.part32));
-  const C* le = reinterpret_cast<const C*>(t.le) + (levels >= 2 ? level_offset(levels) * p : 0);
+  const C* le = reinterpret_cast<const C*>(t.le);  // levels 2 .. L
   hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(tile_loop_blocks(tg.max_tiles)), dim3(256), 0, st,
-                     tpart,
-                     tg.tiles, tg.ntiles, tg.perm, t.root, p, le, near, tg.sched.p_off,
-                     tg.sched.s_off, tg.sched.partial, tg.sched.near, u, v);
+                     tpart, tg.tiles, tg.ntiles, tg.perm, t.root, levels, p, le, tg.leaf_shift,
+                     near, tg.sched.p_off, tg.sched.s_off, tg.sched.partial, tg.sched.near, u, v);
 }
 
 template <typename R>

@@ -484,6 +484,107 @@ inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------------ adaptive tree
+// Particles per box at level l from the counts of level l + 1 (the leaf level's
+// come from the leaf ranges).
+__global__ void __launch_bounds__(256) k_fine_counts(const int32_t* __restrict__ leaf_start,
+                                                     int64_t nleaves, uint32_t* __restrict__ cnt) {
+  const int64_t f = blockIdx.x * 256LL + threadIdx.x;
+  if (f < nleaves) cnt[f] = uint32_t(leaf_start[f + 1] - leaf_start[f]);
+}
+
+__global__ void __launch_bounds__(256) k_coarse_counts(const uint32_t* __restrict__ child, int lev,
+                                                       uint32_t* __restrict__ cnt) {
+  const int64_t b = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t nb = int64_t(1) << (2 * lev);
+  if (b >= nb) return;
+  const int m = 1 << lev, mc = 2 * m;
+  const int bx = int(b & (m - 1)), by = int(b >> lev);
+  const int64_t c0 = int64_t(2 * by) * mc + 2 * bx;
+  cnt[b] = child[c0] + child[c0 + 1] + child[c0 + mc] + child[c0 + mc + 1];
+}
+
+// Level of the adaptive leaf holding each leaf-level box f, as the shift
+// k = L - level: the box at level l above f is split while it holds more
+// than s particles and l < L.  counts holds the levels 0 .. L one after the
+// other (level l at offset (4^l - 1) / 3).
+__global__ void __launch_bounds__(256) k_leaf_shift(const uint32_t* __restrict__ counts, int levels,
+                                                    int64_t s, uint8_t* __restrict__ shift) {
+  const int64_t f = blockIdx.x * 256LL + threadIdx.x;
+  const int64_t nl = int64_t(1) << (2 * levels);
+  if (f >= nl) return;
+  const int fx = int(f & ((1 << levels) - 1)), fy = int(f >> levels);
+  int l = 0;
+  while (l < levels) {
+    const int d = levels - l;
+    const int64_t off = ((int64_t(1) << (2 * l)) - 1) / 3;
+    const int64_t b = int64_t(fy >> d) * (1 << l) + (fx >> d);
+    if (int64_t(counts[off + b]) <= s) break;
+    ++l;
+  }
+  shift[f] = uint8_t(levels - l);
+}
+
+// Sort key of a particle (tree order) as a target of the adaptive tree: the
+// leaf-level box at the lower-left corner of its adaptive leaf.
+__global__ void __launch_bounds__(256) k_adaptive_keys(const uint32_t* __restrict__ tkeys, int64_t n,
+                                                       int levels, const uint8_t* __restrict__ shift,
+                                                       uint32_t* __restrict__ keys,
+                                                       int32_t* __restrict__ idx) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t f = tkeys[i] >> (2 * kSubLevels);
+  const int k = shift[f];
+  const uint32_t m = 1u << levels;
+  const uint32_t fx = (f & (m - 1u)) >> k << k, fy = (f >> levels) >> k << k;
+  keys[i] = fy * m + fx;
+  idx[i] = int32_t(i);
+}
+
+__global__ void __launch_bounds__(256) k_shift_keys(uint32_t* __restrict__ keys, int64_t n) {
+  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < n) keys[i] <<= 2 * kSubLevels;
+}
+
+// Target records of the adaptive set: coordinates relative to the centre of the
+// adaptive leaf (the tree's leaf-local coordinates plus the offset of the two
+// centres, an exact multiple of half the leaf-level side), for L2P and the tile
+// boxes; the tree's own leaf-local record with the leaf-level box in place of
+// the circulation (fine64), from which the near field takes its offsets to the
+// sources, so that a particle meets itself at offset exactly zero; caller index.
+__global__ void __launch_bounds__(256) k_adaptive_coords(const uint32_t* __restrict__ tkeys,
+                                                         const int32_t* __restrict__ idx,
+                                                         const int32_t* __restrict__ tperm,
+                                                         const Part64* __restrict__ tp64, int64_t n,
+                                                         const double* __restrict__ root, int levels,
+                                                         const uint8_t* __restrict__ shift,
+                                                         Part64* __restrict__ p64,
+                                                         Part32* __restrict__ p32,
+                                                         Part64* __restrict__ fine64,
+                                                         int32_t* __restrict__ perm) {
+#pragma clang fp contract(off)
+  const int64_t j = blockIdx.x * 256LL + threadIdx.x;
+  if (j >= n) return;
+  const int32_t i = idx[j];
+  const uint32_t f = tkeys[i] >> (2 * kSubLevels);
+  const int k = shift[f];
+  const int fx = int(f & ((1u << levels) - 1u)), fy = int(f >> levels);
+  const double w = root[3];
+  // (c_f - c_A) / w_L = (fx + 1/2) - (bx + 1/2) 2^k, bx = fx >> k: exact
+  const double ox = (double(fx) + 0.5) - (double(fx >> k) + 0.5) * double(1 << k);
+  const double oy = (double(fy) + 0.5) - (double(fy >> k) + 0.5) * double(1 << k);
+  const Part64 q = tp64[i];
+  const double lx = q.x + ox * w, ly = q.y + oy * w;
+  p64[j] = Part64{lx, ly, 0.0, 0.0};
+  p32[j] = Part32{float(lx), float(ly), 0.0f, 0.0f};
+  fine64[j] = Part64{q.x, q.y, double(f), 0.0};
+  perm[j] = tperm[i];
+}
+
+}  // namespace
+
 hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int levels,
                              const double* domain, const Layout& lay, char* ws, int tile,
                              TreeDev& t, hipStream_t st) {
@@ -640,6 +741,64 @@ hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n,
   const double scale = sigma > 0.0 ? near_scale(sigma) : 0.0;
   hipLaunchKernelGGL(k_gather_gamma, dim3(nblocks(n, 256)), dim3(256), 0, st, gamma, t.perm, n,
                      t.part64, t.part32, t.part32s, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_adaptive(const TreeDev& t, int levels, int64_t s, const AdaptiveLayout& lay,
+                                 char* ws, TargetsDev& out, hipStream_t st) {
+  const TargetLayout& tl = lay.targets;
+  const int64_t n = tl.nt, nl = tl.nleaves;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(ws + lay.counts);
+  uint8_t* shift = reinterpret_cast<uint8_t*>(ws + lay.shift);
+  auto level_counts = [&](int l) { return cnt + ((int64_t(1) << (2 * l)) - 1) / 3; };
+  hipLaunchKernelGGL(k_fine_counts, dim3(nblocks(nl, 256)), dim3(256), 0, st, t.leaf_start, nl,
+                     level_counts(levels));
+  for (int l = levels - 1; l >= 0; --l)
+    hipLaunchKernelGGL(k_coarse_counts, dim3(nblocks(int64_t(1) << (2 * l), 256)), dim3(256), 0,
+                       st, level_counts(l + 1), l, level_counts(l));
+  hipLaunchKernelGGL(k_leaf_shift, dim3(nblocks(nl, 256)), dim3(256), 0, st, cnt, levels, s, shift);
+  uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + tl.keys0);
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(ws + tl.keys1);
+  int32_t* i0 = reinterpret_cast<int32_t*>(ws + tl.idx0);
+  int32_t* i1 = reinterpret_cast<int32_t*>(ws + tl.idx1);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + tl.counts);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(ws + tl.scan_tmp);
+  int32_t* lstart = reinterpret_cast<int32_t*>(ws + tl.leaf_start);
+  uint32_t* toff = reinterpret_cast<uint32_t*>(ws + tl.tile_off);
+  Tile* tiles = reinterpret_cast<Tile*>(ws + tl.tiles);
+  int32_t* ntiles = reinterpret_cast<int32_t*>(ws + tl.ntiles);
+  float4* tbox = reinterpret_cast<float4*>(ws + tl.tile_box);
+  Part64* p64 = reinterpret_cast<Part64*>(ws + tl.part64);
+  Part32* p32 = reinterpret_cast<Part32*>(ws + tl.part32);
+  int32_t* perm = reinterpret_cast<int32_t*>(ws + lay.perm);
+  Part64* fine64 = reinterpret_cast<Part64*>(ws + lay.fine64);
+  hipLaunchKernelGGL(k_adaptive_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, t.keys, n, levels,
+                     shift, k0, i0);
+  // stable sort on the leaf bits: the tree's order is kept inside each
+  // adaptive leaf; then the keys take the usual form (leaf above 2 kSubLevels
+  // zero sub-cell bits)
+  hipError_t e = radix_sort_pairs(k0, k1, i0, i1, n, 2 * levels, counts, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_shift_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, n);
+  hipLaunchKernelGGL(k_leaf_start, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, k0, n, nl, lstart);
+  hipLaunchKernelGGL(k_adaptive_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, t.keys, i0,
+                     t.perm, t.part64, n, t.root, levels, shift, p64, p32, fine64, perm);
+  hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
+                     t.tile, toff);
+  e = scan_exclusive(toff, nl + 1, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
+                     t.tile, tiles, ntiles);
+  hipLaunchKernelGGL(k_tile_box, dim3(tile_loop_blocks(tl.max_tiles)), dim3(256), 0, st, tiles,
+                     ntiles, p32, tbox);
+  const P2PSched sched{reinterpret_cast<uint32_t*>(ws + tl.sched_cnt),
+                       reinterpret_cast<uint32_t*>(ws + tl.sched_poff),
+                       reinterpret_cast<uint32_t*>(ws + tl.sched_soff),
+                       reinterpret_cast<P2PPart*>(ws + tl.sched_parts),
+                       reinterpret_cast<double2*>(ws + tl.sched_partial),
+                       reinterpret_cast<uint64_t*>(ws + tl.sched_bsum), tmp,
+                       reinterpret_cast<double2*>(ws + tl.sched_near)};
+  out = TargetsDev{p64, p32, tiles, ntiles, tbox, toff, perm, tl.max_tiles, sched, shift, fine64};
   return hipGetLastError();
 }
 

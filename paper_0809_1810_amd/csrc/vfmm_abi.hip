@@ -467,6 +467,20 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   return L;
 }
 
+AdaptiveLayout make_adaptive_layout(int64_t n, int levels) {
+  AdaptiveLayout L{};
+  L.targets = make_target_layout(n, levels);
+  size_t off = L.targets.total;
+  auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+  // box counts of levels 0 .. L: (4^(L+1) - 1) / 3 entries
+  L.counts = take(size_t(((int64_t(1) << (2 * (levels + 1))) - 1) / 3) * 4);
+  L.shift = take(size_t(int64_t(1) << (2 * levels)));
+  L.perm = take(size_t(n) * 4);
+  L.fine64 = take(size_t(n) * sizeof(Part64));
+  L.total = off;
+  return L;
+}
+
 }  // namespace vfmm
 
 extern "C" {
@@ -522,6 +536,41 @@ vfmm_status_t vfmm_fmm_velocity_at(vfmm_tree_t t, const double* gamma, double si
   s = evaluate(t, tg, gamma, sigma, p, precision, parts, u, v, mark, st);
   if (s) return s;
   return finite_check(t, gamma, u, v, n_targets, st);
+}
+
+vfmm_status_t vfmm_adaptive_workspace_bytes(int64_t n, int32_t levels, size_t* bytes) {
+  if (!bytes) return fail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
+  if (n < 1 || n > 2147483647LL) return fail(VFMM_ERR_INVALID_ARG, "n out of [1, 2^31-1]");
+  if (levels < 0 || levels > kMaxLevels)
+    return fail(VFMM_ERR_INVALID_ARG, "levels=%d out of [0, %d]", levels, kMaxLevels);
+  *bytes = make_adaptive_layout(n, levels).total;
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_fmm_velocity_adaptive(vfmm_tree_t t, const double* gamma, double sigma,
+                                         int32_t p, int32_t precision, int32_t parts,
+                                         int64_t leaf_capacity, void* workspace, size_t ws_bytes,
+                                         double* u, double* v, void* stream) {
+  vfmm_status_t s = check_eval(t, gamma, sigma, p, precision, parts, u, v);
+  if (s) return s;
+  if (leaf_capacity < 0) return fail(VFMM_ERR_INVALID_ARG, "leaf_capacity < 0");
+  if (!workspace) return fail(VFMM_ERR_INVALID_ARG, "workspace is NULL");
+  const AdaptiveLayout lay = make_adaptive_layout(t->n, t->levels);
+  if (ws_bytes < lay.total)
+    return fail(VFMM_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(VFMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = check_capture(t, st))) return s;
+  const Marks mark(t);
+  mark.begin(kPhGather, st);
+  TargetsDev tg{};
+  hipError_t e = launch_build_adaptive(t->dev, t->levels, leaf_capacity, lay,
+                                       static_cast<char*>(workspace), tg, st);
+  if (e != hipSuccess) return hip_fail(e, "adaptive targets");
+  s = evaluate(t, tg, gamma, sigma, p, precision, parts, u, v, mark, st);
+  if (s) return s;
+  return finite_check(t, gamma, u, v, t->n, st);
 }
 
 vfmm_status_t vfmm_error_field(const double* u, const double* v, const double* ur,

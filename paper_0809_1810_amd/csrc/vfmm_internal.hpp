@@ -166,6 +166,14 @@ struct TargetsDev {
   const int32_t* perm;   // sorted position -> caller's index
   int64_t max_tiles;
   P2PSched sched;
+  // adaptive tree (NULL: every target leaf is a leaf-level box): per
+  // leaf-level box f, k = L - level of the adaptive leaf holding it; a tile's
+  // leaf is then the leaf-level box at the lower-left corner of its adaptive
+  // leaf, which is box (f_x >> k, f_y >> k) of level L - k
+  const uint8_t* leaf_shift;
+  // adaptive tree: per target the tree's leaf-local record, with the
+  // leaf-level box in place of the circulation (offsets to the sources)
+  const Part64* fine64;
 };
 
 inline TargetsDev self_targets(const TreeDev& t, const Layout& lay) {
@@ -183,6 +191,15 @@ struct TargetLayout {
 };
 
 TargetLayout make_target_layout(int64_t nt, int levels);
+
+// Workspace of the adaptive target set of a tree of n particles: the target
+// layout plus the box counts of levels 0 .. L, the per-box level shift and the
+// targets' caller indices.
+struct AdaptiveLayout {
+  TargetLayout targets;
+  size_t counts, shift, perm, fine64, total;
+};
+AdaptiveLayout make_adaptive_layout(int64_t n, int levels);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
@@ -214,8 +231,8 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
 // Reduced-precision evaluation with float64 shifts (p > kShift64P): the
 // float64 multipoles of t.me (P2M and M2M in float64) rounded to float32 into
 // t.me32, M2L on the matrix cores into t.le32, the L2L chain in float64 into
-// t.le (each level: its M2L sum widened plus the shifted parent LE), and the
-// leaf level rounded back into t.le32 for the float32 L2P.
+// t.le (each level: its M2L sum widened plus the shifted parent LE), and every
+// level rounded back into t.le32 for the float32 L2P.
 hipError_t launch_downward_shift64(const TreeDev& t, int levels, int p, int prec,
                                    hipStream_t stream);
 // radius: distance cut-off of the near field (0 = off, < 0 = the distance at
@@ -240,6 +257,13 @@ hipError_t launch_l2p(const TreeDev& t, const TargetsDev& tg, int levels, int p,
 hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, const TreeDev& t,
                                 int levels, const TargetLayout& lay, char* ws, TargetsDev& out,
                                 hipStream_t stream);
+// The tree's particles as targets of the adaptive tree (box split while it
+// holds more than s particles, down to the leaf level): each particle sorted
+// into its adaptive leaf, coordinates relative to that leaf's centre, tiles of
+// t.tile targets of one adaptive leaf.
+hipError_t launch_build_adaptive(const TreeDev& t, int levels, int64_t s,
+                                 const AdaptiveLayout& lay, char* ws, TargetsDev& out,
+                                 hipStream_t stream);
 // Per-point log10 of |dW| / max |W_ref| (metrics[2] holds max |W_ref|).
 hipError_t launch_error_field(const double* u, const double* v, const double* ur,
                               const double* vr, int64_t n, const double* metrics, double* out,

@@ -64,6 +64,10 @@ _SIGS = {
     "vfmm_fmm_velocity_at": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                          C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vfmm_adaptive_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "vfmm_fmm_velocity_adaptive": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                               C.c_int32, C.c_int32, C.c_int64, C.c_void_p,
+                                               C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_direct_velocity_at": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                             C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
                                             C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -288,6 +292,34 @@ class Tree:
                                           workspace.numel() * workspace.element_size(),
                                           u.data_ptr(), v.data_ptr(), _stream()),
                "vfmm_fmm_velocity_at")
+        return u, v
+
+    def velocity_adaptive(self, gamma, sigma: float, p: int, leaf_capacity: int, precision=FP64,
+                          parts=PART_ALL, out=None, workspace=None):
+        """FMM velocity on the adaptive tree whose leaves hold at most
+        ``leaf_capacity`` particles above this tree's leaf level."""
+        torch = _torch()
+        gamma = _dev_f64(gamma, "gamma")
+        if gamma.shape[0] != self.n:
+            raise ValueError("gamma has the wrong length")
+        precision = PRECISIONS.get(precision, precision)
+        if out is None:
+            u = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            v = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        else:
+            u, v = out
+        if workspace is None:
+            b = C.c_size_t(0)
+            _check(lib().vfmm_adaptive_workspace_bytes(self.n, self.levels, C.byref(b)),
+                   "vfmm_adaptive_workspace_bytes")
+            workspace = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        self._adaptive_ws = workspace
+        _check(lib().vfmm_fmm_velocity_adaptive(self._h, gamma.data_ptr(), float(sigma), int(p),
+                                                int(precision), int(parts), int(leaf_capacity),
+                                                workspace.data_ptr(),
+                                                workspace.numel() * workspace.element_size(),
+                                                u.data_ptr(), v.data_ptr(), _stream()),
+               "vfmm_fmm_velocity_adaptive")
         return u, v
 
     def rebuild(self, x, y, domain=None):
