@@ -745,7 +745,13 @@ struct vfmm_batch_s {
   // the expansion sweeps run on `side` (default priority) beside the near field
   hipStream_t side;
   hipEvent_t fork, join;
+  // recorded on the caller's stream at the end of every run: the plan is
+  // released only once its last run has finished
+  hipEvent_t done;
   ~vfmm_batch_s() {
+    if (done) (void)hipEventSynchronize(done);
+    if (side) (void)hipStreamSynchronize(side);
+    if (done) (void)hipEventDestroy(done);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (fork) (void)hipEventDestroy(fork);
@@ -861,7 +867,7 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
 
 extern "C" {
 
-vfmm_status_t vfmm_batch_workspace_bytes(const vfmm_instance* inst, int32_t count, size_t* bytes) {
+static vfmm_status_t vfmm_batch_workspace_bytes_impl(const vfmm_instance* inst, int32_t count, size_t* bytes) {
   if (!bytes) return bfail(VFMM_ERR_INVALID_ARG, "bytes is NULL");
   vfmm_status_t s = check_instances(inst, count);
   if (s) return s;
@@ -869,7 +875,7 @@ vfmm_status_t vfmm_batch_workspace_bytes(const vfmm_instance* inst, int32_t coun
   return VFMM_OK;
 }
 
-vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* workspace,
+static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t count, void* workspace,
                                 size_t ws_bytes, vfmm_batch_t* out) {
   if (!out) return bfail(VFMM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -894,10 +900,11 @@ vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* 
   ls_off[count] = leaf_off[count] + count;
   for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
   vfmm_batch_s* b = new (std::nothrow) vfmm_batch_s{};
-  if (!b) return bfail(VFMM_ERR_INVALID_ARG, "host allocation failed");
+  if (!b) return bfail(VFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
   hipError_t es = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
   if (es == hipSuccess) es = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
   if (es == hipSuccess) es = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  if (es == hipSuccess) es = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (es != hipSuccess) {
     delete b;
     return bfail(hip_status(es), "batch stream / events: %s", hipGetErrorString(es));
@@ -1017,6 +1024,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
     e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->l2l_tot,
                          b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st,
                          b->side, b->fork, b->join);
+    if (e == hipSuccess) e = hipEventRecord(b->done, st);
     return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "batch run: %s", hipGetErrorString(e));
   }
   if (!b->exec) {
@@ -1032,6 +1040,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
     if (e != hipSuccess) return bfail(hip_status(e), "instantiate: %s", hipGetErrorString(e));
   }
   e = hipGraphLaunch(b->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(b->done, st);
   return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "graph launch: %s", hipGetErrorString(e));
 }
 
@@ -1045,6 +1054,27 @@ vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count
   s = vfmm_batch_run(b, 0, stream);
   vfmm_batch_destroy(b);
   return s;
+}
+
+// Host allocations inside (std::vector) report running out of memory as a
+// status instead of letting the exception cross the C ABI.
+vfmm_status_t vfmm_batch_workspace_bytes(const vfmm_instance* inst, int32_t count, size_t* bytes) {
+  try {
+    return vfmm_batch_workspace_bytes_impl(inst, count, bytes);
+  } catch (const std::bad_alloc&) {
+    return bfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_batch_workspace_bytes: host allocation failed");
+  }
+}
+
+// Host allocations inside (std::vector) report running out of memory as a
+// status instead of letting the exception cross the C ABI.
+vfmm_status_t vfmm_batch_create(const vfmm_instance* inst, int32_t count, void* workspace, size_t ws_bytes,
+                                vfmm_batch_t* out) {
+  try {
+    return vfmm_batch_create_impl(inst, count, workspace, ws_bytes, out);
+  } catch (const std::bad_alloc&) {
+    return bfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_batch_create: host allocation failed");
+  }
 }
 
 }  // extern "C"

@@ -10,6 +10,7 @@
 // negligible).
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <cstdarg>
 #include <cstdio>
 #include <vector>
@@ -177,7 +178,7 @@ vfmm_status_t vfmm_selector_features(const double* st, int64_t n, double sigma, 
   return VFMM_OK;
 }
 
-vfmm_status_t vfmm_select_params(const double* x, const double* y, const double* gamma, int64_t n,
+static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, const double* gamma, int64_t n,
                                  double sigma, double tol, const float* params,
                                  const float* feat_mean, const float* feat_std, double margin,
                                  void* scratch, size_t scratch_bytes, int32_t* p_out,
@@ -444,7 +445,7 @@ vfmm_status_t vfmm_select_audit_workspace_bytes(int64_t n, int64_t n_audit, int3
   return VFMM_OK;
 }
 
-vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const double* gamma,
+static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y, const double* gamma,
                                     int64_t n, double sigma, double tol, const float* params,
                                     const float* feat_mean, const float* feat_std, double margin,
                                     const int64_t* targets, int64_t n_audit, const double* u_ref,
@@ -584,6 +585,40 @@ vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const doub
   out->near_radius = best_r;
   out->audit_emax = best_e;
   return VFMM_OK;
+}
+
+// Host allocations inside (std::vector) report running out of memory as a
+// status instead of letting the exception cross the C ABI.
+vfmm_status_t vfmm_select_params(const double* x, const double* y, const double* gamma, int64_t n,
+                                 double sigma, double tol, const float* params,
+                                 const float* feat_mean, const float* feat_std, double margin,
+                                 void* scratch, size_t scratch_bytes, int32_t* p_out,
+                                 int32_t* levels_out, double* pred_out, int32_t* fallback_out,
+                                 void* stream) {
+  try {
+    return vfmm_select_params_impl(x, y, gamma, n, sigma, tol, params, feat_mean, feat_std, margin, scratch,
+                                   scratch_bytes, p_out, levels_out, pred_out, fallback_out, stream);
+  } catch (const std::bad_alloc&) {
+    return sfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_select_params: host allocation failed");
+  }
+}
+
+// Host allocations inside (std::vector) report running out of memory as a
+// status instead of letting the exception cross the C ABI.
+vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const double* gamma,
+                                    int64_t n, double sigma, double tol, const float* params,
+                                    const float* feat_mean, const float* feat_std, double margin,
+                                    const int64_t* targets, int64_t n_audit, const double* u_ref,
+                                    const double* v_ref, int32_t flags, double slack,
+                                    int32_t time_reps, int32_t max_levels, void* workspace,
+                                    size_t ws_bytes, vfmm_selection* out, void* stream) {
+  try {
+    return vfmm_select_and_audit_impl(x, y, gamma, n, sigma, tol, params, feat_mean, feat_std, margin,
+                                      targets, n_audit, u_ref, v_ref, flags, slack, time_reps,
+                                      max_levels, workspace, ws_bytes, out, stream);
+  } catch (const std::bad_alloc&) {
+    return sfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_select_and_audit: host allocation failed");
+  }
 }
 
 }  // extern "C"

@@ -41,7 +41,13 @@ struct vfmm_tree_s {
   // the two device counters are read back into this pinned host pair
   int check_finite;
   unsigned long long* check_host;
+  // recorded on the caller's stream at the end of every evaluation: the
+  // handle (its stream and events) is released only once that work is done
+  hipEvent_t done;
   ~vfmm_tree_s() {
+    if (done) (void)hipEventSynchronize(done);
+    if (side) (void)hipStreamSynchronize(side);
+    if (done) (void)hipEventDestroy(done);
     if (check_host) (void)hipHostFree(check_host);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
@@ -222,6 +228,7 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->gathered, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete t;
     return hip_fail(e, "tree stream / events");
@@ -422,6 +429,8 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   e = launch_l2p(tl, tg, L, far ? p : 0, prec, near ? 1 : 0, u, v, st);
   if (e != hipSuccess) return hip_fail(e, "L2P");
   mark.end(kPhL2P, st);
+  e = hipEventRecord(t->done, st);
+  if (e != hipSuccess) return hip_fail(e, "done event");
   return VFMM_OK;
 }
 
