@@ -15,8 +15,9 @@ Two paths are timed on the same particles:
   box side / sigma >= 8.
 
 Accuracy of both is measured against the float64 direct sum on 4096 sampled
-targets.  The P2P kernel (the dominant one) is timed with HIP events around
-its launches inside the timed region; its roofline uses 15 algorithmic FLOPs
+hold-out targets, disjoint from the 16384 targets of the selector's audit.
+The P2P kernel (the dominant one) is timed with HIP events around its
+launches inside the timed region; its roofline uses 15 algorithmic FLOPs
 per pair (2 sub, r^2 = 3, exponent argument 1, exp 1, 1 - e 1, reciprocal 1,
 2 products, 2 fused accumulations = 4) against the MI355X FP32 vector peak.
 The CPU baseline is the float64 NumPy oracle on a bounded sample of targets.
@@ -42,7 +43,8 @@ import workloads as W  # noqa: E402
 METRIC = "particles/s at N=1M, max rel err ≤1e-6 vs FP64 direct; tuned vs plain FP64"
 FP32_PEAK_TFLOPS = 157.3
 P2P_FLOPS_PER_PAIR = 15
-AUDIT_TARGETS = 4096
+AUDIT_TARGETS = 4096      # the metric's sample: accuracy is reported on this many hold-out targets
+SELECT_AUDIT_TARGETS = 16384  # the selector's audit: the truncation error has a thin tail
 HOLDOUT_SEED = 7919
 CPU_MAX_WORKERS = 16
 
@@ -216,10 +218,12 @@ def main():
                     help="with --p/--levels: distance cut-off radius in units of sigma")
     ap.add_argument("--cpu-targets", type=int, default=65536)
     ap.add_argument("--audit-targets", type=int, default=0,
-                    help="sampled targets of the FP64 direct-sum audit (default 8192 for the "
-                         "2048^2 lattice, the selection workload, else 4096)")
+                    help="sampled targets of the selector's FP64 direct-sum audit (default "
+                         "16384); the accuracy is reported on 4096 other targets")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-quadtree A/B at the tuned parameters")
     ap.add_argument("--no-lattice", action="store_true",
                     help="skip the second N = 1M input (the 1024^2 lattice)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -275,7 +279,7 @@ def main():
 
     P = W.config(a.workload)
     n = P.n
-    n_audit = a.audit_targets or (8192 if a.workload == "lattice_2048" else AUDIT_TARGETS)
+    n_audit = a.audit_targets or SELECT_AUDIT_TARGETS
     log(f"[bench] workload {P.name} n={n} sigma={P.sigma}")
     x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
     g = torch.from_numpy(P.gamma).cuda()
@@ -288,7 +292,7 @@ def main():
     tg = W.sample_targets(n, n_audit, seed=2024)
     tg_d = torch.from_numpy(tg).cuda()
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg_d)
-    th = holdout_targets(n, n_audit, tg, HOLDOUT_SEED)
+    th = holdout_targets(n, AUDIT_TARGETS, tg, HOLDOUT_SEED)
     th_d = torch.from_numpy(th).cuda()
     uh, vh = vf.direct_velocity(x, y, g, P.sigma, targets=th_d)
     torch.cuda.synchronize()
@@ -322,16 +326,22 @@ def main():
 
     from paper_0809_1810_amd import autotune as AT
 
-    def run_path(L, p, prec, steps, warmup, timing=False, radius=0.0):
+    def run_path(L, p, prec, steps, warmup, timing=False, radius=0.0, capacity=None):
         AT.apply_for(n, L, cutoff=radius != 0.0)  # near-field launch shape from the autotuner's table
         override_tuning(a, vf)
         tree = vf.Tree(x, y, L, p_max=p)
         tree.set_near_radius(radius)
         u = torch.empty(n, dtype=torch.float64, device="cuda")
         v = torch.empty(n, dtype=torch.float64, device="cuda")
+
+        def evaluate():
+            if capacity is None:
+                tree.velocity(g, P.sigma, p, prec, out=(u, v))
+            else:  # adaptive tree: leaves of at most `capacity` particles above level L
+                tree.velocity_adaptive(g, P.sigma, p, capacity, prec, out=(u, v))
         for _ in range(warmup):
             tree.rebuild(x, y)
-            tree.velocity(g, P.sigma, p, prec, out=(u, v))
+            evaluate()
         torch.cuda.synchronize()
         if timing:
             tree.enable_timing(steps)
@@ -340,7 +350,7 @@ def main():
         e0.record()
         for _ in range(steps):
             tree.rebuild(x, y)
-            tree.velocity(g, P.sigma, p, prec, out=(u, v))
+            evaluate()
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -349,7 +359,7 @@ def main():
         emax, erms, _ = vf.error_metrics(u[tg_d].contiguous(), v[tg_d].contiguous(), ud, vd)
         hmax, hrms, _ = vf.error_metrics(u[th_d].contiguous(), v[th_d].contiguous(), uh, vh)
         far_phases = []
-        if timing and L >= 2:
+        if timing and L >= 2 and capacity is None:
             # the expansion sweeps alone (far part only: no near field runs
             # beside them), after the timed region, for their own rooflines
             tree.enable_timing(steps)
@@ -368,6 +378,18 @@ def main():
     tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True, radius=radius_t)
     log(f"[bench] tuned {tuned['ms']:.3f} ms/step emax={tuned['emax']:.3e} "
         f"(hold-out {tuned['holdout_emax']:.3e})")
+    # the same method on an adaptive quadtree (A/B against the uniform tree)
+    adaptive = []
+    if not a.no_adaptive and L_t >= 3:
+        for cap in (64, 256):
+            r_ad = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True, radius=radius_t,
+                            capacity=cap)
+            adaptive.append({"leaf_capacity": cap, "levels_max": L_t,
+                             "ms_per_step": round(r_ad["ms"], 4),
+                             "p2p_ms": round(float(np.mean([ph["p2p"] for ph in r_ad["phases"]])), 4),
+                             "holdout_emax": r_ad["holdout_emax"]})
+            log(f"[bench] adaptive capacity {cap}: {r_ad['ms']:.3f} ms/step "
+                f"(hold-out {r_ad['holdout_emax']:.3e})")
     plain = None
     if not a.no_plain:
         log(f"[bench] plain: p={p_plain} L={L_plain} fp64")
@@ -465,6 +487,14 @@ def main():
                              "frac": round((p2m_b + m2m_b) / (sw_ms * 1e-3) / 8e12, 4),
                              "kernel": "k_p2m + k_m2m", "ms": round(sw_ms, 4),
                              "bytes": p2m_b + m2m_b}
+    if adaptive:
+        out["adaptive_tree"] = {
+            "uniform_ms_per_step": round(tuned["ms"], 4),
+            "uniform_p2p_ms": out["phases_ms"]["p2p"],
+            "runs": adaptive,
+            "note": "the same p, deepest level and near radius on the adaptive quadtree (box "
+                    "split above the leaf capacity); the step includes sorting the particles "
+                    "into the adaptive leaves"}
     if not a.no_lattice and a.workload == "clusters_1m":
         out["lattice_1m"] = second_input(a, torch, vf, "lattice_1024")
     print(json.dumps(out), flush=True)
@@ -484,7 +514,7 @@ def second_input(a, torch, vf, name):
     probe = vf.Tree(x, y, 0, p_max=1)
     side = float(probe.arrays()[0][2].item())
     probe.close()
-    tg_h = W.sample_targets(n, AUDIT_TARGETS, seed=2024)
+    tg_h = W.sample_targets(n, SELECT_AUDIT_TARGETS, seed=2024)
     tg = torch.from_numpy(tg_h).cuda()
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg)
     th = torch.from_numpy(holdout_targets(n, AUDIT_TARGETS, tg_h, HOLDOUT_SEED)).cuda()

@@ -556,9 +556,15 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
  *                        or four lanes per target; also the source-chunk size
  *                        of the far-pair test).
  *   VFMM_TUNE_P2P_WAVES: waves per workgroup of the near-field launch: 1, 2, 4, 8.
+ *   VFMM_TUNE_M2L_TILE : float32 matrix-core M2L for p <= 16: 0 = a 32-box tile
+ *                        per workgroup of 4 waves with the operands loaded into
+ *                        registers one offset ahead; 1 / 2 = the tile's source
+ *                        multipoles first staged in LDS (coalesced row loads),
+ *                        4 / 8 waves per workgroup (default 1).
  * Results do not depend on the settings beyond float32 summation order. */
 #define VFMM_TUNE_P2P_TILE 1
 #define VFMM_TUNE_P2P_WAVES 2
+#define VFMM_TUNE_M2L_TILE 3
 vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value);
 int32_t vfmm_get_tuning(int32_t param); /* -1 for an unknown parameter */
 /* The setting a tree was built with (-1 for a NULL tree or an unknown parameter). */

@@ -147,6 +147,22 @@ __global__ void __launch_bounds__(256) k_m2l_mfma_f32(const float2* __restrict__
                    tile - lt.first[lev], packA, sh);
 }
 
+// FP32, p <= 16: the tile's source multipoles staged in LDS first (m2l_tile.hpp),
+// W waves per workgroup.
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_m2l_mfma_f32_staged(const float2* __restrict__ me,
+                                                               float2* __restrict__ le, int levels,
+                                                               int p, LevelTiles lt,
+                                                               const float* __restrict__ packA) {
+  __shared__ M2LStagedLds<W> sh;
+  const int tile = blockIdx.x;
+  if (tile >= lt.first[levels + 1]) return;
+  int lev = 2;
+  while (tile >= lt.first[lev + 1]) ++lev;
+  m2l_f32_tile_staged<W>(me + level_offset(lev) * p, le + level_offset(lev) * p, lev, p,
+                         tile - lt.first[lev], packA, sh);
+}
+
 // 16-bit operands of one interaction offset: the packed operator columns (MT
 // row tiles x ks_n K-steps of 8 values per lane) and the lane's 8 source
 // entries per K-step, multiplied by the level's power of two and rounded.
@@ -307,7 +323,13 @@ void launch_mode(const TreeDev& t, int levels, int p, const LevelTiles& lt, cons
   if constexpr (MODE == kModeF32) {
     const unsigned tiles = unsigned(lt.first[levels + 1]);
     const float* A = static_cast<const float*>(pack);
-    if (mt == 1)
+    if (mt == 1 && t.m2l_tile == 1)
+      hipLaunchKernelGGL((k_m2l_mfma_f32_staged<4>), dim3(tiles), dim3(256), 0, st, me, le, levels,
+                         p, lt, A);
+    else if (mt == 1 && t.m2l_tile == 2)
+      hipLaunchKernelGGL((k_m2l_mfma_f32_staged<8>), dim3(tiles), dim3(512), 0, st, me, le, levels,
+                         p, lt, A);
+    else if (mt == 1)
       hipLaunchKernelGGL((k_m2l_mfma_f32<1>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);
     else if (mt == 2)
       hipLaunchKernelGGL((k_m2l_mfma_f32<2>), dim3(tiles), dim3(256), 0, st, me, le, levels, p, lt, A);

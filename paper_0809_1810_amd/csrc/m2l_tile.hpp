@@ -150,6 +150,130 @@ __device__ __forceinline__ void m2l_f32_tile(const float2* __restrict__ me_l,
     }
 }
 
+// ---------------------------------------------------------------- staged FP32 tile
+//
+// For p <= 16 (one 32-row tile): the multipoles of every source box of the
+// tile's 27 offsets are first copied into LDS by the whole workgroup, row by row
+// (each row of the source region is contiguous in memory, so the loads are
+// coalesced and all in flight at once), then the waves read their B operands
+// from LDS.  The region is split by column parity: the 32 sources of one offset
+// are every other box of a row, and become consecutive records of stride
+// 2p + 1 (odd) floats, so the 32 lanes of a read fall in distinct banks.  The
+// operator columns (A) stay in global memory (L2), loaded one offset ahead.
+// Source region of a tile: rows 2 r0 - 2 .. 2 r1 + 3 and columns 2 c0 - 2 ..
+// 2 c1 + 3 of the level for target class rows r0..r1 and class columns c0..c1,
+// clipped.  With half >= 32 a tile is 32 consecutive boxes of one class row
+// (6 rows, at most 68 columns: at most 35 boxes per parity plane and row);
+// with half <= 16 it spans at most 12 rows of a level at most 32 boxes wide.
+// So 2 x rows x (boxes per plane and row) <= 2 x 6 x 35 records.
+constexpr int kStageSlots = 2 * 6 * 35;
+constexpr int kStageStride = 33;  // 2p + 1 for p = 16, the largest staged order
+
+template <int W>
+struct M2LStagedLds {
+  float part[W - 1][16][64];
+  float src[kStageSlots * kStageStride];
+};
+
+template <int W>
+__device__ __forceinline__ void m2l_f32_tile_staged(const float2* __restrict__ me_l,
+                                                    float2* __restrict__ le_l, int lev, int p,
+                                                    int local, const float* __restrict__ packA,
+                                                    M2LStagedLds<W>& sh) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int half = 1 << (lev - 1), m = 1 << lev;
+  const int per_class = half * half;
+  const int tiles_pc = (per_class + 31) / 32;
+  const int c = local / tiles_pc, tt = local % tiles_pc;
+  const int cx = c & 1, cy = c >> 1;
+  const int col = lane & 31, hi = lane >> 5;
+  const int q = tt * 32 + col;
+  const bool valid = q < per_class;
+  const int qq = valid ? q : 0;
+  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
+  const int twop = 2 * p;
+  const int ks_n = p;
+  const int stride = twop + 1;
+
+  // source region: rows of the tile's first and last target, +-(2..3)
+  const int q0 = tt * 32, q1 = min(q0 + 31, per_class - 1);
+  const int r0 = q0 / half, r1 = q1 / half;  // class rows of the tile
+  const int cx0 = r0 == r1 ? q0 % half : 0, cx1 = r0 == r1 ? q1 % half : half - 1;
+  const int y0 = max(2 * r0 - 2, 0), y1 = min(2 * r1 + 3, m - 1);
+  const int x0 = max(2 * cx0 - 2, 0), x1 = min(2 * cx1 + 3, m - 1);
+  const int rows = y1 - y0 + 1;
+  const int wp = (x1 >> 1) - (x0 >> 1) + 1;  // boxes per parity plane and row
+  const int rowlen = (x1 - x0 + 1) * twop;   // floats of one source row
+  const float* gsrc = reinterpret_cast<const float*>(me_l);
+  for (int f = tid; f < rows * rowlen; f += 64 * W) {
+    const int r = f / rowlen, rem = f - r * rowlen;
+    const int bxo = rem / twop, k = rem - bxo * twop;
+    const int sx = x0 + bxo;
+    const int slot = ((sx & 1) * rows + r) * wp + ((sx >> 1) - (x0 >> 1));
+    sh.src[slot * stride + k] = gsrc[(int64_t(y0 + r) * m + x0) * twop + rem];
+  }
+
+  v16f acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  auto slot_of = [&](int ox, int oy, bool& sv) {
+    const int sx = bx - ox, sy = by - oy;
+    sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
+    return sv ? (((sx & 1) * rows + (sy - y0)) * wp + ((sx >> 1) - (x0 >> 1))) * stride : 0;
+  };
+  auto a_of = [&](int ox, int oy) { return packA + int64_t(m2l_index(ox, oy)) * ks_n * 64 + lane; };
+  float a_cur[16], a_nxt[16];
+  int ox, oy;
+  if (wv < 27) {
+    nth_offset(wv, cx, cy, ox, oy);
+    const float* A = a_of(ox, oy);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+      if (ks < ks_n) a_cur[ks] = A[int64_t(ks) * 64];
+  }
+  __syncthreads();  // the staged sources are complete
+  for (int j = wv; j < 27; j += W) {
+    nth_offset(j, cx, cy, ox, oy);
+    bool sv;
+    const int base = slot_of(ox, oy, sv) + hi;
+    if (j + W < 27) {
+      int ox2, oy2;
+      nth_offset(j + W, cx, cy, ox2, oy2);
+      const float* A = a_of(ox2, oy2);
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks)
+        if (ks < ks_n) a_nxt[ks] = A[int64_t(ks) * 64];
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      if (ks < ks_n) {
+        const float b = sv ? sh.src[base + 2 * ks] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[ks], b, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) a_cur[ks] = a_nxt[ks];
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sh.part[wv - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wv > 0 || !valid) return;
+#pragma unroll
+  for (int w = 0; w < W - 1; ++w)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += sh.part[w][r][lane];
+  float* out = reinterpret_cast<float*>(le_l + (int64_t(by) * m + bx) * p);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * hi + (r & 3);
+    if (i < twop) out[i] = acc[r];
+  }
+}
+
 // ---------------------------------------------------------------- FP64 variant
 //
 // v_mfma_f64_16x16x4f64: A[i][k] with i = lane % 16, k-slot lane / 16; B[k][j]

@@ -79,8 +79,10 @@ void set_last_error(const char* msg) { g_err = msg; }
 
 std::atomic<int> g_tile{kTile};
 std::atomic<int> g_waves{4};
+std::atomic<int> g_m2l_tile{1};
 int tuning_tile() { return g_tile.load(); }
 int tuning_waves() { return g_waves.load(); }
+int tuning_m2l_tile() { return g_m2l_tile.load(); }
 
 }  // namespace vfmm
 
@@ -233,7 +235,8 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
     delete t;
     return hip_fail(e, "tree stream / events");
   }
-  t->dev.waves = tuning_waves();  // the launch shape is the tree's from now on
+  t->dev.waves = tuning_waves();  // the launch shapes are the tree's from now on
+  t->dev.m2l_tile = tuning_m2l_tile();
   e = launch_build_tree(x, y, n, levels, domain, lay, t->ws, tuning_tile(), t->dev,
                         static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
@@ -802,12 +805,18 @@ vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value) {
     g_waves.store(value);
     return VFMM_OK;
   }
+  if (param == VFMM_TUNE_M2L_TILE) {
+    if (value < 0 || value > 2) return fail(VFMM_ERR_INVALID_ARG, "M2L tile must be 0, 1 or 2");
+    g_m2l_tile.store(value);
+    return VFMM_OK;
+  }
   return fail(VFMM_ERR_INVALID_ARG, "unknown tuning parameter %d", param);
 }
 
 int32_t vfmm_get_tuning(int32_t param) {
   if (param == VFMM_TUNE_P2P_TILE) return g_tile.load();
   if (param == VFMM_TUNE_P2P_WAVES) return g_waves.load();
+  if (param == VFMM_TUNE_M2L_TILE) return g_m2l_tile.load();
   return -1;
 }
 
@@ -815,6 +824,7 @@ int32_t vfmm_tree_get_tuning(vfmm_tree_t t, int32_t param) {
   if (!t) return -1;
   if (param == VFMM_TUNE_P2P_TILE) return t->dev.tile;
   if (param == VFMM_TUNE_P2P_WAVES) return t->dev.waves;
+  if (param == VFMM_TUNE_M2L_TILE) return t->dev.m2l_tile;
   return -1;
 }
 

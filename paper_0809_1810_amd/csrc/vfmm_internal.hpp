@@ -136,6 +136,8 @@ struct TreeDev {
   int32_t* leaf_start;   // [nleaves + 1]
   int tile;              // particles per P2P tile: 64, 32 or 16 (64 / lanes per target)
   int waves;             // waves per workgroup of the near-field launch: 1, 2, 4 or 8
+  int m2l_tile;          // FP32 matrix-core M2L tile for p <= 16: 0 operands in registers,
+                         // 1 / 2 sources staged in LDS with 4 / 8 waves per workgroup
   int64_t max_tiles;     // capacity of the tile arrays
   Tile* tiles;           // P2P target tiles (<= tile consecutive particles of one leaf)
   int32_t* ntiles;       // device count of tiles
@@ -210,6 +212,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
 // that trees built from now on take (each tree keeps its own).
 int tuning_tile();
 int tuning_waves();
+int tuning_m2l_tile();
 // Circulations into the sorted particle records; with sigma > 0 also the
 // FP32 near-field sources scaled by sqrt(log2(e) / (2 sigma^2)) (part32s).
 hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,

@@ -137,7 +137,7 @@ class Instance(C.Structure):
                 ("v", C.c_void_p), ("n", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32),
                 ("levels", C.c_int32)]
 
-TUNE_P2P_TILE, TUNE_P2P_WAVES = 1, 2
+TUNE_P2P_TILE, TUNE_P2P_WAVES, TUNE_M2L_TILE = 1, 2, 3
 
 SELECT_AUDIT, SELECT_CUTOFF = 1, 2
 SELECT_TRAIL_MAX = 16
@@ -366,9 +366,10 @@ class Tree:
                "vfmm_tree_set_check_finite")
 
     def tuning(self):
-        """The near-field launch shape this tree was built with: {tile, waves}."""
+        """The launch shapes this tree was built with: {tile, waves, m2l}."""
         return {"tile": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_TILE)),
-                "waves": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_WAVES))}
+                "waves": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_WAVES)),
+                "m2l": int(lib().vfmm_tree_get_tuning(self._h, TUNE_M2L_TILE))}
 
     def enable_timing(self, max_calls: int):
         _check(lib().vfmm_tree_enable_timing(self._h, int(max_calls)), "vfmm_tree_enable_timing")
@@ -636,7 +637,7 @@ def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0
 
 
 def select_and_audit(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin, targets,
-                     reference=None, audit=True, cutoff=True, slack=0.8, time_reps=3,
+                     reference=None, audit=True, cutoff=True, slack=0.5, time_reps=3,
                      max_levels=0):
     """vfmm_select_and_audit: the network's (p, L), audited on ``targets`` (device
     int64 particle indices) against ``reference`` ((u, v) of the FP64 direct sum
@@ -728,14 +729,18 @@ class Batch:
             pass
 
 
-def set_tuning(tile=None, waves=None):
-    """Near-field tile size (64/32/16, for trees built afterwards) and waves per workgroup."""
+def set_tuning(tile=None, waves=None, m2l=None):
+    """Launch shapes for trees built afterwards: near-field tile size (64/32/16),
+    near-field waves per workgroup (1/2/4/8), FP32 matrix-core M2L tile (0/1/2)."""
     if tile is not None:
         _check(lib().vfmm_set_tuning(TUNE_P2P_TILE, int(tile)), "vfmm_set_tuning")
     if waves is not None:
         _check(lib().vfmm_set_tuning(TUNE_P2P_WAVES, int(waves)), "vfmm_set_tuning")
+    if m2l is not None:
+        _check(lib().vfmm_set_tuning(TUNE_M2L_TILE, int(m2l)), "vfmm_set_tuning")
 
 
 def get_tuning():
     return {"tile": int(lib().vfmm_get_tuning(TUNE_P2P_TILE)),
-            "waves": int(lib().vfmm_get_tuning(TUNE_P2P_WAVES))}
+            "waves": int(lib().vfmm_get_tuning(TUNE_P2P_WAVES)),
+            "m2l": int(lib().vfmm_get_tuning(TUNE_M2L_TILE))}

@@ -34,22 +34,22 @@ def test_two_trees_keep_their_own_launch_shape(vf):
     old = vf.get_tuning()
     x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
     try:
-        vf.set_tuning(tile=16, waves=8)
+        vf.set_tuning(tile=16, waves=8, m2l=0)
         ta = vf.Tree(x, y, L, p_max=p)
-        vf.set_tuning(tile=64, waves=1)
+        vf.set_tuning(tile=64, waves=1, m2l=2)
         tb = vf.Tree(x, y, L, p_max=p)
-        vf.set_tuning(tile=32, waves=2)  # neither tree follows later settings
-        assert ta.tuning() == {"tile": 16, "waves": 8}
-        assert tb.tuning() == {"tile": 64, "waves": 1}
+        vf.set_tuning(tile=32, waves=2, m2l=1)  # neither tree follows later settings
+        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0}
+        assert tb.tuning() == {"tile": 64, "waves": 1, "m2l": 2}
         r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L)
         for t in (ta, tb, ta):
             u, v = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
             assert rel_err(u, v, r.u, r.v)[0] < 1e-12
         ta.rebuild(x, y)  # a rebuild keeps the tree's shape
-        assert ta.tuning() == {"tile": 16, "waves": 8}
+        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0}
         ta.close(); tb.close()
     finally:
-        vf.set_tuning(tile=old["tile"], waves=old["waves"])
+        vf.set_tuning(tile=old["tile"], waves=old["waves"], m2l=old["m2l"])
 
 
 def _nonfinite(vf, fn):

@@ -181,3 +181,35 @@ def test_high_order_shifts_in_fp64(vf, prec_name, p, levels):
         t.velocity(g, P.sigma, 16, vf.FP32)
         assert not np.array_equal(host(t.expansions(0, levels, 16)), m16)
     t.close()
+
+
+@pytest.mark.parametrize("p,levels", [(3, 2), (8, 5), (12, 7), (14, 6), (16, 8)])
+def test_m2l_tile_variants_agree(vf, p, levels):
+    """The FP32 matrix-core M2L tiles (operands in registers; sources staged in
+    LDS with 4 or 8 waves) give the same local expansions up to float32
+    summation order, every level (tiles of one row and of several class rows,
+    levels 2 .. 8), and the float64 locals within 1e-5 of each level's
+    largest coefficient."""
+    P = W.clusters(60000, seed=71, n_clusters=5, sigma=0.003)
+    print_case("m2l_tiles", p=p, levels=levels)
+    old = vf.get_tuning()
+    x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
+    les = {}
+    try:
+        for mode in (0, 1, 2):
+            vf.set_tuning(m2l=mode)
+            t = vf.Tree(x, y, levels, p_max=p)
+            assert t.tuning()["m2l"] == mode
+            t.velocity(g, P.sigma, p, vf.FP32, parts=vf.PART_FAR)
+            les[mode] = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+            if mode == 0:
+                t.velocity(g, P.sigma, p, vf.FP64, parts=vf.PART_FAR)
+                les[64] = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
+            t.close()
+    finally:
+        vf.set_tuning(m2l=old["m2l"])
+    for mode in (1, 2):
+        for a, b, c in zip(les[mode], les[0], les[64]):
+            scale = np.max(np.abs(c))
+            assert np.max(np.abs(a - b)) <= 2e-6 * scale
+            assert np.max(np.abs(a - c)) <= 1e-5 * scale
