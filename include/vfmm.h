@@ -360,50 +360,59 @@ vfmm_status_t vfmm_particle_stats(const double* x, const double* y, const double
                                   int64_t n, void* scratch, size_t scratch_bytes, double* stats,
                                   void* stream);
 
-/* Host function: the 10 selector features of (p, levels) for particles with
- * these statistics (out[10], host): p, L, log2 N, log2 N - 2L,
- * log2(leaf side / sigma), log2(sigma / h) with h = S / sqrt(N), mean Gamma /
+/* Host function: the 10 selector features of (p, levels, near_radius) for
+ * particles with these statistics (out[10], host): p, L, log2 N, log2 N - 2L,
+ * log2(max(w_L, a) / sigma) (w_L the leaf side; a the near radius of the
+ * distance cut-off clamped to VFMM_NEAR_RINGS_MAX w_L, 6 sigma for
+ * VFMM_NEAR_RADIUS_AUTO, none for 0: the distance below which every pair uses
+ * the regularised kernel), log2(sigma / h) with h = S / sqrt(N), mean Gamma /
  * rms Gamma, log10(sum |Gamma| / max |Gamma|), std x / S, std y / S, where S is
  * the root side of vfmm_build_tree's bounding square. */
 vfmm_status_t vfmm_selector_features(const double* stats, int64_t n, double sigma, int32_t p,
-                                     int32_t levels, float* out);
+                                     int32_t levels, double near_radius, float* out);
 
-/* Chooses (p, levels) for an FP32 evaluation of these particles with max error
- * <= tol: candidates p = 4..20 and L = 2..min(10, level with ~4 particles per
- * leaf); the network (params, device; bf16) predicts log10 of each
- * candidate's error from its standardised features (feat_mean, feat_std: host,
- * 10 each); among those with prediction + margin <= log10(tol) the one with the
- * least modelled cost (near-field pairs counted from the leaf occupancy,
- * expansion and translation work) is returned.  If none qualifies:
- * p = 20, L = deepest level with leaf side >= 8 sigma, *used_fallback = 1.
+/* Chooses (p, levels, near radius) for an FP32 evaluation of these particles
+ * with max error <= tol: candidates p = 4..20, L = 2..min(10, level with ~4
+ * particles per leaf) and near radius 0 (the paper's split),
+ * VFMM_NEAR_RADIUS_AUTO or sigma sqrt(2 ln(1/tol)) (the distance cut-off, only
+ * where VFMM_NEAR_RINGS_MAX leaf sides reach 6 sigma); the network (params,
+ * device; bf16) predicts log10 of each candidate's error from its standardised
+ * features (feat_mean, feat_std: host, 10 each); among those with prediction +
+ * margin <= log10(tol) the one with the least modelled cost (near-field and
+ * ring pairs counted from the leaf occupancy, expansion and translation work)
+ * is returned.  If none qualifies: p = 20, L = deepest level with leaf side
+ * >= 8 sigma, radius 0, *used_fallback = 1.
  * Outputs are host pointers; the call synchronises `stream`.
  * scratch: device, vfmm_select_scratch_bytes(n) bytes. */
 vfmm_status_t vfmm_select_params(const double* x, const double* y, const double* gamma, int64_t n,
                                  double sigma, double tol, const float* params,
                                  const float* feat_mean, const float* feat_std, double margin,
                                  void* scratch, size_t scratch_bytes, int32_t* p, int32_t* levels,
-                                 double* predicted_log10, int32_t* used_fallback, void* stream);
+                                 double* near_radius, double* predicted_log10,
+                                 int32_t* used_fallback, void* stream);
 
 /* Selection with audit (Section 5: the error of an evaluation measured against
  * the direct sum, eq. 7, on sampled targets and normalised by the maximum
  * velocity, Section 5.1).  Steps:
- *   1. the network's choice (vfmm_select_params);
- *   2. with VFMM_SELECT_AUDIT: that (p, L) evaluated in FP32 at all particles
+ *   1. the network's choice (vfmm_select_params; its near radius is used
+ *      only with VFMM_SELECT_CUTOFF, else the paper's split);
+ *   2. with VFMM_SELECT_AUDIT: that (p, L, radius) evaluated in FP32 at all particles
  *      and its e_max taken on the n_audit targets (device int64 particle
  *      indices) against (u_ref, v_ref) (device, n_audit each; NULL = the FP64
  *      direct sum there, computed now).  The choice passes if
  *      e_max <= slack * tol (a NaN or infinite error fails).  While it fails, p
- *      is raised by 2 (up to 20) at the same L.  If p = 20 still fails, the
+ *      is raised by 2 (up to 20) at the same L and radius.  If p = 20 still fails, the
  *      conservative choice (p = 20, deepest L <= max_levels with leaf side
  *      >= 8 sigma) is evaluated in FP64 and returned (used_fallback = 1);
- *   3. with VFMM_SELECT_CUTOFF as well, for a passing FP32 choice: the same p
- *      one and two levels deeper (if <= max_levels, with at most about four
- *      particles per leaf and leaf side >= 6 sigma / VFMM_NEAR_RINGS_MAX) with
- *      the distance cut-off of the near field (Section 4.1's distance a) at
- *      two radii, VFMM_NEAR_RADIUS_AUTO and sigma sqrt(2 ln(1/tol)) (where one
- *      pair's kernel difference falls to the tolerance), each audited; the
- *      passing ones and the choice of step 2 are timed (median of time_reps
- *      tree rebuild + evaluation runs between HIP events on `stream`) and the
+ *   3. with VFMM_SELECT_CUTOFF as well, for a passing FP32 choice: its
+ *      neighbours, the same p at levels L - 1 .. L + 1 (>= 2, <= max_levels,
+ *      at most about four particles per leaf), each with the paper's split and
+ *      with the distance cut-off of the near field (Section 4.1's distance a)
+ *      at VFMM_NEAR_RADIUS_AUTO and at sigma sqrt(2 ln(1/tol)) (where one
+ *      pair's kernel difference falls to the tolerance; the cut-off only where
+ *      VFMM_NEAR_RINGS_MAX leaf sides reach 6 sigma), each audited; the passing
+ *      ones and the choice of step 2 are timed (median of time_reps tree
+ *      rebuild + evaluation runs between HIP events on `stream`) and the
  *      fastest is returned.
  * Every evaluation is recorded in out->steps (at most VFMM_SELECT_TRAIL_MAX).
  *   params, feat_mean, feat_std, margin: as in vfmm_select_params.
@@ -434,6 +443,7 @@ typedef struct vfmm_selection {
   double near_radius;
   int32_t used_fallback;
   int32_t network_p, network_levels, network_fallback;
+  double network_radius;   /* the network's near radius (0 without VFMM_SELECT_CUTOFF) */
   double predicted_log10;  /* the network's prediction for its choice (NaN for its fallback) */
   double audit_emax;       /* audited e_max of the returned choice (NaN without audit) */
   int32_t n_steps;
@@ -558,9 +568,9 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
  *   VFMM_TUNE_P2P_WAVES: waves per workgroup of the near-field launch: 1, 2, 4, 8.
  *   VFMM_TUNE_M2L_TILE : float32 matrix-core M2L for p <= 16: 0 = a 32-box tile
  *                        per workgroup of 4 waves with the operands loaded into
- *                        registers one offset ahead; 1 / 2 = the tile's source
- *                        multipoles first staged in LDS (coalesced row loads),
- *                        4 / 8 waves per workgroup (default 1).
+ *                        registers one offset ahead (default); 1 / 2 = the
+ *                        tile's source multipoles first staged in LDS
+ *                        (coalesced row loads), 4 / 8 waves per workgroup.
  * Results do not depend on the settings beyond float32 summation order. */
 #define VFMM_TUNE_P2P_TILE 1
 #define VFMM_TUNE_P2P_WAVES 2

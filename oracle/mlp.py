@@ -11,7 +11,12 @@ and root side S:
     f1 = L
     f2 = log2 N
     f3 = log2 N - 2 L                      (log2 of the mean particles per leaf)
-    f4 = log2((S / 2^L) / sigma)           (leaf side over core size)
+    f4 = log2(max(w_L, a) / sigma)         (the distance below which every pair is
+                                            summed with the regularised kernel, over
+                                            the core size: the leaf side w_L = S / 2^L,
+                                            or the near radius a of the distance
+                                            cut-off, a = min(radius, 4 w_L), if larger;
+                                            radius < 0 stands for 6 sigma)
     f5 = log2(sigma / h),  h = S / sqrt(N)
     f6 = mean(Gamma) / rms(Gamma)
     f7 = log10(sum |Gamma| / max |Gamma|)
@@ -112,7 +117,18 @@ def init_params(seed=0):
     return pack(d)
 
 
-def features(x, y, gamma, sigma, p, levels, side):
+def near_distance(side, levels, sigma, radius=0.0):
+    """max(w_L, a): w_L the leaf side, a the near radius clamped to 4 w_L
+    (radius < 0: 6 sigma, the distance beyond which the two kernels agree in
+    float32; 0: the paper's split, no cut-off)."""
+    w = side / 2 ** levels
+    if radius == 0.0:
+        return w
+    a = 6.0 * sigma if radius < 0 else radius
+    return max(w, min(a, 4.0 * w))
+
+
+def features(x, y, gamma, sigma, p, levels, side, radius=0.0):
     """The 10 selector features (see module docstring)."""
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64); g = np.asarray(gamma, np.float64)
     n = len(x)
@@ -121,7 +137,7 @@ def features(x, y, gamma, sigma, p, levels, side):
     amax = float(np.max(np.abs(g)))
     return np.array([
         float(p), float(levels), math.log2(n), math.log2(n) - 2 * levels,
-        math.log2(side / 2 ** levels / sigma), math.log2(sigma / h),
+        math.log2(near_distance(side, levels, sigma, radius) / sigma), math.log2(sigma / h),
         float(np.mean(g)) / rms if rms > 0 else 0.0,
         math.log10(float(np.sum(np.abs(g))) / amax) if amax > 0 else 0.0,
         float(np.std(x)) / side, float(np.std(y)) / side,

@@ -51,6 +51,18 @@ vfmm_status_t sfail(vfmm_status_t s, const char* fmt, ...) {
 
 inline size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// max(w_L, a): the distance below which every pair is summed with the
+// regularised kernel, w_L the leaf side and a the near radius of the distance
+// cut-off clamped to VFMM_NEAR_RINGS_MAX w_L (radius < 0: 6 sigma, the
+// automatic radius of a float32 evaluation; 0: the paper's split).
+double near_distance(double S, int levels, double sigma, double radius) {
+  const double w = S / std::ldexp(1.0, levels);
+  if (radius == 0.0) return w;
+  const double a = radius < 0.0 ? 6.0 * sigma : radius;
+  const double ac = std::fmin(a, VFMM_NEAR_RINGS_MAX * w);
+  return std::fmax(w, ac);
+}
+
 constexpr int kHistMax = 10;   // finest level of the occupancy histogram
 constexpr int kPMin = 4, kPMax = 20;
 
@@ -60,9 +72,13 @@ int hist_level(int64_t n) {
   return l;
 }
 
+// Near-radius options of the candidates: the paper's split, the automatic
+// radius and the radius at which one pair's kernel difference equals tol.
+constexpr int kNRadii = 3;
+
 size_t select_scratch(int64_t n) {
   const int lh = hist_level(n);
-  const int ncand = (kPMax - kPMin + 1) * (lh - 1);
+  const int ncand = (kPMax - kPMin + 1) * (lh - 1) * kNRadii;
   return a256(size_t(kReduceBlocks) * 12 * 8) + a256(12 * 8) +
          a256((size_t(1) << (2 * lh)) * 4) + a256(size_t(ncand) * 10 * 4) + a256(size_t(ncand) * 4);
 }
@@ -72,8 +88,9 @@ double root_side(const double* st) {
   return ext > 0.0 ? ext * (1.0 + 0x1p-20) : 1.0;
 }
 
-// pairs(L) = sum over leaves of n_b * (sum over its 3 x 3 local list of n_s)
-double near_pairs(const std::vector<double>& c, int lev) {
+// pairs(L, d) = sum over leaves of n_b * (sum of n_s over the leaves at
+// Chebyshev distance <= d): d = 1 is the 3 x 3 local list.
+double near_pairs(const std::vector<double>& c, int lev, int d = 1) {
   const int m = 1 << lev;
   double s = 0.0;
   for (int iy = 0; iy < m; ++iy)
@@ -81,8 +98,8 @@ double near_pairs(const std::vector<double>& c, int lev) {
       const double nb = c[size_t(iy) * m + ix];
       if (nb == 0.0) continue;
       double src = 0.0;
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
+      for (int dy = -d; dy <= d; ++dy)
+        for (int dx = -d; dx <= d; ++dx) {
           const int jx = ix + dx, jy = iy + dy;
           if (jx >= 0 && jx < m && jy >= 0 && jy < m) src += c[size_t(jy) * m + jx];
         }
@@ -154,7 +171,7 @@ vfmm_status_t vfmm_particle_stats(const double* x, const double* y, const double
 }
 
 vfmm_status_t vfmm_selector_features(const double* st, int64_t n, double sigma, int32_t p,
-                                     int32_t levels, float* out) {
+                                     int32_t levels, double near_radius, float* out) {
   if (!st || !out) return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
   if (n < 1 || !(sigma > 0.0)) return sfail(VFMM_ERR_INVALID_ARG, "n >= 1 and sigma > 0 required");
   const double dn = double(n);
@@ -169,7 +186,7 @@ vfmm_status_t vfmm_selector_features(const double* st, int64_t n, double sigma, 
   out[1] = float(levels);
   out[2] = float(lg);
   out[3] = float(lg - 2.0 * levels);
-  out[4] = float(std::log2(S / std::ldexp(1.0, levels) / sigma));
+  out[4] = float(std::log2(near_distance(S, levels, sigma, near_radius) / sigma));
   out[5] = float(std::log2(sigma / h));
   out[6] = float(rms > 0.0 ? mean_g / rms : 0.0);
   out[7] = float(st[7] > 0.0 ? std::log10(st[6] / st[7]) : 0.0);
@@ -182,10 +199,10 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
                                  double sigma, double tol, const float* params,
                                  const float* feat_mean, const float* feat_std, double margin,
                                  void* scratch, size_t scratch_bytes, int32_t* p_out,
-                                 int32_t* levels_out, double* pred_out, int32_t* fallback_out,
-                                 void* stream) {
+                                 int32_t* levels_out, double* radius_out, double* pred_out,
+                                 int32_t* fallback_out, void* stream) {
   if (!x || !y || !gamma || !params || !feat_mean || !feat_std || !scratch || !p_out ||
-      !levels_out || !pred_out || !fallback_out)
+      !levels_out || !radius_out || !pred_out || !fallback_out)
     return sfail(VFMM_ERR_INVALID_ARG, "null pointer");
   if (n < 1 || !(sigma > 0.0) || !std::isfinite(sigma)) return sfail(VFMM_ERR_INVALID_ARG, "bad n or sigma");
   if (!(tol > 0.0) || !(margin >= 0.0)) return sfail(VFMM_ERR_INVALID_ARG, "tol > 0 and margin >= 0 required");
@@ -197,7 +214,7 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
   double* part = reinterpret_cast<double*>(s + off); off += a256(size_t(kReduceBlocks) * 12 * 8);
   double* sout = reinterpret_cast<double*>(s + off); off += a256(12 * 8);
   uint32_t* counts = reinterpret_cast<uint32_t*>(s + off); off += a256((size_t(1) << (2 * lh)) * 4);
-  const int ncand = (kPMax - kPMin + 1) * (lh - 1);
+  const int ncand = (kPMax - kPMin + 1) * (lh - 1) * kNRadii;
   float* xd = reinterpret_cast<float*>(s + off); off += a256(size_t(ncand) * 10 * 4);
   float* yd = reinterpret_cast<float*>(s + off);
 
@@ -225,18 +242,26 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
     for (int iy = 0; iy < 2 * m; ++iy)
       for (int ix = 0; ix < 2 * m; ++ix) occ[l][size_t(iy >> 1) * m + (ix >> 1)] += occ[l + 1][size_t(iy) * 2 * m + ix];
   }
-  // candidates and their features (z-scored)
+  // candidates (p, L, near radius) and their features (z-scored).  The
+  // distance cut-off (Section 4.1's distance a) is a candidate where four leaf
+  // sides reach the automatic radius (6 sigma), so that its clamp does not cut it.
+  const double radii[kNRadii] = {0.0, VFMM_NEAR_RADIUS_AUTO,
+                                 sigma * std::sqrt(2.0 * std::log(1.0 / tol))};
   std::vector<float> X(size_t(ncand) * 10);
-  std::vector<int> cp(ncand), cl(ncand);
+  std::vector<int> cp(ncand), cl(ncand), cr(ncand);
+  std::vector<char> cok(ncand);
   int c = 0;
   for (int L = 2; L <= lh; ++L)
-    for (int p = kPMin; p <= kPMax; ++p, ++c) {
-      float f[10];
-      vfmm_selector_features(stats, n, sigma, p, L, f);
-      for (int k = 0; k < 10; ++k) X[size_t(c) * 10 + k] = (f[k] - feat_mean[k]) / feat_std[k];
-      cp[c] = p;
-      cl[c] = L;
-    }
+    for (int r = 0; r < kNRadii; ++r)
+      for (int p = kPMin; p <= kPMax; ++p, ++c) {
+        float f[10];
+        vfmm_selector_features(stats, n, sigma, p, L, radii[r], f);
+        for (int k = 0; k < 10; ++k) X[size_t(c) * 10 + k] = (f[k] - feat_mean[k]) / feat_std[k];
+        cp[c] = p;
+        cl[c] = L;
+        cr[c] = r;
+        cok[c] = r == 0 || VFMM_NEAR_RINGS_MAX * S / std::ldexp(1.0, L) >= 6.0 * sigma;
+      }
   std::vector<float> pred(ncand);
   e = hipMemcpyAsync(xd, X.data(), X.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_mlp_forward(params, true, xd, ncand, yd, st);
@@ -244,17 +269,35 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return sfail(hip_status(e), "select network: %s", hipGetErrorString(e));
 
-  // cost model (seconds on one MI355X, FP32 evaluation): near-field pairs,
-  // per-particle expansion work, per-box translations, per-level launches
+  // cost model (seconds on one MI355X, FP32 evaluation): local-list pairs;
+  // with the cut-off, the pairs of the ring leaves weighted by f^2, f the share
+  // of the rings within the radius of the leaf (a ring chunk farther than the
+  // radius from the target tile is skipped whole, a closer one costs its
+  // tests and the pairs that pass; fitted to the near field measured at
+  // L = 7 and 8 on 2^20 clustered particles, within about 30 %); per-particle
+  // expansion work, per-box translations, per-level launches
   const double lt = std::log10(tol);
   double best = INFINITY;
   int bi = -1;
+  std::vector<double> local(lh + 1, -1.0);
   for (int k = 0; k < ncand; ++k) {
-    if (double(pred[k]) + margin > lt) continue;
+    if (!cok[k] || double(pred[k]) + margin > lt) continue;
     const int L = cl[k], p = cp[k];
     double boxes = 0.0;
     for (int l = 2; l <= L; ++l) boxes += std::ldexp(1.0, 2 * l);
-    const double cost = 3.1e-13 * near_pairs(occ[L], L) + 2.0e-11 * double(n) * p +
+    if (local[L] < 0.0) local[L] = near_pairs(occ[L], L);
+    double ring = 0.0;
+    if (cr[k] > 0) {
+      const double w = S / std::ldexp(1.0, L);
+      const double a = std::fmin(radii[cr[k]] < 0.0 ? 6.0 * sigma : radii[cr[k]],
+                                 VFMM_NEAR_RINGS_MAX * w);
+      int d = 2;
+      while (d < VFMM_NEAR_RINGS_MAX && d * w < a) ++d;
+      const double f = std::fmin(1.0, std::fmax(0.0, ((w + 2.0 * a) * (w + 2.0 * a) - 9.0 * w * w) /
+                                                         (double((2 * d + 1) * (2 * d + 1) - 9) * w * w)));
+      ring = (near_pairs(occ[L], L, d) - local[L]) * f * f;
+    }
+    const double cost = 3.1e-13 * local[L] + 6.4e-13 * ring + 2.0e-11 * double(n) * p +
                         1.2e-10 * boxes * p * p + 2.0e-5 * L;
     if (cost < best) {
       best = cost;
@@ -264,6 +307,7 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
   if (bi >= 0) {
     *p_out = cp[bi];
     *levels_out = cl[bi];
+    *radius_out = radii[cr[bi]];
     *pred_out = double(pred[bi]);
     *fallback_out = 0;
   } else {
@@ -273,6 +317,7 @@ static vfmm_status_t vfmm_select_params_impl(const double* x, const double* y, c
       ++L;
     *p_out = 20;
     *levels_out = L;
+    *radius_out = 0.0;
     *pred_out = NAN;
     *fallback_out = 1;
   }
@@ -479,19 +524,22 @@ static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y
 
   // the network's choice
   int32_t p = 0, L = 0, fb = 0;
-  double pred = 0.0;
+  double pred = 0.0, rad = 0.0;
   vfmm_status_t s = vfmm_select_params(x, y, gamma, n, sigma, tol, params, feat_mean, feat_std,
-                                       margin, w.sel, w.sel_bytes, &p, &L, &pred, &fb, stream);
+                                       margin, w.sel, w.sel_bytes, &p, &L, &rad, &pred, &fb,
+                                       stream);
   if (s) return s;
   if (L > max_levels) L = max_levels;
+  if (!(flags & VFMM_SELECT_CUTOFF)) rad = 0.0;
   out->network_p = p;
   out->network_levels = L;
+  out->network_radius = rad;
   out->network_fallback = fb;
   out->predicted_log10 = pred;
   out->p = p;
   out->levels = L;
   out->precision = VFMM_FP32;
-  out->near_radius = 0.0;
+  out->near_radius = rad;
   out->used_fallback = fb;
   out->audit_emax = NAN;
   if (!audit) return VFMM_OK;
@@ -520,14 +568,14 @@ static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y
   const double bar = slack * tol;
   auto pass = [&](double e) { return e <= bar; };  // NaN or infinity fails
 
-  // FP32 at the network's (p, L); p raised by 2 (up to 20) while it fails
+  // FP32 at the network's (p, L, radius); p raised by 2 (up to 20) while it fails
   double e = 0.0, ms = 0.0;
-  if ((s = a.run(p, L, VFMM_FP32, 0.0, false, e, ms))) return s;
-  record(out, p, L, VFMM_FP32, 0.0, e, ms);
+  if ((s = a.run(p, L, VFMM_FP32, rad, false, e, ms))) return s;
+  record(out, p, L, VFMM_FP32, rad, e, ms);
   while (!pass(e) && p < kPMax) {
     p = p + 2 < kPMax ? p + 2 : kPMax;
-    if ((s = a.run(p, L, VFMM_FP32, 0.0, false, e, ms))) return s;
-    record(out, p, L, VFMM_FP32, 0.0, e, ms);
+    if ((s = a.run(p, L, VFMM_FP32, rad, false, e, ms))) return s;
+    record(out, p, L, VFMM_FP32, rad, e, ms);
   }
   out->p = p;
   out->audit_emax = e;
@@ -551,36 +599,44 @@ static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y
   }
   if (!(flags & VFMM_SELECT_CUTOFF)) return VFMM_OK;
 
-  // Section 4.1's distance a as a parameter: the same p one or two levels
-  // deeper, with far pairs closer than a on the regularised kernel, where the
-  // clamp at VFMM_NEAR_RINGS_MAX leaf sides does not cut the automatic radius
-  // (6 sigma in FP32); radii: the automatic one and sigma sqrt(2 ln(1/tol)),
-  // at which one pair's kernel difference falls to the tolerance.  Passing
-  // candidates are timed against the paper's split at L; the fastest is kept.
-  int deeper[2], nd = 0;
-  for (int LL = L + 1; LL <= L + 2; ++LL)
-    if (LL <= max_levels && S / std::ldexp(1.0, LL) >= 6.0 * sigma / VFMM_NEAR_RINGS_MAX &&
-        (int64_t(1) << (2 * LL)) <= 4 * n)
-      deeper[nd++] = LL;
-  if (nd == 0) return VFMM_OK;
-  double e0 = 0.0, ms0 = 0.0;
-  if ((s = a.run(p, L, VFMM_FP32, 0.0, true, e0, ms0))) return s;
-  out->steps[out->n_steps - 1].ms = ms0;  // the accepted step, now timed
-  double best_ms = ms0, best_e = e, best_r = 0.0;
-  int best_L = L;
-  const double radii[2] = {VFMM_NEAR_RADIUS_AUTO, sigma * std::sqrt(2.0 * std::log(1.0 / tol))};
-  for (int k = 0; k < nd; ++k)
-    for (double rad : radii) {
-      double ec = 0.0, msc = 0.0;
-      if ((s = a.run(p, deeper[k], VFMM_FP32, rad, true, ec, msc))) return s;
-      record(out, p, deeper[k], VFMM_FP32, rad, ec, msc);
-      if (pass(ec) && msc < best_ms) {
-        best_ms = msc;
-        best_e = ec;
-        best_r = rad;
-        best_L = deeper[k];
-      }
+  // Timed comparison with the neighbours of the accepted choice: the same p
+  // at levels L - 1 .. L + 1, each with the paper's split and with the
+  // distance cut-off (Section 4.1's distance a) at the automatic radius and
+  // at sigma sqrt(2 ln(1/tol)), where one pair's kernel difference falls to
+  // the tolerance; the cut-off only where the clamp at VFMM_NEAR_RINGS_MAX
+  // leaf sides leaves 6 sigma uncut.  Each is audited; the passing ones are
+  // timed and the fastest is kept.
+  const double radii3[3] = {0.0, VFMM_NEAR_RADIUS_AUTO,
+                            sigma * std::sqrt(2.0 * std::log(1.0 / tol))};
+  int cand_L[9];
+  double cand_r[9];
+  int nc = 0;
+  for (int LL = L - 1; LL <= L + 1; ++LL) {
+    if (LL < 2 || LL > max_levels || (int64_t(1) << (2 * LL)) > 4 * n) continue;
+    for (double r : radii3) {
+      if (LL == L && r == rad) continue;
+      if (r != 0.0 && VFMM_NEAR_RINGS_MAX * S / std::ldexp(1.0, LL) < 6.0 * sigma) continue;
+      cand_L[nc] = LL;
+      cand_r[nc++] = r;
     }
+  }
+  if (nc == 0) return VFMM_OK;
+  double e0 = 0.0, ms0 = 0.0;
+  if ((s = a.run(p, L, VFMM_FP32, rad, true, e0, ms0))) return s;
+  out->steps[out->n_steps - 1].ms = ms0;  // the accepted step, now timed
+  double best_ms = ms0, best_e = e, best_r = rad;
+  int best_L = L;
+  for (int k = 0; k < nc; ++k) {
+    double ec = 0.0, msc = 0.0;
+    if ((s = a.run(p, cand_L[k], VFMM_FP32, cand_r[k], true, ec, msc))) return s;
+    record(out, p, cand_L[k], VFMM_FP32, cand_r[k], ec, msc);
+    if (pass(ec) && msc < best_ms) {
+      best_ms = msc;
+      best_e = ec;
+      best_r = cand_r[k];
+      best_L = cand_L[k];
+    }
+  }
   out->levels = best_L;
   out->near_radius = best_r;
   out->audit_emax = best_e;
@@ -593,11 +649,12 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
                                  double sigma, double tol, const float* params,
                                  const float* feat_mean, const float* feat_std, double margin,
                                  void* scratch, size_t scratch_bytes, int32_t* p_out,
-                                 int32_t* levels_out, double* pred_out, int32_t* fallback_out,
-                                 void* stream) {
+                                 int32_t* levels_out, double* radius_out, double* pred_out,
+                                 int32_t* fallback_out, void* stream) {
   try {
     return vfmm_select_params_impl(x, y, gamma, n, sigma, tol, params, feat_mean, feat_std, margin, scratch,
-                                   scratch_bytes, p_out, levels_out, pred_out, fallback_out, stream);
+                                   scratch_bytes, p_out, levels_out, radius_out, pred_out,
+                                   fallback_out, stream);
   } catch (const std::bad_alloc&) {
     return sfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_select_params: host allocation failed");
   }

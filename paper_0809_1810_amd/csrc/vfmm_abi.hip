@@ -79,7 +79,7 @@ void set_last_error(const char* msg) { g_err = msg; }
 
 std::atomic<int> g_tile{kTile};
 std::atomic<int> g_waves{4};
-std::atomic<int> g_m2l_tile{1};
+std::atomic<int> g_m2l_tile{0};
 int tuning_tile() { return g_tile.load(); }
 int tuning_waves() { return g_waves.load(); }
 int tuning_m2l_tile() { return g_m2l_tile.load(); }

@@ -14,7 +14,9 @@ when the audit fails.
 Every computation runs in the HIP library; this file only drives it.
 
     python -m paper_0809_1810_amd.selector generate --instances 400 --out data.npz
-    python -m paper_0809_1810_amd.selector train --data data.npz --out weights.npz
+    python -m paper_0809_1810_amd.selector generate --instances 160 --seed 2 --nmax-log2 22 \
+        --cutoff --out data_cutoff.npz
+    python -m paper_0809_1810_amd.selector train --data data.npz,data_cutoff.npz --out weights.npz
 """
 from __future__ import annotations
 
@@ -77,8 +79,17 @@ def random_instance(rng, n_range=(2 ** 11, 2 ** 18)):
 
 # ----------------------------------------------------------------- data generation
 
-def evaluate_grid(P, p_grid=P_GRID, max_levels=9, n_targets=2048, seed=0):
-    """Rows (features, log10 e_max, p, L, ms) of FP32 runs of the library on P."""
+def resolve_radius(r, sigma, tol=1e-6):
+    """Near radius of a grid entry: 0 (the paper's split), V.NEAR_RADIUS_AUTO, or
+    "tol" for sigma sqrt(2 ln(1/tol)), where one pair's kernel difference
+    equals tol."""
+    return sigma * math.sqrt(2.0 * math.log(1.0 / tol)) if r == "tol" else float(r)
+
+
+def evaluate_grid(P, p_grid=P_GRID, max_levels=9, n_targets=2048, seed=0, radii=(0.0,)):
+    """Rows (features, log10 e_max, p, L, radius, ms) of FP32 runs of the library
+    on P, for every near radius of ``radii`` (see resolve_radius) at the levels
+    where NEAR_RINGS_MAX leaf sides reach 6 sigma."""
     torch = _torch()
     x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
     g = torch.from_numpy(P.gamma).cuda()
@@ -91,33 +102,42 @@ def evaluate_grid(P, p_grid=P_GRID, max_levels=9, n_targets=2048, seed=0):
         tg = torch.from_numpy(np.sort(rng.choice(n, n_targets, replace=False)).astype(np.int64)).cuda()
         ur, vr = V.direct_velocity(x, y, g, P.sigma, targets=tg)
     stats = V.particle_stats(x, y, g)
+    side = max(stats[9] - stats[8], stats[11] - stats[10]) * (1.0 + 2.0 ** -20)
     rows = []
     lmax = min(max_levels, int(math.log2(4 * n) // 2))
     for L in range(2, lmax + 1):
         tree = V.Tree(x, y, L, p_max=max(p_grid))
-        for p in p_grid:
-            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            u, v = tree.velocity(g, P.sigma, p, V.FP32)
-            e1.record()
-            if tg is not None:
-                u = u[tg].contiguous(); v = v[tg].contiguous()
-            emax, _, _ = V.error_metrics(u, v, ur, vr)
-            f = V.selector_features(stats, n, P.sigma, p, L)
-            rows.append((f, math.log10(max(emax, 10 ** LOG10_FLOOR)), p, L, e0.elapsed_time(e1)))
+        for rr in radii:
+            r = resolve_radius(rr, P.sigma)
+            if r != 0.0 and V.NEAR_RINGS_MAX * side / 2 ** L < 6.0 * P.sigma:
+                continue
+            tree.set_near_radius(r)
+            for p in p_grid:
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                u, v = tree.velocity(g, P.sigma, p, V.FP32)
+                e1.record()
+                if tg is not None:
+                    u = u[tg].contiguous(); v = v[tg].contiguous()
+                emax, _, _ = V.error_metrics(u, v, ur, vr)
+                f = V.selector_features(stats, n, P.sigma, p, L, r)
+                rows.append((f, math.log10(max(emax, 10 ** LOG10_FLOOR)), p, L, r,
+                             e0.elapsed_time(e1)))
         tree.close()
     return rows
 
 
-def generate(n_instances, seed, out, n_range=(2 ** 11, 2 ** 18), log=print):
+def generate(n_instances, seed, out, n_range=(2 ** 11, 2 ** 18), log=print, radii=(0.0,)):
+    """Training rows of n_instances seeded instances; meta holds (instance, N,
+    p, L, ms, radius) per row."""
     rng = np.random.default_rng(seed)
     F, Y, meta = [], [], []
     t0 = time.time()
     for i in range(n_instances):
         P = random_instance(rng, n_range)
-        for f, lg, p, L, ms in evaluate_grid(P, seed=i):
-            F.append(f); Y.append(lg); meta.append((i, P.n, p, L, ms))
-        if (i + 1) % 20 == 0:
+        for f, lg, p, L, r, ms in evaluate_grid(P, seed=i, radii=radii):
+            F.append(f); Y.append(lg); meta.append((i, P.n, p, L, ms, r))
+        if (i + 1) % 5 == 0:
             log(f"[generate] {i + 1}/{n_instances} instances, {len(Y)} rows, {time.time() - t0:.1f} s")
     np.savez_compressed(out, features=np.array(F, np.float32), target=np.array(Y, np.float32),
                         meta=np.array(meta, np.float64), seed=seed)
@@ -134,12 +154,18 @@ def _he_init(seed):
     return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, np.zeros(1)]).astype(np.float32)
 
 
-def train(data_path, out, epochs=300, batch=256, lr=3e-3, seed=0, val_frac=0.2, log=print):
-    """Trains the selector on the GPU; writes params, feature mean/std and metrics."""
+def train(data_paths, out, epochs=300, batch=256, lr=3e-3, seed=0, val_frac=0.2, log=print):
+    """Trains the selector on the GPU on the rows of one or more data files
+    (their instances kept apart); writes params, feature mean/std and metrics."""
     torch = _torch()
-    d = np.load(data_path)
-    F = d["features"].astype(np.float64); Y = d["target"].astype(np.float64); meta = d["meta"]
-    inst = meta[:, 0].astype(np.int64)
+    if isinstance(data_paths, str):
+        data_paths = data_paths.split(",")
+    Fs, Ys, insts = [], [], []
+    for k, path in enumerate(data_paths):
+        d = np.load(path)
+        Fs.append(d["features"].astype(np.float64)); Ys.append(d["target"].astype(np.float64))
+        insts.append(d["meta"][:, 0].astype(np.int64) + 1_000_000 * k)
+    F = np.concatenate(Fs); Y = np.concatenate(Ys); inst = np.concatenate(insts)
     rng = np.random.default_rng(seed)
     ids = np.unique(inst)
     val_ids = set(rng.choice(ids, max(1, int(len(ids) * val_frac)), replace=False).tolist())
@@ -231,7 +257,8 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     out = {"p": r.p, "levels": r.levels, "predicted_log10": r.predicted_log10,
            "fallback": bool(r.used_fallback), "audited": bool(audit),
            "precision": "fp64" if r.precision == V.FP64 else "fp32",
-           "radius": r.near_radius, "network_choice": [r.network_p, r.network_levels]}
+           "radius": r.near_radius,
+           "network_choice": [r.network_p, r.network_levels, r.network_radius]}
     if audit:
         trail = []
         for k in range(r.n_steps):
@@ -254,6 +281,8 @@ def main(argv=None):
     g.add_argument("--seed", type=int, default=1)
     g.add_argument("--out", required=True)
     g.add_argument("--nmax-log2", type=int, default=18)
+    g.add_argument("--cutoff", action="store_true",
+                   help="also run every grid point with the distance cut-off (both radii)")
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)
     t.add_argument("--out", default=WEIGHTS_PATH)
@@ -262,7 +291,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "generate":
         log = lambda m: print(m, flush=True)
-        rows = generate(a.instances, a.seed, a.out, (2 ** 11, 2 ** a.nmax_log2), log)
+        radii = (0.0, V.NEAR_RADIUS_AUTO, "tol") if a.cutoff else (0.0,)
+        rows = generate(a.instances, a.seed, a.out, (2 ** 11, 2 ** a.nmax_log2), log, radii)
         print(f"[generate] wrote {rows} rows to {a.out}", flush=True)
     else:
         train(a.data, a.out, epochs=a.epochs, seed=a.seed, log=lambda m: print(m, flush=True))

@@ -109,7 +109,7 @@ _SIGS = {
     "vfmm_particle_stats": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.c_size_t, C.POINTER(C.c_double), C.c_void_p]),
     "vfmm_selector_features": (C.c_int32, [C.POINTER(C.c_double), C.c_int64, C.c_double, C.c_int32,
-                                           C.c_int32, C.POINTER(C.c_float)]),
+                                           C.c_int32, C.c_double, C.POINTER(C.c_float)]),
     "vfmm_select_audit_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.c_int32,
                                                       C.POINTER(C.c_size_t)]),
     "vfmm_select_and_audit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -122,7 +122,8 @@ _SIGS = {
                                        C.c_double, C.c_void_p, C.POINTER(C.c_float),
                                        C.POINTER(C.c_float), C.c_double, C.c_void_p, C.c_size_t,
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                       C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32), C.c_void_p]),
 }
 
 NEAR_RADIUS_AUTO = -1.0
@@ -154,7 +155,8 @@ class Selection(C.Structure):
     _fields_ = [("p", C.c_int32), ("levels", C.c_int32), ("precision", C.c_int32),
                 ("near_radius", C.c_double), ("used_fallback", C.c_int32),
                 ("network_p", C.c_int32), ("network_levels", C.c_int32),
-                ("network_fallback", C.c_int32), ("predicted_log10", C.c_double),
+                ("network_fallback", C.c_int32), ("network_radius", C.c_double),
+                ("predicted_log10", C.c_double),
                 ("audit_emax", C.c_double), ("n_steps", C.c_int32),
                 ("steps", AuditStep * SELECT_TRAIL_MAX)]
 
@@ -610,16 +612,18 @@ def particle_stats(x, y, gamma):
     return list(st)
 
 
-def selector_features(stats, n, sigma, p, levels):
+def selector_features(stats, n, sigma, p, levels, radius=0.0):
+    """The ten selector features of (p, levels, near radius) (host function)."""
     st = (C.c_double * 12)(*stats)
     out = (C.c_float * N_FEATURES)()
-    _check(lib().vfmm_selector_features(st, int(n), float(sigma), int(p), int(levels), out),
-           "vfmm_selector_features")
+    _check(lib().vfmm_selector_features(st, int(n), float(sigma), int(p), int(levels),
+                                        float(radius), out), "vfmm_selector_features")
     return list(out)
 
 
 def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0.3):
-    """(p, levels, predicted log10 error, used_fallback) for an FP32 evaluation."""
+    """(p, levels, near radius, predicted log10 error, used_fallback) for an FP32
+    evaluation."""
     torch = _torch()
     for t, nme in ((x, "x"), (y, "y"), (gamma, "gamma")):
         _dev_f64(t, nme)
@@ -628,12 +632,14 @@ def select_params(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin=0
     scratch = torch.empty(int(lib().vfmm_select_scratch_bytes(n)), dtype=torch.uint8, device=x.device)
     fm = (C.c_float * N_FEATURES)(*[float(v) for v in feat_mean])
     fs = (C.c_float * N_FEATURES)(*[float(v) for v in feat_std])
-    p = C.c_int32(0); L = C.c_int32(0); pred = C.c_double(0.0); fb = C.c_int32(0)
+    p = C.c_int32(0); L = C.c_int32(0); rad = C.c_double(0.0); pred = C.c_double(0.0)
+    fb = C.c_int32(0)
     _check(lib().vfmm_select_params(x.data_ptr(), y.data_ptr(), gamma.data_ptr(), n, float(sigma),
                                     float(tol), params.data_ptr(), fm, fs, float(margin),
                                     scratch.data_ptr(), scratch.numel(), C.byref(p), C.byref(L),
-                                    C.byref(pred), C.byref(fb), _stream()), "vfmm_select_params")
-    return int(p.value), int(L.value), float(pred.value), bool(fb.value)
+                                    C.byref(rad), C.byref(pred), C.byref(fb), _stream()),
+           "vfmm_select_params")
+    return int(p.value), int(L.value), float(rad.value), float(pred.value), bool(fb.value)
 
 
 def select_and_audit(x, y, gamma, sigma, tol, params, feat_mean, feat_std, margin, targets,

@@ -149,9 +149,10 @@ def test_selector_features_host_function_matches_oracle():
           np.abs(g).sum(), np.abs(g).max(), P.x.min(), P.x.max(), P.y.min(), P.y.max()]
     side = qt.root_square(P.x, P.y)[2]
     for p, L in ((4, 2), (9, 4), (20, 8)):
-        f = vf.selector_features(st, P.n, P.sigma, p, L)
-        fr = OM.features(P.x, P.y, g, P.sigma, p, L, side)
-        assert np.allclose(f, fr, rtol=1e-6, atol=1e-6), (f, fr)
+        for radius in (0.0, -1.0, 5.26 * P.sigma, 1e3):
+            f = vf.selector_features(st, P.n, P.sigma, p, L, radius)
+            fr = OM.features(P.x, P.y, g, P.sigma, p, L, side, radius)
+            assert np.allclose(f, fr, rtol=1e-6, atol=1e-6), (radius, f, fr)
 
 
 def test_evaluation_point_calls_reject_before_device_work():

@@ -107,9 +107,10 @@ def test_particle_stats_and_features(vf):
     from oracle import quadtree as qt
     side = qt.root_square(P.x, P.y)[2]
     for p, L in ((4, 2), (12, 5), (20, 7)):
-        f = vf.selector_features(st, P.n, P.sigma, p, L)
-        fr = OM.features(P.x, P.y, P.gamma, P.sigma, p, L, side)
-        assert np.allclose(f, fr, rtol=1e-6, atol=1e-6)
+        for radius in (0.0, -1.0, 5.26 * P.sigma):
+            f = vf.selector_features(st, P.n, P.sigma, p, L, radius)
+            fr = OM.features(P.x, P.y, P.gamma, P.sigma, p, L, side, radius)
+            assert np.allclose(f, fr, rtol=1e-6, atol=1e-6)
 
 
 def _time_eval(vf, x, y, g, sigma, p, L, prec, reps=3, radius=0.0):

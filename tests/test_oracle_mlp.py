@@ -78,3 +78,22 @@ def test_features_definitions():
     assert f[6] == pytest.approx(-1.0 / math.sqrt(5.0))
     assert f[7] == pytest.approx(math.log10(32.0 / 3.0))
     assert f[8] == pytest.approx(math.sqrt(1.25) / 4.0) and f[9] == pytest.approx(math.sqrt(1.25) / 4.0)
+
+
+def test_near_distance_feature():
+    """f4 with the distance cut-off: the larger of the leaf side and the near
+    radius clamped to four leaf sides (6 sigma for the automatic radius)."""
+    c = np.arange(4) + 0.5
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    x = xx.ravel(); y = yy.ravel(); g = np.ones(16)
+    # leaf side 1.0 (L = 2 of side 4), sigma 0.25
+    f = lambda r: M.features(x, y, g, sigma=0.25, p=7, levels=2, side=4.0, radius=r)[4]
+    assert f(0.0) == pytest.approx(math.log2(1.0 / 0.25))      # paper split: w_L
+    assert f(0.5) == pytest.approx(math.log2(1.0 / 0.25))      # a < w_L
+    assert f(2.5) == pytest.approx(math.log2(2.5 / 0.25))      # w_L < a < 4 w_L
+    assert f(9.0) == pytest.approx(math.log2(4.0 / 0.25))      # clamped to 4 w_L
+    assert f(-1.0) == pytest.approx(math.log2(1.5 / 0.25))     # automatic: 6 sigma
+    # every other feature ignores the radius
+    a = M.features(x, y, g, sigma=0.25, p=7, levels=2, side=4.0, radius=2.5)
+    b = M.features(x, y, g, sigma=0.25, p=7, levels=2, side=4.0)
+    assert np.array_equal(np.delete(a, 4), np.delete(b, 4))
