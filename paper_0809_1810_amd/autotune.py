@@ -1,4 +1,4 @@
-"""Autotuner for the near-field (P2P) launch shape.
+"""Autotuner for the launch shapes of the near field (P2P) and of the M2L.
 
 Tunable shape: particles per tile T (64, 32, 16: one, two or four lanes per
 target; T is also the source-chunk size of the far-pair test, so smaller tiles
@@ -13,7 +13,14 @@ at the radius where one pair's kernel difference is 1e-6 (``cutoff_ms``), and
 ``apply_for(..., cutoff=True)`` takes the fastest of those (or, for an entry
 without them, the fastest 64-target shape of the paper's split).
 
+M2L on the matrix cores (FP32, p <= 16): the tile variants of
+VFMM_TUNE_M2L_TILE (operands in registers one offset ahead; sources staged in
+LDS with 4 or 8 waves) are timed on the M2L + L2L phase of far-only
+evaluations, and the fastest is stored per entry (``m2l_tile``, ``m2l_ms``);
+``apply_for`` sets it too (0 for an entry without it).
+
     python -m paper_0809_1810_amd.autotune --out tuning.json
+    python -m paper_0809_1810_amd.autotune --m2l-only      (add the M2L timings to the table)
 """
 from __future__ import annotations
 
@@ -32,6 +39,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tuning.json")
 TILES = (64, 32, 16)
 WAVES = (1, 2, 4, 8)
+M2L_TILES = (0, 1, 2)
 
 
 CUTOFF_TOL = 1e-6
@@ -51,6 +59,26 @@ def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5, radius=0.0):
     return ms
 
 
+def time_m2l(x, y, g, sigma, p, levels, mode, reps=10):
+    """Median M2L + L2L phase time (ms) of far-only FP32 evaluations for one M2L tile."""
+    V.set_tuning(m2l=mode)
+    t = V.Tree(x, y, levels, p_max=p)
+    t.velocity(g, sigma, p, V.FP32, parts=V.PART_FAR)
+    t.enable_timing(reps)
+    for _ in range(reps):
+        t.velocity(g, sigma, p, V.FP32, parts=V.PART_FAR)
+    ms = float(np.median([ph["m2l_l2l"] for ph in t.read_timing()]))
+    t.close()
+    V.set_tuning(m2l=0)
+    return ms
+
+
+def m2l_entry(x, y, g, sigma, p, levels):
+    res = {m: time_m2l(x, y, g, sigma, p, levels, m) for m in M2L_TILES}
+    best = min(res, key=res.get)
+    return {"m2l_tile": best, "m2l_ms": {str(k): round(v, 4) for k, v in sorted(res.items())}}
+
+
 def tune_workload(name, P, p, levels, log=print):
     import torch
     x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda(); g = torch.from_numpy(P.gamma).cuda()
@@ -68,6 +96,7 @@ def tune_workload(name, P, p, levels, log=print):
              "all_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in sorted(res.items())},
              "cutoff_radius_sigma": round(radius / P.sigma, 4),
              "cutoff_ms": {f"64x{w}": round(v, 4) for w, v in sorted(cut.items())}}
+    entry.update(m2l_entry(x, y, g, P.sigma, p, levels))
     log(f"[tune] {name} L={levels}: best tile {best[0]} waves {best[1]} {res[best]:.3f} ms "
         f"(default 64x4 {res[(64, 4)]:.3f} ms); with the cut-off 64x{cbest} {cut[cbest]:.3f} ms")
     return entry
@@ -85,6 +114,23 @@ def default_workloads():
         ("lattice_320", W.config("lattice_320"), 14, 6),
         ("uniform_64k", W.uniform(65536, seed=9, sigma=2.0 / 256 / 0.8), 12, 6),
     ]
+
+
+def tune_m2l(path=TABLE_PATH, log=print):
+    """Adds the M2L tile timings to every entry of an existing table."""
+    import torch
+    import workloads as W
+    table = json.load(open(path))
+    work = {(w[0], w[3]): w for w in default_workloads()}
+    for e in table["entries"]:
+        name, P, p, levels = work[(e["workload"], e["levels"])]
+        x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
+        g = torch.from_numpy(P.gamma).cuda()
+        e.update(m2l_entry(x, y, g, P.sigma, p, levels))
+        log(f"[tune] {name} L={levels}: M2L tile {e['m2l_tile']} {e['m2l_ms']}")
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
 
 
 def tune(out=TABLE_PATH, log=print):
@@ -115,17 +161,33 @@ def lookup(n, levels, path=TABLE_PATH, cutoff=False):
     return int(e["tile"]), int(e["waves"])
 
 
+def lookup_m2l(n, levels, path=TABLE_PATH):
+    """M2L tile of the table entry nearest in log2 particles per leaf (0 without)."""
+    try:
+        table = json.load(open(path))
+    except (OSError, ValueError):
+        return 0
+    ppl = math.log2(max(n, 1)) - 2 * levels
+    e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
+    return int(e.get("m2l_tile", 0))
+
+
 def apply_for(n, levels, path=TABLE_PATH, cutoff=False):
     tile, waves = lookup(n, levels, path, cutoff)
-    V.set_tuning(tile=tile, waves=waves)
+    V.set_tuning(tile=tile, waves=waves, m2l=lookup_m2l(n, levels, path))
     return tile, waves
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--m2l-only", action="store_true",
+                    help="time the M2L tiles and add them to the existing table")
     a = ap.parse_args(argv)
-    tune(a.out, log=lambda m: print(m, flush=True))
+    if a.m2l_only:
+        tune_m2l(a.out, log=lambda m: print(m, flush=True))
+    else:
+        tune(a.out, log=lambda m: print(m, flush=True))
 
 
 if __name__ == "__main__":

@@ -137,10 +137,12 @@ def generate(n_instances, seed, out, n_range=(2 ** 11, 2 ** 18), log=print, radi
         P = random_instance(rng, n_range)
         for f, lg, p, L, r, ms in evaluate_grid(P, seed=i, radii=radii):
             F.append(f); Y.append(lg); meta.append((i, P.n, p, L, ms, r))
-        if (i + 1) % 5 == 0:
+        if (i + 1) % 5 == 0 or i + 1 == n_instances:
             log(f"[generate] {i + 1}/{n_instances} instances, {len(Y)} rows, {time.time() - t0:.1f} s")
-    np.savez_compressed(out, features=np.array(F, np.float32), target=np.array(Y, np.float32),
-                        meta=np.array(meta, np.float64), seed=seed)
+            # written as it goes: a run cut short keeps the instances done so far
+            np.savez_compressed(out, features=np.array(F, np.float32),
+                                target=np.array(Y, np.float32), meta=np.array(meta, np.float64),
+                                seed=seed)
     return len(Y)
 
 
@@ -180,6 +182,8 @@ def train(data_paths, out, epochs=300, batch=256, lr=3e-3, seed=0, val_frac=0.2,
     nt = Xt.shape[0]
     steps = 0
     t0 = time.time()
+    # the parameters with the lowest validation error, checked every 10 epochs
+    best = (math.inf, None, 0)
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(nt).astype(np.int64)).cuda()
         lr_ep = lr * 0.5 * (1 + math.cos(math.pi * ep / epochs)) + 1e-5
@@ -187,17 +191,24 @@ def train(data_paths, out, epochs=300, batch=256, lr=3e-3, seed=0, val_frac=0.2,
             idx = perm[s:s + batch]
             tr.step(Xt[idx].contiguous(), Tt[idx].contiguous(), lr_ep)
             steps += 1
-        if (ep + 1) % 50 == 0 or ep == epochs - 1:
+        if (ep + 1) % 10 == 0 or ep == epochs - 1:
             pv = V.mlp_forward(tr.params, Xv).cpu().numpy()
-            log(f"[train] epoch {ep + 1}: val rmse {np.sqrt(np.mean((pv - Tv) ** 2)):.3f} "
-                f"(log10 units), {time.time() - t0:.1f} s")
+            rmse = float(np.sqrt(np.mean((pv - Tv) ** 2)))
+            if rmse < best[0]:
+                best = (rmse, tr.params.clone(), ep + 1)
+            if (ep + 1) % 50 == 0 or ep == epochs - 1:
+                log(f"[train] epoch {ep + 1}: val rmse {rmse:.3f} (log10 units), "
+                    f"{time.time() - t0:.1f} s")
+    tr.params.copy_(best[1])
+    log(f"[train] kept the parameters of epoch {best[2]} (val rmse {best[0]:.3f})")
     pv = V.mlp_forward(tr.params, Xv).cpu().numpy()
     pt = V.mlp_forward(tr.params, Xt).cpu().numpy()
     resid = pv - Tv
     metrics = {"train_rmse": float(np.sqrt(np.mean((pt - Y[~val]) ** 2))),
                "val_rmse": float(np.sqrt(np.mean(resid ** 2))),
                "val_q95_underprediction": float(np.quantile(-resid, 0.95)),
-               "rows_train": int(nt), "rows_val": int(val.sum()), "steps": steps, "epochs": epochs}
+               "rows_train": int(nt), "rows_val": int(val.sum()), "steps": steps, "epochs": epochs,
+               "kept_epoch": best[2]}
     margin = max(0.3, metrics["val_q95_underprediction"])
     np.savez(out, params=tr.params.cpu().numpy(), mean=mean.astype(np.float32),
              std=std.astype(np.float32), margin=np.float64(margin), metrics=json.dumps(metrics))

@@ -42,3 +42,13 @@ def test_cutoff_takes_fastest_64_target_shape(tmp_path):
 
 def test_missing_table_defaults(tmp_path):
     assert AT.lookup(1000, 3, str(tmp_path / "absent.json")) == (64, 4)
+
+
+def test_m2l_tile_lookup(tmp_path):
+    entries = [{"ppl_log2": 8.0, "tile": 64, "waves": 4, "m2l_tile": 2},
+               {"ppl_log2": 4.0, "tile": 16, "waves": 4}]
+    p = tmp_path / "tuning.json"
+    p.write_text(json.dumps({"entries": entries}))
+    assert AT.lookup_m2l(1 << 20, 6, str(p)) == 2
+    assert AT.lookup_m2l(1 << 20, 8, str(p)) == 0    # entry without M2L timings
+    assert AT.lookup_m2l(1000, 3, str(tmp_path / "absent.json")) == 0
