@@ -507,6 +507,13 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t batch, int32_t use_graph, void* stream
  * NULL is ignored. */
 void vfmm_batch_destroy(vfmm_batch_t batch);
 
+/* Kernel-substitution floor of every instance (as vfmm_substitution_bound
+ * with the instance's bounding square, levels and sigma, the paper's split):
+ * bound (host, count) receives 1 / (exp(w_L^2 / 2 sigma^2) - 1) per instance,
+ * for the bounding squares of the last run, which the call waits for.
+ * Errors: VFMM_ERR_INVALID_ARG (NULL pointer, no run yet), VFMM_ERR_HIP. */
+vfmm_status_t vfmm_batch_substitution_bounds(vfmm_batch_t batch, double* bound);
+
 /* One call for one batched evaluation (Sections 3.1-3.3 per instance):
  * vfmm_batch_create, vfmm_batch_run without a graph on `stream`, then the plan
  * is released (the enqueued work still completes).  workspace: at least
@@ -537,6 +544,27 @@ vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count
 #define VFMM_NEAR_RADIUS_AUTO (-1.0)
 #define VFMM_NEAR_RINGS_MAX 4
 vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t tree, double radius);
+
+/* Floor of the kernel substitution (eq. 6 against eq. 15; Section 4.1).  The
+ * far field sums the singular kernel K' for every pair it carries; K' differs
+ * from K_sigma by exp(-r^2 / 2 sigma^2) |K'| at distance r.  Every pair closer
+ * than d = max(w_L, a) is summed with K_sigma: w_L = root_side / 2^levels (two
+ * leaves that are not neighbours are at least one leaf side apart), a the near
+ * radius as vfmm_tree_set_near_radius resolves it for `precision` (0: none;
+ * VFMM_NEAR_RADIUS_AUTO: 6 sigma in the three float32 modes, sqrt(76) sigma in
+ * FP64), clamped to VFMM_NEAR_RINGS_MAX w_L.
+ *   *distance (host, may be NULL) = d;
+ *   *bound    (host) = |K' - K_sigma| / |K_sigma| at r = d
+ *             = 1 / (exp(d^2 / 2 sigma^2) - 1),
+ * the largest relative kernel error of any pair in the far field: an error
+ * floor that no expansion order removes.  Above about 1e-3 the far field is
+ * not a useful approximation of eq. 7 (leaves narrower than a few sigma).
+ * Host only: no device work, no GPU needed.
+ * Errors: VFMM_ERR_INVALID_ARG (root_side or sigma not finite and > 0, levels
+ * outside 0 .. VFMM_MAX_LEVELS, radius not finite, unknown precision). */
+vfmm_status_t vfmm_substitution_bound(double root_side, int32_t levels, double sigma,
+                                      double near_radius, int32_t precision, double* distance,
+                                      double* bound);
 
 /* Advection of the particles with their own velocity (eq. 5, dx_i/dt = u(x_i);
  * the viscous diffusion of eq. 1 is not included).  Heun's explicit two-stage

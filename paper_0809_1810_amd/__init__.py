@@ -9,7 +9,7 @@ from .vfmm import (Batch, FP32, FP64, M2L_BF16, M2L_FP16, MAX_LEVELS, MAX_P, MLP
                    header_symbols, lib, mlp_forward, fmm_velocity_oneshot, particle_stats, select_params,
                    selector_features, set_tuning, get_tuning, workspace_bytes,
                    direct_velocity_at, error_field, targets_workspace_bytes, NEAR_RADIUS_AUTO,
-                   NEAR_RINGS_MAX,
+                   NEAR_RINGS_MAX, substitution_bound,
                    N_PHASES, PHASES)
 
 __all__ = [
@@ -19,6 +19,6 @@ __all__ = [
     "header_symbols", "lib", "mlp_forward", "fmm_velocity_oneshot", "particle_stats", "select_params",
     "selector_features", "set_tuning", "get_tuning", "workspace_bytes",
     "direct_velocity_at", "error_field", "targets_workspace_bytes", "NEAR_RADIUS_AUTO",
-    "NEAR_RINGS_MAX",
+    "NEAR_RINGS_MAX", "substitution_bound",
     "N_PHASES", "PHASES",
 ]

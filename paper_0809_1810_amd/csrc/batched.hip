@@ -748,6 +748,9 @@ struct vfmm_batch_s {
   // recorded on the caller's stream at the end of every run: the plan is
   // released only once its last run has finished
   hipEvent_t done;
+  bool ran;  // a run has been enqueued (the roots of the last one are in d.roots)
+  std::vector<double> sigma;  // per instance, for vfmm_batch_substitution_bounds
+  std::vector<int> levels;
   ~vfmm_batch_s() {
     if (done) (void)hipEventSynchronize(done);
     if (side) (void)hipStreamSynchronize(side);
@@ -899,6 +902,12 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   }
   ls_off[count] = leaf_off[count] + count;
   for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
+  std::vector<double> sig(count);
+  std::vector<int> lev(count);
+  for (int c = 0; c < count; ++c) {
+    sig[c] = inst[c].sigma;
+    lev[c] = inst[c].levels;
+  }
   vfmm_batch_s* b = new (std::nothrow) vfmm_batch_s{};
   if (!b) return bfail(VFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
   hipError_t es = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
@@ -911,6 +920,8 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   }
   for (int p = 0; p <= VFMM_MAX_P; ++p) b->tab_at[p] = L.tab_at[p];
   b->count = count;
+  b->sigma.swap(sig);
+  b->levels.swap(lev);
   b->ntot = L.ntot;
   b->nleaves = L.nleaves;
   b->max_tiles = L.max_tiles;
@@ -1025,6 +1036,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
                          b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st,
                          b->side, b->fork, b->join);
     if (e == hipSuccess) e = hipEventRecord(b->done, st);
+    if (e == hipSuccess) b->ran = true;
     return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "batch run: %s", hipGetErrorString(e));
   }
   if (!b->exec) {
@@ -1041,10 +1053,38 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
   }
   e = hipGraphLaunch(b->exec, st);
   if (e == hipSuccess) e = hipEventRecord(b->done, st);
+  if (e == hipSuccess) b->ran = true;
   return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "graph launch: %s", hipGetErrorString(e));
 }
 
 void vfmm_batch_destroy(vfmm_batch_t b) { delete b; }
+
+// Every instance uses the paper's split, so its substitution distance is its
+// leaf side, known once the last run has computed the bounding squares.
+static vfmm_status_t batch_bounds_impl(vfmm_batch_t b, double* bound) {
+  if (!b || !bound) return bfail(VFMM_ERR_INVALID_ARG, "null pointer");
+  if (!b->ran) return bfail(VFMM_ERR_INVALID_ARG, "the batch has not run yet");
+  hipError_t e = hipEventSynchronize(b->done);
+  std::vector<double> r(size_t(b->count) * 4);
+  if (e == hipSuccess)
+    e = hipMemcpy(r.data(), b->d.roots, r.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bfail(hip_status(e), "batch roots: %s", hipGetErrorString(e));
+  for (int c = 0; c < b->count; ++c) {
+    const vfmm_status_t s =
+        vfmm_substitution_bound(r[4 * size_t(c) + 2], b->levels[c], b->sigma[c], 0.0, VFMM_FP32,
+                                nullptr, bound + c);
+    if (s) return s;
+  }
+  return VFMM_OK;
+}
+
+vfmm_status_t vfmm_batch_substitution_bounds(vfmm_batch_t b, double* bound) {
+  try {
+    return batch_bounds_impl(b, bound);
+  } catch (const std::bad_alloc&) {
+    return bfail(VFMM_ERR_OUT_OF_MEMORY, "vfmm_batch_substitution_bounds: host allocation failed");
+  }
+}
 
 vfmm_status_t vfmm_fmm_velocity_batched(const vfmm_instance* inst, int32_t count, void* workspace,
                                         size_t ws_bytes, void* stream) {

@@ -753,6 +753,33 @@ vfmm_status_t vfmm_tree_set_near_radius(vfmm_tree_t t, double radius) {
   return VFMM_OK;
 }
 
+// Kernel substitution of the far field (eq. 6 against eq. 15): every pair
+// closer than d = max(w_L, a) is summed with K_sigma; beyond it the far field
+// takes K', which differs from K_sigma by exp(-r^2 / 2 sigma^2) |K'|, i.e. by
+// e / (1 - e) |K_sigma| with e = exp(-d^2 / 2 sigma^2) at r = d.
+vfmm_status_t vfmm_substitution_bound(double root_side, int32_t levels, double sigma,
+                                      double near_radius, int32_t precision, double* distance,
+                                      double* bound) {
+  if (!bound) return fail(VFMM_ERR_INVALID_ARG, "bound is NULL");
+  if (!(root_side > 0.0) || !std::isfinite(root_side))
+    return fail(VFMM_ERR_INVALID_ARG, "root side must be finite and > 0");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(VFMM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  if (levels < 0 || levels > VFMM_MAX_LEVELS)
+    return fail(VFMM_ERR_INVALID_ARG, "levels %d out of [0, %d]", levels, VFMM_MAX_LEVELS);
+  if (!std::isfinite(near_radius)) return fail(VFMM_ERR_INVALID_ARG, "radius must be finite");
+  if (precision < VFMM_FP64 || precision > VFMM_M2L_FP16)
+    return fail(VFMM_ERR_INVALID_ARG, "unknown precision %d", precision);
+  const double w = root_side / std::ldexp(1.0, levels);
+  const double a = std::sqrt(near_cut2(near_radius < 0.0 ? -1.0 : near_radius, sigma,
+                                       precision == VFMM_FP64 ? kFP64 : kFP32));
+  const double d = std::fmax(w, std::fmin(a, VFMM_NEAR_RINGS_MAX * w));
+  const double q = d * d / (2.0 * sigma * sigma);
+  if (distance) *distance = d;
+  // e / (1 - e) = 1 / expm1(q), without cancellation for small q
+  *bound = q > 0.0 ? 1.0 / std::expm1(q) : HUGE_VAL;
+  return VFMM_OK;
+}
+
 vfmm_status_t vfmm_tree_enable_timing(vfmm_tree_t t, int32_t max_calls) {
   if (!t) return fail(VFMM_ERR_INVALID_ARG, "tree is NULL");
   if (max_calls < 0 || max_calls > 100000) return fail(VFMM_ERR_INVALID_ARG, "max_calls out of range");

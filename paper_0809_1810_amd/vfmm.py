@@ -84,6 +84,9 @@ _SIGS = {
     "vfmm_tree_rebuild": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vfmm_tree_enable_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "vfmm_tree_set_near_radius": (C.c_int32, [C.c_void_p, C.c_double]),
+    "vfmm_substitution_bound": (C.c_int32, [C.c_double, C.c_int32, C.c_double, C.c_double,
+                                            C.c_int32, C.POINTER(C.c_double),
+                                            C.POINTER(C.c_double)]),
     "vfmm_advect_workspace_bytes": (C.c_int32, [C.c_int64, C.POINTER(C.c_size_t)]),
     "vfmm_advect": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                 C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
@@ -101,6 +104,7 @@ _SIGS = {
                                       C.POINTER(C.c_void_p)]),
     "vfmm_batch_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "vfmm_batch_destroy": (None, [C.c_void_p]),
+    "vfmm_batch_substitution_bounds": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
     "vfmm_set_tuning": (C.c_int32, [C.c_int32, C.c_int32]),
     "vfmm_get_tuning": (C.c_int32, [C.c_int32]),
     "vfmm_tree_get_tuning": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -541,6 +545,17 @@ def error_metrics_noalloc(u, v, u_ref, v_ref, out):
     return out
 
 
+def substitution_bound(root_side, levels, sigma, near_radius=0.0, precision=FP64):
+    """vfmm_substitution_bound (host only): (d, bound) with d the distance below
+    which every pair is summed with the regularised kernel and bound the
+    relative kernel error |K' - K_sigma| / |K_sigma| of a far pair at d."""
+    d = C.c_double(0.0); b = C.c_double(0.0)
+    _check(lib().vfmm_substitution_bound(float(root_side), int(levels), float(sigma),
+                                         float(near_radius), int(precision), C.byref(d),
+                                         C.byref(b)), "vfmm_substitution_bound")
+    return d.value, b.value
+
+
 # ----------------------------------------------------------------- selector network
 
 
@@ -722,6 +737,13 @@ class Batch:
         _check(lib().vfmm_fmm_velocity_batched(self._arr, len(self.u), self.workspace.data_ptr(),
                                                self.workspace.numel(), _stream()),
                "vfmm_fmm_velocity_batched")
+
+    def substitution_bounds(self):
+        """vfmm_batch_substitution_bounds: per-instance kernel-substitution floor
+        (list of floats) for the bounding squares of the last run."""
+        out = (C.c_double * len(self.u))()
+        _check(lib().vfmm_batch_substitution_bounds(self._h, out), "vfmm_batch_substitution_bounds")
+        return list(out)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -261,3 +261,53 @@ def test_select_and_audit_rejects_before_device_work():
     assert call(reps=0) == B.ERR_INVALID_ARG
     assert call(ws=C.c_void_p(257)) == B.ERR_WORKSPACE
     assert call(wsb=16) == B.ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("sig", [0.05, 0.03])
+def test_substitution_bound_host_function(sig):
+    """vfmm_substitution_bound against the kernels of the oracle: at the
+    returned distance d, |K' - K_sigma| / |K_sigma| evaluated from eq. 6 and
+    eq. 15 directly (the difference of the two cancels to a relative accuracy
+    of about 1e-16 / bound); d follows the leaf side, the clamped near radius
+    and the automatic radius of each precision."""
+    import math
+
+    import numpy as np
+
+    from oracle import kernel as K
+    _lib()
+    S, L = 2.0, 5
+    w = S / 2 ** L
+    cases = [
+        (0.0, vf.FP64, w),                       # the paper's split
+        (0.5 * w, vf.FP32, w),                    # a radius below w_L changes nothing
+        (2.5 * w, vf.FP32, 2.5 * w),
+        (9.0 * w, vf.FP64, 4.0 * w),              # clamped to 4 leaf sides
+        (vf.NEAR_RADIUS_AUTO, vf.FP32, max(w, min(6.0 * sig, 4 * w))),
+        (vf.NEAR_RADIUS_AUTO, vf.M2L_BF16, max(w, min(6.0 * sig, 4 * w))),
+        (vf.NEAR_RADIUS_AUTO, vf.FP64, max(w, min(math.sqrt(76.0) * sig, 4 * w))),
+    ]
+    for radius, prec, d_expect in cases:
+        d, b = vf.substitution_bound(S, L, sig, radius, prec)
+        assert d == pytest.approx(d_expect, rel=1e-15), (radius, prec)
+        for ang in (0.0, 0.7, 2.0):
+            dx, dy = d * math.cos(ang), d * math.sin(ang)
+            ks = np.array(K.singular_kernel(dx, dy))
+            kr = np.array(K.regularized_kernel(dx, dy, sig))
+            ref = np.linalg.norm(ks - kr) / np.linalg.norm(kr)
+            assert b == pytest.approx(ref, rel=1e-12 + 1e-15 / b), (radius, prec, ang)
+
+
+def test_substitution_bound_limits_and_errors():
+    l = _lib()
+    # leaves narrower than sigma: the floor exceeds the kernel itself
+    assert vf.substitution_bound(1.0, 8, 0.01)[1] > 1.0
+    # leaves of 10 sigma: below any float64 tolerance
+    assert vf.substitution_bound(1.0, 4, 0.00625)[1] < 1e-20
+    out = C.c_double(0.0)
+    for args in ((0.0, 3, 0.1, 0.0, 0), (1.0, -1, 0.1, 0.0, 0), (1.0, 13, 0.1, 0.0, 0),
+                 (1.0, 3, 0.0, 0.0, 0), (1.0, 3, 0.1, float("nan"), 0), (1.0, 3, 0.1, 0.0, 7),
+                 (float("inf"), 3, 0.1, 0.0, 0)):
+        assert l.vfmm_substitution_bound(*args, None, C.byref(out)) == B.ERR_INVALID_ARG, args
+    assert l.vfmm_substitution_bound(1.0, 3, 0.1, 0.0, 0, None, None) == B.ERR_INVALID_ARG
+    assert l.vfmm_batch_substitution_bounds(None, C.byref(out)) == B.ERR_INVALID_ARG

@@ -135,3 +135,36 @@ def test_full_sweep_batch_against_oracle(vf):
     print("worst e_max: p <= 16 %.2e, p > 16 %.2e" % (worst[False], worst[True]))
     assert sum(d["p"] > 16 for d in insts) == 64
     b.close()
+
+
+def test_substitution_floor_per_instance(vf):
+    """vfmm_batch_substitution_bounds: per instance, the kernel-substitution
+    floor of its bounding square (the oracle's root side) at its levels and
+    sigma.  An instance whose leaves are narrower than sigma gets a floor above
+    1, and its error against the direct sum (eq. 7) is indeed large, while an
+    instance with leaves of 5 sigma or more has a negligible floor and meets
+    the float32 bar against the direct sum."""
+    from oracle import kernel as K
+    from oracle import quadtree as Q
+    Pw = W.uniform(3000, seed=51, sigma=0.01)   # root ~2, L=3: leaves ~25 sigma
+    Pn = W.uniform(3000, seed=52, sigma=0.05)   # L=6: leaves ~0.6 sigma
+    insts = [dict(P=Pw, p=16, levels=3), dict(P=Pn, p=12, levels=6)]
+    for d in insts:
+        P = d["P"]
+        d.update(x=dev(P.x), y=dev(P.y), gamma=dev(P.gamma), sigma=P.sigma)
+    b = vf.Batch(insts)
+    with pytest.raises(vf.VfmmError):
+        b.substitution_bounds()  # no run yet
+    b.run()
+    bounds = b.substitution_bounds()
+    errs = []
+    for i, d in enumerate(insts):
+        P = d["P"]
+        S = Q.root_square(P.x, P.y, None)[2]
+        expect = vf.substitution_bound(S, d["levels"], P.sigma)[1]
+        print_case("substitution floor", i=i, n=P.n, levels=d["levels"], bound=bounds[i])
+        assert bounds[i] == pytest.approx(expect, rel=1e-14)
+        ud, vd = K.direct_velocity(P.x, P.y, P.gamma, P.sigma)
+        errs.append(rel_err(host(b.u[i]), host(b.v[i]), ud, vd)[0])
+    assert bounds[0] < 1e-100 and errs[0] < 1e-6
+    assert bounds[1] > 1.0 and errs[1] > 1e-3
