@@ -234,6 +234,8 @@ def main():
                          "M x M lattice of separate points covering the root square")
     ap.add_argument("--p2p-tile", type=int, default=0,
                     help="override the autotuned near-field tile (64, 32 or 16 targets)")
+    ap.add_argument("--p2p-sym", type=int, default=-1, choices=(-1, 0, 1),
+                    help="symmetric near field for the trees of this run (-1: the tuning table's)")
     ap.add_argument("--p2p-waves", type=int, default=0,
                     help="override the autotuned near-field waves per workgroup (1, 2, 4, 8)")
     ap.add_argument("--advect", type=int, default=0, metavar="K",
@@ -561,6 +563,8 @@ def second_input(a, torch, vf, name):
 def override_tuning(a, vf):
     if a.p2p_tile or a.p2p_waves:
         vf.set_tuning(tile=a.p2p_tile or None, waves=a.p2p_waves or None)
+    if a.p2p_sym >= 0:
+        vf.set_tuning(sym=a.p2p_sym)
 
 
 
@@ -647,7 +651,7 @@ def bench_eval_points(a, torch, vf):
                                   "cell-centred lattice of evaluation points on the root square",
                       "p": p, "levels": L, "selector": how,
                       "near_radius": "auto: min(6 sigma, 4 w_L)" if radius < 0 else radius,
-                      "p2p_tile_waves": list(vf.get_tuning().values())},
+                      "p2p_tile_waves": [vf.get_tuning()["tile"], vf.get_tuning()["waves"]]},
            "accuracy": {"emax": emax, "erms": erms, "sample": AUDIT_TARGETS,
                         "log10_error_quantiles": {q: float(np.quantile(field, float(q)))
                                                   for q in ("0.5", "0.9", "0.99", "1.0")}},

@@ -599,10 +599,22 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
  *                        registers one offset ahead (default); 1 / 2 = the
  *                        tile's source multipoles first staged in LDS
  *                        (coalesced row loads), 4 / 8 waves per workgroup.
+ *   VFMM_TUNE_P2P_SYMMETRIC: 0 (default) or 1, for trees with 64-particle
+ *                        tiles (ignored otherwise): the near field at the
+ *                        particles evaluates each pair of two different leaves
+ *                        of the local list once, both directions from one
+ *                        kernel value (K_sigma is odd: K(-r) = -K(r)); the
+ *                        opposite contributions are added to float64 sums of
+ *                        the source particles with atomic additions, whose
+ *                        order varies from run to run (results reproducible
+ *                        to float64 rounding of those sums, not bit for bit).
+ *                        Evaluation points and the adaptive tree always take
+ *                        both directions separately.
  * Results do not depend on the settings beyond float32 summation order. */
 #define VFMM_TUNE_P2P_TILE 1
 #define VFMM_TUNE_P2P_WAVES 2
 #define VFMM_TUNE_M2L_TILE 3
+#define VFMM_TUNE_P2P_SYMMETRIC 4
 vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value);
 int32_t vfmm_get_tuning(int32_t param); /* -1 for an unknown parameter */
 /* The setting a tree was built with (-1 for a NULL tree or an unknown parameter). */

@@ -13,6 +13,10 @@ at the radius where one pair's kernel difference is 1e-6 (``cutoff_ms``), and
 ``apply_for(..., cutoff=True)`` takes the fastest of those (or, for an entry
 without them, the fastest 64-target shape of the paper's split).
 
+Symmetric near field (VFMM_TUNE_P2P_SYMMETRIC, 64-target tiles): the tuner
+times the 64-target shapes with it too, keyed "64x<waves>s" in ``all_ms`` and
+``cutoff_ms``; ``apply_for`` sets it when such a shape is the fastest.
+
 M2L on the matrix cores (FP32, p <= 16): the tile variants of
 VFMM_TUNE_M2L_TILE (operands in registers one offset ahead; sources staged in
 LDS with 4 or 8 waves) are timed on the M2L + L2L phase of far-only
@@ -21,6 +25,7 @@ evaluations, and the fastest is stored per entry (``m2l_tile``, ``m2l_ms``);
 
     python -m paper_0809_1810_amd.autotune --out tuning.json
     python -m paper_0809_1810_amd.autotune --m2l-only      (add the M2L timings to the table)
+    python -m paper_0809_1810_amd.autotune --sym-only      (add the symmetric near-field timings)
 """
 from __future__ import annotations
 
@@ -45,9 +50,10 @@ M2L_TILES = (0, 1, 2)
 CUTOFF_TOL = 1e-6
 
 
-def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5, radius=0.0):
-    """Median P2P phase time (ms) for one launch shape (radius: near cut-off)."""
-    V.set_tuning(tile=tile, waves=waves)
+def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5, radius=0.0, sym=0):
+    """Median P2P phase time (ms) for one launch shape (radius: near cut-off;
+    sym: symmetric near field, 64-target tiles)."""
+    V.set_tuning(tile=tile, waves=waves, sym=sym)
     t = V.Tree(x, y, levels, p_max=p)
     t.set_near_radius(radius)
     t.velocity(g, sigma, p, V.FP32)
@@ -56,7 +62,17 @@ def time_p2p(x, y, g, sigma, p, levels, tile, waves, reps=5, radius=0.0):
         t.velocity(g, sigma, p, V.FP32)
     ms = float(np.median([ph["p2p"] for ph in t.read_timing()]))
     t.close()
+    V.set_tuning(sym=0)
     return ms
+
+
+def sym_entry(x, y, g, sigma, p, levels):
+    """Timings of the symmetric 64-target shapes, paper split and cut-off."""
+    radius = sigma * math.sqrt(2.0 * math.log(1.0 / CUTOFF_TOL))
+    split = {f"64x{w}s": round(time_p2p(x, y, g, sigma, p, levels, 64, w, sym=1), 4) for w in WAVES}
+    cut = {f"64x{w}s": round(time_p2p(x, y, g, sigma, p, levels, 64, w, radius=radius, sym=1), 4)
+           for w in WAVES}
+    return split, cut
 
 
 def time_m2l(x, y, g, sigma, p, levels, mode, reps=10):
@@ -97,6 +113,9 @@ def tune_workload(name, P, p, levels, log=print):
              "cutoff_radius_sigma": round(radius / P.sigma, 4),
              "cutoff_ms": {f"64x{w}": round(v, 4) for w, v in sorted(cut.items())}}
     entry.update(m2l_entry(x, y, g, P.sigma, p, levels))
+    split, cut_s = sym_entry(x, y, g, P.sigma, p, levels)
+    entry["all_ms"].update(split)
+    entry["cutoff_ms"].update(cut_s)
     log(f"[tune] {name} L={levels}: best tile {best[0]} waves {best[1]} {res[best]:.3f} ms "
         f"(default 64x4 {res[(64, 4)]:.3f} ms); with the cut-off 64x{cbest} {cut[cbest]:.3f} ms")
     return entry
@@ -133,6 +152,24 @@ def tune_m2l(path=TABLE_PATH, log=print):
     return table
 
 
+def tune_sym(path=TABLE_PATH, log=print):
+    """Adds the symmetric near-field timings to every entry of an existing table."""
+    import torch
+    table = json.load(open(path))
+    work = {(w[0], w[3]): w for w in default_workloads()}
+    for e in table["entries"]:
+        name, P, p, levels = work[(e["workload"], e["levels"])]
+        x = torch.from_numpy(P.x).cuda(); y = torch.from_numpy(P.y).cuda()
+        g = torch.from_numpy(P.gamma).cuda()
+        split, cut = sym_entry(x, y, g, P.sigma, p, levels)
+        e.setdefault("all_ms", {}).update(split)
+        e.setdefault("cutoff_ms", {}).update(cut)
+        log(f"[tune] {name} L={levels}: symmetric {split}, with the cut-off {cut}")
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
 def tune(out=TABLE_PATH, log=print):
     t0 = time.time()
     entries = [tune_workload(*w, log=log) for w in default_workloads()]
@@ -143,22 +180,36 @@ def tune(out=TABLE_PATH, log=print):
     return table
 
 
-def lookup(n, levels, path=TABLE_PATH, cutoff=False):
-    """(tile, waves) of the table entry nearest in log2 particles per leaf; with
-    ``cutoff`` the entry's fastest 64-target shape."""
+def _parse(key):
+    """"64x2" -> (64, 2, 0); "64x2s" (symmetric near field) -> (64, 2, 1)."""
+    tile, rest = key.split("x")
+    return int(tile), int(rest.rstrip("s")), int(rest.endswith("s"))
+
+
+def lookup_shape(n, levels, path=TABLE_PATH, cutoff=False):
+    """(tile, waves, sym) of the table entry nearest in log2 particles per leaf:
+    its fastest timed shape; with ``cutoff`` its fastest 64-target shape (timed
+    with the cut-off if it has such timings)."""
     try:
         table = json.load(open(path))
     except (OSError, ValueError):
-        return 64, 4
+        return 64, 4, 0
     ppl = math.log2(max(n, 1)) - 2 * levels
     e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
     if cutoff:
         t64 = e.get("cutoff_ms") or {k: v for k, v in e.get("all_ms", {}).items()
                                      if k.startswith("64x")}
         if t64:
-            return 64, int(min(t64, key=t64.get).split("x")[1])
-        return 64, int(e["waves"]) if int(e["tile"]) == 64 else 4
-    return int(e["tile"]), int(e["waves"])
+            return _parse(min(t64, key=t64.get))
+        return 64, int(e["waves"]) if int(e["tile"]) == 64 else 4, 0
+    if e.get("all_ms"):
+        return _parse(min(e["all_ms"], key=e["all_ms"].get))
+    return int(e["tile"]), int(e["waves"]), 0
+
+
+def lookup(n, levels, path=TABLE_PATH, cutoff=False):
+    """(tile, waves) of ``lookup_shape``."""
+    return lookup_shape(n, levels, path, cutoff)[:2]
 
 
 def lookup_m2l(n, levels, path=TABLE_PATH):
@@ -173,8 +224,8 @@ def lookup_m2l(n, levels, path=TABLE_PATH):
 
 
 def apply_for(n, levels, path=TABLE_PATH, cutoff=False):
-    tile, waves = lookup(n, levels, path, cutoff)
-    V.set_tuning(tile=tile, waves=waves, m2l=lookup_m2l(n, levels, path))
+    tile, waves, sym = lookup_shape(n, levels, path, cutoff)
+    V.set_tuning(tile=tile, waves=waves, m2l=lookup_m2l(n, levels, path), sym=sym)
     return tile, waves
 
 
@@ -183,9 +234,13 @@ def main(argv=None):
     ap.add_argument("--out", default=TABLE_PATH)
     ap.add_argument("--m2l-only", action="store_true",
                     help="time the M2L tiles and add them to the existing table")
+    ap.add_argument("--sym-only", action="store_true",
+                    help="time the symmetric near field and add it to the existing table")
     a = ap.parse_args(argv)
     if a.m2l_only:
         tune_m2l(a.out, log=lambda m: print(m, flush=True))
+    elif a.sym_only:
+        tune_sym(a.out, log=lambda m: print(m, flush=True))
     else:
         tune(a.out, log=lambda m: print(m, flush=True))
 

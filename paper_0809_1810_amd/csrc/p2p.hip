@@ -78,11 +78,17 @@ namespace {
 //   first row by - d, leaves bx - d .. bx + d; then rows by - d + 1 .. by + d - 1,
 //   leaf bx - d then leaf bx + d; last row by + d, leaves bx - d .. bx + d;
 // all clipped to the level.  Returns false for an empty segment.
-__device__ __forceinline__ bool segment(int s, int bx, int by, int m, int& sy, int& lo, int& hi) {
+// Symmetric near field (sym): of the local list only the leaf itself and the
+// neighbours after it in (row, leaf) order -- E in its own row, NW, N and NE
+// above -- remain; row by - 1 and leaf bx - 1 are left out, each such pair of
+// leaves being evaluated once, for both, by the tiles of the earlier leaf.
+__device__ __forceinline__ bool segment(int s, int bx, int by, int m, bool sym, int& sy, int& lo,
+                                        int& hi) {
   int d0, d1;
   if (s < 3) {
+    if (sym && s == 0) return false;
     sy = by - 1 + s;
-    d0 = -1;
+    d0 = sym && s == 1 ? 0 : -1;
     d1 = 1;
   } else {
     int d = 2, base = 3;
@@ -131,10 +137,10 @@ __device__ __forceinline__ NearRings near_rings(double cut2, double w) {
 // 2^k leaf-level rows of the level's segment sg >> k, and spans the 2^k
 // leaf-level boxes of every box of that segment.  (bx, by) are the target
 // leaf's coordinates at its level, ml = 2^(L - k) the boxes per side there.
-__device__ __forceinline__ bool fine_segment(int sg, int k, int bx, int by, int ml, int& sy,
-                                             int& lo, int& hi) {
+__device__ __forceinline__ bool fine_segment(int sg, int k, int bx, int by, int ml, bool sym,
+                                             int& sy, int& lo, int& hi) {
   int syl, lol, hil;
-  if (!segment(sg >> k, bx, by, ml, syl, lol, hil)) return false;
+  if (!segment(sg >> k, bx, by, ml, sym, syl, lol, hil)) return false;
   sy = (syl << k) + (sg & ((1 << k) - 1));
   lo = lol << k;
   hi = ((hil + 1) << k) - 1;
@@ -147,13 +153,13 @@ __device__ __forceinline__ int tile_shift(const uint8_t* __restrict__ leaf_shift
 }
 
 __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int k, int nseg,
-                                                    const uint32_t* __restrict__ tile_off) {
+                                                    bool sym, const uint32_t* __restrict__ tile_off) {
   const int m = 1 << levels;
   const int bx = (leaf & (m - 1)) >> k, by = (leaf >> levels) >> k;
   uint32_t c = 0;
   for (int s = 0; s < (nseg << k); ++s) {
     int sy, lo, hi;
-    if (fine_segment(s, k, bx, by, m >> k, sy, lo, hi))
+    if (fine_segment(s, k, bx, by, m >> k, sym, sy, lo, hi))
       c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
   }
   return c;
@@ -167,7 +173,7 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
                                                      const double* __restrict__ root, int levels,
                                                      double cut2, int64_t max_tiles,
                                                      const uint8_t* __restrict__ leaf_shift,
-                                                     uint32_t* __restrict__ cnt,
+                                                     int sym, uint32_t* __restrict__ cnt,
                                                      uint64_t* __restrict__ bsum) {
   __shared__ uint64_t red[256];
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
@@ -176,7 +182,7 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
     const int leaf = ttiles[t].leaf;
     const int k = tile_shift(leaf_shift, leaf);
     const int nseg = near_rings(cut2, root[3] * double(1 << k)).nseg;
-    c = sequence_chunks(leaf, levels, k, nseg, tile_off);
+    c = sequence_chunks(leaf, levels, k, nseg, sym != 0, tile_off);
   }
   if (t <= max_tiles) cnt[t] = c;
   red[threadIdx.x] = c;
@@ -281,6 +287,10 @@ template <> struct PairK<float> {
   }
   __device__ __forceinline__ float far(float g, float r2) const { return P2PMath<float>::far(g, r2); }
   __device__ __forceinline__ float gauss(float g, float r2) const { return P2PMath<float>::gauss_s(g, r2); }
+  // the kernel value without the circulation, for the symmetric pairs
+  __device__ __forceinline__ float hnear(float r2) const { return P2PMath<float>::h_near_s(r2); }
+  __device__ __forceinline__ float hseries(float r2) const { return P2PMath<float>::h_series_s(r2); }
+  __device__ __forceinline__ float hfar(float r2) const { return P2PMath<float>::h_far(r2); }
 };
 template <> struct PairK<double> {
   double kexp;
@@ -292,9 +302,61 @@ template <> struct PairK<double> {
   __device__ __forceinline__ double gauss(double g, double r2) const {
     return P2PMath<double>::gauss(g, r2, kexp);
   }
+  __device__ __forceinline__ double hnear(double r2) const { return P2PMath<double>::h_near(r2, kexp); }
+  __device__ __forceinline__ double hseries(double r2) const { return hnear(r2); }
+  __device__ __forceinline__ double hfar(double r2) const { return P2PMath<double>::h_far(r2); }
 };
 
-template <typename R, int LPT>
+// Symmetric pairs of two leaves (the target tile's leaf and a neighbour after
+// it): one wave holds 64 targets, one per lane, and a chunk of <= 64 sources,
+// which it stages twice in a row in its own LDS block (entry k holds source
+// (k + 1) mod 64, so that lane l reads source (l - s) mod 64 at step s from a
+// fixed offset); per step each lane evaluates the kernel of its pair once and
+// adds it to its target with the source's circulation and to the source's
+// sums with its own.  The source sums move one lane up per step (DPP row
+// rotation of the whole wave), so after 64 steps every lane holds those of
+// source j0 + lane.
+template <typename R> struct __align__(sizeof(R) * 4) SymRec { R x, y, g, pad; };
+
+__device__ __forceinline__ float lane_up(float v) {  // lane l takes lane l - 1 (mod 64)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C,
+                                                            0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_up(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b)), 0x13C, 0xF, 0xF, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b >> 32)), 0x13C, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// FORM: 0 the near form, 1 with the series for close pairs, 2 the far form.
+template <typename R, int FORM>
+__device__ __forceinline__ void sym_chunk(const SymRec<R>* __restrict__ rd, R tx, R ty, R tg,
+                                          R tiny, const PairK<R>& pk, R& cu, R& cv, R& su,
+                                          R& sv) {
+#pragma unroll 4
+  for (int st = 0; st < 64; ++st) {
+    const SymRec<R> q = rd[63 - st];
+    const R dx = tx - q.x;
+    const R dy = ty - q.y;
+    R h;
+    if constexpr (FORM == 2) {
+      h = pk.hfar(dx * dx + dy * dy);
+    } else {
+      const R r2 = dx * dx + (dy * dy + tiny);
+      h = FORM == 1 ? pk.hseries(r2) : pk.hnear(r2);
+    }
+    const R a = q.g * h, b = tg * h;
+    cu -= a * dy;
+    cv += a * dx;
+    su += b * dy;
+    sv -= b * dx;
+    su = lane_up(su);
+    sv = lane_up(sv);
+  }
+}
+
+template <typename R, int LPT, bool SYM>
 __global__ void __launch_bounds__(512) k_p2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
     const uint32_t* __restrict__ tile_off, const float4* __restrict__ tile_box,
@@ -303,8 +365,11 @@ __global__ void __launch_bounds__(512) k_p2p(
     const P2PPart* __restrict__ parts, const uint32_t* __restrict__ nparts, double2* __restrict__ partial,
     const double* __restrict__ root, int levels, PairK<R> pk, double sd, float far2, float ser2,
     double cut2, const uint8_t* __restrict__ leaf_shift, const Part64* __restrict__ fine64,
-    double2* __restrict__ nearv) {
+    double2* __restrict__ nearv, double2* __restrict__ react) {
   constexpr int T = 64 / LPT;  // targets per tile = sources per chunk
+  // symmetric near field (LPT = 1 only): a block of 128 source records per wave
+  extern __shared__ unsigned char p2p_lds[];
+  constexpr bool sym = SYM && LPT == 1;
   // FP32: sources and targets in units of the Gaussian width (factor sd);
   // FP64: plain units (sd = 1)
   const int wpb = blockDim.x >> 6;
@@ -369,6 +434,11 @@ __global__ void __launch_bounds__(512) k_p2p(
     const double rc2d = nr.rc2;
     const float rc2f = float(rc2d);
     const R rc2 = R(rc2d * sd * sd);
+    // symmetric near field: the target's own circulation (the targets are the
+    // particles, in the sources' order and units); 0 for the padding lanes
+    R tg = R(0);
+    if (sym && active) tg = part[i].g;
+    SymRec<R>* const sbuf = reinterpret_cast<SymRec<R>*>(p2p_lds) + (threadIdx.x >> 6) * 128;
     const float rc2s = float(rc2d * sd * sd);
 
     double nu = 0.0, nv = 0.0;
@@ -380,7 +450,7 @@ __global__ void __launch_bounds__(512) k_p2p(
       uint32_t vb = 0;  // sequence index of the current segment's first chunk
       for (int sg = 0; sg < nseg && vb < v1; ++sg) {
         int sy, lo, hi;
-        if (!fine_segment(sg, k, bx, by, m >> k, sy, lo, hi)) continue;
+        if (!fine_segment(sg, k, bx, by, m >> k, sym, sy, lo, hi)) continue;
         const bool ring = (sg >> k) >= kSegNear;
         // source row centre minus target leaf centre, in leaf-level sides
         // (sy - by exactly when k = 0); the targets themselves take the offset
@@ -407,6 +477,8 @@ __global__ void __launch_bounds__(512) k_p2p(
           const R tx = tx0 - R(oxt * wsd);
           const float bx0 = tb.x - float(ox * w), bx1 = tb.y - float(ox * w);
           const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
+          // a neighbour leaf of the symmetric near field: both directions here
+          const bool sym_leaf = sym && !ring && !(sx == bx && sy == by);
           for (uint32_t ci = qa; ci < qb; ++ci) {
             const int32_t j0 = js + int32_t(ci - la) * T;
             const int32_t j1 = min(j0 + T, je);
@@ -453,6 +525,30 @@ __global__ void __launch_bounds__(512) k_p2p(
                   cu += f * dy;
                   cv -= f * dx;
                 }
+              }
+            } else if (sym_leaf) {
+              // stage the chunk (padding: zero circulation at the leaf centre)
+              SymRec<R> rec{R(0), R(0), R(0), R(0)};
+              if (j0 + lane < j1) {
+                const auto q = part[j0 + lane];
+                rec = SymRec<R>{q.x, q.y, q.g, R(0)};
+              }
+              // this wave's reads of the previous chunk were consumed above
+              // (issued before these writes; LDS operations of a wave are
+              // performed in order), and the reads below wait for the writes
+              sbuf[(lane + 63) & 63] = rec;
+              sbuf[64 + ((lane + 63) & 63)] = rec;
+              __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+              __builtin_amdgcn_wave_barrier();
+              const SymRec<R>* rd = sbuf + lane;
+              R su = R(0), sv = R(0);
+              if (gap2 > far2) sym_chunk<R, 2>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+              else if (gap2 > ser2) sym_chunk<R, 0>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+              else sym_chunk<R, 1>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+              if (j0 + lane < j1) {
+                double* rj = reinterpret_cast<double*>(react + (j0 + lane));
+                unsafeAtomicAdd(rj, double(su) * sd);
+                unsafeAtomicAdd(rj + 1, double(sv) * sd);
               }
             } else if (gap2 > far2) {
 #pragma unroll 8
@@ -531,7 +627,7 @@ __device__ __forceinline__ void l2p_tile(
     const typename Types<R>::C* __restrict__ le_all, const uint8_t* __restrict__ leaf_shift,
     int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
     const double2* __restrict__ partial, const double2* __restrict__ nearv,
-    double* __restrict__ u, double* __restrict__ v) {
+    const double2* __restrict__ react, double* __restrict__ u, double* __restrict__ v) {
   const Tile tile = ttiles[wid];
   if (lane >= tile.count) return;
   const int32_t i = tile.start + lane;
@@ -569,6 +665,11 @@ __device__ __forceinline__ void l2p_tile(
     nu = q.x;
     nv = q.y;
   }
+  if (react) {  // the symmetric pairs' contributions to this particle as a source
+    const double2 q = react[i];
+    nu += q.x * kInv2Pi;
+    nv += q.y * kInv2Pi;
+  }
   u[o] = p > 0 ? nu + fu : nu;
   v[o] = p > 0 ? nv + fv : nv;
 }
@@ -582,16 +683,21 @@ __global__ void __launch_bounds__(256) k_l2p(
     const typename Types<R>::C* __restrict__ le_all, const uint8_t* __restrict__ leaf_shift,
     int near, const uint32_t* __restrict__ p_off, const uint32_t* __restrict__ s_off,
     const double2* __restrict__ partial, const double2* __restrict__ nearv,
-    double* __restrict__ u, double* __restrict__ v) {
+    const double2* __restrict__ react, double* __restrict__ u, double* __restrict__ v) {
   const int nt = *tntiles;
   const int lane = threadIdx.x & 63;
   for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
        wid += 4 * gridDim.x)
     l2p_tile<R, PMAX>(wid, lane, tpart, ttiles, tperm, root, levels, p, le_all, leaf_shift, near,
-                      p_off, s_off, partial, nearv, u, v);
+                      p_off, s_off, partial, nearv, react, u, v);
 }
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+__global__ void __launch_bounds__(256) k_zero2(double2* __restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    a[i] = make_double2(0.0, 0.0);
+}
 
 hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double cut2,
                           hipStream_t st) {
@@ -599,7 +705,8 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, do
   const int64_t mt = tg.max_tiles;
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, s.cnt, s.bsum);
+                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, tg.react ? 1 : 0, s.cnt,
+                     s.bsum);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,
@@ -633,10 +740,23 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   int64_t waves = tg.max_tiles + (pairs_bound < P ? pairs_bound : P);
   if (waves > kP2PMaxWaves) waves = kP2PMaxWaves;
   const P2PSched& s = tg.sched;
-  hipLaunchKernelGGL((k_p2p<R, LPT>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st, part,
-                     t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles, tg.tile_box,
-                     s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk, sd,
-                     far2, ser2, cut2, tg.leaf_shift, tg.fine64, s.near);
+  double2* react = LPT == 1 ? tg.react : nullptr;
+  size_t lds = 0;
+  if (react) {
+    hipLaunchKernelGGL(k_zero2, dim3(nblk(t.n, 256) < 4096 ? nblk(t.n, 256) : 4096u), dim3(256),
+                       0, st, react, t.n);
+    lds = size_t(wpb) * 128 * sizeof(SymRec<R>);
+  }
+  if (react)
+    hipLaunchKernelGGL((k_p2p<R, LPT, true>), dim3(nblk(waves, wpb)), dim3(64 * wpb), lds, st,
+                       part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles,
+                       tg.tile_box, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk,
+                       sd, far2, ser2, cut2, tg.leaf_shift, tg.fine64, s.near, react);
+  else
+    hipLaunchKernelGGL((k_p2p<R, LPT, false>), dim3(nblk(waves, wpb)), dim3(64 * wpb), 0, st,
+                       part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles,
+                       tg.tile_box, s.parts, s.p_off + tg.max_tiles, s.partial, t.root, levels, pk,
+                       sd, far2, ser2, cut2, tg.leaf_shift, tg.fine64, s.near, nullptr);
 }
 
 template <typename R>
@@ -658,7 +778,8 @@ void launch_l2p_t(const TreeDev& t, const TargetsDev& tg, int levels, int p, int
   const C* le = reinterpret_cast<const C*>(t.le);  // levels 2 .. L
   hipLaunchKernelGGL((k_l2p<R, PMAX>), dim3(tile_loop_blocks(tg.max_tiles)), dim3(256), 0, st,
                      tpart, tg.tiles, tg.ntiles, tg.perm, t.root, levels, p, le, tg.leaf_shift,
-                     near, tg.sched.p_off, tg.sched.s_off, tg.sched.partial, tg.sched.near, u, v);
+                     near, tg.sched.p_off, tg.sched.s_off, tg.sched.partial, tg.sched.near,
+                     near ? tg.react : nullptr, u, v);
 }
 
 template <typename R>

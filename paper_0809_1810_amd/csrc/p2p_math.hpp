@@ -34,6 +34,11 @@ template <> struct P2PMath<double> {
   __device__ __forceinline__ static double gauss(double g, double r2, double kexp) {
     return g * (exp(r2 * kexp) / r2);
   }
+  // the same kernel values without the circulation (symmetric pairs)
+  __device__ __forceinline__ static double h_near(double r2, double kexp) {
+    return -expm1(r2 * kexp) / r2;
+  }
+  __device__ __forceinline__ static double h_far(double r2) { return 1.0 / r2; }
 };
 
 template <> struct P2PMath<float> {
@@ -68,6 +73,17 @@ template <> struct P2PMath<float> {
   }
   __device__ __forceinline__ static float gauss_s(float g, float r2) {
     return g * __builtin_amdgcn_exp2f(-r2) * __builtin_amdgcn_rcpf(r2);
+  }
+  // the same kernel values without the circulation (symmetric pairs)
+  __device__ __forceinline__ static float h_far(float r2) { return __builtin_amdgcn_rcpf(r2); }
+  __device__ __forceinline__ static float h_near_s(float r2) {
+    return (1.0f - __builtin_amdgcn_exp2f(-r2)) * __builtin_amdgcn_rcpf(r2);
+  }
+  __device__ __forceinline__ static float h_series_s(float r2) {
+    const float ser = 0.6931471805599453f +
+                      r2 * (-0.2402265069591007f + r2 * (0.05550410866482158f +
+                                                         r2 * -0.009618129107628477f));
+    return r2 < kSeriesR2s ? ser : h_near_s(r2);
   }
 };
 

@@ -625,6 +625,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   const int64_t nl = lay.nleaves;
   hipLaunchKernelGGL(k_leaf_start, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, k0, n, nl,
                      lstart);
+  t.n = n;
   t.root = root;
   t.keys = k0;
   t.perm = i0;
@@ -634,6 +635,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.part64 = reinterpret_cast<Part64*>(ws + lay.part64);
   t.part32 = reinterpret_cast<Part32*>(ws + lay.part32);
   t.part32s = reinterpret_cast<Part32*>(ws + lay.part32s);
+  t.react = reinterpret_cast<double2*>(ws + lay.react);
   t.me = ws + lay.me;
   t.le = ws + lay.le;
   t.me32 = ws + lay.me32;

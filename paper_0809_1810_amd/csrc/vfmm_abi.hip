@@ -80,9 +80,11 @@ void set_last_error(const char* msg) { g_err = msg; }
 std::atomic<int> g_tile{kTile};
 std::atomic<int> g_waves{4};
 std::atomic<int> g_m2l_tile{0};
+std::atomic<int> g_sym{0};
 int tuning_tile() { return g_tile.load(); }
 int tuning_waves() { return g_waves.load(); }
 int tuning_m2l_tile() { return g_m2l_tile.load(); }
+int tuning_sym() { return g_sym.load(); }
 
 }  // namespace vfmm
 
@@ -158,6 +160,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
   L.part32s = take(size_t(n) * sizeof(Part32));
+  L.react = take(size_t(n) * sizeof(double2));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
   L.le = take(size_t(nbox) * p_max * sizeof(double2));
   const size_t nb32 = p_max > kShift64P ? size_t(nbox) * p_max * sizeof(float2) : 0;
@@ -243,6 +246,7 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
     delete t;
     return hip_fail(e, "vfmm_build_tree");
   }
+  t->dev.sym = tuning_sym() && t->dev.tile == 64 ? 1 : 0;
   *out = t;
   return VFMM_OK;
 }
@@ -837,6 +841,11 @@ vfmm_status_t vfmm_set_tuning(int32_t param, int32_t value) {
     g_m2l_tile.store(value);
     return VFMM_OK;
   }
+  if (param == VFMM_TUNE_P2P_SYMMETRIC) {
+    if (value != 0 && value != 1) return fail(VFMM_ERR_INVALID_ARG, "P2P symmetric must be 0 or 1");
+    g_sym.store(value);
+    return VFMM_OK;
+  }
   return fail(VFMM_ERR_INVALID_ARG, "unknown tuning parameter %d", param);
 }
 
@@ -844,6 +853,7 @@ int32_t vfmm_get_tuning(int32_t param) {
   if (param == VFMM_TUNE_P2P_TILE) return g_tile.load();
   if (param == VFMM_TUNE_P2P_WAVES) return g_waves.load();
   if (param == VFMM_TUNE_M2L_TILE) return g_m2l_tile.load();
+  if (param == VFMM_TUNE_P2P_SYMMETRIC) return g_sym.load();
   return -1;
 }
 
@@ -852,6 +862,7 @@ int32_t vfmm_tree_get_tuning(vfmm_tree_t t, int32_t param) {
   if (param == VFMM_TUNE_P2P_TILE) return t->dev.tile;
   if (param == VFMM_TUNE_P2P_WAVES) return t->dev.waves;
   if (param == VFMM_TUNE_M2L_TILE) return t->dev.m2l_tile;
+  if (param == VFMM_TUNE_P2P_SYMMETRIC) return t->dev.sym;
   return -1;
 }
 

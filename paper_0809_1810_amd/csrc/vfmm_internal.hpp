@@ -121,7 +121,7 @@ struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, sched_near;
-  size_t part64, part32, part32s, me, le, me32, le32, ops, check, total;
+  size_t part64, part32, part32s, react, me, le, me32, le32, ops, check, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
 };
@@ -130,6 +130,7 @@ Layout make_layout(int64_t n, int levels, int p_max);
 
 // Device tree state: pointers into the caller's workspace.
 struct TreeDev {
+  int64_t n;             // particles
   double* root;          // [0]=x0 [1]=y0 [2]=S [3]=w_L
   uint32_t* keys;        // sorted leaf keys
   int32_t* perm;         // sorted position -> input index
@@ -138,6 +139,8 @@ struct TreeDev {
   int waves;             // waves per workgroup of the near-field launch: 1, 2, 4 or 8
   int m2l_tile;          // FP32 matrix-core M2L tile for p <= 16: 0 operands in registers,
                          // 1 / 2 sources staged in LDS with 4 / 8 waves per workgroup
+  int sym;               // near field at the particles with the leaf pairs of the local list
+                         // evaluated once (both directions; 64-particle tiles only)
   int64_t max_tiles;     // capacity of the tile arrays
   Tile* tiles;           // P2P target tiles (<= tile consecutive particles of one leaf)
   int32_t* ntiles;       // device count of tiles
@@ -152,6 +155,8 @@ struct TreeDev {
   void* le32;
   void* ops;
   unsigned long long* check;  // [2] counters of the opt-in finiteness check
+  double2* react;        // [n] sorted order: near-field sums the symmetric pairs add to their
+                         // source particles (unscaled, before 1 / 2 pi)
   P2PSched sched;        // near-field schedule of the particles as targets
 };
 
@@ -176,11 +181,19 @@ struct TargetsDev {
   // adaptive tree: per target the tree's leaf-local record, with the
   // leaf-level box in place of the circulation (offsets to the sources)
   const Part64* fine64;
+  // symmetric near field (targets = the tree's particles, uniform tree,
+  // 64-particle tiles; NULL otherwise): a target tile takes, of the local
+  // list, its own leaf and the four neighbours E, NW, N, NE, and every pair
+  // with a neighbour also adds the opposite contribution to the source
+  // particle's entry here; the other four neighbours reach the tile that way
+  double2* react;
 };
 
 inline TargetsDev self_targets(const TreeDev& t, const Layout& lay) {
-  return TargetsDev{t.part64, t.part32, t.tiles, t.ntiles, t.tile_box, t.tile_off, t.perm,
-                    lay.max_tiles, t.sched};
+  TargetsDev tg{t.part64, t.part32, t.tiles, t.ntiles, t.tile_box, t.tile_off, t.perm,
+                lay.max_tiles, t.sched};
+  tg.react = t.sym ? t.react : nullptr;
+  return tg;
 }
 
 // Workspace of a separate evaluation-point set of nt points at leaf level L.
@@ -213,6 +226,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
 int tuning_tile();
 int tuning_waves();
 int tuning_m2l_tile();
+int tuning_sym();
 // Circulations into the sorted particle records; with sigma > 0 also the
 // FP32 near-field sources scaled by sqrt(log2(e) / (2 sigma^2)) (part32s).
 hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,

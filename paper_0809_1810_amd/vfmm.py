@@ -142,7 +142,7 @@ class Instance(C.Structure):
                 ("v", C.c_void_p), ("n", C.c_int64), ("sigma", C.c_double), ("p", C.c_int32),
                 ("levels", C.c_int32)]
 
-TUNE_P2P_TILE, TUNE_P2P_WAVES, TUNE_M2L_TILE = 1, 2, 3
+TUNE_P2P_TILE, TUNE_P2P_WAVES, TUNE_M2L_TILE, TUNE_P2P_SYMMETRIC = 1, 2, 3, 4
 
 SELECT_AUDIT, SELECT_CUTOFF = 1, 2
 SELECT_TRAIL_MAX = 16
@@ -372,10 +372,11 @@ class Tree:
                "vfmm_tree_set_check_finite")
 
     def tuning(self):
-        """The launch shapes this tree was built with: {tile, waves, m2l}."""
+        """The launch shapes this tree was built with: {tile, waves, m2l, sym}."""
         return {"tile": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_TILE)),
                 "waves": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_WAVES)),
-                "m2l": int(lib().vfmm_tree_get_tuning(self._h, TUNE_M2L_TILE))}
+                "m2l": int(lib().vfmm_tree_get_tuning(self._h, TUNE_M2L_TILE)),
+                "sym": int(lib().vfmm_tree_get_tuning(self._h, TUNE_P2P_SYMMETRIC))}
 
     def enable_timing(self, max_calls: int):
         _check(lib().vfmm_tree_enable_timing(self._h, int(max_calls)), "vfmm_tree_enable_timing")
@@ -757,18 +758,22 @@ class Batch:
             pass
 
 
-def set_tuning(tile=None, waves=None, m2l=None):
+def set_tuning(tile=None, waves=None, m2l=None, sym=None):
     """Launch shapes for trees built afterwards: near-field tile size (64/32/16),
-    near-field waves per workgroup (1/2/4/8), FP32 matrix-core M2L tile (0/1/2)."""
+    near-field waves per workgroup (1/2/4/8), FP32 matrix-core M2L tile (0/1/2),
+    symmetric near field (0/1, 64-particle tiles)."""
     if tile is not None:
         _check(lib().vfmm_set_tuning(TUNE_P2P_TILE, int(tile)), "vfmm_set_tuning")
     if waves is not None:
         _check(lib().vfmm_set_tuning(TUNE_P2P_WAVES, int(waves)), "vfmm_set_tuning")
     if m2l is not None:
         _check(lib().vfmm_set_tuning(TUNE_M2L_TILE, int(m2l)), "vfmm_set_tuning")
+    if sym is not None:
+        _check(lib().vfmm_set_tuning(TUNE_P2P_SYMMETRIC, int(sym)), "vfmm_set_tuning")
 
 
 def get_tuning():
     return {"tile": int(lib().vfmm_get_tuning(TUNE_P2P_TILE)),
             "waves": int(lib().vfmm_get_tuning(TUNE_P2P_WAVES)),
-            "m2l": int(lib().vfmm_get_tuning(TUNE_M2L_TILE))}
+            "m2l": int(lib().vfmm_get_tuning(TUNE_M2L_TILE)),
+            "sym": int(lib().vfmm_get_tuning(TUNE_P2P_SYMMETRIC))}

@@ -52,3 +52,23 @@ def test_m2l_tile_lookup(tmp_path):
     assert AT.lookup_m2l(1 << 20, 6, str(p)) == 2
     assert AT.lookup_m2l(1 << 20, 8, str(p)) == 0    # entry without M2L timings
     assert AT.lookup_m2l(1000, 3, str(tmp_path / "absent.json")) == 0
+
+
+def test_symmetric_shapes(tmp_path):
+    """Shapes timed with the symmetric near field ("64x<w>s") win when fastest,
+    with and without the cut-off; entries without them keep sym = 0."""
+    entries = [
+        {"ppl_log2": 6.0, "tile": 64, "waves": 2,
+         "all_ms": {"64x1": 2.2, "64x2": 2.1, "16x4": 3.0, "64x1s": 1.9, "64x2s": 2.0},
+         "cutoff_ms": {"64x1": 2.08, "64x2": 2.11, "64x1s": 2.2, "64x2s": 1.85}},
+        {"ppl_log2": 2.0, "tile": 32, "waves": 2,
+         "all_ms": {"32x2": 1.0, "64x1s": 1.4}},
+    ]
+    p = tmp_path / "tuning.json"
+    p.write_text(json.dumps({"entries": entries}))
+    path = str(p)
+    assert AT.lookup_shape(1 << 20, 7, path) == (64, 1, 1)
+    assert AT.lookup_shape(1 << 20, 7, path, cutoff=True) == (64, 2, 1)
+    assert AT.lookup(1 << 20, 7, path, cutoff=True) == (64, 2)
+    assert AT.lookup_shape(1 << 20, 9, path) == (32, 2, 0)
+    assert AT.lookup_shape(1000, 3, str(tmp_path / "absent.json")) == (64, 4, 0)

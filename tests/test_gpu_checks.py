@@ -39,14 +39,14 @@ def test_two_trees_keep_their_own_launch_shape(vf):
         vf.set_tuning(tile=64, waves=1, m2l=2)
         tb = vf.Tree(x, y, L, p_max=p)
         vf.set_tuning(tile=32, waves=2, m2l=1)  # neither tree follows later settings
-        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0}
-        assert tb.tuning() == {"tile": 64, "waves": 1, "m2l": 2}
+        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0, "sym": 0}
+        assert tb.tuning() == {"tile": 64, "waves": 1, "m2l": 2, "sym": 0}
         r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L)
         for t in (ta, tb, ta):
             u, v = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
             assert rel_err(u, v, r.u, r.v)[0] < 1e-12
         ta.rebuild(x, y)  # a rebuild keeps the tree's shape
-        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0}
+        assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0, "sym": 0}
         ta.close(); tb.close()
     finally:
         vf.set_tuning(tile=old["tile"], waves=old["waves"], m2l=old["m2l"])
