@@ -81,7 +81,8 @@ namespace {
 // Symmetric near field (sym): of the local list only the leaf itself and the
 // neighbours after it in (row, leaf) order -- E in its own row, NW, N and NE
 // above -- remain; row by - 1 and leaf bx - 1 are left out, each such pair of
-// leaves being evaluated once, for both, by the tiles of the earlier leaf.
+// leaves being evaluated once, for both, by the tiles of the earlier leaf
+// (within the leaf itself likewise: each pair of its tiles by the earlier one).
 __device__ __forceinline__ bool segment(int s, int bx, int by, int m, bool sym, int& sy, int& lo,
                                         int& hi) {
   int d0, d1;
@@ -477,9 +478,20 @@ __global__ void __launch_bounds__(512) k_p2p(
           const R tx = tx0 - R(oxt * wsd);
           const float bx0 = tb.x - float(ox * w), bx1 = tb.y - float(ox * w);
           const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
-          // a neighbour leaf of the symmetric near field: both directions here
-          const bool sym_leaf = sym && !ring && !(sx == bx && sy == by);
+          // symmetric near field: a neighbour leaf's chunks take both
+          // directions here; in the tile's own leaf (whose chunks are its
+          // tiles) the chunks after the tile's own do, its own chunk takes one
+          // direction, and the chunks before it were done by their tiles
+          const bool self_leaf = sx == bx && sy == by;
+          const bool sym_leaf = sym && !ring && !self_leaf;
+          const int own = sym && self_leaf ? (t_start - js) / T : 0;
           for (uint32_t ci = qa; ci < qb; ++ci) {
+            bool sym_pair = sym_leaf;
+            if (sym && self_leaf) {
+              const int c = int(ci - la);
+              if (c < own) continue;
+              sym_pair = c > own;
+            }
             const int32_t j0 = js + int32_t(ci - la) * T;
             const int32_t j1 = min(j0 + T, je);
             const float4 sb = tile_box[ci];
@@ -526,7 +538,7 @@ __global__ void __launch_bounds__(512) k_p2p(
                   cv -= f * dx;
                 }
               }
-            } else if (sym_leaf) {
+            } else if (sym_pair) {
               // stage the chunk (padding: zero circulation at the leaf centre)
               SymRec<R> rec{R(0), R(0), R(0), R(0)};
               if (j0 + lane < j1) {

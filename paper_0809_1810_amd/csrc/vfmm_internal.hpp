@@ -183,9 +183,10 @@ struct TargetsDev {
   const Part64* fine64;
   // symmetric near field (targets = the tree's particles, uniform tree,
   // 64-particle tiles; NULL otherwise): a target tile takes, of the local
-  // list, its own leaf and the four neighbours E, NW, N, NE, and every pair
-  // with a neighbour also adds the opposite contribution to the source
-  // particle's entry here; the other four neighbours reach the tile that way
+  // list, the tiles of its own leaf from itself on and the four neighbours E,
+  // NW, N, NE, and every pair with another tile also adds the opposite
+  // contribution to the source particle's entry here; the rest of the local
+  // list reaches the tile that way
   double2* react;
 };
 

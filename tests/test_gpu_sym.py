@@ -3,7 +3,8 @@
 K_sigma is odd (eq. 6: K(-x) = -K(x)), so a pair of particles needs one kernel
 value for both directions.  With the setting on, a tree with 64-particle tiles
 evaluates each pair of two different leaves of the local list once: the tiles
-of a leaf take their own leaf and the neighbours E, NW, N, NE, and add the
+of a leaf take the tiles of their own leaf from themselves on and the
+neighbours E, NW, N, NE, and add the
 opposite contributions to the source particles.  Every pair must still be
 counted exactly once in each direction, which the float64 comparison with the
 oracle checks to 1e-12 of the maximum velocity (near part 1e-13): a missing or
