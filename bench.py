@@ -183,9 +183,10 @@ def radius_tag(radius, sigma):
     return "auto" if radius < 0 else (0.0 if radius == 0 else round(radius / sigma, 3))
 
 
-def recorded_traffic(workload, p, levels, radius=0.0, sigma=1.0):
+def recorded_traffic(workload, p, levels, radius=0.0, sigma=1.0, sym=0):
     """HBM bytes per P2P launch from the committed rocprofv3 counter runs, or None
-    when the kernel source or the configuration differs from the measured one."""
+    when the kernel source or the configuration (symmetric near field included)
+    differs from the measured one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "p2p_traffic_clusters_1m.json")
     csrc = os.path.join(ROOT, "paper_0809_1810_amd", "csrc")
@@ -198,7 +199,8 @@ def recorded_traffic(workload, p, levels, radius=0.0, sigma=1.0):
     if (rec.get("p2p_source_sha256") != cur or rec.get("p2p_math_sha256") != cur_math
             or rec.get("workload") != workload
             or rec.get("p") != p or rec.get("levels") != levels
-            or rec.get("near_radius_sigma", 0.0) != radius_tag(radius, sigma)):
+            or rec.get("near_radius_sigma", 0.0) != radius_tag(radius, sigma)
+            or rec.get("sym", 0) != sym):
         return None
     return float(rec["traffic_bytes"])
 
@@ -312,6 +314,7 @@ def main():
         from paper_0809_1810_amd import selector as S
         weights = S.load_weights()
         s0 = time.perf_counter()
+        selection_shape(n)
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=weights, targets=tg_d,
                                reference=(ud, vd))
         torch.cuda.synchronize()
@@ -374,7 +377,7 @@ def main():
         tree.close()
         return dict(ms=ms, wall_s=wall, phases=phases, far_phases=far_phases, emax=emax, erms=erms,
                     holdout_emax=hmax, holdout_erms=hrms,
-                    pairs=pairs, tile_waves=[tw["tile"], tw["waves"]])
+                    pairs=pairs, tile_waves=[tw["tile"], tw["waves"]], sym=tw["sym"])
 
     log(f"[bench] tuned: p={p_t} L={L_t} precision={a.precision} near radius={radius_t}")
     tuned = run_path(L_t, p_t, prec_t, a.steps, a.warmup, timing=True, radius=radius_t)
@@ -403,8 +406,9 @@ def main():
     achieved = P2P_FLOPS_PER_PAIR * tuned["pairs"] / (p2p_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t, P.sigma),
-                "kernel": "k_p2p<float>", "kernel_ms": round(p2p_ms, 4),
+                "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t, P.sigma, tuned["sym"]),
+                "kernel": "k_p2p<float> (symmetric near field)" if tuned["sym"] else "k_p2p<float>",
+                "kernel_ms": round(p2p_ms, 4),
                 "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR,
                 "work_counted": "local-list pairs only (cut-off ring pairs not counted)"
                 if radius_t else "local-list pairs"}
@@ -441,7 +445,7 @@ def main():
             "workload": f"{P.name}: N={n}, sigma={P.sigma}, seeded synthetic",
             "p": p_t, "levels": L_t, "precision": "fp64" if prec_t == vf.FP64 else a.precision,
             "selector": selector, "selector_info": sel_info, "audit_targets": n_audit,
-            "p2p_tile_waves": tuned["tile_waves"],
+            "p2p_tile_waves": tuned["tile_waves"], "p2p_symmetric": bool(tuned["sym"]),
             "near_radius": ("auto: min(6 sigma, 4 w_L), distance cut-off of the near field"
                             if radius_t < 0 else radius_t),
             "near_radius_sigma": radius_tag(radius_t, P.sigma),
@@ -521,6 +525,7 @@ def second_input(a, torch, vf, name):
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg)
     th = torch.from_numpy(holdout_targets(n, AUDIT_TARGETS, tg_h, HOLDOUT_SEED)).cuda()
     uh, vh = vf.direct_velocity(x, y, g, P.sigma, targets=th)
+    selection_shape(n)
     r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights(), targets=tg,
                            reference=(ud, vd))
     prec = vf.FP64 if r["precision"] == "fp64" else vf.FP32
@@ -558,6 +563,14 @@ def second_input(a, torch, vf, name):
             "audit_emax": r["audit_emax"], "audit_trail": r["trail"],
             "plain_fp64": {"ms_per_step": round(ms_p, 4), "p": 20, "levels": Lp, "emax": e_p},
             "speedup_vs_plain": round(ms_p / ms_t, 3)}
+
+
+def selection_shape(n):
+    """The selection's trial trees take the process-wide launch shape: set the
+    tuning table's shape for about 64 particles per leaf with the cut-off, so
+    that every workload's candidates are timed the way their timed path runs."""
+    from paper_0809_1810_amd import autotune as AT
+    AT.apply_for(n, max(2, int(round(math.log(max(n, 64) / 64.0, 4)))), cutoff=True)
 
 
 def override_tuning(a, vf):
@@ -608,6 +621,7 @@ def bench_eval_points(a, torch, vf):
         p, L, prec, how = a.p, a.levels, vf.PRECISIONS[a.precision], "fixed"
         radius = fixed_radius(a, P.sigma, vf)
     else:
+        selection_shape(n)
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]
         prec = vf.FP64 if r["precision"] == "fp64" else vf.PRECISIONS[a.precision]
@@ -683,6 +697,7 @@ def bench_advect(a, torch, vf):
         p, L = a.p, a.levels
         radius = fixed_radius(a, P.sigma, vf)
     else:
+        selection_shape(n)
         r = S.select_and_audit(x0, y0, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]
     Lp = largest_level(side, P.sigma, 8.0)

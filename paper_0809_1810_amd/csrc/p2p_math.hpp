@@ -77,7 +77,8 @@ template <> struct P2PMath<float> {
   // the same kernel values without the circulation (symmetric pairs)
   __device__ __forceinline__ static float h_far(float r2) { return __builtin_amdgcn_rcpf(r2); }
   __device__ __forceinline__ static float h_near_s(float r2) {
-    return (1.0f - __builtin_amdgcn_exp2f(-r2)) * __builtin_amdgcn_rcpf(r2);
+    const float r = __builtin_amdgcn_rcpf(r2);
+    return __builtin_fmaf(-__builtin_amdgcn_exp2f(-r2), r, r);  // (1 - e) / r'^2 in one op
   }
   __device__ __forceinline__ static float h_series_s(float r2) {
     const float ser = 0.6931471805599453f +
