@@ -412,8 +412,10 @@ vfmm_status_t vfmm_select_params(const double* x, const double* y, const double*
  *      pair's kernel difference falls to the tolerance; the cut-off only where
  *      VFMM_NEAR_RINGS_MAX leaf sides reach 6 sigma), each audited; the passing
  *      ones and the choice of step 2 are timed (median of time_reps tree
- *      rebuild + evaluation runs between HIP events on `stream`) and the
- *      fastest is returned.
+ *      rebuild + evaluation runs between HIP events on `stream`); the
+ *      fastest neighbour is returned if it is more than 3 % faster than the
+ *      choice of step 2 (the spread of repeated timings), else that choice.
+ *      The trial trees take the process-wide tuning (vfmm_set_tuning).
  * Every evaluation is recorded in out->steps (at most VFMM_SELECT_TRAIL_MAX).
  *   params, feat_mean, feat_std, margin: as in vfmm_select_params.
  *   max_levels: deepest tree the workspace is sized for (<= 0: the default,

@@ -605,7 +605,9 @@ static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y
   // at sigma sqrt(2 ln(1/tol)), where one pair's kernel difference falls to
   // the tolerance; the cut-off only where the clamp at VFMM_NEAR_RINGS_MAX
   // leaf sides leaves 6 sigma uncut.  Each is audited; the passing ones are
-  // timed and the fastest is kept.
+  // timed, and the fastest replaces the accepted choice only if it is faster
+  // by more than kTimeMargin (the spread of repeated timings of one
+  // configuration), so that a tie keeps the network's choice.
   const double radii3[3] = {0.0, VFMM_NEAR_RADIUS_AUTO,
                             sigma * std::sqrt(2.0 * std::log(1.0 / tol))};
   int cand_L[9];
@@ -624,7 +626,8 @@ static vfmm_status_t vfmm_select_and_audit_impl(const double* x, const double* y
   double e0 = 0.0, ms0 = 0.0;
   if ((s = a.run(p, L, VFMM_FP32, rad, true, e0, ms0))) return s;
   out->steps[out->n_steps - 1].ms = ms0;  // the accepted step, now timed
-  double best_ms = ms0, best_e = e, best_r = rad;
+  constexpr double kTimeMargin = 0.03;
+  double best_ms = ms0 * (1.0 - kTimeMargin), best_e = e, best_r = rad;
   int best_L = L;
   for (int k = 0; k < nc; ++k) {
     double ec = 0.0, msc = 0.0;

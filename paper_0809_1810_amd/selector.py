@@ -247,7 +247,9 @@ def select_and_audit(x, y, g, sigma, tol, weights=None, n_audit=8192, seed=0, au
     choice is evaluated in FP64.  With ``cutoff``, an accepted FP32 choice is
     compared with the same p one or two levels deeper under the distance
     cut-off of the near field (Section 4.1's distance a) at two radii; the
-    fastest passing candidate is kept.
+    fastest passing candidate replaces the choice if it is more than 3 % faster.
+    The trial trees take the process-wide tuning (set it first, e.g. with
+    ``autotune.apply_for``).
 
     ``targets`` (device int64) and ``reference`` ((u, v) of the direct sum
     there) may be supplied; otherwise n_audit targets are drawn with ``seed``.

@@ -49,7 +49,7 @@ def test_two_trees_keep_their_own_launch_shape(vf):
         assert ta.tuning() == {"tile": 16, "waves": 8, "m2l": 0, "sym": 0}
         ta.close(); tb.close()
     finally:
-        vf.set_tuning(tile=old["tile"], waves=old["waves"], m2l=old["m2l"])
+        vf.set_tuning(**old)
 
 
 def _nonfinite(vf, fn):

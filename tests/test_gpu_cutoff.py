@@ -141,7 +141,7 @@ def test_clusters_full_size_benchmark_configuration(vf):
         u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
         t.close()
     finally:
-        vf.set_tuning(tile=saved["tile"], waves=saved["waves"])
+        vf.set_tuning(**saved)
     tg = W.sample_targets(P.n, 256, seed=32)
     r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=tg, radius=radius)
     assert rel_err(u64[tg], v64[tg], r.u, r.v)[0] < 1e-12
@@ -178,7 +178,7 @@ def test_cutoff_on_every_tile_shape(vf, tile, waves):
         u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
         t.close()
     finally:
-        vf.set_tuning(tile=saved["tile"], waves=saved["waves"])
+        vf.set_tuning(**saved)
     r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, radius=radius)
     assert rel_err(u64, v64, r.u, r.v)[0] < 1e-12
     assert rel_err(u32, v32, u0, v0)[0] < 1e-6

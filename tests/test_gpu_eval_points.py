@@ -72,17 +72,30 @@ def test_velocity_at_particles_equals_velocity(vf):
     P = W.config("lattice_320")
     L, p = 5, 12
     print_case("at_particles", n=P.n)
-    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
     x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
-    for prec in (vf.FP64, vf.FP32, vf.M2L_BF16):
-        u0, v0 = (host(a) for a in t.velocity(g, P.sigma, p, prec))
-        u1, v1 = (host(a) for a in t.velocity_at(g, P.sigma, p, x, y, prec))
-        assert np.array_equal(u0, u1) and np.array_equal(v0, v1), prec
-    # a subset in a shuffled order: float64 agrees to rounding
-    idx = np.random.default_rng(4).permutation(P.n)[:5000]
-    u0, v0 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
-    u1, v1 = (host(a) for a in t.velocity_at(g, P.sigma, p, dev(P.x[idx]), dev(P.y[idx]), vf.FP64))
-    assert rel_err(u1, v1, u0[idx], v0[idx])[0] < 1e-15
+    saved = vf.get_tuning()
+    try:
+        vf.set_tuning(sym=0)  # both paths one direction per pair: the same sums
+        t = vf.Tree(x, y, L, p_max=p)
+        for prec in (vf.FP64, vf.FP32, vf.M2L_BF16):
+            u0, v0 = (host(a) for a in t.velocity(g, P.sigma, p, prec))
+            u1, v1 = (host(a) for a in t.velocity_at(g, P.sigma, p, x, y, prec))
+            assert np.array_equal(u0, u1) and np.array_equal(v0, v1), prec
+        # a subset in a shuffled order: float64 agrees to rounding
+        idx = np.random.default_rng(4).permutation(P.n)[:5000]
+        u0, v0 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+        u1, v1 = (host(a) for a in t.velocity_at(g, P.sigma, p, dev(P.x[idx]), dev(P.y[idx]),
+                                                 vf.FP64))
+        assert rel_err(u1, v1, u0[idx], v0[idx])[0] < 1e-15
+        # a tree with the symmetric near field: its particle path sums the
+        # same pairs in another order, the points keep one direction per pair
+        vf.set_tuning(tile=64, sym=1)
+        ts = vf.Tree(x, y, L, p_max=p)
+        u0, v0 = (host(a) for a in ts.velocity(g, P.sigma, p, vf.FP64))
+        u1, v1 = (host(a) for a in ts.velocity_at(g, P.sigma, p, x, y, vf.FP64))
+        assert rel_err(u1, v1, u0, v0)[0] < 1e-14
+    finally:
+        vf.set_tuning(**saved)
 
 
 def test_section52_single_source_on_lattice(vf):

@@ -207,7 +207,7 @@ def test_m2l_tile_variants_agree(vf, p, levels):
                 les[64] = [host(t.expansions(1, l, p)) for l in range(2, levels + 1)]
             t.close()
     finally:
-        vf.set_tuning(m2l=old["m2l"])
+        vf.set_tuning(**old)
     for mode in (1, 2):
         for a, b, c in zip(les[mode], les[0], les[64]):
             scale = np.max(np.abs(c))

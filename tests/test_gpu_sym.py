@@ -37,7 +37,7 @@ def sym_on(vf):
     old = vf.get_tuning()
     vf.set_tuning(tile=64, sym=1)
     yield
-    vf.set_tuning(tile=old["tile"], waves=old["waves"], m2l=old["m2l"], sym=old["sym"])
+    vf.set_tuning(**old)
 
 
 @pytest.mark.parametrize("case,levels,waves", [("clusters_20k", 3, 1), ("clusters_20k", 5, 4),
