@@ -756,9 +756,15 @@ def bench_batched(a, torch, vf):
         dev.append(dict(x=torch.from_numpy(P.x).cuda(), y=torch.from_numpy(P.y).cuda(),
                         gamma=torch.from_numpy(P.gamma).cuda(), sigma=P.sigma, p=p, levels=L))
     ntot = sum(P.n for P, _, _ in insts)
+    # the symmetric near field for the instances with well filled leaves
+    # (--p2p-sym 0 turns it off); the single-tree comparison keeps the default
+    sym = 0 if a.p2p_sym == 0 else 1
+    saved = vf.get_tuning()
+    vf.set_tuning(sym=sym)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         b = vf.Batch(dev)
+        vf.set_tuning(**saved)
         for _ in range(a.warmup):
             b.run(use_graph=True)
         s.synchronize()
@@ -800,13 +806,15 @@ def bench_batched(a, torch, vf):
             t.close()
     errs, errs_fmm = np.array(errs), np.array(errs_fmm)
     ps = np.array([p for _, p, _ in insts])
+    floors = np.array(b.substitution_bounds())
     out = {"metric": "instances/s, 256 uneven FMM instances in one batched graph replay",
            "value": round(256 / (graph_ms * 1e-3), 1), "unit": "instances/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(graph_ms, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": f"256 instances, N log-uniform [2048, 65536] (total {ntot}), "
-                                  "uniform or lattice, p 5..20, levels 3..6, sigma = h/0.8, seed 4"},
+                                  "uniform or lattice, p 5..20, levels 3..6, sigma = h/0.8, seed 4",
+                      "p2p_symmetric": bool(sym)},
            "particles_per_s": round(ntot / (graph_ms * 1e-3), 1),
            "eager_batched_ms": round(eager_ms, 4), "one_call_per_instance_ms": round(loop_ms, 4),
            "speedup_vs_per_instance": round(loop_ms / graph_ms, 3),
@@ -816,7 +824,13 @@ def bench_batched(a, torch, vf):
                                  "note": "vs the FP64 direct sum: includes the truncation and the "
                                          "kernel-substitution error of the instance's own (p, levels)"},
            "per_instance_emax_vs_fp64_fmm": {"median": float(np.median(errs_fmm)),
-                                             "max": float(errs_fmm.max())}}
+                                             "max": float(errs_fmm.max())},
+           "substitution_floor": {"max": float(floors.max()),
+                                  "instances_above_1e-6": int((floors > 1e-6).sum()),
+                                  "max_emax_where_floor_le_1e-9": float(errs[floors <= 1e-9].max())
+                                  if (floors <= 1e-9).any() else None,
+                                  "note": "vfmm_batch_substitution_bounds: 1 / (exp(w_L^2 / 2 "
+                                          "sigma^2) - 1) per instance"}}
     print(json.dumps(out), flush=True)
 
 

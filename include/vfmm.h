@@ -611,7 +611,11 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
  *                        order varies from run to run (results reproducible
  *                        to float64 rounding of those sums, not bit for bit).
  *                        Evaluation points and the adaptive tree always take
- *                        both directions separately.
+ *                        both directions separately.  vfmm_batch_create reads
+ *                        it too: a batch planned with it uses it for the
+ *                        instances with at least 48 particles per leaf on
+ *                        average (a symmetric pair of chunks always takes 64
+ *                        steps, which sparse leaves do not fill).
  * Results do not depend on the settings beyond float32 summation order. */
 #define VFMM_TUNE_P2P_TILE 1
 #define VFMM_TUNE_P2P_WAVES 2

@@ -40,7 +40,8 @@ struct BatchInst {
   int64_t leaf_off;  // first global leaf; leaf_start entries start at leaf_off + index
   int64_t me_off;    // byte offset of the level-2 coefficients in the ME / LE buffers
   double sigma;
-  int32_t p, L, fp64, pad;
+  int32_t p, L, fp64;
+  int32_t sym;  // symmetric near field for this instance (see k_b_p2p)
 };
 
 constexpr int kBatchMaxLevels = 6;   // leaf index fits 12 key bits
@@ -51,6 +52,7 @@ constexpr int kBatchSub = 2;
 constexpr int kBatchKeyInst = 12 + 2 * kBatchSub;  // key = inst << 16 | leaf << 4 | sub-cell
 constexpr int kBatchMaxCount = 4096;
 constexpr int kBatchP2PWaves = 4;  // near-field waves (tiles) per workgroup
+constexpr int kBatchSymMinPPL = 48;  // mean particles per leaf for the symmetric near field
 constexpr int kBatchPMax = 24;
 
 namespace {
@@ -497,6 +499,23 @@ __device__ __forceinline__ void l2p_eval(const BatchInst& in, const char* le, in
   fv = double(acc.x) * sc;
 }
 
+// Circulation-free kernel values of the symmetric pairs (r'^2 in units of the
+// Gaussian width).
+struct BatchSymK {
+  __device__ __forceinline__ float hnear(float r2) const { return P2PMath<float>::h_near_s(r2); }
+  __device__ __forceinline__ float hseries(float r2) const { return P2PMath<float>::h_series_s(r2); }
+  __device__ __forceinline__ float hfar(float r2) const { return P2PMath<float>::h_far(r2); }
+};
+
+// SYM: the launch holds instances with the symmetric near field
+// (p2p_math.hpp; BatchInst::sym): of its 3 x 3 local list a tile of such an
+// instance takes the neighbours after its leaf in (row, leaf) order -- E, NW,
+// N, NE -- and, in its own leaf, the chunks from its own on; each pair of
+// different chunks adds the opposite contributions to react (the other
+// neighbours' and the earlier chunks' pairs reach the tile that way).  A
+// symmetric chunk pair always takes 64 steps, so only instances with well
+// filled leaves use it (set at plan creation).
+template <bool SYM>
 __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
                                                const Part32* __restrict__ part,
                                                const int32_t* __restrict__ start,
@@ -505,7 +524,9 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
                                                const uint32_t* __restrict__ tile_off,
                                                const float4* __restrict__ tile_box,
                                                const double* __restrict__ roots,
-                                               double2* __restrict__ nearv) {
+                                               double2* __restrict__ nearv,
+                                               double2* __restrict__ react) {
+  extern __shared__ unsigned char b_p2p_lds[];
   const int wid =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (wid >= *ntiles) return;
@@ -527,28 +548,42 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
   const float ser2 = float(P2PMath<float>::kSeriesSigma2 * 1.4426950408889634074 / 2.0);
   const float tiny = float(wsd * wsd * 0x1p-80);
   const float4 tb = tile_box[wid];
+  SymRec<float>* const sbuf = reinterpret_cast<SymRec<float>*>(b_p2p_lds) + (threadIdx.x >> 6) * 128;
+  const bool sym = SYM && __builtin_amdgcn_readfirstlane(in.sym) != 0;
+  const float tg = sym && active ? tp.g : 0.f;
   Acc32 au{0.f, 0.f}, av{0.f, 0.f};
-  for (int oy = -1; oy <= 1; ++oy) {
+  for (int oy = sym ? 0 : -1; oy <= 1; ++oy) {
     const int sy = by + oy;
     if (sy < 0 || sy >= m) continue;
-    for (int ox = -1; ox <= 1; ++ox) {
+    for (int ox = sym && oy == 0 ? 0 : -1; ox <= 1; ++ox) {
       const int sx = bx + ox;
       if (sx < 0 || sx >= m) continue;
       const int64_t gsl = in.leaf_off + sy * m + sx;
       const int32_t js = start[gsl + c], je = start[gsl + c + 1];
+      const bool self_leaf = ox == 0 && oy == 0;
+      const int32_t own = sym && self_leaf ? (tile.start - js) >> 6 : 0;
       const float tx = tp.x - float(double(ox) * wsd);
       const float ty = tp.y - float(double(oy) * wsd);
       const float bx0 = tb.x - float(double(ox) * wsd), bx1 = tb.y - float(double(ox) * wsd);
       const float by0 = tb.z - float(double(oy) * wsd), by1 = tb.w - float(double(oy) * wsd);
       uint32_t ci = tile_off[gsl];
       for (int32_t j0 = js; j0 < je; j0 += 64, ++ci) {
+        bool sym_pair = sym && !self_leaf;
+        if (sym && self_leaf) {
+          const int32_t rel = (j0 - js) >> 6;
+          if (rel < own) continue;
+          sym_pair = rel > own;
+        }
         const int32_t j1 = min(j0 + 64, je);
         const float4 sb = tile_box[ci];
         const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
         const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
         const float gap2 = gx * gx + gy * gy;
         float cu = 0.f, cv = 0.f;
-        if (gap2 > far2) {
+        if (sym_pair) {
+          sym_pair_chunk(sbuf, part, j0, j1, lane, tx, ty, tg, tiny, BatchSymK{},
+                         gap2 > far2 ? 2 : (gap2 > ser2 ? 0 : 1), 1.0, react, cu, cv);
+        } else if (gap2 > far2) {
 #pragma unroll 8
           for (int32_t j = j0; j < j1; ++j) {
             const Part32 s = part[j];
@@ -585,6 +620,11 @@ __global__ void __launch_bounds__(256) k_b_p2p(const BatchInst* __restrict__ I,
   if (active) nearv[i] = make_double2(au.value(), av.value());
 }
 
+__global__ void __launch_bounds__(256) k_b_zero2(double2* __restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    a[i] = make_double2(0.0, 0.0);
+}
+
 // One wave per tile, after the near field and the expansion sweeps: the near
 // sums of k_b_p2p scaled to velocities (each pair term is
 // Gamma (...) d' / r'^2 = (1 / sd) Gamma (...) d / r^2) plus the far field (L2P),
@@ -595,6 +635,7 @@ __device__ __forceinline__ void b_l2p_tile(int wid, int lane, const BatchInst* _
                                            const double* __restrict__ roots,
                                            const char* __restrict__ le,
                                            const double2* __restrict__ nearv,
+                                           const double2* __restrict__ react,
                                            const int32_t* __restrict__ perm) {
   const Tile tile = tiles[wid];
   if (lane >= tile.count) return;
@@ -610,7 +651,12 @@ __device__ __forceinline__ void b_l2p_tile(int wid, int lane, const BatchInst* _
     if (in.fp64) l2p_eval<double>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
     else l2p_eval<float>(in, le, leaf, tp.x, tp.y, wsd, w, fu, fv);
   }
-  const double2 q = nearv[i];
+  double2 q = nearv[i];
+  if (react) {  // the symmetric pairs' contributions to this particle as a source
+    const double2 r = react[i];
+    q.x += r.x;
+    q.y += r.y;
+  }
   const double k = kInv2Pi * near_scale(in.sigma);
   const int64_t o = int64_t(perm[i]) - in.part_off;
   in.u[o] = __builtin_fma(q.x, k, fu);
@@ -625,12 +671,13 @@ __global__ void __launch_bounds__(256) k_b_l2p(const BatchInst* __restrict__ I,
                                                const double* __restrict__ roots,
                                                const char* __restrict__ le,
                                                const double2* __restrict__ nearv,
+                                               const double2* __restrict__ react,
                                                const int32_t* __restrict__ perm) {
   const int nt = *ntiles;
   const int lane = threadIdx.x & 63;
   for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); wid < nt;
        wid += 4 * gridDim.x)
-    b_l2p_tile(wid, lane, I, part, tiles, roots, le, nearv, perm);
+    b_l2p_tile(wid, lane, I, part, tiles, roots, le, nearv, react, perm);
 }
 
 }  // namespace
@@ -656,6 +703,7 @@ struct BatchPlanDev {
   Part32* p32;
   char *me, *le, *tab;
   double2* nearv;  // near field of every particle, sorted order
+  double2* react;  // symmetric near field (NULL: off): the pairs' sums added to their sources
 };
 
 // The sort, leaf ranges and particle records, then the expansion sweeps on the
@@ -714,13 +762,22 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
                      d.toff, ntot, nleaves, d.tiles, d.ntiles);
   e = launch_tile_box(d.tiles, d.ntiles, max_tiles, d.p32, d.tile_box, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_b_p2p, dim3(nb(max_tiles, kBatchP2PWaves)), dim3(64 * kBatchP2PWaves), 0, st,
-                     d.inst, d.p32, d.start, d.tiles, d.ntiles, d.toff, d.tile_box, d.roots,
-                     d.nearv);
+  if (d.react) {
+    hipLaunchKernelGGL(k_b_zero2, dim3(nb(ntot, 256) < 4096 ? nb(ntot, 256) : 4096u), dim3(256), 0,
+                       st, d.react, ntot);
+    hipLaunchKernelGGL(k_b_p2p<true>, dim3(nb(max_tiles, kBatchP2PWaves)),
+                       dim3(64 * kBatchP2PWaves), kBatchP2PWaves * 128 * sizeof(SymRec<float>), st,
+                       d.inst, d.p32, d.start, d.tiles, d.ntiles, d.toff, d.tile_box, d.roots,
+                       d.nearv, d.react);
+  } else {
+    hipLaunchKernelGGL(k_b_p2p<false>, dim3(nb(max_tiles, kBatchP2PWaves)),
+                       dim3(64 * kBatchP2PWaves), 0, st, d.inst, d.p32, d.start, d.tiles, d.ntiles,
+                       d.toff, d.tile_box, d.roots, d.nearv, nullptr);
+  }
   e = hipStreamWaitEvent(st, join, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_l2p, dim3(tile_loop_blocks(max_tiles)), dim3(256), 0, st, d.inst,
-                     d.p32, d.tiles, d.ntiles, d.roots, d.le, d.nearv, i0);
+                     d.p32, d.tiles, d.ntiles, d.roots, d.le, d.nearv, d.react, i0);
   return hipGetLastError();
 }
 
@@ -782,7 +839,7 @@ struct BatchLayout {
   size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
       seg_off64, seg_il64, roots, k0, k1, i0, i1,
       counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, nearv,
-      total;
+      react, total;
   int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
   int maxL;
   std::vector<int64_t> me_off;
@@ -862,6 +919,7 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.le = take(size_t(L.me_bytes));
   L.tab = take(size_t(L.tab_bytes));
   L.nearv = take(sizeof(double2) * size_t(L.ntot));
+  L.react = take(sizeof(double2) * size_t(L.ntot));
   L.total = off;
   return L;
 }
@@ -892,13 +950,21 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   std::vector<BatchInst> hi(count);
   std::vector<int64_t> part_off(count + 1), leaf_off(count + 1), ls_off(count + 1), tab_off(VFMM_MAX_P + 1);
   std::vector<int64_t> m2m(size_t(kBatchMaxLevels + 1) * (count + 1), 0), l2l(size_t(kBatchMaxLevels + 1) * (count + 1), 0);
+  // symmetric near field (VFMM_TUNE_P2P_SYMMETRIC) for the instances with at
+  // least kBatchSymMinPPL particles per leaf on average: a symmetric chunk
+  // pair takes 64 steps however few particles its chunks hold, while one
+  // direction at a time takes one step per particle
+  const bool sym = tuning_sym() != 0;
+  bool any_sym = false;
   for (int c = 0; c < count; ++c) {
     const vfmm_instance& a = inst[c];
     part_off[c + 1] = part_off[c] + a.n;
     leaf_off[c + 1] = leaf_off[c] + (int64_t(1) << (2 * a.levels));
     ls_off[c] = leaf_off[c] + c;
+    const int32_t isym = sym && a.n >= (int64_t(kBatchSymMinPPL) << (2 * a.levels)) ? 1 : 0;
+    any_sym = any_sym || isym;
     hi[c] = BatchInst{a.x, a.y, a.gamma, a.u, a.v, a.n, part_off[c], leaf_off[c], L.me_off[c],
-                      a.sigma, a.p, a.levels, a.p > 16 ? 1 : 0, 0};
+                      a.sigma, a.p, a.levels, a.p > 16 ? 1 : 0, isym};
   }
   ls_off[count] = leaf_off[count] + count;
   for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
@@ -991,6 +1057,7 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   d.le = ws + L.le;
   d.tab = ws + L.tab;
   d.nearv = reinterpret_cast<double2*>(ws + L.nearv);
+  d.react = any_sym ? reinterpret_cast<double2*>(ws + L.react) : nullptr;
   hipError_t e = hipMemcpy(d.inst, hi.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.part_off, part_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.leaf_off, leaf_off.data(), 8 * (count + 1), hipMemcpyHostToDevice);

@@ -308,55 +308,6 @@ template <> struct PairK<double> {
   __device__ __forceinline__ double hfar(double r2) const { return P2PMath<double>::h_far(r2); }
 };
 
-// Symmetric pairs of two leaves (the target tile's leaf and a neighbour after
-// it): one wave holds 64 targets, one per lane, and a chunk of <= 64 sources,
-// which it stages twice in a row in its own LDS block (entry k holds source
-// (k + 1) mod 64, so that lane l reads source (l - s) mod 64 at step s from a
-// fixed offset); per step each lane evaluates the kernel of its pair once and
-// adds it to its target with the source's circulation and to the source's
-// sums with its own.  The source sums move one lane up per step (DPP row
-// rotation of the whole wave), so after 64 steps every lane holds those of
-// source j0 + lane.
-template <typename R> struct __align__(sizeof(R) * 4) SymRec { R x, y, g, pad; };
-
-__device__ __forceinline__ float lane_up(float v) {  // lane l takes lane l - 1 (mod 64)
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C,
-                                                            0xF, 0xF, false));
-}
-__device__ __forceinline__ double lane_up(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b)), 0x13C, 0xF, 0xF, false));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b >> 32)), 0x13C, 0xF, 0xF, false));
-  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
-}
-
-// FORM: 0 the near form, 1 with the series for close pairs, 2 the far form.
-template <typename R, int FORM>
-__device__ __forceinline__ void sym_chunk(const SymRec<R>* __restrict__ rd, R tx, R ty, R tg,
-                                          R tiny, const PairK<R>& pk, R& cu, R& cv, R& su,
-                                          R& sv) {
-#pragma unroll 4
-  for (int st = 0; st < 64; ++st) {
-    const SymRec<R> q = rd[63 - st];
-    const R dx = tx - q.x;
-    const R dy = ty - q.y;
-    R h;
-    if constexpr (FORM == 2) {
-      h = pk.hfar(dx * dx + dy * dy);
-    } else {
-      const R r2 = dx * dx + (dy * dy + tiny);
-      h = FORM == 1 ? pk.hseries(r2) : pk.hnear(r2);
-    }
-    const R a = q.g * h, b = tg * h;
-    cu -= a * dy;
-    cv += a * dx;
-    su += b * dy;
-    sv -= b * dx;
-    su = lane_up(su);
-    sv = lane_up(sv);
-  }
-}
-
 template <typename R, int LPT, bool SYM>
 __global__ void __launch_bounds__(512) k_p2p(
     const typename Types<R>::Part* __restrict__ part, const int32_t* __restrict__ leaf_start,
@@ -539,29 +490,8 @@ __global__ void __launch_bounds__(512) k_p2p(
                 }
               }
             } else if (sym_pair) {
-              // stage the chunk (padding: zero circulation at the leaf centre)
-              SymRec<R> rec{R(0), R(0), R(0), R(0)};
-              if (j0 + lane < j1) {
-                const auto q = part[j0 + lane];
-                rec = SymRec<R>{q.x, q.y, q.g, R(0)};
-              }
-              // this wave's reads of the previous chunk were consumed above
-              // (issued before these writes; LDS operations of a wave are
-              // performed in order), and the reads below wait for the writes
-              sbuf[(lane + 63) & 63] = rec;
-              sbuf[64 + ((lane + 63) & 63)] = rec;
-              __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-              __builtin_amdgcn_wave_barrier();
-              const SymRec<R>* rd = sbuf + lane;
-              R su = R(0), sv = R(0);
-              if (gap2 > far2) sym_chunk<R, 2>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
-              else if (gap2 > ser2) sym_chunk<R, 0>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
-              else sym_chunk<R, 1>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
-              if (j0 + lane < j1) {
-                double* rj = reinterpret_cast<double*>(react + (j0 + lane));
-                unsafeAtomicAdd(rj, double(su) * sd);
-                unsafeAtomicAdd(rj + 1, double(sv) * sd);
-              }
+              sym_pair_chunk(sbuf, part, j0, j1, lane, tx, ty, tg, tiny, pk,
+                             gap2 > far2 ? 2 : (gap2 > ser2 ? 0 : 1), sd, react, cu, cv);
             } else if (gap2 > far2) {
 #pragma unroll 8
               for (int32_t j = j0 + grp; j < j1; j += LPT) {

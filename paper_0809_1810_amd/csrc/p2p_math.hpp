@@ -89,4 +89,90 @@ template <> struct P2PMath<float> {
 };
 
 
+// ------------------------------------------------------- symmetric near field
+// Symmetric pairs of two chunks of <= 64 particles (K_sigma is odd, so one
+// kernel value serves both directions): one wave holds 64 targets, one per
+// lane, and stages the source chunk twice in a row in its own LDS block of 128
+// records (entry k holds source (k + 1) mod 64, so that lane l reads source
+// (l - s) mod 64 at step s from a fixed offset); per step each lane evaluates
+// the kernel of its pair once and adds it to its target with the source's
+// circulation and to the source's sums with its own.  The source sums move one
+// lane up per step (DPP rotation of the whole wave), so after 64 steps every
+// lane holds those of source j0 + lane, which it adds to that particle's
+// float64 entry with an atomic addition.
+template <typename R> struct __align__(sizeof(R) * 4) SymRec { R x, y, g, pad; };
+
+__device__ __forceinline__ float lane_up(float v) {  // lane l takes lane l - 1 (mod 64)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C,
+                                                            0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_up(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b)), 0x13C, 0xF, 0xF, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(b >> 32)), 0x13C, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// The 64 steps.  FORM: 0 the near form, 1 with the series for close pairs, 2
+// the far form; K supplies the circulation-free kernel values hnear, hseries,
+// hfar of r'^2.
+template <typename R, int FORM, typename K>
+__device__ __forceinline__ void sym_steps(const SymRec<R>* __restrict__ rd, R tx, R ty, R tg,
+                                          R tiny, const K& pk, R& cu, R& cv, R& su, R& sv) {
+#pragma unroll 4
+  for (int st = 0; st < 64; ++st) {
+    const SymRec<R> q = rd[63 - st];
+    const R dx = tx - q.x;
+    const R dy = ty - q.y;
+    R h;
+    if constexpr (FORM == 2) {
+      h = pk.hfar(dx * dx + dy * dy);
+    } else {
+      const R r2 = dx * dx + (dy * dy + tiny);
+      h = FORM == 1 ? pk.hseries(r2) : pk.hnear(r2);
+    }
+    const R a = q.g * h, b = tg * h;
+    cu -= a * dy;
+    cv += a * dx;
+    su += b * dy;
+    sv -= b * dx;
+    su = lane_up(su);
+    sv = lane_up(sv);
+  }
+}
+
+// One symmetric chunk pair: stage sources part[j0 .. j1) (padding: zero
+// circulation at the leaf centre) in buf, run the steps against the lane's
+// target (tx, ty, circulation tg; 0 for a padding lane) into (cu, cv), and add
+// the source sums times `scale` to react[j0 + lane].
+template <typename R, typename Part, typename K>
+__device__ __forceinline__ void sym_pair_chunk(SymRec<R>* __restrict__ buf,
+                                               const Part* __restrict__ part, int32_t j0,
+                                               int32_t j1, int lane, R tx, R ty, R tg, R tiny,
+                                               const K& pk, int form, double scale,
+                                               double2* __restrict__ react, R& cu, R& cv) {
+  SymRec<R> rec{R(0), R(0), R(0), R(0)};
+  if (j0 + lane < j1) {
+    const auto q = part[j0 + lane];
+    rec = SymRec<R>{q.x, q.y, q.g, R(0)};
+  }
+  // this wave's reads of the previous chunk were consumed before (issued
+  // before these writes; LDS operations of a wave are performed in order),
+  // and the reads below wait for the writes
+  buf[(lane + 63) & 63] = rec;
+  buf[64 + ((lane + 63) & 63)] = rec;
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  const SymRec<R>* rd = buf + lane;
+  R su = R(0), sv = R(0);
+  if (form == 2) sym_steps<R, 2>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+  else if (form == 0) sym_steps<R, 0>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+  else sym_steps<R, 1>(rd, tx, ty, tg, tiny, pk, cu, cv, su, sv);
+  if (j0 + lane < j1) {
+    double* rj = reinterpret_cast<double*>(react + (j0 + lane));
+    unsafeAtomicAdd(rj, double(su) * scale);
+    unsafeAtomicAdd(rj + 1, double(sv) * scale);
+  }
+}
+
 }  // namespace vfmm

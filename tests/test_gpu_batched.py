@@ -168,3 +168,42 @@ def test_substitution_floor_per_instance(vf):
         errs.append(rel_err(host(b.u[i]), host(b.v[i]), ud, vd)[0])
     assert bounds[0] < 1e-100 and errs[0] < 1e-6
     assert bounds[1] > 1.0 and errs[1] > 1e-3
+
+
+def test_batched_symmetric_near_field(vf):
+    """A batch planned with the symmetric near field (VFMM_TUNE_P2P_SYMMETRIC):
+    every instance against the oracle FMM at its own (p, levels) (1e-6 of the
+    maximum velocity), against the one-direction batch (within the two float32
+    roundings), and graph replays against eager runs (the float64 atomic sums
+    vary in order: 1e-13)."""
+    insts = _instances(16, seed=47, n_range=(300, 12000), levels=(2, 5))
+    P2 = W.clusters(9000, seed=48, sigma=0.004)  # several tiles per leaf
+    insts.append(dict(P=P2, x=dev(P2.x), y=dev(P2.y), gamma=dev(P2.gamma), sigma=P2.sigma, p=12,
+                      levels=3))
+    saved = vf.get_tuning()
+    try:
+        vf.set_tuning(sym=0)
+        b0 = vf.Batch(insts)
+        vf.set_tuning(sym=1)
+        b1 = vf.Batch(insts)
+    finally:
+        vf.set_tuning(**saved)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b0.run()
+        b1.run()
+        s.synchronize()
+        eager = [(host(b1.u[i]).copy(), host(b1.v[i]).copy()) for i in range(len(insts))]
+        b1.run(use_graph=True)
+        s.synchronize()
+    for i, d in enumerate(insts):
+        P = d["P"]
+        print_case("batched_sym", i=i, n=P.n, p=d["p"], levels=d["levels"])
+        u1, v1 = host(b1.u[i]), host(b1.v[i])
+        u0, v0 = host(b0.u[i]), host(b0.v[i])
+        r = F.fmm_velocity(P.x, P.y, P.gamma, d["sigma"], d["p"], d["levels"])
+        e1 = rel_err(u1, v1, r.u, r.v)[0]
+        e0 = rel_err(u0, v0, r.u, r.v)[0]
+        assert e1 < 1e-6
+        assert rel_err(u1, v1, u0, v0)[0] <= e0 + e1 + 1e-12
+        assert rel_err(u1, v1, *eager[i])[0] < 1e-13
