@@ -603,13 +603,14 @@ vfmm_status_t vfmm_advect(vfmm_tree_t tree, double* x, double* y, const double* 
  *                        (coalesced row loads), 4 / 8 waves per workgroup.
  *   VFMM_TUNE_P2P_SYMMETRIC: 0 (default) or 1, for trees with 64-particle
  *                        tiles (ignored otherwise): the near field at the
- *                        particles evaluates each pair of two different leaves
- *                        of the local list once, both directions from one
- *                        kernel value (K_sigma is odd: K(-r) = -K(r)); the
- *                        opposite contributions are added to float64 sums of
- *                        the source particles with atomic additions, whose
- *                        order varies from run to run (results reproducible
- *                        to float64 rounding of those sums, not bit for bit).
+ *                        particles evaluates each pair of two different tiles
+ *                        of the local list that hold 96 or more particles
+ *                        together once, both directions from one kernel value
+ *                        (K_sigma is odd: K(-r) = -K(r)); the opposite
+ *                        contributions are added to float64 sums of the source
+ *                        particles with atomic additions, whose order varies
+ *                        from run to run (results reproducible to float64
+ *                        rounding of those sums, not bit for bit).
  *                        Evaluation points and the adaptive tree always take
  *                        both directions separately.  vfmm_batch_create reads
  *                        it too: a batch planned with it uses it for the

@@ -78,18 +78,11 @@ namespace {
 //   first row by - d, leaves bx - d .. bx + d; then rows by - d + 1 .. by + d - 1,
 //   leaf bx - d then leaf bx + d; last row by + d, leaves bx - d .. bx + d;
 // all clipped to the level.  Returns false for an empty segment.
-// Symmetric near field (sym): of the local list only the leaf itself and the
-// neighbours after it in (row, leaf) order -- E in its own row, NW, N and NE
-// above -- remain; row by - 1 and leaf bx - 1 are left out, each such pair of
-// leaves being evaluated once, for both, by the tiles of the earlier leaf
-// (within the leaf itself likewise: each pair of its tiles by the earlier one).
-__device__ __forceinline__ bool segment(int s, int bx, int by, int m, bool sym, int& sy, int& lo,
-                                        int& hi) {
+__device__ __forceinline__ bool segment(int s, int bx, int by, int m, int& sy, int& lo, int& hi) {
   int d0, d1;
   if (s < 3) {
-    if (sym && s == 0) return false;
     sy = by - 1 + s;
-    d0 = sym && s == 1 ? 0 : -1;
+    d0 = -1;
     d1 = 1;
   } else {
     int d = 2, base = 3;
@@ -116,6 +109,7 @@ __device__ __forceinline__ bool segment(int s, int bx, int by, int m, bool sym, 
 constexpr int kSegNear = 3;
 constexpr int kMaxRings = 4;  // rings of the distance cut-off: Chebyshev distance 2 .. 4
 
+
 // Segments of the chunk sequence and the effective cut-off radius^2 for the
 // requested radius^2 cut2 (0: the paper's split, no rings) at leaf side w.
 struct NearRings {
@@ -138,10 +132,10 @@ __device__ __forceinline__ NearRings near_rings(double cut2, double w) {
 // 2^k leaf-level rows of the level's segment sg >> k, and spans the 2^k
 // leaf-level boxes of every box of that segment.  (bx, by) are the target
 // leaf's coordinates at its level, ml = 2^(L - k) the boxes per side there.
-__device__ __forceinline__ bool fine_segment(int sg, int k, int bx, int by, int ml, bool sym,
-                                             int& sy, int& lo, int& hi) {
+__device__ __forceinline__ bool fine_segment(int sg, int k, int bx, int by, int ml, int& sy,
+                                             int& lo, int& hi) {
   int syl, lol, hil;
-  if (!segment(sg >> k, bx, by, ml, sym, syl, lol, hil)) return false;
+  if (!segment(sg >> k, bx, by, ml, syl, lol, hil)) return false;
   sy = (syl << k) + (sg & ((1 << k) - 1));
   lo = lol << k;
   hi = ((hil + 1) << k) - 1;
@@ -154,13 +148,13 @@ __device__ __forceinline__ int tile_shift(const uint8_t* __restrict__ leaf_shift
 }
 
 __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int k, int nseg,
-                                                    bool sym, const uint32_t* __restrict__ tile_off) {
+                                                    const uint32_t* __restrict__ tile_off) {
   const int m = 1 << levels;
   const int bx = (leaf & (m - 1)) >> k, by = (leaf >> levels) >> k;
   uint32_t c = 0;
   for (int s = 0; s < (nseg << k); ++s) {
     int sy, lo, hi;
-    if (fine_segment(s, k, bx, by, m >> k, sym, sy, lo, hi))
+    if (fine_segment(s, k, bx, by, m >> k, sy, lo, hi))
       c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
   }
   return c;
@@ -174,7 +168,7 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
                                                      const double* __restrict__ root, int levels,
                                                      double cut2, int64_t max_tiles,
                                                      const uint8_t* __restrict__ leaf_shift,
-                                                     int sym, uint32_t* __restrict__ cnt,
+                                                     uint32_t* __restrict__ cnt,
                                                      uint64_t* __restrict__ bsum) {
   __shared__ uint64_t red[256];
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
@@ -183,7 +177,7 @@ __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ tt
     const int leaf = ttiles[t].leaf;
     const int k = tile_shift(leaf_shift, leaf);
     const int nseg = near_rings(cut2, root[3] * double(1 << k)).nseg;
-    c = sequence_chunks(leaf, levels, k, nseg, sym != 0, tile_off);
+    c = sequence_chunks(leaf, levels, k, nseg, tile_off);
   }
   if (t <= max_tiles) cnt[t] = c;
   red[threadIdx.x] = c;
@@ -402,7 +396,7 @@ __global__ void __launch_bounds__(512) k_p2p(
       uint32_t vb = 0;  // sequence index of the current segment's first chunk
       for (int sg = 0; sg < nseg && vb < v1; ++sg) {
         int sy, lo, hi;
-        if (!fine_segment(sg, k, bx, by, m >> k, sym, sy, lo, hi)) continue;
+        if (!fine_segment(sg, k, bx, by, m >> k, sy, lo, hi)) continue;
         const bool ring = (sg >> k) >= kSegNear;
         // source row centre minus target leaf centre, in leaf-level sides
         // (sy - by exactly when k = 0); the targets themselves take the offset
@@ -429,22 +423,25 @@ __global__ void __launch_bounds__(512) k_p2p(
           const R tx = tx0 - R(oxt * wsd);
           const float bx0 = tb.x - float(ox * w), bx1 = tb.y - float(ox * w);
           const int32_t js = leaf_start[sl], je = leaf_start[sl + 1];
-          // symmetric near field: a neighbour leaf's chunks take both
-          // directions here; in the tile's own leaf (whose chunks are its
-          // tiles) the chunks after the tile's own do, its own chunk takes one
-          // direction, and the chunks before it were done by their tiles
-          const bool self_leaf = sx == bx && sy == by;
-          const bool sym_leaf = sym && !ring && !self_leaf;
-          const int own = sym && self_leaf ? (t_start - js) / T : 0;
+          // symmetric near field: a pair of two different tiles of the local
+          // list (a leaf's chunks are its tiles) whose particles number at
+          // least kSymMinPair is evaluated once, both directions, by the tile
+          // that comes first in (row, leaf, tile) order; the later tile skips
+          // it.  Smaller pairs, the tile's own chunk and the rings take one
+          // direction per tile.
+          const int lrel = sy != by ? sy - by : sx - bx;  // > 0: the leaf comes after
+          const int own = sym && lrel == 0 ? (t_start - js) / T : 0;
           for (uint32_t ci = qa; ci < qb; ++ci) {
-            bool sym_pair = sym_leaf;
-            if (sym && self_leaf) {
-              const int c = int(ci - la);
-              if (c < own) continue;
-              sym_pair = c > own;
-            }
             const int32_t j0 = js + int32_t(ci - la) * T;
             const int32_t j1 = min(j0 + T, je);
+            bool sym_pair = false;
+            if (sym && !ring) {
+              const int rel = lrel != 0 ? lrel : int(ci - la) - own;
+              if (rel != 0 && t_count + (j1 - j0) >= kSymMinPair) {
+                if (rel < 0) continue;  // taken by the earlier tile
+                sym_pair = true;
+              }
+            }
             const float4 sb = tile_box[ci];
             const float gx = fmaxf(0.f, fmaxf(sb.x - bx1, bx0 - sb.y));
             const float gy = fmaxf(0.f, fmaxf(sb.z - by1, by0 - sb.w));
@@ -647,8 +644,7 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, do
   const int64_t mt = tg.max_tiles;
   const int64_t nb = nblk(mt + 1, 256);
   hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, tg.react ? 1 : 0, s.cnt,
-                     s.bsum);
+                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, s.cnt, s.bsum);
   hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,

@@ -102,6 +102,12 @@ template <> struct P2PMath<float> {
 // float64 entry with an atomic addition.
 template <typename R> struct __align__(sizeof(R) * 4) SymRec { R x, y, g, pad; };
 
+// The single-tree near field evaluates a pair of chunks both ways at once only
+// when they hold at least this many particles together: the 64 steps of a
+// symmetric pair cost about what one direction per chunk costs for 96
+// particles.
+constexpr int kSymMinPair = 96;
+
 __device__ __forceinline__ float lane_up(float v) {  // lane l takes lane l - 1 (mod 64)
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C,
                                                             0xF, 0xF, false));

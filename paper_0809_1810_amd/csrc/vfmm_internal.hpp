@@ -182,11 +182,10 @@ struct TargetsDev {
   // leaf-level box in place of the circulation (offsets to the sources)
   const Part64* fine64;
   // symmetric near field (targets = the tree's particles, uniform tree,
-  // 64-particle tiles; NULL otherwise): a target tile takes, of the local
-  // list, the tiles of its own leaf from itself on and the four neighbours E,
-  // NW, N, NE, and every pair with another tile also adds the opposite
-  // contribution to the source particle's entry here; the rest of the local
-  // list reaches the tile that way
+  // 64-particle tiles; NULL otherwise): a pair of two different tiles of the
+  // local list with enough particles is evaluated once, by the earlier tile,
+  // which also adds the opposite contribution to the source particle's entry
+  // here; the later tile skips it
   double2* react;
 };
 

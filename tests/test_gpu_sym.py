@@ -2,10 +2,10 @@
 
 K_sigma is odd (eq. 6: K(-x) = -K(x)), so a pair of particles needs one kernel
 value for both directions.  With the setting on, a tree with 64-particle tiles
-evaluates each pair of two different leaves of the local list once: the tiles
-of a leaf take the tiles of their own leaf from themselves on and the
-neighbours E, NW, N, NE, and add the
-opposite contributions to the source particles.  Every pair must still be
+evaluates each pair of two different tiles of the local list that hold 96 or
+more particles together once, by the tile that comes first in (row, leaf,
+tile) order, which adds the opposite contributions to the source particles;
+the later tile skips the pair, and smaller pairs take one direction per tile.  Every pair must still be
 counted exactly once in each direction, which the float64 comparison with the
 oracle checks to 1e-12 of the maximum velocity (near part 1e-13): a missing or
 doubled leaf pair, a wrong lane rotation or a sign error would show at the
