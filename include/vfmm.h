@@ -468,7 +468,8 @@ vfmm_status_t vfmm_select_and_audit(const double* x, const double* y, const doub
  * phase or per level), so the launch count does not grow with the number of
  * instances, and the sequence can be captured in a hipGraph and replayed.
  * Arithmetic: near field in FP32 (compensated sums, series for close pairs);
- * expansions in FP32 for p <= 16 and FP64 for p > 16. */
+ * expansions in FP32 for p <= 16; for p > 16 P2M, M2M, L2L and L2P in FP64 with
+ * the M2L in FP32 on the matrix cores. */
 typedef struct vfmm_instance {
   const double* x;      /* device, n: positions */
   const double* y;

@@ -10,12 +10,14 @@
 // depend on the number of instances, and the whole sequence can be captured
 // once in a hipGraph (two branches) and replayed.
 //
-// Arithmetic per instance: P2P in FP32 (as in p2p.hip); expansions (P2M, M2M,
-// M2L, L2L, L2P) in FP32 for p <= 16 and in FP64 for p > 16, on the scaled,
+// Arithmetic per instance: P2P in FP32 (as in p2p.hip); expansions in FP32 for
+// p <= 16; for p > 16 the shifts (P2M, M2M, L2L) and L2P in FP64 with the M2L
+// in FP32 on the matrix cores (the multipoles rounded to float32 copies, the
+// M2L sums widened back before the float64 L2L chain); on the scaled,
 // level-independent operators of expansions.hip (one table set per p).  The
-// M2L runs on the matrix cores (m2l_tile.hpp): one launch for the FP32
-// instances, one for the FP64 instances, each covering all their levels; the
-// L2L chain then runs one coefficient per thread, one launch per level.
+// M2L (m2l_tile.hpp) takes one launch for the p <= 16 instances and one for the
+// p > 16 instances (64-row tiles), each covering all their levels; the L2L
+// chain then runs one coefficient per thread, one launch per level.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -39,6 +41,7 @@ struct BatchInst {
   int64_t part_off;  // first particle in the concatenated (sorted) arrays
   int64_t leaf_off;  // first global leaf; leaf_start entries start at leaf_off + index
   int64_t me_off;    // byte offset of the level-2 coefficients in the ME / LE buffers
+  int64_t me32_off;  // p > 16: byte offset of their float32 copies in the ME32 / LE32 buffers
   double sigma;
   int32_t p, L, fp64;
   int32_t sym;  // symmetric near field for this instance (see k_b_p2p)
@@ -228,6 +231,10 @@ __global__ void __launch_bounds__(256) k_b_tile_fill(const BatchInst* __restrict
 template <typename R>
 __device__ __forceinline__ typename Types<R>::C* coef(char* base, const BatchInst& in, int lev) {
   return reinterpret_cast<typename Types<R>::C*>(base + in.me_off) + level_offset(lev) * in.p;
+}
+// the float32 copies of a p > 16 instance's coefficients (M2L on the matrix cores)
+__device__ __forceinline__ float2* coef32(char* base, const BatchInst& in, int lev) {
+  return reinterpret_cast<float2*>(base + in.me32_off) + level_offset(lev) * in.p;
 }
 
 // Sum of the wave's values when only lanes 0 .. 2^steps - 1 hold non-zeros:
@@ -436,16 +443,20 @@ __global__ void __launch_bounds__(256) k_b_l2l(const BatchInst* __restrict__ I,
   else l2l_item<float>(in, lev, item, le, tab, tab_off);
 }
 
-// M2L of the FP32 instances on the matrix cores: one workgroup per 32-box tile.
+// M2L on the matrix cores in float32: one workgroup per 32-box tile.
 // Segment s = one (instance, level) pair, its tiles seg_off[s] .. seg_off[s+1)
 // (4 classes x ceil(4^(lev-1) / 32) tiles), seg_il[s] = instance << 8 | level.
-// The FP64 instances likewise, with 16-box tiles.
+// MT = 1: the instances with p <= 16, on their float32 coefficients; MT = 2:
+// the instances with p > 16 (2p <= 48 rows in two 32-row tiles), on the float32
+// copies of their float64 multipoles (k_b_narrow), into float32 locals that
+// k_b_widen adds to the float64 L2L chain.
+template <int MT>
 __global__ void __launch_bounds__(256) k_b_m2l_mfma(const BatchInst* __restrict__ I,
                                                     const int64_t* __restrict__ seg_off,
                                                     const int32_t* __restrict__ seg_il, int nseg,
                                                     char* me, char* le, const char* tab,
                                                     const int64_t* __restrict__ tab_off) {
-  __shared__ M2LTileLds<1> sh;
+  __shared__ M2LTileLds<MT> sh;
   const int64_t tile = blockIdx.x;
   const int s = __builtin_amdgcn_readfirstlane(find_seg(seg_off, nseg, tile));
   const int il = __builtin_amdgcn_readfirstlane(seg_il[s]);
@@ -453,26 +464,36 @@ __global__ void __launch_bounds__(256) k_b_m2l_mfma(const BatchInst* __restrict_
   const BatchInst in = I[c];
   const int p = __builtin_amdgcn_readfirstlane(in.p);
   const float* A = reinterpret_cast<const float*>(tab + tab_off[p] + ops_layout(p).mfma32);
-  m2l_f32_tile<1>(coef<float>(me, in, lev), coef<float>(le, in, lev), lev, p,
-                  int(tile - seg_off[s]), A, sh);
+  if constexpr (MT == 1)
+    m2l_f32_tile<1>(coef<float>(me, in, lev), coef<float>(le, in, lev), lev, p,
+                    int(tile - seg_off[s]), A, sh);
+  else
+    m2l_f32_tile<MT>(coef32(me, in, lev), coef32(le, in, lev), lev, p, int(tile - seg_off[s]),
+                     A, sh);
 }
 
-__global__ void __launch_bounds__(256) k_b_m2l_mfma64(const BatchInst* __restrict__ I,
-                                                      const int64_t* __restrict__ seg_off,
-                                                      const int32_t* __restrict__ seg_il, int nseg,
-                                                      char* me, char* le, const char* tab,
-                                                      const int64_t* __restrict__ tab_off) {
-  __shared__ M2LTileLds64 sh;
-  const int64_t tile = blockIdx.x;
-  const int s = __builtin_amdgcn_readfirstlane(find_seg(seg_off, nseg, tile));
-  const int il = __builtin_amdgcn_readfirstlane(seg_il[s]);
-  const int c = il >> 8, lev = il & 255;
+// The p > 16 instances: every level's float64 multipoles rounded to float32
+// (narrow = true: me -> me32) or every level's float32 M2L sums widened into
+// the float64 locals (narrow = false: le32 -> le), before the float64 L2L chain
+// adds the shifted parent expansions.  Items: their coefficients of levels
+// 2 .. L, instance by instance (items[c] .. items[c + 1]).
+__global__ void __launch_bounds__(256) k_b_convert(const BatchInst* __restrict__ I,
+                                                   const int64_t* __restrict__ items, int count,
+                                                   bool narrow, char* wide, char* thin) {
+  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= items[count]) return;
+  const int c = find_seg(items, count, t);
   const BatchInst in = I[c];
-  const int p = __builtin_amdgcn_readfirstlane(in.p);
-  // packed operands follow the order-p table set (its size is a multiple of 256)
-  const double* A = reinterpret_cast<const double*>(tab + tab_off[p] + ops_layout(p).total);
-  m2l_f64_tile(coef<double>(me, in, lev), coef<double>(le, in, lev), lev, p,
-               int(tile - seg_off[s]), A, sh);
+  const int64_t k = t - items[c];
+  double2* w = reinterpret_cast<double2*>(wide + in.me_off) + level_offset(2) * in.p + k;
+  float2* f = reinterpret_cast<float2*>(thin + in.me32_off) + level_offset(2) * in.p + k;
+  if (narrow) {
+    const double2 v = *w;
+    *f = make_float2(float(v.x), float(v.y));
+  } else {
+    const float2 v = *f;
+    *w = make_double2(double(v.x), double(v.y));
+  }
 }
 
 // ------------------------------------------------------------------ near field + evaluation
@@ -702,6 +723,8 @@ struct BatchPlanDev {
   float4* tile_box;
   Part32* p32;
   char *me, *le, *tab;
+  char *me32, *le32;    // float32 copies of the p > 16 instances' coefficients
+  int64_t* w64_items;   // [count + 1]: their coefficients of levels 2 .. L, cumulated
   double2* nearv;  // near field of every particle, sorted order
   double2* react;  // symmetric near field (NULL: off): the pairs' sums added to their sources
 };
@@ -713,7 +736,7 @@ struct BatchPlanDev {
 hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int64_t nleaves,
                             int64_t max_tiles, const int64_t* m2m_tot, const int64_t* l2l_tot,
                             int maxL, int nseg, int64_t mfma_tiles, int nseg64,
-                            int64_t mfma_tiles64, hipStream_t st, hipStream_t sw,
+                            int64_t mfma_tiles64, int64_t w64_tot, hipStream_t st, hipStream_t sw,
                             hipEvent_t fork, hipEvent_t join) {
   auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
   hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots, d.nbig);
@@ -741,11 +764,17 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
       hipLaunchKernelGGL(k_b_m2m, dim3(nb(m2m_tot[l], 256)), dim3(256), 0, sw, d.inst,
                          d.m2m_items + int64_t(l) * (count + 1), count, l, d.me, d.tab, d.tab_off);
   if (mfma_tiles > 0)
-    hipLaunchKernelGGL(k_b_m2l_mfma, dim3(unsigned(mfma_tiles)), dim3(256), 0, sw, d.inst,
+    hipLaunchKernelGGL(k_b_m2l_mfma<1>, dim3(unsigned(mfma_tiles)), dim3(256), 0, sw, d.inst,
                        d.seg_off, d.seg_il, nseg, d.me, d.le, d.tab, d.tab_off);
-  if (mfma_tiles64 > 0)
-    hipLaunchKernelGGL(k_b_m2l_mfma64, dim3(unsigned(mfma_tiles64)), dim3(256), 0, sw, d.inst,
-                       d.seg_off64, d.seg_il64, nseg64, d.me, d.le, d.tab, d.tab_off);
+  if (mfma_tiles64 > 0) {
+    // p > 16: float64 shifts, M2L in float32 on the matrix cores
+    hipLaunchKernelGGL(k_b_convert, dim3(nb(w64_tot, 256)), dim3(256), 0, sw, d.inst, d.w64_items,
+                       count, true, d.me, d.me32);
+    hipLaunchKernelGGL(k_b_m2l_mfma<2>, dim3(unsigned(mfma_tiles64)), dim3(256), 0, sw, d.inst,
+                       d.seg_off64, d.seg_il64, nseg64, d.me32, d.le32, d.tab, d.tab_off);
+    hipLaunchKernelGGL(k_b_convert, dim3(nb(w64_tot, 256)), dim3(256), 0, sw, d.inst, d.w64_items,
+                       count, false, d.le, d.le32);
+  }
   for (int l = 3; l <= maxL; ++l)
     if (l2l_tot[l] > 0)
       hipLaunchKernelGGL(k_b_l2l, dim3(nb(l2l_tot[l], 256)), dim3(256), 0, sw, d.inst,
@@ -792,7 +821,8 @@ struct vfmm_batch_s {
   int maxL;
   int64_t m2m_tot[kBatchMaxLevels + 1], l2l_tot[kBatchMaxLevels + 1];
   int nseg, nseg64;              // (instance, level) segments of the matrix-core M2L
-  int64_t mfma_tiles, mfma_tiles64;  // their tiles (workgroups), FP32 and FP64
+  int64_t mfma_tiles, mfma_tiles64;  // their tiles (workgroups), p <= 16 and p > 16
+  int64_t w64_tot;               // coefficients of the p > 16 instances (float32 copies)
   std::vector<int> ps;  // distinct expansion orders
   int64_t tab_at[VFMM_MAX_P + 1];  // byte offset of each order's table set
   BatchPlanDev d;
@@ -838,11 +868,11 @@ inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 struct BatchLayout {
   size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
       seg_off64, seg_il64, roots, k0, k1, i0, i1,
-      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, nearv,
-      react, total;
-  int64_t ntot, nleaves, max_tiles, me_bytes, tab_bytes;
+      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, me32, le32,
+      w64_items, nearv, react, total;
+  int64_t ntot, nleaves, max_tiles, me_bytes, me32_bytes, tab_bytes;
   int maxL;
-  std::vector<int64_t> me_off;
+  std::vector<int64_t> me_off, me32_off;
   int64_t tab_at[VFMM_MAX_P + 1];
 };
 
@@ -868,7 +898,8 @@ vfmm_status_t check_instances(const vfmm_instance* in, int count) {
 BatchLayout batch_layout(const vfmm_instance* in, int count) {
   BatchLayout L{};
   L.me_off.resize(count);
-  int64_t me = 0;
+  L.me32_off.resize(count);
+  int64_t me = 0, me32 = 0;
   bool has_p[VFMM_MAX_P + 1] = {};
   for (int c = 0; c < count; ++c) {
     const vfmm_instance& a = in[c];
@@ -878,13 +909,16 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
     L.maxL = std::max(L.maxL, int(a.levels));
     L.me_off[c] = me;
     me += int64_t(al(size_t(n_boxes_2_to(a.levels)) * a.p * (a.p > 16 ? 16 : 8)));
+    L.me32_off[c] = me32;
+    if (a.p > 16) me32 += int64_t(al(size_t(n_boxes_2_to(a.levels)) * a.p * 8));
     has_p[a.p] = true;
   }
   L.me_bytes = me;
+  L.me32_bytes = me32;
   int64_t tb = 0;
   for (int p = 0; p <= VFMM_MAX_P; ++p) {
     L.tab_at[p] = tb;
-    if (has_p[p]) tb += int64_t(al(ops_bytes(p)) + (p > 16 ? al(m2l64_pack_bytes(p)) : 0));
+    if (has_p[p]) tb += int64_t(al(ops_bytes(p)));
   }
   L.tab_bytes = tb;
   const int64_t sort_blocks = (L.ntot + kSortPerBlock - 1) / kSortPerBlock;
@@ -918,6 +952,9 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.me = take(size_t(L.me_bytes));
   L.le = take(size_t(L.me_bytes));
   L.tab = take(size_t(L.tab_bytes));
+  L.me32 = take(size_t(L.me32_bytes));
+  L.le32 = take(size_t(L.me32_bytes));
+  L.w64_items = take(8 * size_t(count + 1));
   L.nearv = take(sizeof(double2) * size_t(L.ntot));
   L.react = take(sizeof(double2) * size_t(L.ntot));
   L.total = off;
@@ -964,7 +1001,7 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
     const int32_t isym = sym && a.n >= (int64_t(kBatchSymMinPPL) << (2 * a.levels)) ? 1 : 0;
     any_sym = any_sym || isym;
     hi[c] = BatchInst{a.x, a.y, a.gamma, a.u, a.v, a.n, part_off[c], leaf_off[c], L.me_off[c],
-                      a.sigma, a.p, a.levels, a.p > 16 ? 1 : 0, isym};
+                      L.me32_off[c], a.sigma, a.p, a.levels, a.p > 16 ? 1 : 0, isym};
   }
   ls_off[count] = leaf_off[count] + count;
   for (int p = 0; p <= VFMM_MAX_P; ++p) tab_off[p] = L.tab_at[p];
@@ -1006,11 +1043,12 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
     b->m2m_tot[l] = a;
     b->l2l_tot[l] = bb;
   }
-  std::vector<int64_t> seg_off(1, 0), seg_off64(1, 0);
+  std::vector<int64_t> seg_off(1, 0), seg_off64(1, 0), w64(count + 1, 0);
   std::vector<int32_t> seg_il, seg_il64;
   for (int c = 0; c < count; ++c) {
     const bool f64 = inst[c].p > 16;
-    const int bw = f64 ? 16 : 32;  // boxes per tile
+    w64[c + 1] = w64[c] + (f64 ? n_boxes_2_to(inst[c].levels) * inst[c].p : 0);
+    const int bw = 32;  // boxes per tile
     std::vector<int64_t>& so = f64 ? seg_off64 : seg_off;
     std::vector<int32_t>& si = f64 ? seg_il64 : seg_il;
     for (int l = 2; l <= inst[c].levels; ++l) {
@@ -1022,6 +1060,7 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   b->mfma_tiles = seg_off.back();
   b->nseg64 = int(seg_il64.size());
   b->mfma_tiles64 = seg_off64.back();
+  b->w64_tot = w64[count];
   for (int c = 0; c < count; ++c) {
     bool seen = false;
     for (int q : b->ps) seen |= q == inst[c].p;
@@ -1056,6 +1095,9 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   d.me = ws + L.me;
   d.le = ws + L.le;
   d.tab = ws + L.tab;
+  d.me32 = ws + L.me32;
+  d.le32 = ws + L.le32;
+  d.w64_items = reinterpret_cast<int64_t*>(ws + L.w64_items);
   d.nearv = reinterpret_cast<double2*>(ws + L.nearv);
   d.react = any_sym ? reinterpret_cast<double2*>(ws + L.react) : nullptr;
   hipError_t e = hipMemcpy(d.inst, hi.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
@@ -1071,6 +1113,7 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   if (e == hipSuccess) e = hipMemcpy(d.seg_off64, seg_off64.data(), 8 * seg_off64.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !seg_il64.empty())
     e = hipMemcpy(d.seg_il64, seg_il64.data(), 4 * seg_il64.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.w64_items, w64.data(), 8 * w64.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete b;
     return bfail(hip_status(e), "batch tables: %s", hipGetErrorString(e));
@@ -1089,10 +1132,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
       TreeDev t{};
       t.ops = b->d.tab + b->tab_at[p];  // translation tables of order p
       e = launch_build_ops(t, p, kFP64, st);
-      if (e == hipSuccess && p <= 16) e = launch_pack_m2l_mfma(t, p, kFP32, st);
-      if (e == hipSuccess && p > 16)
-        e = launch_pack_m2l_mfma64(t.ops, p,
-                                   reinterpret_cast<double*>(static_cast<char*>(t.ops) + ops_bytes(p)), st);
+      if (e == hipSuccess) e = launch_pack_m2l_mfma(t, p, kFP32, st);
       if (e != hipSuccess) break;
     }
     if (e != hipSuccess) return bfail(hip_status(e), "batch tables: %s", hipGetErrorString(e));
@@ -1100,8 +1140,8 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
   }
   if (!use_graph) {
     e = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot, b->l2l_tot,
-                         b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64, st,
-                         b->side, b->fork, b->join);
+                         b->maxL, b->nseg, b->mfma_tiles, b->nseg64, b->mfma_tiles64,
+                         b->w64_tot, st, b->side, b->fork, b->join);
     if (e == hipSuccess) e = hipEventRecord(b->done, st);
     if (e == hipSuccess) b->ran = true;
     return e == hipSuccess ? VFMM_OK : bfail(hip_status(e), "batch run: %s", hipGetErrorString(e));
@@ -1111,7 +1151,7 @@ vfmm_status_t vfmm_batch_run(vfmm_batch_t b, int32_t use_graph, void* stream) {
     if (e != hipSuccess) return bfail(hip_status(e), "begin capture: %s", hipGetErrorString(e));
     hipError_t le = batch_launch_all(b->d, b->count, b->ntot, b->nleaves, b->max_tiles, b->m2m_tot,
                                      b->l2l_tot, b->maxL, b->nseg, b->mfma_tiles, b->nseg64,
-                                     b->mfma_tiles64, st, b->side, b->fork, b->join);
+                                     b->mfma_tiles64, b->w64_tot, st, b->side, b->fork, b->join);
     e = hipStreamEndCapture(st, &b->graph);
     if (le != hipSuccess || e != hipSuccess)
       return bfail(hip_status(le != hipSuccess ? le : e), "capture: %s", hipGetErrorString(le != hipSuccess ? le : e));

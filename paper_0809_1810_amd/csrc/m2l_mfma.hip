@@ -51,28 +51,6 @@ __device__ __forceinline__ float real_block(const double2* T, int p, int i, int 
   return float(v);
 }
 
-// FP64 operands in the lane order of m2l_f64_tile: element (offset, row tile t,
-// K-step ks, lane) = R[16 t + lane % 16][(lane / 16) KS + ks], zero outside 2p.
-__global__ void __launch_bounds__(256) k_pack_f64(const double2* __restrict__ m2l64, int p,
-                                                  double* __restrict__ out) {
-  const int ks_n = m2l64_ks(p);
-  const int64_t total = int64_t(kM2LOffsets) * kM2L64Rows * ks_n * 64;
-  const int64_t e = blockIdx.x * 256LL + threadIdx.x;
-  if (e >= total) return;
-  const int lane = int(e % 64);
-  const int ks = int((e / 64) % ks_n);
-  const int t = int((e / (64LL * ks_n)) % kM2L64Rows);
-  const int o = int(e / (64LL * ks_n * kM2L64Rows));
-  const int i = t * 16 + (lane & 15), k = (lane >> 4) * ks_n + ks;
-  double v = 0.0;
-  if (i < 2 * p && k < 2 * p) {
-    const double2 c = m2l64[int64_t(o) * p * p + (i >> 1) * p + (k >> 1)];
-    if ((i & 1) == 0) v = (k & 1) == 0 ? c.x : -c.y;
-    else v = (k & 1) == 0 ? c.y : c.x;
-  }
-  out[e] = v;
-}
-
 __global__ void __launch_bounds__(256) k_pack_f32(const double2* __restrict__ m2l64, int p, int mt,
                                                   float* __restrict__ out) {
   const int ks_n = p;  // K = 2 per instruction
@@ -366,15 +344,6 @@ hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t s
       hipLaunchKernelGGL(k_pack_16<kModeF16>, dim3(unsigned((total + 255) / 256)), dim3(256), 0,
                          st, m2l64, p, ol.mt, reinterpret_cast<uint16_t*>(ops + ol.mfma16));
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_m2l_mfma64(const void* ops, int p, double* out, hipStream_t st) {
-  if (2 * p > 16 * kM2L64Rows) return hipErrorInvalidValue;
-  const double2* m2l64 =
-      reinterpret_cast<const double2*>(static_cast<const char*>(ops) + ops_layout(p).m2l64);
-  const int64_t total = int64_t(kM2LOffsets) * kM2L64Rows * m2l64_ks(p) * 64;
-  hipLaunchKernelGGL(k_pack_f64, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, m2l64, p, out);
   return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // One column tile of the M2L on the matrix cores (eq. 22): 32 boxes in FP32
 // (shared by the single-tree kernel in m2l_mfma.hip and the batched kernel in
-// batched.hip), 16 boxes in FP64 (batched kernel).
+// batched.hip).
 //
 // For a target box b of child class c = (bx & 1, by & 1) the 27 interaction
 // offsets t are fixed, so l_b = sum_{t in IL(c)} R_t m_{b - t} with R_t the real
@@ -272,104 +272,6 @@ __device__ __forceinline__ void m2l_f32_tile_staged(const float2* __restrict__ m
     const int i = 8 * (r >> 2) + 4 * hi + (r & 3);
     if (i < twop) out[i] = acc[r];
   }
-}
-
-// ---------------------------------------------------------------- FP64 variant
-//
-// v_mfma_f64_16x16x4f64: A[i][k] with i = lane % 16, k-slot lane / 16; B[k][j]
-// with j = lane % 16, k-slot lane / 16; D[i][j] in 4 double registers per lane,
-// row i = 4 r + lane / 16 (register r), column j = lane % 16.  A tile holds 16 target boxes;
-// the 2p rows of the real block form are covered by 3 row tiles of 16
-// (2p <= 48, p <= 24); K = 2p runs in KS = ceil(2p / 4) instructions, K-slot h
-// of instruction ks taking component k = h KS + ks, so that a lane reads a
-// contiguous run of its source box's coefficients.
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-constexpr int kM2L64Rows = 3;   // 16-row tiles
-constexpr int kM2L64KsMax = 12; // p <= 24
-
-__host__ __device__ inline int m2l64_ks(int p) { return (2 * p + 3) / 4; }
-__host__ __device__ inline size_t m2l64_pack_bytes(int p) {
-  return size_t(kM2LOffsets) * kM2L64Rows * m2l64_ks(p) * 64 * sizeof(double);
-}
-
-struct M2LTileLds64 {
-  double part[3][kM2L64Rows][4][64];
-};
-
-// As m2l_f32_tile, in FP64, for tiles of 16 boxes (local = class * tiles per
-// class + column tile, tiles per class = ceil(4^(lev-1) / 16)); packA holds
-// kM2LOffsets x 3 x KS x 64 doubles.
-__device__ __forceinline__ void m2l_f64_tile(const double2* __restrict__ me_l,
-                                             double2* __restrict__ le_l, int lev, int p, int local,
-                                             const double* __restrict__ packA, M2LTileLds64& sh) {
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int half = 1 << (lev - 1), m = 1 << lev;
-  const int per_class = half * half;
-  const int tiles_pc = (per_class + 15) / 16;
-  const int c = local / tiles_pc, tt = local % tiles_pc;
-  const int cx = c & 1, cy = c >> 1;
-  const int col = lane & 15, h = lane >> 4;
-  const int q = tt * 16 + col;
-  const bool valid = q < per_class;
-  const int qq = valid ? q : 0;
-  const int bx = 2 * (qq % half) + cx, by = 2 * (qq / half) + cy;
-  const int twop = 2 * p;
-  const int ks_n = m2l64_ks(p);
-
-  v4d acc[kM2L64Rows];
-#pragma unroll
-  for (int t = 0; t < kM2L64Rows; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
-
-  for (int j = wv; j < 27; j += 4) {
-    int ox, oy;
-    nth_offset(j, cx, cy, ox, oy);
-    const int sx = bx - ox, sy = by - oy;
-    const bool sv = valid && sx >= 0 && sx < m && sy >= 0 && sy < m;
-    const double* src = reinterpret_cast<const double*>(me_l + (sv ? (int64_t(sy) * m + sx) * p : 0));
-    const double* A = packA + int64_t(m2l_index(ox, oy)) * kM2L64Rows * ks_n * 64 + lane;
-    double a[kM2L64Rows][kM2L64KsMax], b[kM2L64KsMax];
-#pragma unroll
-    for (int ks = 0; ks < kM2L64KsMax; ++ks) {
-      if (ks < ks_n) {
-        const int k = h * ks_n + ks;
-        const double v = src[k < twop ? k : twop - 1];
-        b[ks] = (sv && k < twop) ? v : 0.0;
-#pragma unroll
-        for (int t = 0; t < kM2L64Rows; ++t) a[t][ks] = A[(int64_t(t) * ks_n + ks) * 64];
-      }
-    }
-#pragma unroll
-    for (int ks = 0; ks < kM2L64KsMax; ++ks) {
-      if (ks < ks_n) {
-#pragma unroll
-        for (int t = 0; t < kM2L64Rows; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][ks], b[ks], acc[t], 0, 0, 0);
-      }
-    }
-  }
-  if (wv > 0) {
-#pragma unroll
-    for (int t = 0; t < kM2L64Rows; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) sh.part[wv - 1][t][r][lane] = acc[t][r];
-  }
-  __syncthreads();
-  if (wv > 0 || !valid) return;
-  double* out = reinterpret_cast<double*>(le_l + (int64_t(by) * m + bx) * p);
-#pragma unroll
-  for (int t = 0; t < kM2L64Rows; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = t * 16 + 4 * r + h;
-      const double s = acc[t][r] + sh.part[0][t][r][lane] + sh.part[1][t][r][lane] +
-                       sh.part[2][t][r][lane];
-      if (i < twop) out[i] = s;
-    }
 }
 
 }  // namespace vfmm

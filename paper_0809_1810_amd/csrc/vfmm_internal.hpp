@@ -238,9 +238,6 @@ hipError_t launch_downward(const TreeDev& t, int levels, int p, int prec, hipStr
 // Reduced-precision downward sweep: M2L of all levels on the matrix cores
 // (prec = kFP32, kM2L_BF16 or kM2L_FP16), then the L2L chain.
 hipError_t launch_pack_m2l_mfma(const TreeDev& t, int p, int prec, hipStream_t stream);
-// FP64 M2L operands for the matrix cores (m2l_tile.hpp), from the operator
-// tables at ops; out holds m2l64_pack_bytes(p) bytes.
-hipError_t launch_pack_m2l_mfma64(const void* ops, int p, double* out, hipStream_t stream);
 // with_l2l = false: the M2L of every level only (each level's LE holds its
 // interaction-list sum), for a downward sweep whose L2L runs in float64.
 hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, hipStream_t stream,

@@ -113,8 +113,8 @@ def test_full_sweep_batch_against_oracle(vf):
     [2048, 65536], uniform or lattice, p in 5..20, L in 3..6; 4.9M particles)
     evaluated as one batch.  Every instance is compared with the float64 oracle
     FMM at its own (p, L) on 64 sampled targets, to 1e-6 of the sample's
-    maximum velocity; the 64 instances with p > 16 take the float64 expansion
-    path."""
+    maximum velocity; the 64 instances with p > 16 take float64 shifts around
+    a float32 M2L."""
     insts = _instances(256, seed=4, n_range=(2048, 65536), levels=(3, 6))
     b = vf.Batch(insts)
     s = torch.cuda.Stream()
