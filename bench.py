@@ -354,12 +354,14 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        # the same K steps issued eagerly (the adaptive tree's A/B), then, for
-        # the uniform tree, replayed from one hipGraph: the timed result
+        # the K steps issued eagerly, with the phase events (the near-field
+        # kernel's launch durations, the adaptive tree's A/B); then, for the
+        # uniform tree, the same K steps replayed from one hipGraph: the timed
+        # result (events recorded during a capture take no replay timestamps)
         eager_ms, wall, phases = time_steps(torch, step, steps, tree if timing else None, False)
         ms = eager_ms
         if capacity is None and not a.eager:
-            ms, wall, phases = time_steps(torch, step, steps, tree if timing else None, True)
+            ms, wall, _ = time_steps(torch, step, steps, None, True)
         emax, erms, _ = vf.error_metrics(u[tg_d].contiguous(), v[tg_d].contiguous(), ud, vd)
         hmax, hrms, _ = vf.error_metrics(u[th_d].contiguous(), v[th_d].contiguous(), uh, vh)
         far_phases = []
@@ -409,6 +411,9 @@ def main():
                 "traffic": recorded_traffic(a.workload, p_t, L_t, radius_t, P.sigma, tuned["sym"]),
                 "kernel": "k_p2p<float> (symmetric near field)" if tuned["sym"] else "k_p2p<float>",
                 "kernel_ms": round(p2p_ms, 4),
+                "kernel_ms_from": "HIP events around the kernel's launches on its stream in the "
+                                  "K timed steps issued eagerly (the same steps as the "
+                                  "graph-replayed ones)",
                 "pairs_per_launch": tuned["pairs"], "flops_per_pair": P2P_FLOPS_PER_PAIR,
                 "work_counted": "local-list pairs only (cut-off ring pairs not counted)"
                 if radius_t else "local-list pairs"}
@@ -568,8 +573,10 @@ def time_steps(torch, step, steps, tree=None, graph=True):
     """Mean ms of K steps, timed with HIP events on the current stream around
     one replay of a hipGraph that holds the K steps (captured after the warm-up
     and replayed once untimed, which uploads it), or around the K steps issued
-    eagerly.  With a tree, its phase-timing events of the K steps (inside the
-    graph when captured) are read back.  Returns (ms, wall seconds, phases)."""
+    eagerly.  With a tree (eager steps only: its phase events take no
+    timestamps inside a replayed graph), the phase times of the K steps are
+    read back.  Returns (ms, wall seconds, phases)."""
+    assert tree is None or not graph
     if tree is not None:
         tree.enable_timing(steps)
     graph_k = None
@@ -703,7 +710,10 @@ def bench_eval_points(a, torch, vf):
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 3),
                         "traffic": None, "kernel": "k_p2p<float>",
-                        "kernel_ms": round(p2p_ms, 4), "pairs_per_launch": pairs,
+                        "kernel_ms": round(p2p_ms, 4),
+                "kernel_ms_from": "HIP events around the kernel's launches on its stream in the "
+                                  "K timed steps issued eagerly (the same steps as the "
+                                  "graph-replayed ones)", "pairs_per_launch": pairs,
                         "flops_per_pair": P2P_FLOPS_PER_PAIR},
            "phases_ms": {k: round(float(np.mean([ph[k] for ph in phases])), 4) for k in phases[0]}}
     print(json.dumps(out), flush=True)

@@ -304,7 +304,10 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
  * on the tree's stream while 5-6 run on the caller's, so their times overlap.
  * After vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
  * next max_calls evaluations record HIP events at the beginning and end of
- * each phase on the stream that runs it (no synchronisation).
+ * each phase on the stream that runs it (no synchronisation).  In
+ * evaluations captured into a hipGraph these records only order the captured
+ * work and take no timestamps when the graph is replayed: time captured work
+ * from outside the graph.
  * vfmm_tree_read_timing waits for the recorded events, writes
  * ms[call * VFMM_N_PHASES + phase] (host, max_calls * VFMM_N_PHASES doubles)
  * and *n_calls (host), and starts a new recording.  Phases skipped by a call
