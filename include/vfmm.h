@@ -298,10 +298,10 @@ vfmm_status_t vfmm_tree_rebuild(vfmm_tree_t tree, const double* x, const double*
  * 0 gather circulations (and, for vfmm_fmm_velocity_at, the sort of the
  * evaluation points), 1 translation tables, 2 P2M, 3 M2M (levels L-1..2),
  * 4 M2L + L2L (levels 2..L), 5 near-field work schedule, 6 near field (P2P
- * kernel, after waiting for the gather), 7 L2P (after waiting for phases 1-4:
- * sums the parts of split near-field tiles, adds the far field and writes the
- * result).  When a call evaluates both parts, the gather and phases 1-4 run
- * on the tree's stream while 5-6 run on the caller's, so their times overlap.
+ * kernel), 7 L2P (after waiting for phases 1-4: sums the parts of split
+ * near-field tiles, adds the far field and writes the result).  When a call
+ * evaluates both parts, phases 1-4 run on the tree's stream while 5-6 run on
+ * the caller's (after the gather), so their times overlap.
  * After vfmm_tree_enable_timing(tree, max_calls) (max_calls >= 1; 0 disables), the
  * next max_calls evaluations record HIP events at the beginning and end of
  * each phase on the stream that runs it (no synchronisation).  In

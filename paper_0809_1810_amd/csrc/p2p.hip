@@ -147,12 +147,14 @@ __device__ __forceinline__ int tile_shift(const uint8_t* __restrict__ leaf_shift
   return leaf_shift ? int(leaf_shift[leaf]) : 0;
 }
 
+// Source chunks in segments first, first + stride, ... of a tile's sequence.
 __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int k, int nseg,
-                                                    const uint32_t* __restrict__ tile_off) {
+                                                    const uint32_t* __restrict__ tile_off,
+                                                    int first, int stride) {
   const int m = 1 << levels;
   const int bx = (leaf & (m - 1)) >> k, by = (leaf >> levels) >> k;
   uint32_t c = 0;
-  for (int s = 0; s < (nseg << k); ++s) {
+  for (int s = first; s < (nseg << k); s += stride) {
     int sy, lo, hi;
     if (fine_segment(s, k, bx, by, m >> k, sy, lo, hi))
       c += tile_off[sy * m + hi + 1] - tile_off[sy * m + lo];
@@ -160,82 +162,139 @@ __device__ __forceinline__ uint32_t sequence_chunks(int leaf, int levels, int k,
   return c;
 }
 
-// Source chunks per target tile (0 past the last tile), and per block their
-// 64-bit sum (the total over all tiles can exceed 32 bits).
+// Source chunks per target tile: kSchedLanes lanes per tile (an aligned
+// group of a wave) take every kSchedLanes-th segment of its sequence, and the
+// group adds up their counts.
+constexpr int kSchedLanes = 16;
 __global__ void __launch_bounds__(256) k_sched_count(const Tile* __restrict__ ttiles,
                                                      const int32_t* __restrict__ tntiles,
                                                      const uint32_t* __restrict__ tile_off,
                                                      const double* __restrict__ root, int levels,
-                                                     double cut2, int64_t max_tiles,
+                                                     double cut2,
                                                      const uint8_t* __restrict__ leaf_shift,
-                                                     uint32_t* __restrict__ cnt,
-                                                     uint64_t* __restrict__ bsum) {
-  __shared__ uint64_t red[256];
-  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+                                                     uint32_t* __restrict__ cnt) {
+  const int64_t t = (blockIdx.x * 256LL + threadIdx.x) / kSchedLanes;
+  const int sub = int(threadIdx.x) & (kSchedLanes - 1);
+  const bool live = t < *tntiles;
   uint32_t c = 0;
-  if (t < *tntiles) {
+  if (live) {
     const int leaf = ttiles[t].leaf;
     const int k = tile_shift(leaf_shift, leaf);
     const int nseg = near_rings(cut2, root[3] * double(1 << k)).nseg;
-    c = sequence_chunks(leaf, levels, k, nseg, tile_off);
+    c = sequence_chunks(leaf, levels, k, nseg, tile_off, sub, kSchedLanes);
   }
-  if (t <= max_tiles) cnt[t] = c;
-  red[threadIdx.x] = c;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+#pragma unroll
+  for (int o = kSchedLanes / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (live && sub == 0) cnt[t] = c;
 }
 
-// Parts per tile: part size K = max(kP2PMinChunks, ceil(total / P)) with
-// P = p2p_parts(max_tiles), parts = max(1, ceil(ch / K)); so the parts number
-// at most max_tiles + P and the parts of split tiles at most 2 P.  The total
-// chunk count is the sum of the nb block sums of k_sched_count, which every
-// block forms itself; ch is the difference of the scanned counts (exact
-// modulo 2^32).
-__global__ void __launch_bounds__(256) k_sched_parts(const int32_t* __restrict__ tntiles,
-                                                     const uint32_t* __restrict__ cnt,
-                                                     const uint64_t* __restrict__ bsum, int64_t nb,
-                                                     int64_t max_tiles,
-                                                     uint32_t* __restrict__ pcnt,
-                                                     uint32_t* __restrict__ scnt) {
-  __shared__ uint64_t red[256];
-  uint64_t s = 0;
-  for (int64_t b = threadIdx.x; b < nb; b += 256) s += bsum[b];
-  red[threadIdx.x] = s;
+// The schedule's offsets, in one workgroup over the nt = *tntiles tiles:
+// first the total of the source chunks (64 bits), hence the part size
+// K = max(kP2PMinChunks, ceil(total / P)), P = p2p_parts(max_tiles); then in
+// one pass per tile its parts np = max(1, ceil(ch / K)) (ch = cnt[t]), so the
+// parts number at most max_tiles + P and those of split tiles at most 2 P, and
+// three exclusive prefixes: cnt (source chunks, modulo 2^32), p_off (of np)
+// and s_off (of np for split tiles, else 0), with the totals at index nt and,
+// for the near-field kernel, p_off[max_tiles].  The arrays are 16-byte
+// aligned.
+__global__ void __launch_bounds__(kScanOneBlock) k_sched_scan(const int32_t* __restrict__ tntiles,
+                                                              int64_t max_tiles,
+                                                              uint32_t* __restrict__ cnt,
+                                                              uint32_t* __restrict__ p_off,
+                                                              uint32_t* __restrict__ s_off) {
+  __shared__ uint32_t ws[3 * (kScanOneBlock / 64)];
+  __shared__ unsigned long long ws64[kScanOneBlock / 64];
+  const int64_t nt = *tntiles;
+  const int64_t me = int64_t(threadIdx.x) * 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long s64 = 0;
+  for (int64_t i = me; i < nt; i += kScanOneRound) {
+    const uint4 q = scan_load4(cnt, i, nt);
+    s64 += (unsigned long long)q.x + q.y + q.z + q.w;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s64 += __shfl_xor(s64, o, 64);
+  if (lane == 0) ws64[wave] = s64;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  unsigned long long total = 0;
+#pragma unroll
+  for (int w = 0; w < kScanOneBlock / 64; ++w) total += ws64[w];
+  const unsigned long long P = (unsigned long long)p2p_parts(max_tiles);
+  unsigned long long K = (total + P - 1) / P;
+  if (K < kP2PMinChunks) K = kP2PMinChunks;
+  // ch < 2^32, so a part size of 2^32 or more gives one part per tile; below
+  // it ceil(ch / K) from the float64 quotient, corrected to the exact one
+  const bool one_part = K >= (1ull << 32);
+  const int64_t K64 = int64_t(K);
+  const double rK = 1.0 / double(K);
+  uint3 carry = make_uint3(0u, 0u, 0u);
+  for (int64_t base = 0; base < nt; base += kScanOneRound * kScanOneRounds) {
+    uint4 c[kScanOneRounds];
+#pragma unroll
+    for (int r = 0; r < kScanOneRounds; ++r) c[r] = scan_load4(cnt, base + r * kScanOneRound + me, nt);
+#pragma unroll
+    for (int r = 0; r < kScanOneRounds; ++r) {
+      const int64_t i = base + r * kScanOneRound + me;
+      if (base + r * kScanOneRound >= nt) break;  // uniform
+      const uint32_t ch[4] = {c[r].x, c[r].y, c[r].z, c[r].w};
+      uint32_t np[4], sp[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        np[j] = 0u;
+        if (i + j < nt) {
+          if (ch[j] == 0 || one_part) {
+            np[j] = 1u;
+          } else {
+            int64_t q = int64_t(double(ch[j]) * rK);
+            int64_t rem = int64_t(ch[j]) - q * K64;
+            if (rem < 0) { --q; rem += K64; }
+            if (rem >= K64) { ++q; rem -= K64; }
+            np[j] = uint32_t(q + (rem > 0 ? 1 : 0));
+          }
+        }
+        sp[j] = np[j] > 1 ? np[j] : 0u;
+      }
+      uint3 tot;
+      uint3 ex = block1k_scan3_excl(make_uint3(c[r].x + c[r].y + c[r].z + c[r].w,
+                                               np[0] + np[1] + np[2] + np[3],
+                                               sp[0] + sp[1] + sp[2] + sp[3]),
+                                    &tot, ws);
+      ex.x += carry.x;
+      ex.y += carry.y;
+      ex.z += carry.z;
+      scan_store4(cnt, i, nt, c[r], ex.x);
+      scan_store4(p_off, i, nt, make_uint4(np[0], np[1], np[2], np[3]), ex.y);
+      scan_store4(s_off, i, nt, make_uint4(sp[0], sp[1], sp[2], sp[3]), ex.z);
+      carry.x += tot.x;
+      carry.y += tot.y;
+      carry.z += tot.z;
+    }
   }
-  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
-  if (t > max_tiles) return;
-  uint32_t np = 0;
-  if (t < *tntiles) {
-    const uint64_t total = red[0];
-    const uint64_t P = uint64_t(p2p_parts(max_tiles));
-    uint64_t k = (total + P - 1) / P;
-    if (k < kP2PMinChunks) k = kP2PMinChunks;
-    const uint64_t ch = uint32_t(cnt[t + 1] - cnt[t]);
-    np = ch == 0 ? 1u : uint32_t((ch + k - 1) / k);
+  if (threadIdx.x == 0) {
+    cnt[nt] = carry.x;
+    p_off[nt] = carry.y;
+    s_off[nt] = carry.z;
+    p_off[max_tiles] = carry.y;
   }
-  pcnt[t] = np;
-  scnt[t] = np > 1 ? np : 0u;
 }
 
 // The tiles of one leaf share their local list, hence their chunk count and
 // number of parts; their parts are stored part-major (part k of every tile of
 // the leaf, then part k + 1), so that neighbouring waves read the same sources.
+// The same launch clears react (nreact entries; 0 without the symmetric near
+// field).
 __global__ void __launch_bounds__(256) k_sched_fill(const Tile* __restrict__ ttiles,
                                                     const int32_t* __restrict__ tntiles,
                                                     const uint32_t* __restrict__ ttile_off,
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ p_off,
                                                     const uint32_t* __restrict__ s_off,
-                                                    P2PPart* __restrict__ parts) {
+                                                    P2PPart* __restrict__ parts,
+                                                    double2* __restrict__ react, int64_t nreact) {
   const int64_t t = blockIdx.x * 256LL + threadIdx.x;
+  // the symmetric near field's float64 sums start at zero
+  for (int64_t i = t; i < nreact; i += int64_t(gridDim.x) * 256)
+    react[i] = make_double2(0.0, 0.0);
   if (t >= *tntiles) return;
   const int leaf = ttiles[t].leaf;
   const uint32_t t0 = ttile_off[leaf], ntl = ttile_off[leaf + 1] - t0;
@@ -633,26 +692,18 @@ __global__ void __launch_bounds__(256) k_l2p(
 
 inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-__global__ void __launch_bounds__(256) k_zero2(double2* __restrict__ a, int64_t n) {
-  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    a[i] = make_double2(0.0, 0.0);
-}
-
 hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, double cut2,
                           hipStream_t st) {
   const P2PSched& s = tg.sched;
   const int64_t mt = tg.max_tiles;
-  const int64_t nb = nblk(mt + 1, 256);
-  hipLaunchKernelGGL(k_sched_count, dim3(unsigned(nb)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     t.tile_off, t.root, levels, cut2, mt, tg.leaf_shift, s.cnt, s.bsum);
-  hipError_t e = scan_exclusive(s.cnt, mt + 1, s.scan_tmp, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sched_parts, dim3(unsigned(nb)), dim3(256), 0, st, tg.ntiles, s.cnt,
-                     s.bsum, nb, mt, s.p_off, s.s_off);
-  e = scan_exclusive2(s.p_off, s.s_off, mt + 1, s.scan_tmp, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sched_fill, dim3(nblk(mt, 256)), dim3(256), 0, st, tg.tiles, tg.ntiles,
-                     tg.tile_off, s.cnt, s.p_off, s.s_off, s.parts);
+  hipLaunchKernelGGL(k_sched_count, dim3(nblk(mt * kSchedLanes, 256)), dim3(256), 0, st, tg.tiles,
+                     tg.ntiles, t.tile_off, t.root, levels, cut2, tg.leaf_shift, s.cnt);
+  hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kScanOneBlock), 0, st, tg.ntiles, mt, s.cnt,
+                     s.p_off, s.s_off);
+  const int64_t nreact = tg.react ? t.n : 0;
+  const unsigned fb = nblk(mt, 256) > 0 ? nblk(mt, 256) : 1u;
+  hipLaunchKernelGGL(k_sched_fill, dim3(fb), dim3(256), 0, st, tg.tiles, tg.ntiles, tg.tile_off,
+                     s.cnt, s.p_off, s.s_off, s.parts, tg.react, nreact);
   return hipGetLastError();
 }
 
@@ -680,11 +731,7 @@ void launch_t(const TreeDev& t, const TargetsDev& tg, int levels, double sigma, 
   const P2PSched& s = tg.sched;
   double2* react = LPT == 1 ? tg.react : nullptr;
   size_t lds = 0;
-  if (react) {
-    hipLaunchKernelGGL(k_zero2, dim3(nblk(t.n, 256) < 4096 ? nblk(t.n, 256) : 4096u), dim3(256),
-                       0, st, react, t.n);
-    lds = size_t(wpb) * 128 * sizeof(SymRec<R>);
-  }
+  if (react) lds = size_t(wpb) * 128 * sizeof(SymRec<R>);  // react cleared by the schedule
   if (react)
     hipLaunchKernelGGL((k_p2p<R, LPT, true>), dim3(nblk(waves, wpb)), dim3(64 * wpb), lds, st,
                        part, t.leaf_start, t.tile_off, t.tile_box, tpart, tg.part64, tg.tiles,

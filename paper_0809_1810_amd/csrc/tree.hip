@@ -260,13 +260,43 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply_totals(uint32_t* __re
   }
 }
 
+// In-place exclusive scan of n elements by one workgroup (blockIdx.y selects
+// the array; 16-byte aligned), with a running carry (uniform over the
+// workgroup).
+__global__ void __launch_bounds__(kScanOneBlock) k_scan_one(uint32_t* __restrict__ a0,
+                                                            uint32_t* __restrict__ a1, int64_t n) {
+  __shared__ uint32_t ws[kScanOneBlock / 64];
+  uint32_t* a = blockIdx.y ? a1 : a0;
+  const int64_t me = int64_t(threadIdx.x) * 4;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += kScanOneRound * kScanOneRounds) {
+    uint4 q[kScanOneRounds];
+#pragma unroll
+    for (int r = 0; r < kScanOneRounds; ++r) q[r] = scan_load4(a, base + r * kScanOneRound + me, n);
+#pragma unroll
+    for (int r = 0; r < kScanOneRounds; ++r) {
+      if (base + r * kScanOneRound >= n) break;  // uniform
+      uint32_t tot;
+      const uint32_t ex =
+          block1k_scan_excl(q[r].x + q[r].y + q[r].z + q[r].w, &tot, ws) + carry;
+      scan_store4(a, base + r * kScanOneRound + me, n, q[r], ex);
+      carry += tot;
+    }
+  }
+}
+
 constexpr int64_t kScanFusedBlocks = 2048;
 
-// Up to kScanFusedBlocks blocks of kScanPerBlock elements: block totals, then
-// one pass that scans each block after its predecessors' totals (two launches,
-// one if the array fits one block); beyond that the three-phase scan.
+// Up to kScanOneMax elements: one workgroup (one launch).  Up to
+// kScanFusedBlocks blocks of kScanPerBlock elements: block totals, then one
+// pass that scans each block after its predecessors' totals (two launches);
+// beyond that the three-phase scan.
 hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (n <= kScanOneMax && (reinterpret_cast<uintptr_t>(a) & 15) == 0) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneBlock), 0, st, a, a, n);
+    return hipGetLastError();
+  }
   int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
   if (nb <= kScanFusedBlocks) {
     if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, a, a, n, tmp);
@@ -283,6 +313,10 @@ hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st)
 // beyond kScanFusedBlocks blocks, one after the other.
 hipError_t scan_exclusive2(uint32_t* a, uint32_t* b, int64_t n, uint32_t* tmp, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (n <= kScanOneMax && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1, 2), dim3(kScanOneBlock), 0, st, a, b, n);
+    return hipGetLastError();
+  }
   int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
   if (nb > kScanFusedBlocks) {
     hipError_t e = scan_exclusive(a, n, tmp, st);
@@ -656,7 +690,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
                      reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
                      reinterpret_cast<double2*>(ws + lay.sched_partial),
-                     reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp,
+                     tmp,
                      reinterpret_cast<double2*>(ws + lay.sched_near)};
   t.max_tiles = lay.max_tiles;
   hipLaunchKernelGGL(k_tile_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, k0, lstart, toff, n, nl,
@@ -704,7 +738,7 @@ hipError_t launch_build_targets(const double* xt, const double* yt, int64_t nt, 
                        reinterpret_cast<uint32_t*>(ws + lay.sched_soff),
                        reinterpret_cast<P2PPart*>(ws + lay.sched_parts),
                        reinterpret_cast<double2*>(ws + lay.sched_partial),
-                       reinterpret_cast<uint64_t*>(ws + lay.sched_bsum), tmp,
+                       tmp,
                      reinterpret_cast<double2*>(ws + lay.sched_near)};
   out = TargetsDev{p64, p32, tiles, ntiles, tbox, toff, i0, lay.max_tiles, sched};
   return hipGetLastError();
@@ -798,7 +832,7 @@ hipError_t launch_build_adaptive(const TreeDev& t, int levels, int64_t s, const 
                        reinterpret_cast<uint32_t*>(ws + tl.sched_soff),
                        reinterpret_cast<P2PPart*>(ws + tl.sched_parts),
                        reinterpret_cast<double2*>(ws + tl.sched_partial),
-                       reinterpret_cast<uint64_t*>(ws + tl.sched_bsum), tmp,
+                       tmp,
                        reinterpret_cast<double2*>(ws + tl.sched_near)};
   out = TargetsDev{p64, p32, tiles, ntiles, tbox, toff, perm, tl.max_tiles, sched, shift, fine64};
   return hipGetLastError();

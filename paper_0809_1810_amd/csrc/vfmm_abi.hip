@@ -31,12 +31,11 @@ struct vfmm_tree_s {
   std::vector<hipEvent_t> ev;  // phase-timing ring: begin and end of each phase, per call
   int t_slots;
   int t_used;
-  // the gather and the expansion sweeps run on `side` (default priority),
-  // concurrently with the near-field schedule and the near field on the
-  // caller's stream: fork at the start, the near field waits for the gather
-  // (gathered), L2P for the sweeps (join)
+  // the expansion sweeps run on `side` (default priority), concurrently with
+  // the near-field schedule and the near field on the caller's stream: fork
+  // after the gather of the circulations, L2P waits for the sweeps (join)
   hipStream_t side;
-  hipEvent_t fork, gathered, join;
+  hipEvent_t fork, join;
   // opt-in finiteness check of evaluations (vfmm_tree_set_check_finite):
   // the two device counters are read back into this pinned host pair
   int check_finite;
@@ -51,7 +50,6 @@ struct vfmm_tree_s {
     if (check_host) (void)hipHostFree(check_host);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
-    if (gathered) (void)hipEventDestroy(gathered);
     if (join) (void)hipEventDestroy(join);
     if (side) (void)hipStreamDestroy(side);
   }
@@ -155,7 +153,6 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.sched_soff = take(size_t(L.max_tiles + 1) * 4);
   L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
   L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
-  L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
   L.sched_near = take(size_t(n) * sizeof(double2));
   L.part64 = take(size_t(n) * sizeof(Part64));
   L.part32 = take(size_t(n) * sizeof(Part32));
@@ -231,7 +228,6 @@ vfmm_status_t vfmm_build_tree(const double* x, const double* y, int64_t n, int32
   t->last_prec = -1;
   hipError_t e = hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&t->gathered, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -332,13 +328,13 @@ struct Marks {
 
 enum Phase { kPhGather = 0, kPhTables, kPhP2M, kPhM2M, kPhM2L, kPhSched, kPhP2P, kPhL2P };
 
-// One evaluation on target set tg (Fig. 3): on the tree's side stream, the
-// circulations into the sorted particles, the operator tables, P2M, M2M and
-// M2L + L2L, while the caller's stream builds the near-field schedule and,
-// once the circulations are in place, runs the near field; after both, L2P
-// adds the far field to the near field and writes the result.  Every launch is
-// ordered after the work queued on st before the call, and st waits for the
-// side stream before L2P, so the call behaves as one ordered sequence on st.
+// One evaluation on target set tg (Fig. 3): the circulations into the sorted
+// particles on the caller's stream; then on the tree's side stream the
+// operator tables, P2M, M2M and M2L + L2L, while the caller's stream builds
+// the near-field schedule and runs the near field; after both, L2P adds the
+// far field to the near field and writes the result.  Every launch is ordered
+// after the work queued on st before the call, and st waits for the side
+// stream before L2P, so the call behaves as one ordered sequence on st.
 vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma, double sigma,
                        int32_t p, int32_t precision, int32_t parts, double* u, double* v,
                        const Marks& mark, hipStream_t st) {
@@ -354,20 +350,27 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   // the gather and the sweeps go to the side stream only when there is
   // near-field work to overlap
   hipStream_t sw = near && far ? t->side : st;
-  hipError_t e = hipSuccess;
+  // (the caller has opened the gather phase on st) the circulations into the
+  // sorted particles, on st before the fork: the near field then depends on
+  // nothing on the side stream (in a replayed graph, a node whose inputs come
+  // from another branch was measured to start tens of microseconds after them)
+  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, st);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  mark.end(kPhGather, st);
   if (sw != st) {
     e = hipEventRecord(t->fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(sw, t->fork, 0);
     if (e != hipSuccess) return hip_fail(e, "fork");
   }
-  // (the caller has opened the gather phase on st)
-  e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, sw);
-  if (e != hipSuccess) return hip_fail(e, "gather");
-  mark.end(kPhGather, sw);
-  if (sw != st) {
-    e = hipEventRecord(t->gathered, sw);
-    if (e != hipSuccess) return hip_fail(e, "gather event");
+  // the near-field schedule is enqueued before the sweeps: a captured graph
+  // then keeps the caller's branch (schedule, near field) on the queue that
+  // ran the gather
+  mark.begin(kPhSched, st);
+  if (near) {
+    e = launch_p2p_schedule(t->dev, tg, L, prec, sigma, t->near_radius, st);
+    if (e != hipSuccess) return hip_fail(e, "P2P schedule");
   }
+  mark.end(kPhSched, st);
   mark.begin(kPhTables, sw);
   if (far && t->ops_p != p) {
     e = launch_build_ops(t->dev, p, prec, sw);
@@ -407,16 +410,6 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   if (sw != st) {
     e = hipEventRecord(t->join, sw);
     if (e != hipSuccess) return hip_fail(e, "join");
-  }
-  mark.begin(kPhSched, st);
-  if (near) {
-    e = launch_p2p_schedule(t->dev, tg, L, prec, sigma, t->near_radius, st);
-    if (e != hipSuccess) return hip_fail(e, "P2P schedule");
-  }
-  mark.end(kPhSched, st);
-  if (sw != st) {
-    e = hipStreamWaitEvent(st, t->gathered, 0);
-    if (e != hipSuccess) return hip_fail(e, "gather event");
   }
   mark.begin(kPhP2P, st);
   if (near) {
@@ -475,7 +468,6 @@ TargetLayout make_target_layout(int64_t nt, int levels) {
   L.sched_soff = take(size_t(L.max_tiles + 1) * 4);
   L.sched_parts = take(size_t(L.max_tiles + p2p_parts(L.max_tiles)) * sizeof(P2PPart));
   L.sched_partial = take(size_t(2 * p2p_parts(L.max_tiles)) * kTile * sizeof(double2));
-  L.sched_bsum = take(size_t(sched_bsum_len(L.max_tiles)) * sizeof(uint64_t));
   L.sched_near = take(size_t(nt) * sizeof(double2));
   L.part64 = take(size_t(nt) * sizeof(Part64));
   L.part32 = take(size_t(nt) * sizeof(Part32));

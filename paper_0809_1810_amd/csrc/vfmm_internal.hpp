@@ -100,11 +100,9 @@ struct P2PSched {
   uint32_t* s_off;    // [max_tiles + 1] first partial slot of each split tile
   P2PPart* parts;     // [max_tiles + p2p_parts(max_tiles)]
   double2* partial;   // [2 p2p_parts(max_tiles)][kTile] near-field sums (u, v) of one part
-  uint64_t* bsum;     // [ceil((max_tiles + 1) / 256) + 1] chunk sums per block of k_sched_count
   uint32_t* scan_tmp;
   double2* near;      // [targets] near field (times 1 / 2 pi) of single-part tiles, sorted order
 };
-inline int64_t sched_bsum_len(int64_t max_tiles) { return (max_tiles + 1 + 255) / 256 + 1; }
 
 inline __host__ __device__ int64_t level_offset(int l) {
   // boxes of levels 2 .. l-1 stored before level l
@@ -120,7 +118,7 @@ inline __host__ __device__ int64_t n_boxes_2_to(int L) {
 struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
-  size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum, sched_near;
+  size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_near;
   size_t part64, part32, part32s, react, me, le, me32, le32, ops, check, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
@@ -199,7 +197,7 @@ inline TargetsDev self_targets(const TreeDev& t, const Layout& lay) {
 // Workspace of a separate evaluation-point set of nt points at leaf level L.
 struct TargetLayout {
   size_t keys0, keys1, idx0, idx1, counts, scan_tmp, leaf_start, tile_off, tiles, ntiles,
-      tile_box, sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_bsum,
+      tile_box, sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial,
       sched_near, part64,
       part32, total;
   int64_t nt, nleaves, max_tiles, sort_blocks, count_len;
@@ -303,6 +301,115 @@ hipError_t launch_heun_correct(double* x, double* y, const double* u1, const dou
                                const double* u2, const double* v2, int64_t n, double dt,
                                hipStream_t stream);
 size_t ops_bytes(int p);
+
+// Scans inside one workgroup of kScanOneBlock threads (16 waves): the
+// one-launch scans of arrays up to kScanOneMax elements, and the near-field
+// schedule's offsets.  A round takes 4 consecutive elements per thread (one
+// 16-byte access, so a wave reads 1 KB in one instruction); a pass issues the
+// loads of kScanOneRounds rounds before scanning them in order.
+constexpr int kScanOneBlock = 1024;
+constexpr int kScanOneRounds = 4;
+constexpr int64_t kScanOneRound = int64_t(kScanOneBlock) * 4;
+constexpr int64_t kScanOneMax = 65536;
+// Elements i .. i + 3 of a (zeros at and past n); a 16-byte aligned.
+__device__ inline uint4 scan_load4(const uint32_t* a, int64_t i, int64_t n) {
+  if (i + 3 < n) return *reinterpret_cast<const uint4*>(a + i);
+  uint4 q = make_uint4(0u, 0u, 0u, 0u);
+  if (i < n) q.x = a[i];
+  if (i + 1 < n) q.y = a[i + 1];
+  if (i + 2 < n) q.z = a[i + 2];
+  return q;
+}
+// Writes the exclusive prefixes ex, ex + q.x, ... of elements i .. i + 3 (below n).
+__device__ inline void scan_store4(uint32_t* a, int64_t i, int64_t n, uint4 q, uint32_t ex) {
+  uint4 o;
+  o.x = ex;
+  o.y = o.x + q.x;
+  o.z = o.y + q.y;
+  o.w = o.z + q.z;
+  if (i + 3 < n) {
+    *reinterpret_cast<uint4*>(a + i) = o;
+    return;
+  }
+  if (i < n) a[i] = o.x;
+  if (i + 1 < n) a[i + 1] = o.y;
+  if (i + 2 < n) a[i + 2] = o.z;
+}
+// Inclusive scan over a wave by DPP: Hillis-Steele within each row of 16
+// lanes (row_shr 1, 2, 4, 8, zeros shifted in), then the last lane of row 0
+// added to row 1 and of row 2 to row 3 (row_bcast:15), then that of row 1 to
+// rows 2 and 3 (row_bcast:31).
+__device__ inline uint32_t wave_scan_incl_u32(uint32_t v) {
+  int x = int(v);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
+  return uint32_t(x);
+}
+// Exclusive prefix of one value per thread over the workgroup, and the
+// workgroup total; ws: 16 entries of LDS.  Every thread must call it.  The
+// waves' totals are scanned by the first 16 lanes of each wave (row_shr within
+// row 0) and read back with readlane.
+__device__ inline uint32_t block1k_scan_excl(uint32_t v, uint32_t* total, uint32_t* ws) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const uint32_t incl = wave_scan_incl_u32(v);
+  if (lane == 63) ws[wave] = incl;
+  __syncthreads();
+  int a = lane < 16 ? int(ws[lane]) : 0;
+  __syncthreads();
+  a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xf, 0xf, true);
+  const uint32_t pre = wave ? uint32_t(__builtin_amdgcn_readlane(a, wave - 1)) : 0u;
+  *total = uint32_t(__builtin_amdgcn_readlane(a, 15));
+  return pre + incl - v;
+}
+
+// Three exclusive prefixes at once (one value of each of three sequences per
+// thread) over the workgroup, with the totals; ws: 3 x 16 entries of LDS.
+// Every thread must call it.  Each wave's totals are scanned by its first 16
+// lanes (row_shr within row 0) and read back with readlane.
+__device__ inline uint3 block1k_scan3_excl(uint3 v, uint3* total, uint32_t* ws) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const uint32_t ix = wave_scan_incl_u32(v.x), iy = wave_scan_incl_u32(v.y),
+                 iz = wave_scan_incl_u32(v.z);
+  if (lane == 63) {
+    ws[wave] = ix;
+    ws[16 + wave] = iy;
+    ws[32 + wave] = iz;
+  }
+  __syncthreads();
+  int a = lane < 16 ? int(ws[lane]) : 0, b = lane < 16 ? int(ws[16 + lane]) : 0,
+      c = lane < 16 ? int(ws[32 + lane]) : 0;
+  __syncthreads();
+  a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xf, 0xf, true);
+  b += __builtin_amdgcn_update_dpp(0, b, 0x111, 0xf, 0xf, true);
+  c += __builtin_amdgcn_update_dpp(0, c, 0x111, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xf, 0xf, true);
+  b += __builtin_amdgcn_update_dpp(0, b, 0x112, 0xf, 0xf, true);
+  c += __builtin_amdgcn_update_dpp(0, c, 0x112, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xf, 0xf, true);
+  b += __builtin_amdgcn_update_dpp(0, b, 0x114, 0xf, 0xf, true);
+  c += __builtin_amdgcn_update_dpp(0, c, 0x114, 0xf, 0xf, true);
+  a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xf, 0xf, true);
+  b += __builtin_amdgcn_update_dpp(0, b, 0x118, 0xf, 0xf, true);
+  c += __builtin_amdgcn_update_dpp(0, c, 0x118, 0xf, 0xf, true);
+  // lane w of row 0 holds the inclusive sums of the totals of waves 0 .. w
+  const uint32_t px = wave ? uint32_t(__builtin_amdgcn_readlane(a, wave - 1)) : 0u;
+  const uint32_t py = wave ? uint32_t(__builtin_amdgcn_readlane(b, wave - 1)) : 0u;
+  const uint32_t pz = wave ? uint32_t(__builtin_amdgcn_readlane(c, wave - 1)) : 0u;
+  *total = make_uint3(uint32_t(__builtin_amdgcn_readlane(a, 15)),
+                      uint32_t(__builtin_amdgcn_readlane(b, 15)),
+                      uint32_t(__builtin_amdgcn_readlane(c, 15)));
+  return make_uint3(px + ix - v.x, py + iy - v.y, pz + iz - v.z);
+}
+
 // Shared building blocks (tree.hip).
 hipError_t scan_exclusive(uint32_t* a, int64_t n, uint32_t* tmp, hipStream_t st);
 // Two arrays of n elements at once; tmp holds 2 ceil(n / kScanPerBlock) entries.
