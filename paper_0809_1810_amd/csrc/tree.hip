@@ -120,15 +120,21 @@ __device__ inline bool in_root(double x, double y, const double* __restrict__ ro
   return x >= x0 && x <= x0 + S && y >= y0 && y <= y0 + S;
 }
 
+// Sort keys, the identity permutation, and the positions interleaved (one
+// 16-byte record per particle, so that the gather after the sort reads one
+// record per particle instead of two values from two arrays).
 __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
                                               const double* __restrict__ y, int64_t n,
                                               const double* __restrict__ root, int levels,
                                               uint32_t* __restrict__ keys,
-                                              int32_t* __restrict__ idx) {
+                                              int32_t* __restrict__ idx,
+                                              double2* __restrict__ xy) {
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
-  keys[i] = point_key(x[i], y[i], root, levels);
+  const double xi = x[i], yi = y[i];
+  keys[i] = point_key(xi, yi, root, levels);
   idx[i] = int32_t(i);
+  xy[i] = make_double2(xi, yi);
 }
 
 // Evaluation points: points outside the root square get key 0 (their
@@ -404,8 +410,7 @@ __global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__
   start[k] = int32_t(lo);
 }
 
-__global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__ x,
-                                                      const double* __restrict__ y,
+__global__ void __launch_bounds__(256) k_local_coords(const double2* __restrict__ xy,
                                                       const uint32_t* __restrict__ keys,
                                                       const int32_t* __restrict__ perm, int64_t n,
                                                       const double* __restrict__ root, int levels,
@@ -419,8 +424,8 @@ __global__ void __launch_bounds__(256) k_local_coords(const double* __restrict__
   const double w = root[3];
   const double cx = root[0] + (double(ix) + 0.5) * w;
   const double cy = root[1] + (double(iy) + 0.5) * w;
-  const int32_t j = perm[i];
-  const double lx = x[j] - cx, ly = y[j] - cy;
+  const double2 q = xy[perm[i]];
+  const double lx = q.x - cx, ly = q.y - cy;
   p64[i] = Part64{lx, ly, 0.0, 0.0};
   p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
 }
@@ -638,8 +643,9 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, st, bbox, nbb, domain ? 1 : 0,
                      domain ? domain[0] : 0.0, domain ? domain[1] : 0.0,
                      domain ? domain[2] : 1.0, levels, root);
+  double2* xy = reinterpret_cast<double2*>(ws + lay.xy);
   hipLaunchKernelGGL(k_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, n, root, levels, k0,
-                     i0);
+                     i0, xy);
   const int nblk = int(lay.sort_blocks);
   int bits_left = 2 * (levels + kSubLevels), shift = 0;
   while (bits_left > 0) {
@@ -676,7 +682,7 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.le32 = ws + lay.le32;
   t.ops = ws + lay.ops;
   t.check = reinterpret_cast<unsigned long long*>(ws + lay.check);
-  hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, k0, i0, n,
+  hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, xy, k0, i0, n,
                      root, levels, t.part64, t.part32);
   t.tile = tile;
   hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,

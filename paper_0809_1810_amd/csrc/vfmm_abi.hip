@@ -158,6 +158,7 @@ Layout make_layout(int64_t n, int levels, int p_max) {
   L.part32 = take(size_t(n) * sizeof(Part32));
   L.part32s = take(size_t(n) * sizeof(Part32));
   L.react = take(size_t(n) * sizeof(double2));
+  L.xy = take(size_t(n) * sizeof(double2));
   L.me = take(size_t(nbox) * p_max * sizeof(double2));
   L.le = take(size_t(nbox) * p_max * sizeof(double2));
   const size_t nb32 = p_max > kShift64P ? size_t(nbox) * p_max * sizeof(float2) : 0;

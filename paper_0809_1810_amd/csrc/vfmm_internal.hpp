@@ -119,7 +119,7 @@ struct Layout {
   size_t root, bbox, keys0, keys1, idx0, idx1, counts, scan_tmp;
   size_t leaf_start, tile_off, tiles, ntiles, tile_box;
   size_t sched_cnt, sched_poff, sched_soff, sched_parts, sched_partial, sched_near;
-  size_t part64, part32, part32s, react, me, le, me32, le32, ops, check, total;
+  size_t part64, part32, part32s, react, xy, me, le, me32, le32, ops, check, total;
   int64_t n, nleaves, max_tiles, sort_blocks, count_len;
   int levels, p_max;
 };
