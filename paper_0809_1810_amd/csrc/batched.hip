@@ -448,8 +448,8 @@ __global__ void __launch_bounds__(256) k_b_l2l(const BatchInst* __restrict__ I,
 // (4 classes x ceil(4^(lev-1) / 32) tiles), seg_il[s] = instance << 8 | level.
 // MT = 1: the instances with p <= 16, on their float32 coefficients; MT = 2:
 // the instances with p > 16 (2p <= 48 rows in two 32-row tiles), on the float32
-// copies of their float64 multipoles (k_b_narrow), into float32 locals that
-// k_b_widen adds to the float64 L2L chain.
+// copies of their float64 multipoles (k_b_convert, narrow), into float32
+// locals that k_b_convert (widen) adds to the float64 L2L chain.
 template <int MT>
 __global__ void __launch_bounds__(256) k_b_m2l_mfma(const BatchInst* __restrict__ I,
                                                     const int64_t* __restrict__ seg_off,
