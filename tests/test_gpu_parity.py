@@ -54,10 +54,17 @@ def _tree_check(vf, P, levels, domain=None):
 
 
 @pytest.mark.parametrize("case", ["uniform_1k_L3", "uniform_1k_L0", "clusters_64k_L5",
-                                  "lattice_320_L6", "edges_L2", "uniform_33m_L8"])
+                                  "lattice_320_L6", "edges_L2", "uniform_33m_L8",
+                                  "uniform_512k_L6", "uniform_512k1_L6"])
 def test_tree_bit_exact(vf, case):
     print_case("tree", case=case)
-    if case == "uniform_33m_L8":
+    if case in ("uniform_512k_L6", "uniform_512k1_L6"):
+        # 2^19 particles: 256 sort blocks of 2048 keys, 65536 radix counts, the
+        # largest count array scanned by one workgroup; one particle more takes
+        # the two-launch scan
+        n = 2 ** 19 + (1 if case.endswith("1_L6") else 0)
+        _tree_check(vf, W.uniform(n, seed=12), 6).close()
+    elif case == "uniform_33m_L8":
         # 2^25 + 4097 particles: the radix counts (256 per block of 2048 keys)
         # need 2049 scan blocks, past the two-launch scan's limit of 2048, so
         # the sort takes the three-phase scan
@@ -212,6 +219,32 @@ def test_clusters_full_size_sampled(vf):
     e32 = rel_err(u32[tg], v32[tg], ud, vd)[0]
     print(f"clusters_1m L6: fp64 p20 vs direct {e64:.3e}; fp32 p14 vs direct {e32:.3e}")
     assert e64 < 1e-6 and e32 < 1e-6
+
+
+@pytest.mark.parametrize("radius", [0.0, "auto"])
+def test_fmm_fp64_level8_schedule(vf, radius):
+    """L = 8 with about four particles per leaf: 65,537 leaf offsets (past the
+    one-workgroup scan, so the two-launch one), ~60,000 target tiles (the
+    schedule's offsets in several passes of its workgroup), and with the
+    automatic radius four rings of leaves (39 segments per tile sequence).
+    FP64 against the oracle FMM at the same (p, L, radius) on 48 sampled
+    targets, to 1e-12 of the sample's maximum velocity."""
+    P = W.uniform(262144 + 77, seed=21)
+    L, p = 8, 8
+    print_case("fmm_L8_schedule", n=P.n, radius=radius)
+    t = vf.Tree(dev(P.x), dev(P.y), L, p_max=p)
+    w = float(t.arrays()[0][2].item()) / 2 ** L
+    r_eff = 0.0
+    if radius == "auto":
+        t.set_near_radius(vf.NEAR_RADIUS_AUTO)
+        r_eff = min(math.sqrt(76.0) * P.sigma, vf.NEAR_RINGS_MAX * w)
+    u, v = (host(a) for a in t.velocity(dev(P.gamma), P.sigma, p, vf.FP64))
+    t.close()
+    tg = W.sample_targets(P.n, 48, seed=5)
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, L, targets=tg, radius=r_eff)
+    e = rel_err(u[tg], v[tg], r.u, r.v)[0]
+    print(f"L8 schedule radius={radius}: {e:.3e}")
+    assert e < 1e-12
 
 
 @pytest.mark.parametrize("tile,waves,sym", [(64, 1, 0), (32, 2, 0), (16, 8, 0), (32, 4, 0),
