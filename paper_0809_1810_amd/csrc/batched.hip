@@ -126,11 +126,15 @@ __global__ void __launch_bounds__(256) k_b_bbox(const BatchInst* __restrict__ I,
   }
 }
 
+// Sort keys, the identity permutation, and each particle's record in input
+// order (leaf-local position in units of the instance's Gaussian width, as in
+// the single tree, and circulation), which k_b_local moves to sorted order.
 __global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
                                                 const int64_t* __restrict__ part_off, int count,
                                                 int64_t ntot, const double* __restrict__ roots,
                                                 uint32_t* __restrict__ keys,
-                                                int32_t* __restrict__ idx) {
+                                                int32_t* __restrict__ idx,
+                                                Part32* __restrict__ raw) {
 #pragma clang fp contract(off)
   const int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= ntot) return;
@@ -139,8 +143,9 @@ __global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
   const int64_t j = i - in.part_off;
   const double* r = roots + 4 * c;
   const int mf = 1 << (in.L + kBatchSub);
-  const double fx = floor(((in.x[j] - r[0]) / r[2]) * double(mf));
-  const double fy = floor(((in.y[j] - r[1]) / r[2]) * double(mf));
+  const double xj = in.x[j], yj = in.y[j];
+  const double fx = floor(((xj - r[0]) / r[2]) * double(mf));
+  const double fy = floor(((yj - r[1]) / r[2]) * double(mf));
   const int ix = !(fx >= 0.0) ? 0 : (fx > double(mf - 1) ? mf - 1 : int(fx));
   const int iy = !(fy >= 0.0) ? 0 : (fy > double(mf - 1) ? mf - 1 : int(fy));
   const uint32_t leaf = (uint32_t(iy >> kBatchSub) << in.L) | uint32_t(ix >> kBatchSub);
@@ -148,6 +153,10 @@ __global__ void __launch_bounds__(256) k_b_keys(const BatchInst* __restrict__ I,
   const uint32_t sub = spread4b(uint32_t(ix) & cm) | (spread4b(uint32_t(iy) & cm) << 1);
   keys[i] = (uint32_t(c) << kBatchKeyInst) | (leaf << (2 * kBatchSub)) | sub;
   idx[i] = int32_t(i);
+  const double cx = r[0] + (double(ix >> kBatchSub) + 0.5) * r[3];
+  const double cy = r[1] + (double(iy >> kBatchSub) + 0.5) * r[3];
+  const double sd = near_scale(in.sigma);
+  raw[i] = Part32{float((xj - cx) * sd), float((yj - cy) * sd), float(in.g[j]), 0.0f};
 }
 
 // leaf_start[leaf_off + c + k] = first sorted position of leaf k of instance c,
@@ -168,26 +177,14 @@ __global__ void __launch_bounds__(256) k_b_leaf_start(const int64_t* __restrict_
   start[q] = int32_t(lo);
 }
 
-__global__ void __launch_bounds__(256) k_b_local(const BatchInst* __restrict__ I,
-                                                 const uint32_t* __restrict__ keys,
+// The particles' records in sorted order (one 16-byte record per particle
+// through the permutation).
+__global__ void __launch_bounds__(256) k_b_local(const Part32* __restrict__ raw,
                                                  const int32_t* __restrict__ perm, int64_t ntot,
-                                                 const double* __restrict__ roots,
                                                  Part32* __restrict__ p32) {
-#pragma clang fp contract(off)
   const int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= ntot) return;
-  const uint32_t key = keys[i];
-  const int c = int(key >> kBatchKeyInst);
-  const BatchInst in = I[c];
-  const uint32_t leaf = (key >> (2 * kBatchSub)) & 0xFFFu;
-  const int ix = int(leaf & ((1u << in.L) - 1u)), iy = int(leaf >> in.L);
-  const double* r = roots + 4 * c;
-  const double cx = r[0] + (double(ix) + 0.5) * r[3];
-  const double cy = r[1] + (double(iy) + 0.5) * r[3];
-  const int64_t j = int64_t(perm[i]) - in.part_off;
-  // leaf-local, in units of the instance's Gaussian width (as in the single tree)
-  const double sd = near_scale(in.sigma);
-  p32[i] = Part32{float((in.x[j] - cx) * sd), float((in.y[j] - cy) * sd), float(in.g[j]), 0.0f};
+  p32[i] = raw[perm[i]];
 }
 
 __global__ void __launch_bounds__(256) k_b_tile_counts(const int64_t* __restrict__ leaf_off,
@@ -712,7 +709,7 @@ struct BatchPlanDev {
   int64_t* l2l_items;
   int64_t* seg_off;  // matrix-core M2L: first tile of each (instance, level), FP32
   int32_t* seg_il;
-  int64_t* seg_off64;  // and FP64
+  int64_t* seg_off64;  // and of the p > 16 instances (two 32-row tiles)
   int32_t* seg_il64;
   double* roots;
   uint32_t *k0, *k1, *counts, *tmp, *toff;
@@ -722,6 +719,7 @@ struct BatchPlanDev {
   Tile* tiles;
   float4* tile_box;
   Part32* p32;
+  Part32* raw;  // the records in input order (sort phase)
   char *me, *le, *tab;
   char *me32, *le32;    // float32 copies of the p > 16 instances' coefficients
   int64_t* w64_items;   // [count + 1]: their coefficients of levels 2 .. L, cumulated
@@ -741,7 +739,7 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
   auto nb = [](int64_t n, int b) { return unsigned((n + b - 1) / b); };
   hipLaunchKernelGGL(k_b_bbox, dim3(count), dim3(256), 0, st, d.inst, d.roots, d.nbig);
   hipLaunchKernelGGL(k_b_keys, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, d.part_off, count,
-                     ntot, d.roots, d.k0, d.i0);
+                     ntot, d.roots, d.k0, d.i0, d.raw);
   uint32_t* k0 = d.k0; uint32_t* k1 = d.k1;
   int32_t* i0 = d.i0; int32_t* i1 = d.i1;
   int ibits = 1;
@@ -750,8 +748,7 @@ hipError_t batch_launch_all(const BatchPlanDev& d, int count, int64_t ntot, int6
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_b_leaf_start, dim3(nb(nleaves + count, 256)), dim3(256), 0, st, d.ls_off,
                      count, k0, ntot, d.start);
-  hipLaunchKernelGGL(k_b_local, dim3(nb(ntot, 256)), dim3(256), 0, st, d.inst, k0, i0, ntot,
-                     d.roots, d.p32);
+  hipLaunchKernelGGL(k_b_local, dim3(nb(ntot, 256)), dim3(256), 0, st, d.raw, i0, ntot, d.p32);
   e = hipEventRecord(fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(sw, fork, 0);
   if (e != hipSuccess) return e;
@@ -868,7 +865,7 @@ inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 struct BatchLayout {
   size_t inst, part_off, leaf_off, ls_off, tab_off, m2m_items, l2l_items, seg_off, seg_il,
       seg_off64, seg_il64, roots, k0, k1, i0, i1,
-      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, me, le, tab, me32, le32,
+      counts, tmp, toff, start, ntiles, big, nbig, tiles, tile_box, p32, raw, me, le, tab, me32, le32,
       w64_items, nearv, react, total;
   int64_t ntot, nleaves, max_tiles, me_bytes, me32_bytes, tab_bytes;
   int maxL;
@@ -949,6 +946,7 @@ BatchLayout batch_layout(const vfmm_instance* in, int count) {
   L.tiles = take(sizeof(Tile) * size_t(L.max_tiles));
   L.tile_box = take(sizeof(float4) * size_t(L.max_tiles));
   L.p32 = take(sizeof(Part32) * size_t(L.ntot));
+  L.raw = take(sizeof(Part32) * size_t(L.ntot));
   L.me = take(size_t(L.me_bytes));
   L.le = take(size_t(L.me_bytes));
   L.tab = take(size_t(L.tab_bytes));
@@ -1092,6 +1090,7 @@ static vfmm_status_t vfmm_batch_create_impl(const vfmm_instance* inst, int32_t c
   d.tiles = reinterpret_cast<Tile*>(ws + L.tiles);
   d.tile_box = reinterpret_cast<float4*>(ws + L.tile_box);
   d.p32 = reinterpret_cast<Part32*>(ws + L.p32);
+  d.raw = reinterpret_cast<Part32*>(ws + L.raw);
   d.me = ws + L.me;
   d.le = ws + L.le;
   d.tab = ws + L.tab;
