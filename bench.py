@@ -320,7 +320,7 @@ def main():
         from paper_0809_1810_amd import selector as S
         weights = S.load_weights()
         s0 = time.perf_counter()
-        selection_shape(n)
+        selection_shape(P)
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=weights, targets=tg_d,
                                reference=(ud, vd))
         torch.cuda.synchronize()
@@ -338,7 +338,8 @@ def main():
     from paper_0809_1810_amd import autotune as AT
 
     def run_path(L, p, prec, steps, warmup, timing=False, radius=0.0, capacity=None):
-        AT.apply_for(n, L, cutoff=radius != 0.0)  # near-field launch shape from the autotuner's table
+        # near-field launch shape from the autotuner's table (mean and spread of the leaf occupancy)
+        AT.apply_for(n, L, cutoff=radius != 0.0, spread=AT.leaf_spread(P.x, P.y, L))
         override_tuning(a, vf)
         tree = vf.Tree(x, y, L, p_max=p)
         tree.set_near_radius(radius)
@@ -532,13 +533,13 @@ def second_input(a, torch, vf, name):
     ud, vd = vf.direct_velocity(x, y, g, P.sigma, targets=tg)
     th = torch.from_numpy(holdout_targets(n, AUDIT_TARGETS, tg_h, HOLDOUT_SEED)).cuda()
     uh, vh = vf.direct_velocity(x, y, g, P.sigma, targets=th)
-    selection_shape(n)
+    selection_shape(P)
     r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights(), targets=tg,
                            reference=(ud, vd))
     prec = vf.FP64 if r["precision"] == "fp64" else vf.FP32
 
     def run(L, p, pr, radius):
-        AT.apply_for(n, L, cutoff=radius != 0.0)
+        AT.apply_for(n, L, cutoff=radius != 0.0, spread=AT.leaf_spread(P.x, P.y, L))
         override_tuning(a, vf)
         t = vf.Tree(x, y, L, p_max=p)
         t.set_near_radius(radius)
@@ -603,12 +604,14 @@ def time_steps(torch, step, steps, tree=None, graph=True):
     return e0.elapsed_time(e1) / steps, wall, phases
 
 
-def selection_shape(n):
+def selection_shape(P):
     """The selection's trial trees take the process-wide launch shape: set the
-    tuning table's shape for about 64 particles per leaf with the cut-off, so
-    that every workload's candidates are timed the way their timed path runs."""
+    tuning table's shape for about 64 particles per leaf with the cut-off (and
+    the input's leaf-occupancy spread there), so that every workload's
+    candidates are timed the way their timed path runs."""
     from paper_0809_1810_amd import autotune as AT
-    AT.apply_for(n, max(2, int(round(math.log(max(n, 64) / 64.0, 4)))), cutoff=True)
+    L = max(2, int(round(math.log(max(P.n, 64) / 64.0, 4))))
+    AT.apply_for(P.n, L, cutoff=True, spread=AT.leaf_spread(P.x, P.y, L))
 
 
 def override_tuning(a, vf):
@@ -659,14 +662,14 @@ def bench_eval_points(a, torch, vf):
         p, L, prec, how = a.p, a.levels, vf.PRECISIONS[a.precision], "fixed"
         radius = fixed_radius(a, P.sigma, vf)
     else:
-        selection_shape(n)
+        selection_shape(P)
         r = S.select_and_audit(x, y, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]
         prec = vf.FP64 if r["precision"] == "fp64" else vf.PRECISIONS[a.precision]
         how = "learned" if not r["fallback"] else "fallback"
     log(f"[bench] evaluation points: {nt} on the root square, p={p} L={L} ({how}), "
         f"near radius {radius}")
-    AT.apply_for(n, L, cutoff=radius != 0.0)
+    AT.apply_for(n, L, cutoff=radius != 0.0, spread=AT.leaf_spread(P.x, P.y, L))
     override_tuning(a, vf)
     tree = vf.Tree(x, y, L, p_max=p)
     tree.set_near_radius(radius)
@@ -738,7 +741,7 @@ def bench_advect(a, torch, vf):
         p, L = a.p, a.levels
         radius = fixed_radius(a, P.sigma, vf)
     else:
-        selection_shape(n)
+        selection_shape(P)
         r = S.select_and_audit(x0, y0, g, P.sigma, 1e-6, weights=S.load_weights())
         p, L, radius = r["p"], r["levels"], r["radius"]
     Lp = largest_level(side, P.sigma, 8.0)
@@ -750,7 +753,7 @@ def bench_advect(a, torch, vf):
     ws = None
 
     def run(pp, LL, prec, rad, steps):
-        AT.apply_for(n, LL, cutoff=rad != 0.0)
+        AT.apply_for(n, LL, cutoff=rad != 0.0, spread=AT.leaf_spread(P.x, P.y, LL))
         override_tuning(a, vf)
         x = x0.clone(); y = y0.clone()
         tree = vf.Tree(x, y, LL, p_max=pp)

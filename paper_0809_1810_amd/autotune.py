@@ -5,8 +5,11 @@ target; T is also the source-chunk size of the far-pair test, so smaller tiles
 have tighter bounding boxes) and waves per workgroup (1, 2, 4, 8).  For each
 workload the tuner times the P2P phase of FP32 evaluations with HIP events
 (median of repeated calls) for every shape, keeps the fastest, and writes a
-table keyed by log2 of the mean particles per leaf.  ``apply_for(n, levels)``
-sets the library's tuning from the nearest table entry.  With the distance
+table keyed by log2 of the mean particles per leaf and by the occupancy
+spread (``leaf_spread``: log2 of the pair-weighted over the plain mean
+particles per leaf, 0 for even leaves; a clustered and an even input with the
+same mean take different shapes).  ``apply_for(n, levels, spread=...)`` sets
+the library's tuning from the nearest table entry.  With the distance
 cut-off only 64-target tiles (one lane per target) cull the ring sources
 lane-parallel, so the tuner also times the 64-target shapes with the cut-off
 at the radius where one pair's kernel difference is 1e-6 (``cutoff_ms``), and
@@ -107,7 +110,8 @@ def tune_workload(name, P, p, levels, log=print):
     cut = {w: time_p2p(x, y, g, P.sigma, p, levels, 64, w, radius=radius) for w in WAVES}
     cbest = min(cut, key=cut.get)
     entry = {"workload": name, "n": P.n, "levels": levels, "p": p,
-             "ppl_log2": math.log2(P.n) - 2 * levels, "tile": best[0], "waves": best[1],
+             "ppl_log2": math.log2(P.n) - 2 * levels,
+             "spread": round(leaf_spread(P.x, P.y, levels), 4), "tile": best[0], "waves": best[1],
              "p2p_ms": res[best], "default_ms": res[(64, 4)],
              "all_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in sorted(res.items())},
              "cutoff_radius_sigma": round(radius / P.sigma, 4),
@@ -186,16 +190,55 @@ def _parse(key):
     return int(tile), int(rest.rstrip("s")), int(rest.endswith("s"))
 
 
-def lookup_shape(n, levels, path=TABLE_PATH, cutoff=False):
-    """(tile, waves, sym) of the table entry nearest in log2 particles per leaf:
+def spread_from_counts(counts):
+    """Occupancy spread of a leaf population: log2(4^L sum n_b^2 / N^2), i.e.
+    the pair-weighted mean particles per leaf over the plain mean, in log2
+    units (0 when every leaf holds the same number; a clustered input's near
+    field has many more pairs than its mean occupancy suggests)."""
+    c = np.asarray(counts, dtype=np.float64)
+    n = c.sum()
+    if n <= 0:
+        return 0.0
+    return float(math.log2(c.size * float(np.dot(c, c)) / (n * n)))
+
+
+def leaf_spread(x, y, levels):
+    """``spread_from_counts`` of host positions at level ``levels``, with the
+    library's root square (the bounding square of side max extent (1 + 2^-20)
+    centred on the bounding box) and floor-and-clamp leaf rule."""
+    x = np.asarray(x, dtype=np.float64); y = np.asarray(y, dtype=np.float64)
+    if x.size == 0:
+        return 0.0
+    xl, xh, yl, yh = x.min(), x.max(), y.min(), y.max()
+    side = max(xh - xl, yh - yl) * (1.0 + 2.0 ** -20)
+    if side == 0.0:
+        side = 1.0
+    x0 = 0.5 * (xl + xh) - 0.5 * side
+    y0 = 0.5 * (yl + yh) - 0.5 * side
+    m = 1 << levels
+    ix = np.clip(np.floor((x - x0) / side * m), 0, m - 1).astype(np.int64)
+    iy = np.clip(np.floor((y - y0) / side * m), 0, m - 1).astype(np.int64)
+    return spread_from_counts(np.bincount(iy * m + ix, minlength=m * m))
+
+
+def _nearest(entries, n, levels, spread):
+    ppl = math.log2(max(n, 1)) - 2 * levels
+    if spread is None:
+        return min(entries, key=lambda e: abs(e["ppl_log2"] - ppl))
+    # both in log2 units; entries without a recorded spread count as even
+    return min(entries, key=lambda e: abs(e["ppl_log2"] - ppl) + abs(e.get("spread", 0.0) - spread))
+
+
+def lookup_shape(n, levels, path=TABLE_PATH, cutoff=False, spread=None):
+    """(tile, waves, sym) of the table entry nearest in log2 particles per leaf
+    (and, given ``spread``, in occupancy spread: the sum of the two distances):
     its fastest timed shape; with ``cutoff`` its fastest 64-target shape (timed
     with the cut-off if it has such timings)."""
     try:
         table = json.load(open(path))
     except (OSError, ValueError):
         return 64, 4, 0
-    ppl = math.log2(max(n, 1)) - 2 * levels
-    e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
+    e = _nearest(table["entries"], n, levels, spread)
     if cutoff:
         t64 = e.get("cutoff_ms") or {k: v for k, v in e.get("all_ms", {}).items()
                                      if k.startswith("64x")}
@@ -207,25 +250,26 @@ def lookup_shape(n, levels, path=TABLE_PATH, cutoff=False):
     return int(e["tile"]), int(e["waves"]), 0
 
 
-def lookup(n, levels, path=TABLE_PATH, cutoff=False):
+def lookup(n, levels, path=TABLE_PATH, cutoff=False, spread=None):
     """(tile, waves) of ``lookup_shape``."""
-    return lookup_shape(n, levels, path, cutoff)[:2]
+    return lookup_shape(n, levels, path, cutoff, spread)[:2]
 
 
-def lookup_m2l(n, levels, path=TABLE_PATH):
-    """M2L tile of the table entry nearest in log2 particles per leaf (0 without)."""
+def lookup_m2l(n, levels, path=TABLE_PATH, spread=None):
+    """M2L tile of the nearest table entry (as ``lookup_shape``; 0 without)."""
     try:
         table = json.load(open(path))
     except (OSError, ValueError):
         return 0
-    ppl = math.log2(max(n, 1)) - 2 * levels
-    e = min(table["entries"], key=lambda e: abs(e["ppl_log2"] - ppl))
-    return int(e.get("m2l_tile", 0))
+    return int(_nearest(table["entries"], n, levels, spread).get("m2l_tile", 0))
 
 
-def apply_for(n, levels, path=TABLE_PATH, cutoff=False):
-    tile, waves, sym = lookup_shape(n, levels, path, cutoff)
-    V.set_tuning(tile=tile, waves=waves, m2l=lookup_m2l(n, levels, path), sym=sym)
+def apply_for(n, levels, path=TABLE_PATH, cutoff=False, spread=None):
+    """Sets the process-wide tuning from the nearest table entry (``spread``:
+    the input's ``leaf_spread`` at ``levels``, None to match on particles per
+    leaf alone)."""
+    tile, waves, sym = lookup_shape(n, levels, path, cutoff, spread)
+    V.set_tuning(tile=tile, waves=waves, m2l=lookup_m2l(n, levels, path, spread), sym=sym)
     return tile, waves
 
 

@@ -72,3 +72,49 @@ def test_symmetric_shapes(tmp_path):
     assert AT.lookup(1 << 20, 7, path, cutoff=True) == (64, 2)
     assert AT.lookup_shape(1 << 20, 9, path) == (32, 2, 0)
     assert AT.lookup_shape(1000, 3, str(tmp_path / "absent.json")) == (64, 4, 0)
+
+
+def test_leaf_spread():
+    """The occupancy spread: 0 for even leaves, log2(1 + 1/m) in expectation
+    for a Poisson population of mean m, and log2 of the pair-weighted over the
+    plain mean for uneven counts."""
+    import numpy as np
+    assert AT.spread_from_counts([4, 4, 4, 4]) == 0.0
+    assert abs(AT.spread_from_counts([8, 0, 0, 0]) - 2.0) < 1e-12   # 4 * 64 / 64 = 4
+    assert abs(AT.spread_from_counts([3, 1]) - np.log2(2 * 10 / 16)) < 1e-12
+    assert AT.spread_from_counts([0, 0]) == 0.0
+    # a cell-centred 64 x 64 lattice has 4 points in each of the 16 x 16 leaves at L = 4
+    g = (np.arange(64) + 0.5) / 64
+    x, y = np.meshgrid(g, g)
+    assert abs(AT.leaf_spread(x.ravel(), y.ravel(), 4)) < 1e-12
+    rng = np.random.default_rng(1)
+    s = AT.leaf_spread(rng.random(1 << 18), rng.random(1 << 18), 6)   # mean 64 per leaf
+    assert abs(s - np.log2(1 + 1 / 64)) < 0.01
+
+
+def test_lookup_with_spread(tmp_path):
+    """Two entries with the same mean occupancy: without a spread the first is
+    taken, with one the entry nearest in (mean, spread)."""
+    entries = [
+        {"ppl_log2": 6.0, "spread": 3.2, "tile": 64, "waves": 1,
+         "cutoff_ms": {"64x1s": 1.7, "64x2s": 1.8}},
+        {"ppl_log2": 6.0, "spread": 0.0, "tile": 64, "waves": 2,
+         "cutoff_ms": {"64x1s": 0.25, "64x2s": 0.23}, "m2l_tile": 2},
+    ]
+    p = tmp_path / "tuning.json"
+    p.write_text(json.dumps({"entries": entries}))
+    path = str(p)
+    assert AT.lookup_shape(1 << 20, 7, path, cutoff=True) == (64, 1, 1)
+    assert AT.lookup_shape(1 << 20, 7, path, cutoff=True, spread=3.0) == (64, 1, 1)
+    assert AT.lookup_shape(1 << 20, 7, path, cutoff=True, spread=0.02) == (64, 2, 1)
+    assert AT.lookup_m2l(1 << 20, 7, path, spread=0.02) == 2
+    assert AT.lookup_m2l(1 << 20, 7, path) == 0
+
+
+def test_table_spreads():
+    """Every entry of the shipped table records its workload's spread, and the
+    two N = 2^20 inputs at 64 particles per leaf map to their own entries."""
+    table = json.load(open(AT.TABLE_PATH))
+    assert all("spread" in e for e in table["entries"])
+    by = {(e["workload"], e["levels"]): e for e in table["entries"]}
+    assert by[("clusters_1m", 7)]["spread"] > 2.0 and by[("lattice_1024", 7)]["spread"] == 0.0
