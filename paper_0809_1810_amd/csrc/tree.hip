@@ -337,11 +337,13 @@ hipError_t scan_exclusive2(uint32_t* a, uint32_t* b, int64_t n, uint32_t* tmp, h
 // Stable LSD counting sort on `bits` (<= 8) key bits per pass.  counts is
 // digit-major: counts[d * nblk + b].
 
+constexpr int kSortWaves = kSortBlock / 64;
+
 __global__ void __launch_bounds__(kSortBlock) k_radix_count(const uint32_t* __restrict__ keys,
                                                             int64_t n, int shift, uint32_t mask,
                                                             uint32_t* __restrict__ counts, int nblk) {
   __shared__ uint32_t hist[256];
-  hist[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < 256; d += kSortBlock) hist[d] = 0;
   __syncthreads();
   const int64_t base = blockIdx.x * int64_t(kSortPerBlock);
 #pragma unroll
@@ -350,19 +352,22 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_count(const uint32_t* __re
     if (i < n) atomicAdd(&hist[(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  counts[int64_t(threadIdx.x) * nblk + blockIdx.x] = hist[threadIdx.x];
+  for (int d = threadIdx.x; d < 256; d += kSortBlock)
+    counts[int64_t(d) * nblk + blockIdx.x] = hist[d];
 }
 
+// Each round ranks kSortBlock consecutive keys (one per thread): within a
+// wave by ballots over the digit's bits, across the waves of the block by the
+// per-wave digit counts in wc; run holds each digit's next output position.
 __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
     const uint32_t* __restrict__ kin, const int32_t* __restrict__ iin, int64_t n, int shift,
     uint32_t mask, int bits, const uint32_t* __restrict__ offs, int nblk,
     uint32_t* __restrict__ kout, int32_t* __restrict__ iout) {
   __shared__ uint32_t run[256];
-  __shared__ uint32_t wc[4][256];
+  __shared__ uint32_t wc[kSortWaves][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  run[tid] = offs[int64_t(tid) * nblk + blockIdx.x];
-#pragma unroll
-  for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+  for (int d = tid; d < 256; d += kSortBlock) run[d] = offs[int64_t(d) * nblk + blockIdx.x];
+  for (int k = tid; k < kSortWaves * 256; k += kSortBlock) wc[k >> 8][k & 255] = 0;
   __syncthreads();
   const int64_t base = blockIdx.x * int64_t(kSortPerBlock);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -370,6 +375,7 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
     const int64_t i = base + r * kSortBlock + tid;
     const bool valid = i < n;
     const uint32_t k = valid ? kin[i] : 0u;
+    const int32_t ix = valid ? iin[i] : 0;
     const uint32_t d = (k >> shift) & mask;
     uint64_t m = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -385,12 +391,18 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
       uint32_t pos = run[d] + rank_w;
       for (int w = 0; w < wave; ++w) pos += wc[w][d];
       kout[pos] = k;
-      iout[pos] = iin[i];
+      iout[pos] = ix;
     }
     __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+    for (int dd = tid; dd < 256; dd += kSortBlock) {
+      uint32_t s = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+      for (int w = 0; w < kSortWaves; ++w) {
+        s += wc[w][dd];
+        wc[w][dd] = 0;
+      }
+      run[dd] += s;
+    }
     __syncthreads();
   }
 }

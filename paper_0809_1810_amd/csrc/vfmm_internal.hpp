@@ -39,8 +39,8 @@ constexpr int kMaxLevels = 12;
 constexpr int kTile = 64;            // P2P targets per wave tile (default; the batched path)
 constexpr int kTileMin = 16;         // smallest tunable tile (4 lanes per target)
 constexpr int kSubLevels = 4;        // within a leaf, particles are ordered by their cell at level L + 4
-constexpr int kSortItems = 8;        // radix-sort elements per thread
-constexpr int kSortBlock = 256;      // radix-sort threads per block
+constexpr int kSortItems = 2;        // radix-sort elements per thread
+constexpr int kSortBlock = 1024;     // radix-sort threads per block (16 waves)
 constexpr int kSortPerBlock = kSortItems * kSortBlock;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = 256;
