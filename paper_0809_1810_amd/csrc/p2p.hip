@@ -696,8 +696,9 @@ hipError_t build_schedule(const TreeDev& t, const TargetsDev& tg, int levels, do
                           hipStream_t st) {
   const P2PSched& s = tg.sched;
   const int64_t mt = tg.max_tiles;
-  hipLaunchKernelGGL(k_sched_count, dim3(nblk(mt * kSchedLanes, 256)), dim3(256), 0, st, tg.tiles,
-                     tg.ntiles, t.tile_off, t.root, levels, cut2, tg.leaf_shift, s.cnt);
+  const unsigned cb = nblk(mt * kSchedLanes, 256) > 0 ? nblk(mt * kSchedLanes, 256) : 1u;
+  hipLaunchKernelGGL(k_sched_count, dim3(cb), dim3(256), 0, st, tg.tiles, tg.ntiles, t.tile_off,
+                     t.root, levels, cut2, tg.leaf_shift, s.cnt);
   hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kScanOneBlock), 0, st, tg.ntiles, mt, s.cnt,
                      s.p_off, s.s_off);
   const int64_t nreact = tg.react ? t.n : 0;
