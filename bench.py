@@ -676,20 +676,15 @@ def bench_eval_points(a, torch, vf):
     ws = torch.empty(vf.targets_workspace_bytes(nt, L), dtype=torch.uint8, device="cuda")
     u = torch.empty(nt, dtype=torch.float64, device="cuda")
     v = torch.empty(nt, dtype=torch.float64, device="cuda")
+    def step():
+        tree.rebuild(x, y)
+        tree.velocity_at(g, P.sigma, p, xe, ye, prec, out=(u, v), workspace=ws)
     for _ in range(a.warmup):
-        tree.rebuild(x, y)
-        tree.velocity_at(g, P.sigma, p, xe, ye, prec, out=(u, v), workspace=ws)
+        step()
     torch.cuda.synchronize()
-    tree.enable_timing(a.steps)
-    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(a.steps):
-        tree.rebuild(x, y)
-        tree.velocity_at(g, P.sigma, p, xe, ye, prec, out=(u, v), workspace=ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
-    phases = tree.read_timing()
+    # eager steps with the phase events, then the same steps replayed from a graph
+    eager_ms, _, phases = time_steps(torch, step, a.steps, tree, False)
+    ms = eager_ms if a.eager else time_steps(torch, step, a.steps, None, True)[0]
     us, vs = u[sel].contiguous(), v[sel].contiguous()
     emax, erms, _ = vf.error_metrics(us, vs, ud, vd)
     field = vf.error_field(us, vs, ud, vd).cpu().numpy()
@@ -700,6 +695,8 @@ def bench_eval_points(a, torch, vf):
     out = {"metric": "evaluation points/s, FMM of N=2^20 particles at an M x M lattice of points",
            "value": round(nt / (ms * 1e-3), 1), "unit": "points/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
+           "eager_ms_per_step": round(eager_ms, 4),
+           "timed_as": "eager calls" if a.eager else "one hipGraph replay of the K captured steps",
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec != vf.FP64 else "f64", "data": "synthetic",
            "config": {"workload": f"{P.name}: N={n}, sigma={P.sigma}; {a.eval_lattice}^2 "
