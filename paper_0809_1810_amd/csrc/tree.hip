@@ -519,11 +519,12 @@ __global__ void __launch_bounds__(256) k_gather_gamma(const double* __restrict__
                                                       const int32_t* __restrict__ perm, int64_t n,
                                                       Part64* __restrict__ p64,
                                                       Part32* __restrict__ p32,
-                                                      Part32* __restrict__ p32s, double scale) {
+                                                      Part32* __restrict__ p32s, double scale,
+                                                      bool with64) {
   int64_t i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
   const double g = gamma[perm[i]];
-  p64[i].g = g;
+  if (with64) p64[i].g = g;
   p32[i].g = float(g);
   if (scale > 0.0) {
     const Part64 q = p64[i];
@@ -791,10 +792,10 @@ hipError_t launch_tile_box(const Tile* tiles, const int32_t* ntiles, int64_t max
 }
 
 hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,
-                               hipStream_t st) {
+                               bool with64, hipStream_t st) {
   const double scale = sigma > 0.0 ? near_scale(sigma) : 0.0;
   hipLaunchKernelGGL(k_gather_gamma, dim3(nblocks(n, 256)), dim3(256), 0, st, gamma, t.perm, n,
-                     t.part64, t.part32, t.part32s, scale);
+                     t.part64, t.part32, t.part32s, scale, with64);
   return hipGetLastError();
 }
 

@@ -355,7 +355,8 @@ vfmm_status_t evaluate(vfmm_tree_t t, const TargetsDev& tg, const double* gamma,
   // sorted particles, on st before the fork: the near field then depends on
   // nothing on the side stream (in a replayed graph, a node whose inputs come
   // from another branch was measured to start tens of microseconds after them)
-  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0, st);
+  hipError_t e = launch_gather_gamma(t->dev, gamma, t->n, prec == kFP32 && near ? sigma : 0.0,
+                                     prec == kFP64 || shift64, st);
   if (e != hipSuccess) return hip_fail(e, "gather");
   mark.end(kPhGather, st);
   if (sw != st) {

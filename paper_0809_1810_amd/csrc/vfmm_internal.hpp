@@ -225,10 +225,11 @@ int tuning_tile();
 int tuning_waves();
 int tuning_m2l_tile();
 int tuning_sym();
-// Circulations into the sorted particle records; with sigma > 0 also the
-// FP32 near-field sources scaled by sqrt(log2(e) / (2 sigma^2)) (part32s).
+// Circulations into the sorted particle records (part32, and part64 when
+// with64: float64 near field or expansions); with sigma > 0 also the FP32
+// near-field sources scaled by sqrt(log2(e) / (2 sigma^2)) (part32s).
 hipError_t launch_gather_gamma(const TreeDev& t, const double* gamma, int64_t n, double sigma,
-                               hipStream_t stream);
+                               bool with64, hipStream_t stream);
 hipError_t launch_build_ops(const TreeDev& t, int p, int prec, hipStream_t stream);
 hipError_t launch_p2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
 hipError_t launch_m2m(const TreeDev& t, int levels, int p, int prec, hipStream_t stream);
