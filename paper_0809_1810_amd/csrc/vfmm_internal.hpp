@@ -336,19 +336,32 @@ __device__ inline void scan_store4(uint32_t* a, int64_t i, int64_t n, uint4 q, u
   if (i + 1 < n) a[i + 1] = o.y;
   if (i + 2 < n) a[i + 2] = o.z;
 }
+// x plus the DPP-moved x (0 where the move has no source or the row is
+// masked), in unsigned (modulo 2^32) arithmetic.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t x) {
+  return x + uint32_t(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROW_MASK, 0xf, BOUND));
+}
 // Inclusive scan over a wave by DPP: Hillis-Steele within each row of 16
 // lanes (row_shr 1, 2, 4, 8, zeros shifted in), then the last lane of row 0
 // added to row 1 and of row 2 to row 3 (row_bcast:15), then that of row 1 to
 // rows 2 and 3 (row_bcast:31).
-__device__ inline uint32_t wave_scan_incl_u32(uint32_t v) {
-  int x = int(v);
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
-  return uint32_t(x);
+__device__ inline uint32_t wave_scan_incl_u32(uint32_t x) {
+  x = dpp_add<0x111, 0xf, true>(x);    // row_shr:1
+  x = dpp_add<0x112, 0xf, true>(x);    // row_shr:2
+  x = dpp_add<0x114, 0xf, true>(x);    // row_shr:4
+  x = dpp_add<0x118, 0xf, true>(x);    // row_shr:8
+  x = dpp_add<0x142, 0xa, false>(x);   // row_bcast:15, rows 1 and 3
+  x = dpp_add<0x143, 0xc, false>(x);   // row_bcast:31, rows 2 and 3
+  return x;
+}
+// Inclusive scan within each row of 16 lanes (row_shr 1, 2, 4, 8).
+__device__ inline uint32_t row_scan_incl_u32(uint32_t x) {
+  x = dpp_add<0x111, 0xf, true>(x);
+  x = dpp_add<0x112, 0xf, true>(x);
+  x = dpp_add<0x114, 0xf, true>(x);
+  x = dpp_add<0x118, 0xf, true>(x);
+  return x;
 }
 // Exclusive prefix of one value per thread over the workgroup, and the
 // workgroup total; ws: 16 entries of LDS.  Every thread must call it.  The
@@ -360,14 +373,10 @@ __device__ inline uint32_t block1k_scan_excl(uint32_t v, uint32_t* total, uint32
   const uint32_t incl = wave_scan_incl_u32(v);
   if (lane == 63) ws[wave] = incl;
   __syncthreads();
-  int a = lane < 16 ? int(ws[lane]) : 0;
+  const uint32_t a = row_scan_incl_u32(lane < 16 ? ws[lane] : 0u);
   __syncthreads();
-  a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xf, 0xf, true);
-  const uint32_t pre = wave ? uint32_t(__builtin_amdgcn_readlane(a, wave - 1)) : 0u;
-  *total = uint32_t(__builtin_amdgcn_readlane(a, 15));
+  const uint32_t pre = wave ? uint32_t(__builtin_amdgcn_readlane(int(a), wave - 1)) : 0u;
+  *total = uint32_t(__builtin_amdgcn_readlane(int(a), 15));
   return pre + incl - v;
 }
 
@@ -386,28 +395,17 @@ __device__ inline uint3 block1k_scan3_excl(uint3 v, uint3* total, uint32_t* ws) 
     ws[32 + wave] = iz;
   }
   __syncthreads();
-  int a = lane < 16 ? int(ws[lane]) : 0, b = lane < 16 ? int(ws[16 + lane]) : 0,
-      c = lane < 16 ? int(ws[32 + lane]) : 0;
+  const uint32_t a = row_scan_incl_u32(lane < 16 ? ws[lane] : 0u);
+  const uint32_t b = row_scan_incl_u32(lane < 16 ? ws[16 + lane] : 0u);
+  const uint32_t c = row_scan_incl_u32(lane < 16 ? ws[32 + lane] : 0u);
   __syncthreads();
-  a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xf, 0xf, true);
-  b += __builtin_amdgcn_update_dpp(0, b, 0x111, 0xf, 0xf, true);
-  c += __builtin_amdgcn_update_dpp(0, c, 0x111, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xf, 0xf, true);
-  b += __builtin_amdgcn_update_dpp(0, b, 0x112, 0xf, 0xf, true);
-  c += __builtin_amdgcn_update_dpp(0, c, 0x112, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xf, 0xf, true);
-  b += __builtin_amdgcn_update_dpp(0, b, 0x114, 0xf, 0xf, true);
-  c += __builtin_amdgcn_update_dpp(0, c, 0x114, 0xf, 0xf, true);
-  a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xf, 0xf, true);
-  b += __builtin_amdgcn_update_dpp(0, b, 0x118, 0xf, 0xf, true);
-  c += __builtin_amdgcn_update_dpp(0, c, 0x118, 0xf, 0xf, true);
   // lane w of row 0 holds the inclusive sums of the totals of waves 0 .. w
-  const uint32_t px = wave ? uint32_t(__builtin_amdgcn_readlane(a, wave - 1)) : 0u;
-  const uint32_t py = wave ? uint32_t(__builtin_amdgcn_readlane(b, wave - 1)) : 0u;
-  const uint32_t pz = wave ? uint32_t(__builtin_amdgcn_readlane(c, wave - 1)) : 0u;
-  *total = make_uint3(uint32_t(__builtin_amdgcn_readlane(a, 15)),
-                      uint32_t(__builtin_amdgcn_readlane(b, 15)),
-                      uint32_t(__builtin_amdgcn_readlane(c, 15)));
+  const uint32_t px = wave ? uint32_t(__builtin_amdgcn_readlane(int(a), wave - 1)) : 0u;
+  const uint32_t py = wave ? uint32_t(__builtin_amdgcn_readlane(int(b), wave - 1)) : 0u;
+  const uint32_t pz = wave ? uint32_t(__builtin_amdgcn_readlane(int(c), wave - 1)) : 0u;
+  *total = make_uint3(uint32_t(__builtin_amdgcn_readlane(int(a), 15)),
+                      uint32_t(__builtin_amdgcn_readlane(int(b), 15)),
+                      uint32_t(__builtin_amdgcn_readlane(int(c), 15)));
   return make_uint3(px + ix - v.x, py + iy - v.y, pz + iz - v.z);
 }
 
