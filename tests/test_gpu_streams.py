@@ -9,6 +9,8 @@ C ABI.
 * Phase timing records 8 phases; a far-only evaluation skips the near-field
   phases.
 * The far part alone of a tree without far field (L < 2) is zeros.
+* Rebuild + evaluation captured into a graph replay like eager calls, also
+  with the symmetric near field (its float64 sums cleared inside each replay).
 """
 import numpy as np
 import pytest
@@ -118,3 +120,59 @@ def test_graph_capture_of_rebuild_and_velocity(vf):
     step()
     assert np.array_equal(got[0], host(u)) and np.array_equal(got[1], host(v))
     t.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_capture_with_symmetric_near_field(vf, prec):
+    """The symmetric near field inside a captured rebuild + evaluation: its
+    float64 sums are cleared by a kernel of the schedule in every replay, so
+    replays (with eager work and synchronisation between them, and after the
+    circulations change in place) equal an eager evaluation to the rounding of
+    those atomic sums (1e-13 of the maximum velocity in FP64, 1e-6 in FP32),
+    and the FP64 result matches the oracle FMM on sampled targets to 1e-12."""
+    P = W.clusters(60000, seed=16, sigma=0.005)
+    L, p = 5, 12
+    pr = vf.FP64 if prec == "fp64" else vf.FP32
+    print_case("streams_graph_sym", n=P.n, levels=L, p=p, prec=prec)
+    saved = vf.get_tuning()
+    try:
+        vf.set_tuning(tile=64, waves=1, sym=1)
+        x, y, g = dev(P.x), dev(P.y), dev(P.gamma)
+        t = vf.Tree(x, y, L, p_max=p)
+        assert t.tuning()["sym"] == 1
+        u = torch.empty(P.n, dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+
+        def step():
+            t.rebuild(x, y)
+            t.velocity(g, P.sigma, p, pr, out=(u, v))
+
+        step()
+        torch.cuda.synchronize()
+        eager = (host(u).copy(), host(v).copy())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        den = np.max(np.hypot(*eager))
+        tol = 1e-13 if prec == "fp64" else 1e-6
+        for rep in range(3):
+            u.fill_(float("nan"))
+            graph.replay()
+            torch.cuda.synchronize()
+            d = np.max(np.hypot(host(u) - eager[0], host(v) - eager[1])) / den
+            assert d < tol, (rep, d)
+        g.mul_(-0.5)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (host(u).copy(), host(v).copy())
+        step()
+        torch.cuda.synchronize()
+        d = np.max(np.hypot(got[0] - host(u), got[1] - host(v))) / np.max(np.hypot(host(u), host(v)))
+        assert d < tol, d
+        if prec == "fp64":
+            tg = W.sample_targets(P.n, 64, seed=3)
+            r = F.fmm_velocity(P.x, P.y, -0.5 * P.gamma, P.sigma, p, L, targets=tg)
+            assert rel_err(got[0][tg], got[1][tg], r.u, r.v)[0] < 1e-12
+        t.close()
+    finally:
+        vf.set_tuning(**saved)
