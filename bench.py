@@ -478,7 +478,8 @@ def main():
                         for k in tuned["phases"][0]}
     if prec_t != vf.FP64 and L_t >= 2:
         # M2L on the matrix cores: 8 p^2 FLOP per (box, interaction box) pair,
-        # over the M2L + L2L phase (the L2L adds are a few us of it); sweep
+        # over the M2L + L2L phase (the L2L, two short launches at L = 7, is
+        # part of it); sweep
         # phases from the far-only evaluations (in a full evaluation they share
         # the GPU with the near field)
         ph = {k: round(float(np.mean([f[k] for f in tuned["far_phases"]])), 4)
@@ -488,7 +489,7 @@ def main():
         ach = m2l_flop / (ph["m2l_l2l"] * 1e-3) / 1e12
         out["m2l_roofline"] = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
-                               "kernel": "k_m2l_mfma_f32 (+ k_l2l_add)", "ms": ph["m2l_l2l"],
+                               "kernel": "k_m2l_mfma_f32 (+ k_l2l_span)", "ms": ph["m2l_l2l"],
                                "pairs": m2l_pairs(L_t), "flops_per_pair": 8 * p_t * p_t}
         # expansion sweeps: P2M reads the sorted particles (16 B) and writes the
         # leaf MEs; M2M reads 4 children and writes one parent per level (8 B / coefficient)

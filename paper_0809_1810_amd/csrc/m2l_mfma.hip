@@ -272,24 +272,75 @@ __global__ void __launch_bounds__(256) k_m2l_mfma16(const float2* __restrict__ m
     }
 }
 
-// le[l] += L2L(le[l-1]) for one level (the M2L part is already in le[l]).
-__global__ void __launch_bounds__(256) k_l2l_add(const float2* __restrict__ le_par,
-                                                 float2* __restrict__ le, int lev, int p,
-                                                 const float2* __restrict__ B) {
-  const int64_t t = blockIdx.x * 256LL + threadIdx.x;
-  const int64_t nb = int64_t(1) << (2 * lev);
-  if (t >= nb * p) return;
-  const int64_t box = t / p;
-  const int n = int(t % p);
-  const int m = 1 << lev;
-  const int bx = int(box & (m - 1)), by = int(box >> lev);
-  const int64_t pb = int64_t(by >> 1) * (m >> 1) + (bx >> 1);
-  const int c = ((by & 1) << 1) | (bx & 1);
-  const float2* lp = le_par + pb * p;
-  const float2* b = B + (c * p + n) * p;
-  float2 acc = le[box * p + n];
-  for (int k = n; k < p; ++k) cfma(acc, b[k], lp[k]);
-  le[box * p + n] = acc;
+// le[l] += L2L(le[l-1]) for the levels a .. c (c - a < kL2LSpan; the M2L part
+// is already in le[l]), in one launch: one workgroup per level-a box takes
+// its parent's local expansion (final before the launch), completes its own
+// box, then its 4 children, then their 16 children, each level kept in LDS
+// for the next.  Every box of levels a .. c belongs to exactly one workgroup,
+// which reads its M2L part and writes its final expansion.  The four shift
+// operators (4 p^2 coefficients) are staged in LDS and each thread loads the
+// M2L parts of all its outputs first, so that the levels wait on no global
+// loads.
+constexpr int kL2LSpan = 3;
+constexpr int kL2LPer = ((1 << (2 * (kL2LSpan - 1))) * kMaxP + 255) / 256;  // outputs per thread
+size_t l2l_span_lds(int p) { return size_t(4 * p * p + 2 * (1 << (2 * (kL2LSpan - 2))) * p) * sizeof(float2); }
+
+__global__ void __launch_bounds__(256) k_l2l_span(float2* __restrict__ le, int a, int c, int p,
+                                                  const float2* __restrict__ B) {
+  extern __shared__ float2 l2l_sh[];
+  float2* Bs = l2l_sh;  // B[(cls p + n) p + k]
+  float2* lv[2] = {Bs + 4 * p * p, Bs + 4 * p * p + (1 << (2 * (kL2LSpan - 2))) * p};
+  const int ma = 1 << a;
+  const int ax = int(blockIdx.x) & (ma - 1), ay = int(blockIdx.x) >> a;
+  // the box (level a + d) and coefficient of this thread's output o
+  auto where = [&](int d, int o, int& j, int& n, int64_t& g) {
+    j = o / p;
+    n = o - j * p;
+    const int jx = j & ((1 << d) - 1), jy = j >> d;
+    g = level_offset(a + d) * p + ((int64_t((ay << d) + jy) << (a + d)) + (ax << d) + jx) * p + n;
+  };
+  float2 m2l[kL2LSpan][kL2LPer];
+#pragma unroll
+  for (int d = 0; d < kL2LSpan; ++d)
+#pragma unroll
+    for (int r = 0; r < kL2LPer; ++r) {
+      const int o = int(threadIdx.x) + r * 256;
+      if (a + d <= c && o < (p << (2 * d))) {
+        int j, n;
+        int64_t g;
+        where(d, o, j, n, g);
+        m2l[d][r] = le[g];
+      }
+    }
+  for (int i = threadIdx.x; i < 4 * p * p; i += 256) Bs[i] = B[i];
+  const float2* lp = le + level_offset(a - 1) * p + (int64_t(ay >> 1) * (ma >> 1) + (ax >> 1)) * p;
+  for (int k = threadIdx.x; k < p; k += 256) lv[0][k] = lp[k];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < kL2LSpan; ++d) {
+    if (a + d > c) break;  // uniform
+    const float2* prev = lv[d & 1];
+    float2* cur = lv[(d + 1) & 1];
+    const int w = 1 << d;
+#pragma unroll
+    for (int r = 0; r < kL2LPer; ++r) {
+      const int o = int(threadIdx.x) + r * 256;
+      if (o >= (p << (2 * d))) break;
+      int j, n;
+      int64_t g;
+      where(d, o, j, n, g);
+      const int jx = j & (w - 1), jy = j >> d;
+      const int cls = (((ay << d) + jy) & 1) << 1 | (((ax << d) + jx) & 1);
+      // parent: the subtree's box of the previous level (for d = 0, the one entry)
+      const float2* pe = prev + (d == 0 ? 0 : ((jy >> 1) * (w >> 1) + (jx >> 1)) * p);
+      const float2* b = Bs + (cls * p + n) * p;
+      float2 acc = m2l[d][r];
+      for (int k = n; k < p; ++k) cfma(acc, b[k], pe[k]);
+      le[g] = acc;
+      if (a + d < c) cur[o] = acc;
+    }
+    __syncthreads();
+  }
 }
 
 template <int MODE>
@@ -378,11 +429,16 @@ hipError_t launch_downward_mfma(const TreeDev& t, int levels, int p, int prec, h
   if (!with_l2l) return hipGetLastError();
   const float2* B = reinterpret_cast<const float2*>(ops + ol.l2l32);
   float2* le = static_cast<float2*>(t.le);
-  for (int l = 3; l <= levels; ++l) {
-    const int64_t work = (int64_t(1) << (2 * l)) * p;
-    hipLaunchKernelGGL(k_l2l_add, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st,
-                       le + level_offset(l - 1) * p, le + level_offset(l) * p, l, p, B);
+  // spans of kL2LSpan levels from the deepest up, e.g. 3 .. 4 and 5 .. 7 at L = 7
+  int spans[kMaxLevels][2], ns = 0;
+  for (int c = levels; c >= 3; c -= kL2LSpan) {
+    spans[ns][0] = c - kL2LSpan + 1 < 3 ? 3 : c - kL2LSpan + 1;
+    spans[ns][1] = c;
+    ++ns;
   }
+  for (int s = ns - 1; s >= 0; --s)
+    hipLaunchKernelGGL(k_l2l_span, dim3(1u << (2 * spans[s][0])), dim3(256), l2l_span_lds(p), st,
+                       le, spans[s][0], spans[s][1], p, B);
   return hipGetLastError();
 }
 
