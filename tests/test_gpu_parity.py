@@ -169,6 +169,37 @@ def test_fmm_fp32_vs_fp64(vf):
         assert emax < 1e-6 and erms < 2e-7
 
 
+
+@pytest.mark.parametrize("levels", [3, 4, 6, 8, 9])
+def test_fp32_local_expansions_every_level(vf, levels):
+    """FP32 local expansions (M2L on the matrix cores, then the L2L in spans of
+    up to three levels per launch: 3 | 3-4 | 4-6 + 3 | 6-8 + 3-5 | 7-9 + 4-6 +
+    3) on every level: against the oracle's (Section 3.3) at L <= 4 and against
+    the FP64 path's (pinned to the oracle elsewhere) deeper, and the velocities
+    against the FP64 path's."""
+    P = W.uniform(3000, seed=11)
+    p = 12
+    print_case("fp32_le_levels", n=P.n, levels=levels, p=p)
+    t = vf.Tree(dev(P.x), dev(P.y), levels, p_max=p)
+    g = dev(P.gamma)
+    u64, v64 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP64))
+    le64 = {lev: host(t.expansions(1, lev, p)) for lev in range(2, levels + 1)}
+    u32, v32 = (host(a) for a in t.velocity(g, P.sigma, p, vf.FP32))
+    assert rel_err(u32, v32, u64, v64)[0] < 1e-6
+    r = F.fmm_velocity(P.x, P.y, P.gamma, P.sigma, p, levels, keep_expansions=True) if levels <= 4 else None
+    for lev in range(2, levels + 1):
+        le = host(t.expansions(1, lev, p))
+        ref = le64[lev]
+        if r is not None:
+            w = qt.box_side(r.tree.root, lev)
+            m = 1 << lev
+            ref = np.zeros_like(le)
+            for box, b in r.le[lev].items():
+                ref[box[1] * m + box[0]] = oracle_le_scaled(b, w)
+        scale = np.max(np.abs(ref))
+        assert scale > 0
+        assert np.max(np.abs(le - ref)) <= 2e-6 * scale, lev
+
 def test_degenerate_inputs(vf):
     # one particle; all particles coincident; two particles
     for x, y, g in (([0.3], [0.2], [1.0]), ([0.5] * 70, [0.5] * 70, list(np.linspace(-1, 1, 70))),
