@@ -409,12 +409,11 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
 
 namespace {
 
-__global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__ keys, int64_t n,
-                                                    int64_t nleaves, int32_t* __restrict__ start) {
-  int64_t k = blockIdx.x * 256LL + threadIdx.x;
-  if (k > nleaves) return;
+// Start of leaf k in the sorted keys: the first position whose leaf is >= k.
+__device__ __forceinline__ void leaf_start_of(const uint32_t* __restrict__ keys, int64_t n,
+                                              int64_t k, int32_t* __restrict__ start) {
   const uint64_t kk = uint64_t(k) << (2 * kSubLevels);
-  int64_t lo = 0, hi = n;  // first position whose leaf is >= k
+  int64_t lo = 0, hi = n;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
     if (uint64_t(keys[mid]) < kk) lo = mid + 1; else hi = mid;
@@ -422,15 +421,22 @@ __global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__
   start[k] = int32_t(lo);
 }
 
-__global__ void __launch_bounds__(256) k_local_coords(const double2* __restrict__ xy,
-                                                      const uint32_t* __restrict__ keys,
-                                                      const int32_t* __restrict__ perm, int64_t n,
-                                                      const double* __restrict__ root, int levels,
-                                                      Part64* __restrict__ p64,
-                                                      Part32* __restrict__ p32) {
+__global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int64_t nleaves, int32_t* __restrict__ start) {
+  int64_t k = blockIdx.x * 256LL + threadIdx.x;
+  if (k > nleaves) return;
+  leaf_start_of(keys, n, k, start);
+}
+
+// Sorted particle i: its position (through the permutation) relative to its
+// leaf's centre, in float64 and float32.
+__device__ __forceinline__ void local_coords_of(const double2* __restrict__ xy,
+                                                const uint32_t* __restrict__ keys,
+                                                const int32_t* __restrict__ perm, int64_t i,
+                                                const double* __restrict__ root, int levels,
+                                                Part64* __restrict__ p64,
+                                                Part32* __restrict__ p32) {
 #pragma clang fp contract(off)
-  int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n) return;
   const uint32_t leaf = keys[i] >> (2 * kSubLevels);
   const int ix = int(leaf & ((1u << levels) - 1u)), iy = int(leaf >> levels);
   const double w = root[3];
@@ -440,6 +446,27 @@ __global__ void __launch_bounds__(256) k_local_coords(const double2* __restrict_
   const double lx = q.x - cx, ly = q.y - cy;
   p64[i] = Part64{lx, ly, 0.0, 0.0};
   p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
+}
+
+// The leaf starts (nleaves + 1 entries) and the local coordinates in one
+// launch: the first leaf_blocks workgroups take the leaves (a binary search
+// each, latency bound), the rest the particles (a gather through the
+// permutation each), so that the two run side by side.
+__global__ void __launch_bounds__(256) k_leaf_coords(const double2* __restrict__ xy,
+                                                     const uint32_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ perm, int64_t n,
+                                                     int64_t nleaves, unsigned leaf_blocks,
+                                                     const double* __restrict__ root, int levels,
+                                                     int32_t* __restrict__ start,
+                                                     Part64* __restrict__ p64,
+                                                     Part32* __restrict__ p32) {
+  if (blockIdx.x < leaf_blocks) {
+    const int64_t k = blockIdx.x * 256LL + threadIdx.x;
+    if (k <= nleaves) leaf_start_of(keys, n, k, start);
+  } else {
+    const int64_t i = (blockIdx.x - leaf_blocks) * 256LL + threadIdx.x;
+    if (i < n) local_coords_of(xy, keys, perm, i, root, levels, p64, p32);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_target_coords(const double* __restrict__ x,
@@ -676,8 +703,6 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
     bits_left -= bits;
   }
   const int64_t nl = lay.nleaves;
-  hipLaunchKernelGGL(k_leaf_start, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, k0, n, nl,
-                     lstart);
   t.n = n;
   t.root = root;
   t.keys = k0;
@@ -695,8 +720,9 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.le32 = ws + lay.le32;
   t.ops = ws + lay.ops;
   t.check = reinterpret_cast<unsigned long long*>(ws + lay.check);
-  hipLaunchKernelGGL(k_local_coords, dim3(nblocks(n, 256)), dim3(256), 0, st, xy, k0, i0, n,
-                     root, levels, t.part64, t.part32);
+  const unsigned leaf_blocks = nblocks(nl + 1, 256);
+  hipLaunchKernelGGL(k_leaf_coords, dim3(leaf_blocks + nblocks(n, 256)), dim3(256), 0, st, xy, k0,
+                     i0, n, nl, leaf_blocks, root, levels, lstart, t.part64, t.part32);
   t.tile = tile;
   hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
                      tile, toff);
