@@ -410,22 +410,22 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scatter(
 namespace {
 
 // Start of leaf k in the sorted keys: the first position whose leaf is >= k.
-__device__ __forceinline__ void leaf_start_of(const uint32_t* __restrict__ keys, int64_t n,
-                                              int64_t k, int32_t* __restrict__ start) {
+__device__ __forceinline__ int64_t leaf_start_of(const uint32_t* __restrict__ keys, int64_t n,
+                                                 int64_t k) {
   const uint64_t kk = uint64_t(k) << (2 * kSubLevels);
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
     if (uint64_t(keys[mid]) < kk) lo = mid + 1; else hi = mid;
   }
-  start[k] = int32_t(lo);
+  return lo;
 }
 
 __global__ void __launch_bounds__(256) k_leaf_start(const uint32_t* __restrict__ keys, int64_t n,
                                                     int64_t nleaves, int32_t* __restrict__ start) {
   int64_t k = blockIdx.x * 256LL + threadIdx.x;
   if (k > nleaves) return;
-  leaf_start_of(keys, n, k, start);
+  start[k] = int32_t(leaf_start_of(keys, n, k));
 }
 
 // Sorted particle i: its position (through the permutation) relative to its
@@ -448,21 +448,34 @@ __device__ __forceinline__ void local_coords_of(const double2* __restrict__ xy,
   p32[i] = Part32{float(lx), float(ly), 0.0f, 0.0f};
 }
 
-// The leaf starts (nleaves + 1 entries) and the local coordinates in one
-// launch: the first leaf_blocks workgroups take the leaves (a binary search
-// each, latency bound), the rest the particles (a gather through the
-// permutation each), so that the two run side by side.
+// Waves of the leaf part of k_leaf_coords take 63 leaves each and one more:
+// lane l of wave w searches leaf 63 w + l, and lanes 0..62 take their leaf's
+// end from the next lane.
+constexpr int kLeavesPerWave = 63;
+
+// The leaf starts (nleaves + 1 entries), the tiles per leaf (ceil(count /
+// tile); 0 at index nleaves) and the local coordinates in one launch: the
+// first leaf_blocks workgroups take the leaves (one binary search per lane,
+// latency bound), the rest the particles (a gather through the permutation
+// each), so that the two run side by side.
 __global__ void __launch_bounds__(256) k_leaf_coords(const double2* __restrict__ xy,
                                                      const uint32_t* __restrict__ keys,
                                                      const int32_t* __restrict__ perm, int64_t n,
                                                      int64_t nleaves, unsigned leaf_blocks,
-                                                     const double* __restrict__ root, int levels,
-                                                     int32_t* __restrict__ start,
+                                                     int tile, const double* __restrict__ root,
+                                                     int levels, int32_t* __restrict__ start,
+                                                     uint32_t* __restrict__ tiles_per_leaf,
                                                      Part64* __restrict__ p64,
                                                      Part32* __restrict__ p32) {
   if (blockIdx.x < leaf_blocks) {
-    const int64_t k = blockIdx.x * 256LL + threadIdx.x;
-    if (k <= nleaves) leaf_start_of(keys, n, k, start);
+    const int lane = int(threadIdx.x) & 63;
+    const int64_t k = ((blockIdx.x * 256LL + threadIdx.x) >> 6) * kLeavesPerWave + lane;
+    const int64_t s0 = k <= nleaves ? leaf_start_of(keys, n, k) : n;
+    const int64_t s1 = __shfl_down(s0, 1, 64);  // the start of leaf k + 1 (lanes 0..62)
+    if (lane < kLeavesPerWave && k <= nleaves) {  // lane 63's leaf is the next wave's lane 0's
+      start[k] = int32_t(s0);
+      tiles_per_leaf[k] = k < nleaves ? uint32_t((s1 - s0 + tile - 1) / tile) : 0u;
+    }
   } else {
     const int64_t i = (blockIdx.x - leaf_blocks) * 256LL + threadIdx.x;
     if (i < n) local_coords_of(xy, keys, perm, i, root, levels, p64, p32);
@@ -720,12 +733,11 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
   t.le32 = ws + lay.le32;
   t.ops = ws + lay.ops;
   t.check = reinterpret_cast<unsigned long long*>(ws + lay.check);
-  const unsigned leaf_blocks = nblocks(nl + 1, 256);
+  const unsigned leaf_blocks = nblocks(int64_t(nblocks(nl + 1, kLeavesPerWave)) * 64, 256);
   hipLaunchKernelGGL(k_leaf_coords, dim3(leaf_blocks + nblocks(n, 256)), dim3(256), 0, st, xy, k0,
-                     i0, n, nl, leaf_blocks, root, levels, lstart, t.part64, t.part32);
+                     i0, n, nl, leaf_blocks, tile, root, levels, lstart, toff, t.part64,
+                     t.part32);
   t.tile = tile;
-  hipLaunchKernelGGL(k_tile_counts, dim3(nblocks(nl + 1, 256)), dim3(256), 0, st, lstart, nl,
-                     tile, toff);
   hipError_t e = scan_exclusive(toff, nl + 1, tmp, st);
   if (e != hipSuccess) return e;
   t.tile_off = toff;
