@@ -123,18 +123,36 @@ __device__ inline bool in_root(double x, double y, const double* __restrict__ ro
 // Sort keys, the identity permutation, and the positions interleaved (one
 // 16-byte record per particle, so that the gather after the sort reads one
 // record per particle instead of two values from two arrays).
-__global__ void __launch_bounds__(256) k_keys(const double* __restrict__ x,
-                                              const double* __restrict__ y, int64_t n,
-                                              const double* __restrict__ root, int levels,
-                                              uint32_t* __restrict__ keys,
-                                              int32_t* __restrict__ idx,
-                                              double2* __restrict__ xy) {
-  int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n) return;
-  const double xi = x[i], yi = y[i];
-  keys[i] = point_key(xi, yi, root, levels);
-  idx[i] = int32_t(i);
-  xy[i] = make_double2(xi, yi);
+// The sort keys, the identity permutation and the interleaved positions, with
+// the first radix pass's digit counts (the key's low 8 bits) of each sort
+// block: the workgroups are the sort's (kSortPerBlock consecutive points) and
+// the counts go where the counting kernel of that pass would write them.
+__global__ void __launch_bounds__(kSortBlock) k_keys(const double* __restrict__ x,
+                                                     const double* __restrict__ y, int64_t n,
+                                                     const double* __restrict__ root, int levels,
+                                                     uint32_t* __restrict__ keys,
+                                                     int32_t* __restrict__ idx,
+                                                     double2* __restrict__ xy,
+                                                     uint32_t* __restrict__ counts, int nblk) {
+  __shared__ uint32_t hist[256];
+  for (int d = threadIdx.x; d < 256; d += kSortBlock) hist[d] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * int64_t(kSortPerBlock);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kSortBlock + threadIdx.x;
+    if (i < n) {
+      const double xi = x[i], yi = y[i];
+      const uint32_t k = point_key(xi, yi, root, levels);
+      keys[i] = k;
+      idx[i] = int32_t(i);
+      xy[i] = make_double2(xi, yi);
+      atomicAdd(&hist[k & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < 256; d += kSortBlock)
+    counts[int64_t(d) * nblk + blockIdx.x] = hist[d];
 }
 
 // Evaluation points: points outside the root square get key 0 (their
@@ -697,15 +715,17 @@ hipError_t launch_build_tree(const double* x, const double* y, int64_t n, int le
                      domain ? domain[0] : 0.0, domain ? domain[1] : 0.0,
                      domain ? domain[2] : 1.0, levels, root);
   double2* xy = reinterpret_cast<double2*>(ws + lay.xy);
-  hipLaunchKernelGGL(k_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, x, y, n, root, levels, k0,
-                     i0, xy);
   const int nblk = int(lay.sort_blocks);
+  hipLaunchKernelGGL(k_keys, dim3(nblk), dim3(kSortBlock), 0, st, x, y, n, root, levels, k0, i0,
+                     xy, counts, nblk);
   int bits_left = 2 * (levels + kSubLevels), shift = 0;
+  static_assert(2 * kSubLevels >= 8, "the first radix pass takes 8 bits");
   while (bits_left > 0) {
     const int bits = bits_left < 8 ? bits_left : 8;
     const uint32_t mask = (1u << bits) - 1u;
-    hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kSortBlock), 0, st, k0, n, shift, mask,
-                       counts, nblk);
+    if (shift > 0)  // the first pass's counts come with the keys
+      hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kSortBlock), 0, st, k0, n, shift, mask,
+                         counts, nblk);
     hipError_t e = scan_exclusive(counts, int64_t(256) * nblk, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortBlock), 0, st, k0, i0, n, shift,
